@@ -1,0 +1,174 @@
+"""FP64 CPU oracle for the DFacTo hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product path (the HIP library and its Python
+binding) never imports, links or calls it, and it imports nothing from the
+product package.
+
+The arithmetic lives in ``oracle.c`` (plain double-precision loops over
+coordinate-format nonzeros, written from the paper's definitions); this module
+only marshals numpy arrays through ctypes.  Citations for each function are in
+the C source.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with the host C compiler (no fast-math: IEEE FP64)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        lib.oracle_mttkrp.argtypes = [i64, P, P, P, P, P, ctypes.c_int, P, P, P, ctypes.c_int, P]
+        lib.oracle_mttkrp.restype = None
+        lib.oracle_flatten.argtypes = [i64, P, P, P, P, ctypes.c_int, P, P, P, P, P, P, P, P]
+        lib.oracle_flatten.restype = i64
+        lib.oracle_fiber_partials.argtypes = [i64, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
+        lib.oracle_fiber_partials.restype = i64
+        lib.oracle_normsq.argtypes = [i64, P, P, P, P]
+        lib.oracle_normsq.restype = ctypes.c_double
+        lib.oracle_inner.argtypes = [i64, P, P, P, P, ctypes.c_int, P, P, P, P]
+        lib.oracle_inner.restype = ctypes.c_double
+        lib.oracle_als_iter.argtypes = [i64, P, P, P, P, P, ctypes.c_int, ctypes.c_double,
+                                        P, P, P, P, P]
+        lib.oracle_als_iter.restype = ctypes.c_int
+        lib.oracle_gd_grad.argtypes = [i64, P, P, P, P, P, ctypes.c_int, ctypes.c_double,
+                                       P, P, P, P, P, P]
+        lib.oracle_gd_grad.restype = ctypes.c_double
+        _lib = lib
+    return _lib
+
+
+def _u32(a):
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _coo(i, j, k, val):
+    i, j, k, val = _u32(i), _u32(j), _u32(k), _f64(val)
+    assert i.shape == j.shape == k.shape == val.shape
+    return i, j, k, val
+
+
+def mttkrp(i, j, k, val, dims, factors, mode: int) -> np.ndarray:
+    """MTTKRP of ``mode`` (0, 1, 2) by its per-nonzero element form."""
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    A, B, C = (_f64(f) for f in factors)
+    R = A.shape[1]
+    d = np.asarray(dims, dtype=np.int64)
+    out = np.empty((int(dims[mode]), R), dtype=np.float64)
+    lib.oracle_mttkrp(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), R, _p(A), _p(B), _p(C),
+                      int(mode), _p(out))
+    return out
+
+
+def flatten(i, j, k, val, mode: int) -> dict:
+    """Distinct nonzeros of ``mode``'s flattening in (root, mid, leaf) order."""
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    n = len(val)
+    root_id = np.empty(max(n, 1), np.uint32)
+    root_ptr = np.empty(n + 1, np.int64)
+    fib_mid = np.empty(max(n, 1), np.uint32)
+    fib_ptr = np.empty(n + 1, np.int64)
+    leaf = np.empty(max(n, 1), np.uint32)
+    v = np.empty(max(n, 1), np.float64)
+    nroot = np.zeros(1, np.int64)
+    nfib = np.zeros(1, np.int64)
+    m = lib.oracle_flatten(n, _p(i), _p(j), _p(k), _p(val), int(mode), _p(root_id), _p(root_ptr),
+                           _p(fib_mid), _p(fib_ptr), _p(leaf), _p(v), _p(nroot), _p(nfib))
+    nr, nf = int(nroot[0]), int(nfib[0])
+    return dict(nnz=int(m), root_id=root_id[:nr].copy(), root_ptr=root_ptr[:nr + 1].copy(),
+                fib_mid=fib_mid[:nf].copy(), fib_ptr=fib_ptr[:nf + 1].copy(),
+                leaf=leaf[:m].copy(), val=v[:m].copy())
+
+
+def fiber_partials(i, j, k, val, mode: int, Fleaf) -> np.ndarray:
+    """Stage-1 values P[f, :] = sum_leaf x * Fleaf[leaf, :] per nonempty fiber."""
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    Fleaf = _f64(Fleaf)
+    R = Fleaf.shape[1]
+    P = np.empty((max(len(val), 1), R), np.float64)
+    nf = lib.oracle_fiber_partials(len(val), _p(i), _p(j), _p(k), _p(val), int(mode), R,
+                                   _p(Fleaf), _p(P))
+    return P[:nf].copy()
+
+
+def normsq(i, j, k, val) -> float:
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    return float(lib.oracle_normsq(len(val), _p(i), _p(j), _p(k), _p(val)))
+
+
+def inner(i, j, k, val, factors, lam=None) -> float:
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    A, B, C = (_f64(f) for f in factors)
+    lp = None
+    if lam is not None:
+        lam = _f64(lam)
+        lp = _p(lam)
+    return float(lib.oracle_inner(len(val), _p(i), _p(j), _p(k), _p(val), A.shape[1],
+                                  _p(A), _p(B), _p(C), lp))
+
+
+def als_iter(i, j, k, val, dims, factors, reg: float = 0.0):
+    """One CP-ALS iteration.  Returns (A, B, C, lam, info) with new arrays.
+
+    info = dict(fit, inner_direct, normsq, xhat_sq, pinv_mask)."""
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    A, B, C = (np.array(f, dtype=np.float64, order="C", copy=True) for f in factors)
+    R = A.shape[1]
+    d = np.asarray(dims, dtype=np.int64)
+    lam = np.empty(R, np.float64)
+    out = np.empty(4, np.float64)
+    mask = lib.oracle_als_iter(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), R, float(reg),
+                               _p(A), _p(B), _p(C), _p(lam), _p(out))
+    info = dict(fit=float(out[0]), inner_direct=float(out[1]), normsq=float(out[2]),
+                xhat_sq=float(out[3]), pinv_mask=int(mask))
+    return A, B, C, lam, info
+
+
+def gd_grad(i, j, k, val, dims, factors, reg: float = 0.0):
+    """Gradients of f at one point.  Returns ((gA, gB, gC), f)."""
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    A, B, C = (_f64(f) for f in factors)
+    R = A.shape[1]
+    d = np.asarray(dims, dtype=np.int64)
+    g = [np.empty((int(dims[m]), R), np.float64) for m in range(3)]
+    f = lib.oracle_gd_grad(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), R, float(reg),
+                           _p(A), _p(B), _p(C), _p(g[0]), _p(g[1]), _p(g[2]))
+    return tuple(g), float(f)

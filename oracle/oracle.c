@@ -1,0 +1,518 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for the DFacTo hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; it exists so that tests, the smoke check and the CPU
+ * baseline leg of the benchmark can compare the HIP library against an
+ * independent, obviously correct computation.  It shares no code, header,
+ * table or helper with the GPU path.
+ *
+ * Everything here is a slow loop over coordinate-format (COO) nonzeros in
+ * double precision, written from the definitions in
+ *   Choi & Vishwanathan, "DFacTo: Distributed Factorization of Tensors"
+ *   (NIPS 2014):
+ *   - Section 2.1, eq. (1): the three cyclic flattenings
+ *       x_{ijk} = X1[i, j + k*J] = X2[j, k + i*K] = X3[k, i + j*I]   (0-based)
+ *   - Appendix A: Khatri-Rao product, Hadamard product, and the identity
+ *       (A kr B)^T (A kr B) = A^T A * B^T B
+ *   - Lemma 2 (Section 3): column r of X1 (C kr B) equals
+ *       [unvec_(K,I)((X2)^T b_r)]^T c_r ,
+ *     whose entry i is sum_{j,k} x_{ijk} b_{jr} c_{kr}.  The oracle uses that
+ *     element form directly (per nonzero), not the two sparse products.
+ *   - Appendix B: CP model with unit-norm columns and weights lambda,
+ *     Algorithm 2 (CP-ALS, Gauss-Seidel order A, B, C), the least-squares
+ *     update  A <- X1 (C kr B) (C^T C * B^T B + reg I)^{-1}  (ridge form).
+ *   - Appendix C: GD objective f = 1/2 ||X - [[A,B,C]]||^2 (+ ridge), and
+ *       dF/dA = -X1 (C kr B) + A (C^T C * B^T B + reg I).
+ *
+ * Mode numbering is 0-based: mode 0 is the paper's mode 1 (output rows i),
+ * mode 1 is the paper's mode 2 (rows j), mode 2 the paper's mode 3 (rows k).
+ *
+ * Duplicate coordinates are summed (the paper does not say; linear algebra
+ * on a sparse tensor with repeated coordinates sums them).
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* small dense helpers (row-major)                                     */
+/* ------------------------------------------------------------------ */
+
+/* G = F^T F for F (rows x R). */
+static void gram(int64_t rows, int R, const double *F, double *G)
+{
+    memset(G, 0, sizeof(double) * (size_t)R * R);
+    for (int64_t n = 0; n < rows; ++n) {
+        const double *f = F + n * R;
+        for (int r = 0; r < R; ++r)
+            for (int s = 0; s < R; ++s)
+                G[r * R + s] += f[r] * f[s];
+    }
+}
+
+/* Cholesky H = L L^T (L lower, row-major).  Returns 0 on success, -1 when a
+ * pivot falls to or below R * eps * max(diag H): H is then treated as
+ * singular and the caller switches to the pseudo-inverse. */
+static int cholesky(int R, const double *H, double *L)
+{
+    double dmax = 0.0;
+    for (int r = 0; r < R; ++r)
+        if (H[r * R + r] > dmax) dmax = H[r * R + r];
+    const double tol = (double)R * DBL_EPSILON * dmax;
+    if (!(dmax > 0.0)) return -1;
+    memset(L, 0, sizeof(double) * (size_t)R * R);
+    for (int j = 0; j < R; ++j) {
+        double d = H[j * R + j];
+        for (int k = 0; k < j; ++k) d -= L[j * R + k] * L[j * R + k];
+        if (!(d > tol)) return -1;
+        const double ljj = sqrt(d);
+        L[j * R + j] = ljj;
+        for (int i = j + 1; i < R; ++i) {
+            double s = H[i * R + j];
+            for (int k = 0; k < j; ++k) s -= L[i * R + k] * L[j * R + k];
+            L[i * R + j] = s / ljj;
+        }
+    }
+    return 0;
+}
+
+/* Cyclic Jacobi eigen-decomposition of symmetric H: H = V diag(w) V^T.
+ * V is row-major with eigenvectors in columns. */
+static void jacobi_eigen(int R, const double *H, double *w, double *V)
+{
+    double *A = (double *)malloc(sizeof(double) * (size_t)R * R);
+    memcpy(A, H, sizeof(double) * (size_t)R * R);
+    for (int i = 0; i < R; ++i)
+        for (int j = 0; j < R; ++j) V[i * R + j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < R; ++i)
+            for (int j = 0; j < R; ++j) {
+                tot += A[i * R + j] * A[i * R + j];
+                if (i != j) off += A[i * R + j] * A[i * R + j];
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < R - 1; ++p)
+            for (int q = p + 1; q < R; ++q) {
+                const double apq = A[p * R + q];
+                if (apq == 0.0) continue;
+                const double app = A[p * R + p], aqq = A[q * R + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) /
+                                 (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                /* A <- J^T A J with the rotation in the (p, q) plane */
+                for (int k = 0; k < R; ++k) {
+                    const double akp = A[k * R + p], akq = A[k * R + q];
+                    A[k * R + p] = c * akp - s * akq;
+                    A[k * R + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < R; ++k) {
+                    const double apk = A[p * R + k], aqk = A[q * R + k];
+                    A[p * R + k] = c * apk - s * aqk;
+                    A[q * R + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < R; ++k) {
+                    const double vkp = V[k * R + p], vkq = V[k * R + q];
+                    V[k * R + p] = c * vkp - s * vkq;
+                    V[k * R + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < R; ++i) w[i] = A[i * R + i];
+    free(A);
+}
+
+/* Moore-Penrose pseudo-inverse of symmetric PSD H via its eigen-
+ * decomposition; eigenvalues at or below R * eps * max eigenvalue are
+ * treated as zero. */
+static void pinv_sym(int R, const double *H, double *P)
+{
+    double *w = (double *)malloc(sizeof(double) * (size_t)R);
+    double *V = (double *)malloc(sizeof(double) * (size_t)R * R);
+    jacobi_eigen(R, H, w, V);
+    double wmax = 0.0;
+    for (int i = 0; i < R; ++i)
+        if (w[i] > wmax) wmax = w[i];
+    const double tol = (double)R * DBL_EPSILON * wmax;
+    memset(P, 0, sizeof(double) * (size_t)R * R);
+    for (int e = 0; e < R; ++e) {
+        if (!(w[e] > tol)) continue;
+        const double inv = 1.0 / w[e];
+        for (int i = 0; i < R; ++i)
+            for (int j = 0; j < R; ++j)
+                P[i * R + j] += V[i * R + e] * inv * V[j * R + e];
+    }
+    free(w);
+    free(V);
+}
+
+/* F <- M H^{-1} row by row (H symmetric).  Cholesky with forward and back
+ * substitution; pseudo-inverse when H is numerically singular.
+ * Returns 0 if Cholesky was used, 1 if the pseudo-inverse was used. */
+static int solve_rows(int64_t rows, int R, const double *M, const double *H,
+                      double *F)
+{
+    double *L = (double *)malloc(sizeof(double) * (size_t)R * R);
+    int used_pinv = 0;
+    if (cholesky(R, H, L) == 0) {
+        double *y = (double *)malloc(sizeof(double) * (size_t)R);
+        for (int64_t n = 0; n < rows; ++n) {
+            const double *m = M + n * R;
+            double *x = F + n * R;
+            /* H x = m  with H = L L^T  (x is the row written as a column) */
+            for (int i = 0; i < R; ++i) {
+                double s = m[i];
+                for (int k = 0; k < i; ++k) s -= L[i * R + k] * y[k];
+                y[i] = s / L[i * R + i];
+            }
+            for (int i = R - 1; i >= 0; --i) {
+                double s = y[i];
+                for (int k = i + 1; k < R; ++k) s -= L[k * R + i] * x[k];
+                x[i] = s / L[i * R + i];
+            }
+        }
+        free(y);
+    } else {
+        used_pinv = 1;
+        double *P = (double *)malloc(sizeof(double) * (size_t)R * R);
+        pinv_sym(R, H, P);
+        for (int64_t n = 0; n < rows; ++n) {
+            const double *m = M + n * R;
+            double *x = F + n * R;
+            for (int s = 0; s < R; ++s) {
+                double acc = 0.0;
+                for (int r = 0; r < R; ++r) acc += m[r] * P[r * R + s];
+                x[s] = acc;
+            }
+        }
+        free(P);
+    }
+    free(L);
+    return used_pinv;
+}
+
+/* ------------------------------------------------------------------ */
+/* coordinate helpers                                                  */
+/* ------------------------------------------------------------------ */
+
+/* The three index arrays as one table: idx[m][e] is the mode-m index of
+ * nonzero e (m = 0: i, 1: j, 2: k). */
+typedef struct {
+    const uint32_t *idx[3];
+} coords;
+
+/* Per mode n, the flattening that feeds it is ordered (root, mid, leaf):
+ *   mode 0: (i, k, j)  -- fibers x_{i,:,k}, the rows of (X2)^T  (Lemma 1)
+ *   mode 1: (j, i, k)  -- fibers x_{i,j,:}, the rows of (X3)^T
+ *   mode 2: (k, j, i)  -- fibers x_{:,j,k}, the rows of (X1)^T
+ * which are the three products used in Algorithm 4 (Appendix E).  With this
+ * order the flattening of mode n is the CSR matrix X^{n+1} of eq. (1): row
+ * = root, column = leaf + mid * dims[leaf]. */
+static const int ROOT[3] = {0, 1, 2};
+static const int MID[3] = {2, 0, 1};
+static const int LEAF[3] = {1, 2, 0};
+
+typedef struct {
+    uint32_t key[3]; /* root, mid, leaf */
+    double v;
+    int64_t pos; /* original position, breaks ties so the sort is stable */
+} rec;
+
+static int rec_cmp(const void *a, const void *b)
+{
+    const rec *x = (const rec *)a, *y = (const rec *)b;
+    for (int t = 0; t < 3; ++t) {
+        if (x->key[t] < y->key[t]) return -1;
+        if (x->key[t] > y->key[t]) return 1;
+    }
+    return (x->pos < y->pos) ? -1 : (x->pos > y->pos);
+}
+
+/* Sort nonzeros by (root, mid, leaf) of `mode` and sum duplicates in their
+ * input order.  Returns a malloc'd array of distinct records and its size. */
+static rec *sorted_distinct(int64_t nnz, coords c, const double *val, int mode,
+                            int64_t *out_n)
+{
+    rec *a = (rec *)malloc(sizeof(rec) * (size_t)(nnz > 0 ? nnz : 1));
+    for (int64_t e = 0; e < nnz; ++e) {
+        a[e].key[0] = c.idx[ROOT[mode]][e];
+        a[e].key[1] = c.idx[MID[mode]][e];
+        a[e].key[2] = c.idx[LEAF[mode]][e];
+        a[e].v = val[e];
+        a[e].pos = e;
+    }
+    qsort(a, (size_t)nnz, sizeof(rec), rec_cmp);
+    int64_t n = 0;
+    for (int64_t e = 0; e < nnz; ++e) {
+        if (n > 0 && a[n - 1].key[0] == a[e].key[0] &&
+            a[n - 1].key[1] == a[e].key[1] && a[n - 1].key[2] == a[e].key[2]) {
+            a[n - 1].v += a[e].v;
+        } else {
+            a[n++] = a[e];
+        }
+    }
+    *out_n = n;
+    return a;
+}
+
+/* ------------------------------------------------------------------ */
+/* public entry points                                                  */
+/* ------------------------------------------------------------------ */
+
+/* MTTKRP by its element form (Lemma 2; Khatri-Rao definition, Appendix A):
+ *   mode 0: out[i,:] += x_{ijk} * (B[j,:] * C[k,:])
+ *   mode 1: out[j,:] += x_{ijk} * (A[i,:] * C[k,:])
+ *   mode 2: out[k,:] += x_{ijk} * (A[i,:] * B[j,:])
+ * F[m] is dims[m] x R row-major; out is dims[mode] x R and is overwritten. */
+void oracle_mttkrp(int64_t nnz, const uint32_t *i, const uint32_t *j,
+                   const uint32_t *k, const double *val, const int64_t *dims,
+                   int R, const double *A, const double *B, const double *C,
+                   int mode, double *out)
+{
+    const uint32_t *ix[3] = {i, j, k};
+    const double *F[3] = {A, B, C};
+    const int p = (mode + 1) % 3, q = (mode + 2) % 3;
+    memset(out, 0, sizeof(double) * (size_t)dims[mode] * R);
+    for (int64_t e = 0; e < nnz; ++e) {
+        double *o = out + (int64_t)ix[mode][e] * R;
+        const double *fp = F[p] + (int64_t)ix[p][e] * R;
+        const double *fq = F[q] + (int64_t)ix[q][e] * R;
+        for (int r = 0; r < R; ++r) o[r] += val[e] * fp[r] * fq[r];
+    }
+}
+
+/* Flattening of `mode` (Section 2.1 and the CSR discussion of Section 3):
+ * distinct nonzeros sorted by (root, mid, leaf), duplicates summed.
+ * Outputs (caller-allocated, sized for nnz entries):
+ *   root_id[nroot], root_ptr[nroot+1] (fiber offsets),
+ *   fib_mid[nfib], fib_ptr[nfib+1] (nonzero offsets), leaf[n], v[n].
+ * Returns the number n of distinct nonzeros; *nroot and *nfib are set. */
+int64_t oracle_flatten(int64_t nnz, const uint32_t *i, const uint32_t *j,
+                       const uint32_t *k, const double *val, int mode,
+                       uint32_t *root_id, int64_t *root_ptr, uint32_t *fib_mid,
+                       int64_t *fib_ptr, uint32_t *leaf, double *v,
+                       int64_t *nroot, int64_t *nfib)
+{
+    coords c = {{i, j, k}};
+    int64_t n = 0;
+    rec *a = sorted_distinct(nnz, c, val, mode, &n);
+    int64_t nr = 0, nf = 0;
+    for (int64_t e = 0; e < n; ++e) {
+        const int new_root = (e == 0) || a[e].key[0] != a[e - 1].key[0];
+        const int new_fib = new_root || a[e].key[1] != a[e - 1].key[1];
+        if (new_root) {
+            root_id[nr] = a[e].key[0];
+            root_ptr[nr] = nf;
+            ++nr;
+        }
+        if (new_fib) {
+            fib_mid[nf] = a[e].key[1];
+            fib_ptr[nf] = e;
+            ++nf;
+        }
+        leaf[e] = a[e].key[2];
+        v[e] = a[e].v;
+    }
+    root_ptr[nr] = nf;
+    fib_ptr[nf] = n;
+    *nroot = nr;
+    *nfib = nf;
+    free(a);
+    return n;
+}
+
+/* First stage of Algorithm 1 for all R columns at once: for every nonempty
+ * fiber f = (root, mid) of `mode`,
+ *   P[f, r] = sum_{leaf} x * Fleaf[leaf, r],
+ * i.e. the value arrays of the matrices M^r of Lemma 4 (for mode 0,
+ * M^r[i, k] = sum_j x_{ijk} b_{jr}).  Fibers are in (root, mid) order, as
+ * produced by oracle_flatten.  Returns the fiber count. */
+int64_t oracle_fiber_partials(int64_t nnz, const uint32_t *i, const uint32_t *j,
+                              const uint32_t *k, const double *val, int mode,
+                              int R, const double *Fleaf, double *P)
+{
+    coords c = {{i, j, k}};
+    int64_t n = 0;
+    rec *a = sorted_distinct(nnz, c, val, mode, &n);
+    int64_t nf = -1;
+    for (int64_t e = 0; e < n; ++e) {
+        const int new_fib = (e == 0) || a[e].key[0] != a[e - 1].key[0] ||
+                            a[e].key[1] != a[e - 1].key[1];
+        if (new_fib) {
+            ++nf;
+            for (int r = 0; r < R; ++r) P[nf * R + r] = 0.0;
+        }
+        for (int r = 0; r < R; ++r)
+            P[nf * R + r] += a[e].v * Fleaf[(int64_t)a[e].key[2] * R + r];
+    }
+    free(a);
+    return nf + 1;
+}
+
+/* Sum of squares of the distinct (duplicate-summed) entries, ||X||^2. */
+double oracle_normsq(int64_t nnz, const uint32_t *i, const uint32_t *j,
+                     const uint32_t *k, const double *val)
+{
+    coords c = {{i, j, k}};
+    int64_t n = 0;
+    rec *a = sorted_distinct(nnz, c, val, 0, &n);
+    double s = 0.0;
+    for (int64_t e = 0; e < n; ++e) s += a[e].v * a[e].v;
+    free(a);
+    return s;
+}
+
+/* <X, [[lambda; A, B, C]]> summed over the nonzeros directly:
+ *   sum_e x_e sum_r lambda_r a_{ir} b_{jr} c_{kr}   (lambda NULL = ones). */
+double oracle_inner(int64_t nnz, const uint32_t *i, const uint32_t *j,
+                    const uint32_t *k, const double *val, int R,
+                    const double *A, const double *B, const double *C,
+                    const double *lambda)
+{
+    double s = 0.0;
+    for (int64_t e = 0; e < nnz; ++e) {
+        const double *a = A + (int64_t)i[e] * R;
+        const double *b = B + (int64_t)j[e] * R;
+        const double *c = C + (int64_t)k[e] * R;
+        double t = 0.0;
+        for (int r = 0; r < R; ++r)
+            t += (lambda ? lambda[r] : 1.0) * a[r] * b[r] * c[r];
+        s += val[e] * t;
+    }
+    return s;
+}
+
+/* One CP-ALS iteration (Algorithm 2 / Algorithm 4) in Gauss-Seidel order
+ * n = 0, 1, 2, each step using the factors already updated:
+ *   M   = MTTKRP(n)
+ *   H   = (F_p^T F_p) * (F_q^T F_q) + reg I        (Appendix A identity)
+ *   F_n = M H^{-1}  (Cholesky; pseudo-inverse when H is singular)
+ *   lambda_r = ||F_n[:, r]||_2 ; F_n[:, r] /= lambda_r when lambda_r > 0.
+ * After mode 2 the fit of the weighted model [[lambda; A, B, C]]:
+ *   ||Xhat||^2 = lambda^T (G_A * G_B * G_C) lambda
+ *   <X, Xhat>  = sum_r lambda_r sum_k C[k, r] M3[k, r]
+ *   fit = 1 - sqrt(max(0, ||X||^2 + ||Xhat||^2 - 2 <X, Xhat>)) / ||X||
+ *   (fit = 0 when ||X|| = 0).
+ * A, B, C are updated in place.  out[0] = fit, out[1] = <X,Xhat> computed
+ * directly over the nonzeros (independent cross-check), out[2] = ||X||^2,
+ * out[3] = ||Xhat||^2.  Returns a bitmask of the modes that used the
+ * pseudo-inverse. */
+int oracle_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
+                    const uint32_t *k, const double *val, const int64_t *dims,
+                    int R, double reg, double *A, double *B, double *C,
+                    double *lambda, double *out)
+{
+    double *F[3] = {A, B, C};
+    int64_t dmax = dims[0];
+    if (dims[1] > dmax) dmax = dims[1];
+    if (dims[2] > dmax) dmax = dims[2];
+    double *M = (double *)malloc(sizeof(double) * (size_t)dmax * R);
+    double *M3 = (double *)malloc(sizeof(double) * (size_t)dims[2] * R);
+    double *Gp = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *Gq = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *H = (double *)malloc(sizeof(double) * (size_t)R * R);
+    int pinv_mask = 0;
+    for (int n = 0; n < 3; ++n) {
+        const int p = (n + 1) % 3, q = (n + 2) % 3;
+        oracle_mttkrp(nnz, i, j, k, val, dims, R, F[0], F[1], F[2], n, M);
+        gram(dims[p], R, F[p], Gp);
+        gram(dims[q], R, F[q], Gq);
+        for (int t = 0; t < R * R; ++t) H[t] = Gp[t] * Gq[t];
+        for (int r = 0; r < R; ++r) H[r * R + r] += reg;
+        if (solve_rows(dims[n], R, M, H, F[n])) pinv_mask |= 1 << n;
+        for (int r = 0; r < R; ++r) {
+            double s = 0.0;
+            for (int64_t m = 0; m < dims[n]; ++m)
+                s += F[n][m * R + r] * F[n][m * R + r];
+            lambda[r] = sqrt(s);
+            if (lambda[r] > 0.0)
+                for (int64_t m = 0; m < dims[n]; ++m) F[n][m * R + r] /= lambda[r];
+        }
+        if (n == 2) memcpy(M3, M, sizeof(double) * (size_t)dims[2] * R);
+    }
+    /* fit */
+    double *GA = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *GB = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *GC = (double *)malloc(sizeof(double) * (size_t)R * R);
+    gram(dims[0], R, A, GA);
+    gram(dims[1], R, B, GB);
+    gram(dims[2], R, C, GC);
+    double xhat2 = 0.0;
+    for (int r = 0; r < R; ++r)
+        for (int s = 0; s < R; ++s)
+            xhat2 += lambda[r] * lambda[s] * GA[r * R + s] * GB[r * R + s] *
+                     GC[r * R + s];
+    double inner = 0.0;
+    for (int r = 0; r < R; ++r) {
+        double s = 0.0;
+        for (int64_t m = 0; m < dims[2]; ++m) s += C[m * R + r] * M3[m * R + r];
+        inner += lambda[r] * s;
+    }
+    const double x2 = oracle_normsq(nnz, i, j, k, val);
+    double res2 = x2 + xhat2 - 2.0 * inner;
+    if (res2 < 0.0) res2 = 0.0;
+    out[0] = (x2 > 0.0) ? 1.0 - sqrt(res2) / sqrt(x2) : 0.0;
+    out[1] = oracle_inner(nnz, i, j, k, val, R, A, B, C, lambda);
+    out[2] = x2;
+    out[3] = xhat2;
+    free(GA);
+    free(GB);
+    free(GC);
+    free(M);
+    free(M3);
+    free(Gp);
+    free(Gq);
+    free(H);
+    return pinv_mask;
+}
+
+/* GD gradient (Appendix C; Algorithm 3 with the minus sign of the gradient
+ * equation), all three at the same point, unit weights:
+ *   grad_n = -MTTKRP(n) + F_n ((F_p^T F_p) * (F_q^T F_q) + reg I)
+ *   f = 1/2 (||X||^2 - 2 <X, [[A,B,C]]> + sum(G_A * G_B * G_C))
+ *       + 1/2 reg (||A||^2 + ||B||^2 + ||C||^2)
+ * The sum in f runs over every (i, j, k), so zeros count.  G[m] receives a
+ * dims[m] x R gradient.  Returns f. */
+double oracle_gd_grad(int64_t nnz, const uint32_t *i, const uint32_t *j,
+                      const uint32_t *k, const double *val,
+                      const int64_t *dims, int R, double reg, const double *A,
+                      const double *B, const double *C, double *GA_out,
+                      double *GB_out, double *GC_out)
+{
+    const double *F[3] = {A, B, C};
+    double *Gout[3] = {GA_out, GB_out, GC_out};
+    double *Gm[3];
+    for (int m = 0; m < 3; ++m) {
+        Gm[m] = (double *)malloc(sizeof(double) * (size_t)R * R);
+        gram(dims[m], R, F[m], Gm[m]);
+    }
+    double *H = (double *)malloc(sizeof(double) * (size_t)R * R);
+    for (int n = 0; n < 3; ++n) {
+        const int p = (n + 1) % 3, q = (n + 2) % 3;
+        oracle_mttkrp(nnz, i, j, k, val, dims, R, A, B, C, n, Gout[n]);
+        for (int t = 0; t < R * R; ++t) H[t] = Gm[p][t] * Gm[q][t];
+        for (int r = 0; r < R; ++r) H[r * R + r] += reg;
+        for (int64_t m = 0; m < dims[n]; ++m) {
+            const double *fr = F[n] + m * R;
+            double *g = Gout[n] + m * R;
+            for (int s = 0; s < R; ++s) {
+                double acc = 0.0;
+                for (int r = 0; r < R; ++r) acc += fr[r] * H[r * R + s];
+                g[s] = -g[s] + acc;
+            }
+        }
+    }
+    double xhat2 = 0.0, fro2 = 0.0;
+    for (int t = 0; t < R * R; ++t) xhat2 += Gm[0][t] * Gm[1][t] * Gm[2][t];
+    for (int m = 0; m < 3; ++m)
+        for (int r = 0; r < R; ++r) fro2 += Gm[m][r * R + r];
+    const double x2 = oracle_normsq(nnz, i, j, k, val);
+    const double inner = oracle_inner(nnz, i, j, k, val, R, A, B, C, NULL);
+    for (int m = 0; m < 3; ++m) free(Gm[m]);
+    free(H);
+    return 0.5 * (x2 - 2.0 * inner + xhat2) + 0.5 * reg * fro2;
+}

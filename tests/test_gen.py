@@ -1,0 +1,60 @@
+"""Seeded generator checks (CPU only): determinism, distinctness, ranges and
+the Zipf head frequency against its closed form p_1 = 1 / H_{dim,s}."""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+from paper_1406_4519_amd import gen
+
+
+def test_uniform_distinct_deterministic_and_distinct():
+    a = gen.uniform_distinct((200, 150, 100), 20_000, seed=1)
+    b = gen.uniform_distinct((200, 150, 100), 20_000, seed=1)
+    for x, y in ((a.i, b.i), (a.j, b.j), (a.k, b.k), (a.val, b.val)):
+        np.testing.assert_array_equal(x, y)
+    assert a.val.dtype == np.float32 and a.i.dtype == np.uint32
+    lin = (a.i.astype(np.int64) * 150 + a.j) * 100 + a.k
+    assert len(np.unique(lin)) == 20_000
+    assert a.i.max() < 200 and a.j.max() < 150 and a.k.max() < 100
+    c = gen.uniform_distinct((200, 150, 100), 20_000, seed=2)
+    assert not np.array_equal(a.i, c.i)
+
+
+def test_zipf_distinct_counts_and_determinism():
+    dims = (5000, 3000, 2000)
+    a = gen.zipf_distinct(dims, 200_000, 1.1, seed=5)
+    b = gen.zipf_distinct(dims, 200_000, 1.1, seed=5)
+    np.testing.assert_array_equal(a.i, b.i)
+    np.testing.assert_array_equal(a.val, b.val)
+    lin = (a.i.astype(np.int64) * dims[1] + a.j) * dims[2] + a.k
+    assert len(np.unique(lin)) == 200_000
+    assert (a.val >= 0).all()
+    assert a.i.max() < dims[0] and a.j.max() < dims[1] and a.k.max() < dims[2]
+
+
+def test_zipf_head_frequency():
+    dim, s, n = 10_000, 1.1, 2_000_000
+    cdf = gen.zipf_cdf(dim, s)
+    rng = np.random.Generator(np.random.PCG64(9))
+    with ThreadPoolExecutor(4) as pool:
+        r = gen._draw_ranks(cdf, rng.random(n), pool)
+    H = float(np.sum(np.arange(1, dim + 1, dtype=np.float64) ** -s))
+    for rank in (1, 2, 10):
+        p = rank ** -s / H
+        got = float(np.mean(r == rank - 1))
+        assert abs(got - p) < 5 * np.sqrt(p * (1 - p) / n)
+
+
+def test_bf16_rounding_round_to_nearest_even():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 0.0], dtype=np.float32)
+    y = gen.bf16_to_f32(gen.f32_to_bf16(x))
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: rounds to the even (1.0)
+    np.testing.assert_array_equal(y, np.array([1.0, 1.0, 1.0 + 2 ** -6, -2.5, 0.0], np.float32))
+
+
+def test_batched_specs_in_range():
+    for t in range(16):
+        dims, nnz, R, s1, s2 = gen.batched_spec(t)
+        assert all(1000 <= d <= 100_000 for d in dims)
+        assert 10_000 <= nnz <= 5_000_000 or nnz == (dims[0] * dims[1] * dims[2]) // 2
+        assert R in (8, 16, 32)
