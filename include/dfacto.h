@@ -1,0 +1,204 @@
+/*
+ * dfacto.h -- C ABI of the MI355X (gfx950) DFacTo engine.
+ *
+ * The engine computes the matricized-tensor-times-Khatri-Rao product
+ * (MTTKRP) of a sparse 3-way tensor the way DFacTo does (Choi &
+ * Vishwanathan, "DFacTo: Distributed Factorization of Tensors", NIPS 2014,
+ * Section 3, Algorithm 1): as two sparse products over a fiber-compressed
+ * flattening, batched over all R rank columns, and the two solvers that sit
+ * on top of it -- one CP-ALS iteration (Appendix B, Algorithm 2; Appendix E,
+ * Algorithm 4) and the GD gradient (Appendix C, Algorithm 3).
+ *
+ * Conventions for every call:
+ *  - Modes are 0-based: mode 0 = the paper's mode 1 (output rows i),
+ *    mode 1 = mode 2 (rows j), mode 2 = mode 3 (rows k).
+ *  - Pointers named d_* are DEVICE pointers owned by the caller; the library
+ *    never frees them.  Host pointers are named h_* or are plain arrays of
+ *    device pointers (d_F[3]).
+ *  - Factor matrices are row-major dims[m] x R, element type given by a
+ *    dfacto_dtype (FP32, or BF16 stored as raw 16-bit patterns).  Row
+ *    starts must be aligned to the element size.
+ *  - Work is enqueued on the stream bound to the context and is
+ *    stream-ordered; only dfacto_build_flattenings and dfacto_tensor_export
+ *    synchronize.  Inputs must stay unmodified until the stream passes the
+ *    call.
+ *  - Every call returns a status; nothing aborts, throws or prints.  A HIP
+ *    runtime failure is sticky: the context then returns DFACTO_E_DEVICE
+ *    from every later call.  dfacto_last_error() describes the last failure.
+ *  - Results are bitwise reproducible for a given tensor, R and dtype: no
+ *    floating-point atomics are used and every reduction has a fixed order.
+ *  - One context per host thread.  A built tensor is read-only and may be
+ *    used from several contexts on the same device.
+ */
+#ifndef DFACTO_H
+#define DFACTO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DFACTO_OK = 0,
+    DFACTO_E_INVALID = 1,     /* bad argument: null pointer, mode, R, dims, dtype */
+    DFACTO_E_RANGE = 2,       /* a coordinate is >= its dimension */
+    DFACTO_E_NOMEM = 3,       /* a device allocation failed */
+    DFACTO_E_DEVICE = 4,      /* HIP runtime error (sticky on the context) */
+    DFACTO_E_NUMERIC = 5,     /* NaN or Inf among the tensor values */
+    DFACTO_E_UNSUPPORTED = 6  /* sizes beyond the supported limits */
+} dfacto_status;
+
+typedef enum { DFACTO_F32 = 0, DFACTO_BF16 = 1 } dfacto_dtype;
+
+/* Limits.  Each dimension must be in [1, DFACTO_MAX_DIM]; nnz plus the
+ * number of fiber headers must stay below 2^32 - 2^20; R in [1, DFACTO_MAX_R]. */
+#define DFACTO_MAX_DIM ((int64_t)1 << 30)
+#define DFACTO_MAX_R 256
+
+typedef struct dfacto_ctx dfacto_ctx;       /* device, stream, workspace, sticky error */
+typedef struct dfacto_tensor dfacto_tensor; /* the three flattenings, on the device */
+
+/* ------------------------------------------------------------------ */
+/* context                                                              */
+/* ------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  Returns DFACTO_E_DEVICE if
+ * no such device exists. */
+dfacto_status dfacto_ctx_create(int device, void *hip_stream, dfacto_ctx **out);
+
+/* Rebind the context to another stream of the same device. */
+dfacto_status dfacto_ctx_set_stream(dfacto_ctx *ctx, void *hip_stream);
+
+/* Wait until all work the context enqueued has finished. */
+dfacto_status dfacto_ctx_synchronize(dfacto_ctx *ctx);
+
+/* Free the context and its workspace.  NULL is ignored. */
+void dfacto_ctx_destroy(dfacto_ctx *ctx);
+
+/* Message for the last failing call on `ctx` (owned by ctx, valid until
+ * the next call).  Never NULL. */
+const char *dfacto_last_error(const dfacto_ctx *ctx);
+
+/* ------------------------------------------------------------------ */
+/* tensor: the three fiber-compressed flattenings                       */
+/* ------------------------------------------------------------------ */
+
+/* Build the three flattenings of the tensor of size dims[0] x dims[1] x
+ * dims[2] given in coordinate format (d_i[e], d_j[e], d_k[e]) -> d_val[e],
+ * e < nnz, all four arrays on the device (u32 indices, FP32 values).
+ *
+ * Section 2.1, eq. (1) defines the flattenings X1 (I x JK), X2 (J x KI),
+ * X3 (K x IJ); Section 3 stores (X2)^T with its all-zero rows removed and
+ * the sparsity pattern of the matrices M^r precomputed (Lemmas 3 and 4).
+ * Here mode n keeps the nonzeros sorted by (root, mid, leaf):
+ *     mode 0: (i, k, j)   mode 1: (j, i, k)   mode 2: (k, j, i)
+ * i.e. the products of Algorithm 4 (Appendix E).  A fiber is a maximal run
+ * of equal (root, mid); only nonempty fibers and roots are stored.
+ * Duplicate coordinates are summed (in input order).  nnz = 0 is valid.
+ *
+ * Errors: DFACTO_E_INVALID (null pointers with nnz > 0, dims outside
+ * [1, DFACTO_MAX_DIM], nnz < 0), DFACTO_E_RANGE (a coordinate out of range),
+ * DFACTO_E_NUMERIC (NaN/Inf value), DFACTO_E_UNSUPPORTED (too many
+ * entries), DFACTO_E_NOMEM.  This call synchronizes the stream.  The COO
+ * arrays are not retained.  *out is owned by the caller: free it with
+ * dfacto_tensor_destroy. */
+dfacto_status dfacto_build_flattenings(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
+                                       const uint32_t *d_i, const uint32_t *d_j,
+                                       const uint32_t *d_k, const float *d_val,
+                                       dfacto_tensor **out);
+
+typedef struct {
+    int64_t dims[3];
+    int64_t nnz;        /* distinct nonzeros after merging duplicates */
+    int64_t nfib[3];    /* nonempty fibers per mode: nnzc of the paper's flattening */
+    int64_t nroot[3];   /* nonempty output rows per mode */
+    int64_t nentry[3];  /* length of the per-mode stream (nonzeros + fiber headers) */
+    int64_t nchunk[3];  /* work chunks per mode */
+    double normsq;      /* ||X||^2 in FP64 */
+    size_t bytes;       /* device bytes held by the tensor */
+} dfacto_tensor_info;
+
+dfacto_status dfacto_tensor_get_info(const dfacto_tensor *t, dfacto_tensor_info *info);
+
+/* Copy mode `mode`'s flattening to host memory in CSR form, for inspection
+ * and tests: h_root_id[nroot], h_root_ptr[nroot+1] (fiber offsets),
+ * h_fib_mid[nfib], h_fib_ptr[nfib+1] (nonzero offsets), h_leaf[nnz],
+ * h_val[nnz].  Sizes come from dfacto_tensor_get_info.  Synchronizes. */
+dfacto_status dfacto_tensor_export(dfacto_ctx *ctx, const dfacto_tensor *t, int mode,
+                                   uint32_t *h_root_id, int64_t *h_root_ptr,
+                                   uint32_t *h_fib_mid, int64_t *h_fib_ptr,
+                                   uint32_t *h_leaf, float *h_val);
+
+/* Free a tensor (waits for the device).  NULL is ignored. */
+void dfacto_tensor_destroy(dfacto_tensor *t);
+
+/* ------------------------------------------------------------------ */
+/* hot path                                                             */
+/* ------------------------------------------------------------------ */
+
+/* MTTKRP of `mode`: d_out (dims[mode] x R, FP32, overwritten) =
+ *     mode 0: X1 (C kr B)    mode 1: X2 (A kr C)    mode 2: X3 (B kr A)
+ * with d_F = {A, B, C} (d_F[mode] is not read and may be NULL).
+ * Computed as Algorithm 1 for all R columns at once: per fiber the partial
+ * P = sum_leaf x * F_leaf[leaf, :] (the values of M^r, Lemma 2), then per
+ * output row the sum over its fibers of P * F_mid[mid, :]; FP32
+ * accumulation, factor rows widened from the storage dtype.  Rows with no
+ * nonzeros are written as zeros.  Enqueue only. */
+dfacto_status dfacto_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                            dfacto_dtype dtype, const void *const d_F[3], float *d_out);
+
+/* One CP-ALS iteration (Algorithm 2 / Algorithm 4), in place on
+ * d_F = {A, B, C}, modes updated in the order 0, 1, 2, each with the
+ * factors already updated:
+ *     M_n = MTTKRP(n);  H = (F_p^T F_p) * (F_q^T F_q) + reg I;
+ *     F_n = M_n H^{-1}  (FP64 Cholesky; Moore-Penrose pseudo-inverse when
+ *     H is numerically singular);  lambda_r = ||F_n[:, r]||_2;
+ *     F_n[:, r] /= lambda_r (zero columns stay zero, lambda_r = 0).
+ * reg is the ridge parameter of the regularized update (Appendix B),
+ * reg >= 0.  On return d_lambda (R doubles) holds the weights from the
+ * mode-2 normalization and *d_fit (one double) the fit
+ *     1 - ||X - [[lambda; A, B, C]]|| / ||X||   (0 when ||X|| = 0).
+ * Enqueue only (no host synchronization); d_lambda and d_fit are device
+ * pointers. */
+dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R,
+                              dfacto_dtype dtype, double reg, void *const d_F[3],
+                              double *d_lambda, double *d_fit);
+
+/* GD gradient (Appendix C; Algorithm 3) at the point d_F = {A, B, C} with
+ * unit weights, all three gradients at the same point:
+ *     d_G[n] = -MTTKRP(n) + F_n ((F_p^T F_p) * (F_q^T F_q) + reg I)
+ * (FP32, dims[n] x R each) and *d_f (device double) the objective
+ *     1/2 ||X - [[A, B, C]]||^2 + reg/2 (||A||^2 + ||B||^2 + ||C||^2),
+ * summed over every (i, j, k).  Enqueue only. */
+dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R,
+                             dfacto_dtype dtype, double reg, const void *const d_F[3],
+                             float *const d_G[3], double *d_f);
+
+/* ------------------------------------------------------------------ */
+/* measurement                                                          */
+/* ------------------------------------------------------------------ */
+
+/* Turn kernel timing on (1) or off (0) for `ctx`.  While on, every MTTKRP
+ * launch (also those inside dfacto_als_iter and dfacto_gd_grad) records a
+ * pair of HIP events on the context's stream around its main kernel, and
+ * adds the launch's algorithmic byte count (Section 3.2 work model:
+ * 8 B per stored nonzero, 8 B per fiber, 8 B per nonempty row, the output
+ * rows and one read of each factor that is gathered).  Turning it on
+ * clears earlier records. */
+dfacto_status dfacto_profile_enable(dfacto_ctx *ctx, int on);
+
+/* Synchronize and report what was recorded since timing was enabled (or
+ * last read): *launches main-kernel launches, *ms their summed duration,
+ * *bytes their summed algorithmic bytes, *flops their summed
+ * 2 R (nnz + nfib) flops.  Clears the records.  Any pointer may be NULL. */
+dfacto_status dfacto_profile_read(dfacto_ctx *ctx, int64_t *launches, double *ms, double *bytes,
+                                  double *flops);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DFACTO_H */

@@ -1,0 +1,641 @@
+// build.hip -- on-device construction of the three fiber-compressed
+// flattenings (DFacTo, Section 2.1 eq. (1); Section 3, the CSR storage of
+// (X2)^T without zero rows and the precomputed pattern of M^r, Lemmas 3-4).
+//
+// Pipeline (all on the device, one host readback per size that must be
+// known to allocate):
+//   validate -> stable LSD radix sort of the coordinates in mode-0 order
+//   (i, k, j) -> merge duplicates (sum in input order) -> ||X||^2 ->
+//   stable radix sorts by (j, i) and (k, j) for modes 1 and 2 (the mode-0
+//   order keeps leaves ascending inside every fiber) -> per mode: fiber
+//   and root flags, fiber segments of at most kFiberCap nonzeros, the
+//   interleaved header/nonzero stream, empty output rows, work chunks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace dfacto {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(int64_t n, int per_block = kThreads) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (1 << 20)) g = 1 << 20;  // grid-stride beyond this
+    return (unsigned)g;
+}
+
+#define GRID_STRIDE(e, n)                                                           \
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (n);       \
+         e += (int64_t)gridDim.x * blockDim.x)
+
+int bits_for(int64_t d) {  // bits needed to store indices 0 .. d-1
+    int b = 0;
+    while (((int64_t)1 << b) < d) ++b;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// simple elementwise kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_validate(const uint32_t *__restrict__ i, const uint32_t *__restrict__ j,
+                           const uint32_t *__restrict__ k, const float *__restrict__ v,
+                           int64_t n, uint32_t I, uint32_t J, uint32_t K,
+                           uint32_t *__restrict__ flag) {
+    uint32_t bad = 0;
+    GRID_STRIDE(e, n) {
+        if (i[e] >= I || j[e] >= J || k[e] >= K) bad |= 1u;
+        if (!isfinite(v[e])) bad |= 2u;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+__global__ void k_iota(uint32_t *__restrict__ p, int64_t n) {
+    GRID_STRIDE(e, n) p[e] = (uint32_t)e;
+}
+
+// key = (a << sa) | (b << sb) | c   from coordinate arrays, optionally
+// gathered through a permutation.
+__global__ void k_make_key(uint64_t *__restrict__ key, const uint32_t *__restrict__ a, int sa,
+                           const uint32_t *__restrict__ b, int sb,
+                           const uint32_t *__restrict__ c, const uint32_t *__restrict__ perm,
+                           int64_t n) {
+    GRID_STRIDE(e, n) {
+        const int64_t s = perm ? perm[e] : e;
+        uint64_t x = 0;
+        if (a) x |= (uint64_t)a[s] << sa;
+        if (b) x |= (uint64_t)b[s] << sb;
+        if (c) x |= (uint64_t)c[s];
+        key[e] = x;
+    }
+}
+
+__global__ void k_gather4(const uint32_t *__restrict__ perm, int64_t n,
+                          const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+                          const uint32_t *__restrict__ c, const float *__restrict__ v,
+                          uint32_t *__restrict__ oa, uint32_t *__restrict__ ob,
+                          uint32_t *__restrict__ oc, float *__restrict__ ov) {
+    GRID_STRIDE(e, n) {
+        const uint32_t s = perm[e];
+        oa[e] = a[s];
+        ob[e] = b[s];
+        oc[e] = c[s];
+        ov[e] = v[s];
+    }
+}
+
+// flag[e] = 1 where the sorted coordinate differs from its predecessor
+__global__ void k_distinct_flags(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+                                 const uint32_t *__restrict__ c, int64_t n,
+                                 uint32_t *__restrict__ flag) {
+    GRID_STRIDE(e, n) {
+        flag[e] = (e == 0 || a[e] != a[e - 1] || b[e] != b[e - 1] || c[e] != c[e - 1]) ? 1u : 0u;
+    }
+}
+
+// sum each run of equal coordinates in order; write the merged entry
+__global__ void k_merge_runs(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ pos,
+                             int64_t n, const uint32_t *__restrict__ a,
+                             const uint32_t *__restrict__ b, const uint32_t *__restrict__ c,
+                             const float *__restrict__ v, uint32_t *__restrict__ oa,
+                             uint32_t *__restrict__ ob, uint32_t *__restrict__ oc,
+                             float *__restrict__ ov) {
+    GRID_STRIDE(e, n) {
+        if (!flag[e]) continue;
+        float s = v[e];
+        for (int64_t t = e + 1; t < n && !flag[t]; ++t) s += v[t];
+        const uint32_t o = pos[e];
+        if (o >= n) continue;
+        oa[o] = a[e];
+        ob[o] = b[e];
+        oc[o] = c[e];
+        ov[o] = s;
+    }
+}
+
+// per-block partial sums of squares, fixed order
+__global__ void k_sumsq_partial(const float *__restrict__ v, int64_t n, double *__restrict__ part) {
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    GRID_STRIDE(e, n) {
+        const double x = v[e];
+        s += x * x;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_f64_final(const double *__restrict__ part, int n, double *__restrict__ out) {
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    for (int e = threadIdx.x; e < n; e += kThreads) s += part[e];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of u32 (three phases, recursive on block sums)
+// ---------------------------------------------------------------------------
+constexpr int kScanIpt = 8;
+constexpr int kScanTile = kThreads * kScanIpt;
+
+__device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *sh, uint32_t *total) {
+    // Hillis-Steele over kThreads values in LDS
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {
+        uint32_t y = ((int)threadIdx.x >= off) ? sh[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sh[threadIdx.x] += y;
+        __syncthreads();
+    }
+    const uint32_t incl = sh[threadIdx.x];
+    *total = sh[kThreads - 1];
+    __syncthreads();
+    return incl - x;
+}
+
+__global__ void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+                              uint32_t *__restrict__ bsum) {
+    __shared__ uint32_t sh[kThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (int q = 0; q < kScanIpt; ++q) {
+        const int64_t e = base + (int64_t)q * kThreads + threadIdx.x;
+        if (e < n) s += in[e];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+}
+
+__global__ void k_scan_apply(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                             int64_t n, const uint32_t *__restrict__ boff) {
+    __shared__ uint32_t sh[kThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIpt;
+    uint32_t v[kScanIpt];
+    uint32_t s = 0;
+    for (int q = 0; q < kScanIpt; ++q) {
+        const int64_t e = base + q;
+        v[q] = (e < n) ? in[e] : 0u;
+        s += v[q];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, sh, &total) + (boff ? boff[blockIdx.x] : 0u);
+    for (int q = 0; q < kScanIpt; ++q) {
+        const int64_t e = base + q;
+        if (e < n) out[e] = run;
+        run += v[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (u64 key, u32 value) pairs, 8-bit digits
+// ---------------------------------------------------------------------------
+constexpr int kRadixIpt = 8;
+constexpr int kRadixTile = kThreads * kRadixIpt;
+
+__global__ void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                             uint32_t *__restrict__ hist, int64_t nblk) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int q = 0; q < kRadixIpt; ++q) {
+        const int64_t e = base + (int64_t)q * kThreads + threadIdx.x;
+        if (e < n) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Keys of a tile are taken in the order q * 256 + tid; a key's rank among
+// equal digits of the tile is (keys of earlier slots) + (earlier waves of
+// this slot) + (earlier lanes of this wave), the last from 8 ballots that
+// isolate the lanes holding the same digit.
+__global__ void k_radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                int64_t n, int shift, const uint32_t *__restrict__ offs,
+                                int64_t nblk) {
+    __shared__ uint32_t s_run[256];
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_wc[kThreads / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    s_run[tid] = 0;
+    s_base[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int q = 0; q < kRadixIpt; ++q) {
+        const int64_t e = base + (int64_t)q * kThreads + tid;
+        const bool valid = e < n;
+        const uint64_t key = valid ? kin[e] : 0ull;
+        const uint32_t val = valid ? vin[e] : 0u;
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) s_wc[w][tid] = 0;
+        __syncthreads();
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(m & lt);
+        if (valid && rank == 0) s_wc[wave][d] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = s_run[d];
+            for (int w = 0; w < wave; ++w) pre += s_wc[w][d];
+            const uint32_t pos = s_base[d] + pre + rank;
+            if ((int64_t)pos < n) {  // always true for consistent histograms
+                kout[pos] = key;
+                vout[pos] = val;
+            }
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) add += s_wc[w][tid];
+        s_run[tid] += add;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-mode stream construction
+// ---------------------------------------------------------------------------
+
+__global__ void k_fiber_flags(const uint32_t *__restrict__ root, const uint32_t *__restrict__ mid,
+                              int64_t n, uint32_t *__restrict__ fs, uint32_t *__restrict__ rs) {
+    GRID_STRIDE(e, n) {
+        const bool r = (e == 0) || root[e] != root[e - 1];
+        const bool f = r || mid[e] != mid[e - 1];
+        fs[e] = f ? 1u : 0u;
+        rs[e] = r ? 1u : 0u;
+    }
+}
+
+__global__ void k_fiber_start_pos(const uint32_t *__restrict__ fs, const uint32_t *__restrict__ fid,
+                                  int64_t n, int64_t nfib, uint32_t *__restrict__ fptr) {
+    GRID_STRIDE(e, n) {
+        if (fs[e] && fid[e] < nfib) fptr[fid[e]] = (uint32_t)e;
+    }
+}
+
+// h[e] = 1 if a header precedes nonzero e: at every fiber start and every
+// kFiberCap nonzeros inside a fiber.
+__global__ void k_header_flags(const uint32_t *__restrict__ fs, const uint32_t *__restrict__ fid,
+                               const uint32_t *__restrict__ fptr, int64_t n, int64_t nfib,
+                               uint32_t *__restrict__ h) {
+    GRID_STRIDE(e, n) {
+        const uint32_t f = fid[e] + fs[e] - 1u;  // fiber index (inclusive count - 1)
+        const uint32_t off = (f < nfib) ? (uint32_t)e - fptr[f] : 0u;
+        h[e] = (fs[e] || (off % (uint32_t)kFiberCap) == 0u) ? 1u : 0u;
+    }
+}
+
+__global__ void k_emit_stream(const uint32_t *__restrict__ root, const uint32_t *__restrict__ mid,
+                              const uint32_t *__restrict__ leaf, const float *__restrict__ val,
+                              const uint32_t *__restrict__ h, const uint32_t *__restrict__ hex,
+                              const uint32_t *__restrict__ rs, int64_t n, int64_t L,
+                              uint2 *__restrict__ st) {
+    GRID_STRIDE(e, n) {
+        const uint32_t pos = (uint32_t)e + hex[e] + h[e];
+        if ((int64_t)pos >= L) continue;  // never taken when the scan is consistent
+        if (h[e]) {
+            st[pos - 1] = make_uint2(kHdrBit | (rs[e] ? kRootBit : 0u) | mid[e], root[e]);
+        }
+        st[pos] = make_uint2(leaf[e], __float_as_uint(val[e]));
+    }
+}
+
+__global__ void k_fill_pad(uint2 *__restrict__ st, int64_t from, int64_t count) {
+    GRID_STRIDE(e, count) st[from + e] = make_uint2(kHdrBit | kRootBit, 0u);
+}
+
+__global__ void k_mark_rows(const uint32_t *__restrict__ root, const uint32_t *__restrict__ rs,
+                            int64_t n, int64_t nrows, uint32_t *__restrict__ mark) {
+    GRID_STRIDE(e, n) {
+        if (rs[e] && root[e] < nrows) mark[root[e]] = 0u;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
+    GRID_STRIDE(e, n) p[e] = v;
+}
+
+__global__ void k_compact_rows(const uint32_t *__restrict__ mark, const uint32_t *__restrict__ pos,
+                               int64_t n, uint32_t *__restrict__ out) {
+    GRID_STRIDE(e, n) {
+        if (mark[e]) out[pos[e]] = (uint32_t)e;
+    }
+}
+
+// chunk c starts at the first header at or after c * len (or at the end)
+__global__ void k_chunk_starts(const uint2 *__restrict__ st, int64_t nentry, int64_t nchunk,
+                               int len, uint32_t *__restrict__ cs) {
+    GRID_STRIDE(c, nchunk + 1) {
+        int64_t p = c * (int64_t)len;
+        if (c == nchunk || p >= nentry) {
+            p = nentry;
+        } else {
+            while (p < nentry && !(st[p].x & kHdrBit)) ++p;
+        }
+        cs[c] = (uint32_t)p;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+
+struct Scratch {
+    std::vector<void *> ptrs;
+    ~Scratch() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    T *alloc(int64_t n) {
+        void *p = nullptr;
+        const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{DFACTO_E_NOMEM, "device allocation of " + std::to_string(bytes) +
+                                            " bytes failed while building the flattenings"};
+        }
+        ptrs.push_back(p);
+        return (T *)p;
+    }
+    void release(void *p) {
+        for (auto &q : ptrs)
+            if (q == p) {
+                (void)hipFree(q);
+                q = nullptr;
+            }
+    }
+};
+
+template <typename T>
+T *tensor_alloc(dfacto_tensor *t, int64_t n) {
+    void *p = nullptr;
+    const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{DFACTO_E_NOMEM, "device allocation of " + std::to_string(bytes) +
+                                        " bytes failed for the flattenings"};
+    }
+    t->allocations.push_back(p);
+    t->bytes += bytes;
+    return (T *)p;
+}
+
+template <typename T>
+T read_back(const T *d, hipStream_t s) {
+    T h;
+    DF_HIP(hipMemcpyAsync(&h, d, sizeof(T), hipMemcpyDeviceToHost, s));
+    DF_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+void radix_sort(uint64_t *&keys, uint32_t *&vals, uint64_t *&kalt, uint32_t *&valt, int64_t n,
+                int bits, Scratch &sc, hipStream_t s) {
+    if (n <= 1 || bits <= 0) return;
+    const int64_t nblk = (n + kRadixTile - 1) / kRadixTile;
+    uint32_t *hist = sc.alloc<uint32_t>(256 * nblk);
+    uint32_t *offs = sc.alloc<uint32_t>(256 * nblk);
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(kThreads), 0, s, keys, n,
+                           shift, hist, nblk);
+        scan_exclusive_u32(hist, offs, 256 * nblk, s);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, keys,
+                           vals, kalt, valt, n, shift, offs, nblk);
+        std::swap(keys, kalt);
+        std::swap(vals, valt);
+    }
+    DF_HIP(hipGetLastError());
+    sc.release(hist);
+    sc.release(offs);
+}
+
+void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
+                const uint32_t *mid, const uint32_t *leaf, const float *val, int64_t n) {
+    hipStream_t s = ctx->stream;
+    ModeData &md = t->mode[m];
+    const int64_t nrows = t->dims[md.root];
+    Scratch sc;
+    int chunk_len = 4 * kFiberCap;
+    if (const char *env = getenv("DFACTO_CHUNK")) {
+        const int v = atoi(env);
+        if (v >= 2 * kFiberCap && v <= (1 << 20)) chunk_len = v;
+    }
+    md.chunk_len = chunk_len;
+    if (n == 0) {
+        md.nentry = 0;
+        md.nfib = md.nroot = 0;
+        md.stream = tensor_alloc<uint2>(t, kStreamPad);
+        hipLaunchKernelGGL(k_fill_pad, dim3(1), dim3(kThreads), 0, s, md.stream, (int64_t)0,
+                           (int64_t)kStreamPad);
+        md.nchunk = 0;
+        md.chunk_start = tensor_alloc<uint32_t>(t, 1);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kThreads), 0, s, md.chunk_start,
+                           (int64_t)1, 0u);
+        md.nempty = nrows;
+        md.empty_rows = tensor_alloc<uint32_t>(t, nrows);
+        uint32_t *mark = sc.alloc<uint32_t>(nrows);
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, nrows,
+                           1u);
+        uint32_t *pos = sc.alloc<uint32_t>(nrows);
+        scan_exclusive_u32(mark, pos, nrows, s);
+        hipLaunchKernelGGL(k_compact_rows, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, pos,
+                           nrows, md.empty_rows);
+        DF_HIP(hipGetLastError());
+        DF_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    uint32_t *fs = sc.alloc<uint32_t>(n);
+    uint32_t *rs = sc.alloc<uint32_t>(n);
+    uint32_t *fid = sc.alloc<uint32_t>(n);
+    hipLaunchKernelGGL(k_fiber_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, root, mid, n, fs,
+                       rs);
+    scan_exclusive_u32(fs, fid, n, s);
+    md.nfib = (int64_t)read_back(fid + n - 1, s) + read_back(fs + n - 1, s);
+    uint32_t *fptr = sc.alloc<uint32_t>(md.nfib);
+    hipLaunchKernelGGL(k_fiber_start_pos, dim3(grid_for(n)), dim3(kThreads), 0, s, fs, fid, n,
+                       md.nfib, fptr);
+    uint32_t *h = sc.alloc<uint32_t>(n);
+    hipLaunchKernelGGL(k_header_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, fs, fid, fptr, n,
+                       md.nfib, h);
+    sc.release(fptr);
+    uint32_t *hex = fid;  // reuse
+    scan_exclusive_u32(h, hex, n, s);
+    const int64_t nhdr = (int64_t)read_back(hex + n - 1, s) + read_back(h + n - 1, s);
+    const int64_t L = n + nhdr;
+    if (L > (int64_t)0xFFFFFFFFu - (1 << 20))
+        throw Error{DFACTO_E_UNSUPPORTED, "nonzeros plus fiber headers exceed 2^32 - 2^20"};
+    md.nentry = L;
+    md.stream = tensor_alloc<uint2>(t, L + kStreamPad);
+    hipLaunchKernelGGL(k_emit_stream, dim3(grid_for(n)), dim3(kThreads), 0, s, root, mid, leaf, val,
+                       h, hex, rs, n, L, md.stream);
+    hipLaunchKernelGGL(k_fill_pad, dim3(1), dim3(kThreads), 0, s, md.stream, L,
+                       (int64_t)kStreamPad);
+    // roots and empty output rows
+    uint32_t *mark = sc.alloc<uint32_t>(nrows);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, nrows, 1u);
+    hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(n)), dim3(kThreads), 0, s, root, rs, n, nrows,
+                       mark);
+    uint32_t *rpos = sc.alloc<uint32_t>(nrows);
+    scan_exclusive_u32(mark, rpos, nrows, s);
+    md.nempty = (int64_t)read_back(rpos + nrows - 1, s) + read_back(mark + nrows - 1, s);
+    md.nroot = nrows - md.nempty;
+    md.empty_rows = tensor_alloc<uint32_t>(t, md.nempty);
+    hipLaunchKernelGGL(k_compact_rows, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, rpos,
+                       nrows, md.empty_rows);
+    // work chunks
+    md.nchunk = (L + chunk_len - 1) / chunk_len;
+    md.chunk_start = tensor_alloc<uint32_t>(t, md.nchunk + 1);
+    hipLaunchKernelGGL(k_chunk_starts, dim3(grid_for(md.nchunk + 1)), dim3(kThreads), 0, s,
+                       md.stream, L, md.nchunk, chunk_len, md.chunk_start);
+    DF_HIP(hipGetLastError());
+    DF_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kThreads), 0, s, in, out, n,
+                           (const uint32_t *)nullptr);
+        return;
+    }
+    uint32_t *bsum = nullptr, *boff = nullptr;
+    DF_HIP(hipMallocAsync((void **)&bsum, sizeof(uint32_t) * nb, s));
+    DF_HIP(hipMallocAsync((void **)&boff, sizeof(uint32_t) * nb, s));
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, in, n, bsum);
+    scan_exclusive_u32(bsum, boff, nb, s);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, in, out, n,
+                       (const uint32_t *)boff);
+    DF_HIP(hipFreeAsync(bsum, s));
+    DF_HIP(hipFreeAsync(boff, s));
+}
+
+void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const uint32_t *d_j,
+                  const uint32_t *d_k, const float *d_val) {
+    hipStream_t s = ctx->stream;
+    const int64_t n = t->nnz;
+    Scratch sc;
+    static const int ROOT[3] = {0, 1, 2}, MID[3] = {2, 0, 1}, LEAF[3] = {1, 2, 0};
+    for (int m = 0; m < 3; ++m) {
+        t->mode[m].root = ROOT[m];
+        t->mode[m].mid = MID[m];
+        t->mode[m].leaf = LEAF[m];
+    }
+    if (n > 0) {
+        uint32_t *flag = sc.alloc<uint32_t>(1);
+        DF_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t), s));
+        hipLaunchKernelGGL(k_validate, dim3(grid_for(n)), dim3(kThreads), 0, s, d_i, d_j, d_k,
+                           d_val, n, (uint32_t)t->dims[0], (uint32_t)t->dims[1],
+                           (uint32_t)t->dims[2], flag);
+        DF_HIP(hipGetLastError());
+        const uint32_t bad = read_back(flag, s);
+        if (bad & 1u) throw Error{DFACTO_E_RANGE, "a coordinate is not below its dimension"};
+        if (bad & 2u) throw Error{DFACTO_E_NUMERIC, "a tensor value is NaN or Inf"};
+    }
+    if (n == 0) {
+        t->normsq = 0.0;
+        for (int m = 0; m < 3; ++m) build_mode(ctx, t, m, nullptr, nullptr, nullptr, nullptr, 0);
+        return;
+    }
+    const int bI = bits_for(t->dims[0]), bJ = bits_for(t->dims[1]), bK = bits_for(t->dims[2]);
+    uint64_t *key = sc.alloc<uint64_t>(n), *kalt = sc.alloc<uint64_t>(n);
+    uint32_t *perm = sc.alloc<uint32_t>(n), *palt = sc.alloc<uint32_t>(n);
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(kThreads), 0, s, perm, n);
+    // mode-0 order (i, k, j)
+    if (bI + bK + bJ <= 64) {
+        hipLaunchKernelGGL(k_make_key, dim3(grid_for(n)), dim3(kThreads), 0, s, key, d_i, bK + bJ,
+                           d_k, bJ, d_j, (const uint32_t *)nullptr, n);
+        radix_sort(key, perm, kalt, palt, n, bI + bK + bJ, sc, s);
+    } else {
+        hipLaunchKernelGGL(k_make_key, dim3(grid_for(n)), dim3(kThreads), 0, s, key,
+                           (const uint32_t *)nullptr, 0, (const uint32_t *)nullptr, 0, d_j,
+                           (const uint32_t *)nullptr, n);
+        radix_sort(key, perm, kalt, palt, n, bJ, sc, s);
+        hipLaunchKernelGGL(k_make_key, dim3(grid_for(n)), dim3(kThreads), 0, s, key, d_i, bK, d_k,
+                           0, (const uint32_t *)nullptr, (const uint32_t *)perm, n);
+        radix_sort(key, perm, kalt, palt, n, bI + bK, sc, s);
+    }
+    sc.release(key);
+    sc.release(kalt);
+    // gather into sorted coordinates and merge duplicates
+    uint32_t *si = sc.alloc<uint32_t>(n), *sj = sc.alloc<uint32_t>(n), *sk = sc.alloc<uint32_t>(n);
+    float *sv = sc.alloc<float>(n);
+    hipLaunchKernelGGL(k_gather4, dim3(grid_for(n)), dim3(kThreads), 0, s, perm, n, d_i, d_j, d_k,
+                       d_val, si, sj, sk, sv);
+    uint32_t *dflag = perm, *dpos = palt;  // reuse
+    hipLaunchKernelGGL(k_distinct_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, si, sj, sk, n,
+                       dflag);
+    scan_exclusive_u32(dflag, dpos, n, s);
+    const int64_t nd = (int64_t)read_back(dpos + n - 1, s) + read_back(dflag + n - 1, s);
+    uint32_t *di = sc.alloc<uint32_t>(nd), *dj = sc.alloc<uint32_t>(nd), *dk = sc.alloc<uint32_t>(nd);
+    float *dv = sc.alloc<float>(nd);
+    hipLaunchKernelGGL(k_merge_runs, dim3(grid_for(n)), dim3(kThreads), 0, s, dflag, dpos, n, si,
+                       sj, sk, sv, di, dj, dk, dv);
+    DF_HIP(hipGetLastError());
+    sc.release(si);
+    sc.release(sj);
+    sc.release(sk);
+    sc.release(sv);
+    t->nnz = nd;
+    // ||X||^2 in FP64, fixed reduction order
+    {
+        const unsigned nb = std::min<unsigned>(grid_for(nd), 1024u);
+        double *part = sc.alloc<double>(nb), *tot = sc.alloc<double>(1);
+        hipLaunchKernelGGL(k_sumsq_partial, dim3(nb), dim3(kThreads), 0, s, dv, nd, part);
+        hipLaunchKernelGGL(k_sum_f64_final, dim3(1), dim3(kThreads), 0, s, part, (int)nb, tot);
+        t->normsq = read_back(tot, s);
+    }
+    // mode 0: already in (i, k, j) order
+    build_mode(ctx, t, 0, di, dk, dj, dv, nd);
+    // modes 1 and 2: stable sort by (root, mid) from the mode-0 order
+    uint64_t *key2 = sc.alloc<uint64_t>(nd), *kalt2 = sc.alloc<uint64_t>(nd);
+    uint32_t *p2 = perm, *palt2 = palt;  // n >= nd
+    uint32_t *gr = sc.alloc<uint32_t>(nd), *gm = sc.alloc<uint32_t>(nd), *gl = sc.alloc<uint32_t>(nd);
+    float *gv = sc.alloc<float>(nd);
+    const uint32_t *coord[3] = {di, dj, dk};
+    const int bits[3] = {bI, bJ, bK};
+    for (int m = 1; m < 3; ++m) {
+        const ModeData &md = t->mode[m];
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(nd)), dim3(kThreads), 0, s, p2, nd);
+        hipLaunchKernelGGL(k_make_key, dim3(grid_for(nd)), dim3(kThreads), 0, s, key2,
+                           coord[md.root], bits[md.mid], coord[md.mid], 0,
+                           (const uint32_t *)nullptr, (const uint32_t *)nullptr, nd);
+        radix_sort(key2, p2, kalt2, palt2, nd, bits[md.root] + bits[md.mid], sc, s);
+        hipLaunchKernelGGL(k_gather4, dim3(grid_for(nd)), dim3(kThreads), 0, s, p2, nd,
+                           coord[md.root], coord[md.mid], coord[md.leaf], dv, gr, gm, gl, gv);
+        DF_HIP(hipGetLastError());
+        build_mode(ctx, t, m, gr, gm, gl, gv, nd);
+    }
+}
+
+}  // namespace dfacto

@@ -1,0 +1,389 @@
+// capi.hip -- the extern "C" entry points declared in include/dfacto.h:
+// argument validation, context and workspace management, and the order of
+// kernel launches for MTTKRP, one CP-ALS iteration and the GD gradient.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace dfacto {
+
+dfacto_status fail(dfacto_ctx *ctx, dfacto_status code, const std::string &msg) {
+    if (ctx) {
+        ctx->err = msg;
+        if (code == DFACTO_E_DEVICE) ctx->sticky = true;
+    }
+    return code;
+}
+
+void hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    const dfacto_status code = (e == hipErrorOutOfMemory) ? DFACTO_E_NOMEM : DFACTO_E_DEVICE;
+    (void)hipGetLastError();
+    throw Error{code, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+void *ws_get(dfacto_ctx *ctx, dfacto_ctx::Slot slot, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (ctx->ws_size[slot] >= bytes) return ctx->ws[slot];
+    if (ctx->ws[slot]) {
+        DF_HIP(hipStreamSynchronize(ctx->stream));
+        DF_HIP(hipFree(ctx->ws[slot]));
+        ctx->ws[slot] = nullptr;
+        ctx->ws_size[slot] = 0;
+    }
+    const size_t grow = bytes + bytes / 8;
+    void *p = nullptr;
+    hip_check(hipMalloc(&p, grow), "workspace hipMalloc");
+    ctx->ws[slot] = p;
+    ctx->ws_size[slot] = grow;
+    return p;
+}
+
+void prof_mark(dfacto_ctx *ctx) {
+    if (!ctx->profiling) return;
+    if (ctx->ev_used == ctx->ev_pool.size()) {
+        hipEvent_t e;
+        DF_HIP(hipEventCreate(&e));
+        ctx->ev_pool.push_back(e);
+    }
+    DF_HIP(hipEventRecord(ctx->ev_pool[ctx->ev_used++], ctx->stream));
+}
+
+namespace {
+
+// Make the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) DF_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename F>
+dfacto_status guarded(dfacto_ctx *ctx, F &&body) {
+    if (!ctx) return DFACTO_E_INVALID;
+    if (ctx->sticky) return DFACTO_E_DEVICE;
+    try {
+        DeviceGuard g(ctx->device);
+        body();
+        ctx->err.clear();
+        return DFACTO_OK;
+    } catch (const Error &e) {
+        return fail(ctx, e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DFACTO_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DFACTO_E_DEVICE, "unexpected exception");
+    }
+}
+
+void check_common(const dfacto_tensor *t, int R, dfacto_dtype dtype) {
+    if (!t) throw Error{DFACTO_E_INVALID, "tensor is NULL"};
+    if (R < 1 || R > DFACTO_MAX_R) throw Error{DFACTO_E_INVALID, "R must be in [1, 256]"};
+    if (dtype != DFACTO_F32 && dtype != DFACTO_BF16) throw Error{DFACTO_E_INVALID, "bad dtype"};
+}
+
+void check_factor(const void *p, const char *name) {
+    if (!p) throw Error{DFACTO_E_INVALID, std::string(name) + " is NULL"};
+}
+
+size_t elem_size(dfacto_dtype d) { return d == DFACTO_BF16 ? 2 : 4; }
+
+void check_align(const void *p, dfacto_dtype d, const char *name) {
+    if ((uintptr_t)p % elem_size(d) != 0)
+        throw Error{DFACTO_E_INVALID, std::string(name) + " is not aligned to its element size"};
+}
+
+int64_t max_dim(const dfacto_tensor *t) {
+    return std::max(t->dims[0], std::max(t->dims[1], t->dims[2]));
+}
+
+// small FP64 workspace layout (units of doubles)
+struct Small {
+    double *G[3], *Hinv, *W, *MtM, *solve_scratch, *lam_scratch, *H[3], *part0, *part_dummy;
+    int *flag;
+};
+
+Small small_ws(dfacto_ctx *ctx, int R) {
+    const size_t RR = (size_t)R * R;
+    const size_t n = 3 * RR + 3 * RR + 3 * RR + (2 * RR + R) + 3 * RR + 2 * 8192 + 64;
+    double *b = (double *)ws_get(ctx, dfacto_ctx::kSmall, sizeof(double) * n);
+    Small s;
+    size_t o = 0;
+    for (int m = 0; m < 3; ++m) s.G[m] = b + o, o += RR;
+    s.Hinv = b + o, o += RR;
+    s.W = b + o, o += RR;
+    s.MtM = b + o, o += RR;
+    s.solve_scratch = b + o, o += 3 * RR;
+    s.lam_scratch = b + o, o += 2 * RR + R;
+    for (int m = 0; m < 3; ++m) s.H[m] = b + o, o += RR;
+    s.part0 = b + o, o += 8192;
+    s.part_dummy = b + o, o += 8192;
+    s.flag = (int *)(b + o);
+    return s;
+}
+
+}  // namespace
+}  // namespace dfacto
+
+using namespace dfacto;
+
+extern "C" {
+
+dfacto_status dfacto_ctx_create(int device, void *hip_stream, dfacto_ctx **out) {
+    if (!out) return DFACTO_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return DFACTO_E_DEVICE;
+    }
+    if (device < 0 || device >= n) return DFACTO_E_INVALID;
+    dfacto_ctx *ctx = new (std::nothrow) dfacto_ctx();
+    if (!ctx) return DFACTO_E_NOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+    *out = ctx;
+    return DFACTO_OK;
+}
+
+dfacto_status dfacto_ctx_set_stream(dfacto_ctx *ctx, void *hip_stream) {
+    if (!ctx) return DFACTO_E_INVALID;
+    ctx->stream = (hipStream_t)hip_stream;
+    return DFACTO_OK;
+}
+
+dfacto_status dfacto_ctx_synchronize(dfacto_ctx *ctx) {
+    return guarded(ctx, [&] { DF_HIP(hipStreamSynchronize(ctx->stream)); });
+}
+
+void dfacto_ctx_destroy(dfacto_ctx *ctx) {
+    if (!ctx) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int s = 0; s < dfacto_ctx::kNumSlots; ++s)
+        if (ctx->ws[s]) (void)hipFree(ctx->ws[s]);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    delete ctx;
+}
+
+const char *dfacto_last_error(const dfacto_ctx *ctx) {
+    if (!ctx) return "context is NULL";
+    return ctx->err.c_str();
+}
+
+dfacto_status dfacto_build_flattenings(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
+                                       const uint32_t *d_i, const uint32_t *d_j,
+                                       const uint32_t *d_k, const float *d_val,
+                                       dfacto_tensor **out) {
+    if (out) *out = nullptr;
+    return guarded(ctx, [&] {
+        if (!out || !dims) throw Error{DFACTO_E_INVALID, "dims or out is NULL"};
+        for (int m = 0; m < 3; ++m)
+            if (dims[m] < 1 || dims[m] > DFACTO_MAX_DIM)
+                throw Error{DFACTO_E_INVALID, "every dimension must be in [1, 2^30]"};
+        if (nnz < 0) throw Error{DFACTO_E_INVALID, "nnz is negative"};
+        if (nnz > 0 && (!d_i || !d_j || !d_k || !d_val))
+            throw Error{DFACTO_E_INVALID, "coordinate or value array is NULL"};
+        if (nnz >= (int64_t)0xFFFFFFFFu - (1 << 20))
+            throw Error{DFACTO_E_UNSUPPORTED, "nnz must be below 2^32 - 2^20"};
+        dfacto_tensor *t = new dfacto_tensor();
+        t->device = ctx->device;
+        for (int m = 0; m < 3; ++m) t->dims[m] = dims[m];
+        t->nnz = nnz;
+        try {
+            build_tensor(ctx, t, d_i, d_j, d_k, d_val);
+        } catch (...) {
+            dfacto_tensor_destroy(t);
+            throw;
+        }
+        *out = t;
+    });
+}
+
+dfacto_status dfacto_tensor_get_info(const dfacto_tensor *t, dfacto_tensor_info *info) {
+    if (!t || !info) return DFACTO_E_INVALID;
+    memset(info, 0, sizeof(*info));
+    for (int m = 0; m < 3; ++m) {
+        info->dims[m] = t->dims[m];
+        info->nfib[m] = t->mode[m].nfib;
+        info->nroot[m] = t->mode[m].nroot;
+        info->nentry[m] = t->mode[m].nentry;
+        info->nchunk[m] = t->mode[m].nchunk;
+    }
+    info->nnz = t->nnz;
+    info->normsq = t->normsq;
+    info->bytes = t->bytes;
+    return DFACTO_OK;
+}
+
+dfacto_status dfacto_tensor_export(dfacto_ctx *ctx, const dfacto_tensor *t, int mode,
+                                   uint32_t *h_root_id, int64_t *h_root_ptr, uint32_t *h_fib_mid,
+                                   int64_t *h_fib_ptr, uint32_t *h_leaf, float *h_val) {
+    return guarded(ctx, [&] {
+        if (!t) throw Error{DFACTO_E_INVALID, "tensor is NULL"};
+        if (mode < 0 || mode > 2) throw Error{DFACTO_E_INVALID, "mode must be 0, 1 or 2"};
+        if (!h_root_id || !h_root_ptr || !h_fib_mid || !h_fib_ptr || !h_leaf || !h_val)
+            throw Error{DFACTO_E_INVALID, "an output array is NULL"};
+        const ModeData &md = t->mode[mode];
+        std::vector<uint2> st((size_t)md.nentry);
+        if (md.nentry > 0) {
+            DF_HIP(hipMemcpyAsync(st.data(), md.stream, sizeof(uint2) * md.nentry,
+                                  hipMemcpyDeviceToHost, ctx->stream));
+        }
+        DF_HIP(hipStreamSynchronize(ctx->stream));
+        int64_t nr = 0, nf = 0, ne = 0;
+        uint32_t last_mid = 0;
+        for (const uint2 &w : st) {
+            if (w.x & kHdrBit) {
+                const uint32_t mid = w.x & kIdxMask;
+                const bool root = (w.x & kRootBit) != 0;
+                if (root) {
+                    h_root_id[nr] = w.y;
+                    h_root_ptr[nr] = nf;
+                    ++nr;
+                }
+                if (root || mid != last_mid) {  // else: continuation segment of the same fiber
+                    h_fib_mid[nf] = mid;
+                    h_fib_ptr[nf] = ne;
+                    ++nf;
+                }
+                last_mid = mid;
+            } else {
+                h_leaf[ne] = w.x;
+                uint32_t b = w.y;
+                memcpy(&h_val[ne], &b, sizeof(float));
+                ++ne;
+            }
+        }
+        h_root_ptr[nr] = nf;
+        h_fib_ptr[nf] = ne;
+        if (nr != md.nroot || nf != md.nfib || ne != t->nnz)
+            throw Error{DFACTO_E_DEVICE, "flattening stream is inconsistent with its counts"};
+    });
+}
+
+void dfacto_tensor_destroy(dfacto_tensor *t) {
+    if (!t) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(t->device);
+    (void)hipDeviceSynchronize();
+    for (void *p : t->allocations) (void)hipFree(p);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    delete t;
+}
+
+dfacto_status dfacto_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                            dfacto_dtype dtype, const void *const d_F[3], float *d_out) {
+    return guarded(ctx, [&] {
+        check_common(t, R, dtype);
+        if (mode < 0 || mode > 2) throw Error{DFACTO_E_INVALID, "mode must be 0, 1 or 2"};
+        if (!d_F || !d_out) throw Error{DFACTO_E_INVALID, "factor array or output is NULL"};
+        const ModeData &md = t->mode[mode];
+        check_factor(d_F[md.leaf], "leaf factor");
+        check_factor(d_F[md.mid], "mid factor");
+        check_align(d_F[md.leaf], dtype, "leaf factor");
+        check_align(d_F[md.mid], dtype, "mid factor");
+        if ((uintptr_t)d_out % 4) throw Error{DFACTO_E_INVALID, "output is not 4-byte aligned"};
+        launch_mttkrp(ctx, t, mode, R, dtype, d_F[md.leaf], d_F[md.mid], d_out);
+    });
+}
+
+dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfacto_dtype dtype,
+                              double reg, void *const d_F[3], double *d_lambda, double *d_fit) {
+    return guarded(ctx, [&] {
+        check_common(t, R, dtype);
+        if (!d_F || !d_lambda || !d_fit) throw Error{DFACTO_E_INVALID, "NULL argument"};
+        if (!(reg >= 0.0)) throw Error{DFACTO_E_INVALID, "reg must be >= 0"};
+        for (int m = 0; m < 3; ++m) {
+            check_factor(d_F[m], "factor");
+            check_align(d_F[m], dtype, "factor");
+        }
+        Small sw = small_ws(ctx, R);
+        float *M = (float *)ws_get(ctx, dfacto_ctx::kM, sizeof(float) * (size_t)max_dim(t) * R);
+        launch_gram(ctx, d_F[1], dtype, t->dims[1], R, sw.G[1]);
+        launch_gram(ctx, d_F[2], dtype, t->dims[2], R, sw.G[2]);
+        for (int n = 0; n < 3; ++n) {
+            const int p = (n + 1) % 3, q = (n + 2) % 3;
+            const ModeData &md = t->mode[n];
+            launch_solve(ctx, R, sw.G[p], sw.G[q], reg, sw.Hinv, sw.solve_scratch, sw.flag + n);
+            launch_mttkrp(ctx, t, n, R, dtype, d_F[md.leaf], d_F[md.mid], M);
+            launch_gram(ctx, M, DFACTO_F32, t->dims[n], R, sw.MtM);
+            launch_als_lambda(ctx, R, n, sw.Hinv, sw.MtM, sw.G[n], sw.W, d_lambda, sw.G[0],
+                              sw.G[1], t->normsq, d_fit, sw.lam_scratch);
+            launch_rowmap(ctx, M, t->dims[n], R, sw.W, d_F[n], dtype);
+        }
+    });
+}
+
+dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfacto_dtype dtype,
+                             double reg, const void *const d_F[3], float *const d_G[3],
+                             double *d_f) {
+    return guarded(ctx, [&] {
+        check_common(t, R, dtype);
+        if (!d_F || !d_G || !d_f) throw Error{DFACTO_E_INVALID, "NULL argument"};
+        if (!(reg >= 0.0)) throw Error{DFACTO_E_INVALID, "reg must be >= 0"};
+        for (int m = 0; m < 3; ++m) {
+            check_factor(d_F[m], "factor");
+            check_align(d_F[m], dtype, "factor");
+            if (!d_G[m]) throw Error{DFACTO_E_INVALID, "gradient output is NULL"};
+            if ((uintptr_t)d_G[m] % 4) throw Error{DFACTO_E_INVALID, "gradient not aligned"};
+        }
+        Small sw = small_ws(ctx, R);
+        for (int m = 0; m < 3; ++m) launch_gram(ctx, d_F[m], dtype, t->dims[m], R, sw.G[m]);
+        for (int n = 0; n < 3; ++n)
+            launch_hadamard(ctx, R, sw.G[(n + 1) % 3], sw.G[(n + 2) % 3], reg, sw.H[n]);
+        for (int n = 0; n < 3; ++n) {
+            const ModeData &md = t->mode[n];
+            launch_mttkrp(ctx, t, n, R, dtype, d_F[md.leaf], d_F[md.mid], d_G[n]);
+            launch_gd_rows(ctx, d_G[n], d_F[n], dtype, t->dims[n], R, sw.H[n],
+                           n == 0 ? sw.part0 : sw.part_dummy);
+        }
+        launch_gd_f(ctx, R, sw.G[0], sw.G[1], sw.G[2], sw.part0, gd_rows_partials(t->dims[0], R),
+                    t->normsq, reg, d_f);
+    });
+}
+
+dfacto_status dfacto_profile_enable(dfacto_ctx *ctx, int on) {
+    return guarded(ctx, [&] {
+        ctx->profiling = on != 0;
+        ctx->ev_used = 0;
+        ctx->prof_bytes = ctx->prof_flops = 0.0;
+    });
+}
+
+dfacto_status dfacto_profile_read(dfacto_ctx *ctx, int64_t *launches, double *ms, double *bytes,
+                                  double *flops) {
+    return guarded(ctx, [&] {
+        DF_HIP(hipStreamSynchronize(ctx->stream));
+        double total = 0.0;
+        for (size_t e = 0; e + 1 < ctx->ev_used; e += 2) {
+            float t = 0.f;
+            DF_HIP(hipEventElapsedTime(&t, ctx->ev_pool[e], ctx->ev_pool[e + 1]));
+            total += t;
+        }
+        if (launches) *launches = (int64_t)(ctx->ev_used / 2);
+        if (ms) *ms = total;
+        if (bytes) *bytes = ctx->prof_bytes;
+        if (flops) *flops = ctx->prof_flops;
+        ctx->ev_used = 0;
+        ctx->prof_bytes = ctx->prof_flops = 0.0;
+    });
+}
+
+}  // extern "C"

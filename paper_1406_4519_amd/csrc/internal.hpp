@@ -1,0 +1,126 @@
+// internal.hpp -- shared declarations of the DFacTo HIP library (not public).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "dfacto.h"
+
+namespace dfacto {
+
+// ---------------------------------------------------------------------------
+// Per-mode stream layout (one 8-byte entry per nonzero or fiber header)
+//
+//   nonzero : x = leaf index,                      y = float bits of the value
+//   header  : x = HDR | (ROOT if a root starts) | mid index,   y = output row
+//
+// A header opens a fiber segment: the nonzeros that follow, up to the next
+// header, share (root, mid).  Fibers longer than kFiberCap nonzeros are cut
+// into segments, each with its own header (same root and mid, no ROOT bit),
+// so that work chunks -- which always start at a header -- stay balanced.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kHdrBit = 0x80000000u;
+constexpr uint32_t kRootBit = 0x40000000u;
+constexpr uint32_t kIdxMask = 0x3FFFFFFFu;
+constexpr int kFiberCap = 128;     // max nonzeros per fiber segment
+constexpr int kStreamPad = 64;     // sentinel entries after the stream end
+
+struct ModeData {
+    int root = 0, mid = 0, leaf = 0;   // coordinate axes (0 = i, 1 = j, 2 = k)
+    uint2 *stream = nullptr;           // nentry + kStreamPad entries
+    int64_t nentry = 0;
+    int64_t nfib = 0, nroot = 0;
+    uint32_t *empty_rows = nullptr;    // output rows with no nonzeros
+    int64_t nempty = 0;
+    // work chunks: chunk c covers stream entries [chunk_start[c], chunk_start[c+1])
+    uint32_t *chunk_start = nullptr;   // nchunk + 1 entries
+    int64_t nchunk = 0;
+    int chunk_len = 0;                 // target entries per chunk
+};
+
+}  // namespace dfacto
+
+struct dfacto_tensor {
+    int device = 0;
+    int64_t dims[3] = {0, 0, 0};
+    int64_t nnz = 0;
+    double normsq = 0.0;
+    size_t bytes = 0;
+    dfacto::ModeData mode[3];
+    std::vector<void *> allocations;
+};
+
+struct dfacto_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 0;
+    bool sticky = false;
+    std::string err;
+    // growable device workspace, one slot per purpose
+    enum Slot { kM = 0, kCarry, kPartial, kSmall, kNumSlots };
+    void *ws[kNumSlots] = {nullptr, nullptr, nullptr, nullptr};
+    size_t ws_size[kNumSlots] = {0, 0, 0, 0};
+    // kernel timing (dfacto_profile_*)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;  // created on demand, reused
+    size_t ev_used = 0;                // events handed out since the last read
+    double prof_bytes = 0.0, prof_flops = 0.0;
+};
+
+namespace dfacto {
+
+// Error plumbing: every entry point returns a status; HIP failures become
+// sticky DFACTO_E_DEVICE on the context.
+struct Error {
+    dfacto_status code;
+    std::string msg;
+};
+
+dfacto_status fail(dfacto_ctx *ctx, dfacto_status code, const std::string &msg);
+void hip_check(hipError_t e, const char *what);  // throws Error on failure
+#define DF_HIP(call) ::dfacto::hip_check((call), #call)
+
+void *ws_get(dfacto_ctx *ctx, dfacto_ctx::Slot slot, size_t bytes);
+
+// Record one profiling event on the context stream (no-op when off).
+void prof_mark(dfacto_ctx *ctx);
+
+// ---------------------------------------------------------------------------
+// kernels and launchers (implemented in the .hip files)
+// ---------------------------------------------------------------------------
+
+// device-wide primitives (build.hip)
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s);
+
+// builder (build.hip): fills t (allocates its arrays).  Synchronizes.
+void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const uint32_t *d_j,
+                  const uint32_t *d_k, const float *d_val);
+
+// MTTKRP (mttkrp.hip)
+void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype,
+                   const void *Fleaf, const void *Fmid, float *out);
+
+// dense FP64 pieces (dense.hip)
+void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t rows, int R,
+                 double *G);
+void launch_solve(dfacto_ctx *ctx, int R, const double *Gp, const double *Gq, double reg,
+                  double *Hinv, double *scratch, int *flag);
+void launch_als_lambda(dfacto_ctx *ctx, int R, int mode, const double *Hinv, const double *MtM,
+                       double *Gn, double *W, double *lambda_out, const double *GA,
+                       const double *GB, double normsq, double *fit_out, double *scratch);
+void launch_rowmap(dfacto_ctx *ctx, const float *M, int64_t rows, int R, const double *W,
+                   void *F, dfacto_dtype dtype);
+void launch_hadamard(dfacto_ctx *ctx, int R, const double *Gp, const double *Gq, double reg,
+                     double *H);
+void launch_gd_rows(dfacto_ctx *ctx, float *G, const void *F, dfacto_dtype dtype, int64_t rows,
+                    int R, const double *H, double *inner_partial);
+void launch_gd_f(dfacto_ctx *ctx, int R, const double *GA, const double *GB, const double *GC,
+                 const double *inner_partial, int npartial, double normsq, double reg,
+                 double *f_out);
+int gd_rows_partials(int64_t rows, int R);
+
+}  // namespace dfacto

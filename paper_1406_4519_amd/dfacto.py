@@ -1,0 +1,282 @@
+"""Python binding of the C ABI in include/dfacto.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libdfacto.so``; this module only
+checks tensor shapes/dtypes and passes device pointers and the current HIP
+stream through ctypes.  There is no fallback: if the library is missing or
+fails to load, every call raises.
+
+Names follow the C entry points without the ``dfacto_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdfacto.so")
+
+OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = range(7)
+F32, BF16 = 0, 1
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_RANGE", 3: "E_NOMEM", 4: "E_DEVICE",
+                5: "E_NUMERIC", 6: "E_UNSUPPORTED"}
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTS = (
+    "dfacto_ctx_create", "dfacto_ctx_set_stream", "dfacto_ctx_synchronize", "dfacto_ctx_destroy",
+    "dfacto_last_error", "dfacto_build_flattenings", "dfacto_tensor_get_info",
+    "dfacto_tensor_export", "dfacto_tensor_destroy", "dfacto_mttkrp", "dfacto_als_iter",
+    "dfacto_gd_grad", "dfacto_profile_enable", "dfacto_profile_read",
+)
+
+
+class DfactoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int64 * 3), ("nnz", ctypes.c_int64),
+                ("nfib", ctypes.c_int64 * 3), ("nroot", ctypes.c_int64 * 3),
+                ("nentry", ctypes.c_int64 * 3), ("nchunk", ctypes.c_int64 * 3),
+                ("normsq", ctypes.c_double), ("bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load():
+    """Load libdfacto.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    lib.dfacto_ctx_create.argtypes = [I, P, PP]
+    lib.dfacto_ctx_set_stream.argtypes = [P, P]
+    lib.dfacto_ctx_synchronize.argtypes = [P]
+    lib.dfacto_ctx_destroy.argtypes = [P]
+    lib.dfacto_ctx_destroy.restype = None
+    lib.dfacto_last_error.argtypes = [P]
+    lib.dfacto_last_error.restype = ctypes.c_char_p
+    lib.dfacto_build_flattenings.argtypes = [P, ctypes.POINTER(ctypes.c_int64), I64, P, P, P, P, PP]
+    lib.dfacto_tensor_get_info.argtypes = [P, ctypes.POINTER(_Info)]
+    lib.dfacto_tensor_export.argtypes = [P, P, I, P, P, P, P, P, P]
+    lib.dfacto_tensor_destroy.argtypes = [P]
+    lib.dfacto_tensor_destroy.restype = None
+    lib.dfacto_mttkrp.argtypes = [P, P, I, I, I, PP, P]
+    lib.dfacto_als_iter.argtypes = [P, P, I, I, D, PP, P, P]
+    lib.dfacto_gd_grad.argtypes = [P, P, I, I, D, PP, PP, P]
+    lib.dfacto_profile_enable.argtypes = [P, I]
+    lib.dfacto_profile_read.argtypes = [P, P, P, P, P]
+    for name in EXPORTS:
+        if name not in ("dfacto_ctx_destroy", "dfacto_last_error", "dfacto_tensor_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptrs(ts) -> ctypes.Array:
+    return (ctypes.c_void_p * 3)(*[(x.data_ptr() if x is not None else None) for x in ts])
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError(f"factor dtype must be float32 or bfloat16, got {t.dtype}")
+
+
+class Context:
+    """A dfacto_ctx bound to a device and a HIP stream (torch's current one
+    unless given)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        st = lib.dfacto_ctx_create(int(device), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if st != OK:
+            raise DfactoError(st, "dfacto_ctx_create failed")
+        self.handle = h
+        self.device = device
+
+    def check(self, st: int):
+        if st != OK:
+            raise DfactoError(st, load().dfacto_last_error(self.handle).decode())
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self._stream = stream
+        self.check(load().dfacto_ctx_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def synchronize(self):
+        self.check(load().dfacto_ctx_synchronize(self.handle))
+
+    def last_error(self) -> str:
+        return load().dfacto_last_error(self.handle).decode()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().dfacto_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tensor:
+    """A built dfacto_tensor (the three flattenings, resident on the device)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def info(self) -> dict:
+        inf = _Info()
+        st = load().dfacto_tensor_get_info(self.handle, ctypes.byref(inf))
+        if st != OK:
+            raise DfactoError(st, "dfacto_tensor_get_info failed")
+        return dict(dims=tuple(inf.dims), nnz=inf.nnz, nfib=tuple(inf.nfib),
+                    nroot=tuple(inf.nroot), nentry=tuple(inf.nentry), nchunk=tuple(inf.nchunk),
+                    normsq=inf.normsq, bytes=inf.bytes)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().dfacto_tensor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ctx_create(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+def build_flattenings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, k: torch.Tensor,
+                      val: torch.Tensor) -> Tensor:
+    for x in (i, j, k):
+        if x.dtype not in (torch.int32, torch.uint32) or not x.is_contiguous() or not x.is_cuda:
+            raise TypeError("indices must be contiguous int32/uint32 CUDA tensors")
+    if val.dtype != torch.float32 or not val.is_contiguous() or not val.is_cuda:
+        raise TypeError("values must be a contiguous float32 CUDA tensor")
+    n = int(val.numel())
+    if not (i.numel() == j.numel() == k.numel() == n):
+        raise ValueError("index and value arrays differ in length")
+    d = (ctypes.c_int64 * 3)(*[int(x) for x in dims])
+    h = ctypes.c_void_p()
+    ctx.check(load().dfacto_build_flattenings(ctx.handle, d, n, _ptr(i), _ptr(j), _ptr(k), _ptr(val),
+                                              ctypes.byref(h)))
+    return Tensor(h)
+
+
+def tensor_get_info(t: Tensor) -> dict:
+    return t.info()
+
+
+def tensor_export(ctx: Context, t: Tensor, mode: int) -> dict:
+    import numpy as np
+    inf = t.info()
+    nr, nf, nz = inf["nroot"][mode], inf["nfib"][mode], inf["nnz"]
+    root_id = np.empty(max(nr, 1), np.uint32)
+    root_ptr = np.empty(nr + 1, np.int64)
+    fib_mid = np.empty(max(nf, 1), np.uint32)
+    fib_ptr = np.empty(nf + 1, np.int64)
+    leaf = np.empty(max(nz, 1), np.uint32)
+    val = np.empty(max(nz, 1), np.float32)
+    c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    ctx.check(load().dfacto_tensor_export(ctx.handle, t.handle, int(mode), c(root_id), c(root_ptr),
+                                          c(fib_mid), c(fib_ptr), c(leaf), c(val)))
+    return dict(root_id=root_id[:nr], root_ptr=root_ptr, fib_mid=fib_mid[:nf], fib_ptr=fib_ptr,
+                leaf=leaf[:nz], val=val[:nz])
+
+
+def _check_factors(t: Tensor, factors, R: int | None = None, skip: int | None = None):
+    dims = t.info()["dims"]
+    code = None
+    for m, F in enumerate(factors):
+        if F is None:
+            if m == skip:
+                continue
+            raise ValueError(f"factor {m} is None")
+        if not F.is_cuda or not F.is_contiguous() or F.dim() != 2:
+            raise TypeError("factors must be contiguous 2-D CUDA tensors")
+        if F.shape[0] != dims[m]:
+            raise ValueError(f"factor {m} has {F.shape[0]} rows, expected {dims[m]}")
+        if R is None:
+            R = int(F.shape[1])
+        if F.shape[1] != R:
+            raise ValueError("factors disagree on R")
+        c = _dtype_code(F)
+        if code is not None and c != code:
+            raise TypeError("factors must share one dtype")
+        code = c
+    return dims, R, code
+
+
+def mttkrp(ctx: Context, t: Tensor, mode: int, factors, out: torch.Tensor | None = None):
+    """out[dims[mode], R] (float32) = MTTKRP of ``mode`` with factors (A, B, C)."""
+    dims, R, code = _check_factors(t, factors, skip=mode)
+    if out is None:
+        out = torch.empty((dims[mode], R), dtype=torch.float32, device=f"cuda:{ctx.device}")
+    if out.dtype != torch.float32 or not out.is_contiguous() or tuple(out.shape) != (dims[mode], R):
+        raise ValueError("out must be a contiguous float32 tensor of shape (dims[mode], R)")
+    ctx.check(load().dfacto_mttkrp(ctx.handle, t.handle, int(mode), R, code, _ptrs(factors),
+                                   _ptr(out)))
+    return out
+
+
+def als_iter(ctx: Context, t: Tensor, factors, lam: torch.Tensor, fit: torch.Tensor,
+             reg: float = 0.0):
+    """One CP-ALS iteration in place on ``factors``; lam (R,) and fit (1,) are
+    float64 device tensors written on the stream."""
+    dims, R, code = _check_factors(t, factors)
+    if lam.dtype != torch.float64 or lam.numel() < R or not lam.is_cuda:
+        raise ValueError("lam must be a float64 CUDA tensor with R elements")
+    if fit.dtype != torch.float64 or fit.numel() < 1 or not fit.is_cuda:
+        raise ValueError("fit must be a float64 CUDA tensor")
+    ctx.check(load().dfacto_als_iter(ctx.handle, t.handle, R, code, float(reg), _ptrs(factors),
+                                     _ptr(lam), _ptr(fit)))
+
+
+def gd_grad(ctx: Context, t: Tensor, factors, grads, f: torch.Tensor, reg: float = 0.0):
+    """Gradients (float32, shapes of the factors) and objective f (float64)."""
+    dims, R, code = _check_factors(t, factors)
+    for m, g in enumerate(grads):
+        if g.dtype != torch.float32 or not g.is_contiguous() or tuple(g.shape) != (dims[m], R):
+            raise ValueError("gradients must be contiguous float32 (dims[m], R) tensors")
+    if f.dtype != torch.float64 or f.numel() < 1 or not f.is_cuda:
+        raise ValueError("f must be a float64 CUDA tensor")
+    ctx.check(load().dfacto_gd_grad(ctx.handle, t.handle, R, code, float(reg), _ptrs(factors),
+                                    _ptrs(grads), _ptr(f)))
+
+
+def profile_enable(ctx: Context, on: bool = True):
+    ctx.check(load().dfacto_profile_enable(ctx.handle, 1 if on else 0))
+
+
+def profile_read(ctx: Context) -> dict:
+    """Main-kernel MTTKRP launches recorded since enable/last read."""
+    n = ctypes.c_int64()
+    ms, b, f = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    ctx.check(load().dfacto_profile_read(ctx.handle, ctypes.byref(n), ctypes.byref(ms),
+                                         ctypes.byref(b), ctypes.byref(f)))
+    return dict(launches=n.value, ms=ms.value, bytes=b.value, flops=f.value)
