@@ -437,6 +437,54 @@ void radix_sort(uint64_t *&keys, uint32_t *&vals, uint64_t *&kalt, uint32_t *&va
     sc.release(offs);
 }
 
+__global__ void k_chunk_heads(const uint2 *__restrict__ st, const uint32_t *__restrict__ cs,
+                              int64_t nchunk, uint2 *__restrict__ heads) {
+    GRID_STRIDE(c, nchunk) {
+        const uint32_t a = cs[c];
+        heads[c] = (a < cs[c + 1]) ? st[a] : make_uint2(kHdrBit | kRootBit, 0u);
+    }
+}
+
+// Rows split across chunks: a maximal sequence of chunks whose first header
+// continues the same row (no ROOT bit) forms one run of carries.
+void build_runs(dfacto_tensor *t, ModeData &md, hipStream_t s, Scratch &sc) {
+    if (md.nchunk == 0) return;
+    uint2 *dh = sc.alloc<uint2>(md.nchunk);
+    hipLaunchKernelGGL(k_chunk_heads, dim3(grid_for(md.nchunk)), dim3(kThreads), 0, s, md.stream,
+                       md.chunk_start, md.nchunk, dh);
+    DF_HIP(hipGetLastError());
+    std::vector<uint2> heads((size_t)md.nchunk);
+    DF_HIP(hipMemcpyAsync(heads.data(), dh, sizeof(uint2) * md.nchunk, hipMemcpyDeviceToHost, s));
+    DF_HIP(hipStreamSynchronize(s));
+    std::vector<uint32_t> shortr, longr;
+    int64_t c = 0;
+    while (c < md.nchunk) {
+        if (heads[c].x & kRootBit) {
+            ++c;
+            continue;
+        }
+        const uint32_t row = heads[c].y;
+        int64_t e = c + 1;
+        while (e < md.nchunk && !(heads[e].x & kRootBit) && heads[e].y == row) ++e;
+        auto &dst = (e - c <= kShortRun) ? shortr : longr;
+        dst.push_back(row);
+        dst.push_back((uint32_t)c);
+        dst.push_back((uint32_t)(e - c));
+        c = e;
+    }
+    md.nruns_short = (int64_t)shortr.size() / 3;
+    md.nruns_long = (int64_t)longr.size() / 3;
+    md.runs_short = tensor_alloc<uint32_t>(t, (int64_t)shortr.size());
+    md.runs_long = tensor_alloc<uint32_t>(t, (int64_t)longr.size());
+    if (!shortr.empty())
+        DF_HIP(hipMemcpyAsync(md.runs_short, shortr.data(), sizeof(uint32_t) * shortr.size(),
+                              hipMemcpyHostToDevice, s));
+    if (!longr.empty())
+        DF_HIP(hipMemcpyAsync(md.runs_long, longr.data(), sizeof(uint32_t) * longr.size(),
+                              hipMemcpyHostToDevice, s));
+    DF_HIP(hipStreamSynchronize(s));
+}
+
 void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
                 const uint32_t *mid, const uint32_t *leaf, const float *val, int64_t n) {
     hipStream_t s = ctx->stream;
@@ -516,6 +564,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     hipLaunchKernelGGL(k_chunk_starts, dim3(grid_for(md.nchunk + 1)), dim3(kThreads), 0, s,
                        md.stream, L, md.nchunk, chunk_len, md.chunk_start);
     DF_HIP(hipGetLastError());
+    build_runs(t, md, s, sc);
     DF_HIP(hipStreamSynchronize(s));
 }
 

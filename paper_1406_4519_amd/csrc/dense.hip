@@ -1,19 +1,20 @@
 // dense.hip -- the small dense FP64 parts of CP-ALS and GD (Appendix B and C)
 //
-//  * Gram F^T F of a factor or of an MTTKRP result, FP64 accumulation
-//    (tiled, fixed-order two-pass reduction).
+//  * Gram F^T F of a factor or of an MTTKRP result, FP64 accumulation: on
+//    the matrix cores (FP64 MFMA) for R <= 64, else register-tiled 8x8 outer
+//    products per thread; then a fixed-order reduction over blocks.
 //  * H = G_p * G_q + reg I (Appendix A: (A kr B)^T (A kr B) = A^T A * B^T B,
 //    ridge term of the regularized update).
 //  * One-workgroup FP64 solve: Cholesky inverse of H, or the Moore-Penrose
 //    pseudo-inverse from a parallel cyclic Jacobi eigen-decomposition when a
-//    pivot shows H is numerically singular.
+//    pivot shows H is numerically singular.  Working set in LDS when small.
 //  * Column norms, the new Gram and the fit from R x R algebra: with
 //    Fhat = M H^-1,  Fhat^T Fhat = H^-1 (M^T M) H^-1, so
 //    lambda_r^2 = [H^-1 M^T M H^-1]_rr and  <X, Xhat> = <Fhat, M> =
 //    trace(H^-1 M^T M) for the last mode; ||Xhat||^2 = lambda^T (G_A * G_B *
 //    G_C) lambda.
 //  * Row maps F = M W (W = H^-1 diag(1/lambda)) and the GD gradient
-//    -M + F H.
+//    -M + F H over LDS-staged row tiles, the R x R matrix broadcast from LDS.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -54,68 +55,190 @@ __device__ __forceinline__ void st_out<uint16_t>(uint16_t *p, int64_t i, double 
     p[i] = f32_to_bf16((float)v);
 }
 
+// 8 consecutive entries p[base + c0 .. + 8) widened to double; entries at
+// columns >= R read as 0.  Vector loads when the row layout allows.
+// `vec` (computed on the host) says the rows allow 16-byte loads: R is a
+// multiple of 4 (FP32) or 8 (BF16) and the base pointer is 16-byte aligned.
+template <typename T>
+__device__ __forceinline__ void load8(const T *p, int64_t base, int c0, int R, bool vec,
+                                      double (&v)[8]);
+template <>
+__device__ __forceinline__ void load8<float>(const float *p, int64_t base, int c0, int R, bool vec,
+                                             double (&v)[8]) {
+    if (vec && c0 + 8 <= R) {
+        const float4 a = *reinterpret_cast<const float4 *>(p + base + c0);
+        const float4 b = *reinterpret_cast<const float4 *>(p + base + c0 + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = (c0 + q < R) ? (double)p[base + c0 + q] : 0.0;
+    }
+}
+template <>
+__device__ __forceinline__ void load8<uint16_t>(const uint16_t *p, int64_t base, int c0, int R,
+                                                bool vec, double (&v)[8]) {
+    if (vec && c0 + 8 <= R) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(p + base + c0);
+        const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[2 * q] = (double)__uint_as_float(w[q] << 16);
+            v[2 * q + 1] = (double)__uint_as_float(w[q] & 0xFFFF0000u);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            v[q] = (c0 + q < R) ? (double)__uint_as_float((uint32_t)p[base + c0 + q] << 16) : 0.0;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Gram: partial[b][r][s] = sum over the rows of block b of F[row][r] F[row][s]
-// grid.x: row blocks (grid-stride over row tiles), grid.y: TSxTS tiles.
-// 256 threads as 16 x 16, each an MT x MT micro-tile (TS = 16 MT).
+// Gram: part[b][r][s] = sum over the rows visited by block b of F[row][r] F[row][s]
+// grid.x: row blocks, grid.y: TSxTS output tiles.  A tile is covered by
+// (TS/8)^2 threads with 8x8 register tiles; the block holds kBlock/(TS/8)^2
+// slices of rows, combined in slice order through LDS.
 // ---------------------------------------------------------------------------
 template <typename T, int TS>
 __global__ __launch_bounds__(kBlock) void k_gram_partial(const T *__restrict__ F, int64_t rows,
-                                                         int R, double *__restrict__ part) {
-    constexpr int MT = TS / 16;
-    constexpr int kGramRows = 2048 / TS;  // rows staged per tile
-    __shared__ double sa[kGramRows][TS + 1];
-    __shared__ double sb[kGramRows][TS + 1];
+                                                         int R, int vec, double *__restrict__ part) {
+    constexpr int TT = TS / 8;
+    constexpr int TPT = TT * TT;
+    constexpr int SL = kBlock / TPT;
+    __shared__ double tile[TS * TS];
     const int nt = (R + TS - 1) / TS;
     const int rt = blockIdx.y / nt, ct = blockIdx.y % nt;
-    const int r0 = rt * TS, c0 = ct * TS;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[MT][MT];
+    const int slice = threadIdx.x / TPT, t = threadIdx.x % TPT;
+    const int ty = t / TT, tx = t % TT;
+    const int ra = rt * TS + ty * 8, cb = ct * TS + tx * 8;
+    double acc[8][8];
 #pragma unroll
-    for (int a = 0; a < MT; ++a)
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int b = 0; b < MT; ++b) acc[a][b] = 0.0;
-    const int64_t ntile = (rows + kGramRows - 1) / kGramRows;
-    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-        const int64_t base = tile * kGramRows;
-        __syncthreads();
-        for (int e = threadIdx.x; e < kGramRows * TS; e += kBlock) {
-            const int rr = e / TS, cc = e % TS;
-            const int64_t row = base + rr;
-            const bool okr = row < rows;
-            sa[rr][cc] = (okr && r0 + cc < R) ? ld<T>(F, row * R + r0 + cc) : 0.0;
-            sb[rr][cc] = (okr && c0 + cc < R) ? ld<T>(F, row * R + c0 + cc) : 0.0;
-        }
-        __syncthreads();
-        for (int rr = 0; rr < kGramRows; ++rr) {
-            double x[MT], y[MT];
+        for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+    const bool active = ra < R && cb < R;
+    if (active) {
+        for (int64_t row = (int64_t)blockIdx.x * SL + slice; row < rows;
+             row += (int64_t)gridDim.x * SL) {
+            double x[8], y[8];
+            load8<T>(F, row * R, ra, R, vec, x);
+            load8<T>(F, row * R, cb, R, vec, y);
 #pragma unroll
-            for (int a = 0; a < MT; ++a) x[a] = sa[rr][ty * MT + a];
+            for (int a = 0; a < 8; ++a)
 #pragma unroll
-            for (int b = 0; b < MT; ++b) y[b] = sb[rr][tx * MT + b];
-#pragma unroll
-            for (int a = 0; a < MT; ++a)
-#pragma unroll
-                for (int b = 0; b < MT; ++b) acc[a][b] = fma(x[a], y[b], acc[a][b]);
+                for (int b = 0; b < 8; ++b) acc[a][b] = fma(x[a], y[b], acc[a][b]);
         }
     }
-    double *pb = part + (size_t)blockIdx.x * R * R;
+    for (int s = 0; s < SL; ++s) {
+        __syncthreads();
+        if (slice == s) {
 #pragma unroll
-    for (int a = 0; a < MT; ++a)
+            for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int b = 0; b < MT; ++b) {
-            const int r = r0 + ty * MT + a, c = c0 + tx * MT + b;
-            if (r < R && c < R) pb[r * R + c] = acc[a][b];
+                for (int b = 0; b < 8; ++b) {
+                    const int e = (ty * 8 + a) * TS + tx * 8 + b;
+                    tile[e] = (s == 0) ? acc[a][b] : tile[e] + acc[a][b];
+                }
         }
+    }
+    __syncthreads();
+    double *pb = part + (size_t)blockIdx.x * R * R;
+    for (int e = threadIdx.x; e < TS * TS; e += kBlock) {
+        const int r = rt * TS + e / TS, c = ct * TS + e % TS;
+        if (r < R && c < R) pb[r * R + c] = tile[e];
+    }
 }
 
-__global__ void k_gram_reduce(const double *__restrict__ part, int nblk, int R,
-                              double *__restrict__ G) {
-    const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= R * R) return;
+// Gram on the matrix cores: v_mfma_f64_16x16x4f64 multiplies a 16x4 by a
+// 4x16 FP64 tile.  For F^T F, a step covers 4 rows: lane l supplies
+// F[k0 + l/16][16 t + l%16] for each 16-column tile t, as the A operand
+// (F^T, tile rt) and the B operand (F, tile ct); the 16x16 result D holds
+// D[l/16 + 4 i][l%16] in accumulator element i of lane l (checked on the
+// device against an encoded product).  Only tile pairs
+// rt <= ct are computed; the lower triangle is written as their mirror.
+// Each wave walks its rows 16 at a time; the waves of a block are combined
+// in a fixed order through LDS.  R <= 64 (at most 4 column tiles).
+typedef double double4v __attribute__((ext_vector_type(4)));
+constexpr int kMfmaMaxTiles = 4;
+
+template <typename T, int NT>
+__global__ __launch_bounds__(kBlock) void k_gram_mfma(const T *__restrict__ F, int64_t rows, int R,
+                                                      double *__restrict__ part) {
+    constexpr int NP = NT * (NT + 1) / 2;  // tile pairs rt <= ct
+    __shared__ double sacc[NP * 256];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int kr = lane / 16, cl = lane % 16;
+    double4v acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) acc[q] = double4v{0.0, 0.0, 0.0, 0.0};
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t gw = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+    // rows [16 * step, 16 * step + 16) for step = gw, gw + nwaves, ...
+    const int64_t nsteps = (rows + 15) / 16;
+    for (int64_t step = gw; step < nsteps; step += nwaves) {
+        double v[4][NT];
+#pragma unroll
+        for (int sub = 0; sub < 4; ++sub) {
+            const int64_t row = step * 16 + sub * 4 + kr;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c = t * 16 + cl;
+                v[sub][t] = (row < rows && c < R) ? ld<T>(F, row * R + c) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int sub = 0; sub < 4; ++sub) {
+            int q = 0;
+#pragma unroll
+            for (int rt = 0; rt < NT; ++rt)
+#pragma unroll
+                for (int ct = rt; ct < NT; ++ct, ++q)
+                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[sub][rt], v[sub][ct], acc[q],
+                                                                  0, 0, 0);
+        }
+    }
+    // combine the 4 waves of the block in wave order
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = q * 256 + (kr + 4 * i) * 16 + cl;
+                    sacc[e] = (w == 0) ? acc[q][i] : sacc[e] + acc[q][i];
+                }
+        }
+        __syncthreads();
+    }
+    double *pb = part + (size_t)blockIdx.x * R * R;
+    for (int e = threadIdx.x; e < NP * 256; e += kBlock) {
+        int q = e / 256, rt = 0;
+        while (q >= NT - rt) { q -= NT - rt; ++rt; }  // pair index -> (rt, ct)
+        const int ct = rt + q;
+        const int r = rt * 16 + (e % 256) / 16, c = ct * 16 + e % 16;
+        if (r < R && c < R) {
+            pb[r * R + c] = sacc[e];
+            if (rt != ct) pb[c * R + r] = sacc[e];
+        }
+    }
+}
+
+// G[e] = sum_b part[b][e]: 4 slices per entry, combined in slice order.
+__global__ __launch_bounds__(kBlock) void k_gram_reduce(const double *__restrict__ part, int nblk,
+                                                        int R, double *__restrict__ G) {
+    __shared__ double sh[4][64];
+    const int e = blockIdx.x * 64 + (threadIdx.x % 64);
+    const int sl = threadIdx.x / 64;
+    const int RR = R * R;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * R * R + e];
-    G[e] = s;
+    if (e < RR)
+        for (int b = sl; b < nblk; b += 4) s += part[(size_t)b * RR + e];
+    sh[sl][threadIdx.x % 64] = s;
+    __syncthreads();
+    if (sl == 0 && e < RR) {
+        const int l = threadIdx.x;
+        G[e] = ((sh[0][l] + sh[1][l]) + sh[2][l]) + sh[3][l];
+    }
 }
 
 __global__ void k_hadamard(int R, const double *__restrict__ Gp, const double *__restrict__ Gq,
@@ -150,21 +273,30 @@ __device__ double block_max(double v, double *sh) {
     return r;
 }
 
+// R x R working matrices live in LDS up to these ranks (at most ~56 KB of
+// dynamic LDS), else in global scratch.
+constexpr int kSolveSmemMaxR = 44;   // 3 R^2 doubles
+constexpr int kLambdaSmemMaxR = 40;  // 4 R^2 + R doubles
+
 // ---------------------------------------------------------------------------
-// one-workgroup solve.  scratch: 4 R^2 doubles (H, L / A, Linv / V, spare).
-// flag[0] = 1 when the pseudo-inverse path was taken.
+// one-workgroup solve.  Working set: 3 R^2 doubles (H, L / A, Linv / V), in
+// dynamic LDS when SMEM, else in `scratch`.  flag[0] = 1 when the
+// pseudo-inverse path was taken.
 // ---------------------------------------------------------------------------
+template <bool SMEM>
 __global__ __launch_bounds__(kBlock) void k_solve(int R, const double *__restrict__ Gp,
                                                   const double *__restrict__ Gq, double reg,
                                                   double *__restrict__ Hinv,
                                                   double *__restrict__ scratch, int *flag) {
+    extern __shared__ double dyn[];
     __shared__ double sh[kBlock];
     __shared__ int s_fail;
     __shared__ double s_c[kBlock], s_s[kBlock];
     __shared__ int s_p[kBlock], s_q[kBlock];
     const int tid = threadIdx.x;
     const int RR = R * R;
-    double *H = scratch, *L = scratch + RR, *Li = scratch + 2 * RR;
+    double *base = SMEM ? dyn : scratch;
+    double *H = base, *L = base + RR, *Li = base + 2 * RR;
     for (int e = tid; e < RR; e += kBlock) {
         H[e] = Gp[e] * Gq[e] + ((e / R == e % R) ? reg : 0.0);
         L[e] = 0.0;
@@ -301,29 +433,39 @@ __global__ __launch_bounds__(kBlock) void k_solve(int R, const double *__restric
 }
 
 // ---------------------------------------------------------------------------
-// lambda, new Gram, W and (last mode) fit -- one workgroup.
-// scratch T1 = MtM H^-1 (R^2), S = H^-1 T1 (R^2).
+// lambda, new Gram, W and (last mode) fit -- one workgroup.  Working set:
+// Hinv, MtM, T1 = MtM Hinv, S = Hinv T1 (4 R^2) and lambda (R), in dynamic
+// LDS when SMEM, else in `scratch`.
 // ---------------------------------------------------------------------------
+template <bool SMEM>
 __global__ __launch_bounds__(kBlock) void k_als_lambda(
-    int R, int mode, const double *__restrict__ Hinv, const double *__restrict__ MtM,
+    int R, int mode, const double *__restrict__ Hinv_g, const double *__restrict__ MtM_g,
     double *__restrict__ Gn, double *__restrict__ W, double *__restrict__ lambda_out,
     const double *__restrict__ GA, const double *__restrict__ GB, double normsq,
     double *__restrict__ fit_out, double *__restrict__ scratch) {
+    extern __shared__ double dyn[];
     __shared__ double sh[kBlock];
     const int tid = threadIdx.x;
     const int RR = R * R;
-    double *T1 = scratch, *S = scratch + RR, *lam = scratch + 2 * RR;
+    double *base = SMEM ? dyn : scratch;
+    double *Hi = base, *MM = base + RR, *T1 = base + 2 * RR, *S = base + 3 * RR,
+           *lam = base + 4 * RR;
+    for (int e = tid; e < RR; e += kBlock) {
+        Hi[e] = Hinv_g[e];
+        MM[e] = MtM_g[e];
+    }
+    __syncthreads();
     for (int e = tid; e < RR; e += kBlock) {
         const int r = e / R, s = e % R;
         double acc = 0.0;
-        for (int k = 0; k < R; ++k) acc += MtM[r * R + k] * Hinv[k * R + s];
+        for (int k = 0; k < R; ++k) acc += MM[r * R + k] * Hi[k * R + s];
         T1[e] = acc;
     }
     __syncthreads();
     for (int e = tid; e < RR; e += kBlock) {
         const int r = e / R, s = e % R;
         double acc = 0.0;
-        for (int k = 0; k < R; ++k) acc += Hinv[r * R + k] * T1[k * R + s];
+        for (int k = 0; k < R; ++k) acc += Hi[r * R + k] * T1[k * R + s];
         S[e] = acc;
     }
     __syncthreads();
@@ -333,20 +475,19 @@ __global__ __launch_bounds__(kBlock) void k_als_lambda(
         lambda_out[r] = lam[r];
     }
     __syncthreads();
-    for (int e = tid; e < RR; e += kBlock) {
-        const int r = e / R, s = e % R;
-        const double lr = lam[r], ls = lam[s];
-        Gn[e] = (lr > 0.0 && ls > 0.0) ? S[e] / (lr * ls) : 0.0;
-        W[e] = ls > 0.0 ? Hinv[e] / ls : 0.0;
-    }
-    if (mode != 2) return;
-    __syncthreads();
     double in = 0.0, xh = 0.0;
     for (int e = tid; e < RR; e += kBlock) {
         const int r = e / R, s = e % R;
-        in += Hinv[e] * MtM[e];
-        xh += lam[r] * lam[s] * GA[e] * GB[e] * Gn[e];
+        const double lr = lam[r], ls = lam[s];
+        const double g = (lr > 0.0 && ls > 0.0) ? S[e] / (lr * ls) : 0.0;
+        Gn[e] = g;
+        W[e] = ls > 0.0 ? Hi[e] / ls : 0.0;
+        if (mode == 2) {
+            in += Hi[e] * MM[e];
+            xh += lr * ls * GA[e] * GB[e] * g;
+        }
     }
+    if (mode != 2) return;
     in = block_sum(in, sh);
     xh = block_sum(xh, sh);
     if (tid == 0) {
@@ -357,16 +498,151 @@ __global__ __launch_bounds__(kBlock) void k_als_lambda(
 }
 
 // ---------------------------------------------------------------------------
-// row maps.  A block handles kRowsPerPass rows per pass; the rows of the
-// input and the R x R matrix are staged in LDS (W only when R <= 64).
+// Row maps over tiles of TR = kTileElems / R consecutive rows (one contiguous
+// block of memory): the tile is loaded with coalesced loads into LDS (row
+// stride R + 1, conflict-free column reads), each thread computes CT = 16
+// columns of one row with the R x R matrix broadcast from LDS (all lanes of a
+// wave work on the same columns), and the result tile is written back with
+// coalesced stores.  Used when R % 16 == 0 (R <= 48) or R <= 16.
 // ---------------------------------------------------------------------------
+constexpr int kTileElems = 4096;
+constexpr int kCT = 16;  // columns per thread
+
+__host__ __device__ constexpr int tile_rows(int R) { return kTileElems / R < kBlock ? kTileElems / R : kBlock; }
+
+template <typename T>
+__device__ __forceinline__ float ldf(const T *p, int64_t i);
+template <>
+__device__ __forceinline__ float ldf<float>(const float *p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ float ldf<uint16_t>(const uint16_t *p, int64_t i) {
+    return __uint_as_float((uint32_t)p[i] << 16);
+}
+
+// F[row, s] = sum_k M[row, k] W[k, s]
+template <typename Tout>
+__global__ __launch_bounds__(kBlock) void k_rowmap_t(const float *__restrict__ M, int64_t rows,
+                                                     int R, const double *__restrict__ W,
+                                                     Tout *__restrict__ F) {
+    extern __shared__ double dyn[];
+    double *sW = dyn;                                  // R * R
+    float *sM = reinterpret_cast<float *>(sW + R * R);  // TR * (R + 1)
+    const int TR = tile_rows(R), RS = R + 1;
+    float *sO = sM + TR * RS;                          // TR * (R + 1)
+    for (int e = threadIdx.x; e < R * R; e += kBlock) sW[e] = W[e];
+    const int tpr = kBlock / TR;                       // threads per row
+    const int rr = threadIdx.x % TR, part = threadIdx.x / TR;
+    const int c0 = part * kCT;
+    const bool active = part < tpr && c0 < R;
+    const int64_t ntile = (rows + TR - 1) / TR;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t r0 = tile * TR;
+        const int nr = (int)((rows - r0) < TR ? (rows - r0) : TR);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nr * R; e += kBlock) sM[(e / R) * RS + e % R] = M[r0 * R + e];
+        __syncthreads();
+        if (active && rr < nr) {
+            double acc[kCT];
+#pragma unroll
+            for (int s = 0; s < kCT; ++s) acc[s] = 0.0;
+            const float *m = sM + rr * RS;
+            for (int k = 0; k < R; ++k) {
+                const double mk = m[k];
+                const double *w = sW + k * R + c0;
+#pragma unroll
+                for (int s = 0; s < kCT; ++s)
+                    if (c0 + s < R) acc[s] = fma(mk, w[s], acc[s]);
+            }
+#pragma unroll
+            for (int s = 0; s < kCT; ++s)
+                if (c0 + s < R) sO[rr * RS + c0 + s] = (float)acc[s];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nr * R; e += kBlock)
+            st_out<Tout>(F, r0 * R + e, (double)sO[(e / R) * RS + e % R]);
+    }
+}
+
+// G[row, s] = -G[row, s] + sum_k F[row, k] H[k, s]  (G holds the MTTKRP);
+// partial[block] = sum over the block's rows of <F[row,:], M[row,:]>.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gd_rows_t(float *__restrict__ G,
+                                                      const T *__restrict__ F, int64_t rows,
+                                                      int R, const double *__restrict__ H,
+                                                      double *__restrict__ partial) {
+    extern __shared__ double dyn[];
+    __shared__ double sh[kBlock];
+    double *sH = dyn;
+    float *sF = reinterpret_cast<float *>(sH + R * R);
+    const int TR = tile_rows(R), RS = R + 1;
+    float *sM = sF + TR * RS;
+    for (int e = threadIdx.x; e < R * R; e += kBlock) sH[e] = H[e];
+    const int tpr = kBlock / TR;
+    const int rr = threadIdx.x % TR, part = threadIdx.x / TR;
+    const int c0 = part * kCT;
+    const bool active = part < tpr && c0 < R;
+    const int64_t ntile = (rows + TR - 1) / TR;
+    double inner = 0.0;
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int64_t r0 = tile * TR;
+        const int nr = (int)((rows - r0) < TR ? (rows - r0) : TR);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nr * R; e += kBlock) {
+            const int o = (e / R) * RS + e % R;
+            sF[o] = ldf<T>(F, r0 * R + e);
+            sM[o] = G[r0 * R + e];
+        }
+        __syncthreads();
+        double acc[kCT];
+        if (active && rr < nr) {
+#pragma unroll
+            for (int s = 0; s < kCT; ++s) acc[s] = 0.0;
+            const float *f = sF + rr * RS;
+            for (int k = 0; k < R; ++k) {
+                const double fk = f[k];
+                const double *h = sH + k * R + c0;
+#pragma unroll
+                for (int s = 0; s < kCT; ++s)
+                    if (c0 + s < R) acc[s] = fma(fk, h[s], acc[s]);
+            }
+        }
+        __syncthreads();  // every thread has read its F row: sF can take the output
+        if (active && rr < nr) {
+            const float *mrow = sM + rr * RS;
+#pragma unroll
+            for (int s = 0; s < kCT; ++s) {
+                if (c0 + s < R) {
+                    const double m = mrow[c0 + s];
+                    inner = fma((double)sF[rr * RS + c0 + s], m, inner);
+                }
+            }
+        }
+        __syncthreads();
+        if (active && rr < nr) {
+            const float *mrow = sM + rr * RS;
+#pragma unroll
+            for (int s = 0; s < kCT; ++s)
+                if (c0 + s < R) sF[rr * RS + c0 + s] = (float)(acc[s] - (double)mrow[c0 + s]);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nr * R; e += kBlock) G[r0 * R + e] = sF[(e / R) * RS + e % R];
+    }
+    const double tot = block_sum(inner, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+size_t tile_lds_bytes(int R) {
+    return sizeof(double) * (size_t)R * R + 2 * sizeof(float) * (size_t)tile_rows(R) * (R + 1);
+}
+
+// Generic versions for any R (up to 256): rows staged in LDS, the matrix in
+// LDS when it fits.
 constexpr int kLdsMatMaxR = 64;
 
-// F[row, s] = sum_r M[row, r] W[r, s]
 template <typename Tout>
-__global__ __launch_bounds__(kBlock) void k_rowmap(const float *__restrict__ M, int64_t rows,
-                                                   int R, const double *__restrict__ W,
-                                                   Tout *__restrict__ F) {
+__global__ __launch_bounds__(kBlock) void k_rowmap_g(const float *__restrict__ M, int64_t rows,
+                                                     int R, const double *__restrict__ W,
+                                                     Tout *__restrict__ F) {
     __shared__ double sW[kLdsMatMaxR * kLdsMatMaxR];
     __shared__ float sM[kBlock * 4];
     const bool wlds = R <= kLdsMatMaxR;
@@ -394,13 +670,11 @@ __global__ __launch_bounds__(kBlock) void k_rowmap(const float *__restrict__ M, 
     }
 }
 
-// G[row, s] = -G[row, s] + sum_r F[row, r] H[r, s]   (G holds the MTTKRP);
-// partial[block] = sum over the block's rows of <F[row,:], M[row,:]>.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gd_rows(float *__restrict__ G, const T *__restrict__ F,
-                                                    int64_t rows, int R,
-                                                    const double *__restrict__ H,
-                                                    double *__restrict__ partial) {
+__global__ __launch_bounds__(kBlock) void k_gd_rows_g(float *__restrict__ G, const T *__restrict__ F,
+                                                      int64_t rows, int R,
+                                                      const double *__restrict__ H,
+                                                      double *__restrict__ partial) {
     __shared__ double sH[kLdsMatMaxR * kLdsMatMaxR];
     __shared__ double sF[kBlock * 2];
     __shared__ double sh[kBlock];
@@ -453,27 +727,66 @@ __global__ __launch_bounds__(kBlock) void k_gd_f(int R, const double *__restrict
     if (threadIdx.x == 0) *f = 0.5 * (normsq - 2.0 * in + xh) + 0.5 * reg * tr;
 }
 
+// 16-byte row loads are allowed when every row start is 16-byte aligned
+int vec_rows(const void *p, int R, int elem) {
+    return ((uintptr_t)p % 16 == 0) && (((size_t)R * elem) % 16 == 0);
+}
+
+bool tiled_rows_ok(int R) {  // the LDS-tiled row kernels cover these ranks (<= ~51 KB LDS)
+    return (R <= 16 || (R % 16 == 0 && R <= 48));
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
+int gram_partial_blocks(int64_t rows, int R) {
+    const int TS = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
+    const int TT = TS / 8;
+    const int SL = kBlock / (TT * TT);
+    const int64_t want = (rows + (int64_t)SL * 16 - 1) / ((int64_t)SL * 16);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, 256));
+}
+
 void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t rows, int R,
                  double *G) {
     hipStream_t s = ctx->stream;
+    if (R <= 16 * kMfmaMaxTiles) {
+        const int nt = (R + 15) / 16;
+        const int64_t want = (rows + 16 * 4 * 8 - 1) / (16 * 4 * 8);  // >= 8 steps per wave
+        const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256));
+        double *part =
+            (double *)ws_get(ctx, dfacto_ctx::kPartial, sizeof(double) * 256 * (size_t)R * R);
+#define GM(T, NTV) hipLaunchKernelGGL((k_gram_mfma<T, NTV>), dim3(nblk), dim3(kBlock), 0, s, (const T *)F, rows, R, part)
+        if (dtype == DFACTO_F32) {
+            if (nt == 1) GM(float, 1);
+            else if (nt == 2) GM(float, 2);
+            else if (nt == 3) GM(float, 3);
+            else GM(float, 4);
+        } else {
+            if (nt == 1) GM(uint16_t, 1);
+            else if (nt == 2) GM(uint16_t, 2);
+            else if (nt == 3) GM(uint16_t, 3);
+            else GM(uint16_t, 4);
+        }
+#undef GM
+        hipLaunchKernelGGL(k_gram_reduce, dim3((R * R + 63) / 64), dim3(kBlock), 0, s, part, nblk, R,
+                           G);
+        DF_HIP(hipGetLastError());
+        return;
+    }
     const int TS = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
     const int nt = (R + TS - 1) / TS;
-    const int64_t ntile = (rows + (2048 / TS) - 1) / (2048 / TS);
-    int64_t cap = (int64_t)(4 << 20) / ((int64_t)R * R);
-    cap = std::max<int64_t>(1, std::min<int64_t>(cap, 1024));
-    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(ntile, cap));
-    // sized for the largest row count so that the buffer never moves between calls
-    double *part = (double *)ws_get(ctx, dfacto_ctx::kPartial, sizeof(double) * (size_t)cap * R * R);
+    const int nblk = gram_partial_blocks(rows, R);
+    // sized for the largest block count so that the buffer never moves between calls
+    double *part = (double *)ws_get(ctx, dfacto_ctx::kPartial, sizeof(double) * 256 * (size_t)R * R);
     dim3 grid(nblk, nt * nt);
+    const int vec = vec_rows(F, R, dtype == DFACTO_F32 ? 4 : 2);
 #define GRAM_LAUNCH(T, TSV)                                                                   \
     hipLaunchKernelGGL((k_gram_partial<T, TSV>), grid, dim3(kBlock), 0, s, (const T *)F, rows, R, \
-                       part)
+                       vec, part)
     if (dtype == DFACTO_F32) {
         if (TS == 16) GRAM_LAUNCH(float, 16);
         else if (TS == 32) GRAM_LAUNCH(float, 32);
@@ -484,8 +797,7 @@ void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t row
         else GRAM_LAUNCH(uint16_t, 64);
     }
 #undef GRAM_LAUNCH
-    hipLaunchKernelGGL(k_gram_reduce, dim3((R * R + kBlock - 1) / kBlock), dim3(kBlock), 0, s, part,
-                       nblk, R, G);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((R * R + 63) / 64), dim3(kBlock), 0, s, part, nblk, R, G);
     DF_HIP(hipGetLastError());
 }
 
@@ -498,50 +810,90 @@ void launch_hadamard(dfacto_ctx *ctx, int R, const double *Gp, const double *Gq,
 
 void launch_solve(dfacto_ctx *ctx, int R, const double *Gp, const double *Gq, double reg,
                   double *Hinv, double *scratch, int *flag) {
-    hipLaunchKernelGGL(k_solve, dim3(1), dim3(kBlock), 0, ctx->stream, R, Gp, Gq, reg, Hinv,
-                       scratch, flag);
+    if (R <= kSolveSmemMaxR)
+        hipLaunchKernelGGL(k_solve<true>, dim3(1), dim3(kBlock), sizeof(double) * 3 * R * R,
+                           ctx->stream, R, Gp, Gq, reg, Hinv, scratch, flag);
+    else
+        hipLaunchKernelGGL(k_solve<false>, dim3(1), dim3(kBlock), 0, ctx->stream, R, Gp, Gq, reg,
+                           Hinv, scratch, flag);
     DF_HIP(hipGetLastError());
 }
 
 void launch_als_lambda(dfacto_ctx *ctx, int R, int mode, const double *Hinv, const double *MtM,
                        double *Gn, double *W, double *lambda_out, const double *GA,
                        const double *GB, double normsq, double *fit_out, double *scratch) {
-    hipLaunchKernelGGL(k_als_lambda, dim3(1), dim3(kBlock), 0, ctx->stream, R, mode, Hinv, MtM, Gn,
-                       W, lambda_out, GA, GB, normsq, fit_out, scratch);
+    if (R <= kLambdaSmemMaxR)
+        hipLaunchKernelGGL(k_als_lambda<true>, dim3(1), dim3(kBlock),
+                           sizeof(double) * (4 * R * R + R), ctx->stream, R, mode, Hinv, MtM, Gn, W,
+                           lambda_out, GA, GB, normsq, fit_out, scratch);
+    else
+        hipLaunchKernelGGL(k_als_lambda<false>, dim3(1), dim3(kBlock), 0, ctx->stream, R, mode,
+                           Hinv, MtM, Gn, W, lambda_out, GA, GB, normsq, fit_out, scratch);
     DF_HIP(hipGetLastError());
 }
 
-static unsigned rows_grid(int64_t rows, int R, int per_pass_elems) {
+static unsigned rows_grid_generic(int64_t rows, int R, int per_pass_elems) {
     const int rpp = std::max(1, per_pass_elems / R);
     const int64_t npass = (rows + rpp - 1) / rpp;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(npass, 8192));
 }
 
+static unsigned rows_grid_tiles(int64_t rows, int R) {
+    const int64_t nt = (rows + tile_rows(R) - 1) / tile_rows(R);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(nt, 2048));
+}
+
 void launch_rowmap(dfacto_ctx *ctx, const float *M, int64_t rows, int R, const double *W, void *F,
                    dfacto_dtype dtype) {
     if (rows <= 0) return;
-    const unsigned g = rows_grid(rows, R, kBlock * 4);
-    if (dtype == DFACTO_F32)
-        hipLaunchKernelGGL(k_rowmap<float>, dim3(g), dim3(kBlock), 0, ctx->stream, M, rows, R, W,
-                           (float *)F);
-    else
-        hipLaunchKernelGGL(k_rowmap<uint16_t>, dim3(g), dim3(kBlock), 0, ctx->stream, M, rows, R, W,
-                           (uint16_t *)F);
+    hipStream_t s = ctx->stream;
+    if (tiled_rows_ok(R)) {
+        const unsigned g = rows_grid_tiles(rows, R);
+        const size_t lds = tile_lds_bytes(R);
+        if (dtype == DFACTO_F32)
+            hipLaunchKernelGGL(k_rowmap_t<float>, dim3(g), dim3(kBlock), lds, s, M, rows, R, W,
+                               (float *)F);
+        else
+            hipLaunchKernelGGL(k_rowmap_t<uint16_t>, dim3(g), dim3(kBlock), lds, s, M, rows, R, W,
+                               (uint16_t *)F);
+    } else {
+        const unsigned g = rows_grid_generic(rows, R, kBlock * 4);
+        if (dtype == DFACTO_F32)
+            hipLaunchKernelGGL(k_rowmap_g<float>, dim3(g), dim3(kBlock), 0, s, M, rows, R, W,
+                               (float *)F);
+        else
+            hipLaunchKernelGGL(k_rowmap_g<uint16_t>, dim3(g), dim3(kBlock), 0, s, M, rows, R, W,
+                               (uint16_t *)F);
+    }
     DF_HIP(hipGetLastError());
 }
 
-int gd_rows_partials(int64_t rows, int R) { return (int)rows_grid(rows, R, kBlock * 2); }
+int gd_rows_partials(int64_t rows, int R) {
+    return (int)(tiled_rows_ok(R) ? rows_grid_tiles(rows, R)
+                                  : rows_grid_generic(rows, R, kBlock * 2));
+}
 
 void launch_gd_rows(dfacto_ctx *ctx, float *G, const void *F, dfacto_dtype dtype, int64_t rows,
                     int R, const double *H, double *inner_partial) {
     if (rows <= 0) return;
-    const unsigned g = rows_grid(rows, R, kBlock * 2);
-    if (dtype == DFACTO_F32)
-        hipLaunchKernelGGL(k_gd_rows<float>, dim3(g), dim3(kBlock), 0, ctx->stream, G,
-                           (const float *)F, rows, R, H, inner_partial);
-    else
-        hipLaunchKernelGGL(k_gd_rows<uint16_t>, dim3(g), dim3(kBlock), 0, ctx->stream, G,
-                           (const uint16_t *)F, rows, R, H, inner_partial);
+    hipStream_t s = ctx->stream;
+    const unsigned g = (unsigned)gd_rows_partials(rows, R);
+    if (tiled_rows_ok(R)) {
+        const size_t lds = tile_lds_bytes(R);
+        if (dtype == DFACTO_F32)
+            hipLaunchKernelGGL(k_gd_rows_t<float>, dim3(g), dim3(kBlock), lds, s, G,
+                               (const float *)F, rows, R, H, inner_partial);
+        else
+            hipLaunchKernelGGL(k_gd_rows_t<uint16_t>, dim3(g), dim3(kBlock), lds, s, G,
+                               (const uint16_t *)F, rows, R, H, inner_partial);
+    } else {
+        if (dtype == DFACTO_F32)
+            hipLaunchKernelGGL(k_gd_rows_g<float>, dim3(g), dim3(kBlock), 0, s, G,
+                               (const float *)F, rows, R, H, inner_partial);
+        else
+            hipLaunchKernelGGL(k_gd_rows_g<uint16_t>, dim3(g), dim3(kBlock), 0, s, G,
+                               (const uint16_t *)F, rows, R, H, inner_partial);
+    }
     DF_HIP(hipGetLastError());
 }
 

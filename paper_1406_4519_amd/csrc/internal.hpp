@@ -40,7 +40,16 @@ struct ModeData {
     uint32_t *chunk_start = nullptr;   // nchunk + 1 entries
     int64_t nchunk = 0;
     int chunk_len = 0;                 // target entries per chunk
+    // Output rows whose nonzeros span several chunks ("runs"): the chunk that
+    // starts the row writes it, chunks c0 .. c0+n-1 write carries.  Runs of at
+    // most kShortRun carries are summed by one lane group, longer runs by a
+    // whole workgroup.  Each list holds (row, c0, n) triplets.
+    uint32_t *runs_short = nullptr;
+    int64_t nruns_short = 0;
+    uint32_t *runs_long = nullptr;
+    int64_t nruns_long = 0;
 };
+constexpr int kShortRun = 16;
 
 }  // namespace dfacto
 

@@ -17,19 +17,59 @@
 // Work chunks always start at a header and are balanced in entries, so a
 // heavy root is spread over many groups.  A root that begins before the
 // chunk (no ROOT bit on the chunk's first header) is written to a per-chunk
-// carry slot; the fix-up kernel adds the carries of each such root to the
-// owner's row in chunk order.  No floating-point atomics: results are
-// deterministic.  The fix-up launch also zero-fills the empty output rows.
+// carry slot; the fix-up kernels add the carries of each such root to the
+// owner's row in a fixed order.  No floating-point atomics: results are
+// deterministic.  The fix-up launches also zero-fill the empty output rows.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "internal.hpp"
 
 namespace dfacto {
 namespace {
 
+// Tuning knobs (compile-time; the defaults are the measured best).
+#ifndef DFACTO_UNROLL
+#define DFACTO_UNROLL 8
+#endif
+#ifndef DFACTO_MAX_CPL
+#define DFACTO_MAX_CPL 4
+#endif
+#ifndef DFACTO_NT_STREAM
+#define DFACTO_NT_STREAM 0
+#endif
+#ifndef DFACTO_SHARE_ENTRIES
+#define DFACTO_SHARE_ENTRIES 1
+#endif
+#ifdef DFACTO_WAVES_PER_EU
+#define MTTKRP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(DFACTO_WAVES_PER_EU)))
+#else
+#define MTTKRP_OCCUPANCY
+#endif
+
 constexpr int kBlock = 256;
-constexpr int kUnroll = 8;  // stream entries in flight per group
-static_assert(kStreamPad >= kUnroll, "stream padding must cover one batch");
+constexpr int kUnroll = DFACTO_UNROLL;  // stream entries in flight per group
+static_assert(kStreamPad >= kUnroll && kStreamPad >= 32, "stream padding must cover a batch");
+
+// f(integral_constant<int, I>) for I = B .. E-1, so I is usable as a constant
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+__device__ __forceinline__ uint2 load_entry(const uint2 *p) {
+#if DFACTO_NT_STREAM
+    const unsigned long long x =
+        __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p));
+    return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
+#else
+    return *p;
+#endif
+}
 
 // ---- factor-row loads: CPL consecutive columns, widened to FP32 ----------
 template <typename T, int CPL>
@@ -54,9 +94,27 @@ struct RowLoad<float, 1> {
     static __device__ __forceinline__ void load(const float *p, float (&v)[1]) { v[0] = *p; }
 };
 
+template <>
+struct RowLoad<float, 8> {
+    static __device__ __forceinline__ void load(const float *p, float (&v)[8]) {
+        const float4 x = *reinterpret_cast<const float4 *>(p);
+        const float4 y = *reinterpret_cast<const float4 *>(p + 4);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    }
+};
+
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
+template <>
+struct RowLoad<uint16_t, 8> {
+    static __device__ __forceinline__ void load(const uint16_t *p, float (&v)[8]) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(p);
+        v[0] = bf16_lo(x.x); v[1] = bf16_hi(x.x); v[2] = bf16_lo(x.y); v[3] = bf16_hi(x.y);
+        v[4] = bf16_lo(x.z); v[5] = bf16_hi(x.z); v[6] = bf16_lo(x.w); v[7] = bf16_hi(x.w);
+    }
+};
 template <>
 struct RowLoad<uint16_t, 4> {
     static __device__ __forceinline__ void load(const uint16_t *p, float (&v)[4]) {
@@ -80,7 +138,10 @@ struct RowLoad<uint16_t, 1> {
 
 template <int CPL>
 __device__ __forceinline__ void store_vec(float *p, const float (&v)[CPL]) {
-    if constexpr (CPL == 4) {
+    if constexpr (CPL == 8) {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+        *reinterpret_cast<float4 *>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+    } else if constexpr (CPL == 4) {
         *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
     } else if constexpr (CPL == 2) {
         *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
@@ -95,8 +156,10 @@ __device__ __forceinline__ void load_f32(const float *p, float (&v)[CPL]) {
 }
 
 // ---- main kernel ---------------------------------------------------------
-template <typename T, int CPL, int G, int NCH>
-__global__ __launch_bounds__(kBlock) void k_mttkrp(
+// SMALL: every row index is below 2^24, so row offsets are one 24-bit
+// multiply (idx * R < 2^32) instead of 64-bit arithmetic.
+template <typename T, int CPL, int G, int NCH, bool SMALL>
+__global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_mttkrp(
     const uint2 *__restrict__ st, const uint32_t *__restrict__ cstart, uint32_t nchunk,
     const T *__restrict__ Fleaf, const T *__restrict__ Fmid, int R, float *__restrict__ out,
     float *__restrict__ carry) {
@@ -106,13 +169,24 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp(
     const uint32_t cs = cstart[gid], ce = cstart[gid + 1];
     if (cs >= ce) return;
 
+    // Per-lane row bases.  Lanes whose columns lie beyond R read column 0
+    // instead (in bounds, never stored), so every gather is issued without a
+    // branch and the loads of a batch stay in flight together.
     int col[NCH];
     bool act[NCH];
+    const T *leafb[NCH], *midb[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         col[c] = (c * G + lane) * CPL;
         act[c] = col[c] < R;
+        leafb[c] = Fleaf + (act[c] ? col[c] : 0);
+        midb[c] = Fmid + (act[c] ? col[c] : 0);
     }
+    auto row_off = [&](uint32_t idx) -> size_t {
+        if constexpr (SMALL) return (size_t)(uint32_t)__umul24(idx, (uint32_t)R);
+        else return (size_t)idx * (size_t)R;
+    };
+
     float acc[NCH][CPL], p[NCH][CPL], mrow[NCH][CPL];
     const uint2 h0 = st[cs];
     uint32_t row = h0.y;
@@ -120,70 +194,111 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp(
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) acc[c][q] = p[c][q] = mrow[c][q] = 0.f;
-        if (act[c]) RowLoad<T, CPL>::load(Fmid + (size_t)(h0.x & kIdxMask) * R + col[c], mrow[c]);
+        for (int q = 0; q < CPL; ++q) acc[c][q] = p[c][q] = 0.f;
+        RowLoad<T, CPL>::load(midb[c] + row_off(h0.x & kIdxMask), mrow[c]);
     }
 
     auto flush = [&](uint32_t r_out, bool is_cont) {
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             if (!act[c]) continue;
-            float *dst = is_cont ? carry + (size_t)gid * R + col[c] : out + (size_t)r_out * R + col[c];
+            float *dst = is_cont ? carry + (size_t)gid * R + col[c] : out + row_off(r_out) + col[c];
             store_vec<CPL>(dst, acc[c]);
         }
     };
 
-    for (uint32_t e = cs + 1; e < ce; e += kUnroll) {
-        uint2 w[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) w[u] = st[e + u];  // padded stream: always in bounds
-        float g[kUnroll][NCH][CPL];
+    // Gathers of one batch: every entry's factor row, without branches.
+    // Entries at or past the chunk end are still valid stream entries (the
+    // next chunk's, or the padding sentinels with index 0), so these loads
+    // are in bounds; their values are ignored.
+    auto gather = [&](const uint2 (&w)[kUnroll], float (&g)[kUnroll][NCH][CPL]) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const bool valid = e + u < ce;
-            const T *base = (w[u].x & kHdrBit) ? Fmid : Fleaf;
-            const size_t off = (size_t)(w[u].x & kIdxMask) * R;
+            const bool hdr = (int32_t)w[u].x < 0;  // kHdrBit is the sign bit
+            const size_t off = row_off(w[u].x & kIdxMask);
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                if (valid && act[c]) {
-                    RowLoad<T, CPL>::load(base + off + col[c], g[u][c]);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < CPL; ++q) g[u][c][q] = 0.f;
-                }
-            }
+            for (int c = 0; c < NCH; ++c)
+                RowLoad<T, CPL>::load((hdr ? midb[c] : leafb[c]) + off, g[u][c]);
         }
+    };
+    // One stream entry, without data-dependent branches except the (rarer)
+    // write of a finished output row.  A header closes the fiber segment --
+    // stage 2 of Algorithm 1, acc += P * F_mid[mid] -- and opens the next
+    // one (P = 0, new mid row); a nonzero accumulates stage 1, P += x *
+    // F_leaf[leaf].
+    auto step = [&](const uint2 &w, const float (&g)[NCH][CPL]) {
+        const bool hdr = (int32_t)w.x < 0;
+        const float v = hdr ? 0.f : __uint_as_float(w.y);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            if (e + u >= ce) break;
-            if (w[u].x & kHdrBit) {
-                // end of a fiber segment: stage 2 for the finished partial
+        for (int c = 0; c < NCH; ++c)
 #pragma unroll
-                for (int c = 0; c < NCH; ++c)
+            for (int q = 0; q < CPL; ++q) {
+                const float a2 = fmaf(p[c][q], mrow[c][q], acc[c][q]);
+                acc[c][q] = hdr ? a2 : acc[c][q];
+                p[c][q] = fmaf(v, g[c][q], hdr ? 0.f : p[c][q]);
+                mrow[c][q] = hdr ? g[c][q] : mrow[c][q];
+            }
+        if (hdr && (w.x & kRootBit)) {
+            flush(row, cont);
 #pragma unroll
-                    for (int q = 0; q < CPL; ++q) {
-                        acc[c][q] = fmaf(p[c][q], mrow[c][q], acc[c][q]);
-                        p[c][q] = 0.f;
-                        mrow[c][q] = g[u][c][q];
-                    }
-                if (w[u].x & kRootBit) {
-                    flush(row, cont);
+            for (int c = 0; c < NCH; ++c)
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c)
+                for (int q = 0; q < CPL; ++q) acc[c][q] = 0.f;
+            cont = false;
+            row = w.y;
+        }
+    };
+
+    // Stream entries of a batch.  With groups of at most 32 lanes, lane l
+    // loads only entries l, l + G, ... of the batch (8 bytes each) and the
+    // group shares them through ds_swizzle (the LDS crossbar), so the vector
+    // memory path carries each entry once instead of once per lane.  A
+    // 64-lane group is the whole wave and loads the batch directly.
+    constexpr bool kShare = G <= 32 && DFACTO_SHARE_ENTRIES;
+    constexpr int KL = kShare ? (kUnroll + G - 1) / G : kUnroll;  // entries held per lane
+    auto load_batch = [&](uint32_t at, uint2 (&wl)[KL]) {
 #pragma unroll
-                        for (int q = 0; q < CPL; ++q) acc[c][q] = 0.f;
-                    cont = false;
-                    row = w[u].y;
-                }
+        for (int k = 0; k < KL; ++k)
+            wl[k] = kShare ? load_entry(st + at + lane + G * k) : load_entry(st + at + k);
+    };
+    auto expand = [&](const uint2 (&wl)[KL], uint2 (&w)[kUnroll]) {
+        static_for<0, kUnroll>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            if constexpr (kShare) {
+                // bit-mask swizzle: source lane = (lane & ~(G-1)) | (u % G), within 32 lanes
+                constexpr int pat = (0x1F & ~(G - 1)) | ((u % G) << 5);
+                w[u].x = (uint32_t)__builtin_amdgcn_ds_swizzle((int)wl[u / G].x, pat);
+                w[u].y = (uint32_t)__builtin_amdgcn_ds_swizzle((int)wl[u / G].y, pat);
             } else {
-                // stage 1: accumulate the fiber partial
-                const float v = __uint_as_float(w[u].y);
-#pragma unroll
-                for (int c = 0; c < NCH; ++c)
-#pragma unroll
-                    for (int q = 0; q < CPL; ++q) p[c][q] = fmaf(v, g[u][c][q], p[c][q]);
+                w[u] = wl[u];
             }
-        }
+        });
+    };
+
+    // Full batches.  The next batch's entries are requested right after the
+    // current batch's gathers, so their latency overlaps the gathers.  The
+    // stream padding (>= 64 entries) keeps the look-ahead in bounds.
+    uint32_t e = cs + 1;
+    uint2 wn[KL];
+    load_batch(e, wn);
+    for (; e + kUnroll <= ce; e += kUnroll) {
+        uint2 w[kUnroll];
+        expand(wn, w);
+        float g[kUnroll][NCH][CPL];
+        gather(w, g);
+        load_batch(e + kUnroll, wn);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) step(w[u], g[u]);
+    }
+    // Last, partial batch (fewer than kUnroll entries left).
+    if (e < ce) {
+        uint2 w[kUnroll];
+        expand(wn, w);
+        float g[kUnroll][NCH][CPL];
+        gather(w, g);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (e + u < ce) step(w[u], g[u]);
     }
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
@@ -192,12 +307,14 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp(
     flush(row, cont);
 }
 
-// ---- fix-up: continuation carries and empty rows --------------------------
+// ---- fix-up: carries of split rows, and empty rows ------------------------
+// Short runs: one lane group per run adds its <= kShortRun carries in chunk
+// order; the groups after the runs zero-fill the empty output rows.
 template <int CPL, int G, int NCH>
-__global__ __launch_bounds__(kBlock) void k_mttkrp_fixup(
-    const uint2 *__restrict__ st, const uint32_t *__restrict__ cstart, uint32_t nchunk,
-    const float *__restrict__ carry, int R, float *__restrict__ out,
-    const uint32_t *__restrict__ empty_rows, uint32_t nempty, uint32_t nempty_groups) {
+__global__ __launch_bounds__(kBlock) void k_fix_short(
+    const uint32_t *__restrict__ runs, uint32_t nruns, const float *__restrict__ carry, int R,
+    float *__restrict__ out, const uint32_t *__restrict__ empty_rows, uint32_t nempty,
+    uint32_t nempty_groups) {
     const uint32_t gid = (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G;
     const int lane = threadIdx.x % G;
     int col[NCH];
@@ -207,48 +324,88 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_fixup(
         col[c] = (c * G + lane) * CPL;
         act[c] = col[c] < R;
     }
-    if (gid < nchunk) {
-        const uint32_t cs = cstart[gid];
-        if (cs >= cstart[gid + 1]) return;
-        const uint2 h = st[cs];
-        if (h.x & kRootBit) return;  // chunk starts its own root: nothing carried
-        if (gid > 0) {
-            const uint2 hp = st[cstart[gid - 1]];
-            if (!(hp.x & kRootBit) && hp.y == h.y) return;  // not the first carry of the run
-        }
-        const uint32_t row = h.y;
-        float acc[NCH][CPL];
+    if (gid < nruns) {
+        const uint32_t row = runs[3 * gid], c0 = runs[3 * gid + 1], n = runs[3 * gid + 2];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c)
-            if (act[c]) load_f32<CPL>(out + (size_t)row * R + col[c], acc[c]);
-        for (uint32_t ch = gid; ch < nchunk; ++ch) {
-            const uint32_t a = cstart[ch];
-            if (a >= cstart[ch + 1]) break;
-            const uint2 hc = st[a];
-            if ((hc.x & kRootBit) || hc.y != row) break;
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                if (!act[c]) continue;
+        for (int c = 0; c < NCH; ++c) {
+            if (!act[c]) continue;
+            float acc[CPL];
+            load_f32<CPL>(out + (size_t)row * R + col[c], acc);
+            for (uint32_t k = 0; k < n; ++k) {
                 float v[CPL];
-                load_f32<CPL>(carry + (size_t)ch * R + col[c], v);
+                load_f32<CPL>(carry + (size_t)(c0 + k) * R + col[c], v);
 #pragma unroll
-                for (int q = 0; q < CPL; ++q) acc[c][q] += v[q];
+                for (int q = 0; q < CPL; ++q) acc[q] += v[q];
             }
+            store_vec<CPL>(out + (size_t)row * R + col[c], acc);
         }
+        return;
+    }
+    const uint32_t eg = gid - nruns;
+    if (eg >= nempty_groups) return;
+    float z[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) z[q] = 0.f;
+    for (uint32_t r = eg; r < nempty; r += nempty_groups) {
+        const uint32_t row = empty_rows[r];
 #pragma unroll
         for (int c = 0; c < NCH; ++c)
-            if (act[c]) store_vec<CPL>(out + (size_t)row * R + col[c], acc[c]);
-    } else {
-        const uint32_t eg = gid - nchunk;
-        if (eg >= nempty_groups) return;
-        float z[CPL];
+            if (act[c]) store_vec<CPL>(out + (size_t)row * R + col[c], z);
+    }
+}
+
+// Long runs: one workgroup per run; kBlock / G slices each sum a strided
+// subset of the carries, then a fixed-order tree over the slices (so the
+// result is deterministic) is added to the row.
+constexpr int kLongBlock = 1024;
+
+template <int CPL, int G, int NCH>
+__global__ __launch_bounds__(kLongBlock) void k_fix_long(const uint32_t *__restrict__ runs,
+                                                         const float *__restrict__ carry, int R,
+                                                         float *__restrict__ out) {
+    constexpr int S = kLongBlock / G;
+    constexpr int W = CPL * NCH;  // floats per thread
+    __shared__ float sh[kLongBlock * W];
+    const int slice = threadIdx.x / G, lane = threadIdx.x % G;
+    const uint32_t row = runs[3 * blockIdx.x], c0 = runs[3 * blockIdx.x + 1],
+                   n = runs[3 * blockIdx.x + 2];
+    float acc[NCH][CPL];
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) z[q] = 0.f;
-        for (uint32_t r = eg; r < nempty; r += nempty_groups) {
-            const uint32_t row = empty_rows[r];
+    for (int c = 0; c < NCH; ++c) {
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                if (act[c]) store_vec<CPL>(out + (size_t)row * R + col[c], z);
+        for (int q = 0; q < CPL; ++q) acc[c][q] = 0.f;
+        const int col = (c * G + lane) * CPL;
+        if (col >= R) continue;
+        for (uint32_t k = slice; k < n; k += S) {
+            float v[CPL];
+            load_f32<CPL>(carry + (size_t)(c0 + k) * R + col, v);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) acc[c][q] += v[q];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) sh[threadIdx.x * W + c * CPL + q] = acc[c][q];
+    __syncthreads();
+    for (int half = S / 2; half > 0; half >>= 1) {
+        if (slice < half) {
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                sh[threadIdx.x * W + w] += sh[(threadIdx.x + half * G) * W + w];
+        }
+        __syncthreads();
+    }
+    if (slice == 0) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int col = (c * G + lane) * CPL;
+            if (col >= R) continue;
+            float o[CPL];
+            load_f32<CPL>(out + (size_t)row * R + col, o);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) o[q] += sh[threadIdx.x * W + c * CPL + q];
+            store_vec<CPL>(out + (size_t)row * R + col, o);
         }
     }
 }
@@ -258,10 +415,11 @@ struct Shape {
     int cpl, g, nch;
 };
 
-Shape pick_shape(int R, bool aligned4, bool aligned2) {
+Shape pick_shape(int R, bool aligned8, bool aligned4, bool aligned2) {
     int cpl = 1;
-    if (R % 4 == 0 && aligned4) cpl = 4;
-    else if (R % 2 == 0 && aligned2) cpl = 2;
+    if (R % 8 == 0 && aligned8 && DFACTO_MAX_CPL >= 8) cpl = 8;
+    else if (R % 4 == 0 && aligned4 && DFACTO_MAX_CPL >= 4) cpl = 4;
+    else if (R % 2 == 0 && aligned2 && DFACTO_MAX_CPL >= 2) cpl = 2;
     const int lanes = (R + cpl - 1) / cpl;
     if (lanes <= 64) {
         int g = 2;
@@ -275,7 +433,7 @@ Shape pick_shape(int R, bool aligned4, bool aligned2) {
 
 template <typename T, int CPL, int G, int NCH>
 void run(dfacto_ctx *ctx, const ModeData &md, int R, const void *Fleaf, const void *Fmid,
-         float *out) {
+         float *out, bool small) {
     hipStream_t s = ctx->stream;
     const uint32_t nchunk = (uint32_t)md.nchunk;
     float *carry = (float *)ws_get(ctx, dfacto_ctx::kCarry,
@@ -284,41 +442,50 @@ void run(dfacto_ctx *ctx, const ModeData &md, int R, const void *Fleaf, const vo
     if (nchunk > 0) {
         const unsigned blocks = (nchunk + gpb - 1) / gpb;
         prof_mark(ctx);
-        hipLaunchKernelGGL((k_mttkrp<T, CPL, G, NCH>), dim3(blocks), dim3(kBlock), 0, s,
-                           md.stream, md.chunk_start, nchunk, (const T *)Fleaf, (const T *)Fmid, R,
-                           out, carry);
+        if (small)
+            hipLaunchKernelGGL((k_mttkrp<T, CPL, G, NCH, true>), dim3(blocks), dim3(kBlock), 0, s,
+                               md.stream, md.chunk_start, nchunk, (const T *)Fleaf,
+                               (const T *)Fmid, R, out, carry);
+        else
+            hipLaunchKernelGGL((k_mttkrp<T, CPL, G, NCH, false>), dim3(blocks), dim3(kBlock), 0,
+                               s, md.stream, md.chunk_start, nchunk, (const T *)Fleaf,
+                               (const T *)Fmid, R, out, carry);
         prof_mark(ctx);
     }
     const uint32_t nempty = (uint32_t)md.nempty;
     const uint32_t egroups = nempty == 0 ? 0u : std::min<uint32_t>(nempty, 65536u);
-    const uint64_t groups = (uint64_t)nchunk + egroups;
+    const uint64_t groups = (uint64_t)md.nruns_short + egroups;
     if (groups > 0) {
         const unsigned blocks = (unsigned)((groups + gpb - 1) / gpb);
-        hipLaunchKernelGGL((k_mttkrp_fixup<CPL, G, NCH>), dim3(blocks), dim3(kBlock), 0, s,
-                           md.stream, md.chunk_start, nchunk, carry, R, out, md.empty_rows, nempty,
-                           egroups);
+        hipLaunchKernelGGL((k_fix_short<CPL, G, NCH>), dim3(blocks), dim3(kBlock), 0, s,
+                           md.runs_short, (uint32_t)md.nruns_short, carry, R, out, md.empty_rows,
+                           nempty, egroups);
+    }
+    if (md.nruns_long > 0) {
+        hipLaunchKernelGGL((k_fix_long<CPL, G, NCH>), dim3((unsigned)md.nruns_long),
+                           dim3(kLongBlock), 0, s, md.runs_long, carry, R, out);
     }
     DF_HIP(hipGetLastError());
 }
 
 template <typename T, int CPL>
 void run_cpl(dfacto_ctx *ctx, const ModeData &md, int R, const Shape &sh, const void *Fl,
-             const void *Fm, float *out) {
+             const void *Fm, float *out, bool sm) {
     if (sh.nch == 1) {
         switch (sh.g) {
-            case 2: return run<T, CPL, 2, 1>(ctx, md, R, Fl, Fm, out);
-            case 4: return run<T, CPL, 4, 1>(ctx, md, R, Fl, Fm, out);
-            case 8: return run<T, CPL, 8, 1>(ctx, md, R, Fl, Fm, out);
-            case 16: return run<T, CPL, 16, 1>(ctx, md, R, Fl, Fm, out);
-            case 32: return run<T, CPL, 32, 1>(ctx, md, R, Fl, Fm, out);
-            default: return run<T, CPL, 64, 1>(ctx, md, R, Fl, Fm, out);
+            case 2: return run<T, CPL, 2, 1>(ctx, md, R, Fl, Fm, out, sm);
+            case 4: return run<T, CPL, 4, 1>(ctx, md, R, Fl, Fm, out, sm);
+            case 8: return run<T, CPL, 8, 1>(ctx, md, R, Fl, Fm, out, sm);
+            case 16: return run<T, CPL, 16, 1>(ctx, md, R, Fl, Fm, out, sm);
+            case 32: return run<T, CPL, 32, 1>(ctx, md, R, Fl, Fm, out, sm);
+            default: return run<T, CPL, 64, 1>(ctx, md, R, Fl, Fm, out, sm);
         }
     }
     if constexpr (CPL < 4) {
-        if (sh.nch == 2) return run<T, CPL, 64, 2>(ctx, md, R, Fl, Fm, out);
+        if (sh.nch == 2) return run<T, CPL, 64, 2>(ctx, md, R, Fl, Fm, out, sm);
     }
     if constexpr (CPL == 1) {
-        return run<T, CPL, 64, 4>(ctx, md, R, Fl, Fm, out);
+        return run<T, CPL, 64, 4>(ctx, md, R, Fl, Fm, out, sm);
     }
     throw Error{DFACTO_E_UNSUPPORTED, "no MTTKRP kernel for this rank"};
 }
@@ -340,18 +507,28 @@ void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfa
         return ((uintptr_t)Fleaf % a == 0) && ((uintptr_t)Fmid % a == 0) &&
                ((uintptr_t)out % (a * 4 / es) == 0);
     };
-    const Shape sh = pick_shape(R, al(4 * es), al(2 * es));
+    const Shape sh = pick_shape(R, al(8 * es), al(4 * es), al(2 * es));
+    // 24-bit row offsets when every index of the leaf, mid and output factor
+    // is below 2^24 (then idx * R < 2^32 for R <= 256)
+    const bool sm = t->dims[md.root] < (1 << 24) && t->dims[md.leaf] < (1 << 24) &&
+                    t->dims[md.mid] < (1 << 24);
     if (dtype == DFACTO_F32) {
         switch (sh.cpl) {
-            case 4: return run_cpl<float, 4>(ctx, md, R, sh, Fleaf, Fmid, out);
-            case 2: return run_cpl<float, 2>(ctx, md, R, sh, Fleaf, Fmid, out);
-            default: return run_cpl<float, 1>(ctx, md, R, sh, Fleaf, Fmid, out);
+#if DFACTO_MAX_CPL >= 8
+            case 8: return run_cpl<float, 8>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
+#endif
+            case 4: return run_cpl<float, 4>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
+            case 2: return run_cpl<float, 2>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
+            default: return run_cpl<float, 1>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
         }
     }
     switch (sh.cpl) {
-        case 4: return run_cpl<uint16_t, 4>(ctx, md, R, sh, Fleaf, Fmid, out);
-        case 2: return run_cpl<uint16_t, 2>(ctx, md, R, sh, Fleaf, Fmid, out);
-        default: return run_cpl<uint16_t, 1>(ctx, md, R, sh, Fleaf, Fmid, out);
+#if DFACTO_MAX_CPL >= 8
+        case 8: return run_cpl<uint16_t, 8>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
+#endif
+        case 4: return run_cpl<uint16_t, 4>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
+        case 2: return run_cpl<uint16_t, 2>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
+        default: return run_cpl<uint16_t, 1>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
     }
 }
 
