@@ -161,22 +161,24 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const T *__restrict__ F
 typedef double double4v __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxTiles = 4;
 
-template <typename T, int NT>
-__global__ __launch_bounds__(kBlock) void k_gram_mfma(const T *__restrict__ F, int64_t rows, int R,
-                                                      double *__restrict__ part) {
+template <typename T, int NT, int BS>
+__global__ __launch_bounds__(BS) void k_gram_mfma(const T *__restrict__ F, int64_t rows, int R,
+                                                  double *__restrict__ part) {
     constexpr int NP = NT * (NT + 1) / 2;  // tile pairs rt <= ct
+    constexpr int NW = BS / 64;            // waves per block
     __shared__ double sacc[NP * 256];
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int kr = lane / 16, cl = lane % 16;
     double4v acc[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) acc[q] = double4v{0.0, 0.0, 0.0, 0.0};
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    const int64_t gw = (int64_t)blockIdx.x * (kBlock / 64) + wave;
-    // rows [16 * step, 16 * step + 16) for step = gw, gw + nwaves, ...
+    const int64_t nwaves = (int64_t)gridDim.x * NW;
+    const int64_t gw = (int64_t)blockIdx.x * NW + wave;
+    // rows [16 * step, 16 * step + 16) for step = gw, gw + nwaves, ...; rows
+    // past the end read as zero.  The next step is loaded before the current
+    // one's MFMAs.
     const int64_t nsteps = (rows + 15) / 16;
-    for (int64_t step = gw; step < nsteps; step += nwaves) {
-        double v[4][NT];
+    auto load = [&](int64_t step, double (&v)[4][NT]) {
 #pragma unroll
         for (int sub = 0; sub < 4; ++sub) {
             const int64_t row = step * 16 + sub * 4 + kr;
@@ -186,6 +188,12 @@ __global__ __launch_bounds__(kBlock) void k_gram_mfma(const T *__restrict__ F, i
                 v[sub][t] = (row < rows && c < R) ? ld<T>(F, row * R + c) : 0.0;
             }
         }
+    };
+    double v[4][NT];
+    if (gw < nsteps) load(gw, v);
+    for (int64_t step = gw; step < nsteps; step += nwaves) {
+        double vn[4][NT];
+        load(step + nwaves, vn);
 #pragma unroll
         for (int sub = 0; sub < 4; ++sub) {
             int q = 0;
@@ -196,9 +204,13 @@ __global__ __launch_bounds__(kBlock) void k_gram_mfma(const T *__restrict__ F, i
                     acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[sub][rt], v[sub][ct], acc[q],
                                                                   0, 0, 0);
         }
+#pragma unroll
+        for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) v[sub][t] = vn[sub][t];
     }
-    // combine the 4 waves of the block in wave order
-    for (int w = 0; w < kBlock / 64; ++w) {
+    // combine the waves of the block in wave order
+    for (int w = 0; w < NW; ++w) {
         if (wave == w) {
 #pragma unroll
             for (int q = 0; q < NP; ++q)
@@ -211,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_gram_mfma(const T *__restrict__ F, i
         __syncthreads();
     }
     double *pb = part + (size_t)blockIdx.x * R * R;
-    for (int e = threadIdx.x; e < NP * 256; e += kBlock) {
+    for (int e = threadIdx.x; e < NP * 256; e += BS) {
         int q = e / 256, rt = 0;
         while (q >= NT - rt) { q -= NT - rt; ++rt; }  // pair index -> (rt, ct)
         const int ct = rt + q;
@@ -279,7 +291,7 @@ constexpr int kSolveSmemMaxR = 44;   // 3 R^2 doubles
 constexpr int kLambdaSmemMaxR = 40;  // 4 R^2 + R doubles
 
 // ---------------------------------------------------------------------------
-// one-workgroup solve.  Working set: 3 R^2 doubles (H, L / A, Linv / V), in
+// one-workgroup solve.  Working set: 3 R^2 doubles (H, A, B / V), in
 // dynamic LDS when SMEM, else in `scratch`.  flag[0] = 1 when the
 // pseudo-inverse path was taken.
 // ---------------------------------------------------------------------------
@@ -309,41 +321,47 @@ __global__ __launch_bounds__(kBlock) void k_solve(int R, const double *__restric
     const double tol = (double)R * DBL_EPSILON * dmax;
     if (tid == 0) s_fail = (dmax > 0.0) ? 0 : 1;
     __syncthreads();
-    // Cholesky H = L L^T, column by column
-    for (int j = 0; j < R && !s_fail; ++j) {
-        if (tid == 0) {
-            double d = H[j * R + j];
-            for (int k = 0; k < j; ++k) d -= L[j * R + k] * L[j * R + k];
-            if (!(d > tol)) s_fail = 1;
-            else L[j * R + j] = sqrt(d);
+    // Gauss-Jordan on [H | I] without pivoting (H is symmetric): the pivot at
+    // step j is the Schur-complement diagonal d_j = L_jj^2 of the Cholesky
+    // factorization H = L L^T, so "every d_j > R eps max diag(H)" is the
+    // Cholesky test for a numerically positive definite H.  If it fails, the
+    // pseudo-inverse below is used instead.  Aw (in L) is the working copy of
+    // H, Bw (in Li) starts as I and ends as H^-1.
+    double *Aw = L, *Bw = Li;
+    __shared__ double s_f[kBlock];
+    for (int e = tid; e < RR; e += kBlock) {
+        Aw[e] = H[e];
+        Bw[e] = (e / R == e % R) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < R; ++j) {
+        const double piv = Aw[j * R + j];
+        if (!(piv > tol)) {  // uniform: every thread reads the same value
+            if (tid == 0) s_fail = 1;
+            break;
         }
+        const double inv = 1.0 / piv;
+        __syncthreads();  // all threads have read the pivot
+        for (int k = tid; k < 2 * R; k += kBlock) {
+            if (k < R) Aw[j * R + k] *= inv;
+            else Bw[j * R + k - R] *= inv;
+        }
+        for (int i = tid; i < R; i += kBlock) s_f[i] = (i == j) ? 0.0 : Aw[i * R + j];
         __syncthreads();
-        if (s_fail) break;
-        const double ljj = L[j * R + j];
-        for (int i = j + 1 + tid; i < R; i += kBlock) {
-            double s = H[i * R + j];
-            for (int k = 0; k < j; ++k) s -= L[i * R + k] * L[j * R + k];
-            L[i * R + j] = s / ljj;
+        for (int e = tid; e < R * 2 * R; e += kBlock) {
+            const int i = e / (2 * R), k = e % (2 * R);
+            const double f = s_f[i];
+            if (f == 0.0) continue;
+            if (k < R) Aw[i * R + k] = fma(-f, Aw[j * R + k], Aw[i * R + k]);
+            else Bw[i * R + k - R] = fma(-f, Bw[j * R + k - R], Bw[i * R + k - R]);
         }
         __syncthreads();
     }
+    __syncthreads();
     if (!s_fail) {
-        // Linv = L^{-1} (lower triangular), one column per thread
-        for (int c = tid; c < R; c += kBlock) {
-            for (int i = c; i < R; ++i) {
-                double s = (i == c) ? 1.0 : 0.0;
-                for (int k = c; k < i; ++k) s -= L[i * R + k] * Li[k * R + c];
-                Li[i * R + c] = s / L[i * R + i];
-            }
-        }
-        __syncthreads();
-        // H^{-1} = Linv^T Linv
         for (int e = tid; e < RR; e += kBlock) {
-            const int r = e / R, s = e % R;
-            const int k0 = r > s ? r : s;
-            double acc = 0.0;
-            for (int k = k0; k < R; ++k) acc += Li[k * R + r] * Li[k * R + s];
-            Hinv[e] = acc;
+            const int r = e / R, c = e % R;
+            Hinv[e] = 0.5 * (Bw[r * R + c] + Bw[c * R + r]);
         }
         if (tid == 0) flag[0] = 0;
         return;
@@ -503,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_als_lambda(
 // stride R + 1, conflict-free column reads), each thread computes CT = 16
 // columns of one row with the R x R matrix broadcast from LDS (all lanes of a
 // wave work on the same columns), and the result tile is written back with
-// coalesced stores.  Used when R % 16 == 0 (R <= 48) or R <= 16.
+// coalesced stores.  Instantiated for R in {4, 8, 12, 16, 32, 48}.
 // ---------------------------------------------------------------------------
 constexpr int kTileElems = 4096;
 constexpr int kCT = 16;  // columns per thread
@@ -519,18 +537,18 @@ __device__ __forceinline__ float ldf<uint16_t>(const uint16_t *p, int64_t i) {
     return __uint_as_float((uint32_t)p[i] << 16);
 }
 
-// F[row, s] = sum_k M[row, k] W[k, s]
-template <typename Tout>
+// F[row, s] = sum_k M[row, k] W[k, s]   (R is a compile-time constant)
+template <typename Tout, int R>
 __global__ __launch_bounds__(kBlock) void k_rowmap_t(const float *__restrict__ M, int64_t rows,
-                                                     int R, const double *__restrict__ W,
+                                                     const double *__restrict__ W,
                                                      Tout *__restrict__ F) {
     extern __shared__ double dyn[];
     double *sW = dyn;                                  // R * R
     float *sM = reinterpret_cast<float *>(sW + R * R);  // TR * (R + 1)
-    const int TR = tile_rows(R), RS = R + 1;
+    constexpr int TR = tile_rows(R), RS = R + 1;
     float *sO = sM + TR * RS;                          // TR * (R + 1)
     for (int e = threadIdx.x; e < R * R; e += kBlock) sW[e] = W[e];
-    const int tpr = kBlock / TR;                       // threads per row
+    constexpr int tpr = kBlock / TR;                   // threads per row
     const int rr = threadIdx.x % TR, part = threadIdx.x / TR;
     const int c0 = part * kCT;
     const bool active = part < tpr && c0 < R;
@@ -546,6 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_rowmap_t(const float *__restrict__ M
 #pragma unroll
             for (int s = 0; s < kCT; ++s) acc[s] = 0.0;
             const float *m = sM + rr * RS;
+#pragma unroll 4
             for (int k = 0; k < R; ++k) {
                 const double mk = m[k];
                 const double *w = sW + k * R + c0;
@@ -565,19 +584,19 @@ __global__ __launch_bounds__(kBlock) void k_rowmap_t(const float *__restrict__ M
 
 // G[row, s] = -G[row, s] + sum_k F[row, k] H[k, s]  (G holds the MTTKRP);
 // partial[block] = sum over the block's rows of <F[row,:], M[row,:]>.
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_gd_rows_t(float *__restrict__ G,
                                                       const T *__restrict__ F, int64_t rows,
-                                                      int R, const double *__restrict__ H,
+                                                      const double *__restrict__ H,
                                                       double *__restrict__ partial) {
     extern __shared__ double dyn[];
     __shared__ double sh[kBlock];
     double *sH = dyn;
     float *sF = reinterpret_cast<float *>(sH + R * R);
-    const int TR = tile_rows(R), RS = R + 1;
+    constexpr int TR = tile_rows(R), RS = R + 1;
     float *sM = sF + TR * RS;
     for (int e = threadIdx.x; e < R * R; e += kBlock) sH[e] = H[e];
-    const int tpr = kBlock / TR;
+    constexpr int tpr = kBlock / TR;
     const int rr = threadIdx.x % TR, part = threadIdx.x / TR;
     const int c0 = part * kCT;
     const bool active = part < tpr && c0 < R;
@@ -598,6 +617,7 @@ __global__ __launch_bounds__(kBlock) void k_gd_rows_t(float *__restrict__ G,
 #pragma unroll
             for (int s = 0; s < kCT; ++s) acc[s] = 0.0;
             const float *f = sF + rr * RS;
+#pragma unroll 4
             for (int k = 0; k < R; ++k) {
                 const double fk = f[k];
                 const double *h = sH + k * R + c0;
@@ -732,8 +752,8 @@ int vec_rows(const void *p, int R, int elem) {
     return ((uintptr_t)p % 16 == 0) && (((size_t)R * elem) % 16 == 0);
 }
 
-bool tiled_rows_ok(int R) {  // the LDS-tiled row kernels cover these ranks (<= ~51 KB LDS)
-    return (R <= 16 || (R % 16 == 0 && R <= 48));
+bool tiled_rows_ok(int R) {  // ranks with a compile-time LDS-tiled row kernel (<= ~51 KB LDS)
+    return R == 4 || R == 8 || R == 12 || R == 16 || R == 32 || R == 48;
 }
 
 }  // namespace
@@ -755,11 +775,12 @@ void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t row
     hipStream_t s = ctx->stream;
     if (R <= 16 * kMfmaMaxTiles) {
         const int nt = (R + 15) / 16;
-        const int64_t want = (rows + 16 * 4 * 8 - 1) / (16 * 4 * 8);  // >= 8 steps per wave
+        const int bs = nt <= 2 ? 1024 : 256;  // 16 waves per block when the registers allow
+        const int64_t want = (rows + 16 * 8 * (bs / 64) - 1) / (16 * 8 * (bs / 64));
         const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256));
         double *part =
             (double *)ws_get(ctx, dfacto_ctx::kPartial, sizeof(double) * 256 * (size_t)R * R);
-#define GM(T, NTV) hipLaunchKernelGGL((k_gram_mfma<T, NTV>), dim3(nblk), dim3(kBlock), 0, s, (const T *)F, rows, R, part)
+#define GM(T, NTV) hipLaunchKernelGGL((k_gram_mfma<T, NTV, (NTV <= 2 ? 1024 : 256)>), dim3(nblk), dim3(NTV <= 2 ? 1024 : 256), 0, s, (const T *)F, rows, R, part)
         if (dtype == DFACTO_F32) {
             if (nt == 1) GM(float, 1);
             else if (nt == 2) GM(float, 2);
@@ -843,20 +864,54 @@ static unsigned rows_grid_tiles(int64_t rows, int R) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(nt, 2048));
 }
 
+template <typename Tout, int RC>
+void rowmap_tiled(hipStream_t s, const float *M, int64_t rows, const double *W, void *F) {
+    hipLaunchKernelGGL((k_rowmap_t<Tout, RC>), dim3(rows_grid_tiles(rows, RC)), dim3(kBlock),
+                       tile_lds_bytes(RC), s, M, rows, W, (Tout *)F);
+}
+
+template <typename T, int RC>
+void gd_rows_tiled(hipStream_t s, float *G, const void *F, int64_t rows, const double *H,
+                   double *partial) {
+    hipLaunchKernelGGL((k_gd_rows_t<T, RC>), dim3(rows_grid_tiles(rows, RC)), dim3(kBlock),
+                       tile_lds_bytes(RC), s, G, (const T *)F, rows, H, partial);
+}
+
+// Dispatch a tiled row kernel on the compile-time rank; false if R has none.
+template <template <typename, int> class K, typename T, typename... A>
+bool dispatch_tiled(int R, A... args) {
+    switch (R) {
+        case 4: K<T, 4>::run(args...); return true;
+        case 8: K<T, 8>::run(args...); return true;
+        case 12: K<T, 12>::run(args...); return true;
+        case 16: K<T, 16>::run(args...); return true;
+        case 32: K<T, 32>::run(args...); return true;
+        case 48: K<T, 48>::run(args...); return true;
+        default: return false;
+    }
+}
+template <typename T, int RC>
+struct RowmapK {
+    static void run(hipStream_t s, const float *M, int64_t rows, const double *W, void *F) {
+        rowmap_tiled<T, RC>(s, M, rows, W, F);
+    }
+};
+template <typename T, int RC>
+struct GdRowsK {
+    static void run(hipStream_t s, float *G, const void *F, int64_t rows, const double *H,
+                    double *partial) {
+        gd_rows_tiled<T, RC>(s, G, F, rows, H, partial);
+    }
+};
+
 void launch_rowmap(dfacto_ctx *ctx, const float *M, int64_t rows, int R, const double *W, void *F,
                    dfacto_dtype dtype) {
     if (rows <= 0) return;
     hipStream_t s = ctx->stream;
-    if (tiled_rows_ok(R)) {
-        const unsigned g = rows_grid_tiles(rows, R);
-        const size_t lds = tile_lds_bytes(R);
-        if (dtype == DFACTO_F32)
-            hipLaunchKernelGGL(k_rowmap_t<float>, dim3(g), dim3(kBlock), lds, s, M, rows, R, W,
-                               (float *)F);
-        else
-            hipLaunchKernelGGL(k_rowmap_t<uint16_t>, dim3(g), dim3(kBlock), lds, s, M, rows, R, W,
-                               (uint16_t *)F);
-    } else {
+    const bool done = dtype == DFACTO_F32
+                          ? dispatch_tiled<RowmapK, float>(R, s, M, rows, W, F)
+                          : dispatch_tiled<RowmapK, uint16_t>(R, s, M, rows, W, F);
+    if (!done) {
         const unsigned g = rows_grid_generic(rows, R, kBlock * 4);
         if (dtype == DFACTO_F32)
             hipLaunchKernelGGL(k_rowmap_g<float>, dim3(g), dim3(kBlock), 0, s, M, rows, R, W,
@@ -877,16 +932,11 @@ void launch_gd_rows(dfacto_ctx *ctx, float *G, const void *F, dfacto_dtype dtype
                     int R, const double *H, double *inner_partial) {
     if (rows <= 0) return;
     hipStream_t s = ctx->stream;
-    const unsigned g = (unsigned)gd_rows_partials(rows, R);
-    if (tiled_rows_ok(R)) {
-        const size_t lds = tile_lds_bytes(R);
-        if (dtype == DFACTO_F32)
-            hipLaunchKernelGGL(k_gd_rows_t<float>, dim3(g), dim3(kBlock), lds, s, G,
-                               (const float *)F, rows, R, H, inner_partial);
-        else
-            hipLaunchKernelGGL(k_gd_rows_t<uint16_t>, dim3(g), dim3(kBlock), lds, s, G,
-                               (const uint16_t *)F, rows, R, H, inner_partial);
-    } else {
+    const bool done = dtype == DFACTO_F32
+                          ? dispatch_tiled<GdRowsK, float>(R, s, G, F, rows, H, inner_partial)
+                          : dispatch_tiled<GdRowsK, uint16_t>(R, s, G, F, rows, H, inner_partial);
+    if (!done) {
+        const unsigned g = (unsigned)gd_rows_partials(rows, R);
         if (dtype == DFACTO_F32)
             hipLaunchKernelGGL(k_gd_rows_g<float>, dim3(g), dim3(kBlock), 0, s, G,
                                (const float *)F, rows, R, H, inner_partial);
