@@ -161,6 +161,9 @@ dfacto_status dfacto_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, i
  * reg >= 0.  On return d_lambda (R doubles) holds the weights from the
  * mode-2 normalization and *d_fit (one double) the fit
  *     1 - ||X - [[lambda; A, B, C]]|| / ||X||   (0 when ||X|| = 0).
+ * With DFACTO_BF16 the factors are stored rounded (to FP32, then BF16,
+ * nearest-even), and each later mode's Gram is formed from the stored
+ * factor, so the normal equations match what the MTTKRPs read.
  * Enqueue only (no host synchronization); d_lambda and d_fit are device
  * pointers. */
 dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R,

@@ -52,7 +52,7 @@ def _load():
         lib.oracle_inner.argtypes = [i64, P, P, P, P, ctypes.c_int, P, P, P, P]
         lib.oracle_inner.restype = ctypes.c_double
         lib.oracle_als_iter.argtypes = [i64, P, P, P, P, P, ctypes.c_int, ctypes.c_double,
-                                        P, P, P, P, P]
+                                        ctypes.c_int, P, P, P, P, P]
         lib.oracle_als_iter.restype = ctypes.c_int
         lib.oracle_gd_grad.argtypes = [i64, P, P, P, P, P, ctypes.c_int, ctypes.c_double,
                                        P, P, P, P, P, P]
@@ -143,10 +143,13 @@ def inner(i, j, k, val, factors, lam=None) -> float:
                                   _p(A), _p(B), _p(C), lp))
 
 
-def als_iter(i, j, k, val, dims, factors, reg: float = 0.0):
+def als_iter(i, j, k, val, dims, factors, reg: float = 0.0, store: str = "f64"):
     """One CP-ALS iteration.  Returns (A, B, C, lam, info) with new arrays.
+    store="bf16": every new factor is rounded to BF16 before later use.
 
     info = dict(fit, inner_direct, normsq, xhat_sq, pinv_mask)."""
+    if store not in ("f64", "bf16"):
+        raise ValueError("store must be 'f64' or 'bf16'")
     lib = _load()
     i, j, k, val = _coo(i, j, k, val)
     A, B, C = (np.array(f, dtype=np.float64, order="C", copy=True) for f in factors)
@@ -155,7 +158,7 @@ def als_iter(i, j, k, val, dims, factors, reg: float = 0.0):
     lam = np.empty(R, np.float64)
     out = np.empty(4, np.float64)
     mask = lib.oracle_als_iter(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), R, float(reg),
-                               _p(A), _p(B), _p(C), _p(lam), _p(out))
+                               int(store == "bf16"), _p(A), _p(B), _p(C), _p(lam), _p(out))
     info = dict(fit=float(out[0]), inner_direct=float(out[1]), normsq=float(out[2]),
                 xhat_sq=float(out[3]), pinv_mask=int(mask))
     return A, B, C, lam, info

@@ -397,14 +397,34 @@ double oracle_inner(int64_t nnz, const uint32_t *i, const uint32_t *j,
  *   <X, Xhat>  = sum_r lambda_r sum_k C[k, r] M3[k, r]
  *   fit = 1 - sqrt(max(0, ||X||^2 + ||Xhat||^2 - 2 <X, Xhat>)) / ||X||
  *   (fit = 0 when ||X|| = 0).
+ * store_bf16 != 0 models factors kept in BF16 storage: each new F_n is
+ * rounded (FP32 then BF16, nearest-even) before the next mode uses it and
+ * before the fit is formed; lambda comes from the unrounded F_n.
  * A, B, C are updated in place.  out[0] = fit, out[1] = <X,Xhat> computed
  * directly over the nonzeros (independent cross-check), out[2] = ||X||^2,
  * out[3] = ||Xhat||^2.  Returns a bitmask of the modes that used the
  * pseudo-inverse. */
+/* Storage rounding of a factor entry kept in BF16: to the nearest FP32, then
+ * to the nearest BF16 (round to nearest, ties to even on the FP32 bits). */
+static double round_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    if ((b & 0x7F800000u) == 0x7F800000u) {
+        b = (b & 0xFFFF0000u) | ((b & 0xFFFFu) ? 0x00400000u : 0u);
+    } else {
+        b += 0x7FFFu + ((b >> 16) & 1u);
+        b &= 0xFFFF0000u;
+    }
+    memcpy(&f, &b, 4);
+    return (double)f;
+}
+
 int oracle_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
                     const uint32_t *k, const double *val, const int64_t *dims,
-                    int R, double reg, double *A, double *B, double *C,
-                    double *lambda, double *out)
+                    int R, double reg, int store_bf16, double *A, double *B,
+                    double *C, double *lambda, double *out)
 {
     double *F[3] = {A, B, C};
     int64_t dmax = dims[0];
@@ -432,6 +452,9 @@ int oracle_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
             if (lambda[r] > 0.0)
                 for (int64_t m = 0; m < dims[n]; ++m) F[n][m * R + r] /= lambda[r];
         }
+        /* a factor stored in BF16 enters the next mode's update rounded */
+        if (store_bf16)
+            for (int64_t e = 0; e < dims[n] * R; ++e) F[n][e] = round_bf16(F[n][e]);
         if (n == 2) memcpy(M3, M, sizeof(double) * (size_t)dims[2] * R);
     }
     /* fit */

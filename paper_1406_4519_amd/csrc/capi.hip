@@ -327,6 +327,11 @@ dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, df
             launch_als_lambda(ctx, R, n, sw.Hinv, sw.MtM, sw.G[n], sw.W, d_lambda, sw.G[0],
                               sw.G[1], t->normsq, d_fit, sw.lam_scratch);
             launch_rowmap(ctx, M, t->dims[n], R, sw.W, d_F[n], dtype);
+            // A BF16-stored factor differs from the FP64 one by its rounding;
+            // the next modes' normal equations must use the Gram of what the
+            // next MTTKRPs read, so form it from the stored factor.
+            if (dtype == DFACTO_BF16 && n < 2)
+                launch_gram(ctx, d_F[n], dtype, t->dims[n], R, sw.G[n]);
         }
     });
 }
@@ -354,7 +359,8 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfa
             launch_gd_rows(ctx, d_G[n], d_F[n], dtype, t->dims[n], R, sw.H[n],
                            n == 0 ? sw.part0 : sw.part_dummy);
         }
-        launch_gd_f(ctx, R, sw.G[0], sw.G[1], sw.G[2], sw.part0, gd_rows_partials(t->dims[0], R),
+        launch_gd_f(ctx, R, sw.G[0], sw.G[1], sw.G[2], sw.part0,
+                    gd_rows_partials(t->dims[0], R, d_G[0], d_F[0], dtype),
                     t->normsq, reg, d_f);
     });
 }

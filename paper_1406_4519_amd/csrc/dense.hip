@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -161,7 +162,33 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const T *__restrict__ F
 typedef double double4v __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxTiles = 4;
 
-template <typename T, int NT, int BS>
+// NT consecutive entries F[row][c0 .. c0 + NT) widened to double, zero past
+// the last row or column.  VEC: R == 16 NT and the rows are aligned for one
+// NT-element vector load.
+template <typename T, int NT, bool VEC>
+__device__ __forceinline__ void gram_load(const T *__restrict__ F, int64_t row, int64_t rows, int R,
+                                          int c0, double (&v)[NT]) {
+    if (VEC && NT == 2) {
+        if (row < rows) {
+            if constexpr (sizeof(T) == 4) {
+                const float2 a = *reinterpret_cast<const float2 *>(F + row * R + c0);
+                v[0] = a.x;
+                v[1] = a.y;
+            } else {
+                const uint32_t a = *reinterpret_cast<const uint32_t *>(F + row * R + c0);
+                v[0] = __uint_as_float(a << 16);
+                v[1] = __uint_as_float(a & 0xFFFF0000u);
+            }
+        } else {
+            v[0] = v[1] = 0.0;
+        }
+        return;
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) v[t] = (row < rows && c0 + t < R) ? ld<T>(F, row * R + c0 + t) : 0.0;
+}
+
+template <typename T, int NT, int BS, bool VEC>
 __global__ __launch_bounds__(BS) void k_gram_mfma(const T *__restrict__ F, int64_t rows, int R,
                                                   double *__restrict__ part) {
     constexpr int NP = NT * (NT + 1) / 2;  // tile pairs rt <= ct
@@ -178,16 +205,12 @@ __global__ __launch_bounds__(BS) void k_gram_mfma(const T *__restrict__ F, int64
     // past the end read as zero.  The next step is loaded before the current
     // one's MFMAs.
     const int64_t nsteps = (rows + 15) / 16;
+    // Column tile t, MFMA index c is column c * NT + t, so a lane reads the
+    // NT consecutive columns cl * NT .. + NT of a row.
     auto load = [&](int64_t step, double (&v)[4][NT]) {
 #pragma unroll
-        for (int sub = 0; sub < 4; ++sub) {
-            const int64_t row = step * 16 + sub * 4 + kr;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int c = t * 16 + cl;
-                v[sub][t] = (row < rows && c < R) ? ld<T>(F, row * R + c) : 0.0;
-            }
-        }
+        for (int sub = 0; sub < 4; ++sub)
+            gram_load<T, NT, VEC>(F, step * 16 + sub * 4 + kr, rows, R, cl * NT, v[sub]);
     };
     double v[4][NT];
     if (gw < nsteps) load(gw, v);
@@ -227,7 +250,7 @@ __global__ __launch_bounds__(BS) void k_gram_mfma(const T *__restrict__ F, int64
         int q = e / 256, rt = 0;
         while (q >= NT - rt) { q -= NT - rt; ++rt; }  // pair index -> (rt, ct)
         const int ct = rt + q;
-        const int r = rt * 16 + (e % 256) / 16, c = ct * 16 + e % 16;
+        const int r = ((e % 256) / 16) * NT + rt, c = (e % 16) * NT + ct;
         if (r < R && c < R) {
             pb[r * R + c] = sacc[e];
             if (rt != ct) pb[c * R + r] = sacc[e];
@@ -235,21 +258,24 @@ __global__ __launch_bounds__(BS) void k_gram_mfma(const T *__restrict__ F, int64
     }
 }
 
-// G[e] = sum_b part[b][e]: 4 slices per entry, combined in slice order.
+// G[e] = sum_b part[b][e]: a block takes 16 entries; slice q (16 per entry)
+// sums the partials b = q, q + 16, ...; the slices are combined in order.
 __global__ __launch_bounds__(kBlock) void k_gram_reduce(const double *__restrict__ part, int nblk,
                                                         int R, double *__restrict__ G) {
-    __shared__ double sh[4][64];
-    const int e = blockIdx.x * 64 + (threadIdx.x % 64);
-    const int sl = threadIdx.x / 64;
+    __shared__ double sh[16][17];
+    const int e = blockIdx.x * 16 + threadIdx.x % 16;
+    const int sl = threadIdx.x / 16;
     const int RR = R * R;
     double s = 0.0;
     if (e < RR)
-        for (int b = sl; b < nblk; b += 4) s += part[(size_t)b * RR + e];
-    sh[sl][threadIdx.x % 64] = s;
+        for (int b = sl; b < nblk; b += 16) s += part[(size_t)b * RR + e];
+    sh[sl][threadIdx.x % 16] = s;
     __syncthreads();
-    if (sl == 0 && e < RR) {
-        const int l = threadIdx.x;
-        G[e] = ((sh[0][l] + sh[1][l]) + sh[2][l]) + sh[3][l];
+    if (threadIdx.x < 16 && e < RR) {
+        double t = sh[0][threadIdx.x];
+#pragma unroll
+        for (int q = 1; q < 16; ++q) t += sh[q][threadIdx.x];
+        G[e] = t;
     }
 }
 
@@ -295,6 +321,62 @@ constexpr int kLambdaSmemMaxR = 40;  // 4 R^2 + R doubles
 // dynamic LDS when SMEM, else in `scratch`.  flag[0] = 1 when the
 // pseudo-inverse path was taken.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Gauss-Jordan on [H | I] in the registers of one wave (R <= 32): lane l
+// holds column l of the R x 2R working matrix; the pivot and the pivot
+// column's entries reach every lane by readlane.  The arithmetic (scale the
+// pivot row by 1/pivot, then row_i -= a_ij * row_j) is the same, operation
+// for operation, as the LDS version in k_solve.  On success columns R .. 2R-1
+// (H^-1) are written to Bw (R x R, row-major); returns false at the first
+// pivot that is not above tol.
+template <int B, int E, typename Fn>
+__device__ __forceinline__ void unroll_for(Fn &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        unroll_for<B + 1, E>(f);
+    }
+}
+
+__device__ bool gauss_jordan_wave(const double *H, int R, double tol, double *Bw) {
+    constexpr int RM = 32;
+    const int l = threadIdx.x % 64;
+    double col[RM];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+        col[i] = (i < R) ? (l < R ? H[i * R + l] : (l - R == i ? 1.0 : 0.0)) : 0.0;
+    bool ok = true;
+    // j and i are compile-time constants, so col[] stays in registers
+    unroll_for<0, RM>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (!ok || j >= R) return;
+        const double piv = readlane_f64(col[j], j);
+        if (!(piv > tol)) {
+            ok = false;
+            return;
+        }
+        const double inv = 1.0 / piv;
+        col[j] *= inv;
+        unroll_for<0, RM>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if (i == j || i >= R) return;
+            col[i] = fma(-readlane_f64(col[i], j), col[j], col[i]);
+        });
+        __builtin_amdgcn_sched_barrier(0);  // keep the steps apart: no hoisted readlanes
+    });
+    if (!ok) return false;
+    if (l >= R && l < 2 * R) {
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+            if (i < R) Bw[i * R + (l - R)] = col[i];
+    }
+    return true;
+}
+
 template <bool SMEM>
 __global__ __launch_bounds__(kBlock) void k_solve(int R, const double *__restrict__ Gp,
                                                   const double *__restrict__ Gq, double reg,
@@ -329,33 +411,41 @@ __global__ __launch_bounds__(kBlock) void k_solve(int R, const double *__restric
     // H, Bw (in Li) starts as I and ends as H^-1.
     double *Aw = L, *Bw = Li;
     __shared__ double s_f[kBlock];
-    for (int e = tid; e < RR; e += kBlock) {
-        Aw[e] = H[e];
-        Bw[e] = (e / R == e % R) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    for (int j = 0; j < R; ++j) {
-        const double piv = Aw[j * R + j];
-        if (!(piv > tol)) {  // uniform: every thread reads the same value
-            if (tid == 0) s_fail = 1;
-            break;
-        }
-        const double inv = 1.0 / piv;
-        __syncthreads();  // all threads have read the pivot
-        for (int k = tid; k < 2 * R; k += kBlock) {
-            if (k < R) Aw[j * R + k] *= inv;
-            else Bw[j * R + k - R] *= inv;
-        }
-        for (int i = tid; i < R; i += kBlock) s_f[i] = (i == j) ? 0.0 : Aw[i * R + j];
-        __syncthreads();
-        for (int e = tid; e < R * 2 * R; e += kBlock) {
-            const int i = e / (2 * R), k = e % (2 * R);
-            const double f = s_f[i];
-            if (f == 0.0) continue;
-            if (k < R) Aw[i * R + k] = fma(-f, Aw[j * R + k], Aw[i * R + k]);
-            else Bw[i * R + k - R] = fma(-f, Bw[j * R + k - R], Bw[i * R + k - R]);
+    if (R <= 32) {
+        if (tid < 64 && !s_fail) {
+            const bool ok = gauss_jordan_wave(H, R, tol, Bw);
+            if (tid == 0 && !ok) s_fail = 1;
         }
         __syncthreads();
+    } else {
+        for (int e = tid; e < RR; e += kBlock) {
+            Aw[e] = H[e];
+            Bw[e] = (e / R == e % R) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < R; ++j) {
+            const double piv = Aw[j * R + j];
+            if (!(piv > tol)) {  // uniform: every thread reads the same value
+                if (tid == 0) s_fail = 1;
+                break;
+            }
+            const double inv = 1.0 / piv;
+            __syncthreads();  // all threads have read the pivot
+            for (int k = tid; k < 2 * R; k += kBlock) {
+                if (k < R) Aw[j * R + k] *= inv;
+                else Bw[j * R + k - R] *= inv;
+            }
+            for (int i = tid; i < R; i += kBlock) s_f[i] = (i == j) ? 0.0 : Aw[i * R + j];
+            __syncthreads();
+            for (int e = tid; e < R * 2 * R; e += kBlock) {
+                const int i = e / (2 * R), k = e % (2 * R);
+                const double f = s_f[i];
+                if (f == 0.0) continue;
+                if (k < R) Aw[i * R + k] = fma(-f, Aw[j * R + k], Aw[i * R + k]);
+                else Bw[i * R + k - R] = fma(-f, Bw[j * R + k - R], Bw[i * R + k - R]);
+            }
+            __syncthreads();
+        }
     }
     __syncthreads();
     if (!s_fail) {
@@ -752,6 +842,202 @@ int vec_rows(const void *p, int R, int elem) {
     return ((uintptr_t)p % 16 == 0) && (((size_t)R * elem) % 16 == 0);
 }
 
+// ---------------------------------------------------------------------------
+// Row maps on the matrix cores, R = 16 * NCT (16, 32, 48, 64).
+//
+// A wave takes 16 rows X[r0 .. r0+16) at a time and forms out^T = W^T X^T with
+// FP64 MFMA 16x16x4 steps: the R x R matrix is the A operand and stays in
+// registers for the whole kernel (4 * NCT^2 doubles per lane), the rows are
+// the B operand.  Two index permutations make every lane's memory accesses
+// 4 consecutive elements wide:
+//  * contraction index: at step t, lane group g = lane / 16 contributes
+//    k = 16 * (t / 4) + 4 * g + t % 4, so a lane reads columns
+//    16 * c + 4 * g .. + 4 of its row for c = 0 .. NCT-1;
+//  * output index: MFMA output row m of column tile c is column
+//    16 * c + 4 * (m % 4) + m / 4, so the 4 accumulator entries of a lane are
+//    columns 16 * c + 4 * g .. + 4 of row r0 + lane % 16 -- the same columns
+//    it read.
+// Accumulation is FP64; the next tile's rows are loaded before the current
+// tile's MFMAs.
+// ---------------------------------------------------------------------------
+// Raw 4-element runs (kept undecoded while in flight: half the registers of
+// doubles for FP32, a quarter for BF16).
+template <typename T>
+struct Run4;
+template <>
+struct Run4<float> {
+    float4 v;
+    __device__ __forceinline__ void load(const float *p) { v = *reinterpret_cast<const float4 *>(p); }
+    __device__ __forceinline__ void zero() { v = make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ __forceinline__ double operator[](int i) const {
+        return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+    }
+};
+template <>
+struct Run4<uint16_t> {
+    uint2 v;
+    __device__ __forceinline__ void load(const uint16_t *p) { v = *reinterpret_cast<const uint2 *>(p); }
+    __device__ __forceinline__ void zero() { v = make_uint2(0u, 0u); }
+    __device__ __forceinline__ double operator[](int i) const {
+        const uint32_t w = i < 2 ? v.x : v.y;
+        return __uint_as_float((i % 2 == 0) ? (w << 16) : (w & 0xFFFF0000u));
+    }
+};
+__device__ __forceinline__ void store4d(float *p, const double4v &a) {
+    *reinterpret_cast<float4 *>(p) = make_float4((float)a[0], (float)a[1], (float)a[2], (float)a[3]);
+}
+__device__ __forceinline__ void store4d(uint16_t *p, const double4v &a) {
+    uint2 w;
+    w.x = (uint32_t)f32_to_bf16((float)a[0]) | ((uint32_t)f32_to_bf16((float)a[1]) << 16);
+    w.y = (uint32_t)f32_to_bf16((float)a[2]) | ((uint32_t)f32_to_bf16((float)a[3]) << 16);
+    *reinterpret_cast<uint2 *>(p) = w;
+}
+
+// wa[c][t] = W[k(t)][16 c + column of MFMA row lane % 16]
+template <int NCT>
+__device__ __forceinline__ void load_rmat(const double *__restrict__ W, int lane,
+                                          double (&wa)[NCT][4 * NCT]) {
+    constexpr int R = 16 * NCT;
+    const int g = lane / 16, m = lane % 16;
+    const int col = 4 * (m % 4) + m / 4;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+        for (int t = 0; t < 4 * NCT; ++t) {
+            const int k = 16 * (t / 4) + 4 * g + t % 4;
+            wa[c][t] = W[k * R + 16 * c + col];
+        }
+}
+
+// the 4 * NCT entries of row `row` that this lane reads (zero past the last row)
+template <int NCT, typename T>
+__device__ __forceinline__ void load_rowrun(const T *__restrict__ X, int64_t row, int64_t rows,
+                                            int g, Run4<T> (&v)[NCT]) {
+    constexpr int R = 16 * NCT;
+    if (row < rows) {
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) v[c].load(X + row * R + 16 * c + 4 * g);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) v[c].zero();
+    }
+}
+
+// F[row, s] = sum_k M[row, k] W[k, s]
+template <typename Tout, int NCT>
+__global__ __launch_bounds__(kBlock) void k_rowmap_mfma(const float *__restrict__ M, int64_t rows,
+                                                        const double *__restrict__ W,
+                                                        Tout *__restrict__ F) {
+    constexpr int R = 16 * NCT, S = 4 * NCT;
+    const int lane = threadIdx.x % 64, g = lane / 16;
+    double wa[NCT][S];
+    load_rmat<NCT>(W, lane, wa);
+    const int64_t ntile = (rows + 15) / 16;
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    int64_t tile = (int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    Run4<float> x[NCT];
+    load_rowrun<NCT>(M, tile * 16 + lane % 16, rows, g, x);
+    for (; tile < ntile; tile += nw) {
+        const int64_t row = tile * 16 + lane % 16;
+        Run4<float> xn[NCT];
+        load_rowrun<NCT>(M, row + 16 * nw, rows, g, xn);
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+            double4v acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int t = 0; t < S; ++t)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[c][t], x[t / 4][t % 4], acc, 0, 0, 0);
+            if (row < rows) store4d(F + row * R + 16 * c + 4 * g, acc);
+        }
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) x[c] = xn[c];
+    }
+}
+
+// G[row, s] = -G[row, s] + sum_k F[row, k] H[k, s]  (G holds the MTTKRP on
+// entry); partial[block] = sum over the block's rows of <F[row,:], G[row,:]>
+// (the entry values).
+template <typename T, int NCT>
+__global__ __launch_bounds__(kBlock) void k_gd_rows_mfma(float *__restrict__ G,
+                                                         const T *__restrict__ F, int64_t rows,
+                                                         const double *__restrict__ H,
+                                                         double *__restrict__ partial) {
+    constexpr int R = 16 * NCT, S = 4 * NCT;
+    __shared__ double sh[kBlock];
+    const int lane = threadIdx.x % 64, g = lane / 16;
+    double wa[NCT][S];
+    load_rmat<NCT>(H, lane, wa);
+    const int64_t ntile = (rows + 15) / 16;
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    int64_t tile = (int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    double inner = 0.0;
+    Run4<T> f[NCT];
+    Run4<float> m[NCT];
+    load_rowrun<NCT>(F, tile * 16 + lane % 16, rows, g, f);
+    load_rowrun<NCT>((const float *)G, tile * 16 + lane % 16, rows, g, m);
+    for (; tile < ntile; tile += nw) {
+        const int64_t row = tile * 16 + lane % 16;
+        Run4<T> fn[NCT];
+        Run4<float> mn[NCT];
+        load_rowrun<NCT>(F, row + 16 * nw, rows, g, fn);
+        load_rowrun<NCT>((const float *)G, row + 16 * nw, rows, g, mn);
+#pragma unroll
+        for (int t = 0; t < S; ++t) inner = fma(f[t / 4][t % 4], m[t / 4][t % 4], inner);
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+            double4v acc = {-m[c][0], -m[c][1], -m[c][2], -m[c][3]};
+#pragma unroll
+            for (int t = 0; t < S; ++t)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[c][t], f[t / 4][t % 4], acc, 0, 0, 0);
+            if (row < rows) store4d(G + row * R + 16 * c + 4 * g, acc);
+        }
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+            f[c] = fn[c];
+            m[c] = mn[c];
+        }
+    }
+    const double tot = block_sum(inner, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// ranks with a matrix-core row kernel; the rows must start 16-byte aligned
+// (FP32) or 8-byte aligned (BF16)
+bool mfma_rows_ok(int R, const void *a, size_t ea, const void *b, size_t eb) {
+    if (!(R == 16 || R == 32 || R == 48 || R == 64)) return false;
+    return (uintptr_t)a % (4 * ea) == 0 && (uintptr_t)b % (4 * eb) == 0;
+}
+
+unsigned rows_grid_mfma(int64_t rows) {
+    const int64_t ntile = (rows + 15) / 16;
+    const int64_t want = (ntile + 4 * 4 - 1) / (4 * 4);  // about 4 tiles per wave
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 2048));
+}
+
+template <typename Tout>
+void rowmap_mfma(hipStream_t s, const float *M, int64_t rows, int R, const double *W, void *F) {
+    const dim3 grid(rows_grid_mfma(rows)), block(kBlock);
+    switch (R) {
+        case 16: hipLaunchKernelGGL((k_rowmap_mfma<Tout, 1>), grid, block, 0, s, M, rows, W, (Tout *)F); break;
+        case 32: hipLaunchKernelGGL((k_rowmap_mfma<Tout, 2>), grid, block, 0, s, M, rows, W, (Tout *)F); break;
+        case 48: hipLaunchKernelGGL((k_rowmap_mfma<Tout, 3>), grid, block, 0, s, M, rows, W, (Tout *)F); break;
+        default: hipLaunchKernelGGL((k_rowmap_mfma<Tout, 4>), grid, block, 0, s, M, rows, W, (Tout *)F); break;
+    }
+}
+
+template <typename T>
+void gd_rows_mfma(hipStream_t s, float *G, const void *F, int64_t rows, int R, const double *H,
+                  double *partial) {
+    const dim3 grid(rows_grid_mfma(rows)), block(kBlock);
+    const T *Ft = (const T *)F;
+    switch (R) {
+        case 16: hipLaunchKernelGGL((k_gd_rows_mfma<T, 1>), grid, block, 0, s, G, Ft, rows, H, partial); break;
+        case 32: hipLaunchKernelGGL((k_gd_rows_mfma<T, 2>), grid, block, 0, s, G, Ft, rows, H, partial); break;
+        case 48: hipLaunchKernelGGL((k_gd_rows_mfma<T, 3>), grid, block, 0, s, G, Ft, rows, H, partial); break;
+        default: hipLaunchKernelGGL((k_gd_rows_mfma<T, 4>), grid, block, 0, s, G, Ft, rows, H, partial); break;
+    }
+}
+
 bool tiled_rows_ok(int R) {  // ranks with a compile-time LDS-tiled row kernel (<= ~51 KB LDS)
     return R == 4 || R == 8 || R == 12 || R == 16 || R == 32 || R == 48;
 }
@@ -776,24 +1062,30 @@ void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t row
     if (R <= 16 * kMfmaMaxTiles) {
         const int nt = (R + 15) / 16;
         const int bs = nt <= 2 ? 1024 : 256;  // 16 waves per block when the registers allow
-        const int64_t want = (rows + 16 * 8 * (bs / 64) - 1) / (16 * 8 * (bs / 64));
+        const int64_t want = (rows + 16 * 2 * (bs / 64) - 1) / (16 * 2 * (bs / 64));
         const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256));
         double *part =
             (double *)ws_get(ctx, dfacto_ctx::kPartial, sizeof(double) * 256 * (size_t)R * R);
-#define GM(T, NTV) hipLaunchKernelGGL((k_gram_mfma<T, NTV, (NTV <= 2 ? 1024 : 256)>), dim3(nblk), dim3(NTV <= 2 ? 1024 : 256), 0, s, (const T *)F, rows, R, part)
+        const size_t es = dtype == DFACTO_F32 ? 4 : 2;
+        const bool vec2 = R == 32 && (uintptr_t)F % (2 * es) == 0;
+#define GM(T, NTV, V)                                                                              \
+    hipLaunchKernelGGL((k_gram_mfma<T, NTV, (NTV <= 2 ? 1024 : 256), V>), dim3(nblk),              \
+                       dim3(NTV <= 2 ? 1024 : 256), 0, s, (const T *)F, rows, R, part)
         if (dtype == DFACTO_F32) {
-            if (nt == 1) GM(float, 1);
-            else if (nt == 2) GM(float, 2);
-            else if (nt == 3) GM(float, 3);
-            else GM(float, 4);
+            if (nt == 1) GM(float, 1, false);
+            else if (nt == 2 && vec2) GM(float, 2, true);
+            else if (nt == 2) GM(float, 2, false);
+            else if (nt == 3) GM(float, 3, false);
+            else GM(float, 4, false);
         } else {
-            if (nt == 1) GM(uint16_t, 1);
-            else if (nt == 2) GM(uint16_t, 2);
-            else if (nt == 3) GM(uint16_t, 3);
-            else GM(uint16_t, 4);
+            if (nt == 1) GM(uint16_t, 1, false);
+            else if (nt == 2 && vec2) GM(uint16_t, 2, true);
+            else if (nt == 2) GM(uint16_t, 2, false);
+            else if (nt == 3) GM(uint16_t, 3, false);
+            else GM(uint16_t, 4, false);
         }
 #undef GM
-        hipLaunchKernelGGL(k_gram_reduce, dim3((R * R + 63) / 64), dim3(kBlock), 0, s, part, nblk, R,
+        hipLaunchKernelGGL(k_gram_reduce, dim3((R * R + 15) / 16), dim3(kBlock), 0, s, part, nblk, R,
                            G);
         DF_HIP(hipGetLastError());
         return;
@@ -818,7 +1110,7 @@ void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t row
         else GRAM_LAUNCH(uint16_t, 64);
     }
 #undef GRAM_LAUNCH
-    hipLaunchKernelGGL(k_gram_reduce, dim3((R * R + 63) / 64), dim3(kBlock), 0, s, part, nblk, R, G);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((R * R + 15) / 16), dim3(kBlock), 0, s, part, nblk, R, G);
     DF_HIP(hipGetLastError());
 }
 
@@ -908,6 +1200,13 @@ void launch_rowmap(dfacto_ctx *ctx, const float *M, int64_t rows, int R, const d
                    dfacto_dtype dtype) {
     if (rows <= 0) return;
     hipStream_t s = ctx->stream;
+    const size_t ef = dtype == DFACTO_F32 ? 4 : 2;
+    if (mfma_rows_ok(R, M, 4, F, ef)) {
+        if (dtype == DFACTO_F32) rowmap_mfma<float>(s, M, rows, R, W, F);
+        else rowmap_mfma<uint16_t>(s, M, rows, R, W, F);
+        DF_HIP(hipGetLastError());
+        return;
+    }
     const bool done = dtype == DFACTO_F32
                           ? dispatch_tiled<RowmapK, float>(R, s, M, rows, W, F)
                           : dispatch_tiled<RowmapK, uint16_t>(R, s, M, rows, W, F);
@@ -923,7 +1222,8 @@ void launch_rowmap(dfacto_ctx *ctx, const float *M, int64_t rows, int R, const d
     DF_HIP(hipGetLastError());
 }
 
-int gd_rows_partials(int64_t rows, int R) {
+int gd_rows_partials(int64_t rows, int R, const float *G, const void *F, dfacto_dtype dtype) {
+    if (mfma_rows_ok(R, G, 4, F, dtype == DFACTO_F32 ? 4 : 2)) return (int)rows_grid_mfma(rows);
     return (int)(tiled_rows_ok(R) ? rows_grid_tiles(rows, R)
                                   : rows_grid_generic(rows, R, kBlock * 2));
 }
@@ -932,11 +1232,17 @@ void launch_gd_rows(dfacto_ctx *ctx, float *G, const void *F, dfacto_dtype dtype
                     int R, const double *H, double *inner_partial) {
     if (rows <= 0) return;
     hipStream_t s = ctx->stream;
+    if (mfma_rows_ok(R, G, 4, F, dtype == DFACTO_F32 ? 4 : 2)) {
+        if (dtype == DFACTO_F32) gd_rows_mfma<float>(s, G, F, rows, R, H, inner_partial);
+        else gd_rows_mfma<uint16_t>(s, G, F, rows, R, H, inner_partial);
+        DF_HIP(hipGetLastError());
+        return;
+    }
     const bool done = dtype == DFACTO_F32
                           ? dispatch_tiled<GdRowsK, float>(R, s, G, F, rows, H, inner_partial)
                           : dispatch_tiled<GdRowsK, uint16_t>(R, s, G, F, rows, H, inner_partial);
     if (!done) {
-        const unsigned g = (unsigned)gd_rows_partials(rows, R);
+        const unsigned g = (unsigned)gd_rows_partials(rows, R, G, F, dtype);
         if (dtype == DFACTO_F32)
             hipLaunchKernelGGL(k_gd_rows_g<float>, dim3(g), dim3(kBlock), 0, s, G,
                                (const float *)F, rows, R, H, inner_partial);

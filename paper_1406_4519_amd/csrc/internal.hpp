@@ -130,6 +130,6 @@ void launch_gd_rows(dfacto_ctx *ctx, float *G, const void *F, dfacto_dtype dtype
 void launch_gd_f(dfacto_ctx *ctx, int R, const double *GA, const double *GB, const double *GC,
                  const double *inner_partial, int npartial, double normsq, double reg,
                  double *f_out);
-int gd_rows_partials(int64_t rows, int R);
+int gd_rows_partials(int64_t rows, int R, const float *G, const void *F, dfacto_dtype dtype);
 
 }  // namespace dfacto

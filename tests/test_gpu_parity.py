@@ -7,8 +7,12 @@ Tolerances (FP32 arithmetic on the device):
   the fiber, root and carry sums), and relative Frobenius error <= 1e-5.
   BF16 factors are rounded identically for both sides, so the same bound
   applies.
-* ALS / GD: relative Frobenius error <= 1e-5 on FP32 results (BF16-stored
-  factors <= 1e-2), fit within 1e-4.
+* ALS / GD: relative Frobenius error <= 1e-5 on FP32 results, fit within
+  1e-4.  BF16-stored factors are compared with the oracle run with the same
+  storage rounding between modes: each entry is the BF16 rounding of nearly
+  the same FP64 value, so they differ by at most one BF16 unit (2^-8
+  relative) where the two values straddle a rounding boundary; the bound is
+  relative Frobenius error <= 2^-8.
 * Integer work (flattening structure) is compared exactly.
 """
 import json
@@ -26,6 +30,7 @@ from paper_1406_4519_amd import dfacto, gen
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
+BF16_REL = 2.0 ** -8
 
 
 @pytest.fixture(scope="module")
@@ -329,11 +334,11 @@ def test_als_bf16_one_step(ctx):
     t = build(ctx, coo)
     Fd, Fw = factors_to_dev(F0, "bf16")
     lam, fits = _als_gpu(ctx, t, Fd, 1)
-    A, B, C, lam_ref, info = oracle.als_iter(*coo.arrays64(), coo.dims, Fw)
+    A, B, C, lam_ref, info = oracle.als_iter(*coo.arrays64(), coo.dims, Fw, store="bf16")
     errs = [rel_fro(to_host64(Fd[m]), ref) for m, ref in enumerate((A, B, C))]
-    say(f"  als bf16 one step: factor errors {errs}")
-    assert max(errs) <= 1e-2
-    assert rel_fro(lam, lam_ref) <= 1e-2
+    say(f"  als bf16 one step: factor errors {errs}, lambda {rel_fro(lam, lam_ref)}")
+    assert max(errs) <= BF16_REL
+    assert rel_fro(lam, lam_ref) <= BF16_REL
     assert abs(fits[0] - info["fit"]) <= 1e-3
 
 
@@ -376,4 +381,84 @@ def test_gd_grad_parity(ctx, dtype, reg):
     errs = [rel_fro(to_host64(grads[m]), gref[m]) for m in range(3)]
     say(f"  gd {dtype} reg={reg}: grad errors {errs}, f {f.item()} vs {fref}")
     assert max(errs) <= 1e-5
+    assert abs(f.item() - fref) <= 1e-6 * abs(fref)
+
+
+# ---------------------------------------------------------------------------
+# every rank class of the dense kernels: matrix-core row maps (R = 16, 32,
+# 48, 64), LDS-tiled rows (4, 8, 12), generic rows (others); the one-wave
+# register Gauss-Jordan (R <= 32) and the LDS one (R > 32)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def zipf_small(ctx):
+    coo = gen.zipf_distinct((700, 400, 250), 40_000, 1.1, seed=9)
+    return coo, build(ctx, coo)
+
+
+def _misaligned(F64, dtype):
+    """Device factors whose rows start 4 bytes (FP32) or 2 bytes (BF16) past
+    a 16-byte boundary: only the element-aligned kernels may run."""
+    Fd, Fw = factors_to_dev(F64, dtype)
+    out = []
+    for f in Fd:
+        buf = torch.empty(f.numel() + 8, dtype=f.dtype, device=DEV)
+        v = buf[1:1 + f.numel()].view(f.shape)
+        v.copy_(f)
+        out.append(v)
+    return out, Fw
+
+
+@pytest.mark.parametrize("R", [1, 3, 4, 8, 12, 16, 20, 32, 48, 64, 100])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_als_gd_ranks(ctx, zipf_small, R, dtype):
+    coo, t = zipf_small
+    F0 = gen.init_factors(coo.dims, R, seed=300 + R)
+    tol_f = 1e-5 if dtype == "f32" else BF16_REL
+    Fd, Fw = factors_to_dev(F0, dtype)
+    lam, fits = _als_gpu(ctx, t, Fd, 1)
+    A, B, C, lam_ref, info = oracle.als_iter(*coo.arrays64(), coo.dims, Fw,
+                                             store="f64" if dtype == "f32" else "bf16")
+    errs = [rel_fro(to_host64(Fd[m]), ref) for m, ref in enumerate((A, B, C))]
+    say(f"  R={R} {dtype}: als factor errors {max(errs):.2e} lambda {rel_fro(lam, lam_ref):.2e} "
+        f"pinv {info['pinv_mask']}")
+    assert max(errs) <= tol_f
+    assert rel_fro(lam, lam_ref) <= tol_f
+    # GD gradient at the same (start) point
+    Fd, Fw = factors_to_dev(F0, dtype)
+    grads = [torch.empty((d, R), device=DEV) for d in coo.dims]
+    f = torch.zeros(1, dtype=torch.float64, device=DEV)
+    dfacto.gd_grad(ctx, t, Fd, grads, f)
+    torch.cuda.synchronize()
+    gref, fref = oracle.gd_grad(*coo.arrays64(), coo.dims, Fw)
+    gerr = [rel_fro(to_host64(grads[m]), gref[m]) for m in range(3)]
+    say(f"  R={R} {dtype}: gd errors {max(gerr):.2e}, f {f.item()} vs {fref}")
+    assert max(gerr) <= 1e-5
+    assert abs(f.item() - fref) <= 1e-6 * abs(fref)
+
+
+@pytest.mark.parametrize("R", [16, 32])
+def test_als_gd_misaligned_rows(ctx, zipf_small, R):
+    """Factors not 16-byte aligned take the element-aligned row kernels and
+    give the same results."""
+    coo, t = zipf_small
+    F0 = gen.init_factors(coo.dims, R, seed=400 + R)
+    Fd, Fw = _misaligned(F0, "f32")
+    lam, fits = _als_gpu(ctx, t, Fd, 1)
+    A, B, C, lam_ref, info = oracle.als_iter(*coo.arrays64(), coo.dims, Fw)
+    errs = [rel_fro(to_host64(Fd[m]), ref) for m, ref in enumerate((A, B, C))]
+    assert max(errs) <= 1e-5
+    Fd, Fw = _misaligned(F0, "f32")
+    grads = [torch.empty((d, R), device=DEV) for d in coo.dims]
+    gbufs = []
+    for m, d in enumerate(coo.dims):
+        buf = torch.empty(d * R + 8, device=DEV)
+        gbufs.append(buf[1:1 + d * R].view(d, R))
+    f = torch.zeros(1, dtype=torch.float64, device=DEV)
+    dfacto.gd_grad(ctx, t, Fd, gbufs, f)
+    torch.cuda.synchronize()
+    gref, fref = oracle.gd_grad(*coo.arrays64(), coo.dims, Fw)
+    gerr = [rel_fro(to_host64(gbufs[m]), gref[m]) for m in range(3)]
+    say(f"  misaligned R={R}: als {max(errs):.2e} gd {max(gerr):.2e}")
+    assert max(gerr) <= 1e-5
     assert abs(f.item() - fref) <= 1e-6 * abs(fref)

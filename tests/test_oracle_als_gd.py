@@ -63,6 +63,47 @@ def test_als_iteration_vs_dense_least_squares(reg):
     assert info["pinv_mask"] == 0
 
 
+def test_als_bf16_storage_vs_dense_least_squares():
+    """store="bf16": the same dense least-squares steps, each new factor
+    rounded to BF16 (through FP32, nearest-even) before the next mode uses it;
+    lambda from the unrounded factor.  Rounding by gen's independent
+    converter."""
+    rng = np.random.default_rng(3)
+    dims = (7, 6, 5)
+    R = 3
+    i, j, k, val = brute.random_coo(rng, dims, 90)
+    F0 = [rng.random((d, R)) for d in dims]
+    A1, B1, C1, lam, info = oracle.als_iter(i, j, k, val, dims, F0, 0.0, store="bf16")
+    X = brute.dense(dims, i, j, k, val)
+
+    def rnd(F):
+        return gen.bf16_to_f32(gen.f32_to_bf16(F.astype(np.float32))).astype(np.float64)
+
+    def ls(Xn, KR):
+        return np.linalg.solve(KR.T @ KR, KR.T @ Xn.T).T
+
+    A, B, C = (f.copy() for f in F0)
+    A, _ = _normalize(ls(brute.flatten(X, 0), brute.khatri_rao(C, B)))
+    A = rnd(A)
+    B, _ = _normalize(ls(brute.flatten(X, 1), brute.khatri_rao(A, C)))
+    B = rnd(B)
+    C, lamC = _normalize(ls(brute.flatten(X, 2), brute.khatri_rao(B, A)))
+    C = rnd(C)
+    # every output is exactly a BF16 value
+    for F in (A1, B1, C1):
+        np.testing.assert_array_equal(F, rnd(F))
+    np.testing.assert_allclose(A1, A, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(B1, B, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(C1, C, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(lam, lamC, rtol=1e-9)
+    Xh = brute.cp_full((A1, B1, C1), lam)
+    fit = 1 - np.linalg.norm(X - Xh) / np.linalg.norm(X)
+    np.testing.assert_allclose(info["fit"], fit, rtol=1e-9, atol=1e-10)
+    # and it differs from FP64 storage
+    A2, B2, C2, _, _ = oracle.als_iter(i, j, k, val, dims, F0, 0.0)
+    assert np.abs(C2 - C1).max() > 1e-6
+
+
 def test_als_last_mode_is_least_squares_optimal():
     """Right after the mode-3 solve (before normalization), the gradient of
     the ridge objective with respect to C vanishes."""
