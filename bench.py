@@ -80,12 +80,112 @@ def cpu_baseline(coo, R, F0, target_s: float):
                       f"first {S:,} of {coo.nnz:,} nonzeros, same dims, R={R}"}
 
 
+def run_batched(args):
+    """Batched CP-ALS: args.batch independent Zipf(1.1) tensors (dims
+    log-uniform in [1e3, 1e5] per mode, nnz log-uniform in [1e4, 5e6], R from
+    {8, 16, 32}), args.iters ALS iterations each, run as one group (grouped
+    launches, tuned MTTKRP grids) and, for comparison, one tensor at a time
+    through dfacto_als_iter.  value = grouped throughput, sum over tensors of
+    3 nnz R per iteration, per second."""
+    import numpy as np
+    import torch
+    from paper_1406_4519_amd import dfacto, gen
+
+    dev = torch.device("cuda:0")
+    ctx = dfacto.Context(0)
+    t0 = time.perf_counter()
+    members = []
+    for t in range(args.batch):
+        coo, R, F0 = gen.batched_tensor(t)
+        i = torch.from_numpy(coo.i.view(np.int32)).to(dev)
+        j = torch.from_numpy(coo.j.view(np.int32)).to(dev)
+        k = torch.from_numpy(coo.k.view(np.int32)).to(dev)
+        v = torch.from_numpy(coo.val).to(dev)
+        T = dfacto.build_flattenings(ctx, coo.dims, i, j, k, v)
+        members.append((T, R, F0, coo.nnz, coo.dims))
+        del i, j, k, v
+    torch.cuda.synchronize()
+    log(f"generated and built {args.batch} tensors in {time.perf_counter() - t0:.1f}s")
+    work = sum(3.0 * nnz * R for _, R, _, nnz, _ in members) * args.iters
+    total_nnz = sum(nnz for _, _, _, nnz, _ in members)
+
+    def fresh(dtype_name):
+        tdt = torch.float32 if dtype_name == "f32" else torch.bfloat16
+        Fs = [[torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(dev).to(tdt)
+               for f in F0] for _, _, F0, _, _ in members]
+        lams = [torch.zeros(R, dtype=torch.float64, device=dev) for _, R, _, _, _ in members]
+        return Fs, lams, torch.zeros(len(members), dtype=torch.float64, device=dev)
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for dt in ("f32", "bf16"):
+        Fs, lams, fits = fresh(dt)
+        tc = time.perf_counter()
+        g = dfacto.Group(ctx, [m[0] for m in members], Fs, lams, fits, tune=True, graph=True)
+        create_s = time.perf_counter() - tc
+        info = g.info()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        e0.record()
+        g.als(args.iters)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - ts
+        ms = e0.elapsed_time(e1)
+        res[dt] = dict(ms=ms, wall_s=wall, create_s=create_s, info=info,
+                       mean_fit=float(fits.mean().item()))
+        g.close()
+        del Fs, lams, fits
+    # one tensor at a time (FP32), same iterations
+    Fs, lams, fits = fresh("f32")
+    fit1 = torch.zeros(1, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    e0.record()
+    for (T, R, _, _, _), F, lam in zip(members, Fs, lams):
+        for _ in range(args.iters):
+            dfacto.als_iter(ctx, T, F, lam, fit1)
+    e1.record()
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1)
+    seq_wall = time.perf_counter() - ts
+    g32 = res["f32"]
+    line = {"metric": "grouped CP-ALS nnz·R/s (batched solves)",
+            "value": work / (g32["ms"] * 1e-3), "unit": "nnz·R/s", "n_gpus": 1,
+            "steps": args.iters, "warmup": 0, "ms_per_step": round(g32["ms"] / args.iters, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"batched: {args.batch} tensors, dims log-uniform [1e3,1e5], "
+                                   f"nnz log-uniform [1e4,5e6], Zipf(1.1), R in {{8,16,32}}, "
+                                   f"{args.iters} ALS iterations each",
+                       "total_nnz": total_nnz, "parallelism": "single GPU"},
+            "extra": {"solves_per_s_grouped_f32": args.batch / (g32["ms"] * 1e-3),
+                      "solves_per_s_grouped_bf16": args.batch / (res["bf16"]["ms"] * 1e-3),
+                      "solves_per_s_one_at_a_time_f32": args.batch / (seq_ms * 1e-3),
+                      "grouped_ms": {k: round(v["ms"], 3) for k, v in res.items()},
+                      "one_at_a_time_ms": round(seq_ms, 3),
+                      "one_at_a_time_wall_s": round(seq_wall, 3),
+                      "grouped_speedup_f32": round(seq_ms / g32["ms"], 3),
+                      "bf16_value": work / (res["bf16"]["ms"] * 1e-3),
+                      "group_create_s": {k: round(v["create_s"], 3) for k, v in res.items()},
+                      "launches_per_iter": g32["info"]["launches_per_iter"],
+                      "tuned_mttkrp_grid": g32["info"]["mttkrp_grid"],
+                      "group_bytes": g32["info"]["bytes"],
+                      "mean_fit": {k: v["mean_fit"] for k, v in res.items()}}}
+    print(json.dumps(line), flush=True)
+    for m in members:
+        m[0].close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="zipf50m", choices=["zipf50m", "small"])
+    ap.add_argument("--workload", default="zipf50m", choices=["zipf50m", "small", "batched"])
+    ap.add_argument("--batch", type=int, default=256, help="batched workload: number of tensors")
+    ap.add_argument("--iters", type=int, default=20, help="batched workload: ALS iterations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-factor side run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -107,6 +207,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dfacto.load()  # fail loudly if the HIP library is missing
+    if args.workload == "batched":
+        return run_batched(args)
 
     t0 = time.perf_counter()
     if args.workload == "zipf50m":

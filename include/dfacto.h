@@ -181,6 +181,59 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R,
                              float *const d_G[3], double *d_f);
 
 /* ------------------------------------------------------------------ */
+/* grouped CP-ALS (many independent solves at once)                     */
+/* ------------------------------------------------------------------ */
+
+/* A group runs CP-ALS iterations (the same iteration as dfacto_als_iter) for
+ * n independent tensors together: every step of an iteration is one kernel
+ * launch per kernel class for all members (the MTTKRP as a persistent grid
+ * over a work list of (member, chunk group) items), so small tensors do not
+ * pay one launch each.  Per member the results are bitwise those of
+ * dfacto_als_iter on the same inputs.
+ *
+ * Members: tensors[t] (built on ctx's device; they must outlive the group),
+ * ranks[t] in {4, 8, 12, 16, 32, 48, 64}, one storage dtype for all, factors
+ * d_F[3 t + m] (row-major dims[m] x ranks[t], device, 16-byte aligned,
+ * updated in place), d_lambda[t] (ranks[t] doubles, device) and d_fit[t]
+ * (device double).  All pointers are caller-owned and must stay valid while
+ * the group lives.  The group allocates its own workspace (reported by
+ * dfacto_group_get_info) and uses its own HIP stream, ordered after ctx's
+ * stream by events at each call.
+ *
+ * flags: DFACTO_GROUP_GRAPH captures one iteration as a HIP graph on the
+ * first dfacto_group_als call and replays it; DFACTO_GROUP_TUNE times the
+ * MTTKRP launches with several persistent grid sizes at creation and keeps
+ * the fastest (results do not depend on the choice).  Creation synchronizes;
+ * E_UNSUPPORTED for a rank outside the list above. */
+#define DFACTO_GROUP_GRAPH 1
+#define DFACTO_GROUP_TUNE 2
+
+typedef struct dfacto_group dfacto_group;
+
+typedef struct {
+    int members;
+    int launches_per_iter;  /* kernel launches in one iteration */
+    size_t bytes;           /* device workspace and tables owned by the group */
+    int graph;              /* 1 when iterations replay a captured graph */
+    int mttkrp_classes;     /* MTTKRP launches per iteration */
+    int mttkrp_grid[16];    /* their persistent grid sizes (first 16) */
+} dfacto_group_info;
+
+dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *const *tensors,
+                                  const int *ranks, dfacto_dtype dtype, double reg,
+                                  void *const *d_F, double *const *d_lambda, double *d_fit,
+                                  int flags, dfacto_group **out);
+
+/* Enqueue `iters` CP-ALS iterations of every member (no host
+ * synchronization; the fits are written to d_fit each iteration). */
+dfacto_status dfacto_group_als(dfacto_ctx *ctx, dfacto_group *g, int iters);
+
+dfacto_status dfacto_group_get_info(const dfacto_group *g, dfacto_group_info *info);
+
+/* Free the group (waits for its stream).  NULL is ignored. */
+void dfacto_group_destroy(dfacto_group *g);
+
+/* ------------------------------------------------------------------ */
 /* measurement                                                          */
 /* ------------------------------------------------------------------ */
 

@@ -432,7 +432,7 @@ void radix_sort(uint64_t *&keys, uint32_t *&vals, uint64_t *&kalt, uint32_t *&va
         std::swap(keys, kalt);
         std::swap(vals, valt);
     }
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
     sc.release(hist);
     sc.release(offs);
 }
@@ -452,7 +452,7 @@ void build_runs(dfacto_tensor *t, ModeData &md, hipStream_t s, Scratch &sc) {
     uint2 *dh = sc.alloc<uint2>(md.nchunk);
     hipLaunchKernelGGL(k_chunk_heads, dim3(grid_for(md.nchunk)), dim3(kThreads), 0, s, md.stream,
                        md.chunk_start, md.nchunk, dh);
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
     std::vector<uint2> heads((size_t)md.nchunk);
     DF_HIP(hipMemcpyAsync(heads.data(), dh, sizeof(uint2) * md.nchunk, hipMemcpyDeviceToHost, s));
     DF_HIP(hipStreamSynchronize(s));
@@ -516,7 +516,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
         scan_exclusive_u32(mark, pos, nrows, s);
         hipLaunchKernelGGL(k_compact_rows, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, pos,
                            nrows, md.empty_rows);
-        DF_HIP(hipGetLastError());
+        DF_LAUNCHED();
         DF_HIP(hipStreamSynchronize(s));
         return;
     }
@@ -563,7 +563,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     md.chunk_start = tensor_alloc<uint32_t>(t, md.nchunk + 1);
     hipLaunchKernelGGL(k_chunk_starts, dim3(grid_for(md.nchunk + 1)), dim3(kThreads), 0, s,
                        md.stream, L, md.nchunk, chunk_len, md.chunk_start);
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
     build_runs(t, md, s, sc);
     DF_HIP(hipStreamSynchronize(s));
 }
@@ -606,7 +606,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
         hipLaunchKernelGGL(k_validate, dim3(grid_for(n)), dim3(kThreads), 0, s, d_i, d_j, d_k,
                            d_val, n, (uint32_t)t->dims[0], (uint32_t)t->dims[1],
                            (uint32_t)t->dims[2], flag);
-        DF_HIP(hipGetLastError());
+        DF_LAUNCHED();
         const uint32_t bad = read_back(flag, s);
         if (bad & 1u) throw Error{DFACTO_E_RANGE, "a coordinate is not below its dimension"};
         if (bad & 2u) throw Error{DFACTO_E_NUMERIC, "a tensor value is NaN or Inf"};
@@ -650,7 +650,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
     float *dv = sc.alloc<float>(nd);
     hipLaunchKernelGGL(k_merge_runs, dim3(grid_for(n)), dim3(kThreads), 0, s, dflag, dpos, n, si,
                        sj, sk, sv, di, dj, dk, dv);
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
     sc.release(si);
     sc.release(sj);
     sc.release(sk);
@@ -682,7 +682,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
         radix_sort(key2, p2, kalt2, palt2, nd, bits[md.root] + bits[md.mid], sc, s);
         hipLaunchKernelGGL(k_gather4, dim3(grid_for(nd)), dim3(kThreads), 0, s, p2, nd,
                            coord[md.root], coord[md.mid], coord[md.leaf], dv, gr, gm, gl, gv);
-        DF_HIP(hipGetLastError());
+        DF_LAUNCHED();
         build_mode(ctx, t, m, gr, gm, gl, gv, nd);
     }
 }

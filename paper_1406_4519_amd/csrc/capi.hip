@@ -55,48 +55,9 @@ void prof_mark(dfacto_ctx *ctx) {
 
 namespace {
 
-// Make the context's device current for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) DF_HIP(hipSetDevice(dev));
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-template <typename F>
-dfacto_status guarded(dfacto_ctx *ctx, F &&body) {
-    if (!ctx) return DFACTO_E_INVALID;
-    if (ctx->sticky) return DFACTO_E_DEVICE;
-    try {
-        DeviceGuard g(ctx->device);
-        body();
-        ctx->err.clear();
-        return DFACTO_OK;
-    } catch (const Error &e) {
-        return fail(ctx, e.code, e.msg);
-    } catch (const std::bad_alloc &) {
-        return fail(ctx, DFACTO_E_NOMEM, "host allocation failed");
-    } catch (...) {
-        return fail(ctx, DFACTO_E_DEVICE, "unexpected exception");
-    }
-}
-
-void check_common(const dfacto_tensor *t, int R, dfacto_dtype dtype) {
-    if (!t) throw Error{DFACTO_E_INVALID, "tensor is NULL"};
-    if (R < 1 || R > DFACTO_MAX_R) throw Error{DFACTO_E_INVALID, "R must be in [1, 256]"};
-    if (dtype != DFACTO_F32 && dtype != DFACTO_BF16) throw Error{DFACTO_E_INVALID, "bad dtype"};
-}
-
 void check_factor(const void *p, const char *name) {
     if (!p) throw Error{DFACTO_E_INVALID, std::string(name) + " is NULL"};
 }
-
-size_t elem_size(dfacto_dtype d) { return d == DFACTO_BF16 ? 2 : 4; }
 
 void check_align(const void *p, dfacto_dtype d, const char *name) {
     if ((uintptr_t)p % elem_size(d) != 0)
@@ -115,7 +76,7 @@ struct Small {
 
 Small small_ws(dfacto_ctx *ctx, int R) {
     const size_t RR = (size_t)R * R;
-    const size_t n = 3 * RR + 3 * RR + 3 * RR + (2 * RR + R) + 3 * RR + 2 * 8192 + 64;
+    const size_t n = 3 * RR + 3 * RR + 3 * RR + (4 * RR + R) + 3 * RR + 2 * 8192 + 64;
     double *b = (double *)ws_get(ctx, dfacto_ctx::kSmall, sizeof(double) * n);
     Small s;
     size_t o = 0;
@@ -124,7 +85,7 @@ Small small_ws(dfacto_ctx *ctx, int R) {
     s.W = b + o, o += RR;
     s.MtM = b + o, o += RR;
     s.solve_scratch = b + o, o += 3 * RR;
-    s.lam_scratch = b + o, o += 2 * RR + R;
+    s.lam_scratch = b + o, o += 4 * RR + R;
     for (int m = 0; m < 3; ++m) s.H[m] = b + o, o += RR;
     s.part0 = b + o, o += 8192;
     s.part_dummy = b + o, o += 8192;

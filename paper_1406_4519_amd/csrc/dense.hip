@@ -188,9 +188,11 @@ __device__ __forceinline__ void gram_load(const T *__restrict__ F, int64_t row, 
     for (int t = 0; t < NT; ++t) v[t] = (row < rows && c0 + t < R) ? ld<T>(F, row * R + c0 + t) : 0.0;
 }
 
+// Block b of nb: the launch's own block, or a grouped launch's virtual one.
 template <typename T, int NT, int BS, bool VEC>
-__global__ __launch_bounds__(BS) void k_gram_mfma(const T *__restrict__ F, int64_t rows, int R,
-                                                  double *__restrict__ part) {
+__device__ __forceinline__ void gram_mfma_body(const T *__restrict__ F, int64_t rows, int R,
+                                               double *__restrict__ part, uint32_t b,
+                                               uint32_t nb) {
     constexpr int NP = NT * (NT + 1) / 2;  // tile pairs rt <= ct
     constexpr int NW = BS / 64;            // waves per block
     __shared__ double sacc[NP * 256];
@@ -199,8 +201,8 @@ __global__ __launch_bounds__(BS) void k_gram_mfma(const T *__restrict__ F, int64
     double4v acc[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) acc[q] = double4v{0.0, 0.0, 0.0, 0.0};
-    const int64_t nwaves = (int64_t)gridDim.x * NW;
-    const int64_t gw = (int64_t)blockIdx.x * NW + wave;
+    const int64_t nwaves = (int64_t)nb * NW;
+    const int64_t gw = (int64_t)b * NW + wave;
     // rows [16 * step, 16 * step + 16) for step = gw, gw + nwaves, ...; rows
     // past the end read as zero.  The next step is loaded before the current
     // one's MFMAs.
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(BS) void k_gram_mfma(const T *__restrict__ F, int64
         }
         __syncthreads();
     }
-    double *pb = part + (size_t)blockIdx.x * R * R;
+    double *pb = part + (size_t)b * R * R;
     for (int e = threadIdx.x; e < NP * 256; e += BS) {
         int q = e / 256, rt = 0;
         while (q >= NT - rt) { q -= NT - rt; ++rt; }  // pair index -> (rt, ct)
@@ -258,12 +260,26 @@ __global__ __launch_bounds__(BS) void k_gram_mfma(const T *__restrict__ F, int64
     }
 }
 
+template <typename T, int NT, int BS, bool VEC>
+__global__ __launch_bounds__(BS) void k_gram_mfma(const T *__restrict__ F, int64_t rows, int R,
+                                                  double *__restrict__ part) {
+    gram_mfma_body<T, NT, BS, VEC>(F, rows, R, part, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int NT, int BS, bool VEC>
+__global__ __launch_bounds__(BS) void k_gram_mfma_group(const GramJob *__restrict__ jobs,
+                                                        const uint2 *__restrict__ vb) {
+    const uint2 v = vb[blockIdx.x];
+    const GramJob &j = jobs[v.x];
+    gram_mfma_body<T, NT, BS, VEC>((const T *)j.F, j.rows, j.R, j.part, v.y, j.nblk);
+}
+
 // G[e] = sum_b part[b][e]: a block takes 16 entries; slice q (16 per entry)
 // sums the partials b = q, q + 16, ...; the slices are combined in order.
-__global__ __launch_bounds__(kBlock) void k_gram_reduce(const double *__restrict__ part, int nblk,
-                                                        int R, double *__restrict__ G) {
+__device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part, int nblk, int R,
+                                                 double *__restrict__ G, uint32_t b) {
     __shared__ double sh[16][17];
-    const int e = blockIdx.x * 16 + threadIdx.x % 16;
+    const int e = b * 16 + threadIdx.x % 16;
     const int sl = threadIdx.x / 16;
     const int RR = R * R;
     double s = 0.0;
@@ -277,6 +293,18 @@ __global__ __launch_bounds__(kBlock) void k_gram_reduce(const double *__restrict
         for (int q = 1; q < 16; ++q) t += sh[q][threadIdx.x];
         G[e] = t;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gram_reduce(const double *__restrict__ part, int nblk,
+                                                        int R, double *__restrict__ G) {
+    gram_reduce_body(part, nblk, R, G, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gram_reduce_group(const GramJob *__restrict__ jobs,
+                                                              const uint2 *__restrict__ vb) {
+    const uint2 v = vb[blockIdx.x];
+    const GramJob &j = jobs[v.x];
+    gram_reduce_body(j.part, (int)j.nblk, j.R, j.G, v.y);
 }
 
 __global__ void k_hadamard(int R, const double *__restrict__ Gp, const double *__restrict__ Gq,
@@ -378,11 +406,9 @@ __device__ bool gauss_jordan_wave(const double *H, int R, double tol, double *Bw
 }
 
 template <bool SMEM>
-__global__ __launch_bounds__(kBlock) void k_solve(int R, const double *__restrict__ Gp,
-                                                  const double *__restrict__ Gq, double reg,
-                                                  double *__restrict__ Hinv,
-                                                  double *__restrict__ scratch, int *flag) {
-    extern __shared__ double dyn[];
+__device__ void solve_body(int R, const double *__restrict__ Gp, const double *__restrict__ Gq,
+                           double reg, double *__restrict__ Hinv, double *__restrict__ scratch,
+                           int *flag, double *dyn) {
     __shared__ double sh[kBlock];
     __shared__ int s_fail;
     __shared__ double s_c[kBlock], s_s[kBlock];
@@ -540,18 +566,34 @@ __global__ __launch_bounds__(kBlock) void k_solve(int R, const double *__restric
     if (tid == 0) flag[0] = 1;
 }
 
+template <bool SMEM>
+__global__ __launch_bounds__(kBlock) void k_solve(int R, const double *__restrict__ Gp,
+                                                  const double *__restrict__ Gq, double reg,
+                                                  double *__restrict__ Hinv,
+                                                  double *__restrict__ scratch, int *flag) {
+    extern __shared__ double dyn[];
+    solve_body<SMEM>(R, Gp, Gq, reg, Hinv, scratch, flag, dyn);
+}
+
+template <bool SMEM>
+__global__ __launch_bounds__(kBlock) void k_solve_group(const SolveJob *__restrict__ jobs) {
+    extern __shared__ double dyn[];
+    const SolveJob &j = jobs[blockIdx.x];
+    solve_body<SMEM>(j.R, j.Gp, j.Gq, j.reg, j.Hinv, j.scratch, j.flag, dyn);
+}
+
 // ---------------------------------------------------------------------------
 // lambda, new Gram, W and (last mode) fit -- one workgroup.  Working set:
 // Hinv, MtM, T1 = MtM Hinv, S = Hinv T1 (4 R^2) and lambda (R), in dynamic
 // LDS when SMEM, else in `scratch`.
 // ---------------------------------------------------------------------------
 template <bool SMEM>
-__global__ __launch_bounds__(kBlock) void k_als_lambda(
-    int R, int mode, const double *__restrict__ Hinv_g, const double *__restrict__ MtM_g,
-    double *__restrict__ Gn, double *__restrict__ W, double *__restrict__ lambda_out,
-    const double *__restrict__ GA, const double *__restrict__ GB, double normsq,
-    double *__restrict__ fit_out, double *__restrict__ scratch) {
-    extern __shared__ double dyn[];
+__device__ void als_lambda_body(int R, int mode, const double *__restrict__ Hinv_g,
+                                const double *__restrict__ MtM_g, double *__restrict__ Gn,
+                                double *__restrict__ W, double *__restrict__ lambda_out,
+                                const double *__restrict__ GA, const double *__restrict__ GB,
+                                double normsq, double *__restrict__ fit_out,
+                                double *__restrict__ scratch, double *dyn) {
     __shared__ double sh[kBlock];
     const int tid = threadIdx.x;
     const int RR = R * R;
@@ -605,6 +647,25 @@ __global__ __launch_bounds__(kBlock) void k_als_lambda(
     }
 }
 
+template <bool SMEM>
+__global__ __launch_bounds__(kBlock) void k_als_lambda(
+    int R, int mode, const double *__restrict__ Hinv_g, const double *__restrict__ MtM_g,
+    double *__restrict__ Gn, double *__restrict__ W, double *__restrict__ lambda_out,
+    const double *__restrict__ GA, const double *__restrict__ GB, double normsq,
+    double *__restrict__ fit_out, double *__restrict__ scratch) {
+    extern __shared__ double dyn[];
+    als_lambda_body<SMEM>(R, mode, Hinv_g, MtM_g, Gn, W, lambda_out, GA, GB, normsq, fit_out,
+                          scratch, dyn);
+}
+
+template <bool SMEM>
+__global__ __launch_bounds__(kBlock) void k_als_lambda_group(const LambdaJob *__restrict__ jobs) {
+    extern __shared__ double dyn[];
+    const LambdaJob &j = jobs[blockIdx.x];
+    als_lambda_body<SMEM>(j.R, j.mode, j.Hinv, j.MtM, j.Gn, j.W, j.lambda, j.GA, j.GB, j.normsq,
+                          j.fit, j.scratch, dyn);
+}
+
 // ---------------------------------------------------------------------------
 // Row maps over tiles of TR = kTileElems / R consecutive rows (one contiguous
 // block of memory): the tile is loaded with coalesced loads into LDS (row
@@ -629,10 +690,9 @@ __device__ __forceinline__ float ldf<uint16_t>(const uint16_t *p, int64_t i) {
 
 // F[row, s] = sum_k M[row, k] W[k, s]   (R is a compile-time constant)
 template <typename Tout, int R>
-__global__ __launch_bounds__(kBlock) void k_rowmap_t(const float *__restrict__ M, int64_t rows,
-                                                     const double *__restrict__ W,
-                                                     Tout *__restrict__ F) {
-    extern __shared__ double dyn[];
+__device__ __forceinline__ void rowmap_t_body(const float *__restrict__ M, int64_t rows,
+                                              const double *__restrict__ W, Tout *__restrict__ F,
+                                              double *dyn, uint32_t b, uint32_t nb) {
     double *sW = dyn;                                  // R * R
     float *sM = reinterpret_cast<float *>(sW + R * R);  // TR * (R + 1)
     constexpr int TR = tile_rows(R), RS = R + 1;
@@ -643,7 +703,7 @@ __global__ __launch_bounds__(kBlock) void k_rowmap_t(const float *__restrict__ M
     const int c0 = part * kCT;
     const bool active = part < tpr && c0 < R;
     const int64_t ntile = (rows + TR - 1) / TR;
-    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    for (int64_t tile = b; tile < ntile; tile += nb) {
         const int64_t r0 = tile * TR;
         const int nr = (int)((rows - r0) < TR ? (rows - r0) : TR);
         __syncthreads();
@@ -670,6 +730,23 @@ __global__ __launch_bounds__(kBlock) void k_rowmap_t(const float *__restrict__ M
         for (int e = threadIdx.x; e < nr * R; e += kBlock)
             st_out<Tout>(F, r0 * R + e, (double)sO[(e / R) * RS + e % R]);
     }
+}
+
+template <typename Tout, int R>
+__global__ __launch_bounds__(kBlock) void k_rowmap_t(const float *__restrict__ M, int64_t rows,
+                                                     const double *__restrict__ W,
+                                                     Tout *__restrict__ F) {
+    extern __shared__ double dyn[];
+    rowmap_t_body<Tout, R>(M, rows, W, F, dyn, blockIdx.x, gridDim.x);
+}
+
+template <typename Tout, int R>
+__global__ __launch_bounds__(kBlock) void k_rowmap_t_group(const RowmapJob *__restrict__ jobs,
+                                                           const uint2 *__restrict__ vb) {
+    extern __shared__ double dyn[];
+    const uint2 v = vb[blockIdx.x];
+    const RowmapJob &j = jobs[v.x];
+    rowmap_t_body<Tout, R>(j.M, j.rows, j.W, (Tout *)j.F, dyn, v.y, j.nblk);
 }
 
 // G[row, s] = -G[row, s] + sum_k F[row, k] H[k, s]  (G holds the MTTKRP);
@@ -925,16 +1002,16 @@ __device__ __forceinline__ void load_rowrun(const T *__restrict__ X, int64_t row
 
 // F[row, s] = sum_k M[row, k] W[k, s]
 template <typename Tout, int NCT>
-__global__ __launch_bounds__(kBlock) void k_rowmap_mfma(const float *__restrict__ M, int64_t rows,
-                                                        const double *__restrict__ W,
-                                                        Tout *__restrict__ F) {
+__device__ __forceinline__ void rowmap_mfma_body(const float *__restrict__ M, int64_t rows,
+                                                 const double *__restrict__ W,
+                                                 Tout *__restrict__ F, uint32_t b, uint32_t nb) {
     constexpr int R = 16 * NCT, S = 4 * NCT;
     const int lane = threadIdx.x % 64, g = lane / 16;
     double wa[NCT][S];
     load_rmat<NCT>(W, lane, wa);
     const int64_t ntile = (rows + 15) / 16;
-    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-    int64_t tile = (int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    const int64_t nw = (int64_t)nb * (kBlock / 64);
+    int64_t tile = (int64_t)b * (kBlock / 64) + threadIdx.x / 64;
     Run4<float> x[NCT];
     load_rowrun<NCT>(M, tile * 16 + lane % 16, rows, g, x);
     for (; tile < ntile; tile += nw) {
@@ -952,6 +1029,21 @@ __global__ __launch_bounds__(kBlock) void k_rowmap_mfma(const float *__restrict_
 #pragma unroll
         for (int c = 0; c < NCT; ++c) x[c] = xn[c];
     }
+}
+
+template <typename Tout, int NCT>
+__global__ __launch_bounds__(kBlock) void k_rowmap_mfma(const float *__restrict__ M, int64_t rows,
+                                                        const double *__restrict__ W,
+                                                        Tout *__restrict__ F) {
+    rowmap_mfma_body<Tout, NCT>(M, rows, W, F, blockIdx.x, gridDim.x);
+}
+
+template <typename Tout, int NCT>
+__global__ __launch_bounds__(kBlock) void k_rowmap_mfma_group(const RowmapJob *__restrict__ jobs,
+                                                              const uint2 *__restrict__ vb) {
+    const uint2 v = vb[blockIdx.x];
+    const RowmapJob &j = jobs[v.x];
+    rowmap_mfma_body<Tout, NCT>(j.M, j.rows, j.W, (Tout *)j.F, v.y, j.nblk);
 }
 
 // G[row, s] = -G[row, s] + sum_k F[row, k] H[k, s]  (G holds the MTTKRP on
@@ -1056,18 +1148,26 @@ int gram_partial_blocks(int64_t rows, int R) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, 256));
 }
 
+GramPlan gram_plan(int64_t rows, int R, const void *F, dfacto_dtype dtype) {
+    GramPlan g;
+    g.nt = (R + 15) / 16;
+    const int bs = g.nt <= 2 ? 1024 : 256;  // 16 waves per block when the registers allow
+    const int64_t want = (rows + 16 * 2 * (bs / 64) - 1) / (16 * 2 * (bs / 64));
+    g.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256));
+    const size_t es = dtype == DFACTO_F32 ? 4 : 2;
+    g.vec = R == 32 && (uintptr_t)F % (2 * es) == 0;
+    return g;
+}
+
 void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t rows, int R,
                  double *G) {
     hipStream_t s = ctx->stream;
     if (R <= 16 * kMfmaMaxTiles) {
-        const int nt = (R + 15) / 16;
-        const int bs = nt <= 2 ? 1024 : 256;  // 16 waves per block when the registers allow
-        const int64_t want = (rows + 16 * 2 * (bs / 64) - 1) / (16 * 2 * (bs / 64));
-        const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256));
+        const GramPlan gp = gram_plan(rows, R, F, dtype);
+        const int nt = gp.nt, nblk = gp.nblk;
+        const bool vec2 = gp.vec;
         double *part =
             (double *)ws_get(ctx, dfacto_ctx::kPartial, sizeof(double) * 256 * (size_t)R * R);
-        const size_t es = dtype == DFACTO_F32 ? 4 : 2;
-        const bool vec2 = R == 32 && (uintptr_t)F % (2 * es) == 0;
 #define GM(T, NTV, V)                                                                              \
     hipLaunchKernelGGL((k_gram_mfma<T, NTV, (NTV <= 2 ? 1024 : 256), V>), dim3(nblk),              \
                        dim3(NTV <= 2 ? 1024 : 256), 0, s, (const T *)F, rows, R, part)
@@ -1087,7 +1187,7 @@ void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t row
 #undef GM
         hipLaunchKernelGGL(k_gram_reduce, dim3((R * R + 15) / 16), dim3(kBlock), 0, s, part, nblk, R,
                            G);
-        DF_HIP(hipGetLastError());
+        DF_LAUNCHED();
         return;
     }
     const int TS = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
@@ -1111,14 +1211,14 @@ void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t row
     }
 #undef GRAM_LAUNCH
     hipLaunchKernelGGL(k_gram_reduce, dim3((R * R + 15) / 16), dim3(kBlock), 0, s, part, nblk, R, G);
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
 }
 
 void launch_hadamard(dfacto_ctx *ctx, int R, const double *Gp, const double *Gq, double reg,
                      double *H) {
     hipLaunchKernelGGL(k_hadamard, dim3((R * R + kBlock - 1) / kBlock), dim3(kBlock), 0, ctx->stream,
                        R, Gp, Gq, reg, H);
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
 }
 
 void launch_solve(dfacto_ctx *ctx, int R, const double *Gp, const double *Gq, double reg,
@@ -1129,7 +1229,7 @@ void launch_solve(dfacto_ctx *ctx, int R, const double *Gp, const double *Gq, do
     else
         hipLaunchKernelGGL(k_solve<false>, dim3(1), dim3(kBlock), 0, ctx->stream, R, Gp, Gq, reg,
                            Hinv, scratch, flag);
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
 }
 
 void launch_als_lambda(dfacto_ctx *ctx, int R, int mode, const double *Hinv, const double *MtM,
@@ -1142,7 +1242,7 @@ void launch_als_lambda(dfacto_ctx *ctx, int R, int mode, const double *Hinv, con
     else
         hipLaunchKernelGGL(k_als_lambda<false>, dim3(1), dim3(kBlock), 0, ctx->stream, R, mode,
                            Hinv, MtM, Gn, W, lambda_out, GA, GB, normsq, fit_out, scratch);
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
 }
 
 static unsigned rows_grid_generic(int64_t rows, int R, int per_pass_elems) {
@@ -1204,7 +1304,7 @@ void launch_rowmap(dfacto_ctx *ctx, const float *M, int64_t rows, int R, const d
     if (mfma_rows_ok(R, M, 4, F, ef)) {
         if (dtype == DFACTO_F32) rowmap_mfma<float>(s, M, rows, R, W, F);
         else rowmap_mfma<uint16_t>(s, M, rows, R, W, F);
-        DF_HIP(hipGetLastError());
+        DF_LAUNCHED();
         return;
     }
     const bool done = dtype == DFACTO_F32
@@ -1219,7 +1319,7 @@ void launch_rowmap(dfacto_ctx *ctx, const float *M, int64_t rows, int R, const d
             hipLaunchKernelGGL(k_rowmap_g<uint16_t>, dim3(g), dim3(kBlock), 0, s, M, rows, R, W,
                                (uint16_t *)F);
     }
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
 }
 
 int gd_rows_partials(int64_t rows, int R, const float *G, const void *F, dfacto_dtype dtype) {
@@ -1235,7 +1335,7 @@ void launch_gd_rows(dfacto_ctx *ctx, float *G, const void *F, dfacto_dtype dtype
     if (mfma_rows_ok(R, G, 4, F, dtype == DFACTO_F32 ? 4 : 2)) {
         if (dtype == DFACTO_F32) gd_rows_mfma<float>(s, G, F, rows, R, H, inner_partial);
         else gd_rows_mfma<uint16_t>(s, G, F, rows, R, H, inner_partial);
-        DF_HIP(hipGetLastError());
+        DF_LAUNCHED();
         return;
     }
     const bool done = dtype == DFACTO_F32
@@ -1250,7 +1350,7 @@ void launch_gd_rows(dfacto_ctx *ctx, float *G, const void *F, dfacto_dtype dtype
             hipLaunchKernelGGL(k_gd_rows_g<uint16_t>, dim3(g), dim3(kBlock), 0, s, G,
                                (const uint16_t *)F, rows, R, H, inner_partial);
     }
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
 }
 
 void launch_gd_f(dfacto_ctx *ctx, int R, const double *GA, const double *GB, const double *GC,
@@ -1258,7 +1358,117 @@ void launch_gd_f(dfacto_ctx *ctx, int R, const double *GA, const double *GB, con
                  double *f_out) {
     hipLaunchKernelGGL(k_gd_f, dim3(1), dim3(kBlock), 0, ctx->stream, R, GA, GB, GC, inner_partial,
                        npartial, normsq, reg, f_out);
-    DF_HIP(hipGetLastError());
+    DF_LAUNCHED();
+}
+
+// ---- grouped launches (many tensors, one launch per kernel class) ---------
+void launch_gram_group(dfacto_ctx *ctx, dfacto_dtype dtype, int nt, bool vec,
+                       const GramJob *d_jobs, const uint2 *d_vb, uint32_t nvb) {
+    if (nvb == 0) return;
+    hipStream_t s = ctx->stream;
+#define GMG(T, NTV, V)                                                                         \
+    hipLaunchKernelGGL((k_gram_mfma_group<T, NTV, (NTV <= 2 ? 1024 : 256), V>), dim3(nvb),     \
+                       dim3(NTV <= 2 ? 1024 : 256), 0, s, d_jobs, d_vb)
+    if (dtype == DFACTO_F32) {
+        if (nt == 1) GMG(float, 1, false);
+        else if (nt == 2 && vec) GMG(float, 2, true);
+        else if (nt == 2) GMG(float, 2, false);
+        else if (nt == 3) GMG(float, 3, false);
+        else GMG(float, 4, false);
+    } else {
+        if (nt == 1) GMG(uint16_t, 1, false);
+        else if (nt == 2 && vec) GMG(uint16_t, 2, true);
+        else if (nt == 2) GMG(uint16_t, 2, false);
+        else if (nt == 3) GMG(uint16_t, 3, false);
+        else GMG(uint16_t, 4, false);
+    }
+#undef GMG
+    DF_LAUNCHED();
+}
+
+uint32_t gram_reduce_blocks(int R) { return (uint32_t)((R * R + 15) / 16); }
+
+void launch_gram_reduce_group(dfacto_ctx *ctx, const GramJob *d_jobs, const uint2 *d_vb,
+                              uint32_t nvb) {
+    if (nvb == 0) return;
+    hipLaunchKernelGGL(k_gram_reduce_group, dim3(nvb), dim3(kBlock), 0, ctx->stream, d_jobs, d_vb);
+    DF_LAUNCHED();
+}
+
+void launch_solve_group(dfacto_ctx *ctx, int maxR, const SolveJob *d_jobs, uint32_t n) {
+    if (n == 0) return;
+    if (maxR <= kSolveSmemMaxR)
+        hipLaunchKernelGGL(k_solve_group<true>, dim3(n), dim3(kBlock),
+                           sizeof(double) * 3 * maxR * maxR, ctx->stream, d_jobs);
+    else
+        hipLaunchKernelGGL(k_solve_group<false>, dim3(n), dim3(kBlock), 0, ctx->stream, d_jobs);
+    DF_LAUNCHED();
+}
+
+void launch_lambda_group(dfacto_ctx *ctx, int maxR, const LambdaJob *d_jobs, uint32_t n) {
+    if (n == 0) return;
+    if (maxR <= kLambdaSmemMaxR)
+        hipLaunchKernelGGL(k_als_lambda_group<true>, dim3(n), dim3(kBlock),
+                           sizeof(double) * (4 * maxR * maxR + maxR), ctx->stream, d_jobs);
+    else
+        hipLaunchKernelGGL(k_als_lambda_group<false>, dim3(n), dim3(kBlock), 0, ctx->stream,
+                           d_jobs);
+    DF_LAUNCHED();
+}
+
+RowmapPlan rowmap_plan(int R, const float *M, const void *F, dfacto_dtype dtype, int64_t rows) {
+    RowmapPlan p;
+    if (mfma_rows_ok(R, M, 4, F, dtype == DFACTO_F32 ? 4 : 2)) {
+        p.kind = RowmapPlan::kMfma;
+        p.nblk = rows_grid_mfma(rows);
+    } else if (tiled_rows_ok(R)) {
+        p.kind = RowmapPlan::kTiled;
+        p.nblk = rows_grid_tiles(rows, R);
+    } else {
+        p.kind = RowmapPlan::kGeneric;
+        p.nblk = 0;
+    }
+    return p;
+}
+
+void launch_rowmap_group(dfacto_ctx *ctx, dfacto_dtype dtype, int kind, int R,
+                         const RowmapJob *d_jobs, const uint2 *d_vb, uint32_t nvb) {
+    if (nvb == 0) return;
+    hipStream_t s = ctx->stream;
+    const dim3 grid(nvb), block(kBlock);
+    auto mfma = [&](auto tag) {
+        using Tout = decltype(tag);
+        switch (R) {
+            case 16: hipLaunchKernelGGL((k_rowmap_mfma_group<Tout, 1>), grid, block, 0, s, d_jobs, d_vb); break;
+            case 32: hipLaunchKernelGGL((k_rowmap_mfma_group<Tout, 2>), grid, block, 0, s, d_jobs, d_vb); break;
+            case 48: hipLaunchKernelGGL((k_rowmap_mfma_group<Tout, 3>), grid, block, 0, s, d_jobs, d_vb); break;
+            case 64: hipLaunchKernelGGL((k_rowmap_mfma_group<Tout, 4>), grid, block, 0, s, d_jobs, d_vb); break;
+            default: throw Error{DFACTO_E_UNSUPPORTED, "no grouped row map for this rank"};
+        }
+    };
+    auto tiled = [&](auto tag) {
+        using Tout = decltype(tag);
+        const size_t lds = tile_lds_bytes(R);
+        switch (R) {
+            case 4: hipLaunchKernelGGL((k_rowmap_t_group<Tout, 4>), grid, block, lds, s, d_jobs, d_vb); break;
+            case 8: hipLaunchKernelGGL((k_rowmap_t_group<Tout, 8>), grid, block, lds, s, d_jobs, d_vb); break;
+            case 12: hipLaunchKernelGGL((k_rowmap_t_group<Tout, 12>), grid, block, lds, s, d_jobs, d_vb); break;
+            case 16: hipLaunchKernelGGL((k_rowmap_t_group<Tout, 16>), grid, block, lds, s, d_jobs, d_vb); break;
+            case 32: hipLaunchKernelGGL((k_rowmap_t_group<Tout, 32>), grid, block, lds, s, d_jobs, d_vb); break;
+            case 48: hipLaunchKernelGGL((k_rowmap_t_group<Tout, 48>), grid, block, lds, s, d_jobs, d_vb); break;
+            default: throw Error{DFACTO_E_UNSUPPORTED, "no grouped row map for this rank"};
+        }
+    };
+    if (kind == RowmapPlan::kMfma) {
+        if (dtype == DFACTO_F32) mfma(float{});
+        else mfma(uint16_t{});
+    } else if (kind == RowmapPlan::kTiled) {
+        if (dtype == DFACTO_F32) tiled(float{});
+        else tiled(uint16_t{});
+    } else {
+        throw Error{DFACTO_E_UNSUPPORTED, "no grouped row map for this rank"};
+    }
+    DF_LAUNCHED();
 }
 
 }  // namespace dfacto

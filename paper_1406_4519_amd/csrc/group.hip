@@ -1,0 +1,446 @@
+// group.hip -- grouped CP-ALS over many independent tensors (batched solves).
+//
+// Each step of an ALS iteration (Algorithm 2 / Algorithm 4 per member) is
+// enqueued as one launch per kernel class for all members together: the
+// MTTKRP as a persistent grid walking a work list of (tensor, chunk group)
+// items, the carry fix-ups over combined run tables, and the small dense
+// steps (Grams, solve, lambda and fit, row map) over tables of (tensor,
+// block) pairs.  Per member the arithmetic, the work split and the order of
+// every reduction are those of dfacto_als_iter, so the results are bitwise
+// the same as running the members one by one.  One iteration can be captured
+// once as a HIP graph and replayed.  A small autotuner picks the persistent
+// grid size of each MTTKRP kernel class by timing candidates on the group's
+// own data (the grid size does not change any result).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace {
+using namespace dfacto;
+
+// Ranks with a grouped row map (LDS-tiled or matrix-core kernels).
+bool group_rank_ok(int R) {
+    return R == 4 || R == 8 || R == 12 || R == 16 || R == 32 || R == 48 || R == 64;
+}
+}  // namespace
+
+struct dfacto_group {
+    int device = 0;
+    int n = 0, maxR = 0;
+    dfacto_dtype dtype = DFACTO_F32;
+    dfacto_ctx gctx;  // bound to the group's own stream; no workspace use
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    std::vector<std::function<void()>> steps;  // enqueue one iteration
+    int launches = 0;                          // kernel launches per iteration
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // persistent grid size of each MTTKRP launch (tuned or default)
+    std::vector<unsigned> grid_store;
+};
+
+namespace {
+
+template <typename T>
+T *dev_alloc(dfacto_group *g, size_t count) {
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(sizeof(T) * count, 256);
+    hip_check(hipMalloc(&p, bytes), "group hipMalloc");
+    g->allocs.push_back(p);
+    g->bytes += bytes;
+    return (T *)p;
+}
+
+// (set-up time only: a blocking copy, so the host vector may go away)
+template <typename T>
+T *upload(dfacto_group *g, const std::vector<T> &v) {
+    T *d = dev_alloc<T>(g, std::max<size_t>(v.size(), 1));
+    if (!v.empty()) DF_HIP(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return d;
+}
+
+template <typename T>
+std::vector<T> download(const T *d, size_t n, hipStream_t s) {
+    std::vector<T> h(n);
+    if (n) DF_HIP(hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+    DF_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+// Per-member device workspace.
+struct MemberWs {
+    float *M, *carry;
+    double *G[3], *Hinv, *W, *MtM, *solve_scratch, *lam_scratch, *part;
+    int *flag;
+};
+
+struct Build {
+    dfacto_group *g;
+    const std::vector<const dfacto_tensor *> &T;
+    const std::vector<int> &R;
+    double reg;
+    void *const *F;  // 3n
+    double *const *lambda;
+    double *fit;
+    std::vector<MemberWs> ws;
+    std::vector<std::function<void()>> mt_steps;  // the MTTKRP launches, for tuning
+    std::vector<size_t> mt_index;                 // their grid slots
+
+    // One Gram over all members: out[t] = F(t)^T F(t) (rows(t) x R(t)).
+    void add_gram(dfacto_dtype dt, const std::function<const void *(int)> &Fof,
+                  const std::function<int64_t(int)> &rows_of,
+                  const std::function<double *(int)> &out_of) {
+        dfacto_group *const grp = g;  // lambdas outlive this builder: capture the group itself
+        const int n = grp->n;
+        std::vector<GramJob> jobs(n);
+        std::map<std::pair<int, bool>, std::vector<uint2>> cls;  // (nt, vec) -> blocks
+        std::vector<uint2> red;
+        for (int t = 0; t < n; ++t) {
+            const GramPlan p = gram_plan(rows_of(t), R[t], Fof(t), dt);
+            jobs[t] = {Fof(t), rows_of(t), R[t], (uint32_t)p.nblk, ws[t].part, out_of(t)};
+            auto &v = cls[{p.nt, p.vec}];
+            for (int b = 0; b < p.nblk; ++b) v.push_back(make_uint2(t, b));
+            for (uint32_t e = 0; e < gram_reduce_blocks(R[t]); ++e) red.push_back(make_uint2(t, e));
+        }
+        const GramJob *dj = upload(g, jobs);
+        for (auto &kv : cls) {
+            const uint2 *dvb = upload(g, kv.second);
+            const int nt = kv.first.first;
+            const bool vec = kv.first.second;
+            const uint32_t nvb = (uint32_t)kv.second.size();
+            grp->steps.push_back(
+                [grp, dt, nt, vec, dj, dvb, nvb] { launch_gram_group(&grp->gctx, dt, nt, vec, dj, dvb, nvb); });
+            ++g->launches;
+        }
+        const uint2 *dred = upload(g, red);
+        const uint32_t nred = (uint32_t)red.size();
+        grp->steps.push_back(
+            [grp, dj, dred, nred] { launch_gram_reduce_group(&grp->gctx, dj, dred, nred); });
+        ++g->launches;
+    }
+
+    void add_mode(int m) {
+        dfacto_group *const grp = g;  // lambdas outlive this builder: capture the group itself
+        const int n = grp->n;
+        const dfacto_dtype dt = grp->dtype;
+        // solve: H = G_p * G_q + reg I, Hinv
+        {
+            std::vector<SolveJob> jobs(n);
+            const int p = (m + 1) % 3, q = (m + 2) % 3;
+            for (int t = 0; t < n; ++t)
+                jobs[t] = {R[t], reg, ws[t].G[p], ws[t].G[q], ws[t].Hinv, ws[t].solve_scratch,
+                           ws[t].flag + m};
+            const SolveJob *dj = upload(g, jobs);
+            const int maxR = g->maxR;
+            grp->steps.push_back(
+                [grp, maxR, dj, n] { launch_solve_group(&grp->gctx, maxR, dj, (uint32_t)n); });
+            ++g->launches;
+        }
+        // MTTKRP + fix-ups, one launch each per kernel class
+        {
+            std::vector<GroupMttkrp> desc(n);
+            struct Cls {
+                MttkrpShape sh;
+                bool small;
+                std::vector<uint2> items;
+                std::vector<uint4> shortr, longr;
+                std::vector<uint2> empty;
+            };
+            std::map<std::tuple<int, int, int, bool>, Cls> cls;
+            for (int t = 0; t < n; ++t) {
+                const ModeData &md = T[t]->mode[m];
+                const void *Fl = F[3 * t + md.leaf], *Fm = F[3 * t + md.mid];
+                desc[t] = {md.stream, md.chunk_start, (uint32_t)md.nchunk, R[t], Fl, Fm,
+                           ws[t].M, ws[t].carry};
+                const MttkrpShape sh = mttkrp_shape(R[t], dt, Fl, Fm, ws[t].M);
+                const bool sm = mttkrp_small(T[t], m);
+                Cls &c = cls[{sh.cpl, sh.g, sh.nch, sm}];
+                c.sh = sh;
+                c.small = sm;
+                const uint32_t per = mttkrp_group_chunks_per_item(sh);
+                for (uint32_t b = 0; b < (uint32_t)md.nchunk; b += per)
+                    c.items.push_back(make_uint2(t, b));
+                const auto rs = download(md.runs_short, 3 * (size_t)md.nruns_short, g->stream);
+                for (int64_t r = 0; r < md.nruns_short; ++r)
+                    c.shortr.push_back(make_uint4(t, rs[3 * r], rs[3 * r + 1], rs[3 * r + 2]));
+                const auto rl = download(md.runs_long, 3 * (size_t)md.nruns_long, g->stream);
+                for (int64_t r = 0; r < md.nruns_long; ++r)
+                    c.longr.push_back(make_uint4(t, rl[3 * r], rl[3 * r + 1], rl[3 * r + 2]));
+                const auto er = download(md.empty_rows, (size_t)md.nempty, g->stream);
+                for (uint32_t row : er) c.empty.push_back(make_uint2(t, row));
+            }
+            const GroupMttkrp *dd = upload(g, desc);
+            for (auto &kv : cls) {
+                Cls &c = kv.second;
+                const MttkrpShape sh = c.sh;
+                const bool sm = c.small;
+                const uint2 *items = upload(g, c.items);
+                const uint32_t nitems = (uint32_t)c.items.size();
+                g->grid_store.push_back(
+                    std::max(1u, std::min<unsigned>(nitems, (unsigned)g->gctx.num_cu * 8)));
+                const size_t gi = g->grid_store.size() - 1;
+                auto step = [grp, dt, sh, sm, dd, items, nitems, gi] {
+                    launch_mttkrp_group(&grp->gctx, dt, sh, sm, dd, items, nitems,
+                                        grp->grid_store[gi]);
+                };
+                g->steps.push_back(step);
+                mt_steps.push_back(step);
+                mt_index.push_back(gi);
+                ++g->launches;
+                const uint4 *ds = upload(g, c.shortr), *dl = upload(g, c.longr);
+                const uint2 *de = upload(g, c.empty);
+                const uint32_t ns = (uint32_t)c.shortr.size(), ne = (uint32_t)c.empty.size(),
+                               nl = (uint32_t)c.longr.size();
+                grp->steps.push_back([grp, sh, dd, ds, ns, de, ne, dl, nl] {
+                    launch_fix_group(&grp->gctx, sh, dd, ds, ns, de, ne, dl, nl);
+                });
+                g->launches += (ns + ne > 0) + (nl > 0);
+            }
+        }
+        // Gram of the MTTKRP result
+        add_gram(
+            DFACTO_F32, [&](int t) -> const void * { return ws[t].M; },
+            [&](int t) { return T[t]->dims[m]; }, [&](int t) { return ws[t].MtM; });
+        // lambda, new Gram, W, fit
+        {
+            std::vector<LambdaJob> jobs(n);
+            for (int t = 0; t < n; ++t)
+                jobs[t] = {R[t],       m,          ws[t].Hinv,     ws[t].MtM,      ws[t].G[m],
+                           ws[t].W,    lambda[t],  ws[t].G[0],     ws[t].G[1],     T[t]->normsq,
+                           fit + t,    ws[t].lam_scratch};
+            const LambdaJob *dj = upload(g, jobs);
+            const int maxR = g->maxR;
+            grp->steps.push_back(
+                [grp, maxR, dj, n] { launch_lambda_group(&grp->gctx, maxR, dj, (uint32_t)n); });
+            ++g->launches;
+        }
+        // row map F_m = M W
+        {
+            std::vector<RowmapJob> jobs(n);
+            std::map<std::pair<int, int>, std::vector<uint2>> cls;  // (kind, R) -> blocks
+            for (int t = 0; t < n; ++t) {
+                const RowmapPlan p = rowmap_plan(R[t], ws[t].M, F[3 * t + m], dt, T[t]->dims[m]);
+                if (p.kind == RowmapPlan::kGeneric)
+                    throw Error{DFACTO_E_UNSUPPORTED, "no grouped row map for this rank"};
+                jobs[t] = {ws[t].M, T[t]->dims[m], ws[t].W, F[3 * t + m], p.nblk};
+                auto &v = cls[{p.kind, R[t]}];
+                for (uint32_t b = 0; b < p.nblk; ++b) v.push_back(make_uint2(t, b));
+            }
+            const RowmapJob *dj = upload(g, jobs);
+            for (auto &kv : cls) {
+                const uint2 *dvb = upload(g, kv.second);
+                const int kind = kv.first.first, Rc = kv.first.second;
+                const uint32_t nvb = (uint32_t)kv.second.size();
+                grp->steps.push_back([grp, dt, kind, Rc, dj, dvb, nvb] {
+                    launch_rowmap_group(&grp->gctx, dt, kind, Rc, dj, dvb, nvb);
+                });
+                ++g->launches;
+            }
+        }
+        // BF16 storage: later modes use the Gram of the stored factor
+        if (dt == DFACTO_BF16 && m < 2)
+            add_gram(
+                DFACTO_BF16, [&](int t) -> const void * { return F[3 * t + m]; },
+                [&](int t) { return T[t]->dims[m]; }, [&](int t) { return ws[t].G[m]; });
+    }
+};
+
+void run_steps(dfacto_group *g) {
+    for (auto &f : g->steps) f();
+}
+
+// Time the MTTKRP steps of the group with several persistent grid sizes
+// and keep the fastest per kernel class.  Only the MTTKRP kernels run (they
+// write the group's own workspace, never the factors).
+void autotune(dfacto_group *g, const std::vector<std::function<void()>> &mt_steps,
+              const std::vector<size_t> &mt_index) {
+    hipEvent_t e0, e1;
+    DF_HIP(hipEventCreate(&e0));
+    DF_HIP(hipEventCreate(&e1));
+    const int cu = std::max(1, g->gctx.num_cu);
+    for (size_t k = 0; k < mt_steps.size(); ++k) {
+        unsigned &grid = g->grid_store[mt_index[k]];
+        const unsigned cap = grid;  // min(items, 8 per CU)
+        unsigned best = grid;
+        float best_ms = 1e30f;
+        for (unsigned per_cu : {2u, 4u, 8u, 16u, 32u}) {
+            const unsigned cand = std::max(1u, std::min<unsigned>(cap * 4, (unsigned)cu * per_cu));
+            grid = cand;
+            mt_steps[k]();  // warm
+            DF_HIP(hipEventRecord(e0, g->stream));
+            for (int r = 0; r < 3; ++r) mt_steps[k]();
+            DF_HIP(hipEventRecord(e1, g->stream));
+            DF_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            DF_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+            }
+        }
+        grid = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+}  // namespace
+
+using namespace dfacto;
+
+extern "C" {
+
+dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *const *tensors,
+                                  const int *ranks, dfacto_dtype dtype, double reg,
+                                  void *const *d_F, double *const *d_lambda, double *d_fit,
+                                  int flags, dfacto_group **out) {
+    return guarded(ctx, [&] {
+        if (!out) throw Error{DFACTO_E_INVALID, "out is NULL"};
+        *out = nullptr;
+        if (n < 1) throw Error{DFACTO_E_INVALID, "a group needs at least one member"};
+        if (!tensors || !ranks || !d_F || !d_lambda || !d_fit)
+            throw Error{DFACTO_E_INVALID, "NULL argument"};
+        if (!(reg >= 0.0)) throw Error{DFACTO_E_INVALID, "reg must be >= 0"};
+        hip_check(hipGetLastError(), "a HIP call before dfacto_group_create");
+        std::vector<const dfacto_tensor *> T(tensors, tensors + n);
+        std::vector<int> R(ranks, ranks + n);
+        for (int t = 0; t < n; ++t) {
+            check_common(T[t], R[t], dtype);
+            if (T[t]->device != ctx->device)
+                throw Error{DFACTO_E_INVALID, "group member built on another device"};
+            if (!group_rank_ok(R[t]))
+                throw Error{DFACTO_E_UNSUPPORTED,
+                            "grouped ALS supports R in {4, 8, 12, 16, 32, 48, 64}"};
+            for (int m = 0; m < 3; ++m) {
+                if (!d_F[3 * t + m]) throw Error{DFACTO_E_INVALID, "factor is NULL"};
+                if ((uintptr_t)d_F[3 * t + m] % 16)
+                    throw Error{DFACTO_E_INVALID, "grouped factors must be 16-byte aligned"};
+            }
+            if (!d_lambda[t]) throw Error{DFACTO_E_INVALID, "lambda is NULL"};
+        }
+        dfacto_group *g = new dfacto_group();
+        try {
+            g->device = ctx->device;
+            g->n = n;
+            g->dtype = dtype;
+            g->maxR = *std::max_element(R.begin(), R.end());
+            g->use_graph = (flags & DFACTO_GROUP_GRAPH) != 0;
+            DF_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+            DF_HIP(hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
+            DF_HIP(hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
+            g->gctx.device = ctx->device;
+            g->gctx.num_cu = ctx->num_cu;
+            g->gctx.stream = g->stream;
+            // inputs (tensors, factors) come from ctx's stream
+            DF_HIP(hipEventRecord(g->ev_in, ctx->stream));
+            DF_HIP(hipStreamWaitEvent(g->stream, g->ev_in, 0));
+
+            Build b{g, T, R, reg, d_F, d_lambda, d_fit, {}};
+            b.ws.resize(n);
+            for (int t = 0; t < n; ++t) {
+                const size_t RR = (size_t)R[t] * R[t];
+                int64_t dmax = 0, cmax = 1;
+                for (int m = 0; m < 3; ++m) {
+                    dmax = std::max(dmax, T[t]->dims[m]);
+                    cmax = std::max(cmax, T[t]->mode[m].nchunk);
+                }
+                MemberWs &w = b.ws[t];
+                w.M = dev_alloc<float>(g, (size_t)dmax * R[t]);
+                w.carry = dev_alloc<float>(g, (size_t)cmax * R[t]);
+                double *d = dev_alloc<double>(g, 6 * RR + 3 * RR + (4 * RR + R[t]) + 256 * RR + 8);
+                size_t o = 0;
+                for (int m = 0; m < 3; ++m) w.G[m] = d + o, o += RR;
+                w.Hinv = d + o, o += RR;
+                w.W = d + o, o += RR;
+                w.MtM = d + o, o += RR;
+                w.solve_scratch = d + o, o += 3 * RR;
+                w.lam_scratch = d + o, o += 4 * RR + R[t];
+                w.part = d + o, o += 256 * RR;
+                w.flag = (int *)(d + o);
+            }
+            // iteration: Grams of B and C, then modes 0, 1, 2
+            for (int m = 1; m < 3; ++m)
+                b.add_gram(
+                    dtype, [&](int t) -> const void * { return d_F[3 * t + m]; },
+                    [&](int t) { return T[t]->dims[m]; }, [&](int t) { return b.ws[t].G[m]; });
+            for (int m = 0; m < 3; ++m) b.add_mode(m);
+            DF_HIP(hipStreamSynchronize(g->stream));
+
+            if (flags & DFACTO_GROUP_TUNE) autotune(g, b.mt_steps, b.mt_index);
+            *out = g;
+        } catch (...) {
+            dfacto_group_destroy(g);
+            throw;
+        }
+    });
+}
+
+dfacto_status dfacto_group_als(dfacto_ctx *ctx, dfacto_group *g, int iters) {
+    return guarded(ctx, [&] {
+        if (!g) throw Error{DFACTO_E_INVALID, "group is NULL"};
+        if (g->device != ctx->device) throw Error{DFACTO_E_INVALID, "group on another device"};
+        if (iters < 0) throw Error{DFACTO_E_INVALID, "iters must be >= 0"};
+        hip_check(hipGetLastError(), "a HIP call before dfacto_group_als");
+        DF_HIP(hipEventRecord(g->ev_in, ctx->stream));
+        DF_HIP(hipStreamWaitEvent(g->stream, g->ev_in, 0));
+        if (g->use_graph && !g->exec && iters > 0) {
+            DF_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
+            try {
+                run_steps(g);
+            } catch (...) {
+                hipGraph_t tmp = nullptr;
+                (void)hipStreamEndCapture(g->stream, &tmp);
+                if (tmp) (void)hipGraphDestroy(tmp);
+                throw;
+            }
+            DF_HIP(hipStreamEndCapture(g->stream, &g->graph));
+            DF_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        }
+        for (int i = 0; i < iters; ++i) {
+            if (g->use_graph) DF_HIP(hipGraphLaunch(g->exec, g->stream));
+            else run_steps(g);
+        }
+        DF_HIP(hipEventRecord(g->ev_out, g->stream));
+        DF_HIP(hipStreamWaitEvent(ctx->stream, g->ev_out, 0));
+    });
+}
+
+dfacto_status dfacto_group_get_info(const dfacto_group *g, dfacto_group_info *info) {
+    if (!g || !info) return DFACTO_E_INVALID;
+    info->members = g->n;
+    info->launches_per_iter = g->launches;
+    info->bytes = g->bytes;
+    info->graph = g->use_graph ? 1 : 0;
+    info->mttkrp_classes = (int)g->grid_store.size();
+    for (int k = 0; k < 16; ++k)
+        info->mttkrp_grid[k] = k < (int)g->grid_store.size() ? (int)g->grid_store[k] : 0;
+    return DFACTO_OK;
+}
+
+void dfacto_group_destroy(dfacto_group *g) {
+    if (!g) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(g->device);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (void *p : g->allocs) (void)hipFree(p);
+    if (g->ev_in) (void)hipEventDestroy(g->ev_in);
+    if (g->ev_out) (void)hipEventDestroy(g->ev_out);
+    if (g->stream) (void)hipStreamDestroy(g->stream);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    delete g;
+}
+
+}  // extern "C"

@@ -51,6 +51,63 @@ struct ModeData {
 };
 constexpr int kShortRun = 16;
 
+// MTTKRP kernel shape: CPL consecutive columns per lane, lane groups of G
+// lanes, NCH column blocks per lane.
+struct MttkrpShape {
+    int cpl, g, nch;
+};
+
+// Arguments of the dense steps per tensor, for grouped launches.
+struct GramJob {
+    const void *F;
+    int64_t rows;
+    int R;
+    uint32_t nblk;  // partial blocks (gram_plan)
+    double *part;   // nblk x R x R partial sums
+    double *G;      // R x R result
+};
+struct SolveJob {
+    int R;
+    double reg;
+    const double *Gp, *Gq;
+    double *Hinv, *scratch;
+    int *flag;
+};
+struct LambdaJob {
+    int R, mode;
+    const double *Hinv, *MtM;
+    double *Gn, *W, *lambda;
+    const double *GA, *GB;
+    double normsq;
+    double *fit, *scratch;
+};
+struct RowmapJob {
+    const float *M;
+    int64_t rows;
+    const double *W;
+    void *F;
+    uint32_t nblk;
+};
+struct GramPlan {
+    int nt = 0, nblk = 0;
+    bool vec = false;
+};
+struct RowmapPlan {
+    enum { kMfma = 0, kTiled = 1, kGeneric = 2 };
+    int kind = kGeneric;
+    uint32_t nblk = 0;
+};
+
+// Per-(tensor, mode) arguments of a grouped MTTKRP and its fix-ups.
+struct GroupMttkrp {
+    const uint2 *stream;
+    const uint32_t *chunk_start;
+    uint32_t nchunk;
+    int R;
+    const void *Fleaf, *Fmid;
+    float *out, *carry;
+};
+
 }  // namespace dfacto
 
 struct dfacto_tensor {
@@ -92,6 +149,8 @@ struct Error {
 dfacto_status fail(dfacto_ctx *ctx, dfacto_status code, const std::string &msg);
 void hip_check(hipError_t e, const char *what);  // throws Error on failure
 #define DF_HIP(call) ::dfacto::hip_check((call), #call)
+// after kernel launches: a launch error names the launching function
+#define DF_LAUNCHED() ::dfacto::hip_check(hipGetLastError(), __func__)
 
 void *ws_get(dfacto_ctx *ctx, dfacto_ctx::Slot slot, size_t bytes);
 
@@ -112,6 +171,16 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
 // MTTKRP (mttkrp.hip)
 void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype,
                    const void *Fleaf, const void *Fmid, float *out);
+MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
+                         const float *out);
+bool mttkrp_small(const dfacto_tensor *t, int mode);
+unsigned mttkrp_group_chunks_per_item(const MttkrpShape &sh);
+void launch_mttkrp_group(dfacto_ctx *ctx, dfacto_dtype dtype, const MttkrpShape &sh, bool small,
+                         const GroupMttkrp *d_desc, const uint2 *d_items, uint32_t nitems,
+                         unsigned grid);
+void launch_fix_group(dfacto_ctx *ctx, const MttkrpShape &sh, const GroupMttkrp *d_desc,
+                      const uint4 *d_short, uint32_t nshort, const uint2 *d_empty,
+                      uint32_t nempty, const uint4 *d_long, uint32_t nlong);
 
 // dense FP64 pieces (dense.hip)
 void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t rows, int R,
@@ -131,5 +200,56 @@ void launch_gd_f(dfacto_ctx *ctx, int R, const double *GA, const double *GB, con
                  const double *inner_partial, int npartial, double normsq, double reg,
                  double *f_out);
 int gd_rows_partials(int64_t rows, int R, const float *G, const void *F, dfacto_dtype dtype);
+
+GramPlan gram_plan(int64_t rows, int R, const void *F, dfacto_dtype dtype);
+uint32_t gram_reduce_blocks(int R);
+void launch_gram_group(dfacto_ctx *ctx, dfacto_dtype dtype, int nt, bool vec,
+                       const GramJob *d_jobs, const uint2 *d_vb, uint32_t nvb);
+void launch_gram_reduce_group(dfacto_ctx *ctx, const GramJob *d_jobs, const uint2 *d_vb,
+                              uint32_t nvb);
+void launch_solve_group(dfacto_ctx *ctx, int maxR, const SolveJob *d_jobs, uint32_t n);
+void launch_lambda_group(dfacto_ctx *ctx, int maxR, const LambdaJob *d_jobs, uint32_t n);
+RowmapPlan rowmap_plan(int R, const float *M, const void *F, dfacto_dtype dtype, int64_t rows);
+void launch_rowmap_group(dfacto_ctx *ctx, dfacto_dtype dtype, int kind, int R,
+                         const RowmapJob *d_jobs, const uint2 *d_vb, uint32_t nvb);
+
+// Make the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) DF_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename F>
+inline dfacto_status guarded(dfacto_ctx *ctx, F &&body) {
+    if (!ctx) return DFACTO_E_INVALID;
+    if (ctx->sticky) return DFACTO_E_DEVICE;
+    try {
+        DeviceGuard g(ctx->device);
+        body();
+        ctx->err.clear();
+        return DFACTO_OK;
+    } catch (const Error &e) {
+        return fail(ctx, e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DFACTO_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DFACTO_E_DEVICE, "unexpected exception");
+    }
+}
+
+inline void check_common(const dfacto_tensor *t, int R, dfacto_dtype dtype) {
+    if (!t) throw Error{DFACTO_E_INVALID, "tensor is NULL"};
+    if (R < 1 || R > DFACTO_MAX_R) throw Error{DFACTO_E_INVALID, "R must be in [1, 256]"};
+    if (dtype != DFACTO_F32 && dtype != DFACTO_BF16) throw Error{DFACTO_E_INVALID, "bad dtype"};
+}
+
+inline size_t elem_size(dfacto_dtype d) { return d == DFACTO_BF16 ? 2 : 4; }
 
 }  // namespace dfacto

@@ -42,11 +42,13 @@ namespace {
 #ifndef DFACTO_SHARE_ENTRIES
 #define DFACTO_SHARE_ENTRIES 1
 #endif
-#ifdef DFACTO_WAVES_PER_EU
-#define MTTKRP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(DFACTO_WAVES_PER_EU)))
-#else
-#define MTTKRP_OCCUPANCY
+// At least 5 waves per SIMD: the gathers are latency-bound, and the FP32
+// CPL = 4 kernel sits right at the 96-register limit for 5 waves.  Whole-wave
+// groups (G = 64) keep the compiler's choice (they would spill).
+#ifndef DFACTO_WAVES_PER_EU
+#define DFACTO_WAVES_PER_EU 5
 #endif
+#define MTTKRP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(G <= 32 ? DFACTO_WAVES_PER_EU : 1)))
 
 constexpr int kBlock = 256;
 constexpr int kUnroll = DFACTO_UNROLL;  // stream entries in flight per group
@@ -158,13 +160,14 @@ __device__ __forceinline__ void load_f32(const float *p, float (&v)[CPL]) {
 // ---- main kernel ---------------------------------------------------------
 // SMALL: every row index is below 2^24, so row offsets are one 24-bit
 // multiply (idx * R < 2^32) instead of 64-bit arithmetic.
+// One work chunk (gid) per lane group of G lanes (lane = 0 .. G-1).
 template <typename T, int CPL, int G, int NCH, bool SMALL>
-__global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_mttkrp(
-    const uint2 *__restrict__ st, const uint32_t *__restrict__ cstart, uint32_t nchunk,
-    const T *__restrict__ Fleaf, const T *__restrict__ Fmid, int R, float *__restrict__ out,
-    float *__restrict__ carry) {
-    const uint32_t gid = (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G;
-    const int lane = threadIdx.x % G;
+__device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
+                                             const uint32_t *__restrict__ cstart, uint32_t nchunk,
+                                             const T *__restrict__ Fleaf,
+                                             const T *__restrict__ Fmid, int R,
+                                             float *__restrict__ out, float *__restrict__ carry,
+                                             uint32_t gid, int lane) {
     if (gid >= nchunk) return;
     const uint32_t cs = cstart[gid], ce = cstart[gid + 1];
     if (cs >= ce) return;
@@ -307,7 +310,64 @@ __global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_mttkrp(
     flush(row, cont);
 }
 
+template <typename T, int CPL, int G, int NCH, bool SMALL>
+__global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_mttkrp(
+    const uint2 *__restrict__ st, const uint32_t *__restrict__ cstart, uint32_t nchunk,
+    const T *__restrict__ Fleaf, const T *__restrict__ Fmid, int R, float *__restrict__ out,
+    float *__restrict__ carry) {
+    mttkrp_chunk<T, CPL, G, NCH, SMALL>(st, cstart, nchunk, Fleaf, Fmid, R, out, carry,
+                                        (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G,
+                                        threadIdx.x % G);
+}
+
+// Grouped MTTKRP over many tensors of one kernel shape: a persistent grid
+// walks the work items (tensor, first chunk of kBlock / G consecutive
+// chunks) in a fixed order, item blockIdx.x, blockIdx.x + gridDim.x, ...
+template <typename T, int CPL, int G, int NCH, bool SMALL>
+__global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_mttkrp_group(
+    const GroupMttkrp *__restrict__ desc, const uint2 *__restrict__ items, uint32_t nitems) {
+    for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint2 w = items[it];
+        const GroupMttkrp &d = desc[w.x];
+        mttkrp_chunk<T, CPL, G, NCH, SMALL>(d.stream, d.chunk_start, d.nchunk,
+                                            (const T *)d.Fleaf, (const T *)d.Fmid, d.R, d.out,
+                                            d.carry, w.y + threadIdx.x / G, threadIdx.x % G);
+    }
+}
+
 // ---- fix-up: carries of split rows, and empty rows ------------------------
+// out[row] += carry[c0] + ... + carry[c0 + n - 1], in chunk order (one lane
+// group; col/act are the lane's column blocks)
+template <int CPL, int NCH>
+__device__ __forceinline__ void add_run(const float *__restrict__ carry, int R,
+                                        float *__restrict__ out, uint32_t row, uint32_t c0,
+                                        uint32_t n, const int (&col)[NCH], const bool (&act)[NCH]) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        if (!act[c]) continue;
+        float acc[CPL];
+        load_f32<CPL>(out + (size_t)row * R + col[c], acc);
+        for (uint32_t k = 0; k < n; ++k) {
+            float v[CPL];
+            load_f32<CPL>(carry + (size_t)(c0 + k) * R + col[c], v);
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) acc[q] += v[q];
+        }
+        store_vec<CPL>(out + (size_t)row * R + col[c], acc);
+    }
+}
+
+template <int CPL, int NCH>
+__device__ __forceinline__ void zero_row(float *__restrict__ out, int R, uint32_t row,
+                                         const int (&col)[NCH], const bool (&act)[NCH]) {
+    float z[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) z[q] = 0.f;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+        if (act[c]) store_vec<CPL>(out + (size_t)row * R + col[c], z);
+}
+
 // Short runs: one lane group per run adds its <= kShortRun carries in chunk
 // order; the groups after the runs zero-fill the empty output rows.
 template <int CPL, int G, int NCH>
@@ -325,33 +385,14 @@ __global__ __launch_bounds__(kBlock) void k_fix_short(
         act[c] = col[c] < R;
     }
     if (gid < nruns) {
-        const uint32_t row = runs[3 * gid], c0 = runs[3 * gid + 1], n = runs[3 * gid + 2];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            if (!act[c]) continue;
-            float acc[CPL];
-            load_f32<CPL>(out + (size_t)row * R + col[c], acc);
-            for (uint32_t k = 0; k < n; ++k) {
-                float v[CPL];
-                load_f32<CPL>(carry + (size_t)(c0 + k) * R + col[c], v);
-#pragma unroll
-                for (int q = 0; q < CPL; ++q) acc[q] += v[q];
-            }
-            store_vec<CPL>(out + (size_t)row * R + col[c], acc);
-        }
+        add_run<CPL, NCH>(carry, R, out, runs[3 * gid], runs[3 * gid + 1], runs[3 * gid + 2], col,
+                          act);
         return;
     }
     const uint32_t eg = gid - nruns;
     if (eg >= nempty_groups) return;
-    float z[CPL];
-#pragma unroll
-    for (int q = 0; q < CPL; ++q) z[q] = 0.f;
-    for (uint32_t r = eg; r < nempty; r += nempty_groups) {
-        const uint32_t row = empty_rows[r];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c)
-            if (act[c]) store_vec<CPL>(out + (size_t)row * R + col[c], z);
-    }
+    for (uint32_t r = eg; r < nempty; r += nempty_groups)
+        zero_row<CPL, NCH>(out, R, empty_rows[r], col, act);
 }
 
 // Long runs: one workgroup per run; kBlock / G slices each sum a strided
@@ -360,15 +401,13 @@ __global__ __launch_bounds__(kBlock) void k_fix_short(
 constexpr int kLongBlock = 1024;
 
 template <int CPL, int G, int NCH>
-__global__ __launch_bounds__(kLongBlock) void k_fix_long(const uint32_t *__restrict__ runs,
-                                                         const float *__restrict__ carry, int R,
-                                                         float *__restrict__ out) {
+__device__ __forceinline__ void long_run(const float *__restrict__ carry, int R,
+                                         float *__restrict__ out, uint32_t row, uint32_t c0,
+                                         uint32_t n) {
     constexpr int S = kLongBlock / G;
     constexpr int W = CPL * NCH;  // floats per thread
     __shared__ float sh[kLongBlock * W];
     const int slice = threadIdx.x / G, lane = threadIdx.x % G;
-    const uint32_t row = runs[3 * blockIdx.x], c0 = runs[3 * blockIdx.x + 1],
-                   n = runs[3 * blockIdx.x + 2];
     float acc[NCH][CPL];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -410,25 +449,94 @@ __global__ __launch_bounds__(kLongBlock) void k_fix_long(const uint32_t *__restr
     }
 }
 
+template <int CPL, int G, int NCH>
+__global__ __launch_bounds__(kLongBlock) void k_fix_long(const uint32_t *__restrict__ runs,
+                                                         const float *__restrict__ carry, int R,
+                                                         float *__restrict__ out) {
+    long_run<CPL, G, NCH>(carry, R, out, runs[3 * blockIdx.x], runs[3 * blockIdx.x + 1],
+                          runs[3 * blockIdx.x + 2]);
+}
+
+// Grouped fix-ups: runs as (tensor, row, c0, n), empty rows as (tensor, row).
+template <int CPL, int G, int NCH>
+__global__ __launch_bounds__(kBlock) void k_fix_short_group(const GroupMttkrp *__restrict__ desc,
+                                                            const uint4 *__restrict__ runs,
+                                                            uint32_t nruns,
+                                                            const uint2 *__restrict__ empty,
+                                                            uint32_t nempty) {
+    const uint32_t gid = (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G;
+    const int lane = threadIdx.x % G;
+    uint32_t t;
+    if (gid < nruns) t = runs[gid].x;
+    else if (gid - nruns < nempty) t = empty[gid - nruns].x;
+    else return;
+    const GroupMttkrp &d = desc[t];
+    int col[NCH];
+    bool act[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        col[c] = (c * G + lane) * CPL;
+        act[c] = col[c] < d.R;
+    }
+    if (gid < nruns) {
+        const uint4 r = runs[gid];
+        add_run<CPL, NCH>(d.carry, d.R, d.out, r.y, r.z, r.w, col, act);
+    } else {
+        zero_row<CPL, NCH>(d.out, d.R, empty[gid - nruns].y, col, act);
+    }
+}
+
+template <int CPL, int G, int NCH>
+__global__ __launch_bounds__(kLongBlock) void k_fix_long_group(const GroupMttkrp *__restrict__ desc,
+                                                               const uint4 *__restrict__ runs) {
+    const uint4 r = runs[blockIdx.x];
+    const GroupMttkrp &d = desc[r.x];
+    long_run<CPL, G, NCH>(d.carry, d.R, d.out, r.y, r.z, r.w);
+}
+
 // ---- dispatch --------------------------------------------------------------
-struct Shape {
-    int cpl, g, nch;
+template <int V>
+using IntC = std::integral_constant<int, V>;
+template <typename T>
+struct TypeC {
+    using type = T;
 };
 
-Shape pick_shape(int R, bool aligned8, bool aligned4, bool aligned2) {
-    int cpl = 1;
-    if (R % 8 == 0 && aligned8 && DFACTO_MAX_CPL >= 8) cpl = 8;
-    else if (R % 4 == 0 && aligned4 && DFACTO_MAX_CPL >= 4) cpl = 4;
-    else if (R % 2 == 0 && aligned2 && DFACTO_MAX_CPL >= 2) cpl = 2;
-    const int lanes = (R + cpl - 1) / cpl;
-    if (lanes <= 64) {
-        int g = 2;
-        while (g < lanes) g <<= 1;
-        return {cpl, g, 1};
-    }
-    int nch = (lanes + 63) / 64;
-    nch = nch <= 2 ? 2 : 4;
-    return {cpl, 64, nch};
+// f(TypeC<T>, IntC<CPL>, IntC<G>, IntC<NCH>) for the kernel shape
+template <typename F>
+void with_shape(dfacto_dtype dtype, const MttkrpShape &sh, F &&f) {
+    auto by_g = [&](auto tc, auto cplc) {
+        constexpr int CPL = decltype(cplc)::value;
+        if (sh.nch == 1) {
+            switch (sh.g) {
+                case 2: return f(tc, cplc, IntC<2>{}, IntC<1>{});
+                case 4: return f(tc, cplc, IntC<4>{}, IntC<1>{});
+                case 8: return f(tc, cplc, IntC<8>{}, IntC<1>{});
+                case 16: return f(tc, cplc, IntC<16>{}, IntC<1>{});
+                case 32: return f(tc, cplc, IntC<32>{}, IntC<1>{});
+                default: return f(tc, cplc, IntC<64>{}, IntC<1>{});
+            }
+        }
+        if constexpr (CPL < 4) {
+            if (sh.nch == 2) return f(tc, cplc, IntC<64>{}, IntC<2>{});
+        }
+        if constexpr (CPL == 1) {
+            return f(tc, cplc, IntC<64>{}, IntC<4>{});
+        }
+        throw Error{DFACTO_E_UNSUPPORTED, "no MTTKRP kernel for this rank"};
+    };
+    auto by_cpl = [&](auto tc) {
+        switch (sh.cpl) {
+#if DFACTO_MAX_CPL >= 8
+            case 8: return by_g(tc, IntC<8>{});
+#endif
+            case 4: return by_g(tc, IntC<4>{});
+            case 2: return by_g(tc, IntC<2>{});
+            default: return by_g(tc, IntC<1>{});
+        }
+    };
+    if (dtype == DFACTO_F32) by_cpl(TypeC<float>{});
+    else by_cpl(TypeC<uint16_t>{});
 }
 
 template <typename T, int CPL, int G, int NCH>
@@ -465,32 +573,41 @@ void run(dfacto_ctx *ctx, const ModeData &md, int R, const void *Fleaf, const vo
         hipLaunchKernelGGL((k_fix_long<CPL, G, NCH>), dim3((unsigned)md.nruns_long),
                            dim3(kLongBlock), 0, s, md.runs_long, carry, R, out);
     }
-    DF_HIP(hipGetLastError());
-}
-
-template <typename T, int CPL>
-void run_cpl(dfacto_ctx *ctx, const ModeData &md, int R, const Shape &sh, const void *Fl,
-             const void *Fm, float *out, bool sm) {
-    if (sh.nch == 1) {
-        switch (sh.g) {
-            case 2: return run<T, CPL, 2, 1>(ctx, md, R, Fl, Fm, out, sm);
-            case 4: return run<T, CPL, 4, 1>(ctx, md, R, Fl, Fm, out, sm);
-            case 8: return run<T, CPL, 8, 1>(ctx, md, R, Fl, Fm, out, sm);
-            case 16: return run<T, CPL, 16, 1>(ctx, md, R, Fl, Fm, out, sm);
-            case 32: return run<T, CPL, 32, 1>(ctx, md, R, Fl, Fm, out, sm);
-            default: return run<T, CPL, 64, 1>(ctx, md, R, Fl, Fm, out, sm);
-        }
-    }
-    if constexpr (CPL < 4) {
-        if (sh.nch == 2) return run<T, CPL, 64, 2>(ctx, md, R, Fl, Fm, out, sm);
-    }
-    if constexpr (CPL == 1) {
-        return run<T, CPL, 64, 4>(ctx, md, R, Fl, Fm, out, sm);
-    }
-    throw Error{DFACTO_E_UNSUPPORTED, "no MTTKRP kernel for this rank"};
+    DF_LAUNCHED();
 }
 
 }  // namespace
+
+MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
+                         const float *out) {
+    const size_t es = dtype == DFACTO_BF16 ? 2 : 4;
+    auto al = [&](size_t a) {
+        return ((uintptr_t)Fleaf % a == 0) && ((uintptr_t)Fmid % a == 0) &&
+               ((uintptr_t)out % (a * 4 / es) == 0);
+    };
+    const bool aligned8 = al(8 * es), aligned4 = al(4 * es), aligned2 = al(2 * es);
+    int cpl = 1;
+    if (R % 8 == 0 && aligned8 && DFACTO_MAX_CPL >= 8) cpl = 8;
+    else if (R % 4 == 0 && aligned4 && DFACTO_MAX_CPL >= 4) cpl = 4;
+    else if (R % 2 == 0 && aligned2 && DFACTO_MAX_CPL >= 2) cpl = 2;
+    const int lanes = (R + cpl - 1) / cpl;
+    if (lanes <= 64) {
+        int g = 2;
+        while (g < lanes) g <<= 1;
+        return {cpl, g, 1};
+    }
+    int nch = (lanes + 63) / 64;
+    nch = nch <= 2 ? 2 : 4;
+    return {cpl, 64, nch};
+}
+
+bool mttkrp_small(const dfacto_tensor *t, int mode) {
+    // 24-bit row offsets when every index of the leaf, mid and output factor
+    // is below 2^24 (then idx * R < 2^32 for R <= 256)
+    const ModeData &md = t->mode[mode];
+    return t->dims[md.root] < (1 << 24) && t->dims[md.leaf] < (1 << 24) &&
+           t->dims[md.mid] < (1 << 24);
+}
 
 void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype,
                    const void *Fleaf, const void *Fmid, float *out) {
@@ -502,34 +619,55 @@ void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfa
                            sf * (double)(t->dims[md.leaf] + t->dims[md.mid]) * R;
         ctx->prof_flops += 2.0 * R * (double)(t->nnz + md.nfib);
     }
-    const size_t es = dtype == DFACTO_BF16 ? 2 : 4;
-    auto al = [&](size_t a) {
-        return ((uintptr_t)Fleaf % a == 0) && ((uintptr_t)Fmid % a == 0) &&
-               ((uintptr_t)out % (a * 4 / es) == 0);
-    };
-    const Shape sh = pick_shape(R, al(8 * es), al(4 * es), al(2 * es));
-    // 24-bit row offsets when every index of the leaf, mid and output factor
-    // is below 2^24 (then idx * R < 2^32 for R <= 256)
-    const bool sm = t->dims[md.root] < (1 << 24) && t->dims[md.leaf] < (1 << 24) &&
-                    t->dims[md.mid] < (1 << 24);
-    if (dtype == DFACTO_F32) {
-        switch (sh.cpl) {
-#if DFACTO_MAX_CPL >= 8
-            case 8: return run_cpl<float, 8>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
-#endif
-            case 4: return run_cpl<float, 4>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
-            case 2: return run_cpl<float, 2>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
-            default: return run_cpl<float, 1>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
+    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out);
+    const bool sm = mttkrp_small(t, mode);
+    with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
+        using T = typename decltype(tc)::type;
+        run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(
+            ctx, md, R, Fleaf, Fmid, out, sm);
+    });
+}
+
+unsigned mttkrp_group_chunks_per_item(const MttkrpShape &sh) { return (unsigned)(kBlock / sh.g); }
+
+void launch_mttkrp_group(dfacto_ctx *ctx, dfacto_dtype dtype, const MttkrpShape &sh, bool small,
+                         const GroupMttkrp *d_desc, const uint2 *d_items, uint32_t nitems,
+                         unsigned grid) {
+    if (nitems == 0) return;
+    hipStream_t s = ctx->stream;
+    with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
+        using T = typename decltype(tc)::type;
+        constexpr int CPL = decltype(cplc)::value, G = decltype(gc)::value,
+                      NCH = decltype(nchc)::value;
+        if (small)
+            hipLaunchKernelGGL((k_mttkrp_group<T, CPL, G, NCH, true>), dim3(grid), dim3(kBlock), 0,
+                               s, d_desc, d_items, nitems);
+        else
+            hipLaunchKernelGGL((k_mttkrp_group<T, CPL, G, NCH, false>), dim3(grid), dim3(kBlock),
+                               0, s, d_desc, d_items, nitems);
+    });
+    DF_LAUNCHED();
+}
+
+void launch_fix_group(dfacto_ctx *ctx, const MttkrpShape &sh, const GroupMttkrp *d_desc,
+                      const uint4 *d_short, uint32_t nshort, const uint2 *d_empty,
+                      uint32_t nempty, const uint4 *d_long, uint32_t nlong) {
+    hipStream_t s = ctx->stream;
+    // the fix-up kernels do not depend on the factor type
+    with_shape(DFACTO_F32, sh, [&](auto, auto cplc, auto gc, auto nchc) {
+        constexpr int CPL = decltype(cplc)::value, G = decltype(gc)::value,
+                      NCH = decltype(nchc)::value;
+        const uint64_t groups = (uint64_t)nshort + nempty;
+        if (groups > 0) {
+            const unsigned blocks = (unsigned)((groups + kBlock / G - 1) / (kBlock / G));
+            hipLaunchKernelGGL((k_fix_short_group<CPL, G, NCH>), dim3(blocks), dim3(kBlock), 0, s,
+                               d_desc, d_short, nshort, d_empty, nempty);
         }
-    }
-    switch (sh.cpl) {
-#if DFACTO_MAX_CPL >= 8
-        case 8: return run_cpl<uint16_t, 8>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
-#endif
-        case 4: return run_cpl<uint16_t, 4>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
-        case 2: return run_cpl<uint16_t, 2>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
-        default: return run_cpl<uint16_t, 1>(ctx, md, R, sh, Fleaf, Fmid, out, sm);
-    }
+        if (nlong > 0)
+            hipLaunchKernelGGL((k_fix_long_group<CPL, G, NCH>), dim3(nlong), dim3(kLongBlock), 0,
+                               s, d_desc, d_long);
+    });
+    DF_LAUNCHED();
 }
 
 }  // namespace dfacto

@@ -27,8 +27,10 @@ EXPORTS = (
     "dfacto_ctx_create", "dfacto_ctx_set_stream", "dfacto_ctx_synchronize", "dfacto_ctx_destroy",
     "dfacto_last_error", "dfacto_build_flattenings", "dfacto_tensor_get_info",
     "dfacto_tensor_export", "dfacto_tensor_destroy", "dfacto_mttkrp", "dfacto_als_iter",
-    "dfacto_gd_grad", "dfacto_profile_enable", "dfacto_profile_read",
+    "dfacto_gd_grad", "dfacto_group_create", "dfacto_group_als", "dfacto_group_get_info",
+    "dfacto_group_destroy", "dfacto_profile_enable", "dfacto_profile_read",
 )
+GROUP_GRAPH, GROUP_TUNE = 1, 2
 
 
 class DfactoError(RuntimeError):
@@ -42,6 +44,12 @@ class _Info(ctypes.Structure):
                 ("nfib", ctypes.c_int64 * 3), ("nroot", ctypes.c_int64 * 3),
                 ("nentry", ctypes.c_int64 * 3), ("nchunk", ctypes.c_int64 * 3),
                 ("normsq", ctypes.c_double), ("bytes", ctypes.c_size_t)]
+
+
+class _GroupInfo(ctypes.Structure):
+    _fields_ = [("members", ctypes.c_int), ("launches_per_iter", ctypes.c_int),
+                ("bytes", ctypes.c_size_t), ("graph", ctypes.c_int),
+                ("mttkrp_classes", ctypes.c_int), ("mttkrp_grid", ctypes.c_int * 16)]
 
 
 _lib = None
@@ -73,10 +81,17 @@ def load():
     lib.dfacto_mttkrp.argtypes = [P, P, I, I, I, PP, P]
     lib.dfacto_als_iter.argtypes = [P, P, I, I, D, PP, P, P]
     lib.dfacto_gd_grad.argtypes = [P, P, I, I, D, PP, PP, P]
+    lib.dfacto_group_create.argtypes = [P, I, PP, ctypes.POINTER(ctypes.c_int), I, D, PP, PP, P,
+                                        I, PP]
+    lib.dfacto_group_als.argtypes = [P, P, I]
+    lib.dfacto_group_get_info.argtypes = [P, ctypes.POINTER(_GroupInfo)]
+    lib.dfacto_group_destroy.argtypes = [P]
+    lib.dfacto_group_destroy.restype = None
     lib.dfacto_profile_enable.argtypes = [P, I]
     lib.dfacto_profile_read.argtypes = [P, P, P, P, P]
     for name in EXPORTS:
-        if name not in ("dfacto_ctx_destroy", "dfacto_last_error", "dfacto_tensor_destroy"):
+        if name not in ("dfacto_ctx_destroy", "dfacto_last_error", "dfacto_tensor_destroy",
+                        "dfacto_group_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -267,6 +282,83 @@ def gd_grad(ctx: Context, t: Tensor, factors, grads, f: torch.Tensor, reg: float
         raise ValueError("f must be a float64 CUDA tensor")
     ctx.check(load().dfacto_gd_grad(ctx.handle, t.handle, R, code, float(reg), _ptrs(factors),
                                     _ptrs(grads), _ptr(f)))
+
+
+class Group:
+    """Grouped CP-ALS over several built tensors (dfacto_group_*).
+
+    factors[t] = (A, B, C) device tensors of member t (one dtype for all,
+    16-byte aligned rows), lams[t] float64 (R_t,), fits float64 (n,).  The
+    tensors and buffers must stay alive while the group lives (the group
+    keeps references)."""
+
+    def __init__(self, ctx: Context, tensors, factors, lams, fits: torch.Tensor,
+                 reg: float = 0.0, graph: bool = False, tune: bool = False):
+        n = len(tensors)
+        if not (len(factors) == len(lams) == n) or n < 1:
+            raise ValueError("tensors, factors and lams must have one entry per member")
+        if fits.dtype != torch.float64 or fits.numel() < n or not fits.is_cuda:
+            raise ValueError("fits must be a float64 CUDA tensor with one entry per member")
+        ranks, code, ptrs = [], None, []
+        for t, (T, F, lam) in enumerate(zip(tensors, factors, lams)):
+            _, R, c = _check_factors(T, F)
+            if code is not None and c != code:
+                raise TypeError("every member must use one factor dtype")
+            code = c
+            if lam.dtype != torch.float64 or lam.numel() < R or not lam.is_cuda:
+                raise ValueError("lam must be a float64 CUDA tensor with R elements")
+            ranks.append(R)
+            ptrs.extend(x.data_ptr() for x in F)
+        self._keep = (list(tensors), [list(F) for F in factors], list(lams), fits)
+        th = (ctypes.c_void_p * n)(*[T.handle.value for T in tensors])
+        rk = (ctypes.c_int * n)(*ranks)
+        fp = (ctypes.c_void_p * (3 * n))(*ptrs)
+        lp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in lams])
+        flags = (GROUP_GRAPH if graph else 0) | (GROUP_TUNE if tune else 0)
+        h = ctypes.c_void_p()
+        ctx.check(load().dfacto_group_create(ctx.handle, n, th, rk, code, float(reg), fp, lp,
+                                             _ptr(fits), flags, ctypes.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+
+    def als(self, iters: int = 1):
+        self.ctx.check(load().dfacto_group_als(self.ctx.handle, self.handle, int(iters)))
+
+    def info(self) -> dict:
+        inf = _GroupInfo()
+        st = load().dfacto_group_get_info(self.handle, ctypes.byref(inf))
+        if st != OK:
+            raise DfactoError(st, "dfacto_group_get_info failed")
+        return dict(members=inf.members, launches_per_iter=inf.launches_per_iter, bytes=inf.bytes,
+                    graph=bool(inf.graph), mttkrp_classes=inf.mttkrp_classes,
+                    mttkrp_grid=list(inf.mttkrp_grid)[:min(16, inf.mttkrp_classes)])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().dfacto_group_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def group_create(ctx, tensors, factors, lams, fits, reg=0.0, graph=False, tune=False) -> Group:
+    return Group(ctx, tensors, factors, lams, fits, reg, graph, tune)
+
+
+def group_als(ctx, g: Group, iters: int = 1):
+    g.als(iters)
+
+
+def group_get_info(g: Group) -> dict:
+    return g.info()
+
+
+def group_destroy(g: Group):
+    g.close()
 
 
 def profile_enable(ctx: Context, on: bool = True):
