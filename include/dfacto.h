@@ -47,7 +47,8 @@ typedef enum {
     DFACTO_E_NOMEM = 3,       /* a device allocation failed */
     DFACTO_E_DEVICE = 4,      /* HIP runtime error (sticky on the context) */
     DFACTO_E_NUMERIC = 5,     /* NaN or Inf among the tensor values */
-    DFACTO_E_UNSUPPORTED = 6  /* sizes beyond the supported limits */
+    DFACTO_E_UNSUPPORTED = 6, /* sizes beyond the supported limits */
+    DFACTO_E_AGAIN = 7        /* a served result is not ready yet */
 } dfacto_status;
 
 typedef enum { DFACTO_F32 = 0, DFACTO_BF16 = 1 } dfacto_dtype;
@@ -232,6 +233,76 @@ dfacto_status dfacto_group_get_info(const dfacto_group *g, dfacto_group_info *in
 
 /* Free the group (waits for its stream).  NULL is ignored. */
 void dfacto_group_destroy(dfacto_group *g);
+
+/* ------------------------------------------------------------------ */
+/* served solves with continuous batching                               */
+/* ------------------------------------------------------------------ */
+
+/* A server runs CP-ALS solves submitted at any time on one device.  It owns
+ * a worker thread, a HIP stream and a device-memory budget.  At every
+ * iteration boundary the worker admits queued requests in arrival order
+ * while a slot is free and their device footprint fits the budget (the
+ * three flattenings, each at most about the size of the COO tensor, plus
+ * factors and workspace, plus the transient memory of one build), runs one
+ * grouped CP-ALS iteration of every active request, and retires the
+ * requests that met their stopping rule, which frees memory for the queue.
+ * A request's results do not depend on which others run with it: they are
+ * bitwise those of dfacto_als_iter repeated on it alone.
+ *
+ * hbm_budget: device bytes the server may hold (0 = 90% of the free memory
+ * at creation); max_slots: most requests active at once (>= 1). */
+typedef struct dfacto_server dfacto_server;
+
+typedef struct {
+    /* input, host memory, owned by the caller until the request is done */
+    int64_t dims[3];
+    int64_t nnz;
+    const uint32_t *i, *j, *k; /* coordinates (as for dfacto_build_flattenings) */
+    const float *val;
+    int R;                     /* in {4, 8, 12, 16, 32, 48, 64} */
+    dfacto_dtype dtype;        /* factor storage on the device */
+    double reg;                /* ridge parameter (>= 0) */
+    const float *init[3];      /* initial factors, dims[m] x R, FP32 */
+    double tol;                /* stop when |fit - previous fit| < tol ... */
+    int max_iters;             /* ... or after max_iters iterations (>= 1) */
+    /* output, host memory, owned by the caller (may be NULL) */
+    float *out_F[3];           /* final factors, dims[m] x R, FP32 */
+    double *out_lambda;        /* final weights, R */
+} dfacto_request;
+
+typedef struct {
+    int done;                  /* 1 once finished */
+    dfacto_status status;      /* OK, or the error that ended the request */
+    double fit;                /* fit after the last iteration */
+    int iters;                 /* iterations run */
+    double t_submit, t_admit, t_done; /* seconds on the server's clock */
+} dfacto_request_status;
+
+typedef struct {
+    int64_t pending, running, finished;
+    int peak_active;           /* most requests active at one time */
+    int64_t iterations;        /* iteration boundaries run */
+    size_t budget;
+} dfacto_server_stats;
+
+dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
+                                   dfacto_server **out);
+
+/* Queue a request (copied; its host arrays are read at admission and the
+ * outputs written at completion).  *id identifies it.  E_INVALID for bad
+ * arguments, E_UNSUPPORTED for a rank outside the list above. */
+dfacto_status dfacto_server_submit(dfacto_server *srv, const dfacto_request *req, int64_t *id);
+
+/* OK with the final status once the request is done, E_AGAIN before. */
+dfacto_status dfacto_server_poll(dfacto_server *srv, int64_t id, dfacto_request_status *st);
+
+/* Block until the request is done. */
+dfacto_status dfacto_server_wait(dfacto_server *srv, int64_t id, dfacto_request_status *st);
+
+dfacto_status dfacto_server_get_stats(dfacto_server *srv, dfacto_server_stats *out);
+
+/* Finish every submitted request, then free the server.  NULL is ignored. */
+void dfacto_server_destroy(dfacto_server *srv);
 
 /* ------------------------------------------------------------------ */
 /* measurement                                                          */

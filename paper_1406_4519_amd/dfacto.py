@@ -17,10 +17,10 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdfacto.so")
 
-OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = range(7)
+OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED, E_AGAIN = range(8)
 F32, BF16 = 0, 1
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_RANGE", 3: "E_NOMEM", 4: "E_DEVICE",
-                5: "E_NUMERIC", 6: "E_UNSUPPORTED"}
+                5: "E_NUMERIC", 6: "E_UNSUPPORTED", 7: "E_AGAIN"}
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
@@ -28,7 +28,9 @@ EXPORTS = (
     "dfacto_last_error", "dfacto_build_flattenings", "dfacto_tensor_get_info",
     "dfacto_tensor_export", "dfacto_tensor_destroy", "dfacto_mttkrp", "dfacto_als_iter",
     "dfacto_gd_grad", "dfacto_group_create", "dfacto_group_als", "dfacto_group_get_info",
-    "dfacto_group_destroy", "dfacto_profile_enable", "dfacto_profile_read",
+    "dfacto_group_destroy", "dfacto_server_create", "dfacto_server_submit", "dfacto_server_poll",
+    "dfacto_server_wait", "dfacto_server_get_stats", "dfacto_server_destroy",
+    "dfacto_profile_enable", "dfacto_profile_read",
 )
 GROUP_GRAPH, GROUP_TUNE = 1, 2
 
@@ -50,6 +52,27 @@ class _GroupInfo(ctypes.Structure):
     _fields_ = [("members", ctypes.c_int), ("launches_per_iter", ctypes.c_int),
                 ("bytes", ctypes.c_size_t), ("graph", ctypes.c_int),
                 ("mttkrp_classes", ctypes.c_int), ("mttkrp_grid", ctypes.c_int * 16)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int64 * 3), ("nnz", ctypes.c_int64),
+                ("i", ctypes.c_void_p), ("j", ctypes.c_void_p), ("k", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("R", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("reg", ctypes.c_double), ("init", ctypes.c_void_p * 3), ("tol", ctypes.c_double),
+                ("max_iters", ctypes.c_int), ("out_F", ctypes.c_void_p * 3),
+                ("out_lambda", ctypes.c_void_p)]
+
+
+class _RequestStatus(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int), ("status", ctypes.c_int), ("fit", ctypes.c_double),
+                ("iters", ctypes.c_int), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("finished", ctypes.c_int64), ("peak_active", ctypes.c_int),
+                ("iterations", ctypes.c_int64), ("budget", ctypes.c_size_t)]
 
 
 _lib = None
@@ -87,11 +110,18 @@ def load():
     lib.dfacto_group_get_info.argtypes = [P, ctypes.POINTER(_GroupInfo)]
     lib.dfacto_group_destroy.argtypes = [P]
     lib.dfacto_group_destroy.restype = None
+    lib.dfacto_server_create.argtypes = [I, ctypes.c_size_t, I, PP]
+    lib.dfacto_server_submit.argtypes = [P, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_int64)]
+    lib.dfacto_server_poll.argtypes = [P, I64, ctypes.POINTER(_RequestStatus)]
+    lib.dfacto_server_wait.argtypes = [P, I64, ctypes.POINTER(_RequestStatus)]
+    lib.dfacto_server_get_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
+    lib.dfacto_server_destroy.argtypes = [P]
+    lib.dfacto_server_destroy.restype = None
     lib.dfacto_profile_enable.argtypes = [P, I]
     lib.dfacto_profile_read.argtypes = [P, P, P, P, P]
     for name in EXPORTS:
         if name not in ("dfacto_ctx_destroy", "dfacto_last_error", "dfacto_tensor_destroy",
-                        "dfacto_group_destroy"):
+                        "dfacto_group_destroy", "dfacto_server_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -359,6 +389,101 @@ def group_get_info(g: Group) -> dict:
 
 def group_destroy(g: Group):
     g.close()
+
+
+class Server:
+    """A dfacto_server: CP-ALS solves submitted at any time, run with
+    continuous batching on one device.  Inputs are host numpy arrays (kept
+    alive here until the request is collected); results come back as host
+    numpy arrays."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, max_slots: int = 16):
+        h = ctypes.c_void_p()
+        st = load().dfacto_server_create(int(device), int(hbm_budget), int(max_slots),
+                                         ctypes.byref(h))
+        if st != OK:
+            raise DfactoError(st, "dfacto_server_create failed")
+        self.handle = h
+        self._reqs = {}
+
+    def submit(self, dims, i, j, k, val, R: int, init, dtype: str = "f32", reg: float = 0.0,
+               tol: float = 1e-4, max_iters: int = 50) -> int:
+        import numpy as np
+        arrs = [np.ascontiguousarray(x, dtype=np.uint32) for x in (i, j, k)]
+        v = np.ascontiguousarray(val, dtype=np.float32)
+        n = int(v.size)
+        if not all(a.size == n for a in arrs):
+            raise ValueError("index and value arrays differ in length")
+        ini = [np.ascontiguousarray(f, dtype=np.float32) for f in init]
+        for m in range(3):
+            if ini[m].shape != (int(dims[m]), int(R)):
+                raise ValueError(f"init[{m}] must have shape (dims[{m}], R)")
+        outF = [np.empty((int(dims[m]), int(R)), np.float32) for m in range(3)]
+        outL = np.empty(int(R), np.float64)
+        rq = _Request()
+        rq.dims = (ctypes.c_int64 * 3)(*[int(d) for d in dims])
+        rq.nnz = n
+        rq.i, rq.j, rq.k = (a.ctypes.data for a in arrs)
+        rq.val = v.ctypes.data
+        rq.R = int(R)
+        rq.dtype = F32 if dtype == "f32" else BF16
+        rq.reg = float(reg)
+        rq.init = (ctypes.c_void_p * 3)(*[f.ctypes.data for f in ini])
+        rq.tol = float(tol)
+        rq.max_iters = int(max_iters)
+        rq.out_F = (ctypes.c_void_p * 3)(*[f.ctypes.data for f in outF])
+        rq.out_lambda = outL.ctypes.data
+        rid = ctypes.c_int64()
+        st = load().dfacto_server_submit(self.handle, ctypes.byref(rq), ctypes.byref(rid))
+        if st != OK:
+            raise DfactoError(st, "dfacto_server_submit failed")
+        self._reqs[rid.value] = (arrs, v, ini, outF, outL)
+        return rid.value
+
+    def _result(self, rid, s: _RequestStatus) -> dict:
+        _, _, _, outF, outL = self._reqs.pop(rid)
+        return dict(status=s.status, fit=s.fit, iters=s.iters, t_submit=s.t_submit,
+                    t_admit=s.t_admit, t_done=s.t_done, factors=outF, lam=outL)
+
+    def poll(self, rid: int):
+        """The result dict once done, else None."""
+        s = _RequestStatus()
+        st = load().dfacto_server_poll(self.handle, int(rid), ctypes.byref(s))
+        if st == E_AGAIN:
+            return None
+        if st != OK:
+            raise DfactoError(st, "dfacto_server_poll failed")
+        return self._result(rid, s)
+
+    def wait(self, rid: int) -> dict:
+        s = _RequestStatus()
+        st = load().dfacto_server_wait(self.handle, int(rid), ctypes.byref(s))
+        if st != OK:
+            raise DfactoError(st, "dfacto_server_wait failed")
+        return self._result(rid, s)
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        st = load().dfacto_server_get_stats(self.handle, ctypes.byref(s))
+        if st != OK:
+            raise DfactoError(st, "dfacto_server_get_stats failed")
+        return dict(pending=s.pending, running=s.running, finished=s.finished,
+                    peak_active=s.peak_active, iterations=s.iterations, budget=s.budget)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().dfacto_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_create(device=0, hbm_budget=0, max_slots=16) -> Server:
+    return Server(device, hbm_budget, max_slots)
 
 
 def profile_enable(ctx: Context, on: bool = True):

@@ -33,3 +33,13 @@ def test_no_device_is_reported_as_error():
     assert lib.dfacto_ctx_create(0, None, ctypes.byref(h)) == dfacto.E_DEVICE
     assert lib.dfacto_ctx_create(0, None, None) == dfacto.E_INVALID
     assert lib.dfacto_last_error(None) == b"context is NULL"
+
+
+def test_server_create_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        return
+    lib = dfacto.load()
+    h = ctypes.c_void_p()
+    assert lib.dfacto_server_create(0, 0, 4, ctypes.byref(h)) == dfacto.E_DEVICE
+    assert not h.value

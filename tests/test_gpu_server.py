@@ -1,0 +1,136 @@
+"""GPU tests of served solves (dfacto_server_*): continuous batching must not
+change any result -- each request gives bitwise the same factors, weights,
+fit and iteration count alone and in a mix -- and those results are the ones
+of dfacto_als_iter repeated on the request alone; admission respects the slot
+count and the memory budget."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import say, DEV
+from paper_1406_4519_amd import dfacto, gen
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [
+    ((900, 700, 500), 20_000, 8, "f32"),
+    ((3000, 1000, 400), 60_000, 16, "f32"),
+    ((500, 1500, 800), 30_000, 32, "bf16"),
+    ((2000, 2000, 2000), 100_000, 32, "f32"),
+    ((700, 300, 200), 8_000, 16, "bf16"),
+    ((1200, 900, 600), 40_000, 8, "f32"),
+]
+
+
+@pytest.fixture(scope="module")
+def requests():
+    out = []
+    for s, (dims, nnz, R, dt) in enumerate(SPECS):
+        coo = gen.zipf_distinct(dims, nnz, 1.1, seed=900 + s)
+        init = [f.astype(np.float32) for f in gen.init_factors(coo.dims, R, seed=950 + s)]
+        out.append(dict(coo=coo, R=R, dtype=dt, init=init))
+    return out
+
+
+def _submit(srv, r, tol=1e-4, max_iters=12):
+    c = r["coo"]
+    return srv.submit(c.dims, c.i, c.j, c.k, c.val, r["R"], r["init"], dtype=r["dtype"], tol=tol,
+                      max_iters=max_iters)
+
+
+def _alone(requests, **kw):
+    srv = dfacto.Server(0, max_slots=1)
+    res = [srv.wait(_submit(srv, r, **kw)) for r in requests]
+    srv.close()
+    return res
+
+
+def _same(a, b):
+    assert a["status"] == b["status"] == dfacto.OK
+    assert a["iters"] == b["iters"]
+    assert a["fit"] == b["fit"]
+    for m in range(3):
+        assert np.array_equal(a["factors"][m], b["factors"][m])
+    assert np.array_equal(a["lam"], b["lam"])
+
+
+def test_served_results_same_alone_and_in_mix(requests):
+    alone = _alone(requests)
+    srv = dfacto.Server(0, max_slots=8)
+    ids = []
+    for q, r in enumerate(requests):  # staggered arrivals: later ones join running work
+        ids.append(_submit(srv, r))
+        if q % 2 == 1:
+            time.sleep(0.01)
+    mix = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    say(f"  server stats: {st}; iterations per request {[m['iters'] for m in mix]}")
+    assert st["peak_active"] >= 2, "the requests never overlapped"
+    for a, b in zip(alone, mix):
+        _same(a, b)
+
+
+def test_served_result_equals_repeated_als_iter(requests):
+    r = requests[1]
+    res = _alone([r])[0]
+    c = r["coo"]
+    ctx = dfacto.Context(0)
+    from gpu_util import build, factors_to_dev
+    t = build(ctx, c)
+    F = [torch.from_numpy(f.copy()).to(DEV) for f in r["init"]]
+    lam = torch.zeros(r["R"], dtype=torch.float64, device=DEV)
+    fit = torch.zeros(1, dtype=torch.float64, device=DEV)
+    for _ in range(res["iters"]):
+        dfacto.als_iter(ctx, t, F, lam, fit)
+    torch.cuda.synchronize()
+    assert fit.item() == res["fit"]
+    for m in range(3):
+        assert np.array_equal(F[m].cpu().numpy(), res["factors"][m])
+    assert np.array_equal(lam.cpu().numpy(), res["lam"])
+    t.close()
+    ctx.close()
+
+
+def test_admission_limits(requests):
+    # one slot: never more than one active
+    srv = dfacto.Server(0, max_slots=1)
+    ids = [_submit(srv, r, max_iters=3) for r in requests[:3]]
+    res = [srv.wait(i) for i in ids]
+    assert srv.stats()["peak_active"] == 1
+    srv.close()
+    assert all(x["status"] == dfacto.OK for x in res)
+    # a 1-byte budget admits one request at a time (the first always fits)
+    srv = dfacto.Server(0, hbm_budget=1, max_slots=8)
+    ids = [_submit(srv, r, max_iters=3) for r in requests[:4]]
+    res = [srv.wait(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    assert st["peak_active"] == 1
+    assert all(x["status"] == dfacto.OK for x in res)
+    # admission follows arrival order
+    admits = [x["t_admit"] for x in res]
+    assert admits == sorted(admits)
+
+
+def test_submit_errors(requests):
+    srv = dfacto.Server(0, max_slots=2)
+    r = requests[0]
+    c = r["coo"]
+    init5 = [np.zeros((d, 5), np.float32) for d in c.dims]
+    with pytest.raises(dfacto.DfactoError) as e:
+        srv.submit(c.dims, c.i, c.j, c.k, c.val, 5, init5)
+    assert e.value.status == dfacto.E_UNSUPPORTED
+    with pytest.raises(dfacto.DfactoError) as e:
+        srv.submit(c.dims, c.i, c.j, c.k, c.val, r["R"], r["init"], max_iters=0)
+    assert e.value.status == dfacto.E_INVALID
+    # an out-of-range coordinate fails the request, not the server
+    bad = c.i.copy()
+    bad[0] = c.dims[0]
+    rid = srv.submit(c.dims, bad, c.j, c.k, c.val, r["R"], r["init"], max_iters=2)
+    assert srv.wait(rid)["status"] == dfacto.E_RANGE
+    ok = srv.wait(_submit(srv, r, max_iters=2))
+    assert ok["status"] == dfacto.OK and ok["iters"] == 2
+    srv.close()
