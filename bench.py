@@ -246,13 +246,94 @@ def run_served(args):
     print(json.dumps(line), flush=True)
 
 
+def run_paper(args):
+    """Paper-shape tensor on one GPU: 6.5M x 2.5M x 1.5M, 1.2B distinct
+    Zipf(1.2) coordinates, FP32 values; for R = 10 and 32 and FP32 / BF16
+    factor storage: one CP-ALS iteration plus one GD gradient (6 MTTKRPs)
+    after one warm-up step.  value = FP32, R = 32 MTTKRP throughput of the
+    step (6 nnz R per step time)."""
+    import numpy as np
+    import torch
+    from paper_1406_4519_amd import dfacto, gen
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    coo = gen.zipf_distinct((6_500_000, 2_500_000, 1_500_000), 1_200_000_000, 1.2, seed=3,
+                            progress=lambda m: log(f"  [{time.perf_counter() - t0:.0f}s] {m}"))
+    log(f"generated {coo.nnz:,} nonzeros in {time.perf_counter() - t0:.1f}s")
+    ctx = dfacto.Context(0)
+    arrs = [torch.from_numpy(x.view(np.int32)).to(dev) for x in (coo.i, coo.j, coo.k)]
+    v = torch.from_numpy(coo.val).to(dev)
+    dims, nnz = coo.dims, coo.nnz
+    del coo
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    T = dfacto.build_flattenings(ctx, dims, *arrs, v)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - tb) * 1e3
+    del arrs, v
+    torch.cuda.empty_cache()
+    info = T.info()
+    log(f"built in {build_ms:.0f} ms: nfib={info['nfib']} bytes={info['bytes'] / 1e9:.1f} GB")
+    res = {}
+    for R in (32, 10):
+        F0 = gen.init_factors(dims, R, seed=1003)
+        for dt in ("f32", "bf16"):
+            tdt = torch.float32 if dt == "f32" else torch.bfloat16
+            F = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(dev).to(tdt)
+                 for f in F0]
+            G = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in dims]
+            lam = torch.zeros(R, dtype=torch.float64, device=dev)
+            fit = torch.zeros(1, dtype=torch.float64, device=dev)
+            fv = torch.zeros(1, dtype=torch.float64, device=dev)
+            dfacto.als_iter(ctx, T, F, lam, fit)
+            dfacto.gd_grad(ctx, T, F, G, fv)
+            torch.cuda.synchronize()
+            dfacto.profile_enable(ctx, True)
+            ts = time.perf_counter()
+            dfacto.als_iter(ctx, T, F, lam, fit)
+            torch.cuda.synchronize()
+            als_ms = (time.perf_counter() - ts) * 1e3
+            tg = time.perf_counter()
+            dfacto.gd_grad(ctx, T, F, G, fv)
+            torch.cuda.synchronize()
+            gd_ms = (time.perf_counter() - tg) * 1e3
+            prof = dfacto.profile_read(ctx)
+            dfacto.profile_enable(ctx, False)
+            avg = prof["ms"] / max(prof["launches"], 1)
+            gbs = prof["bytes"] / max(prof["launches"], 1) / (avg * 1e-3) / 1e9
+            res[f"R{R}_{dt}"] = dict(als_iter_ms=round(als_ms, 2), gd_grad_ms=round(gd_ms, 2),
+                                     step_nnzR_per_s=6.0 * nnz * R / ((als_ms + gd_ms) * 1e-3),
+                                     mttkrp_main_ms=round(avg, 3), mttkrp_GBs=round(gbs, 1),
+                                     hbm_frac=round(gbs / HBM_PEAK_GBS, 4), fit=float(fit.item()))
+            log(f"R={R} {dt}: {res[f'R{R}_{dt}']}")
+            del F, G
+            torch.cuda.empty_cache()
+    r = res["R32_f32"]
+    line = {"metric": METRIC, "value": r["step_nnzR_per_s"], "unit": "nnz·R/s", "n_gpus": 1,
+            "steps": 1, "warmup": 1, "ms_per_step": round(r["als_iter_ms"] + r["gd_grad_ms"], 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "paper1200m: 6.5M x 2.5M x 1.5M, 1.2B distinct Zipf(1.2) "
+                                   "coordinates, FP32 values; R = 32 (also R = 10) FP32 and BF16 "
+                                   "factors; one CP-ALS iteration + one GD gradient",
+                       "nnz": nnz, "nfib": list(info["nfib"]), "parallelism": "single GPU"},
+            "roofline": {"bound": "hbm", "achieved": r["mttkrp_GBs"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": r["hbm_frac"], "traffic": None},
+            "extra": {"build_ms": round(build_ms, 1), "runs": res,
+                      "paper_context_s": {"als_iter_4_machines": 480, "gd_iter_4_machines": 1143}}}
+    print(json.dumps(line), flush=True)
+    T.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zipf50m",
-                    choices=["zipf50m", "small", "batched", "served"])
+                    choices=["zipf50m", "small", "batched", "served", "paper1200m"])
     ap.add_argument("--batch", type=int, default=256, help="batched workload: number of tensors")
     ap.add_argument("--iters", type=int, default=20, help="batched workload: ALS iterations")
     ap.add_argument("--rate", type=float, default=200.0, help="served workload: arrivals per second")
@@ -286,6 +367,8 @@ def main():
         return run_batched(args)
     if args.workload == "served":
         return run_served(args)
+    if args.workload == "paper1200m":
+        return run_paper(args)
 
     t0 = time.perf_counter()
     if args.workload == "zipf50m":

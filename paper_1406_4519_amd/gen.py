@@ -91,31 +91,49 @@ def _draw_ranks(cdf: np.ndarray, u: np.ndarray, pool: ThreadPoolExecutor) -> np.
     return r
 
 
-def _first_occurrences(keys: np.ndarray, pool: ThreadPoolExecutor) -> np.ndarray:
-    """Sorted positions of the first occurrence of every distinct key."""
+def _first_occurrences(keys: np.ndarray, pool: ThreadPoolExecutor,
+                       lo: np.ndarray | None = None) -> np.ndarray:
+    """Sorted positions of the first occurrence of every distinct key (keys
+    alone, or the pairs (keys, lo) when the coordinate needs two words)."""
     nb = 16
-    bucket = ((keys * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(60)).astype(np.uint8)
+    h = keys if lo is None else (keys * np.uint64(0xD6E8FEB86659FD93)) ^ lo
+    bucket = ((h * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(60)).astype(np.uint8)
 
     def one(b):
         pos = np.flatnonzero(bucket == b)
-        kb = keys[pos]
-        order = np.argsort(kb, kind="stable")
-        ks = kb[order]
-        first = np.ones(len(ks), dtype=bool)
-        if len(ks) > 1:
-            first[1:] = ks[1:] != ks[:-1]
+        if lo is None:
+            kb = keys[pos]
+            order = np.argsort(kb, kind="stable")
+            ks = kb[order]
+            first = np.ones(len(ks), dtype=bool)
+            if len(ks) > 1:
+                first[1:] = ks[1:] != ks[:-1]
+        else:
+            kh, kl = keys[pos], lo[pos]
+            order = np.lexsort((kl, kh))  # stable: equal pairs keep draw order
+            sh, sl = kh[order], kl[order]
+            first = np.ones(len(order), dtype=bool)
+            if len(order) > 1:
+                first[1:] = (sh[1:] != sh[:-1]) | (sl[1:] != sl[:-1])
         return pos[order[first]]
 
-    parts = list(pool.map(one, range(nb)))
+    if len(keys) > 400_000_000:  # bound the memory of concurrent buckets
+        parts = []
+        for g in range(0, nb, 4):
+            parts.extend(pool.map(one, range(g, g + 4)))
+    else:
+        parts = list(pool.map(one, range(nb)))
     return np.sort(np.concatenate(parts))
 
 
-def zipf_distinct(dims, nnz: int, s: float, seed: int, values: str = "absnormal") -> Coo:
+def zipf_distinct(dims, nnz: int, s: float, seed: int, values: str = "absnormal",
+                  progress=None) -> Coo:
     I, J, K = (int(d) for d in dims)
     if I * J * K < nnz:
         raise ValueError("more distinct nonzeros requested than cells")
-    if float(I) * J * K >= 2.0 ** 63:
-        raise ValueError("linear key does not fit in 63 bits; use a smaller tensor")
+    wide = float(I) * J * K >= 2.0 ** 63  # key = (i, j K + k) in two words
+    if wide and float(J) * K >= 2.0 ** 63:
+        raise ValueError("tensor too large for the coordinate key")
     rng = np.random.Generator(np.random.PCG64(seed))
     cdfs = [zipf_cdf(d, s) for d in (I, J, K)]
     perms = [rng.permutation(d).astype(np.uint32) for d in (I, J, K)]
@@ -129,6 +147,9 @@ def zipf_distinct(dims, nnz: int, s: float, seed: int, values: str = "absnormal"
             for m in range(3):
                 u = rng.random(draw)
                 new.append(perms[m][_draw_ranks(cdfs[m], u, pool)])
+                del u
+                if progress is not None:
+                    progress(f"zipf draw: mode {m}, {draw:,} samples")
             if values == "absnormal":
                 v = np.abs(rng.standard_normal(draw)).astype(np.float32)
             elif values == "normal":
@@ -137,9 +158,17 @@ def zipf_distinct(dims, nnz: int, s: float, seed: int, values: str = "absnormal"
                 raise ValueError(values)
             idx = [np.concatenate([idx[m], new[m]]) for m in range(3)]
             vals = np.concatenate([vals, v])
-            keys = (idx[0].astype(np.uint64) * np.uint64(J) + idx[1].astype(np.uint64)) \
-                * np.uint64(K) + idx[2].astype(np.uint64)
-            first = _first_occurrences(keys, pool)
+            if wide:
+                keys = idx[0].astype(np.uint64)
+                lo = idx[1].astype(np.uint64) * np.uint64(K) + idx[2].astype(np.uint64)
+                first = _first_occurrences(keys, pool, lo)
+                del lo
+            else:
+                keys = (idx[0].astype(np.uint64) * np.uint64(J) + idx[1].astype(np.uint64)) \
+                    * np.uint64(K) + idx[2].astype(np.uint64)
+                first = _first_occurrences(keys, pool)
+            if progress is not None:
+                progress(f"zipf draw: {len(keys):,} coordinates, {len(first):,} distinct")
             if len(first) >= nnz:
                 sel = first[:nnz]
                 return Coo((I, J, K), idx[0][sel].copy(), idx[1][sel].copy(),

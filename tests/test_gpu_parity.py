@@ -128,10 +128,13 @@ def test_appendix_a1_flattenings_exact(ctx):
 # builder structure against the oracle's flattening: exact
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("case", ["uniform", "dups", "zipf", "heavy"])
+@pytest.mark.parametrize("case", ["uniform", "dups", "zipf", "heavy", "wide"])
 def test_build_structure_matches_oracle(ctx, case):
-    rng = np.random.default_rng(hash(case) % 2 ** 32)
-    if case == "uniform":
+    rng = np.random.default_rng({"uniform": 31, "dups": 32, "zipf": 33, "heavy": 34, "wide": 35}[case])
+    if case == "wide":
+        # index bits 23 + 22 + 21 > 64: the mode-0 order takes the two-pass sort
+        coo = gen.zipf_distinct((6_500_000, 2_500_000, 1_500_000), 50_000, 1.2, seed=36)
+    elif case == "uniform":
         coo = gen.uniform_distinct((300, 200, 100), 30_000, seed=3)
     elif case == "dups":
         base = gen.uniform_distinct((50, 40, 30), 3000, seed=4)
