@@ -181,6 +181,28 @@ def zipf_distinct(dims, nnz: int, s: float, seed: int, values: str = "absnormal"
         pool.shutdown()
 
 
+def zipf_draws(dims, n: int, s: float, seed: int, progress=None) -> Coo:
+    """n coordinates drawn independently per mode from Zipf(s) over a seeded
+    permutation of each mode, |N(0,1)| values, duplicates kept (the
+    flattening build sums them)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cdfs = [zipf_cdf(int(d), s) for d in dims]
+    perms = [rng.permutation(int(d)).astype(np.uint32) for d in dims]
+    pool = ThreadPoolExecutor(_workers())
+    try:
+        idx = []
+        for m in range(3):
+            u = rng.random(n)
+            idx.append(perms[m][_draw_ranks(cdfs[m], u, pool)])
+            del u
+            if progress is not None:
+                progress(f"zipf draws: mode {m}, {n:,} samples")
+        val = np.abs(rng.standard_normal(n, dtype=np.float32))
+    finally:
+        pool.shutdown()
+    return Coo(tuple(int(d) for d in dims), idx[0], idx[1], idx[2], val)
+
+
 def planted_factors(dims, R: int, seed: int, density: float = 1.0):
     """N(0,1) factors; with density < 1 each column keeps that fraction of
     rows (chosen at random) and is zero elsewhere."""
