@@ -283,6 +283,10 @@ typedef struct {
     int peak_active;           /* most requests active at one time */
     int64_t iterations;        /* iteration boundaries run */
     size_t budget;
+    /* worker wall time, seconds: uploading and building admitted requests,
+     * (re)building groups, running iterations (incl. reading the fits), and
+     * delivering results */
+    double t_admit, t_groups, t_iterate, t_deliver;
 } dfacto_server_stats;
 
 dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,

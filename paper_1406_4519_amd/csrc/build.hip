@@ -369,16 +369,21 @@ __global__ void k_chunk_starts(const uint2 *__restrict__ st, int64_t nentry, int
 // host helpers
 // ---------------------------------------------------------------------------
 
+// Transient build buffers, stream-ordered (hipMallocAsync / hipFreeAsync),
+// so building one tensor never waits for unrelated work on the device.
 struct Scratch {
+    hipStream_t s;
     std::vector<void *> ptrs;
+    explicit Scratch(hipStream_t st) : s(st) {}
     ~Scratch() {
-        for (void *p : ptrs) (void)hipFree(p);
+        for (void *p : ptrs)
+            if (p) (void)hipFreeAsync(p, s);
     }
     template <typename T>
     T *alloc(int64_t n) {
         void *p = nullptr;
         const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
-        if (hipMalloc(&p, bytes) != hipSuccess) {
+        if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
             (void)hipGetLastError();
             throw Error{DFACTO_E_NOMEM, "device allocation of " + std::to_string(bytes) +
                                             " bytes failed while building the flattenings"};
@@ -389,7 +394,7 @@ struct Scratch {
     void release(void *p) {
         for (auto &q : ptrs)
             if (q == p) {
-                (void)hipFree(q);
+                (void)hipFreeAsync(q, s);
                 q = nullptr;
             }
     }
@@ -399,7 +404,9 @@ template <typename T>
 T *tensor_alloc(dfacto_tensor *t, int64_t n) {
     void *p = nullptr;
     const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    const hipError_t e =
+        t->alloc_stream ? hipMallocAsync(&p, bytes, t->alloc_stream) : hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
         (void)hipGetLastError();
         throw Error{DFACTO_E_NOMEM, "device allocation of " + std::to_string(bytes) +
                                         " bytes failed for the flattenings"};
@@ -483,6 +490,8 @@ void build_runs(dfacto_tensor *t, ModeData &md, hipStream_t s, Scratch &sc) {
         DF_HIP(hipMemcpyAsync(md.runs_long, longr.data(), sizeof(uint32_t) * longr.size(),
                               hipMemcpyHostToDevice, s));
     DF_HIP(hipStreamSynchronize(s));
+    md.runs_short_host = std::move(shortr);
+    md.runs_long_host = std::move(longr);
 }
 
 void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
@@ -490,7 +499,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     hipStream_t s = ctx->stream;
     ModeData &md = t->mode[m];
     const int64_t nrows = t->dims[md.root];
-    Scratch sc;
+    Scratch sc(s);
     int chunk_len = 4 * kFiberCap;
     if (const char *env = getenv("DFACTO_CHUNK")) {
         const int v = atoi(env);
@@ -517,6 +526,8 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
         hipLaunchKernelGGL(k_compact_rows, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, pos,
                            nrows, md.empty_rows);
         DF_LAUNCHED();
+        md.empty_rows_host.resize((size_t)nrows);
+        for (int64_t r = 0; r < nrows; ++r) md.empty_rows_host[r] = (uint32_t)r;
         DF_HIP(hipStreamSynchronize(s));
         return;
     }
@@ -565,6 +576,10 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
                        md.stream, L, md.nchunk, chunk_len, md.chunk_start);
     DF_LAUNCHED();
     build_runs(t, md, s, sc);
+    md.empty_rows_host.resize((size_t)md.nempty);
+    if (md.nempty > 0)
+        DF_HIP(hipMemcpyAsync(md.empty_rows_host.data(), md.empty_rows,
+                              sizeof(uint32_t) * md.nempty, hipMemcpyDeviceToHost, s));
     DF_HIP(hipStreamSynchronize(s));
 }
 
@@ -593,7 +608,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
                   const uint32_t *d_k, const float *d_val) {
     hipStream_t s = ctx->stream;
     const int64_t n = t->nnz;
-    Scratch sc;
+    Scratch sc(s);
     static const int ROOT[3] = {0, 1, 2}, MID[3] = {2, 0, 1}, LEAF[3] = {1, 2, 0};
     for (int m = 0; m < 3; ++m) {
         t->mode[m].root = ROOT[m];

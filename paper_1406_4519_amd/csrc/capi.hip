@@ -96,6 +96,47 @@ Small small_ws(dfacto_ctx *ctx, int R) {
 }  // namespace
 }  // namespace dfacto
 
+namespace dfacto {
+
+dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
+                                     const uint32_t *d_i, const uint32_t *d_j,
+                                     const uint32_t *d_k, const float *d_val, dfacto_tensor **out,
+                                     bool async_alloc) {
+    if (out) *out = nullptr;
+    return guarded(ctx, [&] {
+        if (!out || !dims) throw Error{DFACTO_E_INVALID, "dims or out is NULL"};
+        for (int m = 0; m < 3; ++m)
+            if (dims[m] < 1 || dims[m] > DFACTO_MAX_DIM)
+                throw Error{DFACTO_E_INVALID, "every dimension must be in [1, 2^30]"};
+        if (nnz < 0) throw Error{DFACTO_E_INVALID, "nnz is negative"};
+        if (nnz > 0 && (!d_i || !d_j || !d_k || !d_val))
+            throw Error{DFACTO_E_INVALID, "coordinate or value array is NULL"};
+        if (nnz >= (int64_t)0xFFFFFFFFu - (1 << 20))
+            throw Error{DFACTO_E_UNSUPPORTED, "nnz must be below 2^32 - 2^20"};
+        dfacto_tensor *t = new dfacto_tensor();
+        t->device = ctx->device;
+        if (async_alloc) t->alloc_stream = ctx->stream;
+        for (int m = 0; m < 3; ++m) t->dims[m] = dims[m];
+        t->nnz = nnz;
+        try {
+            build_tensor(ctx, t, d_i, d_j, d_k, d_val);
+        } catch (...) {
+            dfacto_tensor_destroy(t);
+            throw;
+        }
+        *out = t;
+    });
+}
+
+dfacto_status build_flattenings_async_alloc(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
+                                            const uint32_t *d_i, const uint32_t *d_j,
+                                            const uint32_t *d_k, const float *d_val,
+                                            dfacto_tensor **out) {
+    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, true);
+}
+
+}  // namespace dfacto
+
 using namespace dfacto;
 
 extern "C" {
@@ -151,29 +192,7 @@ dfacto_status dfacto_build_flattenings(dfacto_ctx *ctx, const int64_t dims[3], i
                                        const uint32_t *d_i, const uint32_t *d_j,
                                        const uint32_t *d_k, const float *d_val,
                                        dfacto_tensor **out) {
-    if (out) *out = nullptr;
-    return guarded(ctx, [&] {
-        if (!out || !dims) throw Error{DFACTO_E_INVALID, "dims or out is NULL"};
-        for (int m = 0; m < 3; ++m)
-            if (dims[m] < 1 || dims[m] > DFACTO_MAX_DIM)
-                throw Error{DFACTO_E_INVALID, "every dimension must be in [1, 2^30]"};
-        if (nnz < 0) throw Error{DFACTO_E_INVALID, "nnz is negative"};
-        if (nnz > 0 && (!d_i || !d_j || !d_k || !d_val))
-            throw Error{DFACTO_E_INVALID, "coordinate or value array is NULL"};
-        if (nnz >= (int64_t)0xFFFFFFFFu - (1 << 20))
-            throw Error{DFACTO_E_UNSUPPORTED, "nnz must be below 2^32 - 2^20"};
-        dfacto_tensor *t = new dfacto_tensor();
-        t->device = ctx->device;
-        for (int m = 0; m < 3; ++m) t->dims[m] = dims[m];
-        t->nnz = nnz;
-        try {
-            build_tensor(ctx, t, d_i, d_j, d_k, d_val);
-        } catch (...) {
-            dfacto_tensor_destroy(t);
-            throw;
-        }
-        *out = t;
-    });
+    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, false);
 }
 
 dfacto_status dfacto_tensor_get_info(const dfacto_tensor *t, dfacto_tensor_info *info) {
@@ -243,8 +262,12 @@ void dfacto_tensor_destroy(dfacto_tensor *t) {
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(t->device);
-    (void)hipDeviceSynchronize();
-    for (void *p : t->allocations) (void)hipFree(p);
+    if (t->alloc_stream) {  // stream-ordered memory: free after the stream's work
+        for (void *p : t->allocations) (void)hipFreeAsync(p, t->alloc_stream);
+    } else {
+        (void)hipDeviceSynchronize();
+        for (void *p : t->allocations) (void)hipFree(p);
+    }
     if (prev >= 0) (void)hipSetDevice(prev);
     delete t;
 }

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <deque>
 #include <functional>
 #include <map>
 #include <tuple>
@@ -47,34 +48,47 @@ struct dfacto_group {
     hipGraphExec_t exec = nullptr;
     // persistent grid size of each MTTKRP launch (tuned or default)
     std::vector<unsigned> grid_store;
+    // device tables (sub-allocated) and their host copies
+    char *arena = nullptr;
+    size_t arena_left = 0;
+    std::deque<std::vector<char>> host_tables;
 };
 
 namespace {
 
+// Stream-ordered allocations on the group's stream: creating and freeing a
+// group never waits for unrelated work on the device.
 template <typename T>
 T *dev_alloc(dfacto_group *g, size_t count) {
     void *p = nullptr;
     const size_t bytes = std::max<size_t>(sizeof(T) * count, 256);
-    hip_check(hipMalloc(&p, bytes), "group hipMalloc");
+    hip_check(hipMallocAsync(&p, bytes, g->stream), "group allocation");
     g->allocs.push_back(p);
     g->bytes += bytes;
     return (T *)p;
 }
 
-// (set-up time only: a blocking copy, so the host vector may go away)
+// Tables go to device chunks of at least 4 MB (few allocations); their host
+// copies stay in the group until it is freed, so the copies are
+// asynchronous on the group's stream.
 template <typename T>
 T *upload(dfacto_group *g, const std::vector<T> &v) {
-    T *d = dev_alloc<T>(g, std::max<size_t>(v.size(), 1));
-    if (!v.empty()) DF_HIP(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    const size_t bytes = (std::max<size_t>(v.size(), 1) * sizeof(T) + 255) & ~(size_t)255;
+    if (g->arena_left < bytes) {
+        const size_t chunk = std::max<size_t>(bytes, 4u << 20);
+        g->arena = dev_alloc<char>(g, chunk);
+        g->arena_left = chunk;
+    }
+    T *d = (T *)g->arena;
+    g->arena += bytes;
+    g->arena_left -= bytes;
+    if (!v.empty()) {
+        g->host_tables.emplace_back(reinterpret_cast<const char *>(v.data()),
+                                    reinterpret_cast<const char *>(v.data() + v.size()));
+        DF_HIP(hipMemcpyAsync(d, g->host_tables.back().data(), sizeof(T) * v.size(),
+                              hipMemcpyHostToDevice, g->stream));
+    }
     return d;
-}
-
-template <typename T>
-std::vector<T> download(const T *d, size_t n, hipStream_t s) {
-    std::vector<T> h(n);
-    if (n) DF_HIP(hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, s));
-    DF_HIP(hipStreamSynchronize(s));
-    return h;
 }
 
 // Per-member device workspace.
@@ -170,14 +184,13 @@ struct Build {
                 const uint32_t per = mttkrp_group_chunks_per_item(sh);
                 for (uint32_t b = 0; b < (uint32_t)md.nchunk; b += per)
                     c.items.push_back(make_uint2(t, b));
-                const auto rs = download(md.runs_short, 3 * (size_t)md.nruns_short, g->stream);
+                const auto &rs = md.runs_short_host;
                 for (int64_t r = 0; r < md.nruns_short; ++r)
                     c.shortr.push_back(make_uint4(t, rs[3 * r], rs[3 * r + 1], rs[3 * r + 2]));
-                const auto rl = download(md.runs_long, 3 * (size_t)md.nruns_long, g->stream);
+                const auto &rl = md.runs_long_host;
                 for (int64_t r = 0; r < md.nruns_long; ++r)
                     c.longr.push_back(make_uint4(t, rl[3 * r], rl[3 * r + 1], rl[3 * r + 2]));
-                const auto er = download(md.empty_rows, (size_t)md.nempty, g->stream);
-                for (uint32_t row : er) c.empty.push_back(make_uint2(t, row));
+                for (uint32_t row : md.empty_rows_host) c.empty.push_back(make_uint2(t, row));
             }
             const GroupMttkrp *dd = upload(g, desc);
             for (auto &kv : cls) {
@@ -432,10 +445,10 @@ void dfacto_group_destroy(dfacto_group *g) {
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(g->device);
-    if (g->stream) (void)hipStreamSynchronize(g->stream);
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    for (void *p : g->allocs) (void)hipFree(p);
+    for (void *p : g->allocs) (void)hipFreeAsync(p, g->stream);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
     if (g->ev_in) (void)hipEventDestroy(g->ev_in);
     if (g->ev_out) (void)hipEventDestroy(g->ev_out);
     if (g->stream) (void)hipStreamDestroy(g->stream);

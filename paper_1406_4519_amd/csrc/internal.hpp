@@ -48,6 +48,9 @@ struct ModeData {
     int64_t nruns_short = 0;
     uint32_t *runs_long = nullptr;
     int64_t nruns_long = 0;
+    // host copies of the run lists and empty rows (for grouped launches,
+    // whose tables combine many tensors)
+    std::vector<uint32_t> runs_short_host, runs_long_host, empty_rows_host;
 };
 constexpr int kShortRun = 16;
 
@@ -112,6 +115,9 @@ struct GroupMttkrp {
 
 struct dfacto_tensor {
     int device = 0;
+    // when set, the tensor's memory is stream-ordered (hipMallocAsync on this
+    // stream) and freeing it does not wait for unrelated device work
+    hipStream_t alloc_stream = nullptr;
     int64_t dims[3] = {0, 0, 0};
     int64_t nnz = 0;
     double normsq = 0.0;
@@ -165,6 +171,11 @@ void prof_mark(dfacto_ctx *ctx);
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s);
 
 // builder (build.hip): fills t (allocates its arrays).  Synchronizes.
+// dfacto_build_flattenings with stream-ordered tensor memory on ctx's stream
+dfacto_status build_flattenings_async_alloc(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
+                                            const uint32_t *d_i, const uint32_t *d_j,
+                                            const uint32_t *d_k, const float *d_val,
+                                            dfacto_tensor **out);
 void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const uint32_t *d_j,
                   const uint32_t *d_k, const float *d_val);
 

@@ -1,20 +1,23 @@
 // server.hip -- served CP-ALS solves with continuous batching.
 //
-// A server owns one worker thread, a HIP stream and a device-memory budget.
-// Clients submit solve requests (host COO, rank, storage dtype, initial
-// factors, stopping rule) at any time.  At every iteration boundary the
-// worker
-//   1. admits queued requests in arrival order while their device footprint
-//      fits the budget and a slot is free: it uploads the COO, builds the
-//      flattenings and uploads the initial factors;
-//   2. runs one CP-ALS iteration (Algorithm 2) of every active request as a
-//      group (grouped launches, one group per storage dtype and ridge value);
-//   3. reads the fits and retires every request whose fit changed by less
-//      than its tolerance or that reached its iteration cap: factors and
-//      lambda are copied to the caller's host buffers and its memory is
-//      freed, which lets the next queued requests in.
-// Requests that arrive while others run join at the next boundary, so work
-// of different requests overlaps on the device.  A member's arithmetic does
+// A server owns two threads, each with its own HIP stream, and a
+// device-memory budget.  Clients submit solve requests (host COO, rank,
+// storage dtype, initial factors, stopping rule) at any time.
+//   - The builder admits queued requests in arrival order while a slot is
+//     free and their device footprint fits the budget (slots and bytes are
+//     reserved at admission): it uploads the COO, builds the flattenings and
+//     uploads the initial factors on its own stream, then hands the request
+//     to the worker.  Building overlaps with the running iterations.
+//   - At every iteration boundary the worker attaches the built requests,
+//     runs one CP-ALS iteration (Algorithm 2) of every active request as a
+//     group (grouped launches, one group per storage dtype and ridge value),
+//     reads the fits and retires every request whose fit changed by less
+//     than its tolerance or that reached its iteration cap: factors and
+//     lambda are copied to the caller's host buffers and its memory is
+//     released (stream-ordered, without waiting for the other requests'
+//     work), which frees its slot and bytes for the next queued requests.
+// Requests that arrive while others run join at the next boundary after
+// their build, so work of different requests overlaps on the device.  A member's arithmetic does
 // not depend on the other members (grouped launches reproduce the
 // single-tensor results bit for bit), so every result is the same alone and
 // in any mix.
@@ -64,6 +67,7 @@ struct Member {
     size_t footprint = 0;  // device bytes held while active
     double prev_fit = 0.0;
     bool has_prev = false;
+    hipStream_t mem_stream = nullptr;  // stream the member's memory is ordered on
 };
 
 }  // namespace
@@ -74,25 +78,30 @@ struct dfacto_server {
     int max_slots = 1;
     dfacto_ctx *ctx = nullptr;  // the worker's context (own stream)
     hipStream_t stream = nullptr;
+    dfacto_ctx *bctx = nullptr;  // the builder's context (own stream)
+    hipStream_t bstream = nullptr;
     Clock::time_point t0;
 
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_build, cv_done;
     bool stop = false;
     int64_t next_id = 1;
-    std::deque<std::unique_ptr<Member>> pending;
+    std::deque<std::unique_ptr<Member>> pending;  // submitted, not yet admitted
+    std::deque<std::unique_ptr<Member>> ready;    // built, not yet attached
     std::map<int64_t, dfacto_request_status> finished;  // id -> final status
     std::map<int64_t, int> running;                     // ids admitted and not yet done
+    int slots = 0;     // requests admitted and not yet retired (building, ready or active)
+    size_t used = 0;   // device bytes reserved by those requests
+    int peak_active = 0;
+    int64_t iterations = 0;
+    double t_admit = 0, t_groups = 0, t_iterate = 0, t_deliver = 0;
 
     // worker-only state
     std::vector<std::unique_ptr<Member>> active;
     std::vector<dfacto_group *> groups;  // over `active`, rebuilt when it changes
     bool dirty = true;
-    size_t used = 0;
-    int peak_active = 0;
-    int64_t iterations = 0;
     double *d_fits = nullptr;  // max_slots doubles
-    std::thread worker;
+    std::thread worker, builder;
 };
 
 namespace {
@@ -121,13 +130,16 @@ size_t footprint_estimate(const dfacto_request &r) {
 // sort keys and permutations, gathered copies).
 size_t build_transient(const dfacto_request &r) { return 80 * (size_t)r.nnz + (1 << 20); }
 
+// Release a member's memory, ordered on the stream it was allocated on.  The
+// caller has already waited for every kernel that reads it.
 void free_member(Member &m) {
     for (int k = 0; k < 3; ++k)
-        if (m.F[k]) (void)hipFree(m.F[k]), m.F[k] = nullptr;
-    if (m.lambda) (void)hipFree(m.lambda), m.lambda = nullptr;
+        if (m.F[k]) (void)hipFreeAsync(m.F[k], m.mem_stream), m.F[k] = nullptr;
+    if (m.lambda) (void)hipFreeAsync(m.lambda, m.mem_stream), m.lambda = nullptr;
     if (m.tensor) dfacto_tensor_destroy(m.tensor), m.tensor = nullptr;
 }
 
+// Record a request's final status and give back its slot and bytes.
 void finish(dfacto_server *s, std::unique_ptr<Member> mp, dfacto_status status) {
     Member &m = *mp;
     m.st.status = status;
@@ -136,24 +148,34 @@ void finish(dfacto_server *s, std::unique_ptr<Member> mp, dfacto_status status) 
     std::lock_guard<std::mutex> lk(s->mu);
     s->running.erase(m.id);
     s->finished[m.id] = m.st;
+    s->slots -= 1;
+    s->used -= std::min(s->used, m.footprint);
     s->cv_done.notify_all();
+    s->cv_build.notify_one();
+    s->cv_work.notify_one();
 }
 
-// Upload, build and initialize one request on the worker's stream.
+// Upload, build and initialize one request on the builder's stream; all of
+// its memory is stream-ordered on that stream.  Returns after the stream has
+// finished, so the member is ready for kernels on any stream.
 void admit(dfacto_server *s, Member &m) {
     const dfacto_request &r = m.req;
-    hipStream_t st = s->stream;
+    hipStream_t st = s->bstream;
+    m.mem_stream = st;
     uint32_t *di = nullptr, *dj = nullptr, *dk = nullptr;
     float *dv = nullptr;
     const size_t n = (size_t)std::max<int64_t>(r.nnz, 1);
-    auto cleanup = [&] {
-        (void)hipFree(di), (void)hipFree(dj), (void)hipFree(dk), (void)hipFree(dv);
+    auto cleanup = [&] {  // stream-ordered: no wait for the other requests' work
+        if (di) (void)hipFreeAsync(di, st);
+        if (dj) (void)hipFreeAsync(dj, st);
+        if (dk) (void)hipFreeAsync(dk, st);
+        if (dv) (void)hipFreeAsync(dv, st);
     };
     try {
-        hip_check(hipMalloc(&di, 4 * n), "request upload");
-        hip_check(hipMalloc(&dj, 4 * n), "request upload");
-        hip_check(hipMalloc(&dk, 4 * n), "request upload");
-        hip_check(hipMalloc(&dv, 4 * n), "request upload");
+        hip_check(hipMallocAsync((void **)&di, 4 * n, st), "request upload");
+        hip_check(hipMallocAsync((void **)&dj, 4 * n, st), "request upload");
+        hip_check(hipMallocAsync((void **)&dk, 4 * n, st), "request upload");
+        hip_check(hipMallocAsync((void **)&dv, 4 * n, st), "request upload");
         if (r.nnz > 0) {
             DF_HIP(hipMemcpyAsync(di, r.i, 4 * r.nnz, hipMemcpyHostToDevice, st));
             DF_HIP(hipMemcpyAsync(dj, r.j, 4 * r.nnz, hipMemcpyHostToDevice, st));
@@ -161,28 +183,32 @@ void admit(dfacto_server *s, Member &m) {
             DF_HIP(hipMemcpyAsync(dv, r.val, 4 * r.nnz, hipMemcpyHostToDevice, st));
         }
         const dfacto_status bs =
-            dfacto_build_flattenings(s->ctx, r.dims, r.nnz, di, dj, dk, dv, &m.tensor);
-        if (bs != DFACTO_OK) throw Error{bs, dfacto_last_error(s->ctx)};
+            build_flattenings_async_alloc(s->bctx, r.dims, r.nnz, di, dj, dk, dv, &m.tensor);
+        if (bs != DFACTO_OK) throw Error{bs, dfacto_last_error(s->bctx)};
         cleanup();
         di = dj = dk = nullptr;
         dv = nullptr;
         const size_t es = r.dtype == DFACTO_BF16 ? 2 : 4;
+        std::vector<uint16_t> h[3];  // BF16 staging, alive until the stream is done
         for (int k = 0; k < 3; ++k) {
             const size_t cnt = (size_t)r.dims[k] * r.R;
-            hip_check(hipMalloc(&m.F[k], std::max<size_t>(es * cnt, 16)), "factor allocation");
+            hip_check(hipMallocAsync(&m.F[k], std::max<size_t>(es * cnt, 16), st),
+                      "factor allocation");
             if (r.dtype == DFACTO_BF16) {
-                std::vector<uint16_t> h(cnt);
-                for (size_t e = 0; e < cnt; ++e) h[e] = host_f32_to_bf16(r.init[k][e]);
-                DF_HIP(hipMemcpy(m.F[k], h.data(), 2 * cnt, hipMemcpyHostToDevice));
+                h[k].resize(cnt);
+                for (size_t e = 0; e < cnt; ++e) h[k][e] = host_f32_to_bf16(r.init[k][e]);
+                DF_HIP(hipMemcpyAsync(m.F[k], h[k].data(), 2 * cnt, hipMemcpyHostToDevice, st));
             } else {
-                DF_HIP(hipMemcpy(m.F[k], r.init[k], 4 * cnt, hipMemcpyHostToDevice));
+                DF_HIP(hipMemcpyAsync(m.F[k], r.init[k], 4 * cnt, hipMemcpyHostToDevice, st));
             }
         }
-        hip_check(hipMalloc(&m.lambda, 8 * (size_t)r.R), "lambda allocation");
+        hip_check(hipMallocAsync((void **)&m.lambda, 8 * (size_t)r.R, st), "lambda allocation");
+        DF_HIP(hipStreamSynchronize(st));
         m.footprint = std::max(m.footprint, m.tensor->bytes + footprint_estimate(r) -
                                                 3 * 16 * (size_t)r.nnz);
     } catch (...) {
         cleanup();
+        (void)hipStreamSynchronize(st);
         throw;
     }
 }
@@ -211,12 +237,12 @@ void drop_groups(dfacto_server *s) {
     s->dirty = true;
 }
 
-// One CP-ALS iteration of every active request.  The active list is kept
-// ordered by (dtype, reg); each run of one class is one group, and a
-// class's members own consecutive fit slots.  The groups are rebuilt only
-// when the active set changes.
-void iterate(dfacto_server *s) {
-    if (s->dirty) {
+// Groups over the active requests.  The active list is kept ordered by
+// (dtype, reg); each run of one class is one group, and a class's members
+// own consecutive fit slots.  The groups are rebuilt only when the active
+// set changes.
+void build_groups(dfacto_server *s) {
+    {
         drop_groups(s);
         std::stable_sort(s->active.begin(), s->active.end(),
                          [](const std::unique_ptr<Member> &a, const std::unique_ptr<Member> &b) {
@@ -251,58 +277,106 @@ void iterate(dfacto_server *s) {
         }
         s->dirty = false;
     }
-    for (dfacto_group *g : s->groups) {
-        const dfacto_status st = dfacto_group_als(s->ctx, g, 1);
-        if (st != DFACTO_OK) throw Error{st, dfacto_last_error(s->ctx)};
+}
+
+// Whether the next queued request can be admitted now: a slot is free and
+// its footprint fits the budget.  A request is always admitted when nothing
+// else holds a slot (it fails with E_NOMEM if the device cannot hold it).
+bool can_admit(const dfacto_server *s) {
+    if (s->pending.empty() || s->slots >= s->max_slots) return false;
+    const dfacto_request &r = s->pending.front()->req;
+    return s->slots == 0 || s->used + footprint_estimate(r) + build_transient(r) <= s->budget;
+}
+
+void builder_main(dfacto_server *s) {
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        std::unique_ptr<Member> m;
+        size_t reserved = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_build.wait(lk, [&] { return (s->stop && s->pending.empty()) || can_admit(s); });
+            if (s->pending.empty()) return;  // stopping, nothing left to admit
+            m = std::move(s->pending.front());
+            s->pending.pop_front();
+            reserved = footprint_estimate(m->req) + build_transient(m->req);
+            m->footprint = reserved;
+            s->running[m->id] = 1;
+            s->slots += 1;
+            s->used += reserved;
+        }
+        m->st.t_admit = seconds_since(s, Clock::now());
+        const auto ta = Clock::now();
+        dfacto_status code = DFACTO_OK;
+        try {
+            admit(s, *m);
+        } catch (const Error &e) {
+            code = e.code;
+        }
+        const double dt = std::chrono::duration<double>(Clock::now() - ta).count();
+        if (code != DFACTO_OK) {
+            free_member(*m);
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->t_admit += dt;
+            }
+            finish(s, std::move(m), code);
+            continue;
+        }
+        // the reservation shrinks to what the built request holds
+        const size_t held = std::max(m->tensor->bytes + footprint_estimate(m->req) -
+                                         std::min(footprint_estimate(m->req), 3 * 16 * (size_t)m->req.nnz),
+                                     footprint_estimate(m->req));
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->t_admit += dt;
+        s->used = s->used - std::min(s->used, reserved) + held;
+        m->footprint = held;
+        s->ready.push_back(std::move(m));
+        s->cv_work.notify_one();
+        s->cv_build.notify_one();
     }
 }
 
 void worker_main(dfacto_server *s) {
     (void)hipSetDevice(s->device);
+    std::deque<std::unique_ptr<Member>> arrived;
     for (;;) {
-        // admission
+        // attach the built requests
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
-            if (s->stop && s->pending.empty() && s->active.empty()) return;
+            s->cv_work.wait(lk, [&] {
+                return (s->stop && s->pending.empty() && s->slots == 0) || !s->ready.empty() ||
+                       !s->active.empty();
+            });
+            if (s->active.empty() && s->ready.empty()) return;  // stopping, all done
+            arrived.swap(s->ready);
         }
-        for (;;) {
-            std::unique_ptr<Member> m;
-            {
-                std::lock_guard<std::mutex> lk(s->mu);
-                if (s->pending.empty() || (int)s->active.size() >= s->max_slots) break;
-                Member &f = *s->pending.front();
-                const size_t need = footprint_estimate(f.req) + build_transient(f.req);
-                // the first request is admitted even when it alone exceeds
-                // the budget (it fails with E_NOMEM if the device cannot hold it)
-                if (!s->active.empty() && s->used + need > s->budget) break;
-                m = std::move(s->pending.front());
-                s->pending.pop_front();
-                s->running[m->id] = 1;
-            }
-            m->st.t_admit = seconds_since(s, Clock::now());
-            m->footprint = footprint_estimate(m->req);
-            try {
-                admit(s, *m);
-            } catch (const Error &e) {
-                free_member(*m);
-                finish(s, std::move(m), e.code);
-                continue;
-            }
-            s->used += m->footprint;
+        if (!arrived.empty()) {
             drop_groups(s);  // the groups refer to the old active set
-            s->active.push_back(std::move(m));
+            for (auto &m : arrived) s->active.push_back(std::move(m));
+            arrived.clear();
+            std::lock_guard<std::mutex> lk(s->mu);
             s->peak_active = std::max(s->peak_active, (int)s->active.size());
         }
-        if (s->active.empty()) continue;
         // one iteration for everyone, then the stopping rule per request
         try {
-            iterate(s);
+            const auto ti = Clock::now();
+            double tg = 0;
+            {
+                const auto tg0 = Clock::now();
+                if (s->dirty) build_groups(s);
+                tg = std::chrono::duration<double>(Clock::now() - tg0).count();
+            }
+            for (dfacto_group *g : s->groups) {
+                const dfacto_status st = dfacto_group_als(s->ctx, g, 1);
+                if (st != DFACTO_OK) throw Error{st, dfacto_last_error(s->ctx)};
+            }
             std::vector<double> fits(s->active.size());
             DF_HIP(hipMemcpyAsync(fits.data(), s->d_fits, 8 * fits.size(), hipMemcpyDeviceToHost,
                                   s->stream));
             DF_HIP(hipStreamSynchronize(s->stream));
-            ++s->iterations;
+            const double titer = std::chrono::duration<double>(Clock::now() - ti).count() - tg;
+            double tdel = 0;
             std::vector<std::unique_ptr<Member>> keep;
             for (size_t a = 0; a < s->active.size(); ++a) {
                 std::unique_ptr<Member> &m = s->active[a];
@@ -314,19 +388,25 @@ void worker_main(dfacto_server *s) {
                 if (conv || m->st.iters >= m->req.max_iters) {
                     if (!s->groups.empty()) drop_groups(s);
                     dfacto_status code = DFACTO_OK;
+                    const auto td = Clock::now();
                     try {
                         deliver(s, *m);
                     } catch (const Error &e) {
                         code = e.code;
                     }
-                    s->used -= std::min(s->used, m->footprint);
                     free_member(*m);
+                    tdel += std::chrono::duration<double>(Clock::now() - td).count();
                     finish(s, std::move(m), code);
                 } else {
                     keep.push_back(std::move(m));
                 }
             }
             s->active.swap(keep);
+            std::lock_guard<std::mutex> lk(s->mu);
+            ++s->iterations;
+            s->t_groups += tg;
+            s->t_iterate += titer;
+            s->t_deliver += tdel;
         } catch (const Error &e) {
             // a device failure ends every active request with its code
             drop_groups(s);
@@ -335,7 +415,6 @@ void worker_main(dfacto_server *s) {
                 finish(s, std::move(m), e.code);
             }
             s->active.clear();
-            s->used = 0;
         }
     }
 }
@@ -363,21 +442,31 @@ dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
         delete s;
         return DFACTO_E_DEVICE;
     }
+    if (hipStreamCreateWithFlags(&s->bstream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        return DFACTO_E_DEVICE;
+    }
     if (hbm_budget == 0) {  // default: 90% of the free device memory
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) hbm_budget = fr / 10 * 9;
     }
     s->budget = hbm_budget;
     if (hipMalloc(&s->d_fits, 8 * (size_t)max_slots) != hipSuccess ||
-        dfacto_ctx_create(device, s->stream, &s->ctx) != DFACTO_OK) {
+        dfacto_ctx_create(device, s->stream, &s->ctx) != DFACTO_OK ||
+        dfacto_ctx_create(device, s->bstream, &s->bctx) != DFACTO_OK) {
         (void)hipGetLastError();
+        if (s->ctx) dfacto_ctx_destroy(s->ctx);
         if (s->d_fits) (void)hipFree(s->d_fits);
         (void)hipStreamDestroy(s->stream);
+        (void)hipStreamDestroy(s->bstream);
         delete s;
         return DFACTO_E_DEVICE;
     }
     if (prev >= 0) (void)hipSetDevice(prev);
     s->worker = std::thread(worker_main, s);
+    s->builder = std::thread(builder_main, s);
     *out = s;
     return DFACTO_OK;
 }
@@ -400,7 +489,7 @@ dfacto_status dfacto_server_submit(dfacto_server *s, const dfacto_request *req, 
     m->id = s->next_id++;
     *id = m->id;
     s->pending.push_back(std::move(m));
-    s->cv_work.notify_one();
+    s->cv_build.notify_one();
     return DFACTO_OK;
 }
 
@@ -434,6 +523,10 @@ dfacto_status dfacto_server_get_stats(dfacto_server *s, dfacto_server_stats *out
     out->peak_active = s->peak_active;
     out->iterations = s->iterations;
     out->budget = s->budget;
+    out->t_admit = s->t_admit;
+    out->t_groups = s->t_groups;
+    out->t_iterate = s->t_iterate;
+    out->t_deliver = s->t_deliver;
     return DFACTO_OK;
 }
 
@@ -444,6 +537,8 @@ void dfacto_server_destroy(dfacto_server *s) {
         s->stop = true;
     }
     s->cv_work.notify_all();
+    s->cv_build.notify_all();
+    if (s->builder.joinable()) s->builder.join();
     if (s->worker.joinable()) s->worker.join();
     int prev = -1;
     (void)hipGetDevice(&prev);
@@ -451,8 +546,11 @@ void dfacto_server_destroy(dfacto_server *s) {
     drop_groups(s);
     for (auto &m : s->active) free_member(*m);
     if (s->ctx) dfacto_ctx_destroy(s->ctx);
+    if (s->bctx) dfacto_ctx_destroy(s->bctx);
     if (s->d_fits) (void)hipFree(s->d_fits);
+    if (s->bstream) (void)hipStreamSynchronize(s->bstream);  // stream-ordered frees
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->bstream) (void)hipStreamDestroy(s->bstream);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete s;
 }

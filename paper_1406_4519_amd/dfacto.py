@@ -72,7 +72,9 @@ class _RequestStatus(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [("pending", ctypes.c_int64), ("running", ctypes.c_int64),
                 ("finished", ctypes.c_int64), ("peak_active", ctypes.c_int),
-                ("iterations", ctypes.c_int64), ("budget", ctypes.c_size_t)]
+                ("iterations", ctypes.c_int64), ("budget", ctypes.c_size_t),
+                ("t_admit", ctypes.c_double), ("t_groups", ctypes.c_double),
+                ("t_iterate", ctypes.c_double), ("t_deliver", ctypes.c_double)]
 
 
 _lib = None
@@ -468,7 +470,9 @@ class Server:
         if st != OK:
             raise DfactoError(st, "dfacto_server_get_stats failed")
         return dict(pending=s.pending, running=s.running, finished=s.finished,
-                    peak_active=s.peak_active, iterations=s.iterations, budget=s.budget)
+                    peak_active=s.peak_active, iterations=s.iterations, budget=s.budget,
+                    t_admit=s.t_admit, t_groups=s.t_groups, t_iterate=s.t_iterate,
+                    t_deliver=s.t_deliver)
 
     def close(self):
         if getattr(self, "handle", None):
