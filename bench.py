@@ -230,7 +230,7 @@ def run_served(args):
                        large_requests=len(big_lat),
                        large_p50_ms=float(np.percentile(big_lat, 50) * 1e3) if big_lat else None,
                        span_s=span, worker_s={k: round(st[k], 3) for k in
-                                              ("t_admit", "t_groups", "t_iterate", "t_deliver")})
+                                              ("t_admit", "t_build", "t_groups", "t_iterate", "t_deliver")})
         log(f"{dt}: {out[dt]}")
     f = out["f32"]
     line = {"metric": "served CP-ALS solves/s, p50/p99 latency",

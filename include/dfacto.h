@@ -204,10 +204,14 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R,
  * flags: DFACTO_GROUP_GRAPH captures one iteration as a HIP graph on the
  * first dfacto_group_als call and replays it; DFACTO_GROUP_TUNE times the
  * MTTKRP launches with several persistent grid sizes at creation and keeps
- * the fastest (results do not depend on the choice).  Creation synchronizes;
- * E_UNSUPPORTED for a rank outside the list above. */
+ * the fastest (results do not depend on the choice); DFACTO_GROUP_CTX_STREAM
+ * launches on the creating context's stream instead of a stream of the
+ * group's own (cheaper to create and free; later calls must pass a context
+ * with that same stream).  Creation synchronizes; E_UNSUPPORTED for a rank
+ * outside the list above. */
 #define DFACTO_GROUP_GRAPH 1
 #define DFACTO_GROUP_TUNE 2
+#define DFACTO_GROUP_CTX_STREAM 4
 
 typedef struct dfacto_group dfacto_group;
 
@@ -239,13 +243,15 @@ void dfacto_group_destroy(dfacto_group *g);
 /* ------------------------------------------------------------------ */
 
 /* A server runs CP-ALS solves submitted at any time on one device.  It owns
- * a worker thread, a HIP stream and a device-memory budget.  At every
- * iteration boundary the worker admits queued requests in arrival order
- * while a slot is free and their device footprint fits the budget (the
- * three flattenings, each at most about the size of the COO tensor, plus
- * factors and workspace, plus the transient memory of one build), runs one
- * grouped CP-ALS iteration of every active request, and retires the
- * requests that met their stopping rule, which frees memory for the queue.
+ * a device-memory budget, a worker thread and two builder threads, each
+ * with its own HIP stream.  The builders admit queued requests in arrival
+ * order while a slot is free and their device footprint fits the budget
+ * (the three flattenings, each at most about the size of the COO tensor,
+ * plus factors and workspace, plus the transient memory of one build) and
+ * build them while the worker iterates.  At every iteration boundary the
+ * worker attaches the built requests, runs one grouped CP-ALS iteration of
+ * every active request, and retires the requests that met their stopping
+ * rule, which frees memory for the queue.
  * A request's results do not depend on which others run with it: they are
  * bitwise those of dfacto_als_iter repeated on it alone.
  *
@@ -283,10 +289,11 @@ typedef struct {
     int peak_active;           /* most requests active at one time */
     int64_t iterations;        /* iteration boundaries run */
     size_t budget;
-    /* worker wall time, seconds: uploading and building admitted requests,
-     * (re)building groups, running iterations (incl. reading the fits), and
-     * delivering results */
-    double t_admit, t_groups, t_iterate, t_deliver;
+    /* wall time, seconds: builders uploading, building and initializing
+     * admitted requests (summed over the builders), of that the flattening
+     * builds; worker (re)building groups, running iterations (incl. reading
+     * the fits), and delivering results */
+    double t_admit, t_build, t_groups, t_iterate, t_deliver;
 } dfacto_server_stats;
 
 dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,

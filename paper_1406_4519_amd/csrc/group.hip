@@ -38,6 +38,7 @@ struct dfacto_group {
     dfacto_dtype dtype = DFACTO_F32;
     dfacto_ctx gctx;  // bound to the group's own stream; no workspace use
     hipStream_t stream = nullptr;
+    bool own_stream = true;  // false: launches go to the creating context's stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<void *> allocs;
     size_t bytes = 0;
@@ -324,6 +325,8 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
         if (!tensors || !ranks || !d_F || !d_lambda || !d_fit)
             throw Error{DFACTO_E_INVALID, "NULL argument"};
         if (!(reg >= 0.0)) throw Error{DFACTO_E_INVALID, "reg must be >= 0"};
+        if ((flags & DFACTO_GROUP_CTX_STREAM) && (flags & DFACTO_GROUP_GRAPH) && !ctx->stream)
+            throw Error{DFACTO_E_INVALID, "graph capture needs a created stream, not the null stream"};
         hip_check(hipGetLastError(), "a HIP call before dfacto_group_create");
         std::vector<const dfacto_tensor *> T(tensors, tensors + n);
         std::vector<int> R(ranks, ranks + n);
@@ -348,18 +351,27 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
             g->dtype = dtype;
             g->maxR = *std::max_element(R.begin(), R.end());
             g->use_graph = (flags & DFACTO_GROUP_GRAPH) != 0;
-            DF_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
-            DF_HIP(hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
-            DF_HIP(hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
+            g->own_stream = (flags & DFACTO_GROUP_CTX_STREAM) == 0;
+            if (g->own_stream) DF_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+            else g->stream = ctx->stream;
             g->gctx.device = ctx->device;
             g->gctx.num_cu = ctx->num_cu;
             g->gctx.stream = g->stream;
-            // inputs (tensors, factors) come from ctx's stream
-            DF_HIP(hipEventRecord(g->ev_in, ctx->stream));
-            DF_HIP(hipStreamWaitEvent(g->stream, g->ev_in, 0));
+            if (g->own_stream) {  // inputs (tensors, factors) come from ctx's stream
+                DF_HIP(hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
+                DF_HIP(hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
+                DF_HIP(hipEventRecord(g->ev_in, ctx->stream));
+                DF_HIP(hipStreamWaitEvent(g->stream, g->ev_in, 0));
+            }
 
             Build b{g, T, R, reg, d_F, d_lambda, d_fit, {}};
             b.ws.resize(n);
+            // one allocation for every member's workspace: per member the
+            // MTTKRP output (largest mode), the carries (most chunks) and the
+            // FP64 R x R block, each starting on a 256-byte boundary
+            auto al = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
+            std::vector<size_t> off_M(n), off_carry(n), off_d(n);
+            size_t total = 0;
             for (int t = 0; t < n; ++t) {
                 const size_t RR = (size_t)R[t] * R[t];
                 int64_t dmax = 0, cmax = 1;
@@ -367,10 +379,17 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
                     dmax = std::max(dmax, T[t]->dims[m]);
                     cmax = std::max(cmax, T[t]->mode[m].nchunk);
                 }
+                off_M[t] = total, total += al(4 * (size_t)dmax * R[t]);
+                off_carry[t] = total, total += al(4 * (size_t)cmax * R[t]);
+                off_d[t] = total, total += al(8 * (6 * RR + 3 * RR + (4 * RR + R[t]) + 256 * RR + 8));
+            }
+            char *base = dev_alloc<char>(g, total);
+            for (int t = 0; t < n; ++t) {
+                const size_t RR = (size_t)R[t] * R[t];
                 MemberWs &w = b.ws[t];
-                w.M = dev_alloc<float>(g, (size_t)dmax * R[t]);
-                w.carry = dev_alloc<float>(g, (size_t)cmax * R[t]);
-                double *d = dev_alloc<double>(g, 6 * RR + 3 * RR + (4 * RR + R[t]) + 256 * RR + 8);
+                w.M = (float *)(base + off_M[t]);
+                w.carry = (float *)(base + off_carry[t]);
+                double *d = (double *)(base + off_d[t]);
                 size_t o = 0;
                 for (int m = 0; m < 3; ++m) w.G[m] = d + o, o += RR;
                 w.Hinv = d + o, o += RR;
@@ -402,10 +421,14 @@ dfacto_status dfacto_group_als(dfacto_ctx *ctx, dfacto_group *g, int iters) {
     return guarded(ctx, [&] {
         if (!g) throw Error{DFACTO_E_INVALID, "group is NULL"};
         if (g->device != ctx->device) throw Error{DFACTO_E_INVALID, "group on another device"};
+        if (!g->own_stream && g->stream != ctx->stream)
+            throw Error{DFACTO_E_INVALID, "group launches on its creating context's stream"};
         if (iters < 0) throw Error{DFACTO_E_INVALID, "iters must be >= 0"};
         hip_check(hipGetLastError(), "a HIP call before dfacto_group_als");
-        DF_HIP(hipEventRecord(g->ev_in, ctx->stream));
-        DF_HIP(hipStreamWaitEvent(g->stream, g->ev_in, 0));
+        if (g->own_stream) {
+            DF_HIP(hipEventRecord(g->ev_in, ctx->stream));
+            DF_HIP(hipStreamWaitEvent(g->stream, g->ev_in, 0));
+        }
         if (g->use_graph && !g->exec && iters > 0) {
             DF_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
             try {
@@ -423,8 +446,10 @@ dfacto_status dfacto_group_als(dfacto_ctx *ctx, dfacto_group *g, int iters) {
             if (g->use_graph) DF_HIP(hipGraphLaunch(g->exec, g->stream));
             else run_steps(g);
         }
-        DF_HIP(hipEventRecord(g->ev_out, g->stream));
-        DF_HIP(hipStreamWaitEvent(ctx->stream, g->ev_out, 0));
+        if (g->own_stream) {
+            DF_HIP(hipEventRecord(g->ev_out, g->stream));
+            DF_HIP(hipStreamWaitEvent(ctx->stream, g->ev_out, 0));
+        }
     });
 }
 
@@ -448,10 +473,10 @@ void dfacto_group_destroy(dfacto_group *g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     for (void *p : g->allocs) (void)hipFreeAsync(p, g->stream);
-    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    if (g->stream || !g->own_stream) (void)hipStreamSynchronize(g->stream);  // host tables
     if (g->ev_in) (void)hipEventDestroy(g->ev_in);
     if (g->ev_out) (void)hipEventDestroy(g->ev_out);
-    if (g->stream) (void)hipStreamDestroy(g->stream);
+    if (g->stream && g->own_stream) (void)hipStreamDestroy(g->stream);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete g;
 }

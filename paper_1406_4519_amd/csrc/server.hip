@@ -1,13 +1,15 @@
 // server.hip -- served CP-ALS solves with continuous batching.
 //
-// A server owns two threads, each with its own HIP stream, and a
-// device-memory budget.  Clients submit solve requests (host COO, rank,
-// storage dtype, initial factors, stopping rule) at any time.
-//   - The builder admits queued requests in arrival order while a slot is
+// A server owns a worker thread and kBuilders builder threads, each with
+// its own HIP stream, and a device-memory budget.  Clients submit solve
+// requests (host COO, rank, storage dtype, initial factors, stopping rule)
+// at any time.
+//   - A builder admits queued requests in arrival order while a slot is
 //     free and their device footprint fits the budget (slots and bytes are
 //     reserved at admission): it uploads the COO, builds the flattenings and
 //     uploads the initial factors on its own stream, then hands the request
-//     to the worker.  Building overlaps with the running iterations.
+//     to the worker.  Building overlaps with the running iterations and with
+//     the other builder's host-side work.
 //   - At every iteration boundary the worker attaches the built requests,
 //     runs one CP-ALS iteration (Algorithm 2) of every active request as a
 //     group (grouped launches, one group per storage dtype and ridge value),
@@ -78,8 +80,9 @@ struct dfacto_server {
     int max_slots = 1;
     dfacto_ctx *ctx = nullptr;  // the worker's context (own stream)
     hipStream_t stream = nullptr;
-    dfacto_ctx *bctx = nullptr;  // the builder's context (own stream)
-    hipStream_t bstream = nullptr;
+    static constexpr int kBuilders = 2;
+    dfacto_ctx *bctx[kBuilders] = {};  // the builders' contexts (own streams)
+    hipStream_t bstream[kBuilders] = {};
     Clock::time_point t0;
 
     std::mutex mu;
@@ -94,14 +97,14 @@ struct dfacto_server {
     size_t used = 0;   // device bytes reserved by those requests
     int peak_active = 0;
     int64_t iterations = 0;
-    double t_admit = 0, t_groups = 0, t_iterate = 0, t_deliver = 0;
+    double t_admit = 0, t_build = 0, t_groups = 0, t_iterate = 0, t_deliver = 0;
 
     // worker-only state
     std::vector<std::unique_ptr<Member>> active;
     std::vector<dfacto_group *> groups;  // over `active`, rebuilt when it changes
     bool dirty = true;
     double *d_fits = nullptr;  // max_slots doubles
-    std::thread worker, builder;
+    std::thread worker, builder[kBuilders];
 };
 
 namespace {
@@ -155,12 +158,13 @@ void finish(dfacto_server *s, std::unique_ptr<Member> mp, dfacto_status status) 
     s->cv_work.notify_one();
 }
 
-// Upload, build and initialize one request on the builder's stream; all of
+// Upload, build and initialize one request on builder b's stream; all of
 // its memory is stream-ordered on that stream.  Returns after the stream has
-// finished, so the member is ready for kernels on any stream.
-void admit(dfacto_server *s, Member &m) {
+// finished, so the member is ready for kernels on any stream.  *t_build
+// receives the time of the flattening build.
+void admit(dfacto_server *s, int b, Member &m, double *t_build) {
     const dfacto_request &r = m.req;
-    hipStream_t st = s->bstream;
+    hipStream_t st = s->bstream[b];
     m.mem_stream = st;
     uint32_t *di = nullptr, *dj = nullptr, *dk = nullptr;
     float *dv = nullptr;
@@ -182,9 +186,11 @@ void admit(dfacto_server *s, Member &m) {
             DF_HIP(hipMemcpyAsync(dk, r.k, 4 * r.nnz, hipMemcpyHostToDevice, st));
             DF_HIP(hipMemcpyAsync(dv, r.val, 4 * r.nnz, hipMemcpyHostToDevice, st));
         }
+        const auto tb = Clock::now();
         const dfacto_status bs =
-            build_flattenings_async_alloc(s->bctx, r.dims, r.nnz, di, dj, dk, dv, &m.tensor);
-        if (bs != DFACTO_OK) throw Error{bs, dfacto_last_error(s->bctx)};
+            build_flattenings_async_alloc(s->bctx[b], r.dims, r.nnz, di, dj, dk, dv, &m.tensor);
+        *t_build = std::chrono::duration<double>(Clock::now() - tb).count();
+        if (bs != DFACTO_OK) throw Error{bs, dfacto_last_error(s->bctx[b])};
         cleanup();
         di = dj = dk = nullptr;
         dv = nullptr;
@@ -270,7 +276,7 @@ void build_groups(dfacto_server *s) {
             dfacto_group *g = nullptr;
             const dfacto_status st =
                 dfacto_group_create(s->ctx, (int)T.size(), T.data(), R.data(), dt, reg, F.data(),
-                                    lam.data(), s->d_fits + a, 0, &g);
+                                    lam.data(), s->d_fits + a, DFACTO_GROUP_CTX_STREAM, &g);
             if (st != DFACTO_OK) throw Error{st, dfacto_last_error(s->ctx)};
             s->groups.push_back(g);
             a = b;
@@ -288,7 +294,7 @@ bool can_admit(const dfacto_server *s) {
     return s->slots == 0 || s->used + footprint_estimate(r) + build_transient(r) <= s->budget;
 }
 
-void builder_main(dfacto_server *s) {
+void builder_main(dfacto_server *s, int b) {
     (void)hipSetDevice(s->device);
     for (;;) {
         std::unique_ptr<Member> m;
@@ -304,12 +310,13 @@ void builder_main(dfacto_server *s) {
             s->running[m->id] = 1;
             s->slots += 1;
             s->used += reserved;
+            m->st.t_admit = seconds_since(s, Clock::now());  // in arrival order
         }
-        m->st.t_admit = seconds_since(s, Clock::now());
         const auto ta = Clock::now();
         dfacto_status code = DFACTO_OK;
+        double tbuild = 0;
         try {
-            admit(s, *m);
+            admit(s, b, *m, &tbuild);
         } catch (const Error &e) {
             code = e.code;
         }
@@ -319,6 +326,7 @@ void builder_main(dfacto_server *s) {
             {
                 std::lock_guard<std::mutex> lk(s->mu);
                 s->t_admit += dt;
+                s->t_build += tbuild;
             }
             finish(s, std::move(m), code);
             continue;
@@ -329,6 +337,7 @@ void builder_main(dfacto_server *s) {
                                      footprint_estimate(m->req));
         std::lock_guard<std::mutex> lk(s->mu);
         s->t_admit += dt;
+        s->t_build += tbuild;
         s->used = s->used - std::min(s->used, reserved) + held;
         m->footprint = held;
         s->ready.push_back(std::move(m));
@@ -442,31 +451,38 @@ dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
         delete s;
         return DFACTO_E_DEVICE;
     }
-    if (hipStreamCreateWithFlags(&s->bstream, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipStreamDestroy(s->stream);
-        delete s;
-        return DFACTO_E_DEVICE;
-    }
+    for (int b = 0; b < dfacto_server::kBuilders; ++b)
+        if (hipStreamCreateWithFlags(&s->bstream[b], hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int c = 0; c < b; ++c) (void)hipStreamDestroy(s->bstream[c]);
+            (void)hipStreamDestroy(s->stream);
+            delete s;
+            return DFACTO_E_DEVICE;
+        }
     if (hbm_budget == 0) {  // default: 90% of the free device memory
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) hbm_budget = fr / 10 * 9;
     }
     s->budget = hbm_budget;
-    if (hipMalloc(&s->d_fits, 8 * (size_t)max_slots) != hipSuccess ||
-        dfacto_ctx_create(device, s->stream, &s->ctx) != DFACTO_OK ||
-        dfacto_ctx_create(device, s->bstream, &s->bctx) != DFACTO_OK) {
+    bool ok = hipMalloc(&s->d_fits, 8 * (size_t)max_slots) == hipSuccess &&
+              dfacto_ctx_create(device, s->stream, &s->ctx) == DFACTO_OK;
+    for (int b = 0; ok && b < dfacto_server::kBuilders; ++b)
+        ok = dfacto_ctx_create(device, s->bstream[b], &s->bctx[b]) == DFACTO_OK;
+    if (!ok) {
         (void)hipGetLastError();
         if (s->ctx) dfacto_ctx_destroy(s->ctx);
+        for (int b = 0; b < dfacto_server::kBuilders; ++b) {
+            if (s->bctx[b]) dfacto_ctx_destroy(s->bctx[b]);
+            (void)hipStreamDestroy(s->bstream[b]);
+        }
         if (s->d_fits) (void)hipFree(s->d_fits);
         (void)hipStreamDestroy(s->stream);
-        (void)hipStreamDestroy(s->bstream);
         delete s;
         return DFACTO_E_DEVICE;
     }
     if (prev >= 0) (void)hipSetDevice(prev);
     s->worker = std::thread(worker_main, s);
-    s->builder = std::thread(builder_main, s);
+    for (int b = 0; b < dfacto_server::kBuilders; ++b) s->builder[b] = std::thread(builder_main, s, b);
     *out = s;
     return DFACTO_OK;
 }
@@ -524,6 +540,7 @@ dfacto_status dfacto_server_get_stats(dfacto_server *s, dfacto_server_stats *out
     out->iterations = s->iterations;
     out->budget = s->budget;
     out->t_admit = s->t_admit;
+    out->t_build = s->t_build;
     out->t_groups = s->t_groups;
     out->t_iterate = s->t_iterate;
     out->t_deliver = s->t_deliver;
@@ -538,7 +555,8 @@ void dfacto_server_destroy(dfacto_server *s) {
     }
     s->cv_work.notify_all();
     s->cv_build.notify_all();
-    if (s->builder.joinable()) s->builder.join();
+    for (auto &b : s->builder)
+        if (b.joinable()) b.join();
     if (s->worker.joinable()) s->worker.join();
     int prev = -1;
     (void)hipGetDevice(&prev);
@@ -546,11 +564,13 @@ void dfacto_server_destroy(dfacto_server *s) {
     drop_groups(s);
     for (auto &m : s->active) free_member(*m);
     if (s->ctx) dfacto_ctx_destroy(s->ctx);
-    if (s->bctx) dfacto_ctx_destroy(s->bctx);
     if (s->d_fits) (void)hipFree(s->d_fits);
-    if (s->bstream) (void)hipStreamSynchronize(s->bstream);  // stream-ordered frees
+    for (int b = 0; b < dfacto_server::kBuilders; ++b) {
+        if (s->bctx[b]) dfacto_ctx_destroy(s->bctx[b]);
+        (void)hipStreamSynchronize(s->bstream[b]);  // stream-ordered frees
+        (void)hipStreamDestroy(s->bstream[b]);
+    }
     if (s->stream) (void)hipStreamDestroy(s->stream);
-    if (s->bstream) (void)hipStreamDestroy(s->bstream);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete s;
 }

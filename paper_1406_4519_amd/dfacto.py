@@ -32,7 +32,7 @@ EXPORTS = (
     "dfacto_server_wait", "dfacto_server_get_stats", "dfacto_server_destroy",
     "dfacto_profile_enable", "dfacto_profile_read",
 )
-GROUP_GRAPH, GROUP_TUNE = 1, 2
+GROUP_GRAPH, GROUP_TUNE, GROUP_CTX_STREAM = 1, 2, 4
 
 
 class DfactoError(RuntimeError):
@@ -73,7 +73,8 @@ class _ServerStats(ctypes.Structure):
     _fields_ = [("pending", ctypes.c_int64), ("running", ctypes.c_int64),
                 ("finished", ctypes.c_int64), ("peak_active", ctypes.c_int),
                 ("iterations", ctypes.c_int64), ("budget", ctypes.c_size_t),
-                ("t_admit", ctypes.c_double), ("t_groups", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_build", ctypes.c_double),
+                ("t_groups", ctypes.c_double),
                 ("t_iterate", ctypes.c_double), ("t_deliver", ctypes.c_double)]
 
 
@@ -325,7 +326,8 @@ class Group:
     keeps references)."""
 
     def __init__(self, ctx: Context, tensors, factors, lams, fits: torch.Tensor,
-                 reg: float = 0.0, graph: bool = False, tune: bool = False):
+                 reg: float = 0.0, graph: bool = False, tune: bool = False,
+                 ctx_stream: bool = False):
         n = len(tensors)
         if not (len(factors) == len(lams) == n) or n < 1:
             raise ValueError("tensors, factors and lams must have one entry per member")
@@ -346,7 +348,8 @@ class Group:
         rk = (ctypes.c_int * n)(*ranks)
         fp = (ctypes.c_void_p * (3 * n))(*ptrs)
         lp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in lams])
-        flags = (GROUP_GRAPH if graph else 0) | (GROUP_TUNE if tune else 0)
+        flags = ((GROUP_GRAPH if graph else 0) | (GROUP_TUNE if tune else 0)
+                 | (GROUP_CTX_STREAM if ctx_stream else 0))
         h = ctypes.c_void_p()
         ctx.check(load().dfacto_group_create(ctx.handle, n, th, rk, code, float(reg), fp, lp,
                                              _ptr(fits), flags, ctypes.byref(h)))
@@ -471,7 +474,8 @@ class Server:
             raise DfactoError(st, "dfacto_server_get_stats failed")
         return dict(pending=s.pending, running=s.running, finished=s.finished,
                     peak_active=s.peak_active, iterations=s.iterations, budget=s.budget,
-                    t_admit=s.t_admit, t_groups=s.t_groups, t_iterate=s.t_iterate,
+                    t_admit=s.t_admit, t_build=s.t_build, t_groups=s.t_groups,
+                    t_iterate=s.t_iterate,
                     t_deliver=s.t_deliver)
 
     def close(self):

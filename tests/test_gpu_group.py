@@ -107,6 +107,37 @@ def test_group_graph_replays(ctx, members):
     gb.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_group_on_context_stream(ctx, members, graph):
+    """A group launching on its context's stream gives bitwise the results of
+    one with its own stream; a context with another stream is refused."""
+    Fa, la, fa = _state(members, "bf16")
+    Fb, lb, fb = _state(members, "bf16")
+    tensors = [m[1] for m in members]
+    torch.cuda.synchronize()
+    sctx = dfacto.Context(0, stream=torch.cuda.Stream())  # capture needs a created stream
+    ga = dfacto.Group(sctx, tensors, Fa, la, fa, graph=graph, ctx_stream=True)
+    gb = dfacto.Group(ctx, tensors, Fb, lb, fb)
+    for _ in range(3):
+        ga.als(1)
+        gb.als(1)
+    sctx.synchronize()
+    torch.cuda.synchronize()
+    for k in range(len(members)):
+        for m in range(3):
+            assert _same(Fa[k][m], Fb[k][m]), f"member {k} factor {m}"
+        assert torch.equal(la[k], lb[k])
+    assert torch.equal(fa, fb)
+    other = dfacto.Context(0, stream=torch.cuda.Stream())
+    with pytest.raises(dfacto.DfactoError) as e:
+        other.check(dfacto.load().dfacto_group_als(other.handle, ga.handle, 1))
+    assert e.value.status == dfacto.E_INVALID
+    other.close()
+    ga.close()
+    gb.close()
+    sctx.close()
+
+
 def test_group_tuning_keeps_results(ctx, members):
     """Tuned persistent grid sizes do not change any result."""
     Fa, la, fa = _state(members, "f32")
