@@ -243,16 +243,16 @@ void dfacto_group_destroy(dfacto_group *g);
 /* ------------------------------------------------------------------ */
 
 /* A server runs CP-ALS solves submitted at any time on one device.  It owns
- * a device-memory budget, a worker thread and two builder threads, each
- * with its own HIP stream.  The builders admit queued requests in arrival
- * order while a slot is free and their device footprint fits the budget
- * (the three flattenings, each at most about the size of the COO tensor,
- * plus factors and workspace, plus the transient memory of one build) and
- * build them while the worker iterates.  At every iteration boundary the
- * worker attaches the built requests, runs one grouped CP-ALS iteration of
- * every active request, and retires the requests that met their stopping
- * rule, which frees memory for the queue.
- * A request's results do not depend on which others run with it: they are
+ * a device-memory budget, a worker thread, two builder threads (each with
+ * its own HIP stream) and a delivery thread.  The builders admit queued
+ * requests in arrival order while a slot is free and their device footprint
+ * fits the budget (the three flattenings, each at most about the size of
+ * the COO tensor, plus factors and workspace, plus the transient memory of
+ * one build) and build them while the worker iterates.  At every iteration
+ * boundary the worker attaches the built requests, runs one grouped CP-ALS
+ * iteration of every active request, and retires the requests that met
+ * their stopping rule; the delivery thread copies their results to the host
+ * and frees their memory for the queue.  A request's results do not depend on which others run with it: they are
  * bitwise those of dfacto_als_iter repeated on it alone.
  *
  * hbm_budget: device bytes the server may hold (0 = 90% of the free memory
@@ -291,8 +291,8 @@ typedef struct {
     size_t budget;
     /* wall time, seconds: builders uploading, building and initializing
      * admitted requests (summed over the builders), of that the flattening
-     * builds; worker (re)building groups, running iterations (incl. reading
-     * the fits), and delivering results */
+     * builds; worker (re)building groups and running iterations (incl.
+     * reading the fits); delivery thread copying results out */
     double t_admit, t_build, t_groups, t_iterate, t_deliver;
 } dfacto_server_stats;
 

@@ -424,6 +424,15 @@ T read_back(const T *d, hipStream_t s) {
     return h;
 }
 
+// *a + *b (the total of an exclusive scan: last offset plus last flag), one wait
+int64_t read_back_sum(const uint32_t *a, const uint32_t *b, hipStream_t s) {
+    uint32_t h[2];
+    DF_HIP(hipMemcpyAsync(&h[0], a, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    DF_HIP(hipMemcpyAsync(&h[1], b, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    DF_HIP(hipStreamSynchronize(s));
+    return (int64_t)h[0] + h[1];
+}
+
 void radix_sort(uint64_t *&keys, uint32_t *&vals, uint64_t *&kalt, uint32_t *&valt, int64_t n,
                 int bits, Scratch &sc, hipStream_t s) {
     if (n <= 1 || bits <= 0) return;
@@ -489,7 +498,8 @@ void build_runs(dfacto_tensor *t, ModeData &md, hipStream_t s, Scratch &sc) {
     if (!longr.empty())
         DF_HIP(hipMemcpyAsync(md.runs_long, longr.data(), sizeof(uint32_t) * longr.size(),
                               hipMemcpyHostToDevice, s));
-    DF_HIP(hipStreamSynchronize(s));
+    // the host lists move into the mode data (same buffers), so they outlive
+    // the asynchronous copies; the build waits for its stream at the end
     md.runs_short_host = std::move(shortr);
     md.runs_long_host = std::move(longr);
 }
@@ -537,7 +547,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     hipLaunchKernelGGL(k_fiber_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, root, mid, n, fs,
                        rs);
     scan_exclusive_u32(fs, fid, n, s);
-    md.nfib = (int64_t)read_back(fid + n - 1, s) + read_back(fs + n - 1, s);
+    md.nfib = read_back_sum(fid + n - 1, fs + n - 1, s);
     uint32_t *fptr = sc.alloc<uint32_t>(md.nfib);
     hipLaunchKernelGGL(k_fiber_start_pos, dim3(grid_for(n)), dim3(kThreads), 0, s, fs, fid, n,
                        md.nfib, fptr);
@@ -547,7 +557,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     sc.release(fptr);
     uint32_t *hex = fid;  // reuse
     scan_exclusive_u32(h, hex, n, s);
-    const int64_t nhdr = (int64_t)read_back(hex + n - 1, s) + read_back(h + n - 1, s);
+    const int64_t nhdr = read_back_sum(hex + n - 1, h + n - 1, s);
     const int64_t L = n + nhdr;
     if (L > (int64_t)0xFFFFFFFFu - (1 << 20))
         throw Error{DFACTO_E_UNSUPPORTED, "nonzeros plus fiber headers exceed 2^32 - 2^20"};
@@ -564,7 +574,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
                        mark);
     uint32_t *rpos = sc.alloc<uint32_t>(nrows);
     scan_exclusive_u32(mark, rpos, nrows, s);
-    md.nempty = (int64_t)read_back(rpos + nrows - 1, s) + read_back(mark + nrows - 1, s);
+    md.nempty = read_back_sum(rpos + nrows - 1, mark + nrows - 1, s);
     md.nroot = nrows - md.nempty;
     md.empty_rows = tensor_alloc<uint32_t>(t, md.nempty);
     hipLaunchKernelGGL(k_compact_rows, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, rpos,
@@ -577,10 +587,9 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     DF_LAUNCHED();
     build_runs(t, md, s, sc);
     md.empty_rows_host.resize((size_t)md.nempty);
-    if (md.nempty > 0)
+    if (md.nempty > 0)  // complete when build_tensor waits for the stream
         DF_HIP(hipMemcpyAsync(md.empty_rows_host.data(), md.empty_rows,
                               sizeof(uint32_t) * md.nempty, hipMemcpyDeviceToHost, s));
-    DF_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace
@@ -660,7 +669,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
     hipLaunchKernelGGL(k_distinct_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, si, sj, sk, n,
                        dflag);
     scan_exclusive_u32(dflag, dpos, n, s);
-    const int64_t nd = (int64_t)read_back(dpos + n - 1, s) + read_back(dflag + n - 1, s);
+    const int64_t nd = read_back_sum(dpos + n - 1, dflag + n - 1, s);
     uint32_t *di = sc.alloc<uint32_t>(nd), *dj = sc.alloc<uint32_t>(nd), *dk = sc.alloc<uint32_t>(nd);
     float *dv = sc.alloc<float>(nd);
     hipLaunchKernelGGL(k_merge_runs, dim3(grid_for(n)), dim3(kThreads), 0, s, dflag, dpos, n, si,
@@ -677,7 +686,8 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
         double *part = sc.alloc<double>(nb), *tot = sc.alloc<double>(1);
         hipLaunchKernelGGL(k_sumsq_partial, dim3(nb), dim3(kThreads), 0, s, dv, nd, part);
         hipLaunchKernelGGL(k_sum_f64_final, dim3(1), dim3(kThreads), 0, s, part, (int)nb, tot);
-        t->normsq = read_back(tot, s);
+        // lands when build_tensor waits for the stream at its end
+        DF_HIP(hipMemcpyAsync(&t->normsq, tot, sizeof(double), hipMemcpyDeviceToHost, s));
     }
     // mode 0: already in (i, k, j) order
     build_mode(ctx, t, 0, di, dk, dj, dv, nd);
@@ -700,6 +710,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
         DF_LAUNCHED();
         build_mode(ctx, t, m, gr, gm, gl, gv, nd);
     }
+    DF_HIP(hipStreamSynchronize(s));  // the host copies of the run lists and empty rows
 }
 
 }  // namespace dfacto

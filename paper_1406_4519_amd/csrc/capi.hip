@@ -121,6 +121,8 @@ dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int
         try {
             build_tensor(ctx, t, d_i, d_j, d_k, d_val);
         } catch (...) {
+            // copies into the tensor's host fields may still be pending
+            (void)hipStreamSynchronize(ctx->stream);
             dfacto_tensor_destroy(t);
             throw;
         }

@@ -14,10 +14,11 @@
 //     runs one CP-ALS iteration (Algorithm 2) of every active request as a
 //     group (grouped launches, one group per storage dtype and ridge value),
 //     reads the fits and retires every request whose fit changed by less
-//     than its tolerance or that reached its iteration cap: factors and
-//     lambda are copied to the caller's host buffers and its memory is
-//     released (stream-ordered, without waiting for the other requests'
-//     work), which frees its slot and bytes for the next queued requests.
+//     than its tolerance or that reached its iteration cap.
+//   - A delivery thread copies a retired request's factors and lambda to the
+//     caller's host buffers and releases its memory (stream-ordered, without
+//     waiting for the other requests' work), which frees its slot and bytes
+//     for the next queued requests.
 // Requests that arrive while others run join at the next boundary after
 // their build, so work of different requests overlaps on the device.  A member's arithmetic does
 // not depend on the other members (grouped launches reproduce the
@@ -86,11 +87,13 @@ struct dfacto_server {
     Clock::time_point t0;
 
     std::mutex mu;
-    std::condition_variable cv_work, cv_build, cv_done;
+    std::condition_variable cv_work, cv_build, cv_deliver, cv_done;
     bool stop = false;
     int64_t next_id = 1;
     std::deque<std::unique_ptr<Member>> pending;  // submitted, not yet admitted
     std::deque<std::unique_ptr<Member>> ready;    // built, not yet attached
+    std::deque<std::unique_ptr<Member>> retired;  // stopped, results not yet delivered
+    bool worker_done = false;
     std::map<int64_t, dfacto_request_status> finished;  // id -> final status
     std::map<int64_t, int> running;                     // ids admitted and not yet done
     int slots = 0;     // requests admitted and not yet retired (building, ready or active)
@@ -104,7 +107,7 @@ struct dfacto_server {
     std::vector<dfacto_group *> groups;  // over `active`, rebuilt when it changes
     bool dirty = true;
     double *d_fits = nullptr;  // max_slots doubles
-    std::thread worker, builder[kBuilders];
+    std::thread worker, deliverer, builder[kBuilders];
 };
 
 namespace {
@@ -346,6 +349,33 @@ void builder_main(dfacto_server *s, int b) {
     }
 }
 
+void deliverer_main(dfacto_server *s) {
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        std::unique_ptr<Member> m;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_deliver.wait(lk, [&] { return !s->retired.empty() || s->worker_done; });
+            if (s->retired.empty()) return;  // the worker has ended and nothing is left
+            m = std::move(s->retired.front());
+            s->retired.pop_front();
+        }
+        dfacto_status code = DFACTO_OK;
+        const auto td = Clock::now();
+        try {
+            deliver(s, *m);
+        } catch (const Error &e) {
+            code = e.code;
+        }
+        free_member(*m);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->t_deliver += std::chrono::duration<double>(Clock::now() - td).count();
+        }
+        finish(s, std::move(m), code);
+    }
+}
+
 void worker_main(dfacto_server *s) {
     (void)hipSetDevice(s->device);
     std::deque<std::unique_ptr<Member>> arrived;
@@ -357,7 +387,11 @@ void worker_main(dfacto_server *s) {
                 return (s->stop && s->pending.empty() && s->slots == 0) || !s->ready.empty() ||
                        !s->active.empty();
             });
-            if (s->active.empty() && s->ready.empty()) return;  // stopping, all done
+            if (s->active.empty() && s->ready.empty()) {  // stopping, all done
+                s->worker_done = true;
+                s->cv_deliver.notify_all();
+                return;
+            }
             arrived.swap(s->ready);
         }
         if (!arrived.empty()) {
@@ -385,8 +419,7 @@ void worker_main(dfacto_server *s) {
                                   s->stream));
             DF_HIP(hipStreamSynchronize(s->stream));
             const double titer = std::chrono::duration<double>(Clock::now() - ti).count() - tg;
-            double tdel = 0;
-            std::vector<std::unique_ptr<Member>> keep;
+            std::vector<std::unique_ptr<Member>> keep, done;
             for (size_t a = 0; a < s->active.size(); ++a) {
                 std::unique_ptr<Member> &m = s->active[a];
                 m->st.iters += 1;
@@ -395,27 +428,21 @@ void worker_main(dfacto_server *s) {
                 m->prev_fit = fits[a];
                 m->has_prev = true;
                 if (conv || m->st.iters >= m->req.max_iters) {
+                    // the groups read its memory: drop them before delivery frees it
                     if (!s->groups.empty()) drop_groups(s);
-                    dfacto_status code = DFACTO_OK;
-                    const auto td = Clock::now();
-                    try {
-                        deliver(s, *m);
-                    } catch (const Error &e) {
-                        code = e.code;
-                    }
-                    free_member(*m);
-                    tdel += std::chrono::duration<double>(Clock::now() - td).count();
-                    finish(s, std::move(m), code);
+                    done.push_back(std::move(m));
                 } else {
                     keep.push_back(std::move(m));
                 }
             }
             s->active.swap(keep);
             std::lock_guard<std::mutex> lk(s->mu);
+            for (auto &m : done) s->retired.push_back(std::move(m));
+            done.clear();
+            if (!s->retired.empty()) s->cv_deliver.notify_one();
             ++s->iterations;
             s->t_groups += tg;
             s->t_iterate += titer;
-            s->t_deliver += tdel;
         } catch (const Error &e) {
             // a device failure ends every active request with its code
             drop_groups(s);
@@ -482,6 +509,7 @@ dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
     }
     if (prev >= 0) (void)hipSetDevice(prev);
     s->worker = std::thread(worker_main, s);
+    s->deliverer = std::thread(deliverer_main, s);
     for (int b = 0; b < dfacto_server::kBuilders; ++b) s->builder[b] = std::thread(builder_main, s, b);
     *out = s;
     return DFACTO_OK;
@@ -558,6 +586,7 @@ void dfacto_server_destroy(dfacto_server *s) {
     for (auto &b : s->builder)
         if (b.joinable()) b.join();
     if (s->worker.joinable()) s->worker.join();
+    if (s->deliverer.joinable()) s->deliverer.join();
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
