@@ -186,6 +186,25 @@ def run_served(args):
     and batched continuously.  Reported per storage dtype: completed solves
     per second over the run and p50 / p99 latency from submission to factors
     on the host."""
+    dts = args.served_dtypes.split(",")
+    if len(dts) > 1:
+        # one fresh process per storage dtype, as a server starts: consecutive
+        # servers in one process were measured to run slower
+        import subprocess
+        out, n = {}, 0
+        for dt in dts:
+            cmd = [sys.executable, "-u", os.path.abspath(__file__), "--workload", "served",
+                   "--served-dtypes", dt, "--rate", str(args.rate), "--duration",
+                   str(args.duration), "--large-frac", str(args.large_frac), "--pool",
+                   str(args.pool)]
+            r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+            if r.returncode != 0:
+                raise SystemExit(f"served run for {dt} failed with exit status {r.returncode}")
+            child = json.loads(r.stdout.strip().splitlines()[-1])
+            out[dt] = child["extra"][dt]
+            n = child["steps"]
+        served_line(args, n, out)
+        return
     import numpy as np
     from paper_1406_4519_amd import dfacto, gen
 
@@ -206,7 +225,7 @@ def run_served(args):
     picks = [big if (big is not None and rng.random() < args.large_frac)
              else pool[int(rng.integers(len(pool)))] for _ in range(n)]
     out = {}
-    for dt in ("f32", "bf16"):
+    for dt in args.served_dtypes.split(","):
         srv = dfacto.Server(0, max_slots=64)
         ids = []
         start = time.perf_counter()
@@ -229,15 +248,19 @@ def run_served(args):
                        peak_active=st["peak_active"], boundaries=st["iterations"],
                        large_requests=len(big_lat),
                        large_p50_ms=float(np.percentile(big_lat, 50) * 1e3) if big_lat else None,
-                       span_s=span, worker_s={k: round(st[k], 3) for k in
+                       span_s=span, budget_gb=round(st["budget"] / 1e9, 1), worker_s={k: round(st[k], 3) for k in
                                               ("t_admit", "t_build", "t_groups", "t_iterate", "t_deliver")})
         log(f"{dt}: {out[dt]}")
-    f = out["f32"]
+    served_line(args, n, out)
+
+
+def served_line(args, n, out):
+    f = out["f32"] if "f32" in out else next(iter(out.values()))
     line = {"metric": "served CP-ALS solves/s, p50/p99 latency",
             "value": f["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": n,
             "warmup": 0, "ms_per_step": round(f["span_s"] * 1e3 / n, 4),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-            "data": "synthetic",
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if "f32" in out else next(iter(out)), "data": "synthetic",
             "config": {"workload": f"served: Poisson {args.rate:g}/s for {args.duration:g}s, "
                                    f"batched-distribution solves + {args.large_frac:g} 50M-nonzero "
                                    f"1M x 500K x 200K requests, fit change < 1e-4 or 50 "
@@ -346,6 +369,8 @@ def main():
     ap.add_argument("--large-frac", type=float, default=0.05,
                     help="served workload: fraction of 50M-nonzero requests")
     ap.add_argument("--pool", type=int, default=48, help="served workload: distinct small tensors")
+    ap.add_argument("--served-dtypes", default="f32,bf16",
+                    help="served workload: factor storage dtypes, run in this order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-factor side run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

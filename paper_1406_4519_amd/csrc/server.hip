@@ -44,19 +44,30 @@ namespace {
 using namespace dfacto;
 using Clock = std::chrono::steady_clock;
 
-uint16_t host_f32_to_bf16(float f) {  // nearest, ties to even (NaN kept quiet)
-    uint32_t b;
-    std::memcpy(&b, &f, 4);
-    if ((b & 0x7F800000u) == 0x7F800000u) return (uint16_t)((b >> 16) | ((b & 0xFFFFu) ? 0x40u : 0u));
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
+// FP32 -> BF16, nearest with ties to even (a NaN stays a quiet NaN)
+__global__ void k_f32_to_bf16(const float *__restrict__ in, uint16_t *__restrict__ out,
+                              int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t b = __float_as_uint(in[e]);
+        if ((b & 0x7F800000u) == 0x7F800000u) {
+            out[e] = (uint16_t)((b >> 16) | ((b & 0xFFFFu) ? 0x40u : 0u));
+        } else {
+            b += 0x7FFFu + ((b >> 16) & 1u);
+            out[e] = (uint16_t)(b >> 16);
+        }
+    }
 }
 
-float host_bf16_to_f32(uint16_t h) {
-    const uint32_t b = (uint32_t)h << 16;
-    float f;
-    std::memcpy(&f, &b, 4);
-    return f;
+__global__ void k_bf16_to_f32(const uint16_t *__restrict__ in, float *__restrict__ out,
+                              int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = __uint_as_float((uint32_t)in[e] << 16);
+}
+
+unsigned convert_grid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
 }
 
 struct Member {
@@ -81,6 +92,7 @@ struct dfacto_server {
     int max_slots = 1;
     dfacto_ctx *ctx = nullptr;  // the worker's context (own stream)
     hipStream_t stream = nullptr;
+    hipStream_t dstream = nullptr;  // the delivery thread's stream
     static constexpr int kBuilders = 2;
     dfacto_ctx *bctx[kBuilders] = {};  // the builders' contexts (own streams)
     hipStream_t bstream[kBuilders] = {};
@@ -198,15 +210,18 @@ void admit(dfacto_server *s, int b, Member &m, double *t_build) {
         di = dj = dk = nullptr;
         dv = nullptr;
         const size_t es = r.dtype == DFACTO_BF16 ? 2 : 4;
-        std::vector<uint16_t> h[3];  // BF16 staging, alive until the stream is done
         for (int k = 0; k < 3; ++k) {
             const size_t cnt = (size_t)r.dims[k] * r.R;
             hip_check(hipMallocAsync(&m.F[k], std::max<size_t>(es * cnt, 16), st),
                       "factor allocation");
-            if (r.dtype == DFACTO_BF16) {
-                h[k].resize(cnt);
-                for (size_t e = 0; e < cnt; ++e) h[k][e] = host_f32_to_bf16(r.init[k][e]);
-                DF_HIP(hipMemcpyAsync(m.F[k], h[k].data(), 2 * cnt, hipMemcpyHostToDevice, st));
+            if (r.dtype == DFACTO_BF16) {  // FP32 upload, rounded to BF16 on the device
+                float *tmp = nullptr;
+                hip_check(hipMallocAsync((void **)&tmp, 4 * cnt, st), "factor staging");
+                DF_HIP(hipMemcpyAsync(tmp, r.init[k], 4 * cnt, hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_f32_to_bf16, dim3(convert_grid((int64_t)cnt)), dim3(256), 0,
+                                   st, tmp, (uint16_t *)m.F[k], (int64_t)cnt);
+                DF_LAUNCHED();
+                DF_HIP(hipFreeAsync(tmp, st));
             } else {
                 DF_HIP(hipMemcpyAsync(m.F[k], r.init[k], 4 * cnt, hipMemcpyHostToDevice, st));
             }
@@ -222,22 +237,38 @@ void admit(dfacto_server *s, int b, Member &m, double *t_build) {
     }
 }
 
-// Copy a finished request's factors and lambda to its host buffers.
+// Copy a finished request's factors (BF16 widened to FP32 on the device) and
+// lambda to its host buffers, on the delivery stream.
 void deliver(dfacto_server *s, Member &m) {
     const dfacto_request &r = m.req;
-    for (int k = 0; k < 3; ++k) {
-        const size_t cnt = (size_t)r.dims[k] * r.R;
-        if (!r.out_F[k]) continue;
-        if (r.dtype == DFACTO_BF16) {
-            std::vector<uint16_t> h(cnt);
-            DF_HIP(hipMemcpy(h.data(), m.F[k], 2 * cnt, hipMemcpyDeviceToHost));
-            for (size_t e = 0; e < cnt; ++e) r.out_F[k][e] = host_bf16_to_f32(h[e]);
-        } else {
-            DF_HIP(hipMemcpy(r.out_F[k], m.F[k], 4 * cnt, hipMemcpyDeviceToHost));
+    hipStream_t st = s->dstream;
+    std::vector<float *> tmps;
+    try {
+        for (int k = 0; k < 3; ++k) {
+            const size_t cnt = (size_t)r.dims[k] * r.R;
+            if (!r.out_F[k]) continue;
+            if (r.dtype == DFACTO_BF16) {
+                float *tmp = nullptr;
+                hip_check(hipMallocAsync((void **)&tmp, 4 * cnt, st), "result staging");
+                tmps.push_back(tmp);
+                hipLaunchKernelGGL(k_bf16_to_f32, dim3(convert_grid((int64_t)cnt)), dim3(256), 0,
+                                   st, (const uint16_t *)m.F[k], tmp, (int64_t)cnt);
+                DF_LAUNCHED();
+                DF_HIP(hipMemcpyAsync(r.out_F[k], tmp, 4 * cnt, hipMemcpyDeviceToHost, st));
+            } else {
+                DF_HIP(hipMemcpyAsync(r.out_F[k], m.F[k], 4 * cnt, hipMemcpyDeviceToHost, st));
+            }
         }
+        if (r.out_lambda)
+            DF_HIP(hipMemcpyAsync(r.out_lambda, m.lambda, 8 * (size_t)r.R, hipMemcpyDeviceToHost,
+                                  st));
+        for (float *p : tmps) (void)hipFreeAsync(p, st);
+        DF_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+        for (float *p : tmps) (void)hipFreeAsync(p, st);
+        (void)hipStreamSynchronize(st);
+        throw;
     }
-    if (r.out_lambda) DF_HIP(hipMemcpy(r.out_lambda, m.lambda, 8 * (size_t)r.R, hipMemcpyDeviceToHost));
-    (void)s;
 }
 
 void drop_groups(dfacto_server *s) {
@@ -478,10 +509,17 @@ dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
         delete s;
         return DFACTO_E_DEVICE;
     }
+    if (hipStreamCreateWithFlags(&s->dstream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        return DFACTO_E_DEVICE;
+    }
     for (int b = 0; b < dfacto_server::kBuilders; ++b)
         if (hipStreamCreateWithFlags(&s->bstream[b], hipStreamNonBlocking) != hipSuccess) {
             (void)hipGetLastError();
             for (int c = 0; c < b; ++c) (void)hipStreamDestroy(s->bstream[c]);
+            (void)hipStreamDestroy(s->dstream);
             (void)hipStreamDestroy(s->stream);
             delete s;
             return DFACTO_E_DEVICE;
@@ -503,6 +541,7 @@ dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
             (void)hipStreamDestroy(s->bstream[b]);
         }
         if (s->d_fits) (void)hipFree(s->d_fits);
+        (void)hipStreamDestroy(s->dstream);
         (void)hipStreamDestroy(s->stream);
         delete s;
         return DFACTO_E_DEVICE;
@@ -599,7 +638,12 @@ void dfacto_server_destroy(dfacto_server *s) {
         (void)hipStreamSynchronize(s->bstream[b]);  // stream-ordered frees
         (void)hipStreamDestroy(s->bstream[b]);
     }
+    if (s->dstream) (void)hipStreamDestroy(s->dstream);
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    // give the stream-ordered memory the server freed back to the device
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess && pool)
+        (void)hipMemPoolTrimTo(pool, 0);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete s;
 }

@@ -73,14 +73,20 @@ def test_served_results_same_alone_and_in_mix(requests):
         _same(a, b)
 
 
-def test_served_result_equals_repeated_als_iter(requests):
-    r = requests[1]
+@pytest.mark.parametrize("which", [1, 2])  # an FP32 and a BF16 request
+def test_served_result_equals_repeated_als_iter(requests, which):
+    """The served solve equals dfacto_als_iter repeated on the request alone;
+    for BF16 storage the server's rounding of the initial factors is torch's
+    (nearest, ties to even) and its widening of the results is exact."""
+    r = requests[which]
     res = _alone([r])[0]
     c = r["coo"]
     ctx = dfacto.Context(0)
-    from gpu_util import build, factors_to_dev
+    from gpu_util import build
     t = build(ctx, c)
     F = [torch.from_numpy(f.copy()).to(DEV) for f in r["init"]]
+    if r["dtype"] == "bf16":
+        F = [f.to(torch.bfloat16) for f in F]
     lam = torch.zeros(r["R"], dtype=torch.float64, device=DEV)
     fit = torch.zeros(1, dtype=torch.float64, device=DEV)
     for _ in range(res["iters"]):
@@ -88,7 +94,7 @@ def test_served_result_equals_repeated_als_iter(requests):
     torch.cuda.synchronize()
     assert fit.item() == res["fit"]
     for m in range(3):
-        assert np.array_equal(F[m].cpu().numpy(), res["factors"][m])
+        assert np.array_equal(F[m].float().cpu().numpy(), res["factors"][m])
     assert np.array_equal(lam.cpu().numpy(), res["lam"])
     t.close()
     ctx.close()
