@@ -271,26 +271,28 @@ def served_line(args, n, out):
 
 
 def run_paper(args):
-    """Paper-shape tensor on one GPU: 6.5M x 2.5M x 1.5M, 1.5B coordinates
-    drawn from Zipf(1.2) per mode (|N(0,1)| FP32 values; duplicates are
-    summed by the flattening build, leaving the distinct nonzeros); for
-    R = 10 and 32 and FP32 / BF16 factor storage: one CP-ALS iteration plus
-    one GD gradient (6 MTTKRPs) after one warm-up step.  value = FP32, R = 32
-    MTTKRP throughput of the step (6 nnz R per step time)."""
+    """Paper-shape tensor on one GPU: 6.5M x 2.5M x 1.5M with 1.2B distinct
+    coordinates, Zipf(1.2) per mode over seeded permutations, |N(0,1)| FP32
+    values (generated and deduplicated on the device); for R = 10 and 32 and
+    FP32 / BF16 factor storage: one CP-ALS iteration plus one GD gradient
+    (6 MTTKRPs) after one warm-up step.  value = FP32, R = 32 MTTKRP
+    throughput of the step (6 nnz R per step time)."""
     import numpy as np
     import torch
     from paper_1406_4519_amd import dfacto, gen
 
     dev = torch.device("cuda:0")
+    dims = (6_500_000, 2_500_000, 1_500_000)
     t0 = time.perf_counter()
-    coo = gen.zipf_draws((6_500_000, 2_500_000, 1_500_000), 1_500_000_000, 1.2, seed=3,
-                         progress=lambda m: log(f"  [{time.perf_counter() - t0:.0f}s] {m}"))
-    log(f"drew {coo.nnz:,} coordinates in {time.perf_counter() - t0:.1f}s")
+    i, j, k, v = gen.zipf_distinct_torch(
+        dims, args.paper_nnz, 1.2, seed=3, device=dev, batch=1 << 28,
+        progress=lambda m: log(f"  [{time.perf_counter() - t0:.0f}s] {m}"))
+    arrs = [i, j, k]
+    del i, j, k
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"generated {args.paper_nnz:,} distinct coordinates in {time.perf_counter() - t0:.1f}s")
     ctx = dfacto.Context(0)
-    arrs = [torch.from_numpy(x.view(np.int32)).to(dev) for x in (coo.i, coo.j, coo.k)]
-    v = torch.from_numpy(coo.val).to(dev)
-    dims, nnz = coo.dims, coo.nnz
-    del coo
     torch.cuda.synchronize()
     tb = time.perf_counter()
     T = dfacto.build_flattenings(ctx, dims, *arrs, v)
@@ -341,9 +343,9 @@ def run_paper(args):
             "steps": 1, "warmup": 1, "ms_per_step": round(r["als_iter_ms"] + r["gd_grad_ms"], 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
-            "config": {"workload": "paper shape: 6.5M x 2.5M x 1.5M, 1.5B Zipf(1.2) draws "
-                                   "(duplicates summed), FP32 values; R = 32 (also R = 10) FP32 "
-                                   "and BF16 factors; one CP-ALS iteration + one GD gradient",
+            "config": {"workload": "paper shape: 6.5M x 2.5M x 1.5M, 1.2B distinct Zipf(1.2) "
+                                   "coordinates, FP32 values; R = 32 (also R = 10) FP32 and BF16 "
+                                   "factors; one CP-ALS iteration + one GD gradient",
                        "nnz": nnz, "nfib": list(info["nfib"]), "parallelism": "single GPU"},
             "roofline": {"bound": "hbm", "achieved": r["mttkrp_GBs"], "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": r["hbm_frac"], "traffic": None},
@@ -369,6 +371,8 @@ def main():
     ap.add_argument("--large-frac", type=float, default=0.05,
                     help="served workload: fraction of 50M-nonzero requests")
     ap.add_argument("--pool", type=int, default=48, help="served workload: distinct small tensors")
+    ap.add_argument("--paper-nnz", type=int, default=1_200_000_000,
+                    help="paper1200m workload: distinct nonzeros")
     ap.add_argument("--served-dtypes", default="f32,bf16",
                     help="served workload: factor storage dtypes, run in this order")
     ap.add_argument("--no-cpu-baseline", action="store_true")

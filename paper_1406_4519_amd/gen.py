@@ -20,6 +20,12 @@ size and skew):
   drawn independently; draws continue until ``nnz`` *distinct* coordinates
   exist and the first draw of a coordinate supplies its value.  Values are
   |N(0,1)| rounded to FP32 (the paper's tensors hold positive counts).
+* ``zipf_distinct_torch``: the same per-mode Zipf(s) draw for tensors too
+  large to deduplicate on the host (the 1.2B-nonzero paper shape), in torch
+  on a given device (``torch.Generator``, Philox on the GPU): draws continue
+  in batches until at least ``nnz`` distinct coordinates exist, then a
+  seeded uniform choice of exactly ``nnz`` of them is kept; values |N(0,1)|
+  FP32.  Its stream differs from the numpy recipes and between devices.
 * ``planted_dense`` / ``planted_sparse``: exact low-rank tensors
   sum_r a_r o b_r o c_r with every entry of the (union) support stored.
 * ``init_factors``: U(0, 1) in FP64, drawn in the order A, B, C.
@@ -201,6 +207,79 @@ def zipf_draws(dims, n: int, s: float, seed: int, progress=None) -> Coo:
     finally:
         pool.shutdown()
     return Coo(tuple(int(d) for d in dims), idx[0], idx[1], idx[2], val)
+
+
+def zipf_distinct_torch(dims, nnz: int, s: float, seed: int, device="cpu",
+                        batch: int = 1 << 27, max_key_bits: int = 63, progress=None):
+    """nnz distinct coordinates with Zipf(s) marginals over a seeded
+    permutation of each mode, generated with torch on ``device``.
+
+    Coordinates are deduplicated as integer keys.  When I*J*K does not fit
+    ``max_key_bits`` bits the coordinates are split into classes by
+    i mod ncls and each class keys (i // ncls, j, k), so every key fits.
+    Returns (i, j, k) as int32 tensors and |N(0,1)| FP32 values on
+    ``device``, sorted by (class, key)."""
+    import torch
+
+    dev = torch.device(device)
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed))
+    I, J, K = (int(d) for d in dims)
+    if nnz > I * J * K:
+        raise ValueError("more distinct coordinates than cells")
+    cdfs = [torch.from_numpy(zipf_cdf(d, s)).to(dev) for d in (I, J, K)]
+    perms = [torch.randperm(d, generator=g, device=dev) for d in (I, J, K)]
+    JK = J * K
+    lim = (1 << max_key_bits) - 1
+    if JK - 1 > lim:
+        raise ValueError("J*K exceeds the key range")
+    ncls = 1
+    while ((I + ncls - 1) // ncls) * JK - 1 > lim:
+        ncls += 1
+    uniq = [torch.empty(0, dtype=torch.int64, device=dev) for _ in range(ncls)]
+    total, drawn = 0, 0
+    while total < nnz:
+        idx = []
+        for m, d in enumerate((I, J, K)):
+            u = torch.rand(batch, generator=g, device=dev, dtype=torch.float64)
+            r = torch.searchsorted(cdfs[m], u, right=True).clamp_(max=d - 1)
+            del u
+            idx.append(perms[m][r])
+            del r
+        lo = idx[1] * K + idx[2]
+        cls = idx[0] % ncls
+        hi = idx[0] // ncls
+        del idx
+        for c in range(ncls):
+            sel = cls == c
+            uniq[c] = torch.unique(torch.cat([uniq[c], hi[sel] * JK + lo[sel]]))
+            del sel
+        del lo, cls, hi
+        drawn += batch
+        total = sum(int(x.numel()) for x in uniq)
+        if progress is not None:
+            progress(f"zipf draws: {drawn:,} drawn, {total:,} distinct")
+    # a seeded uniform choice of exactly nnz of the distinct coordinates
+    keep = torch.randperm(total, generator=g, device=dev)[:nnz].sort().values
+    ii, jj, kk = [], [], []
+    for c in range(ncls):
+        key = uniq[c]
+        uniq[c] = None
+        ii.append(((key // JK) * ncls + c).to(torch.int32))
+        rem = key % JK
+        del key
+        jj.append((rem // K).to(torch.int32))
+        kk.append((rem % K).to(torch.int32))
+        del rem
+    out = []
+    for parts in (ii, jj, kk):
+        a = torch.cat(parts)
+        parts.clear()
+        out.append(a[keep])
+        del a
+    del keep
+    val = torch.randn(nnz, generator=g, device=dev, dtype=torch.float32).abs_()
+    return out[0], out[1], out[2], val
 
 
 def planted_factors(dims, R: int, seed: int, density: float = 1.0):

@@ -58,3 +58,28 @@ def test_batched_specs_in_range():
         assert all(1000 <= d <= 100_000 for d in dims)
         assert 10_000 <= nnz <= 5_000_000 or nnz == (dims[0] * dims[1] * dims[2]) // 2
         assert R in (8, 16, 32)
+
+
+def test_zipf_distinct_torch_counts_classes_and_determinism():
+    """The torch recipe (used for the 1.2B-nonzero paper shape) gives exactly
+    nnz distinct in-range coordinates, deterministically, with and without
+    the split of the key space into classes."""
+    import torch
+
+    dims = (300, 200, 100)
+    for bits in (63, 16):  # 16 bits: keys split over i mod 100 classes
+        a = gen.zipf_distinct_torch(dims, 20_000, 1.1, seed=5, batch=4096, max_key_bits=bits)
+        b = gen.zipf_distinct_torch(dims, 20_000, 1.1, seed=5, batch=4096, max_key_bits=bits)
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+        i, j, k, v = a
+        assert i.dtype == torch.int32 and v.dtype == torch.float32 and i.numel() == 20_000
+        assert 0 <= int(i.min()) and int(i.max()) < dims[0]
+        assert 0 <= int(j.min()) and int(j.max()) < dims[1]
+        assert 0 <= int(k.min()) and int(k.max()) < dims[2]
+        lin = (i.long() * dims[1] + j.long()) * dims[2] + k.long()
+        assert torch.unique(lin).numel() == 20_000
+        assert bool((v >= 0).all())
+    # skew: the most frequent mode-0 index holds far more than a uniform share
+    counts = torch.bincount(a[0].long(), minlength=dims[0])
+    assert int(counts.max()) > 5 * 20_000 / dims[0]
