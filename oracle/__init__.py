@@ -57,6 +57,13 @@ def _load():
         lib.oracle_gd_grad.argtypes = [i64, P, P, P, P, P, ctypes.c_int, ctypes.c_double,
                                        P, P, P, P, P, P]
         lib.oracle_gd_grad.restype = ctypes.c_double
+        lib.oracle_objective.argtypes = [i64, P, P, P, P, P, ctypes.c_int, ctypes.c_double,
+                                         P, P, P]
+        lib.oracle_objective.restype = ctypes.c_double
+        lib.oracle_gd_step.argtypes = [i64, P, P, P, P, P, ctypes.c_int, ctypes.c_double,
+                                       P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int, ctypes.c_int, P]
+        lib.oracle_gd_step.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -175,3 +182,33 @@ def gd_grad(i, j, k, val, dims, factors, reg: float = 0.0):
     f = lib.oracle_gd_grad(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), R, float(reg),
                            _p(A), _p(B), _p(C), _p(g[0]), _p(g[1]), _p(g[2]))
     return tuple(g), float(f)
+
+
+def objective(i, j, k, val, dims, factors, reg: float = 0.0) -> float:
+    """GD objective f at one point (unit weights)."""
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    A, B, C = (_f64(f) for f in factors)
+    d = np.asarray(dims, dtype=np.int64)
+    return float(lib.oracle_objective(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), A.shape[1],
+                                      float(reg), _p(A), _p(B), _p(C)))
+
+
+def gd_step(i, j, k, val, dims, factors, reg: float = 0.0, alpha0: float = 1.0,
+            shrink: float = 0.5, c: float = 1e-4, max_trials: int = 30, store: str = "f64"):
+    """One GD iteration with an Armijo backtracking line search.  Returns
+    (A, B, C, info) with new arrays; info = dict(f0, f, gnorm2, alpha, trials,
+    accepted).  store="bf16": trial factors are rounded to BF16 storage."""
+    if store not in ("f64", "bf16"):
+        raise ValueError("store must be 'f64' or 'bf16'")
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    A, B, C = (np.array(f, dtype=np.float64, order="C", copy=True) for f in factors)
+    d = np.asarray(dims, dtype=np.int64)
+    out = np.zeros(5, np.float64)
+    acc = lib.oracle_gd_step(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), A.shape[1], float(reg),
+                             _p(A), _p(B), _p(C), float(alpha0), float(shrink), float(c),
+                             int(max_trials), 1 if store == "bf16" else 0, _p(out))
+    info = dict(f0=float(out[0]), f=float(out[1]), gnorm2=float(out[2]), alpha=float(out[3]),
+                trials=int(out[4]), accepted=bool(acc))
+    return A, B, C, info

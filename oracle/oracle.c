@@ -24,6 +24,8 @@
  *     update  A <- X1 (C kr B) (C^T C * B^T B + reg I)^{-1}  (ridge form).
  *   - Appendix C: GD objective f = 1/2 ||X - [[A,B,C]]||^2 (+ ridge), and
  *       dF/dA = -X1 (C kr B) + A (C^T C * B^T B + reg I).
+ *   - Algorithm 5 (Appendix E, DFacTo with GD): the three gradients at one
+ *     point, a backtracking line search, the simultaneous update.
  *
  * Mode numbering is 0-based: mode 0 is the paper's mode 1 (output rows i),
  * mode 1 is the paper's mode 2 (rows j), mode 2 the paper's mode 3 (rows k).
@@ -538,4 +540,87 @@ double oracle_gd_grad(int64_t nnz, const uint32_t *i, const uint32_t *j,
     for (int m = 0; m < 3; ++m) free(Gm[m]);
     free(H);
     return 0.5 * (x2 - 2.0 * inner + xhat2) + 0.5 * reg * fro2;
+}
+
+/* GD objective at one point (Appendix C, unit weights), from its definition
+ * through the identity ||[[A,B,C]]||^2 = sum(G_A * G_B * G_C) (Appendix A):
+ *   f = 1/2 (||X||^2 - 2 <X, [[A,B,C]]> + ||[[A,B,C]]||^2)
+ *       + 1/2 reg (||A||^2 + ||B||^2 + ||C||^2). */
+double oracle_objective(int64_t nnz, const uint32_t *i, const uint32_t *j,
+                        const uint32_t *k, const double *val, const int64_t *dims, int R,
+                        double reg, const double *A, const double *B, const double *C)
+{
+    const double *F[3] = {A, B, C};
+    double *Gm[3];
+    for (int m = 0; m < 3; ++m) {
+        Gm[m] = (double *)malloc(sizeof(double) * (size_t)R * R);
+        gram(dims[m], R, F[m], Gm[m]);
+    }
+    double xhat2 = 0.0, fro2 = 0.0;
+    for (int t = 0; t < R * R; ++t) xhat2 += Gm[0][t] * Gm[1][t] * Gm[2][t];
+    for (int m = 0; m < 3; ++m)
+        for (int r = 0; r < R; ++r) fro2 += Gm[m][r * R + r];
+    for (int m = 0; m < 3; ++m) free(Gm[m]);
+    const double x2 = oracle_normsq(nnz, i, j, k, val);
+    const double inner = oracle_inner(nnz, i, j, k, val, R, A, B, C, NULL);
+    return 0.5 * (x2 - 2.0 * inner + xhat2) + 0.5 * reg * fro2;
+}
+
+/* One full GD iteration of DFacTo (Algorithm 5 / Algorithm 3): the three
+ * gradients at the same point (oracle_gd_grad), then a backtracking line
+ * search, then the simultaneous update of A, B and C.  The paper names a
+ * backtracking line search without its constants; here (Armijo): trial
+ * steps alpha = alpha0 * shrink^t, t = 0 .. max_trials - 1, with trial
+ * factors F_m - alpha grad_m (rounded to BF16 storage when store_bf16), and
+ * the first trial with
+ *   f(trial) <= f(F) - c * alpha * (||grad_A||^2 + ||grad_B||^2 + ||grad_C||^2)
+ * is taken.  If no trial passes, the factors are left unchanged.
+ * A, B, C are updated in place.  out[0] = f at the input, out[1] = f at the
+ * returned factors, out[2] = the squared gradient norm, out[3] = the step
+ * taken (0 if none), out[4] = trials evaluated.  Returns 1 if a step was
+ * taken. */
+int oracle_gd_step(int64_t nnz, const uint32_t *i, const uint32_t *j, const uint32_t *k,
+                   const double *val, const int64_t *dims, int R, double reg, double *A,
+                   double *B, double *C, double alpha0, double shrink, double c,
+                   int max_trials, int store_bf16, double *out)
+{
+    double *F[3] = {A, B, C};
+    double *G[3], *T[3];
+    for (int m = 0; m < 3; ++m) {
+        G[m] = (double *)malloc(sizeof(double) * (size_t)dims[m] * R);
+        T[m] = (double *)malloc(sizeof(double) * (size_t)dims[m] * R);
+    }
+    const double f0 = oracle_gd_grad(nnz, i, j, k, val, dims, R, reg, A, B, C, G[0], G[1], G[2]);
+    double g2 = 0.0;
+    for (int m = 0; m < 3; ++m)
+        for (int64_t e = 0; e < dims[m] * R; ++e) g2 += G[m][e] * G[m][e];
+    double alpha = alpha0, f = f0;
+    int trials = 0, taken = 0;
+    for (int t = 0; t < max_trials; ++t) {
+        for (int m = 0; m < 3; ++m)
+            for (int64_t e = 0; e < dims[m] * R; ++e) {
+                const double x = F[m][e] - alpha * G[m][e];
+                T[m][e] = store_bf16 ? round_bf16(x) : x;
+            }
+        const double ft = oracle_objective(nnz, i, j, k, val, dims, R, reg, T[0], T[1], T[2]);
+        ++trials;
+        if (ft <= f0 - c * alpha * g2) {
+            for (int m = 0; m < 3; ++m)
+                memcpy(F[m], T[m], sizeof(double) * (size_t)dims[m] * R);
+            f = ft;
+            taken = 1;
+            break;
+        }
+        alpha *= shrink;
+    }
+    for (int m = 0; m < 3; ++m) {
+        free(G[m]);
+        free(T[m]);
+    }
+    out[0] = f0;
+    out[1] = f;
+    out[2] = g2;
+    out[3] = taken ? alpha : 0.0;
+    out[4] = (double)trials;
+    return taken;
 }
