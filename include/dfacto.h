@@ -319,6 +319,46 @@ void dfacto_server_destroy(dfacto_server *srv);
 /* measurement                                                          */
 /* ------------------------------------------------------------------ */
 
+/* One full GD iteration (Algorithm 5 of Appendix E; Algorithm 3 of
+ * Appendix C): the three gradients at the same point (as dfacto_gd_grad,
+ * written to d_G), then a backtracking line search, then the simultaneous
+ * update of the three factors.  The paper names a backtracking line search
+ * without giving its rule; this one is Armijo's: trial steps
+ * alpha = alpha0 * shrink^t for t = 0 .. max_trials - 1 form the trial
+ * factors F_m - alpha grad_m (in FP64 from the stored factor and the FP32
+ * gradient, stored in the factor dtype), and the first trial with
+ *     f(trial) <= f(F) - c * alpha * (||grad_A||^2 + ||grad_B||^2 + ||grad_C||^2)
+ * replaces the factors.  f(trial) is computed as in dfacto_gd_grad (three
+ * Grams, the mode-0 MTTKRP of the trial point, FP64 reductions).  If no
+ * trial passes, the factors are left unchanged and info->accepted = 0.
+ *
+ * d_F: in/out factors (layout and alignment as dfacto_gd_grad); d_G: the
+ * gradients at the input point (out); ls: host struct; info: host struct,
+ * filled on return.  The trial factors live in a context workspace
+ * (sum of the factor sizes plus one dims[0] x R FP32 buffer).  Synchronizes
+ * the stream once per trial (the test needs f on the host).  Errors: as
+ * dfacto_gd_grad, plus DFACTO_E_INVALID for a NULL ls or info, alpha0 <= 0
+ * or not finite, shrink or c outside (0, 1), max_trials outside [1, 1000]. */
+typedef struct {
+    double alpha0;   /* first trial step, > 0 */
+    double shrink;   /* step factor after a rejected trial, in (0, 1) */
+    double c;        /* sufficient-decrease constant, in (0, 1) */
+    int max_trials;  /* trials at most, in [1, 1000] */
+} dfacto_linesearch;
+
+typedef struct {
+    double f0;       /* objective at the input factors */
+    double f;        /* objective at the returned factors */
+    double gnorm2;   /* squared norm of the gradient (all three factors) */
+    double alpha;    /* step taken, 0 when no trial passed */
+    int trials;      /* trials evaluated */
+    int accepted;    /* 1 if the factors were updated */
+} dfacto_gd_step_info;
+
+dfacto_status dfacto_gd_step(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfacto_dtype dtype,
+                             double reg, void *const d_F[3], float *const d_G[3],
+                             const dfacto_linesearch *ls, dfacto_gd_step_info *info);
+
 /* Turn kernel timing on (1) or off (0) for `ctx`.  While on, every MTTKRP
  * launch (also those inside dfacto_als_iter and dfacto_gd_grad) records a
  * pair of HIP events on the context's stream around its main kernel, and

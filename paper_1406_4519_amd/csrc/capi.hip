@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 
@@ -71,12 +72,14 @@ int64_t max_dim(const dfacto_tensor *t) {
 // small FP64 workspace layout (units of doubles)
 struct Small {
     double *G[3], *Hinv, *W, *MtM, *solve_scratch, *lam_scratch, *H[3], *part0, *part_dummy;
+    double *GT[3], *HT, *part_t, *scal;  // GD step: trial Grams, trial H, partials, scalars
     int *flag;
 };
 
 Small small_ws(dfacto_ctx *ctx, int R) {
     const size_t RR = (size_t)R * R;
-    const size_t n = 3 * RR + 3 * RR + 3 * RR + (4 * RR + R) + 3 * RR + 2 * 8192 + 64;
+    const size_t n = 3 * RR + 3 * RR + 3 * RR + (4 * RR + R) + 3 * RR + 2 * 8192 + 4 * RR +
+                     8192 + 3 * kSumsqBlocks + 8 + 64;
     double *b = (double *)ws_get(ctx, dfacto_ctx::kSmall, sizeof(double) * n);
     Small s;
     size_t o = 0;
@@ -89,6 +92,10 @@ Small small_ws(dfacto_ctx *ctx, int R) {
     for (int m = 0; m < 3; ++m) s.H[m] = b + o, o += RR;
     s.part0 = b + o, o += 8192;
     s.part_dummy = b + o, o += 8192;
+    for (int m = 0; m < 3; ++m) s.GT[m] = b + o, o += RR;
+    s.HT = b + o, o += RR;
+    s.part_t = b + o, o += 8192;
+    s.scal = b + o, o += 3 * kSumsqBlocks + 8;  // partials, then gnorm2, f0, f_trial
     s.flag = (int *)(b + o);
     return s;
 }
@@ -348,6 +355,76 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfa
         launch_gd_f(ctx, R, sw.G[0], sw.G[1], sw.G[2], sw.part0,
                     gd_rows_partials(t->dims[0], R, d_G[0], d_F[0], dtype),
                     t->normsq, reg, d_f);
+    });
+}
+
+dfacto_status dfacto_gd_step(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfacto_dtype dtype,
+                             double reg, void *const d_F[3], float *const d_G[3],
+                             const dfacto_linesearch *ls, dfacto_gd_step_info *info) {
+    return guarded(ctx, [&] {
+        if (!ls || !info) throw Error{DFACTO_E_INVALID, "NULL argument"};
+        if (!(ls->alpha0 > 0.0) || !std::isfinite(ls->alpha0))
+            throw Error{DFACTO_E_INVALID, "alpha0 must be positive and finite"};
+        if (!(ls->shrink > 0.0 && ls->shrink < 1.0))
+            throw Error{DFACTO_E_INVALID, "shrink must be in (0, 1)"};
+        if (!(ls->c > 0.0 && ls->c < 1.0)) throw Error{DFACTO_E_INVALID, "c must be in (0, 1)"};
+        if (ls->max_trials < 1 || ls->max_trials > 1000)
+            throw Error{DFACTO_E_INVALID, "max_trials must be in [1, 1000]"};
+        check_common(t, R, dtype);
+        *info = dfacto_gd_step_info{};
+        // the gradient and f at the input point (validates the other arguments);
+        // the gradient call uses the same small workspace (same R: same buffer)
+        Small sw = small_ws(ctx, R);
+        double *d_gn2 = sw.scal + 3 * kSumsqBlocks, *d_f0 = d_gn2 + 1, *d_ft = d_gn2 + 2;
+        {
+            const dfacto_status st = dfacto_gd_grad(ctx, t, R, dtype, reg, d_F, d_G, d_f0);
+            if (st != DFACTO_OK) throw Error{st, ctx->err};
+        }
+        const int64_t n[3] = {t->dims[0] * R, t->dims[1] * R, t->dims[2] * R};
+        const float *g[3] = {d_G[0], d_G[1], d_G[2]};
+        launch_sumsq3(ctx, g, n, sw.scal, d_gn2);
+        // trial factors and the mode-0 MTTKRP of the trial point
+        const size_t es = elem_size(dtype);
+        size_t off[4], o = 0;
+        for (int m = 0; m < 3; ++m) off[m] = o, o += ((size_t)n[m] * es + 255) & ~(size_t)255;
+        off[3] = o, o += (size_t)n[0] * 4;
+        char *wt = (char *)ws_get(ctx, dfacto_ctx::kTrial, o);
+        void *T[3] = {wt + off[0], wt + off[1], wt + off[2]};
+        float *M = (float *)(wt + off[3]);
+        double host[2];
+        DF_HIP(hipMemcpyAsync(host, d_gn2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        DF_HIP(hipStreamSynchronize(ctx->stream));
+        const double gn2 = host[0], f0 = host[1];
+        info->f0 = f0;
+        info->f = f0;
+        info->gnorm2 = gn2;
+        const ModeData &md = t->mode[0];
+        double alpha = ls->alpha0;
+        for (int trial = 0; trial < ls->max_trials; ++trial) {
+            for (int m = 0; m < 3; ++m) launch_trial_factor(ctx, d_F[m], d_G[m], alpha, T[m], dtype, n[m]);
+            // f at the trial point, as in dfacto_gd_grad: Grams, the mode-0
+            // MTTKRP, <T_0, M> by the gradient-row pass, then the combination
+            for (int m = 0; m < 3; ++m) launch_gram(ctx, T[m], dtype, t->dims[m], R, sw.GT[m]);
+            launch_hadamard(ctx, R, sw.GT[1], sw.GT[2], reg, sw.HT);
+            launch_mttkrp(ctx, t, 0, R, dtype, T[md.leaf], T[md.mid], M);
+            launch_gd_rows(ctx, M, T[0], dtype, t->dims[0], R, sw.HT, sw.part_t);
+            launch_gd_f(ctx, R, sw.GT[0], sw.GT[1], sw.GT[2], sw.part_t,
+                        gd_rows_partials(t->dims[0], R, M, T[0], dtype), t->normsq, reg, d_ft);
+            double ft = 0.0;
+            DF_HIP(hipMemcpyAsync(&ft, d_ft, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+            DF_HIP(hipStreamSynchronize(ctx->stream));
+            info->trials = trial + 1;
+            if (ft <= f0 - ls->c * alpha * gn2) {  // Armijo: sufficient decrease
+                for (int m = 0; m < 3; ++m)
+                    DF_HIP(hipMemcpyAsync(d_F[m], T[m], (size_t)n[m] * es,
+                                          hipMemcpyDeviceToDevice, ctx->stream));
+                info->f = ft;
+                info->alpha = alpha;
+                info->accepted = 1;
+                break;
+            }
+            alpha *= ls->shrink;
+        }
     });
 }
 

@@ -914,6 +914,41 @@ __global__ __launch_bounds__(kBlock) void k_gd_f(int R, const double *__restrict
     if (threadIdx.x == 0) *f = 0.5 * (normsq - 2.0 * in + xh) + 0.5 * reg * tr;
 }
 
+// ---- GD step: trial factors and the squared gradient norm ----------------
+// out = F - alpha * G, formed in FP64 from the stored factor and the FP32
+// gradient, stored in the factor dtype (BF16: FP32 then nearest-even BF16)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_trial_factor(const T *__restrict__ F,
+                                                         const float *__restrict__ G, double alpha,
+                                                         T *__restrict__ out, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kBlock)
+        st_out<T>(out, e, ld<T>(F, e) - alpha * (double)G[e]);
+}
+
+// per-block partial sums of x^2 in FP64 (grid-stride, fixed order)
+__global__ __launch_bounds__(kBlock) void k_sumsq_f32(const float *__restrict__ x, int64_t n,
+                                                      double *__restrict__ part) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kBlock) {
+        const double v = (double)x[e];
+        acc += v * v;
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__ part, int n,
+                                                      double *__restrict__ out) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < n; b += kBlock) acc += part[b];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) *out = acc;
+}
+
 // 16-byte row loads are allowed when every row start is 16-byte aligned
 int vec_rows(const void *p, int R, int elem) {
     return ((uintptr_t)p % 16 == 0) && (((size_t)R * elem) % 16 == 0);
@@ -1358,6 +1393,32 @@ void launch_gd_f(dfacto_ctx *ctx, int R, const double *GA, const double *GB, con
                  double *f_out) {
     hipLaunchKernelGGL(k_gd_f, dim3(1), dim3(kBlock), 0, ctx->stream, R, GA, GB, GC, inner_partial,
                        npartial, normsq, reg, f_out);
+    DF_LAUNCHED();
+}
+
+unsigned stream_grid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
+}
+
+void launch_trial_factor(dfacto_ctx *ctx, const void *F, const float *G, double alpha, void *out,
+                         dfacto_dtype dtype, int64_t n) {
+    if (n <= 0) return;
+    if (dtype == DFACTO_F32)
+        hipLaunchKernelGGL(k_trial_factor<float>, dim3(stream_grid(n)), dim3(kBlock), 0,
+                           ctx->stream, (const float *)F, G, alpha, (float *)out, n);
+    else
+        hipLaunchKernelGGL(k_trial_factor<uint16_t>, dim3(stream_grid(n)), dim3(kBlock), 0,
+                           ctx->stream, (const uint16_t *)F, G, alpha, (uint16_t *)out, n);
+    DF_LAUNCHED();
+}
+
+void launch_sumsq3(dfacto_ctx *ctx, const float *const x[3], const int64_t n[3], double *part,
+                   double *out) {
+    for (int m = 0; m < 3; ++m)
+        hipLaunchKernelGGL(k_sumsq_f32, dim3(kSumsqBlocks), dim3(kBlock), 0, ctx->stream, x[m],
+                           n[m], part + m * kSumsqBlocks);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kBlock), 0, ctx->stream, part,
+                       3 * kSumsqBlocks, out);
     DF_LAUNCHED();
 }
 

@@ -133,9 +133,9 @@ struct dfacto_ctx {
     bool sticky = false;
     std::string err;
     // growable device workspace, one slot per purpose
-    enum Slot { kM = 0, kCarry, kPartial, kSmall, kNumSlots };
-    void *ws[kNumSlots] = {nullptr, nullptr, nullptr, nullptr};
-    size_t ws_size[kNumSlots] = {0, 0, 0, 0};
+    enum Slot { kM = 0, kCarry, kPartial, kSmall, kTrial, kNumSlots };
+    void *ws[kNumSlots] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t ws_size[kNumSlots] = {0, 0, 0, 0, 0};
     // kernel timing (dfacto_profile_*)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;  // created on demand, reused
@@ -211,6 +211,13 @@ void launch_gd_f(dfacto_ctx *ctx, int R, const double *GA, const double *GB, con
                  const double *inner_partial, int npartial, double normsq, double reg,
                  double *f_out);
 int gd_rows_partials(int64_t rows, int R, const float *G, const void *F, dfacto_dtype dtype);
+// GD step pieces: out = F - alpha G in the factor dtype; the FP64 sum of
+// squares of three FP32 arrays (part: 3 * kSumsqBlocks doubles)
+constexpr int kSumsqBlocks = 256;
+void launch_trial_factor(dfacto_ctx *ctx, const void *F, const float *G, double alpha, void *out,
+                         dfacto_dtype dtype, int64_t n);
+void launch_sumsq3(dfacto_ctx *ctx, const float *const x[3], const int64_t n[3], double *part,
+                   double *out);
 
 GramPlan gram_plan(int64_t rows, int R, const void *F, dfacto_dtype dtype);
 uint32_t gram_reduce_blocks(int R);

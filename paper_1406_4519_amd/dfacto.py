@@ -27,7 +27,7 @@ EXPORTS = (
     "dfacto_ctx_create", "dfacto_ctx_set_stream", "dfacto_ctx_synchronize", "dfacto_ctx_destroy",
     "dfacto_last_error", "dfacto_build_flattenings", "dfacto_tensor_get_info",
     "dfacto_tensor_export", "dfacto_tensor_destroy", "dfacto_mttkrp", "dfacto_als_iter",
-    "dfacto_gd_grad", "dfacto_group_create", "dfacto_group_als", "dfacto_group_get_info",
+    "dfacto_gd_grad", "dfacto_gd_step", "dfacto_group_create", "dfacto_group_als", "dfacto_group_get_info",
     "dfacto_group_destroy", "dfacto_server_create", "dfacto_server_submit", "dfacto_server_poll",
     "dfacto_server_wait", "dfacto_server_get_stats", "dfacto_server_destroy",
     "dfacto_profile_enable", "dfacto_profile_read",
@@ -46,6 +46,16 @@ class _Info(ctypes.Structure):
                 ("nfib", ctypes.c_int64 * 3), ("nroot", ctypes.c_int64 * 3),
                 ("nentry", ctypes.c_int64 * 3), ("nchunk", ctypes.c_int64 * 3),
                 ("normsq", ctypes.c_double), ("bytes", ctypes.c_size_t)]
+
+
+class _LineSearch(ctypes.Structure):
+    _fields_ = [("alpha0", ctypes.c_double), ("shrink", ctypes.c_double), ("c", ctypes.c_double),
+                ("max_trials", ctypes.c_int)]
+
+
+class _GdStepInfo(ctypes.Structure):
+    _fields_ = [("f0", ctypes.c_double), ("f", ctypes.c_double), ("gnorm2", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("trials", ctypes.c_int), ("accepted", ctypes.c_int)]
 
 
 class _GroupInfo(ctypes.Structure):
@@ -107,6 +117,8 @@ def load():
     lib.dfacto_mttkrp.argtypes = [P, P, I, I, I, PP, P]
     lib.dfacto_als_iter.argtypes = [P, P, I, I, D, PP, P, P]
     lib.dfacto_gd_grad.argtypes = [P, P, I, I, D, PP, PP, P]
+    lib.dfacto_gd_step.argtypes = [P, P, I, I, D, PP, PP, ctypes.POINTER(_LineSearch),
+                                   ctypes.POINTER(_GdStepInfo)]
     lib.dfacto_group_create.argtypes = [P, I, PP, ctypes.POINTER(ctypes.c_int), I, D, PP, PP, P,
                                         I, PP]
     lib.dfacto_group_als.argtypes = [P, P, I]
@@ -315,6 +327,23 @@ def gd_grad(ctx: Context, t: Tensor, factors, grads, f: torch.Tensor, reg: float
         raise ValueError("f must be a float64 CUDA tensor")
     ctx.check(load().dfacto_gd_grad(ctx.handle, t.handle, R, code, float(reg), _ptrs(factors),
                                     _ptrs(grads), _ptr(f)))
+
+
+def gd_step(ctx: Context, t: Tensor, factors, grads, reg: float = 0.0, alpha0: float = 1.0,
+            shrink: float = 0.5, c: float = 1e-4, max_trials: int = 30) -> dict:
+    """One GD iteration with an Armijo backtracking line search; the factors
+    are updated in place, grads receive the gradients at the input point.
+    Returns dict(f0, f, gnorm2, alpha, trials, accepted)."""
+    dims, R, code = _check_factors(t, factors)
+    for m, g in enumerate(grads):
+        if g.dtype != torch.float32 or not g.is_contiguous() or tuple(g.shape) != (dims[m], R):
+            raise ValueError("gradients must be contiguous float32 (dims[m], R) tensors")
+    ls = _LineSearch(float(alpha0), float(shrink), float(c), int(max_trials))
+    info = _GdStepInfo()
+    ctx.check(load().dfacto_gd_step(ctx.handle, t.handle, R, code, float(reg), _ptrs(factors),
+                                    _ptrs(grads), ctypes.byref(ls), ctypes.byref(info)))
+    return dict(f0=info.f0, f=info.f, gnorm2=info.gnorm2, alpha=info.alpha, trials=info.trials,
+                accepted=bool(info.accepted))
 
 
 class Group:

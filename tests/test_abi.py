@@ -24,6 +24,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_binding_declares_argument_types_of_every_export():
+    """Every exported function has ctypes argument types, so a Python value
+    of the wrong kind is refused instead of passed through."""
+    lib = dfacto.load()
+    for name in dfacto.EXPORTS:
+        assert getattr(lib, name).argtypes is not None, name
+
+
 def test_no_device_is_reported_as_error():
     import torch
     if torch.cuda.is_available():
