@@ -479,8 +479,22 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             mt_ms.append(e0.elapsed_time(e1) / reps)
+        fit_v, f_v = float(fit.item()), float(fval.item())
+        # full GD iterations (gradient + Armijo backtracking + update) from the
+        # initial factors: the first from alpha0 = 1, the next ones from twice
+        # the previous step
+        for m, f0 in enumerate(F0):
+            F[m].copy_(torch.from_numpy(np.ascontiguousarray(f0, dtype=np.float32)).to(dev).to(tdt))
+        gd_iters, a0 = [], 1.0
+        for _ in range(3):
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            inf = dfacto.gd_step(ctx, T, F, G, alpha0=a0, shrink=0.5, c=1e-4, max_trials=60)
+            gd_iters.append(dict(ms=round((time.perf_counter() - tg) * 1e3, 3),
+                                 trials=inf["trials"], alpha=inf["alpha"], f=inf["f"]))
+            a0 = 2.0 * inf["alpha"] if inf["accepted"] else a0
         return dict(elapsed=el, prof=prof, als_ms=als_ms, gd_ms=gd_ms, mttkrp_ms=mt_ms,
-                    fit=float(fit.item()), f=float(fval.item()))
+                    fit=fit_v, f=f_v, gd_iters=gd_iters)
 
     r32 = run("f32")
     nnz = info["nnz"]
@@ -500,7 +514,8 @@ def main():
              "gd_grad_ms": round(r32["gd_ms"], 3),
              "mttkrp_ms": [round(x, 4) for x in r32["mttkrp_ms"]],
              "mttkrp_nnzR_per_s": [round(nnz * R / (x * 1e-3)) for x in r32["mttkrp_ms"]],
-             "fit_after_timed_steps": r32["fit"], "nfib": list(info["nfib"]),
+             "fit_after_timed_steps": r32["fit"], "gd_iterations": r32["gd_iters"],
+             "nfib": list(info["nfib"]),
              "nroot": list(info["nroot"]), "nnz": nnz}
     if not args.no_bf16:
         rb = run("bf16")
@@ -510,6 +525,7 @@ def main():
                          "value": 6.0 * nnz * R * args.steps / rb["elapsed"],
                          "als_iter_ms": round(rb["als_ms"], 3), "gd_grad_ms": round(rb["gd_ms"], 3),
                          "mttkrp_ms": [round(x, 4) for x in rb["mttkrp_ms"]],
+                         "gd_iterations": rb["gd_iters"],
                          "roofline_achieved_GBs": round(pb["bytes"] / max(pb["launches"], 1)
                                                         / (ab * 1e-3) / 1e9, 1) if ab > 0 else 0}
     if args.copy_mib > 0:
