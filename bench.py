@@ -270,6 +270,90 @@ def served_line(args, n, out):
     print(json.dumps(line), flush=True)
 
 
+# DFacTo's own seconds per iteration on its synthetic tensors (Section 5,
+# the two synthetic tables), for context: {I: (ALS, GD)}
+PAPER_T4 = {10_000: (1.14, 2.32), 100_000: (2.72, 5.87), 1_000_000: (7.26, 16.51),
+            10_000_000: (41.64, 121.30)}
+PAPER_T5 = {10_000: (0.05, 0.09), 100_000: (0.92, 1.81), 1_000_000: (12.06, 21.74),
+            10_000_000: (144.48, 275.19)}
+
+
+def run_synthetic(args):
+    """The paper's synthetic sweeps (Section 5) on preferential-attachment
+    tensors, I = J = K in {1e4, 1e5, 1e6, 1e7}: nnz = 1e6 (first table) and
+    nnz = 2 I (second table); R = 10, FP32 factors.  Per case: one CP-ALS
+    iteration (average of 3 after a warm-up) and one full GD iteration
+    (gradient + Armijo line search + update; the average of iterations 2-3,
+    each starting from twice the previous step)."""
+    import numpy as np
+    import torch
+    from paper_1406_4519_amd import dfacto, gen
+
+    dev = torch.device("cuda:0")
+    ctx = dfacto.Context(0)
+    R = 10
+    cases = []
+    for table, nnz_of in (("nnz=1e6", lambda I: 1_000_000), ("nnz=2I", lambda I: 2 * I)):
+        for I in (10_000, 100_000, 1_000_000, 10_000_000):
+            t0 = time.perf_counter()
+            coo = gen.preferential_distinct((I, I, I), nnz_of(I), seed=500 + len(cases))
+            gen_s = time.perf_counter() - t0
+            arrs = [torch.from_numpy(x.view(np.int32)).to(dev) for x in (coo.i, coo.j, coo.k)]
+            v = torch.from_numpy(coo.val).to(dev)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            T = dfacto.build_flattenings(ctx, coo.dims, *arrs, v)
+            torch.cuda.synchronize()
+            build_ms = (time.perf_counter() - tb) * 1e3
+            del arrs, v
+            info = T.info()
+            F0 = gen.init_factors(coo.dims, R, seed=600 + len(cases))
+            F = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(dev) for f in F0]
+            G = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in coo.dims]
+            lam = torch.zeros(R, dtype=torch.float64, device=dev)
+            fit = torch.zeros(1, dtype=torch.float64, device=dev)
+            dfacto.als_iter(ctx, T, F, lam, fit)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for _ in range(3):
+                dfacto.als_iter(ctx, T, F, lam, fit)
+            torch.cuda.synchronize()
+            als_ms = (time.perf_counter() - ts) * 1e3 / 3
+            for m, f0 in enumerate(F0):
+                F[m].copy_(torch.from_numpy(np.ascontiguousarray(f0, dtype=np.float32)).to(dev))
+            gd, a0 = [], 1.0
+            for _ in range(3):
+                torch.cuda.synchronize()
+                tg = time.perf_counter()
+                r = dfacto.gd_step(ctx, T, F, G, alpha0=a0, shrink=0.5, c=1e-4, max_trials=60)
+                gd.append(((time.perf_counter() - tg) * 1e3, r["trials"]))
+                a0 = 2.0 * r["alpha"] if r["accepted"] else a0
+            paper = (PAPER_T4 if table == "nnz=1e6" else PAPER_T5)[I]
+            c = dict(table=table, I=I, nnz=info["nnz"], nfib=list(info["nfib"]),
+                     generate_s=round(gen_s, 2), build_ms=round(build_ms, 2),
+                     als_iter_ms=round(als_ms, 3), fit=float(fit.item()),
+                     gd_iter_ms=round((gd[1][0] + gd[2][0]) / 2, 3),
+                     gd_trials=[x[1] for x in gd], gd_first_iter_ms=round(gd[0][0], 3),
+                     paper_s={"als": paper[0], "gd": paper[1]})
+            log(f"{table} I={I:,}: {c}")
+            cases.append(c)
+            T.close()
+            del F, G
+            torch.cuda.empty_cache()
+    big = [c for c in cases if c["table"] == "nnz=2I" and c["I"] == 10_000_000][0]
+    line = {"metric": "synthetic preferential-attachment tensors: ms per CP-ALS iteration",
+            "value": big["als_iter_ms"], "unit": "ms", "n_gpus": 1, "steps": 3, "warmup": 1,
+            "ms_per_step": big["als_iter_ms"], "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "the paper's synthetic sweeps: I = J = K in {1e4, 1e5, 1e6, 1e7}, "
+                                   "nnz = 1e6 and nnz = 2I, preferential attachment, R = 10; value = "
+                                   "CP-ALS iteration at I = 1e7, nnz = 2e7",
+                       "parallelism": "single GPU"},
+            "extra": {"cases": cases}}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def run_paper(args):
     """Paper-shape tensor on one GPU: 6.5M x 2.5M x 1.5M with 1.2B distinct
     coordinates, Zipf(1.2) per mode over seeded permutations, |N(0,1)| FP32
@@ -362,7 +446,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zipf50m",
-                    choices=["zipf50m", "small", "batched", "served", "paper1200m"])
+                    choices=["zipf50m", "small", "batched", "served", "paper1200m", "synthetic"])
     ap.add_argument("--batch", type=int, default=256, help="batched workload: number of tensors")
     ap.add_argument("--iters", type=int, default=20, help="batched workload: ALS iterations")
     ap.add_argument("--rate", type=float, default=200.0, help="served workload: arrivals per second")
@@ -402,6 +486,8 @@ def main():
         return run_served(args)
     if args.workload == "paper1200m":
         return run_paper(args)
+    if args.workload == "synthetic":
+        return run_synthetic(args)
 
     t0 = time.perf_counter()
     if args.workload == "zipf50m":

@@ -20,6 +20,13 @@ size and skew):
   drawn independently; draws continue until ``nnz`` *distinct* coordinates
   exist and the first draw of a coordinate supplies its value.  Values are
   |N(0,1)| rounded to FP32 (the paper's tensors hold positive counts).
+* ``preferential_distinct``: the paper's synthetic model (Section 5):
+  index i of a mode is drawn with probability proportional to the number of
+  nonzeros already at i, plus an initial weight 1 per index (the model
+  leaves unused indices at zero otherwise).  The draws of that urn are
+  exchangeable with Dirichlet(1, ..., 1) weights, so each mode draws its
+  weights once and then i.i.d. indices; draws continue until ``nnz``
+  distinct coordinates exist, |N(0,1)| FP32 values.
 * ``zipf_distinct_torch``: the same per-mode Zipf(s) draw for tensors too
   large to deduplicate on the host (the 1.2B-nonzero paper shape), in torch
   on a given device (``torch.Generator``, Philox on the GPU): draws continue
@@ -135,14 +142,44 @@ def _first_occurrences(keys: np.ndarray, pool: ThreadPoolExecutor,
 def zipf_distinct(dims, nnz: int, s: float, seed: int, values: str = "absnormal",
                   progress=None) -> Coo:
     I, J, K = (int(d) for d in dims)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cdfs = [zipf_cdf(d, s) for d in (I, J, K)]
+    perms = [rng.permutation(d).astype(np.uint32) for d in (I, J, K)]
+    return _distinct_from_cdfs((I, J, K), nnz, cdfs, perms, rng, values, progress, "zipf")
+
+
+def preferential_cdf(dim: int, rng: np.random.Generator) -> np.ndarray:
+    """Cumulative weights of one mode of the preferential-attachment model
+    with initial weight 1 per index: draw i is index i with probability
+    proportional to (nonzeros already at i) + 1.  That Polya urn's draws are
+    exchangeable with de Finetti measure Dirichlet(1, ..., 1), so drawing
+    weights w ~ Dirichlet(1, ..., 1) (normalized Exp(1) variables) once and
+    then i.i.d. indices from w gives the urn's law exactly."""
+    w = rng.standard_exponential(dim)
+    c = np.cumsum(w)
+    c /= c[-1]
+    c[-1] = 1.0
+    return c
+
+
+def preferential_distinct(dims, nnz: int, seed: int, values: str = "absnormal",
+                          progress=None) -> Coo:
+    I, J, K = (int(d) for d in dims)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cdfs = [preferential_cdf(d, rng) for d in (I, J, K)]
+    return _distinct_from_cdfs((I, J, K), nnz, cdfs, None, rng, values, progress, "preferential")
+
+
+def _distinct_from_cdfs(dims, nnz, cdfs, perms, rng, values, progress, label) -> Coo:
+    """Draw (i, j, k) independently per mode from the cumulative tables
+    (index = perms[m][rank] when perms is given) until nnz distinct
+    coordinates exist; the first draw of a coordinate supplies its value."""
+    I, J, K = dims
     if I * J * K < nnz:
         raise ValueError("more distinct nonzeros requested than cells")
     wide = float(I) * J * K >= 2.0 ** 63  # key = (i, j K + k) in two words
     if wide and float(J) * K >= 2.0 ** 63:
         raise ValueError("tensor too large for the coordinate key")
-    rng = np.random.Generator(np.random.PCG64(seed))
-    cdfs = [zipf_cdf(d, s) for d in (I, J, K)]
-    perms = [rng.permutation(d).astype(np.uint32) for d in (I, J, K)]
     pool = ThreadPoolExecutor(_workers())
     try:
         idx = [np.empty(0, np.uint32) for _ in range(3)]
@@ -152,10 +189,11 @@ def zipf_distinct(dims, nnz: int, s: float, seed: int, values: str = "absnormal"
             new = []
             for m in range(3):
                 u = rng.random(draw)
-                new.append(perms[m][_draw_ranks(cdfs[m], u, pool)])
-                del u
+                r = _draw_ranks(cdfs[m], u, pool)
+                new.append(perms[m][r] if perms is not None else r.astype(np.uint32))
+                del u, r
                 if progress is not None:
-                    progress(f"zipf draw: mode {m}, {draw:,} samples")
+                    progress(f"{label} draw: mode {m}, {draw:,} samples")
             if values == "absnormal":
                 v = np.abs(rng.standard_normal(draw)).astype(np.float32)
             elif values == "normal":
@@ -174,7 +212,7 @@ def zipf_distinct(dims, nnz: int, s: float, seed: int, values: str = "absnormal"
                     * np.uint64(K) + idx[2].astype(np.uint64)
                 first = _first_occurrences(keys, pool)
             if progress is not None:
-                progress(f"zipf draw: {len(keys):,} coordinates, {len(first):,} distinct")
+                progress(f"{label} draw: {len(keys):,} coordinates, {len(first):,} distinct")
             if len(first) >= nnz:
                 sel = first[:nnz]
                 return Coo((I, J, K), idx[0][sel].copy(), idx[1][sel].copy(),

@@ -83,3 +83,41 @@ def test_zipf_distinct_torch_counts_classes_and_determinism():
     # skew: the most frequent mode-0 index holds far more than a uniform share
     counts = torch.bincount(a[0].long(), minlength=dims[0])
     assert int(counts.max()) > 5 * 20_000 / dims[0]
+
+
+def test_preferential_attachment_matches_the_urn():
+    """The preferential-attachment sampler (Dirichlet(1) weights, then i.i.d.
+    draws) has the urn's law: the count at one index after n draws over I
+    indices is Beta-Binomial(n, 1, I - 1), variance n (I-1)(n+I) / (I^2 (I+1)),
+    ten times the variance of independent uniform draws here; a direct
+    sequential urn (weight = nonzeros at the index + 1) agrees as well."""
+    I, n, reps = 20, 200, 3000
+    rng = np.random.default_rng(21)
+    var_bb = n * (I - 1) * (n + I) / (I * I * (I + 1))
+    counts = np.empty(reps)
+    for t in range(reps):
+        cdf = gen.preferential_cdf(I, rng)
+        r = np.minimum(np.searchsorted(cdf, rng.random(n), side="right"), I - 1)
+        counts[t] = np.sum(r == 0)
+    assert abs(counts.mean() - n / I) < 0.1 * n / I
+    assert abs(counts.var() - var_bb) < 0.15 * var_bb
+    urn = np.empty(reps)
+    for t in range(reps):
+        w = np.ones(I)
+        for _ in range(n):
+            i = min(int(np.searchsorted(np.cumsum(w), rng.random() * w.sum(), side="right")), I - 1)
+            w[i] += 1.0
+        urn[t] = w[0] - 1.0
+    assert abs(urn.var() - var_bb) < 0.15 * var_bb
+
+
+def test_preferential_distinct_counts_and_determinism():
+    dims = (2000, 2000, 2000)
+    a = gen.preferential_distinct(dims, 50_000, seed=8)
+    b = gen.preferential_distinct(dims, 50_000, seed=8)
+    for x, y in ((a.i, b.i), (a.j, b.j), (a.k, b.k), (a.val, b.val)):
+        np.testing.assert_array_equal(x, y)
+    lin = (a.i.astype(np.int64) * dims[1] + a.j) * dims[2] + a.k
+    assert len(np.unique(lin)) == 50_000
+    assert a.i.max() < dims[0] and a.j.max() < dims[1] and a.k.max() < dims[2]
+    assert (a.val >= 0).all()
