@@ -64,6 +64,12 @@ def _load():
                                        P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int, ctypes.c_int, P]
         lib.oracle_gd_step.restype = ctypes.c_int
+        lib.oracle_joint_grad.argtypes = [i64, P, P, P, P, P, i64, P, P, P, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_double, P, P, P, P, P, P]
+        lib.oracle_joint_grad.restype = ctypes.c_double
+        lib.oracle_joint_als_iter.argtypes = [i64, P, P, P, P, P, i64, P, P, P, ctypes.c_int,
+                                              ctypes.c_double, ctypes.c_double, P, P, P]
+        lib.oracle_joint_als_iter.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -212,3 +218,39 @@ def gd_step(i, j, k, val, dims, factors, reg: float = 0.0, alpha0: float = 1.0,
     info = dict(f0=float(out[0]), f=float(out[1]), gnorm2=float(out[2]), alpha=float(out[3]),
                 trials=int(out[4]), accepted=bool(acc))
     return A, B, C, info
+
+
+def _ratings(yi, yj, yv):
+    yi, yj, yv = _u32(yi), _u32(yj), _f64(yv)
+    assert yi.shape == yj.shape == yv.shape
+    return yi, yj, yv
+
+
+def joint_grad(i, j, k, val, dims, yi, yj, yv, factors, mu: float, lam: float):
+    """Joint matrix completion + tensor factorization: gradients of f at one
+    point and f.  Returns ((gA, gB, gC), f)."""
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    yi, yj, yv = _ratings(yi, yj, yv)
+    A, B, C = (_f64(f) for f in factors)
+    R = A.shape[1]
+    d = np.asarray(dims, dtype=np.int64)
+    g = [np.empty((int(dims[m]), R), np.float64) for m in range(3)]
+    f = lib.oracle_joint_grad(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), len(yv), _p(yi),
+                              _p(yj), _p(yv), R, float(mu), float(lam), _p(A), _p(B), _p(C),
+                              _p(g[0]), _p(g[1]), _p(g[2]))
+    return tuple(g), float(f)
+
+
+def joint_als_iter(i, j, k, val, dims, yi, yj, yv, factors, mu: float, lam: float):
+    """One ALS iteration of the joint model (A, B, C in order).  Returns
+    (A, B, C, f) with new arrays; f at the new point."""
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    yi, yj, yv = _ratings(yi, yj, yv)
+    A, B, C = (np.array(f, dtype=np.float64, order="C", copy=True) for f in factors)
+    R = A.shape[1]
+    d = np.asarray(dims, dtype=np.int64)
+    f = lib.oracle_joint_als_iter(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), len(yv), _p(yi),
+                                  _p(yj), _p(yv), R, float(mu), float(lam), _p(A), _p(B), _p(C))
+    return A, B, C, float(f)

@@ -26,6 +26,8 @@
  *       dF/dA = -X1 (C kr B) + A (C^T C * B^T B + reg I).
  *   - Algorithm 5 (Appendix E, DFacTo with GD): the three gradients at one
  *     point, a backtracking line search, the simultaneous update.
+ *   - The joint matrix completion and tensor factorization model (its
+ *     objective, per-row gradient and per-row ALS closed form).
  *
  * Mode numbering is 0-based: mode 0 is the paper's mode 1 (output rows i),
  * mode 1 is the paper's mode 2 (rows j), mode 2 the paper's mode 3 (rows k).
@@ -623,4 +625,135 @@ int oracle_gd_step(int64_t nnz, const uint32_t *i, const uint32_t *j, const uint
     out[3] = taken ? alpha : 0.0;
     out[4] = (double)trials;
     return taken;
+}
+
+/* ------------------------------------------------------------------ */
+/* joint matrix completion and tensor factorization                     */
+/* ------------------------------------------------------------------ */
+
+/* The joint model (the section on joint matrix completion and tensor
+ * factorization): a ratings matrix Y (users x items, observed entries
+ * (yi[e], yj[e]) -> yv[e]) shares the user factor A and the item factor B
+ * with the user x item x word tensor X:
+ *   f = 1/2 sum_{(i,j) observed} (y_ij - a_i . b_j)^2
+ *       + mu 1/2 sum_{i,j,k} (x_ijk - [[A,B,C]]_ijk)^2
+ *       + lam 1/2 (||A||^2 + ||B||^2 + ||C||^2)
+ * (the tensor sum runs over every cell, as in the GD objective).
+ * Gradient rows (the paper's per-row gradient eq.; ridge lam):
+ *   g_a_i = -sum_{j in row i} (y_ij - a_i.b_j) b_j + mu (-M0 + A H0)_i + lam a_i
+ *   g_b_j = -sum_{i in col j} (y_ij - a_i.b_j) a_i + mu (-M1 + B H1)_j + lam b_j
+ *   g_c_k =                                          mu (-M2 + C H2)_k + lam c_k
+ * with M_n the MTTKRPs and H_n the Hadamard products of the other two
+ * Grams.  Returns f. */
+double oracle_joint_grad(int64_t nnz, const uint32_t *i, const uint32_t *j, const uint32_t *k,
+                         const double *val, const int64_t *dims, int64_t ny,
+                         const uint32_t *yi, const uint32_t *yj, const double *yv, int R,
+                         double mu, double lam, const double *A, const double *B,
+                         const double *C, double *gA, double *gB, double *gC)
+{
+    const double *F[3] = {A, B, C};
+    double *Gout[3] = {gA, gB, gC};
+    double *Gm[3];
+    for (int m = 0; m < 3; ++m) {
+        Gm[m] = (double *)malloc(sizeof(double) * (size_t)R * R);
+        gram(dims[m], R, F[m], Gm[m]);
+    }
+    double *H = (double *)malloc(sizeof(double) * (size_t)R * R);
+    for (int n = 0; n < 3; ++n) {
+        const int p = (n + 1) % 3, q = (n + 2) % 3;
+        oracle_mttkrp(nnz, i, j, k, val, dims, R, A, B, C, n, Gout[n]);
+        for (int t = 0; t < R * R; ++t) H[t] = Gm[p][t] * Gm[q][t];
+        for (int64_t m = 0; m < dims[n]; ++m) {
+            const double *fr = F[n] + m * R;
+            double *g = Gout[n] + m * R;
+            for (int s = 0; s < R; ++s) {
+                double acc = 0.0;
+                for (int r = 0; r < R; ++r) acc += fr[r] * H[r * R + s];
+                g[s] = mu * (-g[s] + acc) + lam * fr[s];
+            }
+        }
+    }
+    double fy = 0.0;
+    for (int64_t e = 0; e < ny; ++e) {
+        const double *a = A + (int64_t)yi[e] * R, *b = B + (int64_t)yj[e] * R;
+        double dot = 0.0;
+        for (int r = 0; r < R; ++r) dot += a[r] * b[r];
+        const double res = yv[e] - dot;
+        fy += 0.5 * res * res;
+        double *ga = gA + (int64_t)yi[e] * R, *gb = gB + (int64_t)yj[e] * R;
+        for (int r = 0; r < R; ++r) {
+            ga[r] -= res * b[r];
+            gb[r] -= res * a[r];
+        }
+    }
+    double xhat2 = 0.0, fro2 = 0.0;
+    for (int t = 0; t < R * R; ++t) xhat2 += Gm[0][t] * Gm[1][t] * Gm[2][t];
+    for (int m = 0; m < 3; ++m)
+        for (int r = 0; r < R; ++r) fro2 += Gm[m][r * R + r];
+    const double x2 = oracle_normsq(nnz, i, j, k, val);
+    const double inner = oracle_inner(nnz, i, j, k, val, R, A, B, C, NULL);
+    for (int m = 0; m < 3; ++m) free(Gm[m]);
+    free(H);
+    return fy + mu * 0.5 * (x2 - 2.0 * inner + xhat2) + 0.5 * lam * fro2;
+}
+
+/* One ALS iteration of the joint model in the order A, B, C (Gauss-Seidel),
+ * each row set to the minimizer of f with the other factors fixed (the
+ * paper's closed form, from its per-row gradient set to zero):
+ *   a_i = (sum_{j in row i} y_ij b_j + mu M0_i)
+ *         (sum_{j in row i} b_j^T b_j + mu (B^T B * C^T C) + lam I)^{-1}
+ * and likewise for b_j over the users who rated item j (with A^T A * C^T C);
+ * c_k = mu M2_k (mu (A^T A * B^T B) + lam I)^{-1} (no ratings term).  Each
+ * R x R system is solved by Cholesky, or the pseudo-inverse when it is
+ * numerically singular.  A, B, C are updated in place; returns f at the
+ * new point. */
+double oracle_joint_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
+                             const uint32_t *k, const double *val, const int64_t *dims,
+                             int64_t ny, const uint32_t *yi, const uint32_t *yj,
+                             const double *yv, int R, double mu, double lam, double *A,
+                             double *B, double *C)
+{
+    double *F[3] = {A, B, C};
+    const uint32_t *own[2] = {yi, yj}, *other[2] = {yj, yi};
+    double *Gp = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *Gq = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *S = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *rhs = (double *)malloc(sizeof(double) * (size_t)R);
+    for (int n = 0; n < 3; ++n) {
+        const int p = (n + 1) % 3, q = (n + 2) % 3;
+        double *M = (double *)malloc(sizeof(double) * (size_t)dims[n] * R);
+        oracle_mttkrp(nnz, i, j, k, val, dims, R, A, B, C, n, M);
+        gram(dims[p], R, F[p], Gp);
+        gram(dims[q], R, F[q], Gq);
+        for (int64_t row = 0; row < dims[n]; ++row) {
+            for (int t = 0; t < R * R; ++t) S[t] = mu * Gp[t] * Gq[t];
+            for (int r = 0; r < R; ++r) {
+                S[r * R + r] += lam;
+                rhs[r] = mu * M[row * R + r];
+            }
+            if (n < 2) {  /* the ratings of this user (n = 0) or item (n = 1) */
+                const double *Fo = F[1 - n];
+                for (int64_t e = 0; e < ny; ++e) {
+                    if ((int64_t)own[n][e] != row) continue;
+                    const double *v = Fo + (int64_t)other[n][e] * R;
+                    for (int r = 0; r < R; ++r) {
+                        rhs[r] += yv[e] * v[r];
+                        for (int s = 0; s < R; ++s) S[r * R + s] += v[r] * v[s];
+                    }
+                }
+            }
+            solve_rows(1, R, rhs, S, F[n] + row * R);
+        }
+        free(M);
+    }
+    free(Gp);
+    free(Gq);
+    free(S);
+    free(rhs);
+    double *g[3];
+    for (int m = 0; m < 3; ++m) g[m] = (double *)malloc(sizeof(double) * (size_t)dims[m] * R);
+    const double f = oracle_joint_grad(nnz, i, j, k, val, dims, ny, yi, yj, yv, R, mu, lam, A, B,
+                                       C, g[0], g[1], g[2]);
+    for (int m = 0; m < 3; ++m) free(g[m]);
+    return f;
 }
