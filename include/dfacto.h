@@ -319,6 +319,59 @@ void dfacto_server_destroy(dfacto_server *srv);
 /* measurement                                                          */
 /* ------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------ */
+/* joint matrix completion and tensor factorization                     */
+/* ------------------------------------------------------------------ */
+
+/* The joint model of the paper's section on joint matrix completion and
+ * tensor factorization: a ratings matrix Y (users x items, observed entries
+ * only) shares the user factor A and the item factor B with a
+ * users x items x words tensor X (factor C):
+ *   f = 1/2 sum_{(i,j) observed} (y_ij - a_i . b_j)^2
+ *       + mu 1/2 sum_{i,j,k} (x_ijk - [[A,B,C]]_ijk)^2
+ *       + lam 1/2 (||A||^2 + ||B||^2 + ||C||^2)
+ * (the tensor sum runs over every cell, as in dfacto_gd_grad).
+ *
+ * dfacto_build_ratings builds Y from n device COO entries (d_i[e], d_j[e])
+ * -> d_y[e] (u32 indices below dims[0] x dims[1], FP32 values; duplicates
+ * summed) as a dims[0] x dims[1] x 1 tensor (so its MTTKRPs with a row of
+ * ones as third factor are Y B and Y^T A, computed by the DFacTo kernels)
+ * plus per-row entry ranges for the ALS rows.  Errors and ownership as
+ * dfacto_build_flattenings; synchronizes the stream. */
+dfacto_status dfacto_build_ratings(dfacto_ctx *ctx, const int64_t dims[2], int64_t n,
+                                   const uint32_t *d_i, const uint32_t *d_j, const float *d_y,
+                                   dfacto_tensor **out);
+
+/* Gradients of the joint f at one point (the paper's per-row gradient
+ * equation, all rows, all three factors) and f:
+ *   dA = -sum_j (y_ij - a_i.b_j) b_j + mu (-M_0 + A (B^T B * C^T C)) + lam A
+ *   dB = -sum_i (y_ij - a_i.b_j) a_i + mu (-M_1 + B (A^T A * C^T C)) + lam B
+ *   dC =                                mu (-M_2 + C (A^T A * B^T B)) + lam C
+ * The ratings terms are residual MTTKRPs of Y (FP32 accumulation); the
+ * ratings part of f is formed as 1/2 (||Y||^2 - <A, Y B> - <A, residual B>)
+ * in FP64.  X and Y must share dims[0] and dims[1]; mu, lam >= 0.  Factor
+ * and gradient layouts, dtypes and errors as dfacto_gd_grad; Y not built by
+ * dfacto_build_ratings or of the wrong shape: DFACTO_E_INVALID.  Enqueues
+ * only. */
+dfacto_status dfacto_joint_grad(dfacto_ctx *ctx, const dfacto_tensor *X, const dfacto_tensor *Y,
+                                int R, dfacto_dtype dtype, double mu, double lam,
+                                const void *const d_F[3], float *const d_G[3], double *d_f);
+
+/* One ALS iteration of the joint model, A, B, C in order, each row set to
+ * the minimizer with the other factors fixed (the paper's closed form):
+ *   a_i = (sum_j y_ij b_j + mu M_0[i]) (sum_j b_j^T b_j + mu B^T B * C^T C + lam I)^-1
+ * over the items j rated by user i, likewise b_j over the users who rated j,
+ * and c_k = mu M_2[k] (mu A^T A * B^T B + lam I)^-1.  Each user's and item's
+ * R x R system is formed and inverted in FP64 by one wavefront; factors are
+ * updated in place in their dtype (no column normalization).  Needs lam > 0
+ * (every system is then positive definite) and R <= 32
+ * (DFACTO_E_UNSUPPORTED above); DFACTO_E_NUMERIC if a system still fails
+ * the positive-definiteness test.  Synchronizes the stream (the test's
+ * flag is read back). */
+dfacto_status dfacto_joint_als_iter(dfacto_ctx *ctx, const dfacto_tensor *X,
+                                    const dfacto_tensor *Y, int R, dfacto_dtype dtype, double mu,
+                                    double lam, void *const d_F[3]);
+
 /* One full GD iteration (Algorithm 5 of Appendix E; Algorithm 3 of
  * Appendix C): the three gradients at the same point (as dfacto_gd_grad,
  * written to d_G), then a backtracking line search, then the simultaneous

@@ -592,6 +592,26 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
                               sizeof(uint32_t) * md.nempty, hipMemcpyDeviceToHost, s));
 }
 
+// 1 where a stream entry opens an output row (a ROOT header)
+__global__ void k_root_flags(const uint2 *__restrict__ st, int64_t n, uint32_t *__restrict__ f) {
+    GRID_STRIDE(e, n) f[e] = ((st[e].x & (kHdrBit | kRootBit)) == (kHdrBit | kRootBit)) ? 1u : 0u;
+}
+
+// the q-th row opening of the stream at pos[q] covers [pos[q], pos[q+1])
+__global__ void k_row_ranges(const uint2 *__restrict__ st, const uint32_t *__restrict__ flag,
+                             const uint32_t *__restrict__ off, int64_t n, uint32_t *__restrict__ pos) {
+    GRID_STRIDE(e, n) if (flag[e]) pos[off[e]] = (uint32_t)e;
+}
+
+__global__ void k_store_ranges(const uint2 *__restrict__ st, const uint32_t *__restrict__ pos,
+                               int64_t nroot, int64_t n, uint2 *__restrict__ range) {
+    GRID_STRIDE(q, nroot) {
+        const uint32_t b = pos[q];
+        const uint32_t e = (q + 1 < nroot) ? pos[q + 1] : (uint32_t)n;
+        range[st[b].y] = make_uint2(b, e);
+    }
+}
+
 }  // namespace
 
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s) {
@@ -611,6 +631,31 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_
                        (const uint32_t *)boff);
     DF_HIP(hipFreeAsync(bsum, s));
     DF_HIP(hipFreeAsync(boff, s));
+}
+
+void build_row_ranges(dfacto_ctx *ctx, dfacto_tensor *t) {
+    hipStream_t s = ctx->stream;
+    Scratch sc(s);
+    for (int m = 0; m < 2; ++m) {
+        const ModeData &md = t->mode[m];
+        const int64_t rows = t->dims[md.root], n = md.nentry;
+        uint2 *range = tensor_alloc<uint2>(t, rows);
+        DF_HIP(hipMemsetAsync(range, 0, sizeof(uint2) * (size_t)rows, s));
+        if (n > 0 && md.nroot > 0) {
+            uint32_t *flag = sc.alloc<uint32_t>(n), *off = sc.alloc<uint32_t>(n);
+            uint32_t *pos = sc.alloc<uint32_t>(md.nroot);
+            hipLaunchKernelGGL(k_root_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, md.stream, n,
+                               flag);
+            scan_exclusive_u32(flag, off, n, s);
+            hipLaunchKernelGGL(k_row_ranges, dim3(grid_for(n)), dim3(kThreads), 0, s, md.stream,
+                               flag, off, n, pos);
+            hipLaunchKernelGGL(k_store_ranges, dim3(grid_for(md.nroot)), dim3(kThreads), 0, s,
+                               md.stream, pos, md.nroot, n, range);
+            DF_LAUNCHED();
+        }
+        t->row_range[m] = range;
+    }
+    DF_HIP(hipStreamSynchronize(s));
 }
 
 void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const uint32_t *d_j,

@@ -428,6 +428,168 @@ dfacto_status dfacto_gd_step(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfa
     });
 }
 
+// ---- joint matrix completion + tensor factorization -----------------------
+
+dfacto_status dfacto_build_ratings(dfacto_ctx *ctx, const int64_t dims[2], int64_t n,
+                                   const uint32_t *d_i, const uint32_t *d_j, const float *d_y,
+                                   dfacto_tensor **out) {
+    if (out) *out = nullptr;
+    return guarded(ctx, [&] {
+        if (!out || !dims) throw Error{DFACTO_E_INVALID, "dims or out is NULL"};
+        if (n < 0) throw Error{DFACTO_E_INVALID, "n is negative"};
+        uint32_t *k0 = nullptr;
+        hip_check(hipMallocAsync((void **)&k0, sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1),
+                                 ctx->stream),
+                  "ratings staging");
+        DF_HIP(hipMemsetAsync(k0, 0, sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1),
+                              ctx->stream));
+        const int64_t d3[3] = {dims[0], dims[1], 1};
+        dfacto_tensor *t = nullptr;
+        const dfacto_status st = dfacto_build_flattenings(ctx, d3, n, d_i, d_j, k0, d_y, &t);
+        (void)hipFreeAsync(k0, ctx->stream);
+        if (st != DFACTO_OK) throw Error{st, ctx->err};
+        try {
+            build_row_ranges(ctx, t);
+        } catch (...) {
+            dfacto_tensor_destroy(t);
+            throw;
+        }
+        t->ratings = true;
+        *out = t;
+    });
+}
+
+namespace {
+
+void check_joint(const dfacto_tensor *X, const dfacto_tensor *Y, int R, dfacto_dtype dtype,
+                 double mu, double lam) {
+    check_common(X, R, dtype);
+    if (!Y) throw Error{DFACTO_E_INVALID, "ratings matrix is NULL"};
+    if (!Y->ratings) throw Error{DFACTO_E_INVALID, "Y was not built by dfacto_build_ratings"};
+    if (Y->dims[0] != X->dims[0] || Y->dims[1] != X->dims[1])
+        throw Error{DFACTO_E_INVALID, "Y must be users x items of X (dims[0] x dims[1])"};
+    if (Y->device != X->device) throw Error{DFACTO_E_INVALID, "X and Y on different devices"};
+    if (!(mu >= 0.0) || !(lam >= 0.0)) throw Error{DFACTO_E_INVALID, "mu and lam must be >= 0"};
+}
+
+// a 1 x R row of ones in the factor dtype: the third "factor" of the
+// ratings matrix seen as a users x items x 1 tensor
+void *ones_row(dfacto_ctx *ctx, int R, dfacto_dtype dtype, void *dst) {
+#define DF_X8(v) v, v, v, v, v, v, v, v
+#define DF_X64(v) DF_X8(v), DF_X8(v), DF_X8(v), DF_X8(v), DF_X8(v), DF_X8(v), DF_X8(v), DF_X8(v)
+    static_assert(DFACTO_MAX_R == 256, "ones table size");
+    static const float f1[256] = {DF_X64(1.f), DF_X64(1.f), DF_X64(1.f), DF_X64(1.f)};
+    static const uint16_t b1[256] = {DF_X64(0x3F80u), DF_X64(0x3F80u), DF_X64(0x3F80u),
+                                     DF_X64(0x3F80u)};  // BF16 1.0
+#undef DF_X64
+#undef DF_X8
+    DF_HIP(hipMemcpyAsync(dst, dtype == DFACTO_F32 ? (const void *)f1 : (const void *)b1,
+                          (size_t)R * elem_size(dtype), hipMemcpyHostToDevice, ctx->stream));
+    return dst;
+}
+
+}  // namespace
+
+dfacto_status dfacto_joint_grad(dfacto_ctx *ctx, const dfacto_tensor *X, const dfacto_tensor *Y,
+                                int R, dfacto_dtype dtype, double mu, double lam,
+                                const void *const d_F[3], float *const d_G[3], double *d_f) {
+    return guarded(ctx, [&] {
+        check_joint(X, Y, R, dtype, mu, lam);
+        if (!d_F || !d_G || !d_f) throw Error{DFACTO_E_INVALID, "NULL argument"};
+        for (int m = 0; m < 3; ++m) {
+            check_factor(d_F[m], "factor");
+            check_align(d_F[m], dtype, "factor");
+            if (!d_G[m]) throw Error{DFACTO_E_INVALID, "gradient output is NULL"};
+            if ((uintptr_t)d_G[m] % 4) throw Error{DFACTO_E_INVALID, "gradient not aligned"};
+        }
+        Small sw = small_ws(ctx, R);
+        // workspace: ones row, the ratings' residual MTTKRPs of modes 0 and
+        // 1, the plain one of mode 0, partial sums, the tensor objective
+        const size_t d0 = (size_t)X->dims[0] * R, d1 = (size_t)X->dims[1] * R;
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t o_ry0 = al(4 * (size_t)R), o_ry1 = o_ry0 + al(4 * d0);
+        const size_t o_my0 = o_ry1 + al(4 * d1);
+        const size_t o_part = o_my0 + al(4 * d0), o_ft = o_part + al(8 * 2 * kSumsqBlocks);
+        char *w = (char *)ws_get(ctx, dfacto_ctx::kJoint, o_ft + 256);
+        void *one = ones_row(ctx, R, dtype, w);
+        float *RY0 = (float *)(w + o_ry0), *RY1 = (float *)(w + o_ry1), *MY0 = (float *)(w + o_my0);
+        double *part = (double *)(w + o_part), *ft = (double *)(w + o_ft);
+        // tensor part, as dfacto_gd_grad with reg = 0: G_n = -M_n + F_n H_n
+        for (int m = 0; m < 3; ++m) launch_gram(ctx, d_F[m], dtype, X->dims[m], R, sw.G[m]);
+        for (int n = 0; n < 3; ++n)
+            launch_hadamard(ctx, R, sw.G[(n + 1) % 3], sw.G[(n + 2) % 3], 0.0, sw.H[n]);
+        for (int n = 0; n < 3; ++n) {
+            const ModeData &md = X->mode[n];
+            launch_mttkrp(ctx, X, n, R, dtype, d_F[md.leaf], d_F[md.mid], d_G[n]);
+            launch_gd_rows(ctx, d_G[n], d_F[n], dtype, X->dims[n], R, sw.H[n],
+                           n == 0 ? sw.part0 : sw.part_dummy);
+        }
+        launch_gd_f(ctx, R, sw.G[0], sw.G[1], sw.G[2], sw.part0,
+                    gd_rows_partials(X->dims[0], R, d_G[0], d_F[0], dtype), X->normsq, 0.0, ft);
+        // ratings part: Y's mode 0 is (user, 1, item), mode 1 (item, user, 1)
+        launch_mttkrp_resid(ctx, Y, 0, R, dtype, d_F[1], one, d_F[0], RY0);
+        launch_mttkrp_resid(ctx, Y, 1, R, dtype, one, d_F[0], d_F[1], RY1);
+        launch_mttkrp(ctx, Y, 0, R, dtype, d_F[1], one, MY0);
+        launch_joint_combine(ctx, d_G[0], d_F[0], RY0, mu, lam, (int64_t)d0, dtype);
+        launch_joint_combine(ctx, d_G[1], d_F[1], RY1, mu, lam, (int64_t)d1, dtype);
+        launch_joint_combine(ctx, d_G[2], d_F[2], nullptr, mu, lam, X->dims[2] * R, dtype);
+        launch_dot_parts(ctx, d_F[0], MY0, (int64_t)d0, part, dtype);
+        launch_dot_parts(ctx, d_F[0], RY0, (int64_t)d0, part + kSumsqBlocks, dtype);
+        launch_joint_f(ctx, ft, sw.G[0], sw.G[1], sw.G[2], R, part, 2 * kSumsqBlocks, Y->normsq,
+                       mu, lam, d_f);
+    });
+}
+
+dfacto_status dfacto_joint_als_iter(dfacto_ctx *ctx, const dfacto_tensor *X,
+                                    const dfacto_tensor *Y, int R, dfacto_dtype dtype, double mu,
+                                    double lam, void *const d_F[3]) {
+    return guarded(ctx, [&] {
+        check_joint(X, Y, R, dtype, mu, lam);
+        if (R > 32) throw Error{DFACTO_E_UNSUPPORTED, "joint ALS supports R <= 32"};
+        if (!(lam > 0.0)) throw Error{DFACTO_E_INVALID, "joint ALS needs lam > 0"};
+        if (!d_F) throw Error{DFACTO_E_INVALID, "NULL argument"};
+        for (int m = 0; m < 3; ++m) {
+            check_factor(d_F[m], "factor");
+            check_align(d_F[m], dtype, "factor");
+        }
+        Small sw = small_ws(ctx, R);
+        float *M = (float *)ws_get(ctx, dfacto_ctx::kM, sizeof(float) * (size_t)max_dim(X) * R);
+        char *w = (char *)ws_get(ctx, dfacto_ctx::kJoint, 256);
+        void *one = ones_row(ctx, R, dtype, w);
+        DF_HIP(hipMemsetAsync(sw.flag, 0, 4 * sizeof(int), ctx->stream));
+        launch_gram(ctx, d_F[1], dtype, X->dims[1], R, sw.G[1]);
+        launch_gram(ctx, d_F[2], dtype, X->dims[2], R, sw.G[2]);
+        for (int n = 0; n < 3; ++n) {
+            const int p = (n + 1) % 3, q = (n + 2) % 3;
+            const ModeData &md = X->mode[n];
+            if (mu > 0.0) launch_mttkrp(ctx, X, n, R, dtype, d_F[md.leaf], d_F[md.mid], M);
+            if (n < 2) {
+                // users (n = 0): entries (1, item); items (n = 1): entries (user, 1)
+                launch_hadamard(ctx, R, sw.G[p], sw.G[q], 0.0, sw.H[n]);
+                launch_joint_rows(ctx, Y->mode[n], Y->row_range[n], X->dims[n],
+                                  n == 0 ? one : d_F[0], n == 0 ? d_F[1] : one, R,
+                                  mu > 0.0 ? M : nullptr, sw.H[n], mu, lam, d_F[n], dtype,
+                                  sw.flag);
+            } else if (mu > 0.0) {
+                // words: C = mu M (mu H + lam I)^-1 = M (H + (lam / mu) I)^-1
+                launch_solve(ctx, R, sw.G[p], sw.G[q], lam / mu, sw.Hinv, sw.solve_scratch,
+                             sw.flag + 1);
+                launch_rowmap(ctx, M, X->dims[2], R, sw.Hinv, d_F[2], dtype);
+            } else {
+                DF_HIP(hipMemsetAsync(d_F[2], 0, (size_t)X->dims[2] * R * elem_size(dtype),
+                                      ctx->stream));
+            }
+            launch_gram(ctx, d_F[n], dtype, X->dims[n], R, sw.G[n]);
+        }
+        int flag = 0;
+        DF_HIP(hipMemcpyAsync(&flag, sw.flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        DF_HIP(hipStreamSynchronize(ctx->stream));
+        if (flag)
+            throw Error{DFACTO_E_NUMERIC, "a joint ALS row system is not numerically positive "
+                                          "definite"};
+    });
+}
+
 dfacto_status dfacto_profile_enable(dfacto_ctx *ctx, int on) {
     return guarded(ctx, [&] {
         ctx->profiling = on != 0;

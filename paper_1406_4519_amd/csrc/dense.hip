@@ -949,6 +949,121 @@ __global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__
     if (threadIdx.x == 0) *out = acc;
 }
 
+// ---- joint matrix completion + tensor factorization ----------------------
+// One ALS row of the joint model per wave (R <= 32): with the stored
+// entries of that row in a ratings stream (headers name the mid row,
+// nonzeros the leaf row and the rating y; the entry's vector is
+// v = F_mid[mid] * F_leaf[leaf], i.e. the other factor's row when the third
+// factor is a row of ones), form in FP64
+//   S = sum v^T v + mu H + lam I,   rhs = sum y v + mu M[row]
+// (lane l keeps column l of S in registers), invert S by the one-wave
+// Gauss-Jordan and write out[row] = rhs S^-1 in the factor dtype.  A row
+// whose S fails the positive-definiteness test is written as zeros and
+// raises *flag.
+constexpr int kJointRM = 32;
+template <typename T>
+__global__ __launch_bounds__(64) void k_joint_rows(const uint2 *__restrict__ st,
+                                                   const uint2 *__restrict__ range, int64_t nrows,
+                                                   const T *__restrict__ Fmid,
+                                                   const T *__restrict__ Fleaf, int R,
+                                                   const float *__restrict__ M,
+                                                   const double *__restrict__ H, double mu,
+                                                   double lam, T *__restrict__ out,
+                                                   int *__restrict__ flag) {
+    __shared__ double S[kJointRM * kJointRM], Si[kJointRM * kJointRM];
+    const int l = threadIdx.x;
+    const bool own = l < R;
+    for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
+        double col[kJointRM];
+#pragma unroll
+        for (int i = 0; i < kJointRM; ++i)
+            col[i] = (own && i < R) ? mu * H[i * R + l] + (i == l ? lam : 0.0) : 0.0;
+        double rhs = (own && M) ? mu * (double)M[row * R + l] : 0.0;
+        const uint2 rg = range[row];
+        double mv = 0.0;
+        for (uint32_t e = rg.x; e < rg.y; ++e) {
+            const uint2 w = st[e];
+            if (w.x & kHdrBit) {
+                mv = own ? ld<T>(Fmid, (int64_t)(w.x & kIdxMask) * R + l) : 0.0;
+                continue;
+            }
+            const double v = own ? mv * ld<T>(Fleaf, (int64_t)w.x * R + l) : 0.0;
+            rhs = fma((double)__uint_as_float(w.y), v, rhs);
+            unroll_for<0, kJointRM>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if (i < R) col[i] = fma(readlane_f64(v, i), v, col[i]);
+            });
+        }
+        if (own) {
+#pragma unroll
+            for (int i = 0; i < kJointRM; ++i)
+                if (i < R) S[i * R + l] = col[i];
+        }
+        __syncthreads();
+        double dm = own ? S[l * R + l] : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+        const bool ok = dm > 0.0 && gauss_jordan_wave(S, R, (double)R * DBL_EPSILON * dm, Si);
+        __syncthreads();
+        double x = 0.0;
+        unroll_for<0, kJointRM>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if (i < R) x = fma(readlane_f64(rhs, i), own ? Si[i * R + l] : 0.0, x);
+        });
+        if (own) st_out<T>(out, row * R + l, ok ? x : 0.0);
+        if (!ok && l == 0) atomicOr(flag, 1);
+        __syncthreads();
+    }
+}
+
+// G = mu G + lam F - RY (RY may be null): the joint gradient from the
+// tensor part -M + F H, the ridge term and the ratings part
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_joint_combine(float *__restrict__ G,
+                                                          const T *__restrict__ F,
+                                                          const float *__restrict__ RY, double mu,
+                                                          double lam, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kBlock) {
+        double g = mu * (double)G[e] + lam * ld<T>(F, e);
+        if (RY) g -= (double)RY[e];
+        G[e] = (float)g;
+    }
+}
+
+// per-block partial sums of F[e] * X[e] in FP64 (grid-stride, fixed order)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dot_parts(const T *__restrict__ F,
+                                                      const float *__restrict__ X, int64_t n,
+                                                      double *__restrict__ part) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kBlock)
+        acc = fma(ld<T>(F, e), (double)X[e], acc);
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// f = mu f_tensor + lam/2 (tr G_A + tr G_B + tr G_C)
+//     + 1/2 (||Y||^2 - <A, Y B> - <A, residual(Y) B>)
+// (the ratings term: sum r^2 = sum r y - sum r (a.b) = ||Y||^2 - <A,YB> - <A,RB>)
+__global__ __launch_bounds__(kBlock) void k_joint_f(const double *__restrict__ ft,
+                                                    const double *__restrict__ GA,
+                                                    const double *__restrict__ GB,
+                                                    const double *__restrict__ GC, int R,
+                                                    const double *__restrict__ part, int npart,
+                                                    double normsq_y, double mu, double lam,
+                                                    double *__restrict__ f) {
+    __shared__ double sh[kBlock];
+    double in = 0.0, tr = 0.0;
+    for (int b = threadIdx.x; b < npart; b += kBlock) in += part[b];
+    for (int r = threadIdx.x; r < R; r += kBlock) tr += GA[r * R + r] + GB[r * R + r] + GC[r * R + r];
+    in = block_sum(in, sh);
+    tr = block_sum(tr, sh);
+    if (threadIdx.x == 0) *f = mu * ft[0] + 0.5 * lam * tr + 0.5 * (normsq_y - in);
+}
+
 // 16-byte row loads are allowed when every row start is 16-byte aligned
 int vec_rows(const void *p, int R, int elem) {
     return ((uintptr_t)p % 16 == 0) && (((size_t)R * elem) % 16 == 0);
@@ -1419,6 +1534,54 @@ void launch_sumsq3(dfacto_ctx *ctx, const float *const x[3], const int64_t n[3],
                            n[m], part + m * kSumsqBlocks);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kBlock), 0, ctx->stream, part,
                        3 * kSumsqBlocks, out);
+    DF_LAUNCHED();
+}
+
+void launch_joint_rows(dfacto_ctx *ctx, const ModeData &md, const uint2 *range, int64_t nrows,
+                       const void *Fmid, const void *Fleaf, int R, const float *M,
+                       const double *H, double mu, double lam, void *out, dfacto_dtype dtype,
+                       int *flag) {
+    if (nrows <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>(nrows, 1 << 20);
+    if (dtype == DFACTO_F32)
+        hipLaunchKernelGGL(k_joint_rows<float>, dim3(grid), dim3(64), 0, ctx->stream, md.stream,
+                           range, nrows, (const float *)Fmid, (const float *)Fleaf, R, M, H, mu,
+                           lam, (float *)out, flag);
+    else
+        hipLaunchKernelGGL(k_joint_rows<uint16_t>, dim3(grid), dim3(64), 0, ctx->stream,
+                           md.stream, range, nrows, (const uint16_t *)Fmid,
+                           (const uint16_t *)Fleaf, R, M, H, mu, lam, (uint16_t *)out, flag);
+    DF_LAUNCHED();
+}
+
+void launch_joint_combine(dfacto_ctx *ctx, float *G, const void *F, const float *RY, double mu,
+                          double lam, int64_t n, dfacto_dtype dtype) {
+    if (n <= 0) return;
+    if (dtype == DFACTO_F32)
+        hipLaunchKernelGGL(k_joint_combine<float>, dim3(stream_grid(n)), dim3(kBlock), 0,
+                           ctx->stream, G, (const float *)F, RY, mu, lam, n);
+    else
+        hipLaunchKernelGGL(k_joint_combine<uint16_t>, dim3(stream_grid(n)), dim3(kBlock), 0,
+                           ctx->stream, G, (const uint16_t *)F, RY, mu, lam, n);
+    DF_LAUNCHED();
+}
+
+void launch_dot_parts(dfacto_ctx *ctx, const void *F, const float *X, int64_t n, double *part,
+                      dfacto_dtype dtype) {
+    if (dtype == DFACTO_F32)
+        hipLaunchKernelGGL(k_dot_parts<float>, dim3(kSumsqBlocks), dim3(kBlock), 0, ctx->stream,
+                           (const float *)F, X, n, part);
+    else
+        hipLaunchKernelGGL(k_dot_parts<uint16_t>, dim3(kSumsqBlocks), dim3(kBlock), 0,
+                           ctx->stream, (const uint16_t *)F, X, n, part);
+    DF_LAUNCHED();
+}
+
+void launch_joint_f(dfacto_ctx *ctx, const double *ft, const double *GA, const double *GB,
+                    const double *GC, int R, const double *part, int npart, double normsq_y,
+                    double mu, double lam, double *f) {
+    hipLaunchKernelGGL(k_joint_f, dim3(1), dim3(kBlock), 0, ctx->stream, ft, GA, GB, GC, R, part,
+                       npart, normsq_y, mu, lam, f);
     DF_LAUNCHED();
 }
 

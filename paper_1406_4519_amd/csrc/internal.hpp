@@ -124,6 +124,11 @@ struct dfacto_tensor {
     size_t bytes = 0;
     dfacto::ModeData mode[3];
     std::vector<void *> allocations;
+    // ratings matrix of the joint model (dims[2] == 1, built by
+    // dfacto_build_ratings): per output row of modes 0 and 1, the range
+    // [x, y) of its entries in that mode's stream ((0, 0) for an empty row)
+    bool ratings = false;
+    uint2 *row_range[2] = {nullptr, nullptr};
 };
 
 struct dfacto_ctx {
@@ -133,9 +138,9 @@ struct dfacto_ctx {
     bool sticky = false;
     std::string err;
     // growable device workspace, one slot per purpose
-    enum Slot { kM = 0, kCarry, kPartial, kSmall, kTrial, kNumSlots };
-    void *ws[kNumSlots] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    size_t ws_size[kNumSlots] = {0, 0, 0, 0, 0};
+    enum Slot { kM = 0, kCarry, kPartial, kSmall, kTrial, kJoint, kNumSlots };
+    void *ws[kNumSlots] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t ws_size[kNumSlots] = {0, 0, 0, 0, 0, 0};
     // kernel timing (dfacto_profile_*)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;  // created on demand, reused
@@ -176,12 +181,18 @@ dfacto_status build_flattenings_async_alloc(dfacto_ctx *ctx, const int64_t dims[
                                             const uint32_t *d_i, const uint32_t *d_j,
                                             const uint32_t *d_k, const float *d_val,
                                             dfacto_tensor **out);
+// per-row entry ranges of modes 0 and 1 (the joint model's ratings matrix)
+void build_row_ranges(dfacto_ctx *ctx, dfacto_tensor *t);
 void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const uint32_t *d_j,
                   const uint32_t *d_k, const float *d_val);
 
 // MTTKRP (mttkrp.hip)
 void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype,
                    const void *Fleaf, const void *Fmid, float *out);
+// residual MTTKRP over the stored entries (value x - sum_r root*mid*leaf)
+void launch_mttkrp_resid(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                         dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
+                         const void *Froot, float *out);
 MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
                          const float *out);
 bool mttkrp_small(const dfacto_tensor *t, int mode);
@@ -218,6 +229,18 @@ void launch_trial_factor(dfacto_ctx *ctx, const void *F, const float *G, double 
                          dfacto_dtype dtype, int64_t n);
 void launch_sumsq3(dfacto_ctx *ctx, const float *const x[3], const int64_t n[3], double *part,
                    double *out);
+// joint matrix completion + tensor factorization pieces (dense.hip)
+void launch_joint_rows(dfacto_ctx *ctx, const ModeData &md, const uint2 *range, int64_t nrows,
+                       const void *Fmid, const void *Fleaf, int R, const float *M,
+                       const double *H, double mu, double lam, void *out, dfacto_dtype dtype,
+                       int *flag);
+void launch_joint_combine(dfacto_ctx *ctx, float *G, const void *F, const float *RY, double mu,
+                          double lam, int64_t n, dfacto_dtype dtype);
+void launch_dot_parts(dfacto_ctx *ctx, const void *F, const float *X, int64_t n, double *part,
+                      dfacto_dtype dtype);
+void launch_joint_f(dfacto_ctx *ctx, const double *ft, const double *GA, const double *GB,
+                    const double *GC, int R, const double *part, int npart, double normsq_y,
+                    double mu, double lam, double *f);
 
 GramPlan gram_plan(int64_t rows, int R, const void *F, dfacto_dtype dtype);
 uint32_t gram_reduce_blocks(int R);

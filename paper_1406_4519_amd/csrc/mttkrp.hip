@@ -161,13 +161,20 @@ __device__ __forceinline__ void load_f32(const float *p, float (&v)[CPL]) {
 // SMALL: every row index is below 2^24, so row offsets are one 24-bit
 // multiply (idx * R < 2^32) instead of 64-bit arithmetic.
 // One work chunk (gid) per lane group of G lanes (lane = 0 .. G-1).
-template <typename T, int CPL, int G, int NCH, bool SMALL>
+// RES: the residual form used by the joint model's ratings term: each
+// nonzero's value x becomes x - xhat with xhat = sum_r F_root[root, r]
+// F_mid[mid, r] F_leaf[leaf, r] (the CP model at that entry), so the output
+// is the MTTKRP of the residual restricted to the stored entries.  The dot
+// product is reduced across the group's lanes by xor shuffles (every lane
+// ends with the same sum: each step adds two commuted operands).
+template <typename T, int CPL, int G, int NCH, bool SMALL, bool RES = false>
 __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
                                              const uint32_t *__restrict__ cstart, uint32_t nchunk,
                                              const T *__restrict__ Fleaf,
                                              const T *__restrict__ Fmid, int R,
                                              float *__restrict__ out, float *__restrict__ carry,
-                                             uint32_t gid, int lane) {
+                                             uint32_t gid, int lane,
+                                             const T *__restrict__ Froot = nullptr) {
     if (gid >= nchunk) return;
     const uint32_t cs = cstart[gid], ce = cstart[gid + 1];
     if (cs >= ce) return;
@@ -177,13 +184,14 @@ __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
     // branch and the loads of a batch stay in flight together.
     int col[NCH];
     bool act[NCH];
-    const T *leafb[NCH], *midb[NCH];
+    const T *leafb[NCH], *midb[NCH], *rootb[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         col[c] = (c * G + lane) * CPL;
         act[c] = col[c] < R;
         leafb[c] = Fleaf + (act[c] ? col[c] : 0);
         midb[c] = Fmid + (act[c] ? col[c] : 0);
+        rootb[c] = RES ? Froot + (act[c] ? col[c] : 0) : nullptr;
     }
     auto row_off = [&](uint32_t idx) -> size_t {
         if constexpr (SMALL) return (size_t)(uint32_t)__umul24(idx, (uint32_t)R);
@@ -191,6 +199,7 @@ __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
     };
 
     float acc[NCH][CPL], p[NCH][CPL], mrow[NCH][CPL];
+    float rrow[RES ? NCH : 1][CPL];  // the root's factor row (RES only)
     const uint2 h0 = st[cs];
     uint32_t row = h0.y;
     bool cont = !(h0.x & kRootBit);
@@ -199,6 +208,7 @@ __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
 #pragma unroll
         for (int q = 0; q < CPL; ++q) acc[c][q] = p[c][q] = 0.f;
         RowLoad<T, CPL>::load(midb[c] + row_off(h0.x & kIdxMask), mrow[c]);
+        if constexpr (RES) RowLoad<T, CPL>::load(rootb[c] + row_off(row), rrow[c]);
     }
 
     auto flush = [&](uint32_t r_out, bool is_cont) {
@@ -231,7 +241,18 @@ __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
     // F_leaf[leaf].
     auto step = [&](const uint2 &w, const float (&g)[NCH][CPL]) {
         const bool hdr = (int32_t)w.x < 0;
-        const float v = hdr ? 0.f : __uint_as_float(w.y);
+        float v = hdr ? 0.f : __uint_as_float(w.y);
+        if constexpr (RES) {
+            float part = 0.f;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                for (int q = 0; q < CPL; ++q)
+                    part = fmaf(act[c] ? rrow[c][q] * mrow[c][q] : 0.f, g[c][q], part);
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, G);
+            v = hdr ? 0.f : v - part;
+        }
 #pragma unroll
         for (int c = 0; c < NCH; ++c)
 #pragma unroll
@@ -249,6 +270,10 @@ __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
                 for (int q = 0; q < CPL; ++q) acc[c][q] = 0.f;
             cont = false;
             row = w.y;
+            if constexpr (RES) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) RowLoad<T, CPL>::load(rootb[c] + row_off(row), rrow[c]);
+            }
         }
     };
 
@@ -318,6 +343,16 @@ __global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_mttkrp(
     mttkrp_chunk<T, CPL, G, NCH, SMALL>(st, cstart, nchunk, Fleaf, Fmid, R, out, carry,
                                         (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G,
                                         threadIdx.x % G);
+}
+
+template <typename T, int CPL, int G, int NCH, bool SMALL>
+__global__ __launch_bounds__(kBlock) void k_mttkrp_res(
+    const uint2 *__restrict__ st, const uint32_t *__restrict__ cstart, uint32_t nchunk,
+    const T *__restrict__ Fleaf, const T *__restrict__ Fmid, const T *__restrict__ Froot, int R,
+    float *__restrict__ out, float *__restrict__ carry) {
+    mttkrp_chunk<T, CPL, G, NCH, SMALL, true>(st, cstart, nchunk, Fleaf, Fmid, R, out, carry,
+                                              (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G,
+                                              threadIdx.x % G, Froot);
 }
 
 // Grouped MTTKRP over many tensors of one kernel shape: a persistent grid
@@ -541,7 +576,7 @@ void with_shape(dfacto_dtype dtype, const MttkrpShape &sh, F &&f) {
 
 template <typename T, int CPL, int G, int NCH>
 void run(dfacto_ctx *ctx, const ModeData &md, int R, const void *Fleaf, const void *Fmid,
-         float *out, bool small) {
+         float *out, bool small, const void *Froot = nullptr) {
     hipStream_t s = ctx->stream;
     const uint32_t nchunk = (uint32_t)md.nchunk;
     float *carry = (float *)ws_get(ctx, dfacto_ctx::kCarry,
@@ -549,16 +584,29 @@ void run(dfacto_ctx *ctx, const ModeData &md, int R, const void *Fleaf, const vo
     constexpr int gpb = kBlock / G;  // groups per block
     if (nchunk > 0) {
         const unsigned blocks = (nchunk + gpb - 1) / gpb;
-        prof_mark(ctx);
-        if (small)
-            hipLaunchKernelGGL((k_mttkrp<T, CPL, G, NCH, true>), dim3(blocks), dim3(kBlock), 0, s,
-                               md.stream, md.chunk_start, nchunk, (const T *)Fleaf,
-                               (const T *)Fmid, R, out, carry);
-        else
-            hipLaunchKernelGGL((k_mttkrp<T, CPL, G, NCH, false>), dim3(blocks), dim3(kBlock), 0,
-                               s, md.stream, md.chunk_start, nchunk, (const T *)Fleaf,
-                               (const T *)Fmid, R, out, carry);
-        prof_mark(ctx);
+        if (Froot) {
+            if (small)
+                hipLaunchKernelGGL((k_mttkrp_res<T, CPL, G, NCH, true>), dim3(blocks),
+                                   dim3(kBlock), 0, s, md.stream, md.chunk_start, nchunk,
+                                   (const T *)Fleaf, (const T *)Fmid, (const T *)Froot, R, out,
+                                   carry);
+            else
+                hipLaunchKernelGGL((k_mttkrp_res<T, CPL, G, NCH, false>), dim3(blocks),
+                                   dim3(kBlock), 0, s, md.stream, md.chunk_start, nchunk,
+                                   (const T *)Fleaf, (const T *)Fmid, (const T *)Froot, R, out,
+                                   carry);
+        } else {
+            prof_mark(ctx);
+            if (small)
+                hipLaunchKernelGGL((k_mttkrp<T, CPL, G, NCH, true>), dim3(blocks), dim3(kBlock),
+                                   0, s, md.stream, md.chunk_start, nchunk, (const T *)Fleaf,
+                                   (const T *)Fmid, R, out, carry);
+            else
+                hipLaunchKernelGGL((k_mttkrp<T, CPL, G, NCH, false>), dim3(blocks), dim3(kBlock),
+                                   0, s, md.stream, md.chunk_start, nchunk, (const T *)Fleaf,
+                                   (const T *)Fmid, R, out, carry);
+            prof_mark(ctx);
+        }
     }
     const uint32_t nempty = (uint32_t)md.nempty;
     const uint32_t egroups = nempty == 0 ? 0u : std::min<uint32_t>(nempty, 65536u);
@@ -625,6 +673,22 @@ void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfa
         using T = typename decltype(tc)::type;
         run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(
             ctx, md, R, Fleaf, Fmid, out, sm);
+    });
+}
+
+void launch_mttkrp_resid(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                         dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
+                         const void *Froot, float *out) {
+    const ModeData &md = t->mode[mode];
+    // the root rows share the alignment rule of the gathered rows
+    MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out);
+    const MttkrpShape sr = mttkrp_shape(R, dtype, Froot, Froot, out);
+    if (sr.cpl < sh.cpl) sh = sr;
+    const bool sm = mttkrp_small(t, mode);
+    with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
+        using T = typename decltype(tc)::type;
+        run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(
+            ctx, md, R, Fleaf, Fmid, out, sm, Froot);
     });
 }
 

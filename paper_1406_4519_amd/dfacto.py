@@ -27,7 +27,8 @@ EXPORTS = (
     "dfacto_ctx_create", "dfacto_ctx_set_stream", "dfacto_ctx_synchronize", "dfacto_ctx_destroy",
     "dfacto_last_error", "dfacto_build_flattenings", "dfacto_tensor_get_info",
     "dfacto_tensor_export", "dfacto_tensor_destroy", "dfacto_mttkrp", "dfacto_als_iter",
-    "dfacto_gd_grad", "dfacto_gd_step", "dfacto_group_create", "dfacto_group_als", "dfacto_group_get_info",
+    "dfacto_gd_grad", "dfacto_gd_step", "dfacto_build_ratings", "dfacto_joint_grad",
+    "dfacto_joint_als_iter", "dfacto_group_create", "dfacto_group_als", "dfacto_group_get_info",
     "dfacto_group_destroy", "dfacto_server_create", "dfacto_server_submit", "dfacto_server_poll",
     "dfacto_server_wait", "dfacto_server_get_stats", "dfacto_server_destroy",
     "dfacto_profile_enable", "dfacto_profile_read",
@@ -119,6 +120,9 @@ def load():
     lib.dfacto_gd_grad.argtypes = [P, P, I, I, D, PP, PP, P]
     lib.dfacto_gd_step.argtypes = [P, P, I, I, D, PP, PP, ctypes.POINTER(_LineSearch),
                                    ctypes.POINTER(_GdStepInfo)]
+    lib.dfacto_build_ratings.argtypes = [P, ctypes.POINTER(ctypes.c_int64), I64, P, P, P, PP]
+    lib.dfacto_joint_grad.argtypes = [P, P, P, I, I, D, D, PP, PP, P]
+    lib.dfacto_joint_als_iter.argtypes = [P, P, P, I, I, D, D, PP]
     lib.dfacto_group_create.argtypes = [P, I, PP, ctypes.POINTER(ctypes.c_int), I, D, PP, PP, P,
                                         I, PP]
     lib.dfacto_group_als.argtypes = [P, P, I]
@@ -246,6 +250,44 @@ def build_flattenings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, k: t
     ctx.check(load().dfacto_build_flattenings(ctx.handle, d, n, _ptr(i), _ptr(j), _ptr(k), _ptr(val),
                                               ctypes.byref(h)))
     return Tensor(h)
+
+
+def build_ratings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, y: torch.Tensor) -> Tensor:
+    """The joint model's ratings matrix (users x items, observed entries)."""
+    for x in (i, j):
+        if x.dtype not in (torch.int32, torch.uint32) or not x.is_contiguous() or not x.is_cuda:
+            raise TypeError("indices must be contiguous int32/uint32 CUDA tensors")
+    if y.dtype != torch.float32 or not y.is_contiguous() or not y.is_cuda:
+        raise TypeError("ratings must be a contiguous float32 CUDA tensor")
+    n = int(y.numel())
+    if not (i.numel() == j.numel() == n):
+        raise ValueError("index and rating arrays differ in length")
+    d = (ctypes.c_int64 * 2)(*[int(x) for x in dims])
+    h = ctypes.c_void_p()
+    ctx.check(load().dfacto_build_ratings(ctx.handle, d, n, _ptr(i), _ptr(j), _ptr(y),
+                                          ctypes.byref(h)))
+    return Tensor(h)
+
+
+def joint_grad(ctx: Context, X: Tensor, Y: Tensor, factors, grads, f: torch.Tensor, mu: float,
+               lam: float):
+    """Gradients and objective of the joint matrix completion + tensor
+    factorization model at one point."""
+    dims, R, code = _check_factors(X, factors)
+    for m, g in enumerate(grads):
+        if g.dtype != torch.float32 or not g.is_contiguous() or tuple(g.shape) != (dims[m], R):
+            raise ValueError("gradients must be contiguous float32 (dims[m], R) tensors")
+    if f.dtype != torch.float64 or f.numel() < 1 or not f.is_cuda:
+        raise ValueError("f must be a float64 CUDA tensor")
+    ctx.check(load().dfacto_joint_grad(ctx.handle, X.handle, Y.handle, R, code, float(mu),
+                                       float(lam), _ptrs(factors), _ptrs(grads), _ptr(f)))
+
+
+def joint_als_iter(ctx: Context, X: Tensor, Y: Tensor, factors, mu: float, lam: float):
+    """One ALS iteration of the joint model; factors updated in place."""
+    dims, R, code = _check_factors(X, factors)
+    ctx.check(load().dfacto_joint_als_iter(ctx.handle, X.handle, Y.handle, R, code, float(mu),
+                                           float(lam), _ptrs(factors)))
 
 
 def tensor_get_info(t: Tensor) -> dict:
