@@ -354,6 +354,70 @@ def run_synthetic(args):
     ctx.close()
 
 
+def run_joint(args):
+    """Joint matrix completion + tensor factorization at the zipf50m shape:
+    X = the 1M x 500K x 200K, 50M-nonzero Zipf(1.1) tensor (users x items x
+    words) and Y = 10M distinct Zipf(1.1) ratings over the same users and
+    items (|N(0,1)| values), R = 32, FP32 factors, mu = 1, lam = 0.1: time
+    of one joint gradient (+ objective) and one joint ALS iteration."""
+    import numpy as np
+    import torch
+    from paper_1406_4519_amd import dfacto, gen
+
+    dev = torch.device("cuda:0")
+    coo, R, F0 = gen.zipf_50m()
+    yc = gen.zipf_distinct((coo.dims[0], coo.dims[1], 1), 10_000_000, 1.1, seed=31)
+    log("generated X and Y")
+    ctx = dfacto.Context(0)
+    X = dfacto.build_flattenings(ctx, coo.dims,
+                                 *[torch.from_numpy(a.view(np.int32)).to(dev)
+                                   for a in (coo.i, coo.j, coo.k)],
+                                 torch.from_numpy(coo.val).to(dev))
+    tb = time.perf_counter()
+    Y = dfacto.build_ratings(ctx, (coo.dims[0], coo.dims[1]),
+                             torch.from_numpy(yc.i.view(np.int32)).to(dev),
+                             torch.from_numpy(yc.j.view(np.int32)).to(dev),
+                             torch.from_numpy(yc.val).to(dev))
+    torch.cuda.synchronize()
+    yb_ms = (time.perf_counter() - tb) * 1e3
+    F = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(dev) for f in F0]
+    G = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in coo.dims]
+    f = torch.zeros(1, dtype=torch.float64, device=dev)
+    mu, lam = 1.0, 0.1
+    dfacto.joint_grad(ctx, X, Y, F, G, f, mu, lam)
+    dfacto.joint_als_iter(ctx, X, Y, F, mu, lam)
+    torch.cuda.synchronize()
+    reps = 5
+    ts = time.perf_counter()
+    for _ in range(reps):
+        dfacto.joint_grad(ctx, X, Y, F, G, f, mu, lam)
+    torch.cuda.synchronize()
+    grad_ms = (time.perf_counter() - ts) * 1e3 / reps
+    fs = []
+    ts = time.perf_counter()
+    for _ in range(3):
+        dfacto.joint_als_iter(ctx, X, Y, F, mu, lam)
+    torch.cuda.synchronize()
+    als_ms = (time.perf_counter() - ts) * 1e3 / 3
+    dfacto.joint_grad(ctx, X, Y, F, G, f, mu, lam)
+    torch.cuda.synchronize()
+    res = dict(ratings=yc.nnz, ratings_build_ms=round(yb_ms, 1), joint_grad_ms=round(grad_ms, 3),
+               joint_als_iter_ms=round(als_ms, 3), f_after=float(f.item()))
+    log(f"joint: {res}")
+    line = {"metric": "joint matrix completion + tensor factorization: ms per ALS iteration",
+            "value": res["joint_als_iter_ms"], "unit": "ms", "n_gpus": 1, "steps": 3, "warmup": 1,
+            "ms_per_step": res["joint_als_iter_ms"], "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "joint model: X = zipf50m (1M x 500K x 200K, 50M nonzeros), "
+                                   "Y = 10M Zipf(1.1) ratings over its users x items, R = 32, "
+                                   "mu = 1, lam = 0.1", "parallelism": "single GPU"},
+            "extra": res}
+    print(json.dumps(line), flush=True)
+    X.close()
+    Y.close()
+    ctx.close()
+
+
 def run_paper(args):
     """Paper-shape tensor on one GPU: 6.5M x 2.5M x 1.5M with 1.2B distinct
     coordinates, Zipf(1.2) per mode over seeded permutations, |N(0,1)| FP32
@@ -446,7 +510,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zipf50m",
-                    choices=["zipf50m", "small", "batched", "served", "paper1200m", "synthetic"])
+                    choices=["zipf50m", "small", "batched", "served", "paper1200m", "synthetic",
+                             "joint"])
     ap.add_argument("--batch", type=int, default=256, help="batched workload: number of tensors")
     ap.add_argument("--iters", type=int, default=20, help="batched workload: ALS iterations")
     ap.add_argument("--rate", type=float, default=200.0, help="served workload: arrivals per second")
@@ -488,6 +553,8 @@ def main():
         return run_paper(args)
     if args.workload == "synthetic":
         return run_synthetic(args)
+    if args.workload == "joint":
+        return run_joint(args)
 
     t0 = time.perf_counter()
     if args.workload == "zipf50m":

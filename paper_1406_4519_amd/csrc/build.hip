@@ -655,6 +655,34 @@ void build_row_ranges(dfacto_ctx *ctx, dfacto_tensor *t) {
         }
         t->row_range[m] = range;
     }
+    // rows longer than kJointSeg entries become segments of kJointSeg
+    std::vector<uint2> hr, seg[2];
+    std::vector<uint4> heavy[2];
+    for (int m = 0; m < 2; ++m) {
+        const int64_t rows = t->dims[t->mode[m].root];
+        hr.resize((size_t)rows);
+        DF_HIP(hipMemcpyAsync(hr.data(), t->row_range[m], sizeof(uint2) * (size_t)rows,
+                              hipMemcpyDeviceToHost, s));
+        DF_HIP(hipStreamSynchronize(s));
+        for (int64_t r = 0; r < rows; ++r) {
+            const uint32_t b = hr[r].x, e = hr[r].y;
+            if (e - b <= (uint32_t)kJointSeg) continue;
+            heavy[m].push_back(make_uint4((uint32_t)r, (uint32_t)seg[m].size(),
+                                          (e - b + kJointSeg - 1) / kJointSeg, 0u));
+            for (uint32_t x = b; x < e; x += kJointSeg)
+                seg[m].push_back(make_uint2(x, std::min<uint32_t>(e, x + kJointSeg)));
+        }
+        t->nseg[m] = (int64_t)seg[m].size();
+        t->nheavy[m] = (int64_t)heavy[m].size();
+        t->seg_range[m] = tensor_alloc<uint2>(t, t->nseg[m]);
+        t->heavy[m] = tensor_alloc<uint4>(t, t->nheavy[m]);
+        if (t->nseg[m] > 0) {
+            DF_HIP(hipMemcpyAsync(t->seg_range[m], seg[m].data(), sizeof(uint2) * seg[m].size(),
+                                  hipMemcpyHostToDevice, s));
+            DF_HIP(hipMemcpyAsync(t->heavy[m], heavy[m].data(), sizeof(uint4) * heavy[m].size(),
+                                  hipMemcpyHostToDevice, s));
+        }
+    }
     DF_HIP(hipStreamSynchronize(s));
 }
 

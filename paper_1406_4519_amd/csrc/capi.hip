@@ -554,8 +554,12 @@ dfacto_status dfacto_joint_als_iter(dfacto_ctx *ctx, const dfacto_tensor *X,
         }
         Small sw = small_ws(ctx, R);
         float *M = (float *)ws_get(ctx, dfacto_ctx::kM, sizeof(float) * (size_t)max_dim(X) * R);
-        char *w = (char *)ws_get(ctx, dfacto_ctx::kJoint, 256);
+        // ones row, then the heavy rows' partial systems
+        const int64_t nseg = std::max(Y->nseg[0], Y->nseg[1]);
+        char *w = (char *)ws_get(ctx, dfacto_ctx::kJoint,
+                                 256 + sizeof(double) * (size_t)(nseg * (R * R + R) + 1));
         void *one = ones_row(ctx, R, dtype, w);
+        double *part = (double *)(w + 256);
         DF_HIP(hipMemsetAsync(sw.flag, 0, 4 * sizeof(int), ctx->stream));
         launch_gram(ctx, d_F[1], dtype, X->dims[1], R, sw.G[1]);
         launch_gram(ctx, d_F[2], dtype, X->dims[2], R, sw.G[2]);
@@ -566,10 +570,9 @@ dfacto_status dfacto_joint_als_iter(dfacto_ctx *ctx, const dfacto_tensor *X,
             if (n < 2) {
                 // users (n = 0): entries (1, item); items (n = 1): entries (user, 1)
                 launch_hadamard(ctx, R, sw.G[p], sw.G[q], 0.0, sw.H[n]);
-                launch_joint_rows(ctx, Y->mode[n], Y->row_range[n], X->dims[n],
-                                  n == 0 ? one : d_F[0], n == 0 ? d_F[1] : one, R,
-                                  mu > 0.0 ? M : nullptr, sw.H[n], mu, lam, d_F[n], dtype,
-                                  sw.flag);
+                launch_joint_rows(ctx, Y, n, X->dims[n], n == 0 ? one : d_F[0],
+                                  n == 0 ? d_F[1] : one, R, mu > 0.0 ? M : nullptr, sw.H[n], mu,
+                                  lam, d_F[n], dtype, sw.flag, part);
             } else if (mu > 0.0) {
                 // words: C = mu M (mu H + lam I)^-1 = M (H + (lam / mu) I)^-1
                 launch_solve(ctx, R, sw.G[p], sw.G[q], lam / mu, sw.Hinv, sw.solve_scratch,

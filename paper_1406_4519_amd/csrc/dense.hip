@@ -950,17 +950,110 @@ __global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__
 }
 
 // ---- joint matrix completion + tensor factorization ----------------------
-// One ALS row of the joint model per wave (R <= 32): with the stored
-// entries of that row in a ratings stream (headers name the mid row,
+// One ALS row of the joint model per wave (R <= 32).  For the stored
+// entries of the row in a ratings stream (headers name the mid row,
 // nonzeros the leaf row and the rating y; the entry's vector is
-// v = F_mid[mid] * F_leaf[leaf], i.e. the other factor's row when the third
-// factor is a row of ones), form in FP64
+// v = F_mid[mid] * F_leaf[leaf], the other factor's row when the third
+// factor is a row of ones) the wave forms in FP64
 //   S = sum v^T v + mu H + lam I,   rhs = sum y v + mu M[row]
-// (lane l keeps column l of S in registers), invert S by the one-wave
-// Gauss-Jordan and write out[row] = rhs S^-1 in the factor dtype.  A row
-// whose S fails the positive-definiteness test is written as zeros and
-// raises *flag.
+// (lane l keeps column l of S in registers), inverts S by the one-wave
+// Gauss-Jordan and writes out[row] = rhs S^-1 in the factor dtype.
+// Entries are taken 64 at a time: each lane loads its entry's two rows
+// into LDS (all loads of a batch in flight together), then the wave adds
+// the batch's outer products.  Rows longer than kJointSeg entries are
+// split into segments whose partial (S, rhs) go to `part` and are summed in
+// segment order by k_joint_heavy.  A row whose S fails the
+// positive-definiteness test is written as zeros and raises *flag.
 constexpr int kJointRM = 32;
+constexpr int kJointRP = kJointRM + 1;  // padded LDS row of V
+
+template <typename T>
+__device__ void joint_accumulate(const uint2 *__restrict__ st, uint32_t e0, uint32_t e1,
+                                 const T *__restrict__ Fmid, const T *__restrict__ Fleaf, int R,
+                                 double (&col)[kJointRM], double &rhs, double *V, double *Yb) {
+    const int l = threadIdx.x;
+    const bool own = l < R;
+    // the fiber open at e0: its header is at most one fiber (<= kFiberCap
+    // nonzeros) before e0, and the row's first entry is a header
+    uint32_t cur_mid = 0;
+    if (!(st[e0].x & kHdrBit)) {
+        for (uint32_t back = 0; back < e0; back += 64) {
+            const uint32_t e = e0 - 1 - back - (uint32_t)l;  // e0 - 1 - back - l >= row start here
+            const bool in = back + (uint32_t)l < e0;
+            const uint2 w = in ? st[e] : make_uint2(0u, 0u);
+            const uint64_t h = __ballot(in && (w.x & kHdrBit));
+            if (h) {
+                const int src = __ffsll((unsigned long long)h) - 1;  // the nearest header
+                cur_mid = (uint32_t)__shfl((int)(w.x & kIdxMask), src);
+                break;
+            }
+        }
+    }
+    for (uint32_t b = e0; b < e1; b += 64) {
+        const uint32_t e = b + (uint32_t)l;
+        const bool in = e < e1;
+        const uint2 w = in ? st[e] : make_uint2(0u, 0u);
+        const bool hdr = in && (w.x & kHdrBit);
+        const bool nz = in && !(w.x & kHdrBit);
+        const uint64_t hm = __ballot(hdr);
+        const uint64_t upto = hm & (l == 63 ? ~0ull : ((2ull << l) - 1ull));
+        const uint32_t midx = w.x & kIdxMask;
+        const uint32_t lastm = hm ? (uint32_t)__shfl((int)midx, 63 - __clzll((long long)hm)) : 0u;
+        const uint32_t srcm = upto ? (uint32_t)__shfl((int)midx, 63 - __clzll((long long)upto)) : 0u;
+        const uint32_t my_mid = upto ? srcm : cur_mid;
+        if (hm) cur_mid = lastm;
+        if (nz) {
+            const T *pm = Fmid + (int64_t)my_mid * R;
+            const T *pl = Fleaf + (int64_t)w.x * R;
+            for (int r = 0; r < R; ++r) V[l * kJointRP + r] = ld<T>(pm, r) * ld<T>(pl, r);
+            Yb[l] = (double)__uint_as_float(w.y);
+        }
+        __syncthreads();
+        uint64_t nm = __ballot(nz);
+        while (nm) {
+            const int t = __ffsll((unsigned long long)nm) - 1;
+            nm &= nm - 1;
+            const double vl = own ? V[t * kJointRP + l] : 0.0;
+            rhs = fma(Yb[t], vl, rhs);
+#pragma unroll
+            for (int i = 0; i < kJointRM; ++i)
+                if (i < R) col[i] = fma(V[t * kJointRP + i], vl, col[i]);
+        }
+        __syncthreads();
+    }
+}
+
+// S = col + mu H + lam I, rhs += mu M[row]; solve and store out[row]
+template <typename T>
+__device__ void joint_solve_store(double (&col)[kJointRM], double rhs, int64_t row, int R,
+                                  const float *__restrict__ M, const double *__restrict__ H,
+                                  double mu, double lam, T *__restrict__ out,
+                                  int *__restrict__ flag, double *S, double *Si) {
+    const int l = threadIdx.x;
+    const bool own = l < R;
+    if (own) {
+        if (M) rhs = fma(mu, (double)M[row * R + l], rhs);
+#pragma unroll
+        for (int i = 0; i < kJointRM; ++i)
+            if (i < R) S[i * R + l] = col[i] + mu * H[i * R + l] + (i == l ? lam : 0.0);
+    }
+    __syncthreads();
+    double dm = own ? S[l * R + l] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+    const bool ok = dm > 0.0 && gauss_jordan_wave(S, R, (double)R * DBL_EPSILON * dm, Si);
+    __syncthreads();
+    double x = 0.0;
+    unroll_for<0, kJointRM>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if (i < R) x = fma(readlane_f64(rhs, i), own ? Si[i * R + l] : 0.0, x);
+    });
+    if (own) st_out<T>(out, row * R + l, ok ? x : 0.0);
+    if (!ok && l == 0) atomicOr(flag, 1);
+    __syncthreads();
+}
+
+// every row of at most kJointSeg entries: accumulate, solve, store
 template <typename T>
 __global__ __launch_bounds__(64) void k_joint_rows(const uint2 *__restrict__ st,
                                                    const uint2 *__restrict__ range, int64_t nrows,
@@ -970,49 +1063,73 @@ __global__ __launch_bounds__(64) void k_joint_rows(const uint2 *__restrict__ st,
                                                    const double *__restrict__ H, double mu,
                                                    double lam, T *__restrict__ out,
                                                    int *__restrict__ flag) {
+    __shared__ double V[64 * kJointRP], Yb[64];
     __shared__ double S[kJointRM * kJointRM], Si[kJointRM * kJointRM];
-    const int l = threadIdx.x;
-    const bool own = l < R;
     for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
+        const uint2 rg = range[row];
+        if (rg.y - rg.x > (uint32_t)kJointSeg) continue;  // a heavy row: segments below
         double col[kJointRM];
 #pragma unroll
-        for (int i = 0; i < kJointRM; ++i)
-            col[i] = (own && i < R) ? mu * H[i * R + l] + (i == l ? lam : 0.0) : 0.0;
-        double rhs = (own && M) ? mu * (double)M[row * R + l] : 0.0;
-        const uint2 rg = range[row];
-        double mv = 0.0;
-        for (uint32_t e = rg.x; e < rg.y; ++e) {
-            const uint2 w = st[e];
-            if (w.x & kHdrBit) {
-                mv = own ? ld<T>(Fmid, (int64_t)(w.x & kIdxMask) * R + l) : 0.0;
-                continue;
-            }
-            const double v = own ? mv * ld<T>(Fleaf, (int64_t)w.x * R + l) : 0.0;
-            rhs = fma((double)__uint_as_float(w.y), v, rhs);
-            unroll_for<0, kJointRM>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                if (i < R) col[i] = fma(readlane_f64(v, i), v, col[i]);
-            });
-        }
-        if (own) {
+        for (int i = 0; i < kJointRM; ++i) col[i] = 0.0;
+        double rhs = 0.0;
+        if (rg.y > rg.x) joint_accumulate<T>(st, rg.x, rg.y, Fmid, Fleaf, R, col, rhs, V, Yb);
+        joint_solve_store<T>(col, rhs, row, R, M, H, mu, lam, out, flag, S, Si);
+    }
+}
+
+// one segment of a heavy row: partial S (R x R, row-major) and rhs (R)
+template <typename T>
+__global__ __launch_bounds__(64) void k_joint_segments(const uint2 *__restrict__ st,
+                                                       const uint2 *__restrict__ seg,
+                                                       int64_t nseg, const T *__restrict__ Fmid,
+                                                       const T *__restrict__ Fleaf, int R,
+                                                       double *__restrict__ part) {
+    __shared__ double V[64 * kJointRP], Yb[64];
+    const int l = threadIdx.x;
+    for (int64_t q = blockIdx.x; q < nseg; q += gridDim.x) {
+        const uint2 sg = seg[q];
+        double col[kJointRM];
+#pragma unroll
+        for (int i = 0; i < kJointRM; ++i) col[i] = 0.0;
+        double rhs = 0.0;
+        joint_accumulate<T>(st, sg.x, sg.y, Fmid, Fleaf, R, col, rhs, V, Yb);
+        double *P = part + q * (int64_t)(R * R + R);
+        if (l < R) {
 #pragma unroll
             for (int i = 0; i < kJointRM; ++i)
-                if (i < R) S[i * R + l] = col[i];
+                if (i < R) P[i * R + l] = col[i];
+            P[R * R + l] = rhs;
         }
-        __syncthreads();
-        double dm = own ? S[l * R + l] : 0.0;
+    }
+}
+
+// a heavy row: the sum of its segments' partials in segment order, solved
+template <typename T>
+__global__ __launch_bounds__(64) void k_joint_heavy(const uint4 *__restrict__ heavy,
+                                                    int64_t nheavy, int R,
+                                                    const double *__restrict__ part,
+                                                    const float *__restrict__ M,
+                                                    const double *__restrict__ H, double mu,
+                                                    double lam, T *__restrict__ out,
+                                                    int *__restrict__ flag) {
+    __shared__ double S[kJointRM * kJointRM], Si[kJointRM * kJointRM];
+    const int l = threadIdx.x;
+    for (int64_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
+        const uint4 hv = heavy[h];  // (row, first segment, segments, 0)
+        double col[kJointRM];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
-        const bool ok = dm > 0.0 && gauss_jordan_wave(S, R, (double)R * DBL_EPSILON * dm, Si);
-        __syncthreads();
-        double x = 0.0;
-        unroll_for<0, kJointRM>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            if (i < R) x = fma(readlane_f64(rhs, i), own ? Si[i * R + l] : 0.0, x);
-        });
-        if (own) st_out<T>(out, row * R + l, ok ? x : 0.0);
-        if (!ok && l == 0) atomicOr(flag, 1);
-        __syncthreads();
+        for (int i = 0; i < kJointRM; ++i) col[i] = 0.0;
+        double rhs = 0.0;
+        for (uint32_t q = hv.y; q < hv.y + hv.z; ++q) {
+            const double *P = part + (int64_t)q * (R * R + R);
+            if (l < R) {
+#pragma unroll
+                for (int i = 0; i < kJointRM; ++i)
+                    if (i < R) col[i] += P[i * R + l];
+                rhs += P[R * R + l];
+            }
+        }
+        joint_solve_store<T>(col, rhs, (int64_t)hv.x, R, M, H, mu, lam, out, flag, S, Si);
     }
 }
 
@@ -1537,20 +1654,32 @@ void launch_sumsq3(dfacto_ctx *ctx, const float *const x[3], const int64_t n[3],
     DF_LAUNCHED();
 }
 
-void launch_joint_rows(dfacto_ctx *ctx, const ModeData &md, const uint2 *range, int64_t nrows,
+void launch_joint_rows(dfacto_ctx *ctx, const dfacto_tensor *Y, int m, int64_t nrows,
                        const void *Fmid, const void *Fleaf, int R, const float *M,
                        const double *H, double mu, double lam, void *out, dfacto_dtype dtype,
-                       int *flag) {
+                       int *flag, double *part) {
     if (nrows <= 0) return;
+    hipStream_t s = ctx->stream;
+    const uint2 *st = Y->mode[m].stream;
     const unsigned grid = (unsigned)std::min<int64_t>(nrows, 1 << 20);
-    if (dtype == DFACTO_F32)
-        hipLaunchKernelGGL(k_joint_rows<float>, dim3(grid), dim3(64), 0, ctx->stream, md.stream,
-                           range, nrows, (const float *)Fmid, (const float *)Fleaf, R, M, H, mu,
-                           lam, (float *)out, flag);
-    else
-        hipLaunchKernelGGL(k_joint_rows<uint16_t>, dim3(grid), dim3(64), 0, ctx->stream,
-                           md.stream, range, nrows, (const uint16_t *)Fmid,
-                           (const uint16_t *)Fleaf, R, M, H, mu, lam, (uint16_t *)out, flag);
+    const int64_t nseg = Y->nseg[m], nheavy = Y->nheavy[m];
+    const unsigned gseg = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nseg, 1 << 20));
+    const unsigned ghv = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nheavy, 1 << 20));
+#define DF_JOINT(T)                                                                            \
+    hipLaunchKernelGGL(k_joint_rows<T>, dim3(grid), dim3(64), 0, s, st, Y->row_range[m], nrows, \
+                       (const T *)Fmid, (const T *)Fleaf, R, M, H, mu, lam, (T *)out, flag);    \
+    if (nseg > 0) {                                                                            \
+        hipLaunchKernelGGL(k_joint_segments<T>, dim3(gseg), dim3(64), 0, s, st,               \
+                           Y->seg_range[m], nseg, (const T *)Fmid, (const T *)Fleaf, R, part); \
+        hipLaunchKernelGGL(k_joint_heavy<T>, dim3(ghv), dim3(64), 0, s, Y->heavy[m], nheavy,  \
+                           R, part, M, H, mu, lam, (T *)out, flag);                            \
+    }
+    if (dtype == DFACTO_F32) {
+        DF_JOINT(float)
+    } else {
+        DF_JOINT(uint16_t)
+    }
+#undef DF_JOINT
     DF_LAUNCHED();
 }
 

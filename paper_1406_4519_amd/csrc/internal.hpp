@@ -129,6 +129,11 @@ struct dfacto_tensor {
     // [x, y) of its entries in that mode's stream ((0, 0) for an empty row)
     bool ratings = false;
     uint2 *row_range[2] = {nullptr, nullptr};
+    // rows of more than kJointSeg entries, split into segments: seg_range[m]
+    // (begin, end) per segment, heavy[m] (row, first segment, segments, 0)
+    uint2 *seg_range[2] = {nullptr, nullptr};
+    uint4 *heavy[2] = {nullptr, nullptr};
+    int64_t nseg[2] = {0, 0}, nheavy[2] = {0, 0};
 };
 
 struct dfacto_ctx {
@@ -230,10 +235,11 @@ void launch_trial_factor(dfacto_ctx *ctx, const void *F, const float *G, double 
 void launch_sumsq3(dfacto_ctx *ctx, const float *const x[3], const int64_t n[3], double *part,
                    double *out);
 // joint matrix completion + tensor factorization pieces (dense.hip)
-void launch_joint_rows(dfacto_ctx *ctx, const ModeData &md, const uint2 *range, int64_t nrows,
+constexpr int kJointSeg = 4096;  // entries per joint-ALS work item
+void launch_joint_rows(dfacto_ctx *ctx, const dfacto_tensor *Y, int m, int64_t nrows,
                        const void *Fmid, const void *Fleaf, int R, const float *M,
                        const double *H, double mu, double lam, void *out, dfacto_dtype dtype,
-                       int *flag);
+                       int *flag, double *part);
 void launch_joint_combine(dfacto_ctx *ctx, float *G, const void *F, const float *RY, double mu,
                           double lam, int64_t n, dfacto_dtype dtype);
 void launch_dot_parts(dfacto_ctx *ctx, const void *F, const float *X, int64_t n, double *part,

@@ -110,3 +110,37 @@ def test_joint_argument_errors(ctx, problem):
     dfacto.joint_grad(ctx, X, Y, Fd, G, f, 1.0, 0.1)
     torch.cuda.synchronize()
     assert np.isfinite(f.item())
+
+
+@pytest.mark.parametrize("R", [8, 32])
+def test_joint_als_heavy_rows(ctx, R):
+    """Rows longer than one work segment (4096 stream entries): a user with
+    9,000 ratings (segments start inside a fiber) and an item rated by 2,400
+    users; their partial systems are summed in segment order."""
+    dims = (2500, 12000, 50)
+    coo = gen.zipf_distinct(dims, 30_000, 1.1, seed=85)
+    rng = np.random.default_rng(86)
+    lin = rng.choice(dims[0] * dims[1], size=5000, replace=False)
+    yi, yj = (lin // dims[1]).astype(np.uint32), (lin % dims[1]).astype(np.uint32)
+    keep = (yi != 5) & (yj != 7)
+    hu = np.sort(rng.choice(dims[1], 9000, replace=False)).astype(np.uint32)
+    hi = np.sort(rng.choice(np.setdiff1d(np.arange(dims[0]), [5]), 2400, replace=False)).astype(np.uint32)
+    hu = hu[hu != 7]
+    yi = np.concatenate([yi[keep], np.full(len(hu), 5, np.uint32), hi])
+    yj = np.concatenate([yj[keep], hu, np.full(len(hi), 7, np.uint32)])
+    yv = rng.integers(1, 6, len(yi)).astype(np.float32)
+    X = build(ctx, coo)
+    dv = [torch.from_numpy(a.view(np.int32)).to(DEV) for a in (yi, yj)]
+    Y = dfacto.build_ratings(ctx, dims[:2], dv[0], dv[1], torch.from_numpy(yv).to(DEV))
+    F0 = gen.init_factors(coo.dims, R, seed=87)
+    Fd, Fw = factors_to_dev(F0, "f32")
+    dfacto.joint_als_iter(ctx, X, Y, Fd, 0.5, 0.2)
+    torch.cuda.synchronize()
+    A, B, C, _ = oracle.joint_als_iter(*coo.arrays64(), coo.dims, yi, yj, yv.astype(np.float64),
+                                       Fw, 0.5, 0.2)
+    errs = [rel_fro(to_host64(Fd[m]), x) for m, x in enumerate((A, B, C))]
+    rows = [rel_fro(to_host64(Fd[0])[5], A[5]), rel_fro(to_host64(Fd[1])[7], B[7])]
+    say(f"  heavy rows R={R}: factor errors {errs}, heavy user / item rows {rows}")
+    assert max(errs) <= 1e-5 and max(rows) <= 1e-5
+    X.close()
+    Y.close()
