@@ -956,8 +956,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__
 // v = F_mid[mid] * F_leaf[leaf], the other factor's row when the third
 // factor is a row of ones) the wave forms in FP64
 //   S = sum v^T v + mu H + lam I,   rhs = sum y v + mu M[row]
-// (lane l keeps column l of S in registers), inverts S by the one-wave
-// Gauss-Jordan and writes out[row] = rhs S^-1 in the factor dtype.
+// (lane l keeps column l of S in registers), solves S x = rhs by Cholesky
+// and writes out[row] = x in the factor dtype.
 // Entries are taken 64 at a time: each lane loads its entry's two rows
 // into LDS (all loads of a batch in flight together), then the wave adds
 // the batch's outer products.  Rows longer than kJointSeg entries are
@@ -1023,32 +1023,67 @@ __device__ void joint_accumulate(const uint2 *__restrict__ st, uint32_t e0, uint
     }
 }
 
-// S = col + mu H + lam I, rhs += mu M[row]; solve and store out[row]
+// S = col + mu H + lam I, rhs += mu M[row]; solve S x = rhs by a Cholesky
+// factorization in LDS (one wave; lanes share each step's updates) with the
+// pivot test d_j > R eps max diag(S), then forward and back substitution;
+// store out[row] = x
 template <typename T>
 __device__ void joint_solve_store(double (&col)[kJointRM], double rhs, int64_t row, int R,
                                   const float *__restrict__ M, const double *__restrict__ H,
                                   double mu, double lam, T *__restrict__ out,
-                                  int *__restrict__ flag, double *S, double *Si) {
+                                  int *__restrict__ flag, double *S, double *b) {
     const int l = threadIdx.x;
     const bool own = l < R;
     if (own) {
         if (M) rhs = fma(mu, (double)M[row * R + l], rhs);
 #pragma unroll
         for (int i = 0; i < kJointRM; ++i)
-            if (i < R) S[i * R + l] = col[i] + mu * H[i * R + l] + (i == l ? lam : 0.0);
+            if (i < R) S[i * R + l] = col[i];
+        b[l] = rhs;
     }
+    __syncthreads();
+    // + mu H + lam I, lane-strided once the accumulator is in LDS (loading H
+    // beside the register accumulator would double the register footprint)
+    for (int q = l; q < R * R; q += 64) S[q] += mu * H[q] + ((q / R == q % R) ? lam : 0.0);
     __syncthreads();
     double dm = own ? S[l * R + l] : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
-    const bool ok = dm > 0.0 && gauss_jordan_wave(S, R, (double)R * DBL_EPSILON * dm, Si);
-    __syncthreads();
-    double x = 0.0;
-    unroll_for<0, kJointRM>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        if (i < R) x = fma(readlane_f64(rhs, i), own ? Si[i * R + l] : 0.0, x);
-    });
-    if (own) st_out<T>(out, row * R + l, ok ? x : 0.0);
+    const double tol = (double)R * DBL_EPSILON * dm;
+    bool ok = dm > 0.0;
+    for (int j = 0; j < R && ok; ++j) {
+        const double d = S[j * R + j];  // the Schur-complement pivot
+        ok = d > tol;
+        if (!ok) break;
+        const double sd = sqrt(d);
+        __syncthreads();
+        if (l > j && l < R) S[l * R + j] /= sd;
+        if (l == j) S[j * R + j] = sd;
+        __syncthreads();
+        const int m = R - j - 1;  // trailing block (j, R) x (j, R)
+        for (int q = l; q < m * m; q += 64) {
+            const int i = j + 1 + q / m, k = j + 1 + q % m;
+            S[i * R + k] = fma(-S[i * R + j], S[k * R + j], S[i * R + k]);
+        }
+        __syncthreads();
+    }
+    if (ok) {
+        for (int j = 0; j < R; ++j) {  // L y = b
+            const double yj = b[j] / S[j * R + j];
+            __syncthreads();
+            if (l > j && l < R) b[l] = fma(-S[l * R + j], yj, b[l]);
+            if (l == j) b[j] = yj;
+            __syncthreads();
+        }
+        for (int j = R - 1; j >= 0; --j) {  // L^T x = y
+            const double xj = b[j] / S[j * R + j];
+            __syncthreads();
+            if (l < j) b[l] = fma(-S[j * R + l], xj, b[l]);
+            if (l == j) b[j] = xj;
+            __syncthreads();
+        }
+    }
+    if (own) st_out<T>(out, row * R + l, ok ? b[l] : 0.0);
     if (!ok && l == 0) atomicOr(flag, 1);
     __syncthreads();
 }
@@ -1064,7 +1099,7 @@ __global__ __launch_bounds__(64) void k_joint_rows(const uint2 *__restrict__ st,
                                                    double lam, T *__restrict__ out,
                                                    int *__restrict__ flag) {
     __shared__ double V[64 * kJointRP], Yb[64];
-    __shared__ double S[kJointRM * kJointRM], Si[kJointRM * kJointRM];
+    __shared__ double S[kJointRM * kJointRM], b[kJointRM];
     for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
         const uint2 rg = range[row];
         if (rg.y - rg.x > (uint32_t)kJointSeg) continue;  // a heavy row: segments below
@@ -1073,7 +1108,7 @@ __global__ __launch_bounds__(64) void k_joint_rows(const uint2 *__restrict__ st,
         for (int i = 0; i < kJointRM; ++i) col[i] = 0.0;
         double rhs = 0.0;
         if (rg.y > rg.x) joint_accumulate<T>(st, rg.x, rg.y, Fmid, Fleaf, R, col, rhs, V, Yb);
-        joint_solve_store<T>(col, rhs, row, R, M, H, mu, lam, out, flag, S, Si);
+        joint_solve_store<T>(col, rhs, row, R, M, H, mu, lam, out, flag, S, b);
     }
 }
 
@@ -1112,7 +1147,7 @@ __global__ __launch_bounds__(64) void k_joint_heavy(const uint4 *__restrict__ he
                                                     const double *__restrict__ H, double mu,
                                                     double lam, T *__restrict__ out,
                                                     int *__restrict__ flag) {
-    __shared__ double S[kJointRM * kJointRM], Si[kJointRM * kJointRM];
+    __shared__ double S[kJointRM * kJointRM], b[kJointRM];
     const int l = threadIdx.x;
     for (int64_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
         const uint4 hv = heavy[h];  // (row, first segment, segments, 0)
@@ -1129,7 +1164,7 @@ __global__ __launch_bounds__(64) void k_joint_heavy(const uint4 *__restrict__ he
                 rhs += P[R * R + l];
             }
         }
-        joint_solve_store<T>(col, rhs, (int64_t)hv.x, R, M, H, mu, lam, out, flag, S, Si);
+        joint_solve_store<T>(col, rhs, (int64_t)hv.x, R, M, H, mu, lam, out, flag, S, b);
     }
 }
 
