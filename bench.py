@@ -186,25 +186,6 @@ def run_served(args):
     and batched continuously.  Reported per storage dtype: completed solves
     per second over the run and p50 / p99 latency from submission to factors
     on the host."""
-    dts = args.served_dtypes.split(",")
-    if len(dts) > 1:
-        # one fresh process per storage dtype, as a server starts: consecutive
-        # servers in one process were measured to run slower
-        import subprocess
-        out, n = {}, 0
-        for dt in dts:
-            cmd = [sys.executable, "-u", os.path.abspath(__file__), "--workload", "served",
-                   "--served-dtypes", dt, "--rate", str(args.rate), "--duration",
-                   str(args.duration), "--large-frac", str(args.large_frac), "--pool",
-                   str(args.pool)]
-            r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
-            if r.returncode != 0:
-                raise SystemExit(f"served run for {dt} failed with exit status {r.returncode}")
-            child = json.loads(r.stdout.strip().splitlines()[-1])
-            out[dt] = child["extra"][dt]
-            n = child["steps"]
-        served_line(args, n, out)
-        return
     import numpy as np
     from paper_1406_4519_amd import dfacto, gen
 

@@ -122,7 +122,10 @@ dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int
             throw Error{DFACTO_E_UNSUPPORTED, "nnz must be below 2^32 - 2^20"};
         dfacto_tensor *t = new dfacto_tensor();
         t->device = ctx->device;
-        if (async_alloc) t->alloc_stream = ctx->stream;
+        if (async_alloc) {
+            t->alloc_stream = ctx->stream;
+            t->alloc_pool = ctx->pool;
+        }
         for (int m = 0; m < 3; ++m) t->dims[m] = dims[m];
         t->nnz = nnz;
         try {
@@ -438,8 +441,8 @@ dfacto_status dfacto_build_ratings(dfacto_ctx *ctx, const int64_t dims[2], int64
         if (!out || !dims) throw Error{DFACTO_E_INVALID, "dims or out is NULL"};
         if (n < 0) throw Error{DFACTO_E_INVALID, "n is negative"};
         uint32_t *k0 = nullptr;
-        hip_check(hipMallocAsync((void **)&k0, sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1),
-                                 ctx->stream),
+        hip_check(stream_alloc((void **)&k0, sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1),
+                               ctx->stream, ctx->pool),
                   "ratings staging");
         DF_HIP(hipMemsetAsync(k0, 0, sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1),
                               ctx->stream));

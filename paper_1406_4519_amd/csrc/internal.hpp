@@ -118,6 +118,7 @@ struct dfacto_tensor {
     // when set, the tensor's memory is stream-ordered (hipMallocAsync on this
     // stream) and freeing it does not wait for unrelated device work
     hipStream_t alloc_stream = nullptr;
+    hipMemPool_t alloc_pool = nullptr;  // pool of those allocations (null: the device default)
     int64_t dims[3] = {0, 0, 0};
     int64_t nnz = 0;
     double normsq = 0.0;
@@ -139,6 +140,9 @@ struct dfacto_tensor {
 struct dfacto_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // memory pool for the stream-ordered allocations made on this context's
+    // behalf (null: the device's default pool)
+    hipMemPool_t pool = nullptr;
     int num_cu = 0;
     bool sticky = false;
     std::string err;
@@ -163,6 +167,11 @@ struct Error {
 };
 
 dfacto_status fail(dfacto_ctx *ctx, dfacto_status code, const std::string &msg);
+
+// stream-ordered allocation from `pool`, or from the device default pool
+inline hipError_t stream_alloc(void **p, size_t bytes, hipStream_t s, hipMemPool_t pool) {
+    return pool ? hipMallocFromPoolAsync(p, bytes, pool, s) : hipMallocAsync(p, bytes, s);
+}
 void hip_check(hipError_t e, const char *what);  // throws Error on failure
 #define DF_HIP(call) ::dfacto::hip_check((call), #call)
 // after kernel launches: a launch error names the launching function
@@ -178,7 +187,8 @@ void prof_mark(dfacto_ctx *ctx);
 // ---------------------------------------------------------------------------
 
 // device-wide primitives (build.hip)
-void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s);
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s,
+                        hipMemPool_t pool = nullptr);
 
 // builder (build.hip): fills t (allocates its arrays).  Synchronizes.
 // dfacto_build_flattenings with stream-ordered tensor memory on ctx's stream

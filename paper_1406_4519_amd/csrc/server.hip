@@ -93,6 +93,10 @@ struct dfacto_server {
     dfacto_ctx *ctx = nullptr;  // the worker's context (own stream)
     hipStream_t stream = nullptr;
     hipStream_t dstream = nullptr;  // the delivery thread's stream
+    // the server's own pool for every stream-ordered allocation it makes; it
+    // keeps freed memory mapped (the default pool unmaps it at each
+    // synchronization, which made a long-running server progressively slower)
+    hipMemPool_t pool = nullptr;
     static constexpr int kBuilders = 2;
     dfacto_ctx *bctx[kBuilders] = {};  // the builders' contexts (own streams)
     hipStream_t bstream[kBuilders] = {};
@@ -191,10 +195,10 @@ void admit(dfacto_server *s, int b, Member &m, double *t_build) {
         if (dv) (void)hipFreeAsync(dv, st);
     };
     try {
-        hip_check(hipMallocAsync((void **)&di, 4 * n, st), "request upload");
-        hip_check(hipMallocAsync((void **)&dj, 4 * n, st), "request upload");
-        hip_check(hipMallocAsync((void **)&dk, 4 * n, st), "request upload");
-        hip_check(hipMallocAsync((void **)&dv, 4 * n, st), "request upload");
+        hip_check(stream_alloc((void **)&di, 4 * n, st, s->pool), "request upload");
+        hip_check(stream_alloc((void **)&dj, 4 * n, st, s->pool), "request upload");
+        hip_check(stream_alloc((void **)&dk, 4 * n, st, s->pool), "request upload");
+        hip_check(stream_alloc((void **)&dv, 4 * n, st, s->pool), "request upload");
         if (r.nnz > 0) {
             DF_HIP(hipMemcpyAsync(di, r.i, 4 * r.nnz, hipMemcpyHostToDevice, st));
             DF_HIP(hipMemcpyAsync(dj, r.j, 4 * r.nnz, hipMemcpyHostToDevice, st));
@@ -212,11 +216,11 @@ void admit(dfacto_server *s, int b, Member &m, double *t_build) {
         const size_t es = r.dtype == DFACTO_BF16 ? 2 : 4;
         for (int k = 0; k < 3; ++k) {
             const size_t cnt = (size_t)r.dims[k] * r.R;
-            hip_check(hipMallocAsync(&m.F[k], std::max<size_t>(es * cnt, 16), st),
+            hip_check(stream_alloc(&m.F[k], std::max<size_t>(es * cnt, 16), st, s->pool),
                       "factor allocation");
             if (r.dtype == DFACTO_BF16) {  // FP32 upload, rounded to BF16 on the device
                 float *tmp = nullptr;
-                hip_check(hipMallocAsync((void **)&tmp, 4 * cnt, st), "factor staging");
+                hip_check(stream_alloc((void **)&tmp, 4 * cnt, st, s->pool), "factor staging");
                 DF_HIP(hipMemcpyAsync(tmp, r.init[k], 4 * cnt, hipMemcpyHostToDevice, st));
                 hipLaunchKernelGGL(k_f32_to_bf16, dim3(convert_grid((int64_t)cnt)), dim3(256), 0,
                                    st, tmp, (uint16_t *)m.F[k], (int64_t)cnt);
@@ -226,7 +230,8 @@ void admit(dfacto_server *s, int b, Member &m, double *t_build) {
                 DF_HIP(hipMemcpyAsync(m.F[k], r.init[k], 4 * cnt, hipMemcpyHostToDevice, st));
             }
         }
-        hip_check(hipMallocAsync((void **)&m.lambda, 8 * (size_t)r.R, st), "lambda allocation");
+        hip_check(stream_alloc((void **)&m.lambda, 8 * (size_t)r.R, st, s->pool),
+                  "lambda allocation");
         DF_HIP(hipStreamSynchronize(st));
         m.footprint = std::max(m.footprint, m.tensor->bytes + footprint_estimate(r) -
                                                 3 * 16 * (size_t)r.nnz);
@@ -249,7 +254,7 @@ void deliver(dfacto_server *s, Member &m) {
             if (!r.out_F[k]) continue;
             if (r.dtype == DFACTO_BF16) {
                 float *tmp = nullptr;
-                hip_check(hipMallocAsync((void **)&tmp, 4 * cnt, st), "result staging");
+                hip_check(stream_alloc((void **)&tmp, 4 * cnt, st, s->pool), "result staging");
                 tmps.push_back(tmp);
                 hipLaunchKernelGGL(k_bf16_to_f32, dim3(convert_grid((int64_t)cnt)), dim3(256), 0,
                                    st, (const uint16_t *)m.F[k], tmp, (int64_t)cnt);
@@ -524,6 +529,23 @@ dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
             delete s;
             return DFACTO_E_DEVICE;
         }
+    {
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = device;
+        uint64_t keep = UINT64_MAX;
+        if (hipMemPoolCreate(&s->pool, &props) != hipSuccess ||
+            hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+            (void)hipGetLastError();
+            if (s->pool) (void)hipMemPoolDestroy(s->pool);
+            for (int b = 0; b < dfacto_server::kBuilders; ++b) (void)hipStreamDestroy(s->bstream[b]);
+            (void)hipStreamDestroy(s->dstream);
+            (void)hipStreamDestroy(s->stream);
+            delete s;
+            return DFACTO_E_DEVICE;
+        }
+    }
     if (hbm_budget == 0) {  // default: 90% of the free device memory
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) hbm_budget = fr / 10 * 9;
@@ -533,6 +555,10 @@ dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
               dfacto_ctx_create(device, s->stream, &s->ctx) == DFACTO_OK;
     for (int b = 0; ok && b < dfacto_server::kBuilders; ++b)
         ok = dfacto_ctx_create(device, s->bstream[b], &s->bctx[b]) == DFACTO_OK;
+    if (ok) {
+        s->ctx->pool = s->pool;
+        for (int b = 0; b < dfacto_server::kBuilders; ++b) s->bctx[b]->pool = s->pool;
+    }
     if (!ok) {
         (void)hipGetLastError();
         if (s->ctx) dfacto_ctx_destroy(s->ctx);
@@ -541,6 +567,7 @@ dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
             (void)hipStreamDestroy(s->bstream[b]);
         }
         if (s->d_fits) (void)hipFree(s->d_fits);
+        (void)hipMemPoolDestroy(s->pool);
         (void)hipStreamDestroy(s->dstream);
         (void)hipStreamDestroy(s->stream);
         delete s;
@@ -640,10 +667,9 @@ void dfacto_server_destroy(dfacto_server *s) {
     }
     if (s->dstream) (void)hipStreamDestroy(s->dstream);
     if (s->stream) (void)hipStreamDestroy(s->stream);
-    // give the stream-ordered memory the server freed back to the device
-    hipMemPool_t pool = nullptr;
-    if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess && pool)
-        (void)hipMemPoolTrimTo(pool, 0);
+    // every allocation from the pool has been freed and its stream finished
+    (void)hipDeviceSynchronize();
+    if (s->pool) (void)hipMemPoolDestroy(s->pool);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete s;
 }
