@@ -507,6 +507,8 @@ def main():
                     help="served workload: factor storage dtypes, run in this order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-factor side run")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches instead of a HIP graph replay of the step")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB "
@@ -589,6 +591,46 @@ def main():
         el = time.perf_counter() - ts
         prof = dfacto.profile_read(ctx)
         dfacto.profile_enable(ctx, False)
+        el_eager = el
+        graph_ok = None
+        if not args.no_graph:
+            # the same step captured once as a HIP graph and replayed; its
+            # first replay must equal an eager step from the same state
+            state = [x.clone() for x in (*F, lam, fit)]
+            step()
+            torch.cuda.synchronize()
+            eager = [x.clone() for x in (*F, lam, fit, *G, fval)]
+            for x, y in zip((*F, lam, fit), state):
+                x.copy_(y)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            main = torch.cuda.current_stream()
+            try:
+                with torch.cuda.graph(g, stream=side):
+                    ctx.set_stream(side)
+                    step()
+            finally:
+                ctx.set_stream(main)
+            g.replay()
+            torch.cuda.synchronize()
+            got = [x.clone() for x in (*F, lam, fit, *G, fval)]
+            graph_ok = all(torch.equal(a.view(torch.int16) if a.dtype == torch.bfloat16 else a,
+                                       b.view(torch.int16) if b.dtype == torch.bfloat16 else b)
+                           for a, b in zip(got, eager))
+            if graph_ok:
+                for _ in range(2):
+                    g.replay()
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                for _ in range(args.steps):
+                    g.replay()
+                torch.cuda.synchronize()
+                el = time.perf_counter() - ts
+            else:
+                log("graph replay differs from the eager step: timing the eager steps")
+            del g
         # per-call timings (separately, after the timed region)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         reps = max(3, min(args.steps, 10))
@@ -627,8 +669,9 @@ def main():
             gd_iters.append(dict(ms=round((time.perf_counter() - tg) * 1e3, 3),
                                  trials=inf["trials"], alpha=inf["alpha"], f=inf["f"]))
             a0 = 2.0 * inf["alpha"] if inf["accepted"] else a0
-        return dict(elapsed=el, prof=prof, als_ms=als_ms, gd_ms=gd_ms, mttkrp_ms=mt_ms,
-                    fit=fit_v, f=f_v, gd_iters=gd_iters)
+        return dict(elapsed=el, elapsed_eager=el_eager, graph_ok=graph_ok, prof=prof,
+                    als_ms=als_ms, gd_ms=gd_ms, mttkrp_ms=mt_ms, fit=fit_v, f=f_v,
+                    gd_iters=gd_iters)
 
     r32 = run("f32")
     nnz = info["nnz"]
@@ -644,7 +687,10 @@ def main():
                 "kernel": "k_mttkrp (main MTTKRP kernel, all 3 modes)",
                 "launches": prof["launches"], "avg_launch_ms": round(avg_ms, 4),
                 "alg_bytes_per_launch": round(bytes_per_launch)}
-    extra = {"build_ms": round(build_ms, 1), "als_iter_ms": round(r32["als_ms"], 3),
+    extra = {"timed_as": "HIP graph replay of the step" if r32["graph_ok"] else "eager launches",
+             "graph_replay_equals_eager": r32["graph_ok"],
+             "ms_per_step_eager": round(r32["elapsed_eager"] * 1e3 / args.steps, 4),
+             "build_ms": round(build_ms, 1), "als_iter_ms": round(r32["als_ms"], 3),
              "gd_grad_ms": round(r32["gd_ms"], 3),
              "mttkrp_ms": [round(x, 4) for x in r32["mttkrp_ms"]],
              "mttkrp_nnzR_per_s": [round(nnz * R / (x * 1e-3)) for x in r32["mttkrp_ms"]],
@@ -656,6 +702,8 @@ def main():
         pb = rb["prof"]
         ab = pb["ms"] / max(pb["launches"], 1)
         extra["bf16"] = {"ms_per_step": round(rb["elapsed"] * 1e3 / args.steps, 4),
+                         "ms_per_step_eager": round(rb["elapsed_eager"] * 1e3 / args.steps, 4),
+                         "graph_replay_equals_eager": rb["graph_ok"],
                          "value": 6.0 * nnz * R * args.steps / rb["elapsed"],
                          "als_iter_ms": round(rb["als_ms"], 3), "gd_grad_ms": round(rb["gd_ms"], 3),
                          "mttkrp_ms": [round(x, 4) for x in rb["mttkrp_ms"]],
