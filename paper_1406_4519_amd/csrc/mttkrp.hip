@@ -450,7 +450,20 @@ __device__ __forceinline__ void long_run(const float *__restrict__ carry, int R,
         for (int q = 0; q < CPL; ++q) acc[c][q] = 0.f;
         const int col = (c * G + lane) * CPL;
         if (col >= R) continue;
-        for (uint32_t k = slice; k < n; k += S) {
+        // eight loads in flight, then the adds in the same order as one at
+        // a time (k, k + S, k + 2S, ...): the sum is bitwise the same
+        uint32_t k = slice;
+        for (; k + 7u * S < n; k += 8u * S) {
+            float v[8][CPL];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                load_f32<CPL>(carry + (size_t)(c0 + k + u * S) * R + col, v[u]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) acc[c][q] += v[u][q];
+        }
+        for (; k < n; k += S) {
             float v[CPL];
             load_f32<CPL>(carry + (size_t)(c0 + k) * R + col, v);
 #pragma unroll
