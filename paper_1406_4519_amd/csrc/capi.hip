@@ -65,6 +65,22 @@ void check_align(const void *p, dfacto_dtype d, const char *name) {
         throw Error{DFACTO_E_INVALID, std::string(name) + " is not aligned to its element size"};
 }
 
+// the context's side stream and its fork / join events, created once
+void ensure_side(dfacto_ctx *ctx) {
+    if (ctx->side) return;
+    DF_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    DF_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    DF_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+}
+
+// launches made while alive go to `s` (the launchers use ctx->stream)
+struct OnStream {
+    dfacto_ctx *ctx;
+    hipStream_t saved;
+    OnStream(dfacto_ctx *c, hipStream_t s) : ctx(c), saved(c->stream) { c->stream = s; }
+    ~OnStream() { ctx->stream = saved; }
+};
+
 int64_t max_dim(const dfacto_tensor *t) {
     return std::max(t->dims[0], std::max(t->dims[1], t->dims[2]));
 }
@@ -188,6 +204,12 @@ void dfacto_ctx_destroy(dfacto_ctx *ctx) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     for (int s = 0; s < dfacto_ctx::kNumSlots; ++s)
         if (ctx->ws[s]) (void)hipFree(ctx->ws[s]);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -312,14 +334,24 @@ dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, df
         }
         Small sw = small_ws(ctx, R);
         float *M = (float *)ws_get(ctx, dfacto_ctx::kM, sizeof(float) * (size_t)max_dim(t) * R);
+        ensure_side(ctx);
         launch_gram(ctx, d_F[1], dtype, t->dims[1], R, sw.G[1]);
         launch_gram(ctx, d_F[2], dtype, t->dims[2], R, sw.G[2]);
         for (int n = 0; n < 3; ++n) {
             const int p = (n + 1) % 3, q = (n + 2) % 3;
             const ModeData &md = t->mode[n];
-            launch_solve(ctx, R, sw.G[p], sw.G[q], reg, sw.Hinv, sw.solve_scratch, sw.flag + n);
+            // the R x R solve needs only the other modes' Grams: it runs on
+            // the side stream beside this mode's MTTKRP, joined before use
+            DF_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
+            DF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+            {
+                OnStream on(ctx, ctx->side);
+                launch_solve(ctx, R, sw.G[p], sw.G[q], reg, sw.Hinv, sw.solve_scratch, sw.flag + n);
+            }
+            DF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
             launch_mttkrp(ctx, t, n, R, dtype, d_F[md.leaf], d_F[md.mid], M);
             launch_gram(ctx, M, DFACTO_F32, t->dims[n], R, sw.MtM);
+            DF_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
             launch_als_lambda(ctx, R, n, sw.Hinv, sw.MtM, sw.G[n], sw.W, d_lambda, sw.G[0],
                               sw.G[1], t->normsq, d_fit, sw.lam_scratch);
             launch_rowmap(ctx, M, t->dims[n], R, sw.W, d_F[n], dtype);

@@ -143,6 +143,10 @@ struct dfacto_ctx {
     // memory pool for the stream-ordered allocations made on this context's
     // behalf (null: the device's default pool)
     hipMemPool_t pool = nullptr;
+    // a second stream for work that overlaps the main stream's (created on
+    // first use), joined back by events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int num_cu = 0;
     bool sticky = false;
     std::string err;
