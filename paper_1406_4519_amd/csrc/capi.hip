@@ -70,6 +70,7 @@ void ensure_side(dfacto_ctx *ctx) {
     if (ctx->side) return;
     DF_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
     DF_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    DF_HIP(hipEventCreateWithFlags(&ctx->ev_step, hipEventDisableTiming));
     DF_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
 }
 
@@ -210,6 +211,7 @@ void dfacto_ctx_destroy(dfacto_ctx *ctx) {
     }
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_step) (void)hipEventDestroy(ctx->ev_step);
     for (int s = 0; s < dfacto_ctx::kNumSlots; ++s)
         if (ctx->ws[s]) (void)hipFree(ctx->ws[s]);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -378,18 +380,36 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfa
             if ((uintptr_t)d_G[m] % 4) throw Error{DFACTO_E_INVALID, "gradient not aligned"};
         }
         Small sw = small_ws(ctx, R);
-        for (int m = 0; m < 3; ++m) launch_gram(ctx, d_F[m], dtype, t->dims[m], R, sw.G[m]);
-        for (int n = 0; n < 3; ++n)
-            launch_hadamard(ctx, R, sw.G[(n + 1) % 3], sw.G[(n + 2) % 3], reg, sw.H[n]);
+        ensure_side(ctx);
+        // the three MTTKRPs run back to back on the main stream; the Grams
+        // and each mode's gradient rows (which need only that mode's MTTKRP)
+        // run on the side stream beside the next MTTKRP; joined at the end
+        const hipStream_t main = ctx->stream;
+        DF_HIP(hipEventRecord(ctx->ev_fork, main));
+        DF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+        {
+            OnStream on(ctx, ctx->side);
+            for (int m = 0; m < 3; ++m) launch_gram(ctx, d_F[m], dtype, t->dims[m], R, sw.G[m]);
+            for (int n = 0; n < 3; ++n)
+                launch_hadamard(ctx, R, sw.G[(n + 1) % 3], sw.G[(n + 2) % 3], reg, sw.H[n]);
+        }
         for (int n = 0; n < 3; ++n) {
             const ModeData &md = t->mode[n];
             launch_mttkrp(ctx, t, n, R, dtype, d_F[md.leaf], d_F[md.mid], d_G[n]);
+            DF_HIP(hipEventRecord(ctx->ev_step, main));
+            DF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_step, 0));
+            OnStream on(ctx, ctx->side);
             launch_gd_rows(ctx, d_G[n], d_F[n], dtype, t->dims[n], R, sw.H[n],
                            n == 0 ? sw.part0 : sw.part_dummy);
         }
-        launch_gd_f(ctx, R, sw.G[0], sw.G[1], sw.G[2], sw.part0,
-                    gd_rows_partials(t->dims[0], R, d_G[0], d_F[0], dtype),
-                    t->normsq, reg, d_f);
+        {
+            OnStream on(ctx, ctx->side);
+            launch_gd_f(ctx, R, sw.G[0], sw.G[1], sw.G[2], sw.part0,
+                        gd_rows_partials(t->dims[0], R, d_G[0], d_F[0], dtype),
+                        t->normsq, reg, d_f);
+        }
+        DF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+        DF_HIP(hipStreamWaitEvent(main, ctx->ev_join, 0));
     });
 }
 

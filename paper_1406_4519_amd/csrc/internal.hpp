@@ -146,7 +146,7 @@ struct dfacto_ctx {
     // a second stream for work that overlaps the main stream's (created on
     // first use), joined back by events
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_step = nullptr;
     int num_cu = 0;
     bool sticky = false;
     std::string err;
