@@ -956,47 +956,72 @@ __global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__
 // v = F_mid[mid] * F_leaf[leaf], the other factor's row when the third
 // factor is a row of ones) the wave forms in FP64
 //   S = sum v^T v + mu H + lam I,   rhs = sum y v + mu M[row]
-// (lane l keeps column l of S in registers), solves S x = rhs by Cholesky
-// and writes out[row] = x in the factor dtype.
-// Entries are taken 64 at a time: each lane loads its entry's two rows
-// into LDS (all loads of a batch in flight together), then the wave adds
-// the batch's outer products.  Rows longer than kJointSeg entries are
-// split into segments whose partial (S, rhs) go to `part` and are summed in
-// segment order by k_joint_heavy.  A row whose S fails the
-// positive-definiteness test is written as zeros and raises *flag.
-constexpr int kJointRM = 32;
-constexpr int kJointRP = kJointRM + 1;  // padded LDS row of V
+// solves S x = rhs by Cholesky and writes out[row] = x in the factor dtype.
+// Register layout: lane (h, r) = (lane / 32, lane % 32) keeps
+// S[r][2k + h], k < 16, so both half-waves work on the row; entries, rows
+// and columns beyond R are zero.  Entries are taken 32 at a time (two lanes
+// load each entry's vector into LDS, all loads of a batch in flight
+// together), then the wave adds the batch's outer products in entry order.
+// Rows longer than kJointSeg entries are split into segments whose partial
+// (S, rhs) go to `part` and are summed in segment order by k_joint_heavy.
+// A row whose S fails the positive-definiteness test is written as zeros and
+// raises *flag.
+constexpr int kJointRM = 32;            // largest rank
+constexpr int kJointRP = kJointRM + 1;  // padded LDS row
+constexpr int kJointK = kJointRM / 2;   // columns of S per lane
+constexpr int kJointB = 32;             // entries per batch
 
-template <typename T>
+// lane `src`'s v (src uniform) in every lane
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const long long x = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(x & 0xffffffffll), src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), src);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// lane (h, r): p[k] = (mu H + lam I)[r][2k + h] (zero outside R x R)
+__device__ __forceinline__ void joint_shift(const double *__restrict__ H, int R, double mu,
+                                            double lam, double (&p)[kJointK]) {
+    const int h = threadIdx.x >> 5, r = threadIdx.x & 31;
+#pragma unroll
+    for (int k = 0; k < kJointK; ++k) {
+        const int q = 2 * k + h;
+        p[k] = (r < R && q < R) ? mu * H[r * R + q] + (q == r ? lam : 0.0) : 0.0;
+    }
+}
+
+// c[k] += sum over the entries [e0, e1) of v[r] v[2k + h]; rhs += sum y v[r]
+template <typename T, bool kSegment>
 __device__ void joint_accumulate(const uint2 *__restrict__ st, uint32_t e0, uint32_t e1,
                                  const T *__restrict__ Fmid, const T *__restrict__ Fleaf, int R,
-                                 double (&col)[kJointRM], double &rhs, double *V, double *Yb) {
-    const int l = threadIdx.x;
-    const bool own = l < R;
-    // the fiber open at e0: its header is at most one fiber (<= kFiberCap
-    // nonzeros) before e0, and the row's first entry is a header
+                                 double (&c)[kJointK], double &rhs, double *V, double *Yb) {
+    const int l = threadIdx.x, h = l >> 5, t = l & 31;
+    // a segment may start inside a fiber: the fiber's header is at most one
+    // fiber (<= kFiberCap nonzeros) before e0, and the row's first entry is a
+    // header (a whole row starts with one)
     uint32_t cur_mid = 0;
-    if (!(st[e0].x & kHdrBit)) {
+    if (kSegment && !(st[e0].x & kHdrBit)) {
         for (uint32_t back = 0; back < e0; back += 64) {
             const uint32_t e = e0 - 1 - back - (uint32_t)l;  // e0 - 1 - back - l >= row start here
             const bool in = back + (uint32_t)l < e0;
             const uint2 w = in ? st[e] : make_uint2(0u, 0u);
-            const uint64_t h = __ballot(in && (w.x & kHdrBit));
-            if (h) {
-                const int src = __ffsll((unsigned long long)h) - 1;  // the nearest header
+            const uint64_t hb = __ballot(in && (w.x & kHdrBit));
+            if (hb) {
+                const int src = __ffsll((unsigned long long)hb) - 1;  // the nearest header
                 cur_mid = (uint32_t)__shfl((int)(w.x & kIdxMask), src);
                 break;
             }
         }
     }
-    for (uint32_t b = e0; b < e1; b += 64) {
-        const uint32_t e = b + (uint32_t)l;
+    for (uint32_t b = e0; b < e1; b += kJointB) {
+        // entry t of the batch in lanes t and t + 32
+        const uint32_t e = b + (uint32_t)t;
         const bool in = e < e1;
         const uint2 w = in ? st[e] : make_uint2(0u, 0u);
         const bool hdr = in && (w.x & kHdrBit);
         const bool nz = in && !(w.x & kHdrBit);
-        const uint64_t hm = __ballot(hdr);
-        const uint64_t upto = hm & (l == 63 ? ~0ull : ((2ull << l) - 1ull));
+        const uint64_t hm = __ballot(hdr) & 0xffffffffull;
+        const uint64_t upto = hm & ((2ull << t) - 1ull);
         const uint32_t midx = w.x & kIdxMask;
         const uint32_t lastm = hm ? (uint32_t)__shfl((int)midx, 63 - __clzll((long long)hm)) : 0u;
         const uint32_t srcm = upto ? (uint32_t)__shfl((int)midx, 63 - __clzll((long long)upto)) : 0u;
@@ -1005,90 +1030,103 @@ __device__ void joint_accumulate(const uint2 *__restrict__ st, uint32_t e0, uint
         if (nz) {
             const T *pm = Fmid + (int64_t)my_mid * R;
             const T *pl = Fleaf + (int64_t)w.x * R;
-            for (int r = 0; r < R; ++r) V[l * kJointRP + r] = ld<T>(pm, r) * ld<T>(pl, r);
-            Yb[l] = (double)__uint_as_float(w.y);
+#pragma unroll
+            for (int k = 0; k < kJointK; ++k) {
+                const int q = 2 * k + h;
+                V[t * kJointRP + q] = q < R ? ld<T>(pm, q) * ld<T>(pl, q) : 0.0;
+            }
+            if (h == 0) Yb[t] = (double)__uint_as_float(w.y);
         }
         __syncthreads();
-        uint64_t nm = __ballot(nz);
+        uint64_t nm = __ballot(nz) & 0xffffffffull;
         while (nm) {
-            const int t = __ffsll((unsigned long long)nm) - 1;
+            const int u = __ffsll((unsigned long long)nm) - 1;
             nm &= nm - 1;
-            const double vl = own ? V[t * kJointRP + l] : 0.0;
-            rhs = fma(Yb[t], vl, rhs);
+            const double vr = V[u * kJointRP + t];  // v[r]: zero for r >= R
+            rhs = fma(Yb[u], vr, rhs);
 #pragma unroll
-            for (int i = 0; i < kJointRM; ++i)
-                if (i < R) col[i] = fma(V[t * kJointRP + i], vl, col[i]);
+            for (int k = 0; k < kJointK; ++k) c[k] = fma(V[u * kJointRP + 2 * k + h], vr, c[k]);
         }
         __syncthreads();
     }
 }
 
-// S = col + mu H + lam I, rhs += mu M[row]; solve S x = rhs by a Cholesky
-// factorization in LDS (one wave; lanes share each step's updates) with the
-// pivot test d_j > R eps max diag(S), then forward and back substitution;
-// store out[row] = x
+// S = c + p (p = mu H + lam I in the same layout); b = rhs (lane (h, r)
+// holds rhs[r]).  Cholesky S = L L^T with
+// the pivot test d_j > R eps max diag(S), forward substitution folded into
+// the factorization, then L^T x = y after one transpose of L through LDS;
+// out[row] = x.  Lc (2 x 32 doubles) carries the current column of L,
+// Tl (32 x kJointRP doubles) the transpose.
 template <typename T>
-__device__ void joint_solve_store(double (&col)[kJointRM], double rhs, int64_t row, int R,
-                                  const float *__restrict__ M, const double *__restrict__ H,
-                                  double mu, double lam, T *__restrict__ out,
-                                  int *__restrict__ flag, double *S, double *b) {
-    const int l = threadIdx.x;
-    const bool own = l < R;
-    if (own) {
-        if (M) rhs = fma(mu, (double)M[row * R + l], rhs);
+__device__ void joint_solve_store(double (&c)[kJointK], double b, const double (&p)[kJointK],
+                                  int64_t row, int R, T *__restrict__ out,
+                                  int *__restrict__ flag, double *Lc, double *Tl) {
+    const int l = threadIdx.x, h = l >> 5, r = l & 31;
+    double dl = 0.0;
 #pragma unroll
-        for (int i = 0; i < kJointRM; ++i)
-            if (i < R) S[i * R + l] = col[i];
-        b[l] = rhs;
+    for (int k = 0; k < kJointK; ++k) {
+        const int q = 2 * k + h;
+        c[k] += p[k];
+        if (q == r) dl = c[k];
     }
-    __syncthreads();
-    // + mu H + lam I, lane-strided once the accumulator is in LDS (loading H
-    // beside the register accumulator would double the register footprint)
-    for (int q = l; q < R * R; q += 64) S[q] += mu * H[q] + ((q / R == q % R) ? lam : 0.0);
-    __syncthreads();
-    double dm = own ? S[l * R + l] : 0.0;
+    double dm = dl;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
     const double tol = (double)R * DBL_EPSILON * dm;
     bool ok = dm > 0.0;
-    for (int j = 0; j < R && ok; ++j) {
-        const double d = S[j * R + j];  // the Schur-complement pivot
-        ok = d > tol;
-        if (!ok) break;
-        const double sd = sqrt(d);
-        __syncthreads();
-        if (l > j && l < R) S[l * R + j] /= sd;
-        if (l == j) S[j * R + j] = sd;
-        __syncthreads();
-        const int m = R - j - 1;  // trailing block (j, R) x (j, R)
-        for (int q = l; q < m * m; q += 64) {
-            const int i = j + 1 + q / m, k = j + 1 + q % m;
-            S[i * R + k] = fma(-S[i * R + j], S[k * R + j], S[i * R + k]);
+    double myinv = 0.0;  // 1 / L[r][r]
+    // fully unrolled (no early exit): every index into c is a constant
+#pragma unroll
+    for (int j = 0; j < kJointRM; ++j) {
+        const int jh = j & 1, jk = j >> 1;
+        const double d = lane_bcast(c[jk], jh * 32 + j);  // the Schur-complement pivot
+        if (j < R && ok) ok = d > tol;
+        if (j < R && ok) {
+            const double inv = rsqrt(d);
+            double *lc = Lc + jh * 32;  // two buffers: no barrier before the next write
+            if (h == jh) lc[r] = r > j ? c[jk] * inv : 0.0;
+            const double yj = lane_bcast(b, j) * inv;
+            if (r == j) myinv = inv;
+            __syncthreads();
+            const double lr = lc[r];  // L[r][j], zero for r <= j
+            if (h == jh && r > j) c[jk] = lr;
+            b = r == j ? yj : fma(-lr, yj, b);
+            double lk[kJointK];  // all reads of the column in flight together
+#pragma unroll
+            for (int k = jk; k < kJointK; ++k) lk[k] = lc[2 * k + h];
+#pragma unroll
+            for (int k = jk; k < kJointK; ++k) c[k] = fma(-lr, lk[k], c[k]);
         }
-        __syncthreads();
     }
     if (ok) {
-        for (int j = 0; j < R; ++j) {  // L y = b
-            const double yj = b[j] / S[j * R + j];
-            __syncthreads();
-            if (l > j && l < R) b[l] = fma(-S[l * R + j], yj, b[l]);
-            if (l == j) b[j] = yj;
-            __syncthreads();
+        // L^T x = y: lane (h, r) keeps lt[k] = L[2k + h][r] and in acc the
+        // sum of L[j][r] x_j over the solved j of its parity h, so
+        // x_j = (y_j - acc(0, j) - acc(1, j)) / L[j][j]
+#pragma unroll
+        for (int k = 0; k < kJointK; ++k) Tl[r * kJointRP + 2 * k + h] = c[k];
+        __syncthreads();
+        double lt[kJointK];
+#pragma unroll
+        for (int k = 0; k < kJointK; ++k) lt[k] = Tl[(2 * k + h) * kJointRP + r];
+        double acc = 0.0, x = 0.0;
+#pragma unroll
+        for (int j = kJointRM - 1; j >= 0; --j) {
+            if (j < R) {
+                const double xj = (lane_bcast(b - acc, j) - lane_bcast(acc, 32 + j)) *
+                                  lane_bcast(myinv, j);
+                if (r == j) x = xj;
+                if (h == (j & 1) && r < j) acc = fma(lt[j >> 1], xj, acc);
+            }
         }
-        for (int j = R - 1; j >= 0; --j) {  // L^T x = y
-            const double xj = b[j] / S[j * R + j];
-            __syncthreads();
-            if (l < j) b[l] = fma(-S[j * R + l], xj, b[l]);
-            if (l == j) b[j] = xj;
-            __syncthreads();
-        }
+        b = x;
     }
-    if (own) st_out<T>(out, row * R + l, ok ? b[l] : 0.0);
+    __syncthreads();  // Tl and Lc are free again
+    if (h == 0 && r < R) st_out<T>(out, row * R + r, ok ? b : 0.0);
     if (!ok && l == 0) atomicOr(flag, 1);
-    __syncthreads();
 }
 
 // every row of at most kJointSeg entries: accumulate, solve, store
+// (persistent grid: each workgroup forms mu H + lam I once and walks rows)
 template <typename T>
 __global__ __launch_bounds__(64) void k_joint_rows(const uint2 *__restrict__ st,
                                                    const uint2 *__restrict__ range, int64_t nrows,
@@ -1098,17 +1136,23 @@ __global__ __launch_bounds__(64) void k_joint_rows(const uint2 *__restrict__ st,
                                                    const double *__restrict__ H, double mu,
                                                    double lam, T *__restrict__ out,
                                                    int *__restrict__ flag) {
-    __shared__ double V[64 * kJointRP], Yb[64];
-    __shared__ double S[kJointRM * kJointRM], b[kJointRM];
+    __shared__ double V[kJointB * kJointRP], Yb[kJointB], Lc[2 * 32];
+    const int r = threadIdx.x & 31;
+    double p[kJointK];
+    joint_shift(H, R, mu, lam, p);
+    uint2 next = blockIdx.x < nrows ? range[blockIdx.x] : make_uint2(0u, 0u);
     for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
-        const uint2 rg = range[row];
+        const uint2 rg = next;  // the next row's range is read while this one is solved
+        if (row + gridDim.x < nrows) next = range[row + gridDim.x];
         if (rg.y - rg.x > (uint32_t)kJointSeg) continue;  // a heavy row: segments below
-        double col[kJointRM];
+        const double m = (M && r < R) ? (double)M[row * R + r] : 0.0;
+        double c[kJointK];
 #pragma unroll
-        for (int i = 0; i < kJointRM; ++i) col[i] = 0.0;
+        for (int k = 0; k < kJointK; ++k) c[k] = 0.0;
         double rhs = 0.0;
-        if (rg.y > rg.x) joint_accumulate<T>(st, rg.x, rg.y, Fmid, Fleaf, R, col, rhs, V, Yb);
-        joint_solve_store<T>(col, rhs, row, R, M, H, mu, lam, out, flag, S, b);
+        if (rg.y > rg.x) joint_accumulate<T, false>(st, rg.x, rg.y, Fmid, Fleaf, R, c, rhs, V, Yb);
+        if (M) rhs = fma(mu, m, rhs);
+        joint_solve_store<T>(c, rhs, p, row, R, out, flag, Lc, V);
     }
 }
 
@@ -1119,21 +1163,21 @@ __global__ __launch_bounds__(64) void k_joint_segments(const uint2 *__restrict__
                                                        int64_t nseg, const T *__restrict__ Fmid,
                                                        const T *__restrict__ Fleaf, int R,
                                                        double *__restrict__ part) {
-    __shared__ double V[64 * kJointRP], Yb[64];
-    const int l = threadIdx.x;
+    __shared__ double V[kJointB * kJointRP], Yb[kJointB];
+    const int h = threadIdx.x >> 5, r = threadIdx.x & 31;
     for (int64_t q = blockIdx.x; q < nseg; q += gridDim.x) {
         const uint2 sg = seg[q];
-        double col[kJointRM];
+        double c[kJointK];
 #pragma unroll
-        for (int i = 0; i < kJointRM; ++i) col[i] = 0.0;
+        for (int k = 0; k < kJointK; ++k) c[k] = 0.0;
         double rhs = 0.0;
-        joint_accumulate<T>(st, sg.x, sg.y, Fmid, Fleaf, R, col, rhs, V, Yb);
+        joint_accumulate<T, true>(st, sg.x, sg.y, Fmid, Fleaf, R, c, rhs, V, Yb);
         double *P = part + q * (int64_t)(R * R + R);
-        if (l < R) {
+        if (r < R) {
 #pragma unroll
-            for (int i = 0; i < kJointRM; ++i)
-                if (i < R) P[i * R + l] = col[i];
-            P[R * R + l] = rhs;
+            for (int k = 0; k < kJointK; ++k)
+                if (2 * k + h < R) P[r * R + 2 * k + h] = c[k];
+            if (h == 0) P[R * R + r] = rhs;
         }
     }
 }
@@ -1147,24 +1191,27 @@ __global__ __launch_bounds__(64) void k_joint_heavy(const uint4 *__restrict__ he
                                                     const double *__restrict__ H, double mu,
                                                     double lam, T *__restrict__ out,
                                                     int *__restrict__ flag) {
-    __shared__ double S[kJointRM * kJointRM], b[kJointRM];
-    const int l = threadIdx.x;
-    for (int64_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
-        const uint4 hv = heavy[h];  // (row, first segment, segments, 0)
-        double col[kJointRM];
+    __shared__ double Tl[kJointRM * kJointRP], Lc[2 * 32];
+    const int h = threadIdx.x >> 5, r = threadIdx.x & 31;
+    double p[kJointK];
+    joint_shift(H, R, mu, lam, p);
+    for (int64_t hi = blockIdx.x; hi < nheavy; hi += gridDim.x) {
+        const uint4 hv = heavy[hi];  // (row, first segment, segments, 0)
+        double c[kJointK];
 #pragma unroll
-        for (int i = 0; i < kJointRM; ++i) col[i] = 0.0;
+        for (int k = 0; k < kJointK; ++k) c[k] = 0.0;
         double rhs = 0.0;
-        for (uint32_t q = hv.y; q < hv.y + hv.z; ++q) {
-            const double *P = part + (int64_t)q * (R * R + R);
-            if (l < R) {
+        if (r < R) {
+            for (uint32_t q = hv.y; q < hv.y + hv.z; ++q) {
+                const double *P = part + (int64_t)q * (R * R + R);
 #pragma unroll
-                for (int i = 0; i < kJointRM; ++i)
-                    if (i < R) col[i] += P[i * R + l];
-                rhs += P[R * R + l];
+                for (int k = 0; k < kJointK; ++k)
+                    if (2 * k + h < R) c[k] += P[r * R + 2 * k + h];
+                rhs += P[R * R + r];
             }
         }
-        joint_solve_store<T>(col, rhs, (int64_t)hv.x, R, M, H, mu, lam, out, flag, S, b);
+        if (M && r < R) rhs = fma(mu, (double)M[(int64_t)hv.x * R + r], rhs);
+        joint_solve_store<T>(c, rhs, p, (int64_t)hv.x, R, out, flag, Lc, Tl);
     }
 }
 
@@ -1689,6 +1736,15 @@ void launch_sumsq3(dfacto_ctx *ctx, const float *const x[3], const int64_t n[3],
     DF_LAUNCHED();
 }
 
+// workgroups of `block` threads of `kernel` that one CU holds at once (>= 1)
+template <typename K>
+int resident_blocks(K kernel, int block) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, 0) != hipSuccess || n < 1)
+        n = 1;
+    return n;
+}
+
 void launch_joint_rows(dfacto_ctx *ctx, const dfacto_tensor *Y, int m, int64_t nrows,
                        const void *Fmid, const void *Fleaf, int R, const float *M,
                        const double *H, double mu, double lam, void *out, dfacto_dtype dtype,
@@ -1696,7 +1752,13 @@ void launch_joint_rows(dfacto_ctx *ctx, const dfacto_tensor *Y, int m, int64_t n
     if (nrows <= 0) return;
     hipStream_t s = ctx->stream;
     const uint2 *st = Y->mode[m].stream;
-    const unsigned grid = (unsigned)std::min<int64_t>(nrows, 1 << 20);
+    // persistent: the grid is what the device holds at once, so no
+    // workgroup waits for a second round
+    static const int occ_f32 = resident_blocks(k_joint_rows<float>, 64);
+    static const int occ_bf16 = resident_blocks(k_joint_rows<uint16_t>, 64);
+    const int occ = dtype == DFACTO_F32 ? occ_f32 : occ_bf16;
+    const unsigned grid =
+        (unsigned)std::min<int64_t>(nrows, (int64_t)std::max(1, ctx->num_cu) * occ);
     const int64_t nseg = Y->nseg[m], nheavy = Y->nheavy[m];
     const unsigned gseg = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nseg, 1 << 20));
     const unsigned ghv = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nheavy, 1 << 20));
