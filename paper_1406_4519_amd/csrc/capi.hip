@@ -625,9 +625,19 @@ dfacto_status dfacto_joint_als_iter(dfacto_ctx *ctx, const dfacto_tensor *X,
             if (n < 2) {
                 // users (n = 0): entries (1, item); items (n = 1): entries (user, 1)
                 launch_hadamard(ctx, R, sw.G[p], sw.G[q], 0.0, sw.H[n]);
+                // P^-1 for the short rows: (mu H + lam I)^-1 = (H + (lam / mu) I)^-1 / mu,
+                // or I / lam without the tensor term
+                const double *Pinv = nullptr;
+                double ws = 1.0 / lam;
+                if (mu > 0.0) {
+                    launch_solve(ctx, R, sw.G[p], sw.G[q], lam / mu, sw.Hinv, sw.solve_scratch,
+                                 sw.flag + 2);
+                    Pinv = sw.Hinv;
+                    ws = 1.0 / mu;
+                }
                 launch_joint_rows(ctx, Y, n, X->dims[n], n == 0 ? one : d_F[0],
                                   n == 0 ? d_F[1] : one, R, mu > 0.0 ? M : nullptr, sw.H[n], mu,
-                                  lam, d_F[n], dtype, sw.flag, part);
+                                  lam, Pinv, ws, sw.flag + 2, d_F[n], dtype, sw.flag, part);
             } else if (mu > 0.0) {
                 // words: C = mu M (mu H + lam I)^-1 = M (H + (lam / mu) I)^-1
                 launch_solve(ctx, R, sw.G[p], sw.G[q], lam / mu, sw.Hinv, sw.solve_scratch,

@@ -990,12 +990,64 @@ __device__ __forceinline__ void joint_shift(const double *__restrict__ H, int R,
     }
 }
 
+// One batch [b, min(b + 32, e1)) of a ratings stream: the nonzeros'
+// vectors go, compacted in stream order, to rows 0 .. n-1 of V (columns
+// beyond R zero) and their ratings to Yb; returns n.  cur_mid is the mid row
+// of the fiber open at b and comes back as the one open at the batch's end.
+template <typename T>
+__device__ int joint_load_batch(const uint2 *__restrict__ st, uint32_t b, uint32_t e1,
+                                const T *__restrict__ Fmid, const T *__restrict__ Fleaf, int R,
+                                uint32_t &cur_mid, double *V, double *Yb) {
+    const int h = threadIdx.x >> 5, t = threadIdx.x & 31;
+    // entry t of the batch in lanes t and t + 32
+    const uint32_t e = b + (uint32_t)t;
+    const bool in = e < e1;
+    const uint2 w = in ? st[e] : make_uint2(0u, 0u);
+    const bool hdr = in && (w.x & kHdrBit);
+    const bool nz = in && !(w.x & kHdrBit);
+    const uint64_t hm = __ballot(hdr) & 0xffffffffull;
+    const uint64_t nm = __ballot(nz) & 0xffffffffull;
+    const uint64_t upto = hm & ((2ull << t) - 1ull);
+    const uint32_t midx = w.x & kIdxMask;
+    const uint32_t lastm = hm ? (uint32_t)__shfl((int)midx, 63 - __clzll((long long)hm)) : 0u;
+    const uint32_t srcm = upto ? (uint32_t)__shfl((int)midx, 63 - __clzll((long long)upto)) : 0u;
+    const uint32_t my_mid = upto ? srcm : cur_mid;
+    if (hm) cur_mid = lastm;
+    if (nz) {
+        const int slot = __popcll(nm & ((1ull << t) - 1ull));
+        const T *pm = Fmid + (int64_t)my_mid * R;
+        const T *pl = Fleaf + (int64_t)w.x * R;
+#pragma unroll
+        for (int k = 0; k < kJointK; ++k) {
+            const int q = 2 * k + h;
+            V[slot * kJointRP + q] = q < R ? ld<T>(pm, q) * ld<T>(pl, q) : 0.0;
+        }
+        if (h == 0) Yb[slot] = (double)__uint_as_float(w.y);
+    }
+    __syncthreads();
+    return __popcll(nm);
+}
+
+// c[k] += sum_u v_u[r] v_u[2k + h], rhs += sum_u y_u v_u[r] over the n
+// loaded entries, in order
+__device__ __forceinline__ void joint_add_batch(int n, double (&c)[kJointK], double &rhs,
+                                                const double *V, const double *Yb) {
+    const int h = threadIdx.x >> 5, t = threadIdx.x & 31;
+    for (int u = 0; u < n; ++u) {
+        const double vr = V[u * kJointRP + t];  // v[r]: zero for r >= R
+        rhs = fma(Yb[u], vr, rhs);
+#pragma unroll
+        for (int k = 0; k < kJointK; ++k) c[k] = fma(V[u * kJointRP + 2 * k + h], vr, c[k]);
+    }
+    __syncthreads();
+}
+
 // c[k] += sum over the entries [e0, e1) of v[r] v[2k + h]; rhs += sum y v[r]
 template <typename T, bool kSegment>
 __device__ void joint_accumulate(const uint2 *__restrict__ st, uint32_t e0, uint32_t e1,
                                  const T *__restrict__ Fmid, const T *__restrict__ Fleaf, int R,
                                  double (&c)[kJointK], double &rhs, double *V, double *Yb) {
-    const int l = threadIdx.x, h = l >> 5, t = l & 31;
+    const int l = threadIdx.x;
     // a segment may start inside a fiber: the fiber's header is at most one
     // fiber (<= kFiberCap nonzeros) before e0, and the row's first entry is a
     // header (a whole row starts with one)
@@ -1014,41 +1066,75 @@ __device__ void joint_accumulate(const uint2 *__restrict__ st, uint32_t e0, uint
         }
     }
     for (uint32_t b = e0; b < e1; b += kJointB) {
-        // entry t of the batch in lanes t and t + 32
-        const uint32_t e = b + (uint32_t)t;
-        const bool in = e < e1;
-        const uint2 w = in ? st[e] : make_uint2(0u, 0u);
-        const bool hdr = in && (w.x & kHdrBit);
-        const bool nz = in && !(w.x & kHdrBit);
-        const uint64_t hm = __ballot(hdr) & 0xffffffffull;
-        const uint64_t upto = hm & ((2ull << t) - 1ull);
-        const uint32_t midx = w.x & kIdxMask;
-        const uint32_t lastm = hm ? (uint32_t)__shfl((int)midx, 63 - __clzll((long long)hm)) : 0u;
-        const uint32_t srcm = upto ? (uint32_t)__shfl((int)midx, 63 - __clzll((long long)upto)) : 0u;
-        const uint32_t my_mid = upto ? srcm : cur_mid;
-        if (hm) cur_mid = lastm;
-        if (nz) {
-            const T *pm = Fmid + (int64_t)my_mid * R;
-            const T *pl = Fleaf + (int64_t)w.x * R;
-#pragma unroll
-            for (int k = 0; k < kJointK; ++k) {
-                const int q = 2 * k + h;
-                V[t * kJointRP + q] = q < R ? ld<T>(pm, q) * ld<T>(pl, q) : 0.0;
-            }
-            if (h == 0) Yb[t] = (double)__uint_as_float(w.y);
-        }
-        __syncthreads();
-        uint64_t nm = __ballot(nz) & 0xffffffffull;
-        while (nm) {
-            const int u = __ffsll((unsigned long long)nm) - 1;
-            nm &= nm - 1;
-            const double vr = V[u * kJointRP + t];  // v[r]: zero for r >= R
-            rhs = fma(Yb[u], vr, rhs);
-#pragma unroll
-            for (int k = 0; k < kJointK; ++k) c[k] = fma(V[u * kJointRP + 2 * k + h], vr, c[k]);
-        }
-        __syncthreads();
+        const int n = joint_load_batch<T>(st, b, e1, Fmid, Fleaf, R, cur_mid, V, Yb);
+        joint_add_batch(n, c, rhs, V, Yb);
     }
+}
+
+// A row of at most kJointWood entries (vectors v_e in rows of V, ratings in
+// Yb) solved without factorizing its own S = P + V^T V, from P^-1 (the same
+// for every row of the mode) by the Sherman-Morrison-Woodbury identity:
+//   b = sum_e y_e v_e + mu m,  z = P^-1 b,  u_e = P^-1 v_e,
+//   K = I + [v_e . u_f],  t = [v_e . z],  K w = t,  x = z - sum_e w_e u_e.
+// P^-1 = ws * Pinv (R x R, row-major), or ws * I when Pinv is null.  K is
+// symmetric positive definite with eigenvalues >= 1 and is solved by
+// Gauss-Jordan without pivoting, lane (e, f) = e * 8 + f holding K[e][f]
+// and lane (e, n) holding t[e].  U (kJointRM rows of kJointRP doubles, apart
+// from V's first n rows) holds u_e and z; Bb (32 doubles) carries b.
+constexpr int kJointWood = 7;
+
+// (not inlined: inside the rows kernel's loop it would cost a wave per SIMD
+// of registers)
+template <typename T>
+__device__ __noinline__ void joint_woodbury(int n, const double *V, const double *Yb, double mu, double m,
+                               const double *__restrict__ Pinv, double ws, int R, int64_t row,
+                               T *__restrict__ out, double *U, double *Bb) {
+    const int l = threadIdx.x, h = l >> 5, r = l & 31;
+    double wr[kJointK];  // P^-1[r][2k + h]
+#pragma unroll
+    for (int k = 0; k < kJointK; ++k) {
+        const int q = 2 * k + h;
+        wr[k] = (r < R && q < R) ? (Pinv ? ws * Pinv[r * R + q] : (q == r ? ws : 0.0)) : 0.0;
+    }
+    double b = 0.0;
+    for (int e = 0; e < n; ++e) b = fma(Yb[e], V[e * kJointRP + r], b);
+    b = fma(mu, m, b);
+    if (h == 0) Bb[r] = b;
+    __syncthreads();
+    double zp = 0.0;
+#pragma unroll
+    for (int k = 0; k < kJointK; ++k) zp = fma(wr[k], Bb[2 * k + h], zp);
+    const double z = zp + __shfl_xor(zp, 32, 64);  // the halves' sums, equal in both
+    for (int e = 0; e < n; ++e) {
+        double up = 0.0;
+#pragma unroll
+        for (int k = 0; k < kJointK; ++k) up = fma(wr[k], V[e * kJointRP + 2 * k + h], up);
+        const double u = up + __shfl_xor(up, 32, 64);
+        if (h == 0) U[e * kJointRP + r] = u;
+    }
+    if (h == 0) U[n * kJointRP + r] = z;
+    __syncthreads();
+    // G[e][f] = a_e . v_f for e <= n (a_e = u_e, a_n = z) and f < n
+    const int ge = l >> 3, gf = l & 7;
+    double g = 0.0;
+    if (ge <= n && gf < n) {
+#pragma unroll 4
+        for (int q = 0; q < kJointRM; ++q) g = fma(U[ge * kJointRP + q], V[gf * kJointRP + q], g);
+    }
+    const double tv = __shfl(g, n * 8 + ge, 64);  // t[ge] = z . v_ge
+    double a = 0.0;
+    if (ge < n && gf < n) a = g + (ge == gf ? 1.0 : 0.0);
+    if (ge < n && gf == n) a = tv;
+    for (int j = 0; j < n; ++j) {
+        const double inv = 1.0 / lane_bcast(a, j * 9);  // K's pivot at step j
+        const double rowj = __shfl(a, j * 8 + gf, 64);
+        const double colj = __shfl(a, ge * 8 + j, 64);
+        a = ge == j ? rowj * inv : fma(-colj * inv, rowj, a);
+    }
+    double x = z;
+    for (int e = 0; e < n; ++e) x = fma(-lane_bcast(a, e * 8 + n), U[e * kJointRP + r], x);
+    if (h == 0 && r < R) st_out<T>(out, row * R + r, x);
+    __syncthreads();  // U, V and Bb are free again
 }
 
 // S = c + p (p = mu H + lam I in the same layout); b = rhs (lane (h, r)
@@ -1127,6 +1213,9 @@ __device__ void joint_solve_store(double (&c)[kJointK], double b, const double (
 
 // every row of at most kJointSeg entries: accumulate, solve, store
 // (persistent grid: each workgroup forms mu H + lam I once and walks rows)
+// Rows whose stream range fits one batch and holds at most kJointWood
+// entries take joint_woodbury when P^-1 is valid (Pinv null, or its solve
+// reported success in *pflag == 0).
 template <typename T>
 __global__ __launch_bounds__(64) void k_joint_rows(const uint2 *__restrict__ st,
                                                    const uint2 *__restrict__ range, int64_t nrows,
@@ -1134,12 +1223,14 @@ __global__ __launch_bounds__(64) void k_joint_rows(const uint2 *__restrict__ st,
                                                    const T *__restrict__ Fleaf, int R,
                                                    const float *__restrict__ M,
                                                    const double *__restrict__ H, double mu,
-                                                   double lam, T *__restrict__ out,
-                                                   int *__restrict__ flag) {
+                                                   double lam, const double *__restrict__ Pinv,
+                                                   double ws, const int *__restrict__ pflag,
+                                                   T *__restrict__ out, int *__restrict__ flag) {
     __shared__ double V[kJointB * kJointRP], Yb[kJointB], Lc[2 * 32];
     const int r = threadIdx.x & 31;
     double p[kJointK];
     joint_shift(H, R, mu, lam, p);
+    const bool wood = !Pinv || *pflag == 0;
     uint2 next = blockIdx.x < nrows ? range[blockIdx.x] : make_uint2(0u, 0u);
     for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
         const uint2 rg = next;  // the next row's range is read while this one is solved
@@ -1150,7 +1241,20 @@ __global__ __launch_bounds__(64) void k_joint_rows(const uint2 *__restrict__ st,
 #pragma unroll
         for (int k = 0; k < kJointK; ++k) c[k] = 0.0;
         double rhs = 0.0;
-        if (rg.y > rg.x) joint_accumulate<T, false>(st, rg.x, rg.y, Fmid, Fleaf, R, c, rhs, V, Yb);
+        if (wood && rg.y - rg.x <= (uint32_t)kJointB) {
+            uint32_t cur_mid = 0;
+            const int n =
+                rg.y > rg.x ? joint_load_batch<T>(st, rg.x, rg.y, Fmid, Fleaf, R, cur_mid, V, Yb)
+                            : 0;
+            if (n <= kJointWood) {
+                joint_woodbury<T>(n, V, Yb, mu, m, Pinv, ws, R, row, out,
+                                  V + 16 * kJointRP, Lc);
+                continue;
+            }
+            joint_add_batch(n, c, rhs, V, Yb);
+        } else if (rg.y > rg.x) {
+            joint_accumulate<T, false>(st, rg.x, rg.y, Fmid, Fleaf, R, c, rhs, V, Yb);
+        }
         if (M) rhs = fma(mu, m, rhs);
         joint_solve_store<T>(c, rhs, p, row, R, out, flag, Lc, V);
     }
@@ -1747,8 +1851,8 @@ int resident_blocks(K kernel, int block) {
 
 void launch_joint_rows(dfacto_ctx *ctx, const dfacto_tensor *Y, int m, int64_t nrows,
                        const void *Fmid, const void *Fleaf, int R, const float *M,
-                       const double *H, double mu, double lam, void *out, dfacto_dtype dtype,
-                       int *flag, double *part) {
+                       const double *H, double mu, double lam, const double *Pinv, double ws,
+                       const int *pflag, void *out, dfacto_dtype dtype, int *flag, double *part) {
     if (nrows <= 0) return;
     hipStream_t s = ctx->stream;
     const uint2 *st = Y->mode[m].stream;
@@ -1764,7 +1868,8 @@ void launch_joint_rows(dfacto_ctx *ctx, const dfacto_tensor *Y, int m, int64_t n
     const unsigned ghv = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nheavy, 1 << 20));
 #define DF_JOINT(T)                                                                            \
     hipLaunchKernelGGL(k_joint_rows<T>, dim3(grid), dim3(64), 0, s, st, Y->row_range[m], nrows, \
-                       (const T *)Fmid, (const T *)Fleaf, R, M, H, mu, lam, (T *)out, flag);    \
+                       (const T *)Fmid, (const T *)Fleaf, R, M, H, mu, lam, Pinv, ws, pflag,   \
+                       (T *)out, flag);                                                        \
     if (nseg > 0) {                                                                            \
         hipLaunchKernelGGL(k_joint_segments<T>, dim3(gseg), dim3(64), 0, s, st,               \
                            Y->seg_range[m], nseg, (const T *)Fmid, (const T *)Fleaf, R, part); \

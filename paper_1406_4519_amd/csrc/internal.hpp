@@ -250,10 +250,13 @@ void launch_sumsq3(dfacto_ctx *ctx, const float *const x[3], const int64_t n[3],
                    double *out);
 // joint matrix completion + tensor factorization pieces (dense.hip)
 constexpr int kJointSeg = 4096;  // entries per joint-ALS work item
+// Row m of the joint ALS for every row of ratings mode m: S = sum v^T v +
+// mu H + lam I.  Short rows use P^-1 = ws * Pinv (P = mu H + lam I; ws * I
+// when Pinv is null) when *pflag == 0, the others a Cholesky of S.
 void launch_joint_rows(dfacto_ctx *ctx, const dfacto_tensor *Y, int m, int64_t nrows,
                        const void *Fmid, const void *Fleaf, int R, const float *M,
-                       const double *H, double mu, double lam, void *out, dfacto_dtype dtype,
-                       int *flag, double *part);
+                       const double *H, double mu, double lam, const double *Pinv, double ws,
+                       const int *pflag, void *out, dfacto_dtype dtype, int *flag, double *part);
 void launch_joint_combine(dfacto_ctx *ctx, float *G, const void *F, const float *RY, double mu,
                           double lam, int64_t n, dfacto_dtype dtype);
 void launch_dot_parts(dfacto_ctx *ctx, const void *F, const float *X, int64_t n, double *part,
