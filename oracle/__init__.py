@@ -68,7 +68,8 @@ def _load():
                                           ctypes.c_double, ctypes.c_double, P, P, P, P, P, P]
         lib.oracle_joint_grad.restype = ctypes.c_double
         lib.oracle_joint_als_iter.argtypes = [i64, P, P, P, P, P, i64, P, P, P, ctypes.c_int,
-                                              ctypes.c_double, ctypes.c_double, P, P, P]
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                              P, P, P]
         lib.oracle_joint_als_iter.restype = ctypes.c_double
         _lib = lib
     return _lib
@@ -242,9 +243,13 @@ def joint_grad(i, j, k, val, dims, yi, yj, yv, factors, mu: float, lam: float):
     return tuple(g), float(f)
 
 
-def joint_als_iter(i, j, k, val, dims, yi, yj, yv, factors, mu: float, lam: float):
+def joint_als_iter(i, j, k, val, dims, yi, yj, yv, factors, mu: float, lam: float,
+                   store: str = "f64"):
     """One ALS iteration of the joint model (A, B, C in order).  Returns
-    (A, B, C, f) with new arrays; f at the new point."""
+    (A, B, C, f) with new arrays; f at the new point.  store="bf16": every
+    new factor is rounded to BF16 before later use."""
+    if store not in ("f64", "bf16"):
+        raise ValueError("store must be 'f64' or 'bf16'")
     lib = _load()
     i, j, k, val = _coo(i, j, k, val)
     yi, yj, yv = _ratings(yi, yj, yv)
@@ -252,5 +257,6 @@ def joint_als_iter(i, j, k, val, dims, yi, yj, yv, factors, mu: float, lam: floa
     R = A.shape[1]
     d = np.asarray(dims, dtype=np.int64)
     f = lib.oracle_joint_als_iter(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), len(yv), _p(yi),
-                                  _p(yj), _p(yv), R, float(mu), float(lam), _p(A), _p(B), _p(C))
+                                  _p(yj), _p(yv), R, float(mu), float(lam), int(store == "bf16"),
+                                  _p(A), _p(B), _p(C))
     return A, B, C, float(f)

@@ -705,13 +705,14 @@ double oracle_joint_grad(int64_t nnz, const uint32_t *i, const uint32_t *j, cons
  * and likewise for b_j over the users who rated item j (with A^T A * C^T C);
  * c_k = mu M2_k (mu (A^T A * B^T B) + lam I)^{-1} (no ratings term).  Each
  * R x R system is solved by Cholesky, or the pseudo-inverse when it is
- * numerically singular.  A, B, C are updated in place; returns f at the
- * new point. */
+ * numerically singular.  store_bf16 != 0 models factors kept in BF16
+ * storage: each new factor is rounded to BF16 before later use.  A, B, C are
+ * updated in place; returns f at the new point. */
 double oracle_joint_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
                              const uint32_t *k, const double *val, const int64_t *dims,
                              int64_t ny, const uint32_t *yi, const uint32_t *yj,
-                             const double *yv, int R, double mu, double lam, double *A,
-                             double *B, double *C)
+                             const double *yv, int R, double mu, double lam, int store_bf16,
+                             double *A, double *B, double *C)
 {
     double *F[3] = {A, B, C};
     const uint32_t *own[2] = {yi, yj}, *other[2] = {yj, yi};
@@ -744,6 +745,8 @@ double oracle_joint_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
             }
             solve_rows(1, R, rhs, S, F[n] + row * R);
         }
+        if (store_bf16)
+            for (int64_t e = 0; e < dims[n] * R; ++e) F[n][e] = round_bf16(F[n][e]);
         free(M);
     }
     free(Gp);

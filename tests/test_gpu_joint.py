@@ -68,26 +68,37 @@ def test_joint_grad(ctx, problem, R, dtype, mu, lam):
     assert abs(f.item() - fref) <= 1e-6 * abs(fref)
 
 
-@pytest.mark.parametrize("R,mu,lam", [(8, 0.5, 0.1), (16, 1.0, 1.0), (32, 0.0, 0.5), (5, 0.3, 0.2)])
-def test_joint_als_iterations(ctx, problem, R, mu, lam):
+@pytest.mark.parametrize("R,mu,lam,dtype", [(8, 0.5, 0.1, "f32"), (16, 1.0, 1.0, "f32"),
+                                            (32, 0.0, 0.5, "f32"), (5, 0.3, 0.2, "f32"),
+                                            (12, 0.5, 0.2, "bf16"), (32, 1.0, 0.1, "bf16")])
+def test_joint_als_iterations(ctx, problem, R, mu, lam, dtype):
+    """Three iterations against the oracle, each from the oracle's previous
+    factors; the rows take both the short-row (Woodbury) and the Cholesky
+    path.  BF16: the oracle rounds each new factor to BF16 as the device
+    stores it."""
     coo, y, X, Y = problem
     F0 = gen.init_factors(coo.dims, R, seed=95 + R)
-    Fd, Fw = factors_to_dev(F0, "f32")
+    Fd, Fw = factors_to_dev(F0, dtype)
     ref = Fw
+    tol = 1e-5 if dtype == "f32" else BF16_REL
+    store = "f64" if dtype == "f32" else "bf16"
     for it in range(3):
         dfacto.joint_als_iter(ctx, X, Y, Fd, mu, lam)
         torch.cuda.synchronize()
-        A, B, C, fref = oracle.joint_als_iter(*coo.arrays64(), coo.dims, *y, ref, mu, lam)
+        A, B, C, fref = oracle.joint_als_iter(*coo.arrays64(), coo.dims, *y, ref, mu, lam,
+                                              store=store)
         errs = [rel_fro(to_host64(Fd[m]), x) for m, x in enumerate((A, B, C))]
-        say(f"  joint ALS R={R} mu={mu} lam={lam} iteration {it}: factor errors {errs}")
-        assert max(errs) <= 1e-5
+        say(f"  joint ALS R={R} {dtype} mu={mu} lam={lam} iteration {it}: factor errors {errs}")
+        assert max(errs) <= tol
         ref = [A, B, C]
+        if dtype == "bf16":  # continue from the oracle's factors, exactly representable
+            Fd, _ = factors_to_dev(ref, dtype)
     # the objective at the GPU's factors equals the oracle's at its own
     G = [torch.empty((d, R), device=DEV) for d in coo.dims]
     f = torch.zeros(1, dtype=torch.float64, device=DEV)
     dfacto.joint_grad(ctx, X, Y, Fd, G, f, mu, lam)
     torch.cuda.synchronize()
-    assert abs(f.item() - fref) <= 1e-5 * abs(fref)
+    assert abs(f.item() - fref) <= (1e-5 if dtype == "f32" else 1e-3) * abs(fref)
 
 
 def test_joint_argument_errors(ctx, problem):

@@ -1,13 +1,14 @@
 """Pins for the oracle's joint matrix completion + tensor factorization
 model (CPU only): the objective against a dense brute force, the gradient
 against central finite differences of that objective, every ALS block
-against per-row dense least squares solved by numpy, and monotone descent of
-the alternating updates."""
+against per-row dense least squares solved by numpy (also with BF16 factor
+storage), and monotone descent of the alternating updates."""
 import numpy as np
 import pytest
 
 import brute
 import oracle
+from paper_1406_4519_amd import gen
 
 
 def _problem(seed, dims=(6, 5, 4), nnz=40, ny=14, R=3):
@@ -88,6 +89,32 @@ def test_joint_als_blocks_are_row_least_squares(mu, lam):
             ref = _row_lstsq(X, y, cur, mu, lam, n, row)
             np.testing.assert_allclose(new[row], ref, rtol=1e-9, atol=1e-10)
     np.testing.assert_allclose(f, _dense_f(dims, x, y, [A, B, C], mu, lam), rtol=1e-12)
+
+
+def test_joint_als_bf16_storage_blocks():
+    """store="bf16": every block is the same per-row least squares, from the
+    factors as stored, and is then rounded to BF16 (through FP32,
+    nearest-even) before the next block uses it.  Rounding by gen's
+    independent converter."""
+    dims = (6, 5, 4)
+    x, y, F = _problem(6, dims)
+    X = brute.dense(dims, *x)
+    mu, lam = 0.7, 0.2
+
+    def rnd(M):
+        return gen.bf16_to_f32(gen.f32_to_bf16(M.astype(np.float32))).astype(np.float64)
+
+    F = [rnd(f) for f in F]
+    A, B, C, f = oracle.joint_als_iter(*x, dims, *y, F, mu, lam, store="bf16")
+    for new in (A, B, C):
+        np.testing.assert_array_equal(new, rnd(new))
+    steps = [(0, [F[0], F[1], F[2]], A), (1, [A, F[1], F[2]], B), (2, [A, B, F[2]], C)]
+    for n, cur, new in steps:
+        ref = np.array([_row_lstsq(X, y, cur, mu, lam, n, row) for row in range(dims[n])])
+        np.testing.assert_allclose(new, rnd(ref), rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(f, _dense_f(dims, x, y, [A, B, C], mu, lam), rtol=1e-12)
+    with pytest.raises(ValueError):
+        oracle.joint_als_iter(*x, dims, *y, F, mu, lam, store="f16")
 
 
 def test_joint_als_descends():
