@@ -65,10 +65,35 @@ typedef struct dfacto_tensor dfacto_tensor; /* the three flattenings, on the dev
 /* context                                                              */
 /* ------------------------------------------------------------------ */
 
+/* A caller's source of device memory, so that a framework's own caching
+ * allocator can own what the library allocates.  alloc(bytes, stream, user)
+ * returns device memory of `bytes` bytes usable on `stream` (a hipStream_t),
+ * aligned to 256 bytes, or NULL when it cannot (the call then fails with
+ * DFACTO_E_NOMEM).  free(ptr, stream, user) gives it back; `stream` is the
+ * stream of the memory's last use, and the allocator must not hand the
+ * memory out again before that stream's work up to the free has finished
+ * (stream-ordered reuse, as hipFreeAsync).  Both are called only from the
+ * thread that calls the library, during its calls (and dfacto_*_destroy). */
+typedef struct dfacto_allocator {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, void *stream, void *user);
+    void *user;
+} dfacto_allocator;
+
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
- * (a hipStream_t; NULL = the default stream).  Returns DFACTO_E_DEVICE if
- * no such device exists. */
-dfacto_status dfacto_ctx_create(int device, void *hip_stream, dfacto_ctx **out);
+ * (a hipStream_t; NULL = the default stream).
+ * alloc: NULL, and the library allocates itself (hipMalloc for tensors and
+ * workspaces, stream-ordered hipMallocAsync for build temporaries); or the
+ * caller's allocator, which then serves every device allocation made on the
+ * context's behalf: the flattenings of the tensors it builds (which keep
+ * the allocator and the context's stream of that time for their
+ * dfacto_tensor_destroy), build temporaries, workspaces and group
+ * workspaces.  The struct is copied; the functions and `user` must stay
+ * valid until the context and everything built with it are destroyed.
+ * Errors: DFACTO_E_INVALID (out NULL, device out of range, alloc given with
+ * a NULL function), DFACTO_E_DEVICE (no HIP device). */
+dfacto_status dfacto_ctx_create(int device, void *hip_stream, const dfacto_allocator *alloc,
+                                dfacto_ctx **out);
 
 /* Rebind the context to another stream of the same device. */
 dfacto_status dfacto_ctx_set_stream(dfacto_ctx *ctx, void *hip_stream);

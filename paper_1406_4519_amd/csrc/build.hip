@@ -369,22 +369,22 @@ __global__ void k_chunk_starts(const uint2 *__restrict__ st, int64_t nentry, int
 // host helpers
 // ---------------------------------------------------------------------------
 
-// Transient build buffers, stream-ordered (hipMallocAsync / hipFreeAsync),
-// so building one tensor never waits for unrelated work on the device.
+// Transient build buffers, stream-ordered (from the context's memory
+// source, freed on the build stream), so building one tensor never waits for
+// unrelated work on the device.
 struct Scratch {
     hipStream_t s;
-    hipMemPool_t pool;
+    DevMem mem;
     std::vector<void *> ptrs;
-    explicit Scratch(hipStream_t st, hipMemPool_t pl = nullptr) : s(st), pool(pl) {}
+    Scratch(hipStream_t st, const DevMem &m) : s(st), mem(m) {}
     ~Scratch() {
-        for (void *p : ptrs)
-            if (p) (void)hipFreeAsync(p, s);
+        for (void *p : ptrs) mem.free(p, s);
     }
     template <typename T>
     T *alloc(int64_t n) {
         void *p = nullptr;
         const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
-        if (stream_alloc(&p, bytes, s, pool) != hipSuccess) {
+        if (mem.alloc(&p, bytes, s) != hipSuccess) {
             (void)hipGetLastError();
             throw Error{DFACTO_E_NOMEM, "device allocation of " + std::to_string(bytes) +
                                             " bytes failed while building the flattenings"};
@@ -395,7 +395,7 @@ struct Scratch {
     void release(void *p) {
         for (auto &q : ptrs)
             if (q == p) {
-                (void)hipFreeAsync(q, s);
+                mem.free(q, s);
                 q = nullptr;
             }
     }
@@ -406,7 +406,7 @@ T *tensor_alloc(dfacto_tensor *t, int64_t n) {
     void *p = nullptr;
     const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
     const hipError_t e =
-        t->alloc_stream ? stream_alloc(&p, bytes, t->alloc_stream, t->alloc_pool) : hipMalloc(&p, bytes);
+        t->alloc_stream ? t->mem.alloc(&p, bytes, t->alloc_stream) : hipMalloc(&p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         throw Error{DFACTO_E_NOMEM, "device allocation of " + std::to_string(bytes) +
@@ -443,7 +443,7 @@ void radix_sort(uint64_t *&keys, uint32_t *&vals, uint64_t *&kalt, uint32_t *&va
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(kThreads), 0, s, keys, n,
                            shift, hist, nblk);
-        scan_exclusive_u32(hist, offs, 256 * nblk, s, sc.pool);
+        scan_exclusive_u32(hist, offs, 256 * nblk, s, &sc.mem);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, keys,
                            vals, kalt, valt, n, shift, offs, nblk);
         std::swap(keys, kalt);
@@ -510,7 +510,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     hipStream_t s = ctx->stream;
     ModeData &md = t->mode[m];
     const int64_t nrows = t->dims[md.root];
-    Scratch sc(s, ctx->pool);
+    Scratch sc(s, ctx->mem);
     int chunk_len = 4 * kFiberCap;
     if (const char *env = getenv("DFACTO_CHUNK")) {
         const int v = atoi(env);
@@ -533,7 +533,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, nrows,
                            1u);
         uint32_t *pos = sc.alloc<uint32_t>(nrows);
-        scan_exclusive_u32(mark, pos, nrows, s, sc.pool);
+        scan_exclusive_u32(mark, pos, nrows, s, &sc.mem);
         hipLaunchKernelGGL(k_compact_rows, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, pos,
                            nrows, md.empty_rows);
         DF_LAUNCHED();
@@ -547,7 +547,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     uint32_t *fid = sc.alloc<uint32_t>(n);
     hipLaunchKernelGGL(k_fiber_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, root, mid, n, fs,
                        rs);
-    scan_exclusive_u32(fs, fid, n, s, sc.pool);
+    scan_exclusive_u32(fs, fid, n, s, &sc.mem);
     md.nfib = read_back_sum(fid + n - 1, fs + n - 1, s);
     uint32_t *fptr = sc.alloc<uint32_t>(md.nfib);
     hipLaunchKernelGGL(k_fiber_start_pos, dim3(grid_for(n)), dim3(kThreads), 0, s, fs, fid, n,
@@ -557,7 +557,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
                        md.nfib, h);
     sc.release(fptr);
     uint32_t *hex = fid;  // reuse
-    scan_exclusive_u32(h, hex, n, s, sc.pool);
+    scan_exclusive_u32(h, hex, n, s, &sc.mem);
     const int64_t nhdr = read_back_sum(hex + n - 1, h + n - 1, s);
     const int64_t L = n + nhdr;
     if (L > (int64_t)0xFFFFFFFFu - (1 << 20))
@@ -574,7 +574,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(n)), dim3(kThreads), 0, s, root, rs, n, nrows,
                        mark);
     uint32_t *rpos = sc.alloc<uint32_t>(nrows);
-    scan_exclusive_u32(mark, rpos, nrows, s, sc.pool);
+    scan_exclusive_u32(mark, rpos, nrows, s, &sc.mem);
     md.nempty = read_back_sum(rpos + nrows - 1, mark + nrows - 1, s);
     md.nroot = nrows - md.nempty;
     md.empty_rows = tensor_alloc<uint32_t>(t, md.nempty);
@@ -616,7 +616,7 @@ __global__ void k_store_ranges(const uint2 *__restrict__ st, const uint32_t *__r
 }  // namespace
 
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s,
-                        hipMemPool_t pool) {
+                        const DevMem *mem) {
     if (n <= 0) return;
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 1) {
@@ -624,20 +624,17 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_
                            (const uint32_t *)nullptr);
         return;
     }
-    uint32_t *bsum = nullptr, *boff = nullptr;
-    DF_HIP(stream_alloc((void **)&bsum, sizeof(uint32_t) * nb, s, pool));
-    DF_HIP(stream_alloc((void **)&boff, sizeof(uint32_t) * nb, s, pool));
+    Scratch sc(s, mem ? *mem : DevMem{});
+    uint32_t *bsum = sc.alloc<uint32_t>(nb), *boff = sc.alloc<uint32_t>(nb);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kThreads), 0, s, in, n, bsum);
-    scan_exclusive_u32(bsum, boff, nb, s, pool);
+    scan_exclusive_u32(bsum, boff, nb, s, &sc.mem);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kThreads), 0, s, in, out, n,
                        (const uint32_t *)boff);
-    DF_HIP(hipFreeAsync(bsum, s));
-    DF_HIP(hipFreeAsync(boff, s));
 }
 
 void build_row_ranges(dfacto_ctx *ctx, dfacto_tensor *t) {
     hipStream_t s = ctx->stream;
-    Scratch sc(s, ctx->pool);
+    Scratch sc(s, ctx->mem);
     for (int m = 0; m < 2; ++m) {
         const ModeData &md = t->mode[m];
         const int64_t rows = t->dims[md.root], n = md.nentry;
@@ -648,7 +645,7 @@ void build_row_ranges(dfacto_ctx *ctx, dfacto_tensor *t) {
             uint32_t *pos = sc.alloc<uint32_t>(md.nroot);
             hipLaunchKernelGGL(k_root_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, md.stream, n,
                                flag);
-            scan_exclusive_u32(flag, off, n, s, sc.pool);
+            scan_exclusive_u32(flag, off, n, s, &sc.mem);
             hipLaunchKernelGGL(k_row_ranges, dim3(grid_for(n)), dim3(kThreads), 0, s, md.stream,
                                flag, off, n, pos);
             hipLaunchKernelGGL(k_store_ranges, dim3(grid_for(md.nroot)), dim3(kThreads), 0, s,
@@ -692,7 +689,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
                   const uint32_t *d_k, const float *d_val) {
     hipStream_t s = ctx->stream;
     const int64_t n = t->nnz;
-    Scratch sc(s, ctx->pool);
+    Scratch sc(s, ctx->mem);
     static const int ROOT[3] = {0, 1, 2}, MID[3] = {2, 0, 1}, LEAF[3] = {1, 2, 0};
     for (int m = 0; m < 3; ++m) {
         t->mode[m].root = ROOT[m];
@@ -743,7 +740,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
     uint32_t *dflag = perm, *dpos = palt;  // reuse
     hipLaunchKernelGGL(k_distinct_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, si, sj, sk, n,
                        dflag);
-    scan_exclusive_u32(dflag, dpos, n, s, sc.pool);
+    scan_exclusive_u32(dflag, dpos, n, s, &sc.mem);
     const int64_t nd = read_back_sum(dpos + n - 1, dflag + n - 1, s);
     uint32_t *di = sc.alloc<uint32_t>(nd), *dj = sc.alloc<uint32_t>(nd), *dk = sc.alloc<uint32_t>(nd);
     float *dv = sc.alloc<float>(nd);

@@ -30,15 +30,21 @@ void hip_check(hipError_t e, const char *what) {
 void *ws_get(dfacto_ctx *ctx, dfacto_ctx::Slot slot, size_t bytes) {
     bytes = std::max<size_t>(bytes, 256);
     if (ctx->ws_size[slot] >= bytes) return ctx->ws[slot];
+    const bool user = ctx->mem.has_user();
     if (ctx->ws[slot]) {
-        DF_HIP(hipStreamSynchronize(ctx->stream));
-        DF_HIP(hipFree(ctx->ws[slot]));
+        if (user) {  // the caller's allocator orders reuse after the stream's work
+            ctx->mem.free(ctx->ws[slot], ctx->stream);
+        } else {
+            DF_HIP(hipStreamSynchronize(ctx->stream));
+            DF_HIP(hipFree(ctx->ws[slot]));
+        }
         ctx->ws[slot] = nullptr;
         ctx->ws_size[slot] = 0;
     }
     const size_t grow = bytes + bytes / 8;
     void *p = nullptr;
-    hip_check(hipMalloc(&p, grow), "workspace hipMalloc");
+    hip_check(user ? ctx->mem.alloc(&p, grow, ctx->stream) : hipMalloc(&p, grow),
+              "workspace allocation");
     ctx->ws[slot] = p;
     ctx->ws_size[slot] = grow;
     return p;
@@ -139,9 +145,9 @@ dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int
             throw Error{DFACTO_E_UNSUPPORTED, "nnz must be below 2^32 - 2^20"};
         dfacto_tensor *t = new dfacto_tensor();
         t->device = ctx->device;
-        if (async_alloc) {
+        if (async_alloc || ctx->mem.has_user()) {
             t->alloc_stream = ctx->stream;
-            t->alloc_pool = ctx->pool;
+            t->mem = ctx->mem;
         }
         for (int m = 0; m < 3; ++m) t->dims[m] = dims[m];
         t->nnz = nnz;
@@ -170,9 +176,11 @@ using namespace dfacto;
 
 extern "C" {
 
-dfacto_status dfacto_ctx_create(int device, void *hip_stream, dfacto_ctx **out) {
+dfacto_status dfacto_ctx_create(int device, void *hip_stream, const dfacto_allocator *alloc,
+                                dfacto_ctx **out) {
     if (!out) return DFACTO_E_INVALID;
     *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free)) return DFACTO_E_INVALID;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
         (void)hipGetLastError();
@@ -183,6 +191,7 @@ dfacto_status dfacto_ctx_create(int device, void *hip_stream, dfacto_ctx **out) 
     if (!ctx) return DFACTO_E_NOMEM;
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
+    if (alloc) ctx->mem.user = *alloc;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
     *out = ctx;
@@ -212,8 +221,11 @@ void dfacto_ctx_destroy(dfacto_ctx *ctx) {
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->ev_step) (void)hipEventDestroy(ctx->ev_step);
-    for (int s = 0; s < dfacto_ctx::kNumSlots; ++s)
-        if (ctx->ws[s]) (void)hipFree(ctx->ws[s]);
+    for (int s = 0; s < dfacto_ctx::kNumSlots; ++s) {
+        if (!ctx->ws[s]) continue;
+        if (ctx->mem.has_user()) ctx->mem.free(ctx->ws[s], ctx->stream);
+        else (void)hipFree(ctx->ws[s]);
+    }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete ctx;
@@ -299,7 +311,7 @@ void dfacto_tensor_destroy(dfacto_tensor *t) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(t->device);
     if (t->alloc_stream) {  // stream-ordered memory: free after the stream's work
-        for (void *p : t->allocations) (void)hipFreeAsync(p, t->alloc_stream);
+        for (void *p : t->allocations) t->mem.free(p, t->alloc_stream);
     } else {
         (void)hipDeviceSynchronize();
         for (void *p : t->allocations) (void)hipFree(p);
@@ -493,15 +505,15 @@ dfacto_status dfacto_build_ratings(dfacto_ctx *ctx, const int64_t dims[2], int64
         if (!out || !dims) throw Error{DFACTO_E_INVALID, "dims or out is NULL"};
         if (n < 0) throw Error{DFACTO_E_INVALID, "n is negative"};
         uint32_t *k0 = nullptr;
-        hip_check(stream_alloc((void **)&k0, sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1),
-                               ctx->stream, ctx->pool),
+        hip_check(ctx->mem.alloc((void **)&k0, sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1),
+                                 ctx->stream),
                   "ratings staging");
         DF_HIP(hipMemsetAsync(k0, 0, sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1),
                               ctx->stream));
         const int64_t d3[3] = {dims[0], dims[1], 1};
         dfacto_tensor *t = nullptr;
         const dfacto_status st = dfacto_build_flattenings(ctx, d3, n, d_i, d_j, k0, d_y, &t);
-        (void)hipFreeAsync(k0, ctx->stream);
+        ctx->mem.free(k0, ctx->stream);
         if (st != DFACTO_OK) throw Error{st, ctx->err};
         try {
             build_row_ranges(ctx, t);

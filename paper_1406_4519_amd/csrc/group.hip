@@ -39,7 +39,7 @@ struct dfacto_group {
     dfacto_ctx gctx;  // bound to the group's own stream; no workspace use
     hipStream_t stream = nullptr;
     bool own_stream = true;  // false: launches go to the creating context's stream
-    hipMemPool_t pool = nullptr;  // the creating context's pool for stream-ordered memory
+    DevMem mem;  // the creating context's memory source
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<void *> allocs;
     size_t bytes = 0;
@@ -64,7 +64,7 @@ template <typename T>
 T *dev_alloc(dfacto_group *g, size_t count) {
     void *p = nullptr;
     const size_t bytes = std::max<size_t>(sizeof(T) * count, 256);
-    hip_check(stream_alloc(&p, bytes, g->stream, g->pool), "group allocation");
+    hip_check(g->mem.alloc(&p, bytes, g->stream), "group allocation");
     g->allocs.push_back(p);
     g->bytes += bytes;
     return (T *)p;
@@ -353,7 +353,7 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
             g->maxR = *std::max_element(R.begin(), R.end());
             g->use_graph = (flags & DFACTO_GROUP_GRAPH) != 0;
             g->own_stream = (flags & DFACTO_GROUP_CTX_STREAM) == 0;
-            g->pool = ctx->pool;
+            g->mem = ctx->mem;
             if (g->own_stream) DF_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
             else g->stream = ctx->stream;
             g->gctx.device = ctx->device;
@@ -474,7 +474,7 @@ void dfacto_group_destroy(dfacto_group *g) {
     (void)hipSetDevice(g->device);
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    for (void *p : g->allocs) (void)hipFreeAsync(p, g->stream);
+    for (void *p : g->allocs) g->mem.free(p, g->stream);
     if (g->stream || !g->own_stream) (void)hipStreamSynchronize(g->stream);  // host tables
     if (g->ev_in) (void)hipEventDestroy(g->ev_in);
     if (g->ev_out) (void)hipEventDestroy(g->ev_out);

@@ -111,14 +111,42 @@ struct GroupMttkrp {
     float *out, *carry;
 };
 
+// stream-ordered allocation from `pool`, or from the device default pool
+inline hipError_t stream_alloc(void **p, size_t bytes, hipStream_t s, hipMemPool_t pool) {
+    return pool ? hipMallocFromPoolAsync(p, bytes, pool, s) : hipMallocAsync(p, bytes, s);
+}
+
+// Where device memory made on a context's behalf comes from: the caller's
+// callbacks when user.alloc is set, else stream-ordered allocation from
+// `pool` (null: the device's default pool).  Every free names the stream the
+// memory was last used on, so its reuse is ordered after that stream's work.
+struct DevMem {
+    dfacto_allocator user{nullptr, nullptr, nullptr};
+    hipMemPool_t pool = nullptr;
+    bool has_user() const { return user.alloc != nullptr; }
+    hipError_t alloc(void **p, size_t bytes, hipStream_t s) const {
+        if (has_user()) {
+            *p = user.alloc(bytes, (void *)s, user.user);
+            return *p ? hipSuccess : hipErrorOutOfMemory;
+        }
+        return stream_alloc(p, bytes, s, pool);
+    }
+    void free(void *p, hipStream_t s) const {
+        if (!p) return;
+        if (has_user()) user.free(p, (void *)s, user.user);
+        else (void)hipFreeAsync(p, s);
+    }
+};
+
 }  // namespace dfacto
 
 struct dfacto_tensor {
     int device = 0;
-    // when set, the tensor's memory is stream-ordered (hipMallocAsync on this
-    // stream) and freeing it does not wait for unrelated device work
+    // when set, the tensor's memory is stream-ordered (from `mem`, on this
+    // stream) and freeing it does not wait for unrelated device work;
+    // otherwise it comes from hipMalloc
     hipStream_t alloc_stream = nullptr;
-    hipMemPool_t alloc_pool = nullptr;  // pool of those allocations (null: the device default)
+    dfacto::DevMem mem;
     int64_t dims[3] = {0, 0, 0};
     int64_t nnz = 0;
     double normsq = 0.0;
@@ -140,9 +168,8 @@ struct dfacto_tensor {
 struct dfacto_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    // memory pool for the stream-ordered allocations made on this context's
-    // behalf (null: the device's default pool)
-    hipMemPool_t pool = nullptr;
+    // source of the device memory made on this context's behalf
+    dfacto::DevMem mem;
     // a second stream for work that overlaps the main stream's (created on
     // first use), joined back by events
     hipStream_t side = nullptr;
@@ -172,10 +199,6 @@ struct Error {
 
 dfacto_status fail(dfacto_ctx *ctx, dfacto_status code, const std::string &msg);
 
-// stream-ordered allocation from `pool`, or from the device default pool
-inline hipError_t stream_alloc(void **p, size_t bytes, hipStream_t s, hipMemPool_t pool) {
-    return pool ? hipMallocFromPoolAsync(p, bytes, pool, s) : hipMallocAsync(p, bytes, s);
-}
 void hip_check(hipError_t e, const char *what);  // throws Error on failure
 #define DF_HIP(call) ::dfacto::hip_check((call), #call)
 // after kernel launches: a launch error names the launching function
@@ -191,8 +214,9 @@ void prof_mark(dfacto_ctx *ctx);
 // ---------------------------------------------------------------------------
 
 // device-wide primitives (build.hip)
+// (temporaries from mem, the device default pool when null)
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s,
-                        hipMemPool_t pool = nullptr);
+                        const DevMem *mem = nullptr);
 
 // builder (build.hip): fills t (allocates its arrays).  Synchronizes.
 // dfacto_build_flattenings with stream-ordered tensor memory on ctx's stream

@@ -552,12 +552,12 @@ dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
     }
     s->budget = hbm_budget;
     bool ok = hipMalloc(&s->d_fits, 8 * (size_t)max_slots) == hipSuccess &&
-              dfacto_ctx_create(device, s->stream, &s->ctx) == DFACTO_OK;
+              dfacto_ctx_create(device, s->stream, nullptr, &s->ctx) == DFACTO_OK;
     for (int b = 0; ok && b < dfacto_server::kBuilders; ++b)
-        ok = dfacto_ctx_create(device, s->bstream[b], &s->bctx[b]) == DFACTO_OK;
+        ok = dfacto_ctx_create(device, s->bstream[b], nullptr, &s->bctx[b]) == DFACTO_OK;
     if (ok) {
-        s->ctx->pool = s->pool;
-        for (int b = 0; b < dfacto_server::kBuilders; ++b) s->bctx[b]->pool = s->pool;
+        s->ctx->mem.pool = s->pool;
+        for (int b = 0; b < dfacto_server::kBuilders; ++b) s->bctx[b]->mem.pool = s->pool;
     }
     if (!ok) {
         (void)hipGetLastError();

@@ -103,7 +103,7 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     PP = ctypes.POINTER(ctypes.c_void_p)
-    lib.dfacto_ctx_create.argtypes = [I, P, PP]
+    lib.dfacto_ctx_create.argtypes = [I, P, P, PP]
     lib.dfacto_ctx_set_stream.argtypes = [P, P]
     lib.dfacto_ctx_synchronize.argtypes = [P]
     lib.dfacto_ctx_destroy.argtypes = [P]
@@ -162,17 +162,59 @@ def _dtype_code(t: torch.Tensor) -> int:
     raise TypeError(f"factor dtype must be float32 or bfloat16, got {t.dtype}")
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """A dfacto_allocator served by torch's caching allocator: the library's
+    device memory is torch memory (counted by torch.cuda.memory_allocated and
+    reused by torch once freed, in the order of the stream it was allocated
+    on).  An allocation torch cannot serve becomes DFACTO_E_NOMEM."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+
+        def _alloc(nbytes, stream, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream or 0)
+            except Exception:
+                return None
+
+        def _free(ptr, stream, user):
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:  # torch already torn down at interpreter exit
+                pass
+
+        self._fns = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+        self.struct = _Allocator(self._fns[0], self._fns[1], None)
+
+
 class Context:
     """A dfacto_ctx bound to a device and a HIP stream (torch's current one
-    unless given)."""
+    unless given).  allocator: None (the library allocates), "torch" (a
+    TorchAllocator) or an object with a ctypes `struct` field laid out as
+    dfacto_allocator; it is kept alive by the context and by every tensor
+    built with it."""
 
-    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None,
+                 allocator=None):
         lib = load()
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self._stream = stream
+        if allocator == "torch":
+            allocator = TorchAllocator(device)
+        self.allocator = allocator
         h = ctypes.c_void_p()
-        st = lib.dfacto_ctx_create(int(device), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        st = lib.dfacto_ctx_create(int(device), ctypes.c_void_p(stream.cuda_stream),
+                                   ctypes.byref(allocator.struct) if allocator else None,
+                                   ctypes.byref(h))
         if st != OK:
             raise DfactoError(st, "dfacto_ctx_create failed")
         self.handle = h
@@ -207,8 +249,9 @@ class Context:
 class Tensor:
     """A built dfacto_tensor (the three flattenings, resident on the device)."""
 
-    def __init__(self, handle):
+    def __init__(self, handle, allocator=None):
         self.handle = handle
+        self._allocator = allocator  # frees the flattenings in close()
 
     def info(self) -> dict:
         inf = _Info()
@@ -231,8 +274,8 @@ class Tensor:
             pass
 
 
-def ctx_create(device: int = 0, stream=None) -> Context:
-    return Context(device, stream)
+def ctx_create(device: int = 0, stream=None, allocator=None) -> Context:
+    return Context(device, stream, allocator)
 
 
 def build_flattenings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, k: torch.Tensor,
@@ -249,7 +292,7 @@ def build_flattenings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, k: t
     h = ctypes.c_void_p()
     ctx.check(load().dfacto_build_flattenings(ctx.handle, d, n, _ptr(i), _ptr(j), _ptr(k), _ptr(val),
                                               ctypes.byref(h)))
-    return Tensor(h)
+    return Tensor(h, ctx.allocator)
 
 
 def build_ratings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, y: torch.Tensor) -> Tensor:
@@ -266,7 +309,7 @@ def build_ratings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, y: torch
     h = ctypes.c_void_p()
     ctx.check(load().dfacto_build_ratings(ctx.handle, d, n, _ptr(i), _ptr(j), _ptr(y),
                                           ctypes.byref(h)))
-    return Tensor(h)
+    return Tensor(h, ctx.allocator)
 
 
 def joint_grad(ctx: Context, X: Tensor, Y: Tensor, factors, grads, f: torch.Tensor, mu: float,

@@ -38,8 +38,12 @@ def test_no_device_is_reported_as_error():
         return
     lib = dfacto.load()
     h = ctypes.c_void_p()
-    assert lib.dfacto_ctx_create(0, None, ctypes.byref(h)) == dfacto.E_DEVICE
-    assert lib.dfacto_ctx_create(0, None, None) == dfacto.E_INVALID
+    assert lib.dfacto_ctx_create(0, None, None, ctypes.byref(h)) == dfacto.E_DEVICE
+    assert lib.dfacto_ctx_create(0, None, None, None) == dfacto.E_INVALID
+    # an allocator must name both functions
+    half = dfacto._Allocator()
+    half.alloc = dfacto._ALLOC_FN(lambda n, s, u: None)
+    assert lib.dfacto_ctx_create(0, None, ctypes.byref(half), ctypes.byref(h)) == dfacto.E_INVALID
     assert lib.dfacto_last_error(None) == b"context is NULL"
 
 
