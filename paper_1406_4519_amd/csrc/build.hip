@@ -537,8 +537,6 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
         hipLaunchKernelGGL(k_compact_rows, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, pos,
                            nrows, md.empty_rows);
         DF_LAUNCHED();
-        md.empty_rows_host.resize((size_t)nrows);
-        for (int64_t r = 0; r < nrows; ++r) md.empty_rows_host[r] = (uint32_t)r;
         DF_HIP(hipStreamSynchronize(s));
         return;
     }
@@ -587,10 +585,6 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
                        md.stream, L, md.nchunk, chunk_len, md.chunk_start);
     DF_LAUNCHED();
     build_runs(t, md, s, sc);
-    md.empty_rows_host.resize((size_t)md.nempty);
-    if (md.nempty > 0)  // complete when build_tensor waits for the stream
-        DF_HIP(hipMemcpyAsync(md.empty_rows_host.data(), md.empty_rows,
-                              sizeof(uint32_t) * md.nempty, hipMemcpyDeviceToHost, s));
 }
 
 // 1 where a stream entry opens an output row (a ROOT header)

@@ -50,10 +50,20 @@ struct dfacto_group {
     hipGraphExec_t exec = nullptr;
     // persistent grid size of each MTTKRP launch (tuned or default)
     std::vector<unsigned> grid_store;
-    // device tables (sub-allocated) and their host copies
-    char *arena = nullptr;
-    size_t arena_left = 0;
-    std::deque<std::vector<char>> host_tables;
+    // Small tables built on the host go to arena chunks (device memory of at
+    // least 4 MB) through one host staging buffer per chunk, copied once the
+    // group is built (the staging stays until the group is freed, so the
+    // copy is asynchronous).  Tables combined from the members' device lists
+    // (work items, runs, empty rows) are expanded on the device into
+    // separately reserved space.
+    struct Chunk {
+        char *dev;
+        size_t cap, used;
+        std::vector<char> host;
+    };
+    std::deque<Chunk> arena;
+    char *dev_arena = nullptr;
+    size_t dev_left = 0;
 };
 
 namespace {
@@ -70,28 +80,88 @@ T *dev_alloc(dfacto_group *g, size_t count) {
     return (T *)p;
 }
 
-// Tables go to device chunks of at least 4 MB (few allocations); their host
-// copies stay in the group until it is freed, so the copies are
-// asynchronous on the group's stream.
+// A host table's place in the arena; its bytes are staged and copied with
+// the whole chunk by upload_all().
 template <typename T>
 T *upload(dfacto_group *g, const std::vector<T> &v) {
     const size_t bytes = (std::max<size_t>(v.size(), 1) * sizeof(T) + 255) & ~(size_t)255;
-    if (g->arena_left < bytes) {
-        const size_t chunk = std::max<size_t>(bytes, 4u << 20);
-        g->arena = dev_alloc<char>(g, chunk);
-        g->arena_left = chunk;
+    if (g->arena.empty() || g->arena.back().cap - g->arena.back().used < bytes) {
+        const size_t cap = std::max<size_t>(bytes, 4u << 20);
+        g->arena.push_back({dev_alloc<char>(g, cap), cap, 0, {}});
     }
-    T *d = (T *)g->arena;
-    g->arena += bytes;
-    g->arena_left -= bytes;
-    if (!v.empty()) {
-        g->host_tables.emplace_back(reinterpret_cast<const char *>(v.data()),
-                                    reinterpret_cast<const char *>(v.data() + v.size()));
-        DF_HIP(hipMemcpyAsync(d, g->host_tables.back().data(), sizeof(T) * v.size(),
-                              hipMemcpyHostToDevice, g->stream));
-    }
+    dfacto_group::Chunk &c = g->arena.back();
+    T *d = (T *)(c.dev + c.used);
+    c.host.resize(c.used + bytes);
+    if (!v.empty()) std::memcpy(c.host.data() + c.used, v.data(), sizeof(T) * v.size());
+    c.used += bytes;
     return d;
 }
+
+void upload_all(dfacto_group *g) {
+    for (dfacto_group::Chunk &c : g->arena)
+        if (c.used)
+            DF_HIP(hipMemcpyAsync(c.dev, c.host.data(), c.used, hipMemcpyHostToDevice, g->stream));
+}
+
+// Device space for an expanded table (chunks of at least 16 MB).
+template <typename T>
+T *dev_reserve(dfacto_group *g, size_t count) {
+    const size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) & ~(size_t)255;
+    if (g->dev_left < bytes) {
+        const size_t cap = std::max<size_t>(bytes, 16u << 20);
+        g->dev_arena = dev_alloc<char>(g, cap);
+        g->dev_left = cap;
+    }
+    T *d = (T *)g->dev_arena;
+    g->dev_arena += bytes;
+    g->dev_left -= bytes;
+    return d;
+}
+
+// One member's part of a combined table: `count` elements from `off` on.
+// width 0: (t, x * step) work items; 1: (t, src[x]); 3: (t, src[3x],
+// src[3x + 1], src[3x + 2]).
+struct ExpandJob {
+    const uint32_t *src;
+    uint64_t off;
+    uint32_t t, count, width, step;
+};
+
+// out[x] for x < total from the job whose range holds x (jobs in order of off)
+template <typename V>
+__global__ __launch_bounds__(256) void k_expand(const ExpandJob *__restrict__ jobs, int njobs,
+                                                uint64_t total, V *__restrict__ out) {
+    for (uint64_t x = blockIdx.x * 256ull + threadIdx.x; x < total;
+         x += (uint64_t)gridDim.x * 256ull) {
+        int lo = 0, hi = njobs - 1;  // the last job with off <= x
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (jobs[mid].off <= x) lo = mid;
+            else hi = mid - 1;
+        }
+        const ExpandJob j = jobs[lo];
+        const uint32_t e = (uint32_t)(x - j.off);
+        if constexpr (sizeof(V) == 8) {
+            out[x] = make_uint2(j.t, j.width ? j.src[e] : e * j.step);
+        } else {
+            const uint32_t *p = j.src + 3ull * e;
+            out[x] = make_uint4(j.t, p[0], p[1], p[2]);
+        }
+    }
+}
+
+// A combined table whose jobs are uploaded now and expanded after upload_all.
+template <typename V>
+struct Expansion {
+    std::vector<ExpandJob> jobs;
+    uint64_t total = 0;
+    V *out = nullptr;
+    void add(uint32_t t, const uint32_t *src, uint64_t count, uint32_t width, uint32_t step) {
+        if (count == 0) return;
+        jobs.push_back({src, total, t, (uint32_t)count, width, step});
+        total += count;
+    }
+};
 
 // Per-member device workspace.
 struct MemberWs {
@@ -111,6 +181,25 @@ struct Build {
     std::vector<MemberWs> ws;
     std::vector<std::function<void()>> mt_steps;  // the MTTKRP launches, for tuning
     std::vector<size_t> mt_index;                 // their grid slots
+    std::vector<std::function<void()>> post;      // table expansions, after upload_all
+
+    // device space for a combined table; its expansion runs after upload_all
+    template <typename V>
+    V *expand(const Expansion<V> &x) {
+        V *out = dev_reserve<V>(g, x.total);
+        if (x.total == 0) return out;
+        const ExpandJob *dj = upload(g, x.jobs);
+        const int nj = (int)x.jobs.size();
+        const uint64_t total = x.total;
+        dfacto_group *const grp = g;
+        post.push_back([grp, dj, nj, total, out] {
+            const unsigned grid = (unsigned)std::min<uint64_t>((total + 255) / 256, 8192);
+            hipLaunchKernelGGL(k_expand<V>, dim3(grid), dim3(256), 0, grp->stream, dj, nj, total,
+                               out);
+            DF_LAUNCHED();
+        });
+        return out;
+    }
 
     // One Gram over all members: out[t] = F(t)^T F(t) (rows(t) x R(t)).
     void add_gram(dfacto_dtype dt, const std::function<const void *(int)> &Fof,
@@ -168,9 +257,8 @@ struct Build {
             struct Cls {
                 MttkrpShape sh;
                 bool small;
-                std::vector<uint2> items;
-                std::vector<uint4> shortr, longr;
-                std::vector<uint2> empty;
+                Expansion<uint2> items, empty;
+                Expansion<uint4> shortr, longr;
             };
             std::map<std::tuple<int, int, int, bool>, Cls> cls;
             for (int t = 0; t < n; ++t) {
@@ -183,24 +271,21 @@ struct Build {
                 Cls &c = cls[{sh.cpl, sh.g, sh.nch, sm}];
                 c.sh = sh;
                 c.small = sm;
+                // (t, first chunk) items; (t, row, first chunk, chunks) runs;
+                // (t, row) empty rows -- from the member's own device lists
                 const uint32_t per = mttkrp_group_chunks_per_item(sh);
-                for (uint32_t b = 0; b < (uint32_t)md.nchunk; b += per)
-                    c.items.push_back(make_uint2(t, b));
-                const auto &rs = md.runs_short_host;
-                for (int64_t r = 0; r < md.nruns_short; ++r)
-                    c.shortr.push_back(make_uint4(t, rs[3 * r], rs[3 * r + 1], rs[3 * r + 2]));
-                const auto &rl = md.runs_long_host;
-                for (int64_t r = 0; r < md.nruns_long; ++r)
-                    c.longr.push_back(make_uint4(t, rl[3 * r], rl[3 * r + 1], rl[3 * r + 2]));
-                for (uint32_t row : md.empty_rows_host) c.empty.push_back(make_uint2(t, row));
+                c.items.add(t, nullptr, (md.nchunk + per - 1) / per, 0, per);
+                c.shortr.add(t, md.runs_short, md.nruns_short, 3, 0);
+                c.longr.add(t, md.runs_long, md.nruns_long, 3, 0);
+                c.empty.add(t, md.empty_rows, md.nempty, 1, 0);
             }
             const GroupMttkrp *dd = upload(g, desc);
             for (auto &kv : cls) {
                 Cls &c = kv.second;
                 const MttkrpShape sh = c.sh;
                 const bool sm = c.small;
-                const uint2 *items = upload(g, c.items);
-                const uint32_t nitems = (uint32_t)c.items.size();
+                const uint2 *items = expand(c.items);
+                const uint32_t nitems = (uint32_t)c.items.total;
                 g->grid_store.push_back(
                     std::max(1u, std::min<unsigned>(nitems, (unsigned)g->gctx.num_cu * 8)));
                 const size_t gi = g->grid_store.size() - 1;
@@ -212,10 +297,10 @@ struct Build {
                 mt_steps.push_back(step);
                 mt_index.push_back(gi);
                 ++g->launches;
-                const uint4 *ds = upload(g, c.shortr), *dl = upload(g, c.longr);
-                const uint2 *de = upload(g, c.empty);
-                const uint32_t ns = (uint32_t)c.shortr.size(), ne = (uint32_t)c.empty.size(),
-                               nl = (uint32_t)c.longr.size();
+                const uint4 *ds = expand(c.shortr), *dl = expand(c.longr);
+                const uint2 *de = expand(c.empty);
+                const uint32_t ns = (uint32_t)c.shortr.total, ne = (uint32_t)c.empty.total,
+                               nl = (uint32_t)c.longr.total;
                 grp->steps.push_back([grp, sh, dd, ds, ns, de, ne, dl, nl] {
                     launch_fix_group(&grp->gctx, sh, dd, ds, ns, de, ne, dl, nl);
                 });
@@ -408,7 +493,11 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
                     dtype, [&](int t) -> const void * { return d_F[3 * t + m]; },
                     [&](int t) { return T[t]->dims[m]; }, [&](int t) { return b.ws[t].G[m]; });
             for (int m = 0; m < 3; ++m) b.add_mode(m);
-            DF_HIP(hipStreamSynchronize(g->stream));
+            // the host tables in one copy per arena chunk, then the combined
+            // tables expanded on the device (stream order keeps them ahead of
+            // every iteration)
+            upload_all(g);
+            for (auto &f : b.post) f();
 
             if (flags & DFACTO_GROUP_TUNE) autotune(g, b.mt_steps, b.mt_index);
             *out = g;

@@ -48,9 +48,8 @@ struct ModeData {
     int64_t nruns_short = 0;
     uint32_t *runs_long = nullptr;
     int64_t nruns_long = 0;
-    // host copies of the run lists and empty rows (for grouped launches,
-    // whose tables combine many tensors)
-    std::vector<uint32_t> runs_short_host, runs_long_host, empty_rows_host;
+    // host copies of the run lists (the sources of their uploads)
+    std::vector<uint32_t> runs_short_host, runs_long_host;
 };
 constexpr int kShortRun = 16;
 
