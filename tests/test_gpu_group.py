@@ -59,6 +59,52 @@ def _same(a, b):
                        b.view(torch.int16) if b.dtype == torch.bfloat16 else b)
 
 
+def _edge_members(ctx):
+    """Members that stress the combined tables: no nonzeros (no chunks, every
+    row empty), one nonzero, one row of 20,000 nonzeros (long carry runs)
+    next to light rows, and a full 12 x 11 x 10 tensor (no empty row)."""
+    rng = np.random.default_rng(901)
+    u32 = lambda a: np.asarray(a, dtype=np.uint32)
+    coos = [gen.Coo((50, 40, 30), u32([]), u32([]), u32([]), np.zeros(0, np.float32)),
+            gen.Coo((60, 50, 40), u32([7]), u32([3]), u32([39]), np.ones(1, np.float32))]
+    lin = rng.choice(300 * 200, 20_000, replace=False)
+    extra = rng.choice(400 * 300 * 200, 5_000, replace=False)
+    ei, ej, ek = extra // (300 * 200), (extra // 200) % 300, extra % 200
+    keep = ei != 5
+    coos.append(gen.Coo((400, 300, 200), u32(np.concatenate([np.full(20_000, 5), ei[keep]])),
+                        u32(np.concatenate([lin // 200, ej[keep]])),
+                        u32(np.concatenate([lin % 200, ek[keep]])),
+                        rng.standard_normal(20_000 + int(keep.sum())).astype(np.float32)))
+    g = np.indices((12, 11, 10)).reshape(3, -1)
+    coos.append(gen.Coo((12, 11, 10), u32(g[0]), u32(g[1]), u32(g[2]),
+                        rng.standard_normal(g.shape[1]).astype(np.float32)))
+    return [(c, build(ctx, c), R, gen.init_factors(c.dims, R, seed=910 + s))
+            for s, (c, R) in enumerate(zip(coos, (8, 16, 32, 4)))]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_group_edge_members_bitwise(ctx, dtype):
+    members = _edge_members(ctx)
+    Fg, lg, fg = _state(members, dtype)
+    Fs, ls, fs = _state(members, dtype)
+    g = dfacto.Group(ctx, [m[1] for m in members], Fg, lg, fg)
+    g.als(2)
+    for k, (coo, t, R, _) in enumerate(members):
+        fit = torch.zeros(1, dtype=torch.float64, device=DEV)
+        for _ in range(2):
+            dfacto.als_iter(ctx, t, Fs[k], ls[k], fit)
+        fs[k] = fit[0]
+    torch.cuda.synchronize()
+    say(f"  edge members: nnz {[m[0].nnz for m in members]}, fits {fg.tolist()}")
+    for k in range(len(members)):
+        for m in range(3):
+            assert _same(Fg[k][m], Fs[k][m]), f"member {k} factor {m} differs"
+        assert torch.equal(lg[k], ls[k]) and torch.equal(fg[k], fs[k]), f"member {k}"
+    g.close()
+    for m in members:
+        m[1].close()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_group_bitwise_equals_single(ctx, members, dtype):
     Fg, lg, fg = _state(members, dtype)
