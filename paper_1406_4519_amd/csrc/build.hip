@@ -417,21 +417,18 @@ T *tensor_alloc(dfacto_tensor *t, int64_t n) {
     return (T *)p;
 }
 
-template <typename T>
-T read_back(const T *d, hipStream_t s) {
-    T h;
-    DF_HIP(hipMemcpyAsync(&h, d, sizeof(T), hipMemcpyDeviceToHost, s));
+// out[q] = *a[q] + *b[q] for several scan totals (last offset plus last
+// flag of an exclusive scan), one wait
+template <int N>
+void read_back_sums(const uint32_t *const (&a)[N], const uint32_t *const (&b)[N], int64_t (&out)[N],
+                    hipStream_t s) {
+    uint32_t h[2 * N];
+    for (int q = 0; q < N; ++q) {
+        DF_HIP(hipMemcpyAsync(&h[2 * q], a[q], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        DF_HIP(hipMemcpyAsync(&h[2 * q + 1], b[q], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    }
     DF_HIP(hipStreamSynchronize(s));
-    return h;
-}
-
-// *a + *b (the total of an exclusive scan: last offset plus last flag), one wait
-int64_t read_back_sum(const uint32_t *a, const uint32_t *b, hipStream_t s) {
-    uint32_t h[2];
-    DF_HIP(hipMemcpyAsync(&h[0], a, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    DF_HIP(hipMemcpyAsync(&h[1], b, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    DF_HIP(hipStreamSynchronize(s));
-    return (int64_t)h[0] + h[1];
+    for (int q = 0; q < N; ++q) out[q] = (int64_t)h[2 * q] + h[2 * q + 1];
 }
 
 void radix_sort(uint64_t *&keys, uint32_t *&vals, uint64_t *&kalt, uint32_t *&valt, int64_t n,
@@ -464,15 +461,20 @@ __global__ void k_chunk_heads(const uint2 *__restrict__ st, const uint32_t *__re
 
 // Rows split across chunks: a maximal sequence of chunks whose first header
 // continues the same row (no ROOT bit) forms one run of carries.
-void build_runs(dfacto_tensor *t, ModeData &md, hipStream_t s, Scratch &sc) {
+// The heads of the mode's chunks, copied to `heads` (complete at the build's
+// next wait); finish_runs forms the run lists from them.
+void chunk_heads(ModeData &md, hipStream_t s, Scratch &sc, std::vector<uint2> &heads) {
+    heads.assign((size_t)md.nchunk, make_uint2(0u, 0u));
     if (md.nchunk == 0) return;
     uint2 *dh = sc.alloc<uint2>(md.nchunk);
     hipLaunchKernelGGL(k_chunk_heads, dim3(grid_for(md.nchunk)), dim3(kThreads), 0, s, md.stream,
                        md.chunk_start, md.nchunk, dh);
     DF_LAUNCHED();
-    std::vector<uint2> heads((size_t)md.nchunk);
     DF_HIP(hipMemcpyAsync(heads.data(), dh, sizeof(uint2) * md.nchunk, hipMemcpyDeviceToHost, s));
-    DF_HIP(hipStreamSynchronize(s));
+}
+
+void finish_runs(dfacto_tensor *t, ModeData &md, hipStream_t s, const std::vector<uint2> &heads) {
+    if (md.nchunk == 0) return;
     std::vector<uint32_t> shortr, longr;
     int64_t c = 0;
     while (c < md.nchunk) {
@@ -505,8 +507,11 @@ void build_runs(dfacto_tensor *t, ModeData &md, hipStream_t s, Scratch &sc) {
     md.runs_long_host = std::move(longr);
 }
 
+// Mode m's flattening from its nonzeros in (root, mid) order; the chunk
+// heads for its run lists land in `heads` at the build's next wait.
 void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
-                const uint32_t *mid, const uint32_t *leaf, const float *val, int64_t n) {
+                const uint32_t *mid, const uint32_t *leaf, const float *val, int64_t n,
+                std::vector<uint2> &heads) {
     hipStream_t s = ctx->stream;
     ModeData &md = t->mode[m];
     const int64_t nrows = t->dims[md.root];
@@ -546,17 +551,31 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     hipLaunchKernelGGL(k_fiber_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, root, mid, n, fs,
                        rs);
     scan_exclusive_u32(fs, fid, n, s, &sc.mem);
-    md.nfib = read_back_sum(fid + n - 1, fs + n - 1, s);
-    uint32_t *fptr = sc.alloc<uint32_t>(md.nfib);
-    hipLaunchKernelGGL(k_fiber_start_pos, dim3(grid_for(n)), dim3(kThreads), 0, s, fs, fid, n,
-                       md.nfib, fptr);
+    // fiber starts (n bounds the fiber count: no wait for it here)
+    uint32_t *fptr = sc.alloc<uint32_t>(n);
+    hipLaunchKernelGGL(k_fiber_start_pos, dim3(grid_for(n)), dim3(kThreads), 0, s, fs, fid, n, n,
+                       fptr);
     uint32_t *h = sc.alloc<uint32_t>(n);
     hipLaunchKernelGGL(k_header_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, fs, fid, fptr, n,
-                       md.nfib, h);
+                       n, h);
     sc.release(fptr);
-    uint32_t *hex = fid;  // reuse
+    uint32_t *hex = sc.alloc<uint32_t>(n);
     scan_exclusive_u32(h, hex, n, s, &sc.mem);
-    const int64_t nhdr = read_back_sum(hex + n - 1, h + n - 1, s);
+    // roots and empty output rows
+    uint32_t *mark = sc.alloc<uint32_t>(nrows);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, nrows, 1u);
+    hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(n)), dim3(kThreads), 0, s, root, rs, n, nrows,
+                       mark);
+    uint32_t *rpos = sc.alloc<uint32_t>(nrows);
+    scan_exclusive_u32(mark, rpos, nrows, s, &sc.mem);
+    DF_LAUNCHED();
+    // fibers, headers and empty rows, one wait
+    int64_t cnt[3];
+    read_back_sums<3>({fid + n - 1, hex + n - 1, rpos + nrows - 1},
+                      {fs + n - 1, h + n - 1, mark + nrows - 1}, cnt, s);
+    md.nfib = cnt[0];
+    const int64_t nhdr = cnt[1];
+    md.nempty = cnt[2];
     const int64_t L = n + nhdr;
     if (L > (int64_t)0xFFFFFFFFu - (1 << 20))
         throw Error{DFACTO_E_UNSUPPORTED, "nonzeros plus fiber headers exceed 2^32 - 2^20"};
@@ -566,14 +585,6 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
                        h, hex, rs, n, L, md.stream);
     hipLaunchKernelGGL(k_fill_pad, dim3(1), dim3(kThreads), 0, s, md.stream, L,
                        (int64_t)kStreamPad);
-    // roots and empty output rows
-    uint32_t *mark = sc.alloc<uint32_t>(nrows);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, nrows, 1u);
-    hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(n)), dim3(kThreads), 0, s, root, rs, n, nrows,
-                       mark);
-    uint32_t *rpos = sc.alloc<uint32_t>(nrows);
-    scan_exclusive_u32(mark, rpos, nrows, s, &sc.mem);
-    md.nempty = read_back_sum(rpos + nrows - 1, mark + nrows - 1, s);
     md.nroot = nrows - md.nempty;
     md.empty_rows = tensor_alloc<uint32_t>(t, md.nempty);
     hipLaunchKernelGGL(k_compact_rows, dim3(grid_for(nrows)), dim3(kThreads), 0, s, mark, rpos,
@@ -584,7 +595,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     hipLaunchKernelGGL(k_chunk_starts, dim3(grid_for(md.nchunk + 1)), dim3(kThreads), 0, s,
                        md.stream, L, md.nchunk, chunk_len, md.chunk_start);
     DF_LAUNCHED();
-    build_runs(t, md, s, sc);
+    chunk_heads(md, s, sc, heads);
 }
 
 // 1 where a stream entry opens an output row (a ROOT header)
@@ -690,22 +701,21 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
         t->mode[m].mid = MID[m];
         t->mode[m].leaf = LEAF[m];
     }
-    if (n > 0) {
-        uint32_t *flag = sc.alloc<uint32_t>(1);
-        DF_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t), s));
-        hipLaunchKernelGGL(k_validate, dim3(grid_for(n)), dim3(kThreads), 0, s, d_i, d_j, d_k,
-                           d_val, n, (uint32_t)t->dims[0], (uint32_t)t->dims[1],
-                           (uint32_t)t->dims[2], flag);
-        DF_LAUNCHED();
-        const uint32_t bad = read_back(flag, s);
-        if (bad & 1u) throw Error{DFACTO_E_RANGE, "a coordinate is not below its dimension"};
-        if (bad & 2u) throw Error{DFACTO_E_NUMERIC, "a tensor value is NaN or Inf"};
-    }
+    std::vector<uint2> heads[3];
     if (n == 0) {
         t->normsq = 0.0;
-        for (int m = 0; m < 3; ++m) build_mode(ctx, t, m, nullptr, nullptr, nullptr, nullptr, 0);
+        for (int m = 0; m < 3; ++m)
+            build_mode(ctx, t, m, nullptr, nullptr, nullptr, nullptr, 0, heads[m]);
         return;
     }
+    // coordinates and values are checked here and the verdict read with the
+    // distinct count below: until then only sort keys (any bits) and
+    // permutation-indexed copies depend on them
+    uint32_t *flag = sc.alloc<uint32_t>(1);
+    DF_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t), s));
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(n)), dim3(kThreads), 0, s, d_i, d_j, d_k, d_val,
+                       n, (uint32_t)t->dims[0], (uint32_t)t->dims[1], (uint32_t)t->dims[2], flag);
+    DF_LAUNCHED();
     const int bI = bits_for(t->dims[0]), bJ = bits_for(t->dims[1]), bK = bits_for(t->dims[2]);
     uint64_t *key = sc.alloc<uint64_t>(n), *kalt = sc.alloc<uint64_t>(n);
     uint32_t *perm = sc.alloc<uint32_t>(n), *palt = sc.alloc<uint32_t>(n);
@@ -735,7 +745,14 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
     hipLaunchKernelGGL(k_distinct_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, si, sj, sk, n,
                        dflag);
     scan_exclusive_u32(dflag, dpos, n, s, &sc.mem);
-    const int64_t nd = read_back_sum(dpos + n - 1, dflag + n - 1, s);
+    uint32_t h[3];
+    DF_HIP(hipMemcpyAsync(&h[0], flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    DF_HIP(hipMemcpyAsync(&h[1], dpos + n - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    DF_HIP(hipMemcpyAsync(&h[2], dflag + n - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    DF_HIP(hipStreamSynchronize(s));
+    if (h[0] & 1u) throw Error{DFACTO_E_RANGE, "a coordinate is not below its dimension"};
+    if (h[0] & 2u) throw Error{DFACTO_E_NUMERIC, "a tensor value is NaN or Inf"};
+    const int64_t nd = (int64_t)h[1] + h[2];
     uint32_t *di = sc.alloc<uint32_t>(nd), *dj = sc.alloc<uint32_t>(nd), *dk = sc.alloc<uint32_t>(nd);
     float *dv = sc.alloc<float>(nd);
     hipLaunchKernelGGL(k_merge_runs, dim3(grid_for(n)), dim3(kThreads), 0, s, dflag, dpos, n, si,
@@ -756,7 +773,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
         DF_HIP(hipMemcpyAsync(&t->normsq, tot, sizeof(double), hipMemcpyDeviceToHost, s));
     }
     // mode 0: already in (i, k, j) order
-    build_mode(ctx, t, 0, di, dk, dj, dv, nd);
+    build_mode(ctx, t, 0, di, dk, dj, dv, nd, heads[0]);
     // modes 1 and 2: stable sort by (root, mid) from the mode-0 order
     uint64_t *key2 = sc.alloc<uint64_t>(nd), *kalt2 = sc.alloc<uint64_t>(nd);
     uint32_t *p2 = perm, *palt2 = palt;  // n >= nd
@@ -774,9 +791,11 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
         hipLaunchKernelGGL(k_gather4, dim3(grid_for(nd)), dim3(kThreads), 0, s, p2, nd,
                            coord[md.root], coord[md.mid], coord[md.leaf], dv, gr, gm, gl, gv);
         DF_LAUNCHED();
-        build_mode(ctx, t, m, gr, gm, gl, gv, nd);
+        build_mode(ctx, t, m, gr, gm, gl, gv, nd, heads[m]);
     }
-    DF_HIP(hipStreamSynchronize(s));  // the host copies of the run lists and empty rows
+    DF_HIP(hipStreamSynchronize(s));  // the chunk heads and ||X||^2
+    for (int m = 0; m < 3; ++m) finish_runs(t, t->mode[m], s, heads[m]);
+    DF_HIP(hipStreamSynchronize(s));  // the run lists' uploads
 }
 
 }  // namespace dfacto
