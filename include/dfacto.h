@@ -19,8 +19,14 @@
  *    dfacto_dtype (FP32, or BF16 stored as raw 16-bit patterns).  Row
  *    starts must be aligned to the element size.
  *  - Work is enqueued on the stream bound to the context and is
- *    stream-ordered; only dfacto_build_flattenings and dfacto_tensor_export
- *    synchronize.  Inputs must stay unmodified until the stream passes the
+ *    stream-ordered.  Calls that synchronize: the builds
+ *    (dfacto_build_flattenings, dfacto_build_ratings), dfacto_tensor_export,
+ *    the calls that return host results (dfacto_gd_step,
+ *    dfacto_joint_als_iter, dfacto_profile_read, dfacto_ctx_synchronize),
+ *    and a call that has to grow one of the context's workspaces (the first
+ *    call at a larger size, when the library allocates itself); a call
+ *    repeated at the same sizes only enqueues, so it can be captured in a
+ *    HIP graph.  Inputs must stay unmodified until the stream passes the
  *    call.
  *  - Every call returns a status; nothing aborts, throws or prints.  A HIP
  *    runtime failure is sticky: the context then returns DFACTO_E_DEVICE
@@ -222,9 +228,10 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R,
  * d_F[3 t + m] (row-major dims[m] x ranks[t], device, 16-byte aligned,
  * updated in place), d_lambda[t] (ranks[t] doubles, device) and d_fit[t]
  * (device double).  All pointers are caller-owned and must stay valid while
- * the group lives.  The group allocates its own workspace (reported by
- * dfacto_group_get_info) and uses its own HIP stream, ordered after ctx's
- * stream by events at each call.
+ * the group lives.  The group allocates its own workspace and tables
+ * (reported by dfacto_group_get_info; from ctx's memory source, the caller's
+ * allocator when one was given) and uses its own HIP stream, ordered after
+ * ctx's stream by events at each call.
  *
  * flags: DFACTO_GROUP_GRAPH captures one iteration as a HIP graph on the
  * first dfacto_group_als call and replays it; DFACTO_GROUP_TUNE times the
@@ -232,7 +239,9 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R,
  * the fastest (results do not depend on the choice); DFACTO_GROUP_CTX_STREAM
  * launches on the creating context's stream instead of a stream of the
  * group's own (cheaper to create and free; later calls must pass a context
- * with that same stream).  Creation synchronizes; E_UNSUPPORTED for a rank
+ * with that same stream).  Creation enqueues the upload and device-side
+ * assembly of the group's tables on its stream and returns without waiting
+ * (DFACTO_GROUP_TUNE waits for its timings); E_UNSUPPORTED for a rank
  * outside the list above. */
 #define DFACTO_GROUP_GRAPH 1
 #define DFACTO_GROUP_TUNE 2
