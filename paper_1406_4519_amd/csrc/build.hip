@@ -232,7 +232,12 @@ __global__ void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int s
 // Keys of a tile are taken in the order q * 256 + tid; a key's rank among
 // equal digits of the tile is (keys of earlier slots) + (earlier waves of
 // this slot) + (earlier lanes of this wave), the last from 8 ballots that
-// isolate the lanes holding the same digit.
+// isolate the lanes holding the same digit.  The tile's first position for
+// digit d is offs[d * nblk + tile] (the exclusive scan of the histograms in
+// (digit, tile) order); with kOwn the block forms it itself from the
+// histograms (few tiles: nblk reads per thread and a scan over the digits).
+constexpr int64_t kRadixOwnMax = 256;  // most tiles for kOwn
+template <bool kOwn>
 __global__ void k_radix_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                 uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                 int64_t n, int shift, const uint32_t *__restrict__ offs,
@@ -242,7 +247,28 @@ __global__ void k_radix_scatter(const uint64_t *__restrict__ kin, const uint32_t
     __shared__ uint32_t s_wc[kThreads / 64][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     s_run[tid] = 0;
-    s_base[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    if constexpr (kOwn) {  // offs holds the histograms here
+        const uint32_t *hd = offs + (int64_t)tid * nblk;
+        uint32_t tot = 0, pre = 0;
+        for (int64_t b = 0; b < nblk; ++b) {
+            const uint32_t c = hd[b];
+            tot += c;
+            pre += (b < (int64_t)blockIdx.x) ? c : 0u;
+        }
+        // inclusive scan of the digit totals (s_base as scratch), then
+        // exclusive = inclusive - own total
+        s_base[tid] = tot;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const uint32_t v = tid >= o ? s_base[tid - o] : 0u;
+            __syncthreads();
+            s_base[tid] += v;
+            __syncthreads();
+        }
+        s_base[tid] = s_base[tid] - tot + pre;
+    } else {
+        s_base[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     for (int q = 0; q < kRadixIpt; ++q) {
@@ -440,9 +466,14 @@ void radix_sort(uint64_t *&keys, uint32_t *&vals, uint64_t *&kalt, uint32_t *&va
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(kThreads), 0, s, keys, n,
                            shift, hist, nblk);
-        scan_exclusive_u32(hist, offs, 256 * nblk, s, &sc.mem);
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, keys,
-                           vals, kalt, valt, n, shift, offs, nblk);
+        if (nblk <= kRadixOwnMax) {  // two launches per pass instead of five
+            hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nblk), dim3(kThreads), 0, s,
+                               keys, vals, kalt, valt, n, shift, hist, nblk);
+        } else {
+            scan_exclusive_u32(hist, offs, 256 * nblk, s, &sc.mem);
+            hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nblk), dim3(kThreads), 0, s,
+                               keys, vals, kalt, valt, n, shift, offs, nblk);
+        }
         std::swap(keys, kalt);
         std::swap(vals, valt);
     }
