@@ -739,7 +739,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
             build_mode(ctx, t, m, nullptr, nullptr, nullptr, nullptr, 0, heads[m]);
         return;
     }
-    // coordinates and values are checked here and the verdict read with the
+    // coordinates and values are checked here and the outcome read with the
     // distinct count below: until then only sort keys (any bits) and
     // permutation-indexed copies depend on them
     uint32_t *flag = sc.alloc<uint32_t>(1);
