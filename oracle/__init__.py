@@ -71,6 +71,10 @@ def _load():
                                               ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                               P, P, P]
         lib.oracle_joint_als_iter.restype = ctypes.c_double
+        lib.oracle_joint_als_rows.argtypes = [i64, P, P, P, P, P, i64, P, P, P, ctypes.c_int,
+                                              ctypes.c_double, ctypes.c_double, P, P, P,
+                                              ctypes.c_int, i64, P, P]
+        lib.oracle_joint_als_rows.restype = None
         _lib = lib
     return _lib
 
@@ -260,3 +264,24 @@ def joint_als_iter(i, j, k, val, dims, yi, yj, yv, factors, mu: float, lam: floa
                                   _p(yj), _p(yv), R, float(mu), float(lam), int(store == "bf16"),
                                   _p(A), _p(B), _p(C))
     return A, B, C, float(f)
+
+
+def joint_als_rows(i, j, k, val, dims, yi, yj, yv, factors, mu: float, lam: float, mode: int,
+                   rows) -> np.ndarray:
+    """The listed rows of the users' (mode 0) or items' (mode 1) block of one
+    joint ALS iteration, from the factors as given (for mode 1 pass the
+    updated A), each solved as joint_als_iter solves it; (len(rows), R)."""
+    if mode not in (0, 1):
+        raise ValueError("mode must be 0 (users) or 1 (items)")
+    lib = _load()
+    i, j, k, val = _coo(i, j, k, val)
+    yi, yj, yv = _ratings(yi, yj, yv)
+    A, B, C = (_f64(f) for f in factors)
+    R = A.shape[1]
+    d = np.asarray(dims, dtype=np.int64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((len(rows), R), dtype=np.float64)
+    lib.oracle_joint_als_rows(len(val), _p(i), _p(j), _p(k), _p(val), _p(d), len(yv), _p(yi),
+                              _p(yj), _p(yv), R, float(mu), float(lam), _p(A), _p(B), _p(C),
+                              int(mode), len(rows), _p(rows), _p(out))
+    return out

@@ -708,6 +708,33 @@ double oracle_joint_grad(int64_t nnz, const uint32_t *i, const uint32_t *j, cons
  * numerically singular.  store_bf16 != 0 models factors kept in BF16
  * storage: each new factor is rounded to BF16 before later use.  A, B, C are
  * updated in place; returns f at the new point. */
+/* Row `row` of mode n's block of the joint ALS (the closed form above):
+ * S = mu (Gp * Gq) + lam I + sum over the row's ratings of v v^T, rhs =
+ * mu M[row] + sum y v, with v the other side's factor row (n < 2; the words
+ * mode has no ratings term); out = S^-1 rhs.  S and rhs are scratch. */
+static void joint_row(int n, int64_t row, int R, double mu, double lam, const double *Gp,
+                      const double *Gq, const double *M, int64_t ny, const uint32_t *own,
+                      const uint32_t *other, const double *yv, const double *Fo, double *S,
+                      double *rhs, double *out)
+{
+    for (int t = 0; t < R * R; ++t) S[t] = mu * Gp[t] * Gq[t];
+    for (int r = 0; r < R; ++r) {
+        S[r * R + r] += lam;
+        rhs[r] = mu * M[row * R + r];
+    }
+    if (n < 2) {  /* the ratings of this user (n = 0) or item (n = 1) */
+        for (int64_t e = 0; e < ny; ++e) {
+            if ((int64_t)own[e] != row) continue;
+            const double *v = Fo + (int64_t)other[e] * R;
+            for (int r = 0; r < R; ++r) {
+                rhs[r] += yv[e] * v[r];
+                for (int s = 0; s < R; ++s) S[r * R + s] += v[r] * v[s];
+            }
+        }
+    }
+    solve_rows(1, R, rhs, S, out);
+}
+
 double oracle_joint_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
                              const uint32_t *k, const double *val, const int64_t *dims,
                              int64_t ny, const uint32_t *yi, const uint32_t *yj,
@@ -726,25 +753,10 @@ double oracle_joint_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
         oracle_mttkrp(nnz, i, j, k, val, dims, R, A, B, C, n, M);
         gram(dims[p], R, F[p], Gp);
         gram(dims[q], R, F[q], Gq);
-        for (int64_t row = 0; row < dims[n]; ++row) {
-            for (int t = 0; t < R * R; ++t) S[t] = mu * Gp[t] * Gq[t];
-            for (int r = 0; r < R; ++r) {
-                S[r * R + r] += lam;
-                rhs[r] = mu * M[row * R + r];
-            }
-            if (n < 2) {  /* the ratings of this user (n = 0) or item (n = 1) */
-                const double *Fo = F[1 - n];
-                for (int64_t e = 0; e < ny; ++e) {
-                    if ((int64_t)own[n][e] != row) continue;
-                    const double *v = Fo + (int64_t)other[n][e] * R;
-                    for (int r = 0; r < R; ++r) {
-                        rhs[r] += yv[e] * v[r];
-                        for (int s = 0; s < R; ++s) S[r * R + s] += v[r] * v[s];
-                    }
-                }
-            }
-            solve_rows(1, R, rhs, S, F[n] + row * R);
-        }
+        for (int64_t row = 0; row < dims[n]; ++row)
+            joint_row(n, row, R, mu, lam, Gp, Gq, M, ny, n < 2 ? own[n] : NULL,
+                      n < 2 ? other[n] : NULL, yv, n < 2 ? F[1 - n] : NULL, S, rhs,
+                      F[n] + row * R);
         if (store_bf16)
             for (int64_t e = 0; e < dims[n] * R; ++e) F[n][e] = round_bf16(F[n][e]);
         free(M);
@@ -759,4 +771,36 @@ double oracle_joint_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
                                        C, g[0], g[1], g[2]);
     for (int m = 0; m < 3; ++m) free(g[m]);
     return f;
+}
+
+/* The listed rows of mode n's block (n = 0 users, 1 items) of one joint ALS
+ * iteration, from the factors as given (A, B, C: for n = 1 pass the updated
+ * A), each as in oracle_joint_als_iter: out[q] = row rows[q] (nrows x R).
+ * For checking sampled rows of a large problem: only the listed rows are
+ * solved. */
+void oracle_joint_als_rows(int64_t nnz, const uint32_t *i, const uint32_t *j, const uint32_t *k,
+                           const double *val, const int64_t *dims, int64_t ny,
+                           const uint32_t *yi, const uint32_t *yj, const double *yv, int R,
+                           double mu, double lam, const double *A, const double *B,
+                           const double *C, int n, int64_t nrows, const int64_t *rows,
+                           double *out)
+{
+    const double *F[3] = {A, B, C};
+    const int p = (n + 1) % 3, q = (n + 2) % 3;
+    double *Gp = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *Gq = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *S = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *rhs = (double *)malloc(sizeof(double) * (size_t)R);
+    double *M = (double *)malloc(sizeof(double) * (size_t)dims[n] * R);
+    oracle_mttkrp(nnz, i, j, k, val, dims, R, A, B, C, n, M);
+    gram(dims[p], R, F[p], Gp);
+    gram(dims[q], R, F[q], Gq);
+    for (int64_t t = 0; t < nrows; ++t)
+        joint_row(n, rows[t], R, mu, lam, Gp, Gq, M, ny, n == 0 ? yi : yj, n == 0 ? yj : yi, yv,
+                  F[1 - n], S, rhs, out + t * R);
+    free(M);
+    free(Gp);
+    free(Gq);
+    free(S);
+    free(rhs);
 }

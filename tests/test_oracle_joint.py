@@ -117,6 +117,23 @@ def test_joint_als_bf16_storage_blocks():
         oracle.joint_als_iter(*x, dims, *y, F, mu, lam, store="f16")
 
 
+def test_joint_als_rows_equal_the_iteration():
+    """joint_als_rows solves the listed rows exactly as joint_als_iter does:
+    users from the initial factors, items from the updated A (bitwise, same
+    arithmetic), in any order and with repeats."""
+    dims = (7, 6, 5)
+    x, y, F = _problem(7, dims, nnz=60, ny=20)
+    A, B, C, _ = oracle.joint_als_iter(*x, dims, *y, F, 0.6, 0.3)
+    users = np.array([3, 0, 6, 3])
+    np.testing.assert_array_equal(oracle.joint_als_rows(*x, dims, *y, F, 0.6, 0.3, 0, users),
+                                  A[users])
+    items = np.arange(dims[1])[::-1]
+    np.testing.assert_array_equal(
+        oracle.joint_als_rows(*x, dims, *y, [A, F[1], F[2]], 0.6, 0.3, 1, items), B[items])
+    with pytest.raises(ValueError):
+        oracle.joint_als_rows(*x, dims, *y, F, 0.6, 0.3, 2, users)
+
+
 def test_joint_als_descends():
     dims = (7, 6, 5)
     x, y, F = _problem(5, dims, nnz=60, ny=20)
