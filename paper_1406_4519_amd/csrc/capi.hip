@@ -393,10 +393,17 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfa
         }
         Small sw = small_ws(ctx, R);
         ensure_side(ctx);
-        // the three MTTKRPs run back to back on the main stream; the Grams
-        // and each mode's gradient rows (which need only that mode's MTTKRP)
-        // run on the side stream beside the next MTTKRP; joined at the end
+        // the three MTTKRPs' main kernels run back to back on the main
+        // stream, each with carries of its own; the Grams, each mode's carry
+        // fix-ups and its gradient rows (which need only that mode's
+        // MTTKRP) run on the side stream beside the next MTTKRP; joined at
+        // the end
         const hipStream_t main = ctx->stream;
+        int64_t cmax = 1;
+        for (int m = 0; m < 3; ++m) cmax = std::max<int64_t>(cmax, t->mode[m].nchunk);
+        const size_t cstride = (size_t)cmax * R;
+        float *carry =
+            (float *)ws_get(ctx, dfacto_ctx::kCarry, sizeof(float) * 3 * cstride);
         DF_HIP(hipEventRecord(ctx->ev_fork, main));
         DF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
         {
@@ -407,9 +414,8 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfa
         }
         for (int n = 0; n < 3; ++n) {
             const ModeData &md = t->mode[n];
-            launch_mttkrp(ctx, t, n, R, dtype, d_F[md.leaf], d_F[md.mid], d_G[n]);
-            DF_HIP(hipEventRecord(ctx->ev_step, main));
-            DF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_step, 0));
+            launch_mttkrp_split(ctx, t, n, R, dtype, d_F[md.leaf], d_F[md.mid], d_G[n],
+                                carry + n * cstride, ctx->side, ctx->ev_step);
             OnStream on(ctx, ctx->side);
             launch_gd_rows(ctx, d_G[n], d_F[n], dtype, t->dims[n], R, sw.H[n],
                            n == 0 ? sw.part0 : sw.part_dummy);

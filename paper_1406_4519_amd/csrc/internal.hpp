@@ -231,6 +231,12 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
 // MTTKRP (mttkrp.hip)
 void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype,
                    const void *Fleaf, const void *Fmid, float *out);
+// The same with the carries in `carry` (nchunk x R floats of the caller's)
+// and the carry fix-ups on stream `fix`, after `ev` recorded on ctx's stream
+// behind the main kernel: `out` is complete in stream order on `fix`.
+void launch_mttkrp_split(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                         dfacto_dtype dtype, const void *Fleaf, const void *Fmid, float *out,
+                         float *carry, hipStream_t fix, hipEvent_t ev);
 // residual MTTKRP over the stored entries (value x - sum_r root*mid*leaf)
 void launch_mttkrp_resid(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
                          dfacto_dtype dtype, const void *Fleaf, const void *Fmid,

@@ -588,12 +588,18 @@ void with_shape(dfacto_dtype dtype, const MttkrpShape &sh, F &&f) {
 }
 
 template <typename T, int CPL, int G, int NCH>
+// fix/ev: when set, the carry fix-ups go to stream `fix`, ordered after the
+// main kernel by `ev` recorded on ctx's stream; carry_in: the carries' buffer
+// (else the context's carry workspace)
 void run(dfacto_ctx *ctx, const ModeData &md, int R, const void *Fleaf, const void *Fmid,
-         float *out, bool small, const void *Froot = nullptr) {
+         float *out, bool small, const void *Froot = nullptr, float *carry_in = nullptr,
+         hipStream_t fix = nullptr, hipEvent_t ev = nullptr) {
     hipStream_t s = ctx->stream;
     const uint32_t nchunk = (uint32_t)md.nchunk;
-    float *carry = (float *)ws_get(ctx, dfacto_ctx::kCarry,
-                                   sizeof(float) * (size_t)std::max<int64_t>(md.nchunk, 1) * R);
+    float *carry = carry_in ? carry_in
+                            : (float *)ws_get(ctx, dfacto_ctx::kCarry,
+                                              sizeof(float) *
+                                                  (size_t)std::max<int64_t>(md.nchunk, 1) * R);
     constexpr int gpb = kBlock / G;  // groups per block
     if (nchunk > 0) {
         const unsigned blocks = (nchunk + gpb - 1) / gpb;
@@ -620,6 +626,11 @@ void run(dfacto_ctx *ctx, const ModeData &md, int R, const void *Fleaf, const vo
                                    (const T *)Fmid, R, out, carry);
             prof_mark(ctx);
         }
+    }
+    if (fix) {
+        DF_HIP(hipEventRecord(ev, s));
+        DF_HIP(hipStreamWaitEvent(fix, ev, 0));
+        s = fix;
     }
     const uint32_t nempty = (uint32_t)md.nempty;
     const uint32_t egroups = nempty == 0 ? 0u : std::min<uint32_t>(nempty, 65536u);
@@ -686,6 +697,26 @@ void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfa
         using T = typename decltype(tc)::type;
         run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(
             ctx, md, R, Fleaf, Fmid, out, sm);
+    });
+}
+
+void launch_mttkrp_split(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                         dfacto_dtype dtype, const void *Fleaf, const void *Fmid, float *out,
+                         float *carry, hipStream_t fix, hipEvent_t ev) {
+    const ModeData &md = t->mode[mode];
+    if (ctx->profiling && md.nchunk > 0) {
+        const double sf = dtype == DFACTO_BF16 ? 2.0 : 4.0;
+        ctx->prof_bytes += 8.0 * (double)t->nnz + 8.0 * (double)md.nfib + 8.0 * (double)md.nroot +
+                           4.0 * (double)t->dims[md.root] * R +
+                           sf * (double)(t->dims[md.leaf] + t->dims[md.mid]) * R;
+        ctx->prof_flops += 2.0 * R * (double)(t->nnz + md.nfib);
+    }
+    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out);
+    const bool sm = mttkrp_small(t, mode);
+    with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
+        using T = typename decltype(tc)::type;
+        run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(
+            ctx, md, R, Fleaf, Fmid, out, sm, nullptr, carry, fix, ev);
     });
 }
 
