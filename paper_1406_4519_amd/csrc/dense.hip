@@ -162,30 +162,32 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const T *__restrict__ F
 typedef double double4v __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxTiles = 4;
 
-// NT consecutive entries F[row][c0 .. c0 + NT) widened to double, zero past
-// the last row or column.  VEC: R == 16 NT and the rows are aligned for one
-// NT-element vector load.
+// NT consecutive entries F[row][c0 .. c0 + NT) as FP32 bit patterns (a BF16
+// value is its FP32 pattern with the low half zero), zero past the last row
+// or column.  VEC: R == 16 NT and the rows are aligned for one NT-element
+// vector load.
 template <typename T, int NT, bool VEC>
 __device__ __forceinline__ void gram_load(const T *__restrict__ F, int64_t row, int64_t rows, int R,
-                                          int c0, double (&v)[NT]) {
+                                          int c0, uint32_t (&v)[NT]) {
     if (VEC && NT == 2) {
         if (row < rows) {
             if constexpr (sizeof(T) == 4) {
-                const float2 a = *reinterpret_cast<const float2 *>(F + row * R + c0);
+                const uint2 a = *reinterpret_cast<const uint2 *>(F + row * R + c0);
                 v[0] = a.x;
                 v[1] = a.y;
             } else {
                 const uint32_t a = *reinterpret_cast<const uint32_t *>(F + row * R + c0);
-                v[0] = __uint_as_float(a << 16);
-                v[1] = __uint_as_float(a & 0xFFFF0000u);
+                v[0] = a << 16;
+                v[1] = a & 0xFFFF0000u;
             }
         } else {
-            v[0] = v[1] = 0.0;
+            v[0] = v[1] = 0u;
         }
         return;
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t) v[t] = (row < rows && c0 + t < R) ? ld<T>(F, row * R + c0 + t) : 0.0;
+    for (int t = 0; t < NT; ++t)
+        v[t] = (row < rows && c0 + t < R) ? __float_as_uint((float)ld<T>(F, row * R + c0 + t)) : 0u;
 }
 
 // Block b of nb: the launch's own block, or a grouped launch's virtual one.
@@ -195,6 +197,11 @@ __device__ __forceinline__ void gram_mfma_body(const T *__restrict__ F, int64_t 
                                                uint32_t nb) {
     constexpr int NP = NT * (NT + 1) / 2;  // tile pairs rt <= ct
     constexpr int NW = BS / 64;            // waves per block
+    // steps loaded per batch: the next batch's loads are in flight while the
+    // current one's MFMAs run (a wave takes only a few dozen steps, so one
+    // step ahead leaves the loop waiting on memory); one step for R > 32,
+    // where a second would cost occupancy
+    constexpr int PD = NT <= 2 ? 2 : 1;
     __shared__ double sacc[NP * 256];
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int kr = lane / 16, cl = lane % 16;
@@ -203,36 +210,46 @@ __device__ __forceinline__ void gram_mfma_body(const T *__restrict__ F, int64_t 
     for (int q = 0; q < NP; ++q) acc[q] = double4v{0.0, 0.0, 0.0, 0.0};
     const int64_t nwaves = (int64_t)nb * NW;
     const int64_t gw = (int64_t)b * NW + wave;
-    // rows [16 * step, 16 * step + 16) for step = gw, gw + nwaves, ...; rows
-    // past the end read as zero.  The next step is loaded before the current
-    // one's MFMAs.
+    // rows [16 * step, 16 * step + 16) for step = gw, gw + nwaves, ... in
+    // that order; rows past the end read as zero.
     const int64_t nsteps = (rows + 15) / 16;
     // Column tile t, MFMA index c is column c * NT + t, so a lane reads the
     // NT consecutive columns cl * NT .. + NT of a row.
-    auto load = [&](int64_t step, double (&v)[4][NT]) {
+    auto load = [&](int64_t s0, uint32_t (&v)[PD][4][NT]) {
 #pragma unroll
-        for (int sub = 0; sub < 4; ++sub)
-            gram_load<T, NT, VEC>(F, step * 16 + sub * 4 + kr, rows, R, cl * NT, v[sub]);
+        for (int p = 0; p < PD; ++p)
+#pragma unroll
+            for (int sub = 0; sub < 4; ++sub)
+                gram_load<T, NT, VEC>(F, (s0 + p * nwaves) * 16 + sub * 4 + kr, rows, R, cl * NT,
+                                      v[p][sub]);
     };
-    double v[4][NT];
+    uint32_t v[PD][4][NT];
     if (gw < nsteps) load(gw, v);
-    for (int64_t step = gw; step < nsteps; step += nwaves) {
-        double vn[4][NT];
-        load(step + nwaves, vn);
+    for (int64_t s0 = gw; s0 < nsteps; s0 += PD * nwaves) {
+        uint32_t vn[PD][4][NT];
+        load(s0 + PD * nwaves, vn);
 #pragma unroll
-        for (int sub = 0; sub < 4; ++sub) {
-            int q = 0;
+        for (int p = 0; p < PD; ++p) {
+            if (s0 + p * nwaves >= nsteps) continue;  // uniform across the wave
 #pragma unroll
-            for (int rt = 0; rt < NT; ++rt)
+            for (int sub = 0; sub < 4; ++sub) {
+                double x[NT];
 #pragma unroll
-                for (int ct = rt; ct < NT; ++ct, ++q)
-                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[sub][rt], v[sub][ct], acc[q],
-                                                                  0, 0, 0);
+                for (int t = 0; t < NT; ++t) x[t] = (double)__uint_as_float(v[p][sub][t]);
+                int q = 0;
+#pragma unroll
+                for (int rt = 0; rt < NT; ++rt)
+#pragma unroll
+                    for (int ct = rt; ct < NT; ++ct, ++q)
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[rt], x[ct], acc[q], 0, 0, 0);
+            }
         }
 #pragma unroll
-        for (int sub = 0; sub < 4; ++sub)
+        for (int p = 0; p < PD; ++p)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) v[sub][t] = vn[sub][t];
+            for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) v[p][sub][t] = vn[p][sub][t];
     }
     // combine the waves of the block in wave order
     for (int w = 0; w < NW; ++w) {
@@ -276,6 +293,7 @@ __global__ __launch_bounds__(BS) void k_gram_mfma_group(const GramJob *__restric
 
 // G[e] = sum_b part[b][e]: a block takes 16 entries; slice q (16 per entry)
 // sums the partials b = q, q + 16, ...; the slices are combined in order.
+// The first 16 partials of a slice are loaded together, then added in order.
 __device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part, int nblk, int R,
                                                  double *__restrict__ G, uint32_t b) {
     __shared__ double sh[16][17];
@@ -283,8 +301,18 @@ __device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part
     const int sl = threadIdx.x / 16;
     const int RR = R * R;
     double s = 0.0;
-    if (e < RR)
-        for (int b = sl; b < nblk; b += 16) s += part[(size_t)b * RR + e];
+    if (e < RR) {
+        double x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int pb = sl + 16 * u;
+            x[u] = pb < nblk ? part[(size_t)pb * RR + e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (sl + 16 * u < nblk) s += x[u];
+        for (int pb = sl + 256; pb < nblk; pb += 16) s += part[(size_t)pb * RR + e];
+    }
     sh[sl][threadIdx.x % 16] = s;
     __syncthreads();
     if (threadIdx.x < 16 && e < RR) {
