@@ -406,11 +406,11 @@ __device__ __forceinline__ void zero_row(float *__restrict__ out, int R, uint32_
 // Short runs: one lane group per run adds its <= kShortRun carries in chunk
 // order; the groups after the runs zero-fill the empty output rows.
 template <int CPL, int G, int NCH>
-__global__ __launch_bounds__(kBlock) void k_fix_short(
-    const uint32_t *__restrict__ runs, uint32_t nruns, const float *__restrict__ carry, int R,
-    float *__restrict__ out, const uint32_t *__restrict__ empty_rows, uint32_t nempty,
-    uint32_t nempty_groups) {
-    const uint32_t gid = (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G;
+__device__ __forceinline__ void short_runs(uint32_t gid, const uint32_t *__restrict__ runs,
+                                           uint32_t nruns, const float *__restrict__ carry, int R,
+                                           float *__restrict__ out,
+                                           const uint32_t *__restrict__ empty_rows,
+                                           uint32_t nempty, uint32_t nempty_groups) {
     const int lane = threadIdx.x % G;
     int col[NCH];
     bool act[NCH];
@@ -497,12 +497,22 @@ __device__ __forceinline__ void long_run(const float *__restrict__ carry, int R,
     }
 }
 
+// Every fix-up of one MTTKRP in one launch (short runs, long runs and empty
+// rows own disjoint output rows): blocks [0, nlong) take a long run each, the
+// blocks after them the short runs and then the empty rows, one lane group
+// each.
 template <int CPL, int G, int NCH>
-__global__ __launch_bounds__(kLongBlock) void k_fix_long(const uint32_t *__restrict__ runs,
-                                                         const float *__restrict__ carry, int R,
-                                                         float *__restrict__ out) {
-    long_run<CPL, G, NCH>(carry, R, out, runs[3 * blockIdx.x], runs[3 * blockIdx.x + 1],
-                          runs[3 * blockIdx.x + 2]);
+__global__ __launch_bounds__(kLongBlock) void k_fix(
+    const uint32_t *__restrict__ runs_long, uint32_t nlong, const uint32_t *__restrict__ runs,
+    uint32_t nruns, const float *__restrict__ carry, int R, float *__restrict__ out,
+    const uint32_t *__restrict__ empty_rows, uint32_t nempty, uint32_t nempty_groups) {
+    if (blockIdx.x < nlong) {
+        long_run<CPL, G, NCH>(carry, R, out, runs_long[3 * blockIdx.x],
+                              runs_long[3 * blockIdx.x + 1], runs_long[3 * blockIdx.x + 2]);
+        return;
+    }
+    short_runs<CPL, G, NCH>(((blockIdx.x - nlong) * (uint32_t)kLongBlock + threadIdx.x) / G, runs,
+                            nruns, carry, R, out, empty_rows, nempty, nempty_groups);
 }
 
 // Grouped fix-ups: runs as (tensor, row, c0, n), empty rows as (tensor, row).
@@ -635,16 +645,13 @@ void run(dfacto_ctx *ctx, const ModeData &md, int R, const void *Fleaf, const vo
     const uint32_t nempty = (uint32_t)md.nempty;
     const uint32_t egroups = nempty == 0 ? 0u : std::min<uint32_t>(nempty, 65536u);
     const uint64_t groups = (uint64_t)md.nruns_short + egroups;
-    if (groups > 0) {
-        const unsigned blocks = (unsigned)((groups + gpb - 1) / gpb);
-        hipLaunchKernelGGL((k_fix_short<CPL, G, NCH>), dim3(blocks), dim3(kBlock), 0, s,
-                           md.runs_short, (uint32_t)md.nruns_short, carry, R, out, md.empty_rows,
-                           nempty, egroups);
-    }
-    if (md.nruns_long > 0) {
-        hipLaunchKernelGGL((k_fix_long<CPL, G, NCH>), dim3((unsigned)md.nruns_long),
-                           dim3(kLongBlock), 0, s, md.runs_long, carry, R, out);
-    }
+    constexpr int gpl = kLongBlock / G;  // lane groups per fix-up block
+    const uint64_t blocks = (uint64_t)md.nruns_long + (groups + gpl - 1) / gpl;
+    if (blocks > 0)
+        hipLaunchKernelGGL((k_fix<CPL, G, NCH>), dim3((unsigned)blocks), dim3(kLongBlock), 0, s,
+                           md.runs_long, (uint32_t)md.nruns_long, md.runs_short,
+                           (uint32_t)md.nruns_short, carry, R, out, md.empty_rows, nempty,
+                           egroups);
     DF_LAUNCHED();
 }
 
