@@ -349,8 +349,15 @@ dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, df
         Small sw = small_ws(ctx, R);
         float *M = (float *)ws_get(ctx, dfacto_ctx::kM, sizeof(float) * (size_t)max_dim(t) * R);
         ensure_side(ctx);
-        launch_gram(ctx, d_F[1], dtype, t->dims[1], R, sw.G[1]);
-        launch_gram(ctx, d_F[2], dtype, t->dims[2], R, sw.G[2]);
+        // the first solve needs the Grams of F[1] and F[2]: formed on the
+        // side stream ahead of it, beside the first MTTKRP
+        DF_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
+        DF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+        {
+            OnStream on(ctx, ctx->side);
+            launch_gram(ctx, d_F[1], dtype, t->dims[1], R, sw.G[1]);
+            launch_gram(ctx, d_F[2], dtype, t->dims[2], R, sw.G[2]);
+        }
         for (int n = 0; n < 3; ++n) {
             const int p = (n + 1) % 3, q = (n + 2) % 3;
             const ModeData &md = t->mode[n];

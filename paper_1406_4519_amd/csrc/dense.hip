@@ -1640,6 +1640,12 @@ GramPlan gram_plan(int64_t rows, int R, const void *F, dfacto_dtype dtype) {
     return g;
 }
 
+// the partial-sum buffer of the stream the Gram is launched on
+static dfacto_ctx::Slot gram_slot(const dfacto_ctx *ctx) {
+    return (ctx->side && ctx->stream == ctx->side) ? dfacto_ctx::kPartialSide
+                                                   : dfacto_ctx::kPartial;
+}
+
 void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t rows, int R,
                  double *G) {
     hipStream_t s = ctx->stream;
@@ -1647,8 +1653,8 @@ void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t row
         const GramPlan gp = gram_plan(rows, R, F, dtype);
         const int nt = gp.nt, nblk = gp.nblk;
         const bool vec2 = gp.vec;
-        double *part =
-            (double *)ws_get(ctx, dfacto_ctx::kPartial, sizeof(double) * 256 * (size_t)R * R);
+        double *part = (double *)ws_get(ctx, gram_slot(ctx),
+                                        sizeof(double) * 256 * (size_t)R * R);
 #define GM(T, NTV, V)                                                                              \
     hipLaunchKernelGGL((k_gram_mfma<T, NTV, (NTV <= 2 ? 1024 : 256), V>), dim3(nblk),              \
                        dim3(NTV <= 2 ? 1024 : 256), 0, s, (const T *)F, rows, R, part)
@@ -1675,7 +1681,7 @@ void launch_gram(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, int64_t row
     const int nt = (R + TS - 1) / TS;
     const int nblk = gram_partial_blocks(rows, R);
     // sized for the largest block count so that the buffer never moves between calls
-    double *part = (double *)ws_get(ctx, dfacto_ctx::kPartial, sizeof(double) * 256 * (size_t)R * R);
+    double *part = (double *)ws_get(ctx, gram_slot(ctx), sizeof(double) * 256 * (size_t)R * R);
     dim3 grid(nblk, nt * nt);
     const int vec = vec_rows(F, R, dtype == DFACTO_F32 ? 4 : 2);
 #define GRAM_LAUNCH(T, TSV)                                                                   \

@@ -176,10 +176,11 @@ struct dfacto_ctx {
     int num_cu = 0;
     bool sticky = false;
     std::string err;
-    // growable device workspace, one slot per purpose
-    enum Slot { kM = 0, kCarry, kPartial, kSmall, kTrial, kJoint, kNumSlots };
-    void *ws[kNumSlots] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    size_t ws_size[kNumSlots] = {0, 0, 0, 0, 0, 0};
+    // growable device workspace, one slot per purpose (Gram partial sums: one
+    // slot per stream, so that Grams on the two streams may overlap)
+    enum Slot { kM = 0, kCarry, kPartial, kPartialSide, kSmall, kTrial, kJoint, kNumSlots };
+    void *ws[kNumSlots] = {};
+    size_t ws_size[kNumSlots] = {};
     // kernel timing (dfacto_profile_*)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;  // created on demand, reused
