@@ -349,38 +349,44 @@ dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, df
         Small sw = small_ws(ctx, R);
         float *M = (float *)ws_get(ctx, dfacto_ctx::kM, sizeof(float) * (size_t)max_dim(t) * R);
         ensure_side(ctx);
-        // the first solve needs the Grams of F[1] and F[2]: formed on the
-        // side stream ahead of it, beside the first MTTKRP
-        DF_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
-        DF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-        {
-            OnStream on(ctx, ctx->side);
-            launch_gram(ctx, d_F[1], dtype, t->dims[1], R, sw.G[1]);
-            launch_gram(ctx, d_F[2], dtype, t->dims[2], R, sw.G[2]);
-        }
-        for (int n = 0; n < 3; ++n) {
-            const int p = (n + 1) % 3, q = (n + 2) % 3;
-            const ModeData &md = t->mode[n];
-            // the R x R solve needs only the other modes' Grams: it runs on
-            // the side stream beside this mode's MTTKRP, joined before use
+        // Mode n's R x R solve needs only the other modes' Grams, so it runs
+        // on the side stream as soon as they are final, beside the main
+        // stream's work, and is joined before mode n's lambda step.  Mode 0's
+        // solve follows the Grams of F[1] and F[2], also formed there.
+        auto fork_solve = [&](int n) {
             DF_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
             DF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
             {
                 OnStream on(ctx, ctx->side);
-                launch_solve(ctx, R, sw.G[p], sw.G[q], reg, sw.Hinv, sw.solve_scratch, sw.flag + n);
+                if (n == 0) {
+                    launch_gram(ctx, d_F[1], dtype, t->dims[1], R, sw.G[1]);
+                    launch_gram(ctx, d_F[2], dtype, t->dims[2], R, sw.G[2]);
+                }
+                launch_solve(ctx, R, sw.G[(n + 1) % 3], sw.G[(n + 2) % 3], reg, sw.Hinv,
+                             sw.solve_scratch, sw.flag + n);
             }
             DF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+        };
+        fork_solve(0);
+        for (int n = 0; n < 3; ++n) {
+            const ModeData &md = t->mode[n];
             launch_mttkrp(ctx, t, n, R, dtype, d_F[md.leaf], d_F[md.mid], M);
             launch_gram(ctx, M, DFACTO_F32, t->dims[n], R, sw.MtM);
             DF_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
+            // writes G[n] (the new factor's Gram) and W; reads H^-1
             launch_als_lambda(ctx, R, n, sw.Hinv, sw.MtM, sw.G[n], sw.W, d_lambda, sw.G[0],
                               sw.G[1], t->normsq, d_fit, sw.lam_scratch);
+            // the next solve overwrites H^-1 only after the lambda step (it
+            // is forked after it); the row map reads W, not H^-1
+            if (dtype == DFACTO_F32 && n < 2) fork_solve(n + 1);
             launch_rowmap(ctx, M, t->dims[n], R, sw.W, d_F[n], dtype);
             // A BF16-stored factor differs from the FP64 one by its rounding;
             // the next modes' normal equations must use the Gram of what the
             // next MTTKRPs read, so form it from the stored factor.
-            if (dtype == DFACTO_BF16 && n < 2)
+            if (dtype == DFACTO_BF16 && n < 2) {
                 launch_gram(ctx, d_F[n], dtype, t->dims[n], R, sw.G[n]);
+                fork_solve(n + 1);
+            }
         }
     });
 }
