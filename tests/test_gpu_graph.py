@@ -1,0 +1,85 @@
+"""CP-ALS and the GD gradient captured in a HIP graph: the calls fork part of
+their work onto the context's second stream and join it back by events, and
+enqueue no memset or copy, so a captured step replays exactly.  One step
+(three ALS iterations, then the GD gradient at the result) is captured on a
+torch stream the context is bound to, then replayed three times with eager
+work and synchronizations between the replays; every replay must equal, bit
+for bit, the same step run eagerly from the same state."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import build, say, DEV
+from paper_1406_4519_amd import dfacto, gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits(x):
+    return x.view(torch.int16) if x.dtype == torch.bfloat16 else x
+
+
+@pytest.mark.parametrize("R,dtype", [(32, "f32"), (16, "bf16")])
+def test_captured_step_replays_bitwise(R, dtype):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    coo = gen.zipf_distinct((20_000, 15_000, 10_000), 300_000, 1.1, seed=81)
+    F0 = gen.init_factors(coo.dims, R, seed=82)
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    ctx = dfacto.Context(0)
+    T = build(ctx, coo)
+    F = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(DEV).to(tdt) for f in F0]
+    G = [torch.empty((d, R), dtype=torch.float32, device=DEV) for d in coo.dims]
+    lam = torch.zeros(R, dtype=torch.float64, device=DEV)
+    fit = torch.zeros(1, dtype=torch.float64, device=DEV)
+    fv = torch.zeros(1, dtype=torch.float64, device=DEV)
+    state = (*F, lam, fit)
+    outs = (*F, lam, fit, *G, fv)
+
+    def step():
+        for _ in range(3):
+            dfacto.als_iter(ctx, T, F, lam, fit)
+        dfacto.gd_grad(ctx, T, F, G, fv, 0.05)
+
+    start = [x.clone() for x in state]
+    # eager reference: three steps from the start (this also sizes every
+    # workspace, so nothing allocates during the capture)
+    eager = []
+    for _ in range(3):
+        step()
+        torch.cuda.synchronize()
+        eager.append([x.clone() for x in outs])
+    for x, y in zip(state, start):
+        x.copy_(y)
+    torch.cuda.synchronize()
+
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    main = torch.cuda.current_stream()
+    try:
+        with torch.cuda.graph(g, stream=side):
+            ctx.set_stream(side)
+            step()
+    finally:
+        ctx.set_stream(main)
+    torch.cuda.synchronize()
+    # the capture ran nothing: restore the start state before the replays
+    for x, y in zip(state, start):
+        x.copy_(y)
+    torch.cuda.synchronize()
+    scratch = torch.empty((coo.dims[0], R), device=DEV)
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        got = [x.clone() for x in outs]
+        same = [torch.equal(_bits(a), _bits(b)) for a, b in zip(got, eager[k])]
+        say(f"  R={R} {dtype}: replay {k + 1} equal to eager step {k + 1}: {all(same)} "
+            f"(fit {float(fit):.6f})")
+        assert all(same), [i for i, s in enumerate(same) if not s]
+        # eager library work between the replays (it must not disturb them)
+        dfacto.mttkrp(ctx, T, 0, F, scratch)
+        torch.cuda.synchronize()
+    del g
+    T.close()
+    ctx.close()
