@@ -647,32 +647,43 @@ dfacto_status dfacto_joint_als_iter(dfacto_ctx *ctx, const dfacto_tensor *X,
         void *one = ones_row(ctx, R, dtype, w);
         double *part = (double *)(w + 256);
         DF_HIP(hipMemsetAsync(sw.flag, 0, 4 * sizeof(int), ctx->stream));
-        launch_gram(ctx, d_F[1], dtype, X->dims[1], R, sw.G[1]);
-        launch_gram(ctx, d_F[2], dtype, X->dims[2], R, sw.G[2]);
+        ensure_side(ctx);
         for (int n = 0; n < 3; ++n) {
             const int p = (n + 1) % 3, q = (n + 2) % 3;
             const ModeData &md = X->mode[n];
-            if (mu > 0.0) launch_mttkrp(ctx, X, n, R, dtype, d_F[md.leaf], d_F[md.mid], M);
-            if (n < 2) {
-                // users (n = 0): entries (1, item); items (n = 1): entries (user, 1)
-                launch_hadamard(ctx, R, sw.G[p], sw.G[q], 0.0, sw.H[n]);
-                // P^-1 for the short rows: (mu H + lam I)^-1 = (H + (lam / mu) I)^-1 / mu,
-                // or I / lam without the tensor term
-                const double *Pinv = nullptr;
-                double ws = 1.0 / lam;
-                if (mu > 0.0) {
-                    launch_solve(ctx, R, sw.G[p], sw.G[q], lam / mu, sw.Hinv, sw.solve_scratch,
-                                 sw.flag + 2);
-                    Pinv = sw.Hinv;
-                    ws = 1.0 / mu;
+            // Mode n's R x R work needs only the other modes' Grams, final
+            // here (and the previous mode's row pass, the last reader of
+            // H^-1, is done): it runs on the side stream beside this mode's
+            // MTTKRP and is joined before the rows.  Mode 0 first forms the
+            // Grams of F[1] and F[2] there.
+            DF_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
+            DF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+            {
+                OnStream on(ctx, ctx->side);
+                if (n == 0) {
+                    launch_gram(ctx, d_F[1], dtype, X->dims[1], R, sw.G[1]);
+                    launch_gram(ctx, d_F[2], dtype, X->dims[2], R, sw.G[2]);
                 }
+                // users (n = 0), items (n = 1): H for the row systems, and
+                // P^-1 for the short rows: (mu H + lam I)^-1 = (H + (lam / mu) I)^-1 / mu;
+                // words: C = mu M (mu H + lam I)^-1 = M (H + (lam / mu) I)^-1
+                if (n < 2) launch_hadamard(ctx, R, sw.G[p], sw.G[q], 0.0, sw.H[n]);
+                if (mu > 0.0)
+                    launch_solve(ctx, R, sw.G[p], sw.G[q], lam / mu, sw.Hinv, sw.solve_scratch,
+                                 sw.flag + (n < 2 ? 2 : 1));
+            }
+            DF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+            if (mu > 0.0) launch_mttkrp(ctx, X, n, R, dtype, d_F[md.leaf], d_F[md.mid], M);
+            DF_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
+            if (n < 2) {
+                // users (n = 0): entries (1, item); items (n = 1): entries (user, 1);
+                // without the tensor term P^-1 = I / lam
+                const double *Pinv = mu > 0.0 ? sw.Hinv : nullptr;
+                const double ws = mu > 0.0 ? 1.0 / mu : 1.0 / lam;
                 launch_joint_rows(ctx, Y, n, X->dims[n], n == 0 ? one : d_F[0],
                                   n == 0 ? d_F[1] : one, R, mu > 0.0 ? M : nullptr, sw.H[n], mu,
                                   lam, Pinv, ws, sw.flag + 2, d_F[n], dtype, sw.flag, part);
             } else if (mu > 0.0) {
-                // words: C = mu M (mu H + lam I)^-1 = M (H + (lam / mu) I)^-1
-                launch_solve(ctx, R, sw.G[p], sw.G[q], lam / mu, sw.Hinv, sw.solve_scratch,
-                             sw.flag + 1);
                 launch_rowmap(ctx, M, X->dims[2], R, sw.Hinv, d_F[2], dtype);
             } else {
                 DF_HIP(hipMemsetAsync(d_F[2], 0, (size_t)X->dims[2] * R * elem_size(dtype),
