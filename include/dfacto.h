@@ -19,10 +19,11 @@
  *    dfacto_dtype (FP32, or BF16 stored as raw 16-bit patterns).  Row
  *    starts must be aligned to the element size.
  *  - Work is enqueued on the stream bound to the context and is
- *    stream-ordered.  Some calls (ALS, GD gradient) run part of their work
- *    on a second stream of the context, forked from the bound stream and
- *    joined back to it by events within the call, so the order seen from
- *    the bound stream is unchanged.  Calls that synchronize: the builds
+ *    stream-ordered.  Some calls (CP-ALS, GD gradient, joint ALS) run part
+ *    of their work on a second stream of the context, forked from the bound
+ *    stream and joined back to it by events within the call, so the order
+ *    seen from the bound stream is unchanged.  Calls that synchronize: the
+ *    builds
  *    (dfacto_build_flattenings, dfacto_build_ratings), dfacto_tensor_export,
  *    the calls that return host results (dfacto_gd_step,
  *    dfacto_joint_als_iter, dfacto_profile_read, dfacto_ctx_synchronize),
