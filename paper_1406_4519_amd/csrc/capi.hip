@@ -349,12 +349,15 @@ dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, df
         Small sw = small_ws(ctx, R);
         float *M = (float *)ws_get(ctx, dfacto_ctx::kM, sizeof(float) * (size_t)max_dim(t) * R);
         ensure_side(ctx);
-        // Mode n's R x R solve needs only the other modes' Grams, so it runs
-        // on the side stream as soon as they are final, beside the main
-        // stream's work, and is joined before mode n's lambda step.  Mode 0's
-        // solve follows the Grams of F[1] and F[2], also formed there.
-        auto fork_solve = [&](int n) {
+        // Mode n's R x R solve needs only the other modes' Grams, final once
+        // mode n - 1's factor and Gram are: it runs on the side stream beside
+        // mode n's MTTKRP and is joined before mode n's lambda step.  Mode 0's
+        // solve follows the Grams of F[1] and F[2], also formed there.  The
+        // MTTKRP is enqueued before the side stream's part.
+        for (int n = 0; n < 3; ++n) {
+            const ModeData &md = t->mode[n];
             DF_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
+            launch_mttkrp(ctx, t, n, R, dtype, d_F[md.leaf], d_F[md.mid], M);
             DF_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
             {
                 OnStream on(ctx, ctx->side);
@@ -366,27 +369,17 @@ dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, df
                              sw.solve_scratch, sw.flag + n);
             }
             DF_HIP(hipEventRecord(ctx->ev_join, ctx->side));
-        };
-        fork_solve(0);
-        for (int n = 0; n < 3; ++n) {
-            const ModeData &md = t->mode[n];
-            launch_mttkrp(ctx, t, n, R, dtype, d_F[md.leaf], d_F[md.mid], M);
             launch_gram(ctx, M, DFACTO_F32, t->dims[n], R, sw.MtM);
             DF_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
             // writes G[n] (the new factor's Gram) and W; reads H^-1
             launch_als_lambda(ctx, R, n, sw.Hinv, sw.MtM, sw.G[n], sw.W, d_lambda, sw.G[0],
                               sw.G[1], t->normsq, d_fit, sw.lam_scratch);
-            // the next solve overwrites H^-1 only after the lambda step (it
-            // is forked after it); the row map reads W, not H^-1
-            if (dtype == DFACTO_F32 && n < 2) fork_solve(n + 1);
             launch_rowmap(ctx, M, t->dims[n], R, sw.W, d_F[n], dtype);
             // A BF16-stored factor differs from the FP64 one by its rounding;
             // the next modes' normal equations must use the Gram of what the
             // next MTTKRPs read, so form it from the stored factor.
-            if (dtype == DFACTO_BF16 && n < 2) {
+            if (dtype == DFACTO_BF16 && n < 2)
                 launch_gram(ctx, d_F[n], dtype, t->dims[n], R, sw.G[n]);
-                fork_solve(n + 1);
-            }
         }
     });
 }
