@@ -29,7 +29,8 @@ def build(force: bool = False) -> str:
     """Compile oracle.c with the host C compiler (no fast-math: IEEE FP64)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-pthread", "-o", tmp,
+                               _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -41,6 +42,8 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
+        lib.oracle_config.argtypes = [ctypes.c_int, ctypes.c_int]
+        lib.oracle_config.restype = None
         lib.oracle_mttkrp.argtypes = [i64, P, P, P, P, P, ctypes.c_int, P, P, P, ctypes.c_int, P]
         lib.oracle_mttkrp.restype = None
         lib.oracle_flatten.argtypes = [i64, P, P, P, P, ctypes.c_int, P, P, P, P, P, P, P, P]
@@ -77,6 +80,26 @@ def _load():
         lib.oracle_joint_als_rows.restype = None
         _lib = lib
     return _lib
+
+
+def config(threads: int = 1, assume_distinct: bool = False):
+    """Worker threads of the oracle's loops (results are bitwise the same for
+    any count) and whether the caller guarantees distinct coordinates (then
+    ||X||^2 sums the values in input order instead of sorting them)."""
+    _load().oracle_config(int(threads), int(bool(assume_distinct)))
+
+
+def host_threads() -> int:
+    """Host cores this process may run on (sched_getaffinity)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def host_threads_capped(cap: int = 16) -> int:
+    """host_threads(), at most `cap` (a one-GPU share of a large host)."""
+    return max(1, min(host_threads(), int(cap)))
 
 
 def _u32(a):

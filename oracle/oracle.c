@@ -34,27 +34,110 @@
  *
  * Duplicate coordinates are summed (the paper does not say; linear algebra
  * on a sparse tensor with repeated coordinates sums them).
+ *
+ * Threads (oracle_config): the same loops can be spread over host threads
+ * for full-size checks and the all-cores CPU baseline.  Only independent
+ * work is split -- disjoint output rows of an MTTKRP (each row still adds
+ * its nonzeros in input order), disjoint Gram entries, rows of a solve,
+ * columns of a norm -- and every sum keeps its serial order, so results are
+ * bitwise the same for any thread count.
  */
+#define _POSIX_C_SOURCE 200809L
 #include <float.h>
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 /* ------------------------------------------------------------------ */
+/* optional threads                                                    */
+/* ------------------------------------------------------------------ */
+
+#define MAX_THREADS 256
+static int g_threads = 1;  /* worker threads of the loops below */
+static int g_distinct = 0; /* caller guarantees distinct coordinates */
+
+/* threads: worker threads (1 = serial).  assume_distinct != 0: the caller
+ * guarantees that no coordinate repeats, so merging duplicates is the
+ * identity and ||X||^2 is the sum of squared values in input order (no
+ * sort of the nonzeros). */
+void oracle_config(int threads, int assume_distinct)
+{
+    g_threads = threads < 1 ? 1 : (threads > MAX_THREADS ? MAX_THREADS : threads);
+    g_distinct = assume_distinct != 0;
+}
+
+typedef void (*range_fn)(void *arg, int64_t lo, int64_t hi);
+typedef struct {
+    range_fn fn;
+    void *arg;
+    int64_t lo, hi;
+} par_job;
+
+static void *par_run(void *p)
+{
+    par_job *j = (par_job *)p;
+    j->fn(j->arg, j->lo, j->hi);
+    return NULL;
+}
+
+/* fn over [0, n) in g_threads contiguous ranges, one thread each. */
+static void par_for(int64_t n, range_fn fn, void *arg)
+{
+    int T = g_threads;
+    if ((int64_t)T > n) T = n > 1 ? (int)n : 1;
+    if (T <= 1) {
+        fn(arg, 0, n);
+        return;
+    }
+    pthread_t th[MAX_THREADS];
+    par_job jb[MAX_THREADS];
+    for (int t = 0; t < T; ++t) {
+        jb[t].fn = fn;
+        jb[t].arg = arg;
+        jb[t].lo = n * t / T;
+        jb[t].hi = n * (t + 1) / T;
+        if (pthread_create(&th[t], NULL, par_run, &jb[t]) != 0) {
+            par_run(&jb[t]); /* no thread: run it here */
+            th[t] = pthread_self();
+        }
+    }
+    for (int t = 0; t < T; ++t)
+        if (!pthread_equal(th[t], pthread_self())) pthread_join(th[t], NULL);
+}
+
+/* ------------------------------------------------------------------ */
 /* small dense helpers (row-major)                                     */
 /* ------------------------------------------------------------------ */
 
-/* G = F^T F for F (rows x R). */
+/* G = F^T F for F (rows x R): G[r][s] = sum over n (in order) of
+ * F[n][r] F[n][s].  Threads take disjoint rows r of G. */
+typedef struct {
+    int64_t rows;
+    int R;
+    const double *F;
+    double *G;
+} gram_arg;
+
+static void gram_part(void *p, int64_t r0, int64_t r1)
+{
+    const gram_arg *a = (const gram_arg *)p;
+    const int R = a->R;
+    for (int64_t n = 0; n < a->rows; ++n) {
+        const double *f = a->F + n * R;
+        for (int64_t r = r0; r < r1; ++r)
+            for (int s = 0; s < R; ++s)
+                a->G[r * R + s] += f[r] * f[s];
+    }
+}
+
 static void gram(int64_t rows, int R, const double *F, double *G)
 {
     memset(G, 0, sizeof(double) * (size_t)R * R);
-    for (int64_t n = 0; n < rows; ++n) {
-        const double *f = F + n * R;
-        for (int r = 0; r < R; ++r)
-            for (int s = 0; s < R; ++s)
-                G[r * R + s] += f[r] * f[s];
-    }
+    gram_arg a = {rows, R, F, G};
+    if (g_threads > 1 && rows * R > 65536) par_for(R, gram_part, &a);
+    else gram_part(&a, 0, R);
 }
 
 /* Cholesky H = L L^T (L lower, row-major).  Returns 0 on success, -1 when a
@@ -155,18 +238,25 @@ static void pinv_sym(int R, const double *H, double *P)
 }
 
 /* F <- M H^{-1} row by row (H symmetric).  Cholesky with forward and back
- * substitution; pseudo-inverse when H is numerically singular.
+ * substitution; pseudo-inverse when H is numerically singular.  Rows are
+ * independent (threads take disjoint row ranges).
  * Returns 0 if Cholesky was used, 1 if the pseudo-inverse was used. */
-static int solve_rows(int64_t rows, int R, const double *M, const double *H,
-                      double *F)
+typedef struct {
+    int R;
+    const double *M, *L, *P; /* L: Cholesky factor, or P: pseudo-inverse */
+    double *F;
+} solve_arg;
+
+static void solve_part(void *p, int64_t n0, int64_t n1)
 {
-    double *L = (double *)malloc(sizeof(double) * (size_t)R * R);
-    int used_pinv = 0;
-    if (cholesky(R, H, L) == 0) {
-        double *y = (double *)malloc(sizeof(double) * (size_t)R);
-        for (int64_t n = 0; n < rows; ++n) {
-            const double *m = M + n * R;
-            double *x = F + n * R;
+    const solve_arg *a = (const solve_arg *)p;
+    const int R = a->R;
+    const double *L = a->L, *P = a->P;
+    double *y = (double *)malloc(sizeof(double) * (size_t)R);
+    for (int64_t n = n0; n < n1; ++n) {
+        const double *m = a->M + n * R;
+        double *x = a->F + n * R;
+        if (L) {
             /* H x = m  with H = L L^T  (x is the row written as a column) */
             for (int i = 0; i < R; ++i) {
                 double s = m[i];
@@ -178,23 +268,32 @@ static int solve_rows(int64_t rows, int R, const double *M, const double *H,
                 for (int k = i + 1; k < R; ++k) s -= L[k * R + i] * x[k];
                 x[i] = s / L[i * R + i];
             }
-        }
-        free(y);
-    } else {
-        used_pinv = 1;
-        double *P = (double *)malloc(sizeof(double) * (size_t)R * R);
-        pinv_sym(R, H, P);
-        for (int64_t n = 0; n < rows; ++n) {
-            const double *m = M + n * R;
-            double *x = F + n * R;
+        } else {
             for (int s = 0; s < R; ++s) {
                 double acc = 0.0;
                 for (int r = 0; r < R; ++r) acc += m[r] * P[r * R + s];
                 x[s] = acc;
             }
         }
-        free(P);
     }
+    free(y);
+}
+
+static int solve_rows(int64_t rows, int R, const double *M, const double *H,
+                      double *F)
+{
+    double *L = (double *)malloc(sizeof(double) * (size_t)R * R);
+    double *P = NULL;
+    int used_pinv = 0;
+    if (cholesky(R, H, L) != 0) {
+        used_pinv = 1;
+        P = (double *)malloc(sizeof(double) * (size_t)R * R);
+        pinv_sym(R, H, P);
+    }
+    solve_arg a = {R, M, used_pinv ? NULL : L, P, F};
+    if (g_threads > 1 && rows > 4096) par_for(rows, solve_part, &a);
+    else solve_part(&a, 0, rows);
+    free(P);
     free(L);
     return used_pinv;
 }
@@ -272,6 +371,71 @@ static rec *sorted_distinct(int64_t nnz, coords c, const double *val, int mode,
  *   mode 1: out[j,:] += x_{ijk} * (A[i,:] * C[k,:])
  *   mode 2: out[k,:] += x_{ijk} * (A[i,:] * B[j,:])
  * F[m] is dims[m] x R row-major; out is dims[mode] x R and is overwritten. */
+/* With threads: output rows are cut into g_threads ranges of about equal
+ * nonzero counts; each thread adds the nonzeros of its rows in input order,
+ * so every output row is the same sum in the same order as serially. */
+typedef struct {
+    int64_t nnz, rows;
+    const uint32_t *root;   /* output-row index of each nonzero */
+    const uint32_t *part;   /* row -> range (rows entries) */
+    int T;                  /* ranges */
+    uint32_t *hist;         /* per chunk: rows counts (pass 1), then T counts */
+    int64_t *off;           /* per (chunk, range): first slot */
+    uint32_t *order;        /* nonzero ids grouped by range, input order kept */
+    /* the arithmetic */
+    const uint32_t *ixp, *ixq;
+    const double *val, *Fp, *Fq;
+    int R;
+    double *out;
+} mtt_arg;
+
+static void mtt_count_rows(void *p, int64_t c0, int64_t c1)
+{
+    mtt_arg *a = (mtt_arg *)p;
+    for (int64_t c = c0; c < c1; ++c) {
+        uint32_t *h = a->hist + c * a->rows;
+        const int64_t e0 = a->nnz * c / a->T, e1 = a->nnz * (c + 1) / a->T;
+        for (int64_t e = e0; e < e1; ++e) ++h[a->root[e]];
+    }
+}
+
+static void mtt_count_parts(void *p, int64_t c0, int64_t c1)
+{
+    mtt_arg *a = (mtt_arg *)p;
+    for (int64_t c = c0; c < c1; ++c) {
+        int64_t *o = a->off + c * a->T;
+        const int64_t e0 = a->nnz * c / a->T, e1 = a->nnz * (c + 1) / a->T;
+        for (int64_t e = e0; e < e1; ++e) ++o[a->part[a->root[e]]];
+    }
+}
+
+static void mtt_scatter(void *p, int64_t c0, int64_t c1)
+{
+    mtt_arg *a = (mtt_arg *)p;
+    for (int64_t c = c0; c < c1; ++c) {
+        int64_t *o = a->off + c * a->T;
+        const int64_t e0 = a->nnz * c / a->T, e1 = a->nnz * (c + 1) / a->T;
+        for (int64_t e = e0; e < e1; ++e) a->order[o[a->part[a->root[e]]]++] = (uint32_t)e;
+    }
+}
+
+static void mtt_compute(void *p, int64_t t0, int64_t t1)
+{
+    mtt_arg *a = (mtt_arg *)p;
+    const int R = a->R;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t b = t == 0 ? 0 : a->off[(int64_t)(a->T - 1) * a->T + t - 1];
+        const int64_t e1 = a->off[(int64_t)(a->T - 1) * a->T + t];
+        for (int64_t x = b; x < e1; ++x) {
+            const int64_t e = a->order[x];
+            double *o = a->out + (int64_t)a->root[e] * R;
+            const double *fp = a->Fp + (int64_t)a->ixp[e] * R;
+            const double *fq = a->Fq + (int64_t)a->ixq[e] * R;
+            for (int r = 0; r < R; ++r) o[r] += a->val[e] * fp[r] * fq[r];
+        }
+    }
+}
+
 void oracle_mttkrp(int64_t nnz, const uint32_t *i, const uint32_t *j,
                    const uint32_t *k, const double *val, const int64_t *dims,
                    int R, const double *A, const double *B, const double *C,
@@ -281,12 +445,65 @@ void oracle_mttkrp(int64_t nnz, const uint32_t *i, const uint32_t *j,
     const double *F[3] = {A, B, C};
     const int p = (mode + 1) % 3, q = (mode + 2) % 3;
     memset(out, 0, sizeof(double) * (size_t)dims[mode] * R);
-    for (int64_t e = 0; e < nnz; ++e) {
-        double *o = out + (int64_t)ix[mode][e] * R;
-        const double *fp = F[p] + (int64_t)ix[p][e] * R;
-        const double *fq = F[q] + (int64_t)ix[q][e] * R;
-        for (int r = 0; r < R; ++r) o[r] += val[e] * fp[r] * fq[r];
+    const int T = g_threads;
+    if (T <= 1 || nnz < 65536 || nnz > 0xFFFFFFFFll) {
+        for (int64_t e = 0; e < nnz; ++e) {
+            double *o = out + (int64_t)ix[mode][e] * R;
+            const double *fp = F[p] + (int64_t)ix[p][e] * R;
+            const double *fq = F[q] + (int64_t)ix[q][e] * R;
+            for (int r = 0; r < R; ++r) o[r] += val[e] * fp[r] * fq[r];
+        }
+        return;
     }
+    const int64_t rows = dims[mode];
+    mtt_arg a;
+    memset(&a, 0, sizeof(a));
+    a.nnz = nnz;
+    a.rows = rows;
+    a.root = ix[mode];
+    a.T = T;
+    a.ixp = ix[p];
+    a.ixq = ix[q];
+    a.val = val;
+    a.Fp = F[p];
+    a.Fq = F[q];
+    a.R = R;
+    a.out = out;
+    /* nonzeros per row (one histogram per input chunk, then summed) */
+    a.hist = (uint32_t *)calloc((size_t)T * rows, sizeof(uint32_t));
+    par_for(T, mtt_count_rows, &a);
+    /* row ranges of about nnz / T nonzeros each */
+    uint32_t *part = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)rows);
+    int64_t acc = 0;
+    int cur = 0;
+    for (int64_t r = 0; r < rows; ++r) {
+        int64_t c = 0;
+        for (int t = 0; t < T; ++t) c += a.hist[(int64_t)t * rows + r];
+        while (cur < T - 1 && acc >= nnz * (cur + 1) / T) ++cur;
+        part[r] = (uint32_t)cur;
+        acc += c;
+    }
+    free(a.hist);
+    a.hist = NULL;
+    a.part = part;
+    /* per (chunk, range) counts -> first slots: range-major, chunk-minor,
+     * so each range lists its nonzeros in input order */
+    a.off = (int64_t *)calloc((size_t)T * T, sizeof(int64_t));
+    par_for(T, mtt_count_parts, &a);
+    int64_t run = 0;
+    for (int t = 0; t < T; ++t)
+        for (int c = 0; c < T; ++c) {
+            const int64_t n = a.off[(int64_t)c * T + t];
+            a.off[(int64_t)c * T + t] = run;
+            run += n;
+        }
+    a.order = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)nnz);
+    par_for(T, mtt_scatter, &a);
+    /* after the scatter, off[(T-1) * T + t] is the end of range t */
+    par_for(T, mtt_compute, &a);
+    free(a.order);
+    free(a.off);
+    free(part);
 }
 
 /* Flattening of `mode` (Section 2.1 and the CSR discussion of Section 3):
@@ -361,6 +578,11 @@ int64_t oracle_fiber_partials(int64_t nnz, const uint32_t *i, const uint32_t *j,
 double oracle_normsq(int64_t nnz, const uint32_t *i, const uint32_t *j,
                      const uint32_t *k, const double *val)
 {
+    if (g_distinct) { /* nothing to merge: the values in input order */
+        double s = 0.0;
+        for (int64_t e = 0; e < nnz; ++e) s += val[e] * val[e];
+        return s;
+    }
     coords c = {{i, j, k}};
     int64_t n = 0;
     rec *a = sorted_distinct(nnz, c, val, 0, &n);
@@ -372,21 +594,42 @@ double oracle_normsq(int64_t nnz, const uint32_t *i, const uint32_t *j,
 
 /* <X, [[lambda; A, B, C]]> summed over the nonzeros directly:
  *   sum_e x_e sum_r lambda_r a_{ir} b_{jr} c_{kr}   (lambda NULL = ones). */
+typedef struct {
+    const uint32_t *i, *j, *k;
+    int R;
+    const double *A, *B, *C, *lambda;
+    double *t;
+} inner_arg;
+
+static void inner_terms(void *p, int64_t e0, int64_t e1)
+{
+    const inner_arg *a = (const inner_arg *)p;
+    const int R = a->R;
+    for (int64_t e = e0; e < e1; ++e) {
+        const double *x = a->A + (int64_t)a->i[e] * R;
+        const double *y = a->B + (int64_t)a->j[e] * R;
+        const double *z = a->C + (int64_t)a->k[e] * R;
+        double t = 0.0;
+        for (int r = 0; r < R; ++r)
+            t += (a->lambda ? a->lambda[r] : 1.0) * x[r] * y[r] * z[r];
+        a->t[e] = t;
+    }
+}
+
 double oracle_inner(int64_t nnz, const uint32_t *i, const uint32_t *j,
                     const uint32_t *k, const double *val, int R,
                     const double *A, const double *B, const double *C,
                     const double *lambda)
 {
+    /* each nonzero's model value (threads: disjoint nonzeros), then the sum
+     * over the nonzeros in input order */
+    double *t = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    inner_arg a = {i, j, k, R, A, B, C, lambda, t};
+    if (g_threads > 1 && nnz > 65536) par_for(nnz, inner_terms, &a);
+    else inner_terms(&a, 0, nnz);
     double s = 0.0;
-    for (int64_t e = 0; e < nnz; ++e) {
-        const double *a = A + (int64_t)i[e] * R;
-        const double *b = B + (int64_t)j[e] * R;
-        const double *c = C + (int64_t)k[e] * R;
-        double t = 0.0;
-        for (int r = 0; r < R; ++r)
-            t += (lambda ? lambda[r] : 1.0) * a[r] * b[r] * c[r];
-        s += val[e] * t;
-    }
+    for (int64_t e = 0; e < nnz; ++e) s += val[e] * t[e];
+    free(t);
     return s;
 }
 
@@ -425,6 +668,51 @@ static double round_bf16(double x)
     return (double)f;
 }
 
+/* column pieces of the ALS step, split over columns r (each a sum over the
+ * rows in order) or over entries */
+typedef struct {
+    int64_t rows;
+    int R;
+    double *F, *lambda;
+} colnorm_arg;
+
+static void colnorm_part(void *p, int64_t r0, int64_t r1)
+{
+    const colnorm_arg *a = (const colnorm_arg *)p;
+    const int R = a->R;
+    for (int64_t r = r0; r < r1; ++r) {
+        double s = 0.0;
+        for (int64_t m = 0; m < a->rows; ++m) s += a->F[m * R + r] * a->F[m * R + r];
+        a->lambda[r] = sqrt(s);
+        if (a->lambda[r] > 0.0)
+            for (int64_t m = 0; m < a->rows; ++m) a->F[m * R + r] /= a->lambda[r];
+    }
+}
+
+static void round_part(void *p, int64_t e0, int64_t e1)
+{
+    double *F = (double *)p;
+    for (int64_t e = e0; e < e1; ++e) F[e] = round_bf16(F[e]);
+}
+
+typedef struct {
+    int64_t rows;
+    int R;
+    const double *C, *M;
+    double *out;
+} coldot_arg;
+
+static void coldot_part(void *p, int64_t r0, int64_t r1)
+{
+    const coldot_arg *a = (const coldot_arg *)p;
+    const int R = a->R;
+    for (int64_t r = r0; r < r1; ++r) {
+        double s = 0.0;
+        for (int64_t m = 0; m < a->rows; ++m) s += a->C[m * R + r] * a->M[m * R + r];
+        a->out[r] = s;
+    }
+}
+
 int oracle_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
                     const uint32_t *k, const double *val, const int64_t *dims,
                     int R, double reg, int store_bf16, double *A, double *B,
@@ -448,17 +736,15 @@ int oracle_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
         for (int t = 0; t < R * R; ++t) H[t] = Gp[t] * Gq[t];
         for (int r = 0; r < R; ++r) H[r * R + r] += reg;
         if (solve_rows(dims[n], R, M, H, F[n])) pinv_mask |= 1 << n;
-        for (int r = 0; r < R; ++r) {
-            double s = 0.0;
-            for (int64_t m = 0; m < dims[n]; ++m)
-                s += F[n][m * R + r] * F[n][m * R + r];
-            lambda[r] = sqrt(s);
-            if (lambda[r] > 0.0)
-                for (int64_t m = 0; m < dims[n]; ++m) F[n][m * R + r] /= lambda[r];
-        }
+        /* lambda_r = ||F_n[:, r]||_2, then unit columns (threads: columns) */
+        colnorm_arg cn = {dims[n], R, F[n], lambda};
+        if (g_threads > 1 && dims[n] > 4096) par_for(R, colnorm_part, &cn);
+        else colnorm_part(&cn, 0, R);
         /* a factor stored in BF16 enters the next mode's update rounded */
-        if (store_bf16)
-            for (int64_t e = 0; e < dims[n] * R; ++e) F[n][e] = round_bf16(F[n][e]);
+        if (store_bf16) {
+            if (g_threads > 1 && dims[n] > 4096) par_for(dims[n] * R, round_part, F[n]);
+            else round_part(F[n], 0, dims[n] * R);
+        }
         if (n == 2) memcpy(M3, M, sizeof(double) * (size_t)dims[2] * R);
     }
     /* fit */
@@ -473,12 +759,14 @@ int oracle_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
         for (int s = 0; s < R; ++s)
             xhat2 += lambda[r] * lambda[s] * GA[r * R + s] * GB[r * R + s] *
                      GC[r * R + s];
+    /* <X, Xhat> = sum_r lambda_r sum_k C[k, r] M3[k, r] (threads: columns) */
+    double *colsum = (double *)malloc(sizeof(double) * (size_t)R);
+    coldot_arg cd = {dims[2], R, C, M3, colsum};
+    if (g_threads > 1 && dims[2] > 4096) par_for(R, coldot_part, &cd);
+    else coldot_part(&cd, 0, R);
     double inner = 0.0;
-    for (int r = 0; r < R; ++r) {
-        double s = 0.0;
-        for (int64_t m = 0; m < dims[2]; ++m) s += C[m * R + r] * M3[m * R + r];
-        inner += lambda[r] * s;
-    }
+    for (int r = 0; r < R; ++r) inner += lambda[r] * colsum[r];
+    free(colsum);
     const double x2 = oracle_normsq(nnz, i, j, k, val);
     double res2 = x2 + xhat2 - 2.0 * inner;
     if (res2 < 0.0) res2 = 0.0;
@@ -504,6 +792,28 @@ int oracle_als_iter(int64_t nnz, const uint32_t *i, const uint32_t *j,
  *       + 1/2 reg (||A||^2 + ||B||^2 + ||C||^2)
  * The sum in f runs over every (i, j, k), so zeros count.  G[m] receives a
  * dims[m] x R gradient.  Returns f. */
+/* gradient rows g = -M + F H (threads: rows) */
+typedef struct {
+    int R;
+    const double *F, *H;
+    double *G;
+} gdrow_arg;
+
+static void gdrow_part(void *p, int64_t m0, int64_t m1)
+{
+    const gdrow_arg *a = (const gdrow_arg *)p;
+    const int R = a->R;
+    for (int64_t m = m0; m < m1; ++m) {
+        const double *fr = a->F + m * R;
+        double *g = a->G + m * R;
+        for (int s = 0; s < R; ++s) {
+            double acc = 0.0;
+            for (int r = 0; r < R; ++r) acc += fr[r] * a->H[r * R + s];
+            g[s] = -g[s] + acc;
+        }
+    }
+}
+
 double oracle_gd_grad(int64_t nnz, const uint32_t *i, const uint32_t *j,
                       const uint32_t *k, const double *val,
                       const int64_t *dims, int R, double reg, const double *A,
@@ -523,15 +833,9 @@ double oracle_gd_grad(int64_t nnz, const uint32_t *i, const uint32_t *j,
         oracle_mttkrp(nnz, i, j, k, val, dims, R, A, B, C, n, Gout[n]);
         for (int t = 0; t < R * R; ++t) H[t] = Gm[p][t] * Gm[q][t];
         for (int r = 0; r < R; ++r) H[r * R + r] += reg;
-        for (int64_t m = 0; m < dims[n]; ++m) {
-            const double *fr = F[n] + m * R;
-            double *g = Gout[n] + m * R;
-            for (int s = 0; s < R; ++s) {
-                double acc = 0.0;
-                for (int r = 0; r < R; ++r) acc += fr[r] * H[r * R + s];
-                g[s] = -g[s] + acc;
-            }
-        }
+        gdrow_arg ga = {R, F[n], H, Gout[n]};
+        if (g_threads > 1 && dims[n] > 4096) par_for(dims[n], gdrow_part, &ga);
+        else gdrow_part(&ga, 0, dims[n]);
     }
     double xhat2 = 0.0, fro2 = 0.0;
     for (int t = 0; t < R * R; ++t) xhat2 += Gm[0][t] * Gm[1][t] * Gm[2][t];
