@@ -30,8 +30,13 @@
  *    and a call that has to grow one of the context's workspaces (the first
  *    call at a larger size, when the library allocates itself); a call
  *    repeated at the same sizes only enqueues, so it can be captured in a
- *    HIP graph.  Inputs must stay unmodified until the stream passes the
- *    call.
+ *    HIP graph.  A captured graph keeps the addresses of the context's
+ *    workspaces: it stays valid only while no later call on that context
+ *    grows a workspace (a growing call frees the old one).  To rule that
+ *    out, run the calls to be captured once, then dfacto_ctx_freeze(ctx, 1):
+ *    from then on a call that would grow a workspace fails with
+ *    DFACTO_E_INVALID instead.  Inputs must stay unmodified until the
+ *    stream passes the call.
  *  - Every call returns a status; nothing aborts, throws or prints.  A HIP
  *    runtime failure is sticky: the context then returns DFACTO_E_DEVICE
  *    from every later call.  dfacto_last_error() describes the last failure.
@@ -111,6 +116,13 @@ dfacto_status dfacto_ctx_set_stream(dfacto_ctx *ctx, void *hip_stream);
 /* Wait until all work the context enqueued has finished. */
 dfacto_status dfacto_ctx_synchronize(dfacto_ctx *ctx);
 
+/* Freeze (on = 1) or unfreeze (0) the context's workspaces.  While frozen,
+ * a call that needs a larger workspace than the context holds fails with
+ * DFACTO_E_INVALID and enqueues nothing, so workspace addresses recorded in
+ * a HIP graph stay valid.  Size the workspaces first by running each call
+ * to be captured once at its largest sizes. */
+dfacto_status dfacto_ctx_freeze(dfacto_ctx *ctx, int on);
+
 /* Free the context and its workspace.  NULL is ignored. */
 void dfacto_ctx_destroy(dfacto_ctx *ctx);
 
@@ -146,6 +158,26 @@ dfacto_status dfacto_build_flattenings(dfacto_ctx *ctx, const int64_t dims[3], i
                                        const uint32_t *d_k, const float *d_val,
                                        dfacto_tensor **out);
 
+/* Build flags.  The MTTKRP gathers one factor row per stored nonzero (its
+ * leaf) and one per fiber (its mid), and most gathers of a skewed tensor
+ * fall on few rows.  A relabeled build stores, in place of those indices,
+ * each row's rank in the order of decreasing gather count (ties by index;
+ * one order per gathered table and mode); the MTTKRP then reads the factors
+ * through copies permuted into that order, where the most-gathered rows
+ * share cache lines (rows shorter than a line: BF16 factors, small R).
+ * The nonzeros' order, and so every result, is the same either way.
+ * DFACTO_BUILD_RELABEL: relabel; DFACTO_BUILD_NO_RELABEL: plain indices;
+ * neither (dfacto_build_flattenings): relabel from 2^23 stored nonzeros on. */
+#define DFACTO_BUILD_RELABEL 1
+#define DFACTO_BUILD_NO_RELABEL 2
+
+/* dfacto_build_flattenings with build flags (above).  Errors as there, and
+ * DFACTO_E_INVALID for unknown or contradictory flags. */
+dfacto_status dfacto_build_flattenings_ex(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
+                                          const uint32_t *d_i, const uint32_t *d_j,
+                                          const uint32_t *d_k, const float *d_val, int flags,
+                                          dfacto_tensor **out);
+
 typedef struct {
     int64_t dims[3];
     int64_t nnz;        /* distinct nonzeros after merging duplicates */
@@ -155,6 +187,7 @@ typedef struct {
     int64_t nchunk[3];  /* work chunks per mode */
     double normsq;      /* ||X||^2 in FP64 */
     size_t bytes;       /* device bytes held by the tensor */
+    int relabeled;      /* 1 when built with relabeled gathers */
 } dfacto_tensor_info;
 
 dfacto_status dfacto_tensor_get_info(const dfacto_tensor *t, dfacto_tensor_info *info);
@@ -465,6 +498,31 @@ dfacto_status dfacto_profile_enable(dfacto_ctx *ctx, int on);
  * 2 R (nnz + nfib) flops.  Clears the records.  Any pointer may be NULL. */
 dfacto_status dfacto_profile_read(dfacto_ctx *ctx, int64_t *launches, double *ms, double *bytes,
                                   double *flops);
+
+/* Measurement of the MTTKRP's memory-request ceiling (Section 3.2: the
+ * product is a scan of the mode's flattening with one factor-row gather per
+ * stored nonzero and per fiber).  Runs the main MTTKRP kernel's memory
+ * requests for `mode` -- the same work chunks, lane groups, batches and row
+ * loads -- with the arithmetic replaced by a plain sum of each gathered row.
+ * pattern 0: each entry gathers its own row (the MTTKRP's exact request
+ * sequence); 1: a row drawn uniformly at random from the same factor (leaf
+ * factor for a nonzero, mid factor for a header); 2: a row among that
+ * factor's first 4096; 3: no gathers, the flattening is only read; 4: a row
+ * among the factor's first 32; 5: a row of a 128-row table held in LDS
+ * (R <= 64); 6-9 gather leaf rows (a header's mid index taken modulo the
+ * leaf rows) with buffer loads: 6 every load out of range (no memory
+ * request), 7 the entry's own row, 8 half of the entries (by a hash bit)
+ * from the LDS table and half their own rows, split by a branch, 9 the same
+ * split without a branch (an out-of-range load beside an LDS load).
+ * d_F as for dfacto_mttkrp (only R <= 64 x the kernel's columns per lane);
+ * d_sink: device buffer of at least 64 x (work chunks of the mode) floats,
+ * 16-byte aligned, overwritten with meaningless sums.  With timing on
+ * (dfacto_profile_enable) the launch is recorded like an MTTKRP's main
+ * kernel, without bytes.  Errors: DFACTO_E_INVALID (arguments),
+ * DFACTO_E_UNSUPPORTED (R too large for one column block). */
+dfacto_status dfacto_gather_probe(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                                  dfacto_dtype dtype, const void *const d_F[3], int pattern,
+                                  float *d_sink);
 
 #ifdef __cplusplus
 }

@@ -340,19 +340,46 @@ __global__ void k_header_flags(const uint32_t *__restrict__ fs, const uint32_t *
     }
 }
 
+// inv_leaf / inv_mid (or null): the relabeled index of each leaf / mid row
 __global__ void k_emit_stream(const uint32_t *__restrict__ root, const uint32_t *__restrict__ mid,
                               const uint32_t *__restrict__ leaf, const float *__restrict__ val,
                               const uint32_t *__restrict__ h, const uint32_t *__restrict__ hex,
                               const uint32_t *__restrict__ rs, int64_t n, int64_t L,
-                              uint2 *__restrict__ st) {
+                              const uint32_t *__restrict__ inv_leaf,
+                              const uint32_t *__restrict__ inv_mid, uint2 *__restrict__ st) {
     GRID_STRIDE(e, n) {
         const uint32_t pos = (uint32_t)e + hex[e] + h[e];
         if ((int64_t)pos >= L) continue;  // never taken when the scan is consistent
         if (h[e]) {
-            st[pos - 1] = make_uint2(kHdrBit | (rs[e] ? kRootBit : 0u) | mid[e], root[e]);
+            const uint32_t m = inv_mid ? inv_mid[mid[e]] : mid[e];
+            st[pos - 1] = make_uint2(kHdrBit | (rs[e] ? kRootBit : 0u) | m, root[e]);
         }
-        st[pos] = make_uint2(leaf[e], __float_as_uint(val[e]));
+        st[pos] = make_uint2(inv_leaf ? inv_leaf[leaf[e]] : leaf[e], __float_as_uint(val[e]));
     }
+}
+
+// gathers per row: every nonzero gathers its leaf row, every header (fiber
+// start or segment start) its mid row
+__global__ void k_count_gathers(const uint32_t *__restrict__ leaf, const uint32_t *__restrict__ mid,
+                                const uint32_t *__restrict__ h, int64_t n,
+                                uint32_t *__restrict__ cnt_leaf, uint32_t *__restrict__ cnt_mid) {
+    GRID_STRIDE(e, n) {
+        atomicAdd(&cnt_leaf[leaf[e]], 1u);
+        if (h[e]) atomicAdd(&cnt_mid[mid[e]], 1u);
+    }
+}
+
+// sort key: count descending (a stable sort keeps equal counts in index order)
+__global__ void k_count_keys(const uint32_t *__restrict__ cnt, int64_t n,
+                             uint64_t *__restrict__ key, uint32_t *__restrict__ idx) {
+    GRID_STRIDE(e, n) {
+        key[e] = (uint64_t)(0xFFFFFFFFu - cnt[e]);
+        idx[e] = (uint32_t)e;
+    }
+}
+
+__global__ void k_invert(const uint32_t *__restrict__ perm, int64_t n, uint32_t *__restrict__ inv) {
+    GRID_STRIDE(e, n) inv[perm[e]] = (uint32_t)e;
 }
 
 __global__ void k_fill_pad(uint2 *__restrict__ st, int64_t from, int64_t count) {
@@ -538,6 +565,27 @@ void finish_runs(dfacto_tensor *t, ModeData &md, hipStream_t s, const std::vecto
     md.runs_long_host = std::move(longr);
 }
 
+// The order of a gathered table's rows by decreasing gather count (ties by
+// index): perm[r] = the row ranked r (tensor memory).  The counts of the
+// first kTopRows ranks go to `top` (host), landing at the build's next wait.
+uint32_t *relabel_order(dfacto_tensor *t, const uint32_t *cnt, int64_t rows, Scratch &sc,
+                        hipStream_t s, std::vector<uint32_t> &top) {
+    uint64_t *key = sc.alloc<uint64_t>(rows), *kalt = sc.alloc<uint64_t>(rows);
+    uint32_t *idx = sc.alloc<uint32_t>(rows), *ialt = sc.alloc<uint32_t>(rows);
+    hipLaunchKernelGGL(k_count_keys, dim3(grid_for(rows)), dim3(kThreads), 0, s, cnt, rows, key,
+                       idx);
+    DF_LAUNCHED();
+    radix_sort(key, idx, kalt, ialt, rows, 32, sc, s);
+    uint32_t *perm = tensor_alloc<uint32_t>(t, rows);
+    DF_HIP(hipMemcpyAsync(perm, idx, sizeof(uint32_t) * (size_t)rows, hipMemcpyDeviceToDevice, s));
+    const int64_t nt = std::min<int64_t>(rows, kTopRows);
+    std::vector<uint64_t> *keys = new std::vector<uint64_t>((size_t)nt);
+    t->pending_top.push_back({keys, &top});
+    DF_HIP(hipMemcpyAsync(keys->data(), key, sizeof(uint64_t) * (size_t)nt, hipMemcpyDeviceToHost,
+                          s));
+    return perm;
+}
+
 // Mode m's flattening from its nonzeros in (root, mid) order; the chunk
 // heads for its run lists land in `heads` at the build's next wait.
 void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
@@ -611,9 +659,28 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     if (L > (int64_t)0xFFFFFFFFu - (1 << 20))
         throw Error{DFACTO_E_UNSUPPORTED, "nonzeros plus fiber headers exceed 2^32 - 2^20"};
     md.nentry = L;
+    // relabeled gathers: ranks by decreasing gather count per gathered table
+    const uint32_t *inv_leaf = nullptr, *inv_mid = nullptr;
+    if (t->relabel) {
+        const int64_t dl = t->dims[md.leaf], dm = t->dims[md.mid];
+        uint32_t *cl = sc.alloc<uint32_t>(dl), *cm = sc.alloc<uint32_t>(dm);
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(dl)), dim3(kThreads), 0, s, cl, dl, 0u);
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(dm)), dim3(kThreads), 0, s, cm, dm, 0u);
+        hipLaunchKernelGGL(k_count_gathers, dim3(grid_for(n)), dim3(kThreads), 0, s, leaf, mid, h, n,
+                           cl, cm);
+        DF_LAUNCHED();
+        md.perm_leaf = relabel_order(t, cl, dl, sc, s, md.top_leaf);
+        md.perm_mid = relabel_order(t, cm, dm, sc, s, md.top_mid);
+        uint32_t *il = sc.alloc<uint32_t>(dl), *im = sc.alloc<uint32_t>(dm);
+        hipLaunchKernelGGL(k_invert, dim3(grid_for(dl)), dim3(kThreads), 0, s, md.perm_leaf, dl, il);
+        hipLaunchKernelGGL(k_invert, dim3(grid_for(dm)), dim3(kThreads), 0, s, md.perm_mid, dm, im);
+        DF_LAUNCHED();
+        inv_leaf = il;
+        inv_mid = im;
+    }
     md.stream = tensor_alloc<uint2>(t, L + kStreamPad);
     hipLaunchKernelGGL(k_emit_stream, dim3(grid_for(n)), dim3(kThreads), 0, s, root, mid, leaf, val,
-                       h, hex, rs, n, L, md.stream);
+                       h, hex, rs, n, L, inv_leaf, inv_mid, md.stream);
     hipLaunchKernelGGL(k_fill_pad, dim3(1), dim3(kThreads), 0, s, md.stream, L,
                        (int64_t)kStreamPad);
     md.nroot = nrows - md.nempty;
@@ -721,6 +788,17 @@ void build_row_ranges(dfacto_ctx *ctx, dfacto_tensor *t) {
     DF_HIP(hipStreamSynchronize(s));
 }
 
+// the top gather counts copied during the build, as counts
+void take_top_counts(dfacto_tensor *t) {
+    for (auto &p : t->pending_top) {
+        p.second->resize(p.first->size());
+        for (size_t r = 0; r < p.first->size(); ++r)
+            (*p.second)[r] = 0xFFFFFFFFu - (uint32_t)(*p.first)[r];
+        delete p.first;
+    }
+    t->pending_top.clear();
+}
+
 void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const uint32_t *d_j,
                   const uint32_t *d_k, const float *d_val) {
     hipStream_t s = ctx->stream;
@@ -824,7 +902,8 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
         DF_LAUNCHED();
         build_mode(ctx, t, m, gr, gm, gl, gv, nd, heads[m]);
     }
-    DF_HIP(hipStreamSynchronize(s));  // the chunk heads and ||X||^2
+    DF_HIP(hipStreamSynchronize(s));  // the chunk heads, ||X||^2, the top counts
+    take_top_counts(t);
     for (int m = 0; m < 3; ++m) finish_runs(t, t->mode[m], s, heads[m]);
     DF_HIP(hipStreamSynchronize(s));  // the run lists' uploads
 }

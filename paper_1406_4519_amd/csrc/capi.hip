@@ -30,6 +30,9 @@ void hip_check(hipError_t e, const char *what) {
 void *ws_get(dfacto_ctx *ctx, dfacto_ctx::Slot slot, size_t bytes) {
     bytes = std::max<size_t>(bytes, 256);
     if (ctx->ws_size[slot] >= bytes) return ctx->ws[slot];
+    if (ctx->frozen)
+        throw Error{DFACTO_E_INVALID,
+                    "a workspace would have to grow while the context is frozen"};
     const bool user = ctx->mem.has_user();
     if (ctx->ws[slot]) {
         if (user) {  // the caller's allocator orders reuse after the stream's work
@@ -92,6 +95,26 @@ int64_t max_dim(const dfacto_tensor *t) {
     return std::max(t->dims[0], std::max(t->dims[1], t->dims[2]));
 }
 
+// The workspaces that a call's launches take further down (carries of
+// `carry_sets` MTTKRPs of the largest mode, the Gram partial sums of both
+// streams), acquired before the call enqueues anything: a frozen context
+// then fails before any work is queued.
+void ws_prepare(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfacto_dtype dt, int carry_sets,
+                bool grams, const dfacto_tensor *t2 = nullptr) {
+    int64_t cmax = 1;
+    for (int m = 0; m < 3; ++m) {
+        cmax = std::max<int64_t>(cmax, t->mode[m].nchunk);
+        if (t2) cmax = std::max<int64_t>(cmax, t2->mode[m].nchunk);
+    }
+    ws_get(ctx, dfacto_ctx::kCarry, sizeof(float) * (size_t)carry_sets * cmax * R);
+    const size_t pb = perm_bytes(t, R, dt);
+    if (pb) ws_get(ctx, dfacto_ctx::kPerm, pb);
+    if (grams) {
+        ws_get(ctx, dfacto_ctx::kPartial, sizeof(double) * 256 * (size_t)R * R);
+        ws_get(ctx, dfacto_ctx::kPartialSide, sizeof(double) * 256 * (size_t)R * R);
+    }
+}
+
 // small FP64 workspace layout (units of doubles)
 struct Small {
     double *G[3], *Hinv, *W, *MtM, *solve_scratch, *lam_scratch, *H[3], *part0, *part_dummy;
@@ -131,7 +154,7 @@ namespace dfacto {
 dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
                                      const uint32_t *d_i, const uint32_t *d_j,
                                      const uint32_t *d_k, const float *d_val, dfacto_tensor **out,
-                                     bool async_alloc) {
+                                     bool async_alloc, int flags) {
     if (out) *out = nullptr;
     return guarded(ctx, [&] {
         if (!out || !dims) throw Error{DFACTO_E_INVALID, "dims or out is NULL"};
@@ -143,7 +166,12 @@ dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int
             throw Error{DFACTO_E_INVALID, "coordinate or value array is NULL"};
         if (nnz >= (int64_t)0xFFFFFFFFu - (1 << 20))
             throw Error{DFACTO_E_UNSUPPORTED, "nnz must be below 2^32 - 2^20"};
+        if (flags & ~(DFACTO_BUILD_RELABEL | DFACTO_BUILD_NO_RELABEL) ||
+            (flags & DFACTO_BUILD_RELABEL && flags & DFACTO_BUILD_NO_RELABEL))
+            throw Error{DFACTO_E_INVALID, "bad build flags"};
         dfacto_tensor *t = new dfacto_tensor();
+        t->relabel = (flags & DFACTO_BUILD_RELABEL) ||
+                     (!(flags & DFACTO_BUILD_NO_RELABEL) && nnz >= kRelabelMinNnz);
         t->device = ctx->device;
         if (async_alloc || ctx->mem.has_user()) {
             t->alloc_stream = ctx->stream;
@@ -167,7 +195,8 @@ dfacto_status build_flattenings_async_alloc(dfacto_ctx *ctx, const int64_t dims[
                                             const uint32_t *d_i, const uint32_t *d_j,
                                             const uint32_t *d_k, const float *d_val,
                                             dfacto_tensor **out) {
-    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, true);
+    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, true,
+                                  DFACTO_BUILD_NO_RELABEL);
 }
 
 }  // namespace dfacto
@@ -208,6 +237,12 @@ dfacto_status dfacto_ctx_synchronize(dfacto_ctx *ctx) {
     return guarded(ctx, [&] { DF_HIP(hipStreamSynchronize(ctx->stream)); });
 }
 
+dfacto_status dfacto_ctx_freeze(dfacto_ctx *ctx, int on) {
+    if (!ctx) return DFACTO_E_INVALID;
+    ctx->frozen = on != 0;
+    return DFACTO_OK;
+}
+
 void dfacto_ctx_destroy(dfacto_ctx *ctx) {
     if (!ctx) return;
     int prev = -1;
@@ -240,7 +275,14 @@ dfacto_status dfacto_build_flattenings(dfacto_ctx *ctx, const int64_t dims[3], i
                                        const uint32_t *d_i, const uint32_t *d_j,
                                        const uint32_t *d_k, const float *d_val,
                                        dfacto_tensor **out) {
-    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, false);
+    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, false, 0);
+}
+
+dfacto_status dfacto_build_flattenings_ex(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
+                                          const uint32_t *d_i, const uint32_t *d_j,
+                                          const uint32_t *d_k, const float *d_val, int flags,
+                                          dfacto_tensor **out) {
+    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, false, flags);
 }
 
 dfacto_status dfacto_tensor_get_info(const dfacto_tensor *t, dfacto_tensor_info *info) {
@@ -253,6 +295,7 @@ dfacto_status dfacto_tensor_get_info(const dfacto_tensor *t, dfacto_tensor_info 
         info->nentry[m] = t->mode[m].nentry;
         info->nchunk[m] = t->mode[m].nchunk;
     }
+    info->relabeled = t->relabel ? 1 : 0;
     info->nnz = t->nnz;
     info->normsq = t->normsq;
     info->bytes = t->bytes;
@@ -273,7 +316,22 @@ dfacto_status dfacto_tensor_export(dfacto_ctx *ctx, const dfacto_tensor *t, int 
             DF_HIP(hipMemcpyAsync(st.data(), md.stream, sizeof(uint2) * md.nentry,
                                   hipMemcpyDeviceToHost, ctx->stream));
         }
+        // relabeled gathers: back to the factor rows
+        std::vector<uint32_t> pl, pm;
+        if (md.perm_leaf) {
+            pl.resize((size_t)t->dims[md.leaf]);
+            pm.resize((size_t)t->dims[md.mid]);
+            DF_HIP(hipMemcpyAsync(pl.data(), md.perm_leaf, sizeof(uint32_t) * pl.size(),
+                                  hipMemcpyDeviceToHost, ctx->stream));
+            DF_HIP(hipMemcpyAsync(pm.data(), md.perm_mid, sizeof(uint32_t) * pm.size(),
+                                  hipMemcpyDeviceToHost, ctx->stream));
+        }
         DF_HIP(hipStreamSynchronize(ctx->stream));
+        if (md.perm_leaf)
+            for (uint2 &w : st) {
+                if (w.x & kHdrBit) w.x = (w.x & ~kIdxMask) | pm[w.x & kIdxMask];
+                else w.x = pl[w.x];
+            }
         int64_t nr = 0, nf = 0, ne = 0;
         uint32_t last_mid = 0;
         for (const uint2 &w : st) {
@@ -307,6 +365,7 @@ dfacto_status dfacto_tensor_export(dfacto_ctx *ctx, const dfacto_tensor *t, int 
 
 void dfacto_tensor_destroy(dfacto_tensor *t) {
     if (!t) return;
+    for (auto &p : t->pending_top) delete p.first;  // a build that failed midway
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(t->device);
@@ -332,7 +391,26 @@ dfacto_status dfacto_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, i
         check_align(d_F[md.leaf], dtype, "leaf factor");
         check_align(d_F[md.mid], dtype, "mid factor");
         if ((uintptr_t)d_out % 4) throw Error{DFACTO_E_INVALID, "output is not 4-byte aligned"};
+        ws_prepare(ctx, t, R, dtype, 1, false);
         launch_mttkrp(ctx, t, mode, R, dtype, d_F[md.leaf], d_F[md.mid], d_out);
+    });
+}
+
+dfacto_status dfacto_gather_probe(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                                  dfacto_dtype dtype, const void *const d_F[3], int pattern,
+                                  float *d_sink) {
+    return guarded(ctx, [&] {
+        check_common(t, R, dtype);
+        if (mode < 0 || mode > 2) throw Error{DFACTO_E_INVALID, "mode must be 0, 1 or 2"};
+        if (pattern < 0 || pattern > 9) throw Error{DFACTO_E_INVALID, "pattern must be 0 .. 9"};
+        if (!d_F || !d_sink) throw Error{DFACTO_E_INVALID, "factor array or sink is NULL"};
+        const ModeData &md = t->mode[mode];
+        check_factor(d_F[md.leaf], "leaf factor");
+        check_factor(d_F[md.mid], "mid factor");
+        check_align(d_F[md.leaf], dtype, "leaf factor");
+        check_align(d_F[md.mid], dtype, "mid factor");
+        if ((uintptr_t)d_sink % 16) throw Error{DFACTO_E_INVALID, "sink is not 16-byte aligned"};
+        launch_gather_probe(ctx, t, mode, R, dtype, d_F[md.leaf], d_F[md.mid], pattern, d_sink);
     });
 }
 
@@ -348,6 +426,7 @@ dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, df
         }
         Small sw = small_ws(ctx, R);
         float *M = (float *)ws_get(ctx, dfacto_ctx::kM, sizeof(float) * (size_t)max_dim(t) * R);
+        ws_prepare(ctx, t, R, dtype, 1, true);
         ensure_side(ctx);
         // Mode n's R x R solve needs only the other modes' Grams, final once
         // mode n - 1's factor and Gram are: it runs on the side stream beside
@@ -377,9 +456,14 @@ dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, df
             launch_rowmap(ctx, M, t->dims[n], R, sw.W, d_F[n], dtype);
             // A BF16-stored factor differs from the FP64 one by its rounding;
             // the next modes' normal equations must use the Gram of what the
-            // next MTTKRPs read, so form it from the stored factor.
-            if (dtype == DFACTO_BF16 && n < 2)
+            // next MTTKRPs read, so form it from the stored factor; and the
+            // fit is that of the stored factors (lambda from the FP64 ones).
+            if (dtype == DFACTO_BF16) {
                 launch_gram(ctx, d_F[n], dtype, t->dims[n], R, sw.G[n]);
+                if (n == 2)
+                    launch_fit_stored(ctx, d_F[2], dtype, M, t->dims[2], R, d_lambda, sw.G[0],
+                                      sw.G[1], sw.G[2], t->normsq, sw.part0, d_fit);
+            }
         }
     });
 }
@@ -398,6 +482,7 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfa
             if ((uintptr_t)d_G[m] % 4) throw Error{DFACTO_E_INVALID, "gradient not aligned"};
         }
         Small sw = small_ws(ctx, R);
+        ws_prepare(ctx, t, R, dtype, 3, true);
         ensure_side(ctx);
         // the three MTTKRPs' main kernels run back to back on the main
         // stream, each with carries of its own; the Grams, each mode's carry
@@ -524,7 +609,9 @@ dfacto_status dfacto_build_ratings(dfacto_ctx *ctx, const int64_t dims[2], int64
                               ctx->stream));
         const int64_t d3[3] = {dims[0], dims[1], 1};
         dfacto_tensor *t = nullptr;
-        const dfacto_status st = dfacto_build_flattenings(ctx, d3, n, d_i, d_j, k0, d_y, &t);
+        // the joint rows read the ratings' streams directly: plain indices
+        const dfacto_status st = dfacto_build_flattenings_ex(ctx, d3, n, d_i, d_j, k0, d_y,
+                                                             DFACTO_BUILD_NO_RELABEL, &t);
         ctx->mem.free(k0, ctx->stream);
         if (st != DFACTO_OK) throw Error{st, ctx->err};
         try {
@@ -590,6 +677,7 @@ dfacto_status dfacto_joint_grad(dfacto_ctx *ctx, const dfacto_tensor *X, const d
         const size_t o_my0 = o_ry1 + al(4 * d1);
         const size_t o_part = o_my0 + al(4 * d0), o_ft = o_part + al(8 * 2 * kSumsqBlocks);
         char *w = (char *)ws_get(ctx, dfacto_ctx::kJoint, o_ft + 256);
+        ws_prepare(ctx, X, R, dtype, 1, true, Y);
         void *one = ones_row(ctx, R, dtype, w);
         float *RY0 = (float *)(w + o_ry0), *RY1 = (float *)(w + o_ry1), *MY0 = (float *)(w + o_my0);
         double *part = (double *)(w + o_part), *ft = (double *)(w + o_ft);

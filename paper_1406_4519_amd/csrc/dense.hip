@@ -17,6 +17,7 @@
 //    -M + F H over LDS-staged row tiles, the R x R matrix broadcast from LDS.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <type_traits>
 
@@ -673,6 +674,92 @@ __device__ void als_lambda_body(int R, int mode, const double *__restrict__ Hinv
         if (res2 < 0.0) res2 = 0.0;
         *fit_out = normsq > 0.0 ? 1.0 - sqrt(res2) / sqrt(normsq) : 0.0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Fit from the STORED last factor (BF16 storage): the rounded factor C that
+// later calls read differs from M H^-1 diag(1/lambda), so the fit is formed
+// from C itself, as for the other two factors whose Grams are re-formed
+// from their stored values:
+//   <X, Xhat> = sum_r lambda_r sum_k C[k, r] M[k, r]   (M: mode-2 MTTKRP)
+//   ||Xhat||^2 = lambda^T (G_A * G_B * G_C) lambda     (G_C from stored C)
+// Partial sums of the weighted inner product per block (fit_blocks of them,
+// each a fixed-order strided sum), then one block finishes.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void wdot_body(const T *__restrict__ F, const float *__restrict__ X, int64_t rows,
+                          int R, const double *__restrict__ lam, uint32_t b, uint32_t nb,
+                          double *__restrict__ part, double *sh, double *sl) {
+    for (int r = threadIdx.x; r < R; r += kBlock) sl[r] = lam[r];
+    __syncthreads();
+    const int64_t n = rows * (int64_t)R;
+    const int64_t S = (int64_t)nb * kBlock;
+    int64_t e = (int64_t)b * kBlock + threadIdx.x;
+    int r = (int)(e % R);
+    const int dr = (int)(S % R);
+    double acc = 0.0;
+    for (; e < n; e += S) {
+        acc = fma(sl[r] * ld<T>(F, e), (double)X[e], acc);
+        r += dr;
+        if (r >= R) r -= R;
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[b] = acc;
+}
+
+__device__ void fit_finish_body(int R, const double *__restrict__ lam,
+                                const double *__restrict__ GA, const double *__restrict__ GB,
+                                const double *__restrict__ GC, const double *__restrict__ part,
+                                uint32_t npart, double normsq, double *__restrict__ fit,
+                                double *sh) {
+    double in = 0.0, xh = 0.0;
+    for (uint32_t b = threadIdx.x; b < npart; b += kBlock) in += part[b];
+    for (int e = threadIdx.x; e < R * R; e += kBlock) {
+        const int r = e / R, s = e % R;
+        xh += lam[r] * lam[s] * GA[e] * GB[e] * GC[e];
+    }
+    in = block_sum(in, sh);
+    xh = block_sum(xh, sh);
+    if (threadIdx.x == 0) {
+        double res2 = normsq + xh - 2.0 * in;
+        if (res2 < 0.0) res2 = 0.0;
+        *fit = normsq > 0.0 ? 1.0 - sqrt(res2) / sqrt(normsq) : 0.0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_wdot(const T *__restrict__ F,
+                                                 const float *__restrict__ X, int64_t rows, int R,
+                                                 const double *__restrict__ lam,
+                                                 double *__restrict__ part) {
+    __shared__ double sh[kBlock], sl[DFACTO_MAX_R];
+    wdot_body<T>(F, X, rows, R, lam, blockIdx.x, gridDim.x, part, sh, sl);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fit_finish(int R, const double *__restrict__ lam,
+                                                       const double *__restrict__ GA,
+                                                       const double *__restrict__ GB,
+                                                       const double *__restrict__ GC,
+                                                       const double *__restrict__ part,
+                                                       uint32_t npart, double normsq,
+                                                       double *__restrict__ fit) {
+    __shared__ double sh[kBlock];
+    fit_finish_body(R, lam, GA, GB, GC, part, npart, normsq, fit, sh);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_wdot_group(const FitJob *__restrict__ jobs,
+                                                       const uint2 *__restrict__ items) {
+    __shared__ double sh[kBlock], sl[DFACTO_MAX_R];
+    const uint2 v = items[blockIdx.x];
+    const FitJob &j = jobs[v.x];
+    wdot_body<T>((const T *)j.F, j.M, j.rows, j.R, j.lambda, v.y, j.nblk, j.part, sh, sl);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fit_finish_group(const FitJob *__restrict__ jobs) {
+    __shared__ double sh[kBlock];
+    const FitJob &j = jobs[blockIdx.x];
+    fit_finish_body(j.R, j.lambda, j.GA, j.GB, j.GC, j.part, j.nblk, j.normsq, j.fit, sh);
 }
 
 template <bool SMEM>
@@ -1928,6 +2015,41 @@ void launch_joint_combine(dfacto_ctx *ctx, float *G, const void *F, const float 
     else
         hipLaunchKernelGGL(k_joint_combine<uint16_t>, dim3(stream_grid(n)), dim3(kBlock), 0,
                            ctx->stream, G, (const uint16_t *)F, RY, mu, lam, n);
+    DF_LAUNCHED();
+}
+
+uint32_t fit_blocks(int64_t rows, int R) {
+    const int64_t n = rows * (int64_t)R;
+    return (uint32_t)std::min<int64_t>(64, std::max<int64_t>(1, (n + 16383) / 16384));
+}
+
+void launch_fit_stored(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, const float *M,
+                       int64_t rows, int R, const double *lambda, const double *GA,
+                       const double *GB, const double *GC, double normsq, double *part,
+                       double *fit) {
+    const uint32_t nb = fit_blocks(rows, R);
+    if (dtype == DFACTO_F32)
+        hipLaunchKernelGGL(k_wdot<float>, dim3(nb), dim3(kBlock), 0, ctx->stream,
+                           (const float *)F, M, rows, R, lambda, part);
+    else
+        hipLaunchKernelGGL(k_wdot<uint16_t>, dim3(nb), dim3(kBlock), 0, ctx->stream,
+                           (const uint16_t *)F, M, rows, R, lambda, part);
+    hipLaunchKernelGGL(k_fit_finish, dim3(1), dim3(kBlock), 0, ctx->stream, R, lambda, GA, GB, GC,
+                       part, nb, normsq, fit);
+    DF_LAUNCHED();
+}
+
+void launch_fit_group(dfacto_ctx *ctx, dfacto_dtype dtype, const FitJob *d_jobs, uint32_t n,
+                      const uint2 *d_items, uint32_t nitems) {
+    if (nitems > 0) {
+        if (dtype == DFACTO_F32)
+            hipLaunchKernelGGL(k_wdot_group<float>, dim3(nitems), dim3(kBlock), 0, ctx->stream,
+                               d_jobs, d_items);
+        else
+            hipLaunchKernelGGL(k_wdot_group<uint16_t>, dim3(nitems), dim3(kBlock), 0,
+                               ctx->stream, d_jobs, d_items);
+    }
+    hipLaunchKernelGGL(k_fit_finish_group, dim3(n), dim3(kBlock), 0, ctx->stream, d_jobs);
     DF_LAUNCHED();
 }
 

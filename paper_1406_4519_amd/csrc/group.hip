@@ -166,6 +166,7 @@ struct Expansion {
 // Per-member device workspace.
 struct MemberWs {
     float *M, *carry;
+    void *perm;  // permuted tables of a relabeled member (else null)
     double *G[3], *Hinv, *W, *MtM, *solve_scratch, *lam_scratch, *part;
     int *flag;
 };
@@ -254,6 +255,20 @@ struct Build {
         // MTTKRP + fix-ups, one launch each per kernel class
         {
             std::vector<GroupMttkrp> desc(n);
+            // relabeled members gather from copies of their factors in rank
+            // order, permuted before the MTTKRP on the group's stream
+            for (int t = 0; t < n; ++t) {
+                if (!ws[t].perm) continue;
+                const ModeData &md = T[t]->mode[m];
+                const dfacto_tensor *tt = T[t];
+                const int Rt = R[t];
+                const void *Fl = F[3 * t + md.leaf], *Fm = F[3 * t + md.mid];
+                void *buf = ws[t].perm;
+                grp->steps.push_back([grp, tt, m, Rt, dt, Fl, Fm, buf] {
+                    launch_relabeled_tables(&grp->gctx, tt, m, Rt, dt, Fl, Fm, buf);
+                });
+                g->launches += 2;
+            }
             struct Cls {
                 MttkrpShape sh;
                 bool small;
@@ -264,6 +279,8 @@ struct Build {
             for (int t = 0; t < n; ++t) {
                 const ModeData &md = T[t]->mode[m];
                 const void *Fl = F[3 * t + md.leaf], *Fm = F[3 * t + md.mid];
+                if (ws[t].perm && md.perm_leaf)
+                    relabeled_tables(T[t], m, R[t], dt, ws[t].perm, &Fl, &Fm);
                 desc[t] = {md.stream, md.chunk_start, (uint32_t)md.nchunk, R[t], Fl, Fm,
                            ws[t].M, ws[t].carry};
                 const MttkrpShape sh = mttkrp_shape(R[t], dt, Fl, Fm, ws[t].M);
@@ -347,11 +364,38 @@ struct Build {
                 ++g->launches;
             }
         }
-        // BF16 storage: later modes use the Gram of the stored factor
-        if (dt == DFACTO_BF16 && m < 2)
+        // BF16 storage: later modes use the Gram of the stored factor, and
+        // the fit is that of the stored factors
+        if (dt == DFACTO_BF16) {
             add_gram(
                 DFACTO_BF16, [&](int t) -> const void * { return F[3 * t + m]; },
                 [&](int t) { return T[t]->dims[m]; }, [&](int t) { return ws[t].G[m]; });
+            if (m == 2) add_fit();
+        }
+    }
+
+    // fit of the stored factors, every member: (member, block) partial sums
+    // of <C diag(lambda), M> into the member's Gram partial buffer (free
+    // again once the Gram above is reduced), then one block per member
+    void add_fit() {
+        dfacto_group *const grp = g;
+        const int n = grp->n;
+        std::vector<FitJob> jobs(n);
+        std::vector<uint2> items;
+        for (int t = 0; t < n; ++t) {
+            const int64_t rows = T[t]->dims[2];
+            const uint32_t nb = fit_blocks(rows, R[t]);
+            jobs[t] = {F[3 * t + 2], ws[t].M, rows, R[t], nb, lambda[t], ws[t].G[0],
+                       ws[t].G[1], ws[t].G[2], T[t]->normsq, ws[t].part, fit + t};
+            for (uint32_t b = 0; b < nb; ++b) items.push_back(make_uint2(t, b));
+        }
+        const FitJob *dj = upload(g, jobs);
+        const uint2 *di = upload(g, items);
+        const uint32_t ni = (uint32_t)items.size();
+        const dfacto_dtype dt = grp->dtype;
+        grp->steps.push_back(
+            [grp, dt, dj, n, di, ni] { launch_fit_group(&grp->gctx, dt, dj, (uint32_t)n, di, ni); });
+        g->launches += 2;
     }
 };
 
@@ -457,7 +501,7 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
             // MTTKRP output (largest mode), the carries (most chunks) and the
             // FP64 R x R block, each starting on a 256-byte boundary
             auto al = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
-            std::vector<size_t> off_M(n), off_carry(n), off_d(n);
+            std::vector<size_t> off_M(n), off_carry(n), off_d(n), off_p(n);
             size_t total = 0;
             for (int t = 0; t < n; ++t) {
                 const size_t RR = (size_t)R[t] * R[t];
@@ -469,6 +513,9 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
                 off_M[t] = total, total += al(4 * (size_t)dmax * R[t]);
                 off_carry[t] = total, total += al(4 * (size_t)cmax * R[t]);
                 off_d[t] = total, total += al(8 * (6 * RR + 3 * RR + (4 * RR + R[t]) + 256 * RR + 8));
+                const size_t pb = perm_bytes(T[t], R[t], dtype);
+                off_p[t] = pb ? total : 0;
+                total += al(pb);
             }
             char *base = dev_alloc<char>(g, total);
             for (int t = 0; t < n; ++t) {
@@ -476,6 +523,7 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
                 MemberWs &w = b.ws[t];
                 w.M = (float *)(base + off_M[t]);
                 w.carry = (float *)(base + off_carry[t]);
+                w.perm = off_p[t] ? base + off_p[t] : nullptr;
                 double *d = (double *)(base + off_d[t]);
                 size_t o = 0;
                 for (int m = 0; m < 3; ++m) w.G[m] = d + o, o += RR;

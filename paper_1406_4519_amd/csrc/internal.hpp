@@ -50,7 +50,19 @@ struct ModeData {
     int64_t nruns_long = 0;
     // host copies of the run lists (the sources of their uploads)
     std::vector<uint32_t> runs_short_host, runs_long_host;
+    // Relabeled gathers (null when the stream holds the original indices):
+    // the stream's leaf and mid indices are ranks in the order of decreasing
+    // gather count (nonzeros per leaf row, fiber headers per mid row; ties
+    // by index), so row r of a gathered table is factor row perm_*[r] and
+    // the most-gathered rows are the first ones.  top_*: gather counts of
+    // the first kTopRows ranks, for sizing the rows kept on chip.
+    uint32_t *perm_leaf = nullptr, *perm_mid = nullptr;
+    std::vector<uint32_t> top_leaf, top_mid;
 };
+constexpr int kTopRows = 16384;
+// dfacto_build_flattenings relabels the gathers of tensors from this size on
+constexpr int64_t kRelabelMinNnz = (int64_t)1 << 23;
+
 constexpr int kShortRun = 16;
 
 // MTTKRP kernel shape: CPL consecutive columns per lane, lane groups of G
@@ -82,6 +94,18 @@ struct LambdaJob {
     const double *GA, *GB;
     double normsq;
     double *fit, *scratch;
+};
+// The fit from a stored (rounded) last factor, per tensor.
+struct FitJob {
+    const void *F;    // stored mode-2 factor, rows x R
+    const float *M;   // its MTTKRP
+    int64_t rows;
+    int R;
+    uint32_t nblk;    // partial blocks (fit_blocks)
+    const double *lambda, *GA, *GB, *GC;
+    double normsq;
+    double *part;     // nblk partial sums
+    double *fit;
 };
 struct RowmapJob {
     const float *M;
@@ -149,6 +173,9 @@ struct dfacto_tensor {
     int64_t dims[3] = {0, 0, 0};
     int64_t nnz = 0;
     double normsq = 0.0;
+    bool relabel = false;  // build the streams with relabeled gathers
+    // host copies in flight during the build (top gather counts, as sort keys)
+    std::vector<std::pair<std::vector<uint64_t> *, std::vector<uint32_t> *>> pending_top;
     size_t bytes = 0;
     dfacto::ModeData mode[3];
     std::vector<void *> allocations;
@@ -178,9 +205,10 @@ struct dfacto_ctx {
     std::string err;
     // growable device workspace, one slot per purpose (Gram partial sums: one
     // slot per stream, so that Grams on the two streams may overlap)
-    enum Slot { kM = 0, kCarry, kPartial, kPartialSide, kSmall, kTrial, kJoint, kNumSlots };
+    enum Slot { kM = 0, kCarry, kPartial, kPartialSide, kSmall, kTrial, kJoint, kPerm, kNumSlots };
     void *ws[kNumSlots] = {};
     size_t ws_size[kNumSlots] = {};
+    bool frozen = false;  // dfacto_ctx_freeze: workspaces may not grow
     // kernel timing (dfacto_profile_*)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;  // created on demand, reused
@@ -230,6 +258,15 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
                   const uint32_t *d_k, const float *d_val);
 
 // MTTKRP (mttkrp.hip)
+// Device bytes of the permuted copies a relabeled tensor's MTTKRPs gather
+// from (0 when not relabeled), the largest over the modes.
+size_t perm_bytes(const dfacto_tensor *t, int R, dfacto_dtype dtype);
+// A relabeled mode's permuted tables in `buf` (perm_bytes): their places,
+// and the launches that fill them from the factors (on ctx's stream).
+void relabeled_tables(const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype, void *buf,
+                      const void **leaf, const void **mid);
+void launch_relabeled_tables(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                             dfacto_dtype dtype, const void *Fleaf, const void *Fmid, void *buf);
 void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype,
                    const void *Fleaf, const void *Fmid, float *out);
 // The same with the carries in `carry` (nchunk x R floats of the caller's)
@@ -238,10 +275,23 @@ void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfa
 void launch_mttkrp_split(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
                          dfacto_dtype dtype, const void *Fleaf, const void *Fmid, float *out,
                          float *carry, hipStream_t fix, hipEvent_t ev);
+// Buffers of one MTTKRP when the caller provides them: returns the bytes
+// of the permuted tables (0 when not relabeled), *carry_bytes the carries'.
+size_t mttkrp_buffers(const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype,
+                      size_t *carry_bytes);
+// launch_mttkrp with the caller's carries (carry_bytes) and permuted-table
+// buffer (or null when not relabeled): takes no workspace of the context.
+void launch_mttkrp_in(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                      dfacto_dtype dtype, const void *Fleaf, const void *Fmid, float *out,
+                      float *carry, void *perm);
 // residual MTTKRP over the stored entries (value x - sum_r root*mid*leaf)
 void launch_mttkrp_resid(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
                          dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
                          const void *Froot, float *out);
+// the main kernel's requests without its arithmetic (dfacto_gather_probe)
+void launch_gather_probe(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                         dfacto_dtype dtype, const void *Fleaf, const void *Fmid, int pattern,
+                         float *sink);
 MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
                          const float *out);
 bool mttkrp_small(const dfacto_tensor *t, int mode);
@@ -289,6 +339,17 @@ void launch_joint_rows(dfacto_ctx *ctx, const dfacto_tensor *Y, int m, int64_t n
                        const int *pflag, void *out, dfacto_dtype dtype, int *flag, double *part);
 void launch_joint_combine(dfacto_ctx *ctx, float *G, const void *F, const float *RY, double mu,
                           double lam, int64_t n, dfacto_dtype dtype);
+// fit = 1 - sqrt(max(0, ||X||^2 + lambda^T (GA*GB*GC) lambda - 2 <C diag(lambda), M>)) / ||X||
+// from the stored factor C (rows x R) and its MTTKRP M; part: fit_blocks doubles
+uint32_t fit_blocks(int64_t rows, int R);
+void launch_fit_stored(dfacto_ctx *ctx, const void *F, dfacto_dtype dtype, const float *M,
+                       int64_t rows, int R, const double *lambda, const double *GA,
+                       const double *GB, const double *GC, double normsq, double *part,
+                       double *fit);
+// the same for every member of a group: (member, block) items, then one
+// finishing block per member
+void launch_fit_group(dfacto_ctx *ctx, dfacto_dtype dtype, const FitJob *d_jobs, uint32_t n,
+                      const uint2 *d_items, uint32_t nitems);
 void launch_dot_parts(dfacto_ctx *ctx, const void *F, const float *X, int64_t n, double *part,
                       dfacto_dtype dtype);
 void launch_joint_f(dfacto_ctx *ctx, const double *ft, const double *GA, const double *GB,

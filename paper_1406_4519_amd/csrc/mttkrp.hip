@@ -34,7 +34,7 @@ namespace {
 #define DFACTO_UNROLL 8
 #endif
 #ifndef DFACTO_MAX_CPL
-#define DFACTO_MAX_CPL 4
+#define DFACTO_MAX_CPL 8
 #endif
 #ifndef DFACTO_NT_STREAM
 #define DFACTO_NT_STREAM 0
@@ -48,7 +48,10 @@ namespace {
 #ifndef DFACTO_WAVES_PER_EU
 #define DFACTO_WAVES_PER_EU 5
 #endif
-#define MTTKRP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(G <= 32 ? DFACTO_WAVES_PER_EU : 1)))
+// Eight columns per lane hold twice the gathered data per batch: 4 waves
+// per SIMD (128 registers) keep them out of scratch.
+#define MTTKRP_OCCUPANCY                                                               \
+    __attribute__((amdgpu_waves_per_eu(G <= 32 ? (CPL >= 8 ? 4 : DFACTO_WAVES_PER_EU) : 1)))
 
 constexpr int kBlock = 256;
 constexpr int kUnroll = DFACTO_UNROLL;  // stream entries in flight per group
@@ -157,21 +160,125 @@ __device__ __forceinline__ void load_f32(const float *p, float (&v)[CPL]) {
     RowLoad<float, CPL>::load(p, v);
 }
 
-// ---- main kernel ---------------------------------------------------------
+// ---- factor-row sources ------------------------------------------------------
+// load(w, c, v): the row that stream entry w gathers -- the leaf row for a
+// nonzero, the mid row for a header -- columns of block c (CPL per lane),
+// widened to FP32.  Lanes whose columns lie beyond R read column 0 instead
+// (in bounds, never stored), so every gather is issued without a branch and
+// the loads of a batch stay in flight together.
 // SMALL: every row index is below 2^24, so row offsets are one 24-bit
 // multiply (idx * R < 2^32) instead of 64-bit arithmetic.
-// One work chunk (gid) per lane group of G lanes (lane = 0 .. G-1).
+
+// Rows straight from the two factor tables in device memory.
+template <typename T, int CPL, int NCH, bool SMALL>
+struct GlobalRows {
+    const T *leafb[NCH], *midb[NCH];
+    int R;
+    __device__ __forceinline__ GlobalRows(const T *Fleaf, const T *Fmid, int R_, int G, int lane)
+        : R(R_) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int col = (c * G + lane) * CPL;
+            leafb[c] = Fleaf + (col < R ? col : 0);
+            midb[c] = Fmid + (col < R ? col : 0);
+        }
+    }
+    __device__ __forceinline__ size_t off(uint32_t idx) const {
+        if constexpr (SMALL) return (size_t)(uint32_t)__umul24(idx, (uint32_t)R);
+        else return (size_t)idx * (size_t)R;
+    }
+    __device__ __forceinline__ void load(const uint2 &w, int c, float (&v)[CPL]) const {
+        const bool hdr = (int32_t)w.x < 0;  // kHdrBit is the sign bit
+        RowLoad<T, CPL>::load((hdr ? midb[c] : leafb[c]) + off(w.x & kIdxMask), v);
+    }
+};
+
+// CPL elements of T at byte offset `off` of a buffer resource; an offset
+// past the buffer's end loads zeros and makes no memory request.
+template <typename T, int CPL>
+struct BufLoad;
+template <>
+struct BufLoad<float, 4> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                float (&v)[4]) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        v[0] = __uint_as_float(x[0]); v[1] = __uint_as_float(x[1]);
+        v[2] = __uint_as_float(x[2]); v[3] = __uint_as_float(x[3]);
+    }
+};
+template <>
+struct BufLoad<float, 2> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                float (&v)[2]) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        v[0] = __uint_as_float(x[0]); v[1] = __uint_as_float(x[1]);
+    }
+};
+template <>
+struct BufLoad<float, 1> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                float (&v)[1]) {
+        v[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+};
+template <>
+struct BufLoad<float, 8> {  // two 16-byte loads
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                float (&v)[8]) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const auto y = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0);
+        v[0] = __uint_as_float(x[0]); v[1] = __uint_as_float(x[1]);
+        v[2] = __uint_as_float(x[2]); v[3] = __uint_as_float(x[3]);
+        v[4] = __uint_as_float(y[0]); v[5] = __uint_as_float(y[1]);
+        v[6] = __uint_as_float(y[2]); v[7] = __uint_as_float(y[3]);
+    }
+};
+template <>
+struct BufLoad<uint16_t, 8> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                float (&v)[8]) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        v[0] = bf16_lo(x[0]); v[1] = bf16_hi(x[0]); v[2] = bf16_lo(x[1]); v[3] = bf16_hi(x[1]);
+        v[4] = bf16_lo(x[2]); v[5] = bf16_hi(x[2]); v[6] = bf16_lo(x[3]); v[7] = bf16_hi(x[3]);
+    }
+};
+template <>
+struct BufLoad<uint16_t, 4> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                float (&v)[4]) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        v[0] = bf16_lo(x[0]); v[1] = bf16_hi(x[0]); v[2] = bf16_lo(x[1]); v[3] = bf16_hi(x[1]);
+    }
+};
+template <>
+struct BufLoad<uint16_t, 2> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                float (&v)[2]) {
+        const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        v[0] = bf16_lo(x); v[1] = bf16_hi(x);
+    }
+};
+template <>
+struct BufLoad<uint16_t, 1> {
+    static __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                float (&v)[1]) {
+        v[0] = __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0) << 16);
+    }
+};
+
+// ---- main kernel ---------------------------------------------------------
+// One work chunk (gid) per lane group of G lanes (lane = 0 .. G-1), its
+// factor rows from `src`.
 // RES: the residual form used by the joint model's ratings term: each
 // nonzero's value x becomes x - xhat with xhat = sum_r F_root[root, r]
 // F_mid[mid, r] F_leaf[leaf, r] (the CP model at that entry), so the output
 // is the MTTKRP of the residual restricted to the stored entries.  The dot
 // product is reduced across the group's lanes by xor shuffles (every lane
 // ends with the same sum: each step adds two commuted operands).
-template <typename T, int CPL, int G, int NCH, bool SMALL, bool RES = false>
+template <typename T, int CPL, int G, int NCH, bool SMALL, bool RES = false, class Src>
 __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
                                              const uint32_t *__restrict__ cstart, uint32_t nchunk,
-                                             const T *__restrict__ Fleaf,
-                                             const T *__restrict__ Fmid, int R,
+                                             const Src &src, int R,
                                              float *__restrict__ out, float *__restrict__ carry,
                                              uint32_t gid, int lane,
                                              const T *__restrict__ Froot = nullptr) {
@@ -179,25 +286,19 @@ __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
     const uint32_t cs = cstart[gid], ce = cstart[gid + 1];
     if (cs >= ce) return;
 
-    // Per-lane row bases.  Lanes whose columns lie beyond R read column 0
-    // instead (in bounds, never stored), so every gather is issued without a
-    // branch and the loads of a batch stay in flight together.
     int col[NCH];
     bool act[NCH];
-    const T *leafb[NCH], *midb[NCH], *rootb[NCH];
+    const T *rootb[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         col[c] = (c * G + lane) * CPL;
         act[c] = col[c] < R;
-        leafb[c] = Fleaf + (act[c] ? col[c] : 0);
-        midb[c] = Fmid + (act[c] ? col[c] : 0);
         rootb[c] = RES ? Froot + (act[c] ? col[c] : 0) : nullptr;
     }
     auto row_off = [&](uint32_t idx) -> size_t {
         if constexpr (SMALL) return (size_t)(uint32_t)__umul24(idx, (uint32_t)R);
         else return (size_t)idx * (size_t)R;
     };
-
     float acc[NCH][CPL], p[NCH][CPL], mrow[NCH][CPL];
     float rrow[RES ? NCH : 1][CPL];  // the root's factor row (RES only)
     const uint2 h0 = st[cs];
@@ -207,7 +308,7 @@ __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
     for (int c = 0; c < NCH; ++c) {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) acc[c][q] = p[c][q] = 0.f;
-        RowLoad<T, CPL>::load(midb[c] + row_off(h0.x & kIdxMask), mrow[c]);
+        src.load(h0, c, mrow[c]);  // h0 is a header: its mid row
         if constexpr (RES) RowLoad<T, CPL>::load(rootb[c] + row_off(row), rrow[c]);
     }
 
@@ -226,13 +327,9 @@ __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
     // are in bounds; their values are ignored.
     auto gather = [&](const uint2 (&w)[kUnroll], float (&g)[kUnroll][NCH][CPL]) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const bool hdr = (int32_t)w[u].x < 0;  // kHdrBit is the sign bit
-            const size_t off = row_off(w[u].x & kIdxMask);
+        for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                RowLoad<T, CPL>::load((hdr ? midb[c] : leafb[c]) + off, g[u][c]);
-        }
+            for (int c = 0; c < NCH; ++c) src.load(w[u], c, g[u][c]);
     };
     // One stream entry, without data-dependent branches except the (rarer)
     // write of a finished output row.  A header closes the fiber segment --
@@ -340,9 +437,10 @@ __global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_mttkrp(
     const uint2 *__restrict__ st, const uint32_t *__restrict__ cstart, uint32_t nchunk,
     const T *__restrict__ Fleaf, const T *__restrict__ Fmid, int R, float *__restrict__ out,
     float *__restrict__ carry) {
-    mttkrp_chunk<T, CPL, G, NCH, SMALL>(st, cstart, nchunk, Fleaf, Fmid, R, out, carry,
-                                        (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G,
-                                        threadIdx.x % G);
+    const int lane = threadIdx.x % G;
+    const GlobalRows<T, CPL, NCH, SMALL> src(Fleaf, Fmid, R, G, lane);
+    mttkrp_chunk<T, CPL, G, NCH, SMALL>(st, cstart, nchunk, src, R, out, carry,
+                                        (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G, lane);
 }
 
 template <typename T, int CPL, int G, int NCH, bool SMALL>
@@ -350,9 +448,11 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_res(
     const uint2 *__restrict__ st, const uint32_t *__restrict__ cstart, uint32_t nchunk,
     const T *__restrict__ Fleaf, const T *__restrict__ Fmid, const T *__restrict__ Froot, int R,
     float *__restrict__ out, float *__restrict__ carry) {
-    mttkrp_chunk<T, CPL, G, NCH, SMALL, true>(st, cstart, nchunk, Fleaf, Fmid, R, out, carry,
+    const int lane = threadIdx.x % G;
+    const GlobalRows<T, CPL, NCH, SMALL> src(Fleaf, Fmid, R, G, lane);
+    mttkrp_chunk<T, CPL, G, NCH, SMALL, true>(st, cstart, nchunk, src, R, out, carry,
                                               (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G,
-                                              threadIdx.x % G, Froot);
+                                              lane, Froot);
 }
 
 // Grouped MTTKRP over many tensors of one kernel shape: a persistent grid
@@ -361,13 +461,163 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_res(
 template <typename T, int CPL, int G, int NCH, bool SMALL>
 __global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_mttkrp_group(
     const GroupMttkrp *__restrict__ desc, const uint2 *__restrict__ items, uint32_t nitems) {
+    const int lane = threadIdx.x % G;
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const uint2 w = items[it];
         const GroupMttkrp &d = desc[w.x];
-        mttkrp_chunk<T, CPL, G, NCH, SMALL>(d.stream, d.chunk_start, d.nchunk,
-                                            (const T *)d.Fleaf, (const T *)d.Fmid, d.R, d.out,
-                                            d.carry, w.y + threadIdx.x / G, threadIdx.x % G);
+        const GlobalRows<T, CPL, NCH, SMALL> src((const T *)d.Fleaf, (const T *)d.Fmid, d.R, G,
+                                                 lane);
+        mttkrp_chunk<T, CPL, G, NCH, SMALL>(d.stream, d.chunk_start, d.nchunk, src, d.R, d.out,
+                                            d.carry, w.y + threadIdx.x / G, lane);
     }
+}
+
+// ---- gather ceiling --------------------------------------------------------
+// The main kernel's memory requests without its arithmetic: the same work
+// chunks, lane groups, batches of kUnroll entries (shared through
+// ds_swizzle) and row loads, but every gathered row is only summed.  PAT
+// selects the row that an entry gathers:
+//   0  the entry's own row (leaf for a nonzero, mid for a header): the
+//      MTTKRP's exact request sequence;
+//   1  a row drawn uniformly from the same table (hash of the position);
+//   2  a row among the table's first 4096 (a working set that stays in L2);
+//   3  none: the stream is read, nothing is gathered.
+// Each lane writes its sum to sink[gid * G + lane], so nothing is elided.
+__device__ __forceinline__ uint32_t probe_hash(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+constexpr int kProbeLdsRows = 128, kProbeLdsRowElems = 64;
+
+template <typename T, int CPL, int G, bool SMALL, int PAT>
+__global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_gather_probe(
+    const uint2 *__restrict__ st, const uint32_t *__restrict__ cstart, uint32_t nchunk,
+    const T *__restrict__ Fleaf, const T *__restrict__ Fmid, int R, uint32_t nleaf,
+    uint32_t nmid, float *__restrict__ sink) {
+    const uint32_t gid0 = (blockIdx.x * (uint32_t)kBlock + threadIdx.x) / G;
+    const int lane = threadIdx.x % G;
+    // groups past the last chunk walk an empty range (they still take part
+    // in the block's barrier)
+    const uint32_t gid = gid0 < nchunk ? gid0 : nchunk;
+    const uint32_t cs = cstart[gid], ce = gid0 < nchunk ? cstart[gid + 1] : cs;
+    const int col = lane * CPL;
+    const bool act = col < R;
+    const T *leafb = Fleaf + (act ? col : 0), *midb = Fmid + (act ? col : 0);
+    auto row_off = [&](uint32_t idx) -> size_t {
+        if constexpr (SMALL) return (size_t)(uint32_t)__umul24(idx, (uint32_t)R);
+        else return (size_t)idx * (size_t)R;
+    };
+    float acc[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) acc[q] = 0.f;
+    // PAT 5, 8, 9: rows read from an LDS table (kProbeLdsRows rows)
+    constexpr bool kLds = PAT == 5 || PAT == 8 || PAT == 9;
+    __shared__ T lds_rows[kLds ? kProbeLdsRows * kProbeLdsRowElems : 1];
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)Fleaf, (short)0, (int)((uint64_t)nleaf * R * sizeof(T) < 0xFFFFFF00ull
+                                            ? (uint64_t)nleaf * R * sizeof(T)
+                                            : 0xFFFFFF00ull),
+        0x00020000);
+    if constexpr (kLds) {
+        const uint64_t have = (uint64_t)nleaf * (uint64_t)R;
+        const uint32_t nfill = have < (uint64_t)kProbeLdsRowElems ? (uint32_t)have
+                                                                   : (uint32_t)kProbeLdsRowElems;
+        for (int x = threadIdx.x; x < kProbeLdsRows * kProbeLdsRowElems; x += kBlock)
+            lds_rows[x] = Fleaf[(uint32_t)x % nfill];
+        __syncthreads();
+    }
+    constexpr bool kShare = G <= 32 && DFACTO_SHARE_ENTRIES;
+    constexpr int KL = kShare ? (kUnroll + G - 1) / G : kUnroll;
+    auto load_batch = [&](uint32_t at, uint2 (&wl)[KL]) {
+#pragma unroll
+        for (int k = 0; k < KL; ++k)
+            wl[k] = kShare ? load_entry(st + at + lane + G * k) : load_entry(st + at + k);
+    };
+    auto expand = [&](const uint2 (&wl)[KL], uint2 (&w)[kUnroll]) {
+        static_for<0, kUnroll>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            if constexpr (kShare) {
+                constexpr int pat = (0x1F & ~(G - 1)) | ((u % G) << 5);
+                w[u].x = (uint32_t)__builtin_amdgcn_ds_swizzle((int)wl[u / G].x, pat);
+                w[u].y = (uint32_t)__builtin_amdgcn_ds_swizzle((int)wl[u / G].y, pat);
+            } else {
+                w[u] = wl[u];
+            }
+        });
+    };
+    uint2 wn[KL];
+    load_batch(cs, wn);
+    for (uint32_t e = cs; e < ce; e += kUnroll) {
+        uint2 w[kUnroll];
+        expand(wn, w);
+        load_batch(e + kUnroll, wn);
+        float g[kUnroll][CPL];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const bool hdr = (int32_t)w[u].x < 0;
+            if constexpr (PAT == 3) {
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) g[u][q] = __uint_as_float(w[u].y & 0x3F7FFFFFu);
+            } else if constexpr (PAT == 5) {
+                const uint32_t h = probe_hash(e + u) & (kProbeLdsRows - 1);
+                RowLoad<T, CPL>::load(lds_rows + h * (kProbeLdsRowElems) + (act ? col : 0), g[u]);
+            } else if constexpr (PAT >= 6) {
+                // buffer loads of leaf rows: 6 every offset out of range; 7 the
+                // entry's own row (mid index taken modulo the leaf rows); 8 half
+                // of the entries (a hash bit) from the LDS table, the other
+                // half own rows, split by a branch; 9 the same half split
+                // without a branch (out-of-range buffer load + LDS row 0)
+                const uint32_t idx = (w[u].x & kIdxMask) % nleaf;
+                const uint32_t boff = (uint32_t)(idx * (uint32_t)R + (act ? col : 0)) * sizeof(T);
+                const bool lhot = (probe_hash(e + u) & 1u) != 0;
+                const uint32_t h = probe_hash(e + u) >> 25;  // < 128 rows
+                if constexpr (PAT == 6) {
+                    BufLoad<T, CPL>::load(rsrc, 0xFFFFFF00u, g[u]);
+                } else if constexpr (PAT == 7) {
+                    BufLoad<T, CPL>::load(rsrc, boff, g[u]);
+                } else if constexpr (PAT == 8) {
+                    if (lhot)
+                        RowLoad<T, CPL>::load(lds_rows + h * kProbeLdsRowElems + (act ? col : 0),
+                                              g[u]);
+                    else
+                        BufLoad<T, CPL>::load(rsrc, boff, g[u]);
+                } else {
+                    float gv[CPL], lv[CPL];
+                    BufLoad<T, CPL>::load(rsrc, lhot ? 0xFFFFFF00u : boff, gv);
+                    RowLoad<T, CPL>::load(lds_rows + (lhot ? h : 0u) * kProbeLdsRowElems +
+                                              (act ? col : 0),
+                                          lv);
+#pragma unroll
+                    for (int q = 0; q < CPL; ++q) g[u][q] = lhot ? lv[q] : gv[q];
+                }
+            } else {
+                uint32_t idx;
+                if constexpr (PAT == 0) {
+                    idx = w[u].x & kIdxMask;
+                } else {
+                    const uint32_t n = hdr ? nmid : nleaf;
+                    const uint32_t h = probe_hash(e + u);
+                    const uint32_t lim = PAT == 2 ? 4096u : 32u;
+                    idx = PAT == 1 ? (uint32_t)(((uint64_t)h * n) >> 32)
+                                   : (h & (lim - 1)) % (n < lim ? n : lim);
+                }
+                RowLoad<T, CPL>::load((hdr ? midb : leafb) + row_off(idx), g[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) acc[q] += (e + u < ce) ? g[u][q] : 0.f;
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) s += acc[q];
+    if (gid0 < nchunk) sink[(size_t)gid * G + lane] = s;
 }
 
 // ---- fix-up: carries of split rows, and empty rows ------------------------
@@ -552,6 +802,27 @@ __global__ __launch_bounds__(kLongBlock) void k_fix_long_group(const GroupMttkrp
     long_run<CPL, G, NCH>(d.carry, d.R, d.out, r.y, r.z, r.w);
 }
 
+// ---- relabeled tables ------------------------------------------------------
+// out[r] = in[perm[r]], rows of vr elements of V (a row of R factor entries
+// in 16-, 8-, 4- or 2-byte pieces)
+template <typename V, bool WIDE>
+__global__ __launch_bounds__(256) void k_permute_rows(const V *__restrict__ in,
+                                                      const uint32_t *__restrict__ perm,
+                                                      int64_t rows, int vr, V *__restrict__ out) {
+    const int64_t n = rows * vr;
+    for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        int64_t r, c;
+        if constexpr (WIDE) {
+            r = e / vr;
+            c = e - r * vr;
+        } else {
+            r = (uint32_t)e / (uint32_t)vr;
+            c = (uint32_t)e - (uint32_t)r * (uint32_t)vr;
+        }
+        out[e] = in[(int64_t)perm[r] * vr + c];
+    }
+}
+
 // ---- dispatch --------------------------------------------------------------
 template <int V>
 using IntC = std::integral_constant<int, V>;
@@ -597,43 +868,47 @@ void with_shape(dfacto_dtype dtype, const MttkrpShape &sh, F &&f) {
     else by_cpl(TypeC<uint16_t>{});
 }
 
+// The tables the main kernel gathers from.
+struct Tables {
+    const void *leaf = nullptr, *mid = nullptr;
+};
+
 template <typename T, int CPL, int G, int NCH>
 // fix/ev: when set, the carry fix-ups go to stream `fix`, ordered after the
 // main kernel by `ev` recorded on ctx's stream; carry_in: the carries' buffer
 // (else the context's carry workspace)
-void run(dfacto_ctx *ctx, const ModeData &md, int R, const void *Fleaf, const void *Fmid,
-         float *out, bool small, const void *Froot = nullptr, float *carry_in = nullptr,
-         hipStream_t fix = nullptr, hipEvent_t ev = nullptr) {
+void run(dfacto_ctx *ctx, const ModeData &md, int R, const Tables &tb, float *out, bool small,
+         const void *Froot = nullptr, float *carry_in = nullptr, hipStream_t fix = nullptr,
+         hipEvent_t ev = nullptr) {
     hipStream_t s = ctx->stream;
     const uint32_t nchunk = (uint32_t)md.nchunk;
     float *carry = carry_in ? carry_in
                             : (float *)ws_get(ctx, dfacto_ctx::kCarry,
                                               sizeof(float) *
                                                   (size_t)std::max<int64_t>(md.nchunk, 1) * R);
+    const T *Fleaf = (const T *)tb.leaf, *Fmid = (const T *)tb.mid;
     constexpr int gpb = kBlock / G;  // groups per block
     if (nchunk > 0) {
         const unsigned blocks = (nchunk + gpb - 1) / gpb;
         if (Froot) {
             if (small)
                 hipLaunchKernelGGL((k_mttkrp_res<T, CPL, G, NCH, true>), dim3(blocks),
-                                   dim3(kBlock), 0, s, md.stream, md.chunk_start, nchunk,
-                                   (const T *)Fleaf, (const T *)Fmid, (const T *)Froot, R, out,
-                                   carry);
+                                   dim3(kBlock), 0, s, md.stream, md.chunk_start, nchunk, Fleaf,
+                                   Fmid, (const T *)Froot, R, out, carry);
             else
                 hipLaunchKernelGGL((k_mttkrp_res<T, CPL, G, NCH, false>), dim3(blocks),
-                                   dim3(kBlock), 0, s, md.stream, md.chunk_start, nchunk,
-                                   (const T *)Fleaf, (const T *)Fmid, (const T *)Froot, R, out,
-                                   carry);
+                                   dim3(kBlock), 0, s, md.stream, md.chunk_start, nchunk, Fleaf,
+                                   Fmid, (const T *)Froot, R, out, carry);
         } else {
             prof_mark(ctx);
             if (small)
                 hipLaunchKernelGGL((k_mttkrp<T, CPL, G, NCH, true>), dim3(blocks), dim3(kBlock),
-                                   0, s, md.stream, md.chunk_start, nchunk, (const T *)Fleaf,
-                                   (const T *)Fmid, R, out, carry);
+                                   0, s, md.stream, md.chunk_start, nchunk, Fleaf, Fmid, R, out,
+                                   carry);
             else
                 hipLaunchKernelGGL((k_mttkrp<T, CPL, G, NCH, false>), dim3(blocks), dim3(kBlock),
-                                   0, s, md.stream, md.chunk_start, nchunk, (const T *)Fleaf,
-                                   (const T *)Fmid, R, out, carry);
+                                   0, s, md.stream, md.chunk_start, nchunk, Fleaf, Fmid, R, out,
+                                   carry);
             prof_mark(ctx);
         }
     }
@@ -646,16 +921,108 @@ void run(dfacto_ctx *ctx, const ModeData &md, int R, const void *Fleaf, const vo
     const uint32_t egroups = nempty == 0 ? 0u : std::min<uint32_t>(nempty, 65536u);
     const uint64_t groups = (uint64_t)md.nruns_short + egroups;
     constexpr int gpl = kLongBlock / G;  // lane groups per fix-up block
-    const uint64_t blocks = (uint64_t)md.nruns_long + (groups + gpl - 1) / gpl;
-    if (blocks > 0)
-        hipLaunchKernelGGL((k_fix<CPL, G, NCH>), dim3((unsigned)blocks), dim3(kLongBlock), 0, s,
+    const uint64_t fblocks = (uint64_t)md.nruns_long + (groups + gpl - 1) / gpl;
+    if (fblocks > 0)
+        hipLaunchKernelGGL((k_fix<CPL, G, NCH>), dim3((unsigned)fblocks), dim3(kLongBlock), 0, s,
                            md.runs_long, (uint32_t)md.nruns_long, md.runs_short,
                            (uint32_t)md.nruns_short, carry, R, out, md.empty_rows, nempty,
                            egroups);
     DF_LAUNCHED();
 }
 
+// Byte offset of the mid table after `rows` leaf rows of `rowb` bytes: a
+// whole number of rows that is a multiple of 256 bytes.
+size_t mid_offset(int64_t rows, size_t rowb) {
+    size_t g = 256, b = rowb;  // gcd(rowb, 256)
+    while (b) {
+        const size_t r = g % b;
+        g = b;
+        b = r;
+    }
+    const size_t m = 256 / g;  // rows per 256-byte multiple
+    return ((size_t)rows + m - 1) / m * m * rowb;
+}
+
+// rows x R entries of dtype from F into `out` in the order of perm
+void launch_permute(dfacto_ctx *ctx, const void *F, const uint32_t *perm, int64_t rows, int R,
+                    dfacto_dtype dtype, void *out) {
+    if (rows <= 0) return;
+    const size_t rowb = (size_t)R * elem_size(dtype);
+    auto al = [&](size_t a) {
+        return rowb % a == 0 && (uintptr_t)F % a == 0 && (uintptr_t)out % a == 0;
+    };
+    auto go = [&](auto vt, size_t vb) {
+        using V = typename decltype(vt)::type;
+        const int vr = (int)(rowb / vb);
+        const int64_t n = rows * vr;
+        const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+        if (n < ((int64_t)1 << 32))
+            hipLaunchKernelGGL((k_permute_rows<V, false>), dim3(grid), dim3(256), 0, ctx->stream,
+                               (const V *)F, perm, rows, vr, (V *)out);
+        else
+            hipLaunchKernelGGL((k_permute_rows<V, true>), dim3(grid), dim3(256), 0, ctx->stream,
+                               (const V *)F, perm, rows, vr, (V *)out);
+    };
+    if (al(16)) go(TypeC<uint4>{}, 16);
+    else if (al(8)) go(TypeC<uint2>{}, 8);
+    else if (al(4)) go(TypeC<uint32_t>{}, 4);
+    else go(TypeC<uint16_t>{}, 2);
+    DF_LAUNCHED();
+}
+
+// The tables a mode's main kernel gathers from: the factors themselves, or
+// for a relabeled mode copies permuted into rank order -- the leaf table,
+// then the mid table (mid_offset), in the context's permutation workspace
+// or in `buf`.
+Tables gather_tables(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype,
+                     const void *Fleaf, const void *Fmid, void *buf = nullptr) {
+    const ModeData &md = t->mode[mode];
+    Tables tb;
+    if (!md.perm_leaf) {
+        tb.leaf = Fleaf;
+        tb.mid = Fmid;
+        return tb;
+    }
+    const int64_t dl = t->dims[md.leaf], dm = t->dims[md.mid];
+    const size_t es = elem_size(dtype);
+    const size_t off_mid = mid_offset(dl, (size_t)R * es);
+    const size_t total = off_mid + (size_t)dm * R * es;
+    char *w = buf ? (char *)buf : (char *)ws_get(ctx, dfacto_ctx::kPerm, total);
+    launch_permute(ctx, Fleaf, md.perm_leaf, dl, R, dtype, w);
+    launch_permute(ctx, Fmid, md.perm_mid, dm, R, dtype, w + off_mid);
+    tb.leaf = w;
+    tb.mid = w + off_mid;
+    return tb;
+}
+
 }  // namespace
+
+void relabeled_tables(const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype, void *buf,
+                      const void **leaf, const void **mid) {
+    const ModeData &md = t->mode[mode];
+    *leaf = buf;
+    *mid = (char *)buf + mid_offset(t->dims[md.leaf], (size_t)R * elem_size(dtype));
+}
+
+void launch_relabeled_tables(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                             dfacto_dtype dtype, const void *Fleaf, const void *Fmid, void *buf) {
+    const ModeData &md = t->mode[mode];
+    const void *l, *m;
+    relabeled_tables(t, mode, R, dtype, buf, &l, &m);
+    launch_permute(ctx, Fleaf, md.perm_leaf, t->dims[md.leaf], R, dtype, (void *)l);
+    launch_permute(ctx, Fmid, md.perm_mid, t->dims[md.mid], R, dtype, (void *)m);
+}
+
+size_t perm_bytes(const dfacto_tensor *t, int R, dfacto_dtype dtype) {
+    size_t b = 0;
+    const size_t rowb = (size_t)R * elem_size(dtype);
+    for (int m = 0; m < 3; ++m) {
+        const ModeData &md = t->mode[m];
+        if (!md.perm_leaf) continue;
+        b = std::max(b, mid_offset(t->dims[md.leaf], rowb) + (size_t)t->dims[md.mid] * rowb);
+    }
+    return b;
+}
 
 MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
                          const float *out) {
@@ -666,7 +1033,10 @@ MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const voi
     };
     const bool aligned8 = al(8 * es), aligned4 = al(4 * es), aligned2 = al(2 * es);
     int cpl = 1;
-    if (R % 8 == 0 && aligned8 && DFACTO_MAX_CPL >= 8) cpl = 8;
+    // Eight columns per lane only for BF16 (one 16-byte load per lane): a
+    // gather instruction then fetches 16 rows of 64 bytes instead of 8.  For
+    // FP32 eight columns are two loads per lane, no fewer instructions.
+    if (dtype == DFACTO_BF16 && R % 8 == 0 && aligned8 && DFACTO_MAX_CPL >= 8) cpl = 8;
     else if (R % 4 == 0 && aligned4 && DFACTO_MAX_CPL >= 4) cpl = 4;
     else if (R % 2 == 0 && aligned2 && DFACTO_MAX_CPL >= 2) cpl = 2;
     const int lanes = (R + cpl - 1) / cpl;
@@ -700,10 +1070,36 @@ void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfa
     }
     const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out);
     const bool sm = mttkrp_small(t, mode);
+    const Tables tb = gather_tables(ctx, t, mode, R, dtype, Fleaf, Fmid);
     with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
         using T = typename decltype(tc)::type;
-        run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(
-            ctx, md, R, Fleaf, Fmid, out, sm);
+        run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(ctx, md, R, tb,
+                                                                                 out, sm);
+    });
+}
+
+size_t mttkrp_buffers(const dfacto_tensor *t, int mode, int R, dfacto_dtype dtype,
+                      size_t *carry_bytes) {
+    const ModeData &md = t->mode[mode];
+    *carry_bytes = (sizeof(float) * (size_t)std::max<int64_t>(md.nchunk, 1) * R + 255) &
+                   ~(size_t)255;
+    if (!md.perm_leaf) return 0;
+    const size_t rowb = (size_t)R * elem_size(dtype);
+    return mid_offset(t->dims[md.leaf], rowb) + (size_t)t->dims[md.mid] * rowb;
+}
+
+void launch_mttkrp_in(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                      dfacto_dtype dtype, const void *Fleaf, const void *Fmid, float *out,
+                      float *carry, void *perm) {
+    const ModeData &md = t->mode[mode];
+    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out);
+    const bool sm = mttkrp_small(t, mode);
+    const Tables tb = gather_tables(ctx, t, mode, R, dtype, Fleaf, Fmid, perm);
+    with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
+        using T = typename decltype(tc)::type;
+        run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(ctx, md, R, tb,
+                                                                                 out, sm, nullptr,
+                                                                                 carry);
     });
 }
 
@@ -720,10 +1116,11 @@ void launch_mttkrp_split(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int 
     }
     const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out);
     const bool sm = mttkrp_small(t, mode);
+    const Tables tb = gather_tables(ctx, t, mode, R, dtype, Fleaf, Fmid);
     with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
         using T = typename decltype(tc)::type;
         run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(
-            ctx, md, R, Fleaf, Fmid, out, sm, nullptr, carry, fix, ev);
+            ctx, md, R, tb, out, sm, nullptr, carry, fix, ev);
     });
 }
 
@@ -736,11 +1133,63 @@ void launch_mttkrp_resid(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int 
     const MttkrpShape sr = mttkrp_shape(R, dtype, Froot, Froot, out);
     if (sr.cpl < sh.cpl) sh = sr;
     const bool sm = mttkrp_small(t, mode);
+    const Tables tb = gather_tables(ctx, t, mode, R, dtype, Fleaf, Fmid);
     with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
         using T = typename decltype(tc)::type;
-        run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(
-            ctx, md, R, Fleaf, Fmid, out, sm, Froot);
+        run<T, decltype(cplc)::value, decltype(gc)::value, decltype(nchc)::value>(ctx, md, R, tb,
+                                                                                 out, sm, Froot);
     });
+}
+
+void launch_gather_probe(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                         dfacto_dtype dtype, const void *Fleaf, const void *Fmid, int pattern,
+                         float *sink) {
+    const ModeData &md = t->mode[mode];
+    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, sink);
+    if (sh.nch != 1) throw Error{DFACTO_E_UNSUPPORTED, "the gather probe takes R <= 64 * CPL"};
+    if ((pattern == 5 || pattern >= 8) && R > kProbeLdsRowElems)
+        throw Error{DFACTO_E_UNSUPPORTED, "the LDS patterns take R <= 64"};
+    if (pattern >= 6 && (uint64_t)t->dims[md.leaf] * R * elem_size(dtype) >= 0xFFFFFF00ull)
+        throw Error{DFACTO_E_UNSUPPORTED, "the buffer patterns take a leaf table below 4 GB"};
+    const bool sm = mttkrp_small(t, mode);
+    const uint32_t nchunk = (uint32_t)md.nchunk;
+    if (nchunk == 0) return;
+    const uint32_t nleaf = (uint32_t)t->dims[md.leaf], nmid = (uint32_t)t->dims[md.mid];
+    const Tables tb = gather_tables(ctx, t, mode, R, dtype, Fleaf, Fmid);
+    Fleaf = tb.leaf;
+    Fmid = tb.mid;
+    with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto) {
+        using T = typename decltype(tc)::type;
+        constexpr int CPL = decltype(cplc)::value, G = decltype(gc)::value;
+        if constexpr (G <= 64) {
+            const unsigned blocks = (nchunk + kBlock / G - 1) / (kBlock / G);
+            auto go = [&](auto kern) {
+                prof_mark(ctx);
+                hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, ctx->stream, md.stream,
+                                   md.chunk_start, nchunk, (const T *)Fleaf, (const T *)Fmid, R,
+                                   nleaf, nmid, sink);
+                prof_mark(ctx);
+            };
+            auto by_pat = [&](auto smc) {
+                constexpr bool S = decltype(smc)::value;
+                switch (pattern) {
+                    case 0: return go(k_gather_probe<T, CPL, G, S, 0>);
+                    case 1: return go(k_gather_probe<T, CPL, G, S, 1>);
+                    case 2: return go(k_gather_probe<T, CPL, G, S, 2>);
+                    case 3: return go(k_gather_probe<T, CPL, G, S, 3>);
+                    case 4: return go(k_gather_probe<T, CPL, G, S, 4>);
+                    case 5: return go(k_gather_probe<T, CPL, G, S, 5>);
+                    case 6: return go(k_gather_probe<T, CPL, G, S, 6>);
+                    case 7: return go(k_gather_probe<T, CPL, G, S, 7>);
+                    case 8: return go(k_gather_probe<T, CPL, G, S, 8>);
+                    default: return go(k_gather_probe<T, CPL, G, S, 9>);
+                }
+            };
+            if (sm) by_pat(std::true_type{});
+            else by_pat(std::false_type{});
+        }
+    });
+    DF_LAUNCHED();
 }
 
 unsigned mttkrp_group_chunks_per_item(const MttkrpShape &sh) { return (unsigned)(kBlock / sh.g); }

@@ -25,13 +25,15 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_RANGE", 3: "E_NOMEM", 4: "E_DEVIC
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = (
     "dfacto_ctx_create", "dfacto_ctx_set_stream", "dfacto_ctx_synchronize", "dfacto_ctx_destroy",
-    "dfacto_last_error", "dfacto_build_flattenings", "dfacto_tensor_get_info",
+    "dfacto_ctx_freeze",
+    "dfacto_last_error", "dfacto_build_flattenings", "dfacto_build_flattenings_ex",
+    "dfacto_tensor_get_info",
     "dfacto_tensor_export", "dfacto_tensor_destroy", "dfacto_mttkrp", "dfacto_als_iter",
     "dfacto_gd_grad", "dfacto_gd_step", "dfacto_build_ratings", "dfacto_joint_grad",
     "dfacto_joint_als_iter", "dfacto_group_create", "dfacto_group_als", "dfacto_group_get_info",
     "dfacto_group_destroy", "dfacto_server_create", "dfacto_server_submit", "dfacto_server_poll",
     "dfacto_server_wait", "dfacto_server_get_stats", "dfacto_server_destroy",
-    "dfacto_profile_enable", "dfacto_profile_read",
+    "dfacto_profile_enable", "dfacto_profile_read", "dfacto_gather_probe",
 )
 GROUP_GRAPH, GROUP_TUNE, GROUP_CTX_STREAM = 1, 2, 4
 
@@ -46,7 +48,8 @@ class _Info(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int64 * 3), ("nnz", ctypes.c_int64),
                 ("nfib", ctypes.c_int64 * 3), ("nroot", ctypes.c_int64 * 3),
                 ("nentry", ctypes.c_int64 * 3), ("nchunk", ctypes.c_int64 * 3),
-                ("normsq", ctypes.c_double), ("bytes", ctypes.c_size_t)]
+                ("normsq", ctypes.c_double), ("bytes", ctypes.c_size_t),
+                ("relabeled", ctypes.c_int)]
 
 
 class _LineSearch(ctypes.Structure):
@@ -106,11 +109,14 @@ def load():
     lib.dfacto_ctx_create.argtypes = [I, P, P, PP]
     lib.dfacto_ctx_set_stream.argtypes = [P, P]
     lib.dfacto_ctx_synchronize.argtypes = [P]
+    lib.dfacto_ctx_freeze.argtypes = [P, I]
     lib.dfacto_ctx_destroy.argtypes = [P]
     lib.dfacto_ctx_destroy.restype = None
     lib.dfacto_last_error.argtypes = [P]
     lib.dfacto_last_error.restype = ctypes.c_char_p
     lib.dfacto_build_flattenings.argtypes = [P, ctypes.POINTER(ctypes.c_int64), I64, P, P, P, P, PP]
+    lib.dfacto_build_flattenings_ex.argtypes = [P, ctypes.POINTER(ctypes.c_int64), I64, P, P, P, P,
+                                                I, PP]
     lib.dfacto_tensor_get_info.argtypes = [P, ctypes.POINTER(_Info)]
     lib.dfacto_tensor_export.argtypes = [P, P, I, P, P, P, P, P, P]
     lib.dfacto_tensor_destroy.argtypes = [P]
@@ -138,6 +144,7 @@ def load():
     lib.dfacto_server_destroy.restype = None
     lib.dfacto_profile_enable.argtypes = [P, I]
     lib.dfacto_profile_read.argtypes = [P, P, P, P, P]
+    lib.dfacto_gather_probe.argtypes = [P, P, I, I, I, PP, I, P]
     for name in EXPORTS:
         if name not in ("dfacto_ctx_destroy", "dfacto_last_error", "dfacto_tensor_destroy",
                         "dfacto_group_destroy", "dfacto_server_destroy"):
@@ -231,6 +238,10 @@ class Context:
     def synchronize(self):
         self.check(load().dfacto_ctx_synchronize(self.handle))
 
+    def freeze(self, on: bool = True):
+        """While frozen, a call that would grow a workspace fails (E_INVALID)."""
+        self.check(load().dfacto_ctx_freeze(self.handle, 1 if on else 0))
+
     def last_error(self) -> str:
         return load().dfacto_last_error(self.handle).decode()
 
@@ -260,7 +271,7 @@ class Tensor:
             raise DfactoError(st, "dfacto_tensor_get_info failed")
         return dict(dims=tuple(inf.dims), nnz=inf.nnz, nfib=tuple(inf.nfib),
                     nroot=tuple(inf.nroot), nentry=tuple(inf.nentry), nchunk=tuple(inf.nchunk),
-                    normsq=inf.normsq, bytes=inf.bytes)
+                    normsq=inf.normsq, bytes=inf.bytes, relabeled=bool(inf.relabeled))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -278,8 +289,12 @@ def ctx_create(device: int = 0, stream=None, allocator=None) -> Context:
     return Context(device, stream, allocator)
 
 
+BUILD_RELABEL, BUILD_NO_RELABEL = 1, 2
+
+
 def build_flattenings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, k: torch.Tensor,
-                      val: torch.Tensor) -> Tensor:
+                      val: torch.Tensor, relabel: bool | None = None) -> Tensor:
+    """relabel: None (by size), True or False (dfacto_build_flattenings_ex flags)."""
     for x in (i, j, k):
         if x.dtype not in (torch.int32, torch.uint32) or not x.is_contiguous() or not x.is_cuda:
             raise TypeError("indices must be contiguous int32/uint32 CUDA tensors")
@@ -290,8 +305,9 @@ def build_flattenings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, k: t
         raise ValueError("index and value arrays differ in length")
     d = (ctypes.c_int64 * 3)(*[int(x) for x in dims])
     h = ctypes.c_void_p()
-    ctx.check(load().dfacto_build_flattenings(ctx.handle, d, n, _ptr(i), _ptr(j), _ptr(k), _ptr(val),
-                                              ctypes.byref(h)))
+    flags = 0 if relabel is None else (BUILD_RELABEL if relabel else BUILD_NO_RELABEL)
+    ctx.check(load().dfacto_build_flattenings_ex(ctx.handle, d, n, _ptr(i), _ptr(j), _ptr(k),
+                                                 _ptr(val), flags, ctypes.byref(h)))
     return Tensor(h, ctx.allocator)
 
 
@@ -387,6 +403,21 @@ def mttkrp(ctx: Context, t: Tensor, mode: int, factors, out: torch.Tensor | None
     ctx.check(load().dfacto_mttkrp(ctx.handle, t.handle, int(mode), R, code, _ptrs(factors),
                                    _ptr(out)))
     return out
+
+
+def gather_probe(ctx: Context, t: Tensor, mode: int, factors, pattern: int,
+                 sink: torch.Tensor | None = None) -> torch.Tensor:
+    """The MTTKRP main kernel's memory requests for ``mode`` without its
+    arithmetic (pattern 0 own rows, 1 uniform random rows, 2 rows among the
+    first 4096, 3 no gathers, 4 rows among the first 32, 5 rows of a small
+    LDS table); returns the sink buffer."""
+    dims, R, code = _check_factors(t, factors, skip=mode)
+    n = 64 * max(1, int(t.info()["nchunk"][mode]))
+    if sink is None or sink.numel() < n:
+        sink = torch.empty(n, dtype=torch.float32, device=f"cuda:{ctx.device}")
+    ctx.check(load().dfacto_gather_probe(ctx.handle, t.handle, int(mode), R, code,
+                                         _ptrs(factors), int(pattern), _ptr(sink)))
+    return sink
 
 
 def als_iter(ctx: Context, t: Tensor, factors, lam: torch.Tensor, fit: torch.Tensor,

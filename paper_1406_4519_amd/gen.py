@@ -349,6 +349,22 @@ def planted_dense(dims, R: int, seed: int) -> tuple:
     return coo, (A, B, C), X.ravel().copy()
 
 
+def planted_dense_noisy(dims, R: int, seed: int, noise: float) -> tuple:
+    """Dense rank-R tensor plus Gaussian noise, all I*J*K entries stored:
+    x = model + noise * rms(model) * N(0,1), so a rank-R fit leaves about
+    noise^2 / (1 + noise^2) of ||X||^2 unexplained.  Returns (Coo with FP32
+    values, factors)."""
+    A, B, C = planted_factors(dims, R, seed)
+    X = np.einsum("ir,jr,kr->ijk", A, B, C)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    X = X + noise * np.sqrt(np.mean(X * X)) * rng.standard_normal(X.shape)
+    I, J, K = X.shape
+    ii, jj, kk = np.meshgrid(np.arange(I), np.arange(J), np.arange(K), indexing="ij")
+    coo = Coo((I, J, K), ii.ravel().astype(np.uint32), jj.ravel().astype(np.uint32),
+              kk.ravel().astype(np.uint32), X.ravel().astype(np.float32))
+    return coo, (A, B, C)
+
+
 def planted_sparse(dims, R: int, seed: int, density: float = 0.2) -> tuple:
     """Exact rank-R tensor whose factor columns are ``density``-sparse; every
     entry of the union of the R rank-one supports is stored (zeros included

@@ -20,9 +20,9 @@ def coo_to_dev(coo):
     return i, j, k, v
 
 
-def build(ctx, coo):
+def build(ctx, coo, relabel=None):
     i, j, k, v = coo_to_dev(coo)
-    t = dfacto.build_flattenings(ctx, coo.dims, i, j, k, v)
+    t = dfacto.build_flattenings(ctx, coo.dims, i, j, k, v, relabel=relabel)
     torch.cuda.synchronize()
     return t
 

@@ -1,15 +1,21 @@
 """Parity at the paper-shape full size, in the launch configuration the
 benchmark times: 6.5M x 2.5M x 1.5M with 1.2B distinct Zipf(1.2)
-coordinates (drawn and deduplicated on the device, as the benchmark does),
-R = 32, FP32 factors (and BF16 for mode 0).
+coordinates (drawn and deduplicated on the device, as the benchmark does).
 
-An output row of mode n depends only on the nonzeros whose mode-n index is
-that row, so the FP64 oracle, run on the sub-tensor of the sampled rows'
-nonzeros with the full factors, gives those rows exactly.  Sampled per mode
-(on the device, from the row counts): the 10th and 1000th heaviest rows
-(millions and tens of thousands of nonzeros, split over many work chunks),
-40 random nonempty rows, and empty rows (which must come out exactly
-zero)."""
+MTTKRP, R = 32 (FP32 and BF16) and R = 10: an output row of mode n depends
+only on the nonzeros whose mode-n index is that row, so the FP64 oracle, run
+on the sub-tensor of the sampled rows' nonzeros with the full factors, gives
+those rows exactly.  Sampled per mode (on the device, from the row counts):
+the 10th and 1000th heaviest rows (millions and tens of thousands of
+nonzeros, split over many work chunks), 40 random nonempty rows, and empty
+rows (which must come out exactly zero).
+
+One CP-ALS iteration and the GD gradient, R = 32 and R = 10 (FP32) and one
+BF16 ALS iteration at R = 10: against the oracle run on the whole tensor
+(its loops spread over the host's cores, bitwise the same as one core), so
+every row of every factor, the weights, the fit and the objective are
+compared; no input of the oracle comes from the device.  Each oracle run
+takes tens of seconds on 16 cores."""
 import numpy as np
 import pytest
 import torch
@@ -63,10 +69,15 @@ def paper():
         say(f"  mode {m}: {len(rows_h)} sampled rows, {len(sub[3]):,} of their nonzeros, "
             f"10th heaviest {int(cnt[order[10]]):,}")
         del cnt, order, nonempty, keep, mark
+    # the whole tensor on the host for the solver checks (FP64 values)
+    host = tuple(np.ascontiguousarray(a.cpu().numpy()).view(np.uint32) for a in (i, j, k))
+    host = host + (v.cpu().numpy().astype(np.float64),)
     del i, j, k, v, coords
     torch.cuda.empty_cache()
     F0 = gen.init_factors(DIMS, R, seed=1003)
-    yield ctx, t, samples, F0
+    oracle.config(oracle.host_threads_capped(16), assume_distinct=True)
+    yield ctx, t, samples, F0, host
+    oracle.config(1, False)
     t.close()
     ctx.close()
     torch.cuda.empty_cache()
@@ -84,7 +95,7 @@ def _check(got, ref, rows, empty, what):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_paper_shape_mttkrp_sampled_rows(paper, dtype):
-    ctx, t, samples, F0 = paper
+    ctx, t, samples, F0, _ = paper
     Fd, Fw = factors_to_dev(F0, dtype)
     modes = range(3) if dtype == "f32" else [0]
     for m in modes:
@@ -97,3 +108,67 @@ def test_paper_shape_mttkrp_sampled_rows(paper, dtype):
         _check(got, ref, s["rows"], s["empty"], f"{dtype} MTTKRP mode {m}")
     del Fd
     torch.cuda.empty_cache()
+
+
+def test_paper_shape_mttkrp_r10_sampled_rows(paper):
+    ctx, t, samples, _, _ = paper
+    F0 = gen.init_factors(DIMS, 10, seed=1010)
+    Fd, Fw = factors_to_dev(F0, "f32")
+    for m in range(3):
+        out = torch.full((DIMS[m], 10), float("nan"), device=DEV)
+        dfacto.mttkrp(ctx, t, m, Fd, out)
+        s = samples[m]
+        got = to_host64(out[torch.from_numpy(s["rows"]).to(DEV)])
+        del out
+        ref = oracle.mttkrp(*s["sub"], DIMS, Fw, m)[s["rows"]]
+        _check(got, ref, s["rows"], s["empty"], f"R=10 MTTKRP mode {m}")
+    del Fd
+    torch.cuda.empty_cache()
+
+
+# FP32: relative Frobenius 1e-5 on factors, weights and gradients, fit 1e-6,
+# objective 1e-6 relative; BF16 storage: 2^-8 and fit 1e-4 (as at small size)
+SOLVER_TOL = {"f32": (1e-5, 1e-6), "bf16": (2.0 ** -8, 1e-4)}
+
+
+@pytest.mark.parametrize("Rr,dtype", [(32, "f32"), (10, "f32"), (10, "bf16")])
+def test_paper_shape_als_iteration(paper, Rr, dtype):
+    ctx, t, _, _, host = paper
+    F0 = gen.init_factors(DIMS, Rr, seed=1003 if Rr == 32 else 1010)
+    Fd, Fw = factors_to_dev(F0, dtype)
+    lam = torch.zeros(Rr, dtype=torch.float64, device=DEV)
+    fit = torch.zeros(1, dtype=torch.float64, device=DEV)
+    dfacto.als_iter(ctx, t, Fd, lam, fit)
+    torch.cuda.synchronize()
+    got = [to_host64(f) for f in Fd]
+    del Fd
+    torch.cuda.empty_cache()
+    A, B, C, lam_ref, info = oracle.als_iter(*host, DIMS, Fw,
+                                             store="f64" if dtype == "f32" else "bf16")
+    ftol, fit_tol = SOLVER_TOL[dtype]
+    errs = [rel_fro(g, ref) for g, ref in zip(got, (A, B, C))]
+    say(f"  ALS R={Rr} {dtype}: factor errors {errs}, lambda "
+        f"{rel_fro(lam.cpu().numpy(), lam_ref):.2e}, fit {fit.item():.9f} vs {info['fit']:.9f}, "
+        f"pinv {info['pinv_mask']}")
+    assert max(errs) <= ftol
+    assert rel_fro(lam.cpu().numpy(), lam_ref) <= ftol
+    assert abs(fit.item() - info["fit"]) <= fit_tol
+
+
+@pytest.mark.parametrize("Rr", [32, 10])
+def test_paper_shape_gd_gradient(paper, Rr):
+    ctx, t, _, _, host = paper
+    F0 = gen.init_factors(DIMS, Rr, seed=1003 if Rr == 32 else 1010)
+    Fd, Fw = factors_to_dev(F0, "f32")
+    G = [torch.empty((d, Rr), device=DEV) for d in DIMS]
+    f = torch.zeros(1, dtype=torch.float64, device=DEV)
+    dfacto.gd_grad(ctx, t, Fd, G, f)
+    torch.cuda.synchronize()
+    got = [to_host64(g) for g in G]
+    del Fd, G
+    torch.cuda.empty_cache()
+    gref, fref = oracle.gd_grad(*host, DIMS, Fw)
+    errs = [rel_fro(g, ref) for g, ref in zip(got, gref)]
+    say(f"  GD R={Rr}: gradient errors {errs}, f {f.item():.12e} vs {fref:.12e}")
+    assert max(errs) <= 1e-5
+    assert abs(f.item() - fref) <= 1e-6 * abs(fref)

@@ -83,3 +83,42 @@ def test_captured_step_replays_bitwise(R, dtype):
     del g
     T.close()
     ctx.close()
+
+
+def test_frozen_context_refuses_to_grow_workspaces():
+    """After dfacto_ctx_freeze a call that needs larger workspaces fails with
+    E_INVALID (so addresses recorded in a graph stay valid); calls at the
+    sizes already reserved still run, and unfreezing restores growth."""
+    from gpu_util import build, factors_to_dev
+    ctx = dfacto.Context(0)
+    small = gen.uniform_distinct((50, 40, 30), 2_000, seed=31)
+    big = gen.zipf_distinct((4000, 3000, 2000), 200_000, 1.1, seed=32)
+    t1, t2 = build(ctx, small), build(ctx, big)
+    R = 8
+    F1, _ = factors_to_dev(gen.init_factors(small.dims, R, seed=33), "f32")
+    lam = torch.zeros(R, dtype=torch.float64, device="cuda:0")
+    fit = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    dfacto.als_iter(ctx, t1, F1, lam, fit)  # sizes the workspaces for t1
+    ctx.freeze(True)
+    dfacto.als_iter(ctx, t1, F1, lam, fit)  # same sizes: runs
+    F2, _ = factors_to_dev(gen.init_factors(big.dims, R, seed=34), "f32")
+    with pytest.raises(dfacto.DfactoError) as e:
+        dfacto.als_iter(ctx, t2, F2, lam, fit)
+    assert e.value.status == dfacto.E_INVALID and "frozen" in ctx.last_error()
+    ctx.freeze(False)
+    dfacto.als_iter(ctx, t2, F2, lam, fit)  # grows now
+    torch.cuda.synchronize()
+    # the same iteration on a fresh context: bitwise the same factors
+    ctx2 = dfacto.Context(0)
+    F3, _ = factors_to_dev(gen.init_factors(big.dims, R, seed=34), "f32")
+    lam2 = torch.zeros_like(lam)
+    fit2 = torch.zeros_like(fit)
+    dfacto.als_iter(ctx2, t2, F3, lam2, fit2)
+    torch.cuda.synchronize()
+    for a, b in zip(F2, F3):
+        assert torch.equal(a, b)
+    assert fit.item() == fit2.item()
+    for t in (t1, t2):
+        t.close()
+    ctx.close()
+    ctx2.close()

@@ -8,7 +8,7 @@ Tolerances (FP32 arithmetic on the device):
   BF16 factors are rounded identically for both sides, so the same bound
   applies.
 * ALS / GD: relative Frobenius error <= 1e-5 on FP32 results, fit within
-  1e-4.  BF16-stored factors are compared with the oracle run with the same
+  1e-6 (the fit of tensors far from 0 is checked in test_gpu_fit.py).  BF16-stored factors are compared with the oracle run with the same
   storage rounding between modes: each entry is the BF16 rounding of nearly
   the same FP64 value, so they differ by at most one BF16 unit (2^-8
   relative) where the two values straddle a rounding boundary; the bound is
@@ -311,7 +311,7 @@ def test_als_one_step_parity(ctx, reg):
         f"fit {fits[0]} vs {info['fit']}")
     assert max(errs) <= 1e-5
     assert rel_fro(lam, lam_ref) <= 1e-5
-    assert abs(fits[0] - info["fit"]) <= 1e-4
+    assert abs(fits[0] - info["fit"]) <= 1e-6
 
 
 def test_als_trajectory_5_iterations(ctx):
@@ -327,9 +327,9 @@ def test_als_trajectory_5_iterations(ctx):
         F = [A, B, C]
         errs = [rel_fro(to_host64(Fd[m]), F[m]) for m in range(3)]
         say(f"  iter {it}: fit gpu {fits[0]:.8f} oracle {info['fit']:.8f} factor err {max(errs):.2e}")
-        assert abs(fits[0] - info["fit"]) <= 1e-4
-        assert max(errs) <= 1e-4
-        assert rel_fro(lam, lam_ref) <= 1e-4
+        assert abs(fits[0] - info["fit"]) <= 1e-6
+        assert max(errs) <= 1e-5
+        assert rel_fro(lam, lam_ref) <= 1e-5
 
 
 def test_als_bf16_one_step(ctx):
@@ -340,9 +340,12 @@ def test_als_bf16_one_step(ctx):
     A, B, C, lam_ref, info = oracle.als_iter(*coo.arrays64(), coo.dims, Fw, store="bf16")
     errs = [rel_fro(to_host64(Fd[m]), ref) for m, ref in enumerate((A, B, C))]
     say(f"  als bf16 one step: factor errors {errs}, lambda {rel_fro(lam, lam_ref)}")
+    say(f"  fit gpu {fits[0]:.9f} oracle {info['fit']:.9f}")
     assert max(errs) <= BF16_REL
     assert rel_fro(lam, lam_ref) <= BF16_REL
-    assert abs(fits[0] - info["fit"]) <= 1e-3
+    # the fit of the stored (rounded) factors on both sides; a few percent
+    # of this small fit (about 6e-4) at most
+    assert abs(fits[0] - info["fit"]) <= 2e-5
 
 
 def test_als_singular_gram_pinv(ctx):

@@ -1,7 +1,8 @@
 """GPU tests of served solves (dfacto_server_*): continuous batching must not
 change any result -- each request gives bitwise the same factors, weights,
 fit and iteration count alone and in a mix -- and those results are the ones
-of dfacto_als_iter repeated on the request alone; admission respects the slot
+of dfacto_als_iter repeated on the request alone and agree with the FP64
+oracle's CP-ALS trajectory from the same start; admission respects the slot
 count and the memory budget."""
 import time
 
@@ -9,7 +10,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import say, DEV
+import oracle
+from gpu_util import rel_fro, say, DEV
 from paper_1406_4519_amd import dfacto, gen
 
 pytestmark = pytest.mark.gpu
@@ -140,3 +142,57 @@ def test_submit_errors(requests):
     ok = srv.wait(_submit(srv, r, max_iters=2))
     assert ok["status"] == dfacto.OK and ok["iters"] == 2
     srv.close()
+
+
+def _oracle_solve(coo, init, R, dtype, tol, max_iters):
+    """The oracle's CP-ALS from the served start (the factors as stored:
+    FP32, or BF16 rounded to nearest even), with the served stopping rule:
+    stop after the iteration whose fit differs from the previous one by less
+    than tol, or after max_iters.  Returns factors, lambda, fits."""
+    store = "f64" if dtype == "f32" else "bf16"
+    F = gen.round_factors(init, dtype)
+    fits = []
+    for it in range(max_iters):
+        A, B, C, lam, info = oracle.als_iter(*coo.arrays64(), coo.dims, F, store=store)
+        F = [A, B, C]
+        fits.append(info["fit"])
+        if it > 0 and abs(fits[-1] - fits[-2]) < tol:
+            break
+    return F, lam, fits
+
+
+SERVED_ORACLE = {  # (fit, factors and lambda) bounds per storage dtype
+    "f32": (1e-6, 1e-5),
+    "bf16": (1e-4, 2.0 ** -8),
+}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_served_results_match_oracle(dtype):
+    """Served solves run to the served stopping rule (fit change < 1e-4 or 50
+    iterations): the iteration count, final factors, weights and fit equal
+    the oracle's trajectory from the same start.  A planted rank-4 tensor
+    plus noise (every entry stored: its fit converges to about 0.74) and a
+    Zipf tensor capped at 12 iterations, submitted together."""
+    coo_p, _ = gen.planted_dense_noisy((40, 30, 25), 4, seed=21, noise=0.1)
+    init_p = [f.astype(np.float32) for f in gen.init_factors(coo_p.dims, 4, seed=22)]
+    coo_z = gen.zipf_distinct((900, 700, 500), 20_000, 1.1, seed=900)
+    init_z = [f.astype(np.float32) for f in gen.init_factors(coo_z.dims, 8, seed=950)]
+    cases = [(coo_p, init_p, 4, 50), (coo_z, init_z, 8, 12)]
+    srv = dfacto.Server(0, max_slots=4)
+    ids = [srv.submit(c.dims, c.i, c.j, c.k, c.val, R, init, dtype=dtype, tol=1e-4,
+                      max_iters=mi) for c, init, R, mi in cases]
+    got = [srv.wait(i) for i in ids]
+    srv.close()
+    ftol, rtol = SERVED_ORACLE[dtype]
+    for (c, init, R, mi), res in zip(cases, got):
+        assert res["status"] == dfacto.OK
+        F, lam, fits = _oracle_solve(c, init, R, dtype, 1e-4, mi)
+        errs = [rel_fro(res["factors"][m], F[m]) for m in range(3)]
+        say(f"  {dtype} R={R}: served {res['iters']} iterations, oracle {len(fits)}; fit "
+            f"{res['fit']:.9f} vs {fits[-1]:.9f}; factors {max(errs):.2e} lambda "
+            f"{rel_fro(res['lam'], lam):.2e}")
+        assert res["iters"] == len(fits)
+        assert abs(res["fit"] - fits[-1]) <= ftol
+        assert max(errs) <= rtol
+        assert rel_fro(res["lam"], lam) <= rtol
