@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the DFacTo hot path on one MI355X.
 
-Workload (default): 1,000,000 x 500,000 x 200,000 tensor with 50M distinct
-Zipf(1.1)-skewed coordinates (seeded permutation per mode), |N(0,1)| FP32
-values, rank R = 32, FP32 factors initialized U(0,1).
+Workload (default, ``paper1200m``): the paper-shape tensor, 6,500,000 x
+2,500,000 x 1,500,000 with 1.2B distinct coordinates, Zipf(1.2) per mode over
+seeded permutations (drawn and deduplicated on the device), |N(0,1)| FP32
+values; rank R = 32 with FP32 factors initialized U(0,1).  The same run
+measures R = 32 with BF16-stored factors and R = 10 (FP32 and BF16) beside
+it.  ``--workload zipf50m`` runs the 1M x 500K x 200K, 50M-nonzero Zipf(1.1)
+tensor instead.
 
-One step = ten CP-ALS iterations (each three MTTKRPs with the FP64 Gram /
-solve / normalize epilogue and the fit) followed by one GD gradient at the
-resulting point (three more MTTKRPs, gradients and the objective): 33
-MTTKRPs (--als-per-step changes the ten).
-``value`` is the step's MTTKRP throughput, 33 * nnz * R per step, in nnz*R/s.
-The flattenings are built once, before the timed region (as the paper's
-per-iteration times also exclude it); the build time is reported separately.
+One step = --als-per-step CP-ALS iterations (each three MTTKRPs with the
+FP64 Gram / solve / normalize epilogue and the fit; default 1 for the paper
+shape, 10 for zipf50m) followed by one GD gradient at the resulting point
+(three more MTTKRPs, gradients and the objective).  ``value`` is the step's
+MTTKRP throughput, MTTKRPs per step * nnz * R / step time, in nnz*R/s, with
+the tensor resident in HBM.  The flattenings are built once, before the
+timed region (as the paper's per-iteration times also exclude it); the build
+time is reported separately.
 
 Prints ONE JSON line (see --help for options).
 """
@@ -29,7 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MTTKRP nnz·R/s + % HBM peak; CP-ALS iter time; served solves/s, p50/p99"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mttkrp_zipf50m_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mttkrp_{}_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1406_4519_amd", "csrc", "mttkrp.hip")
 
 
@@ -42,11 +47,12 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
+def load_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    the workload, or None when there is none or the kernel source changed
+    since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE.format(workload)) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
@@ -55,30 +61,48 @@ def load_traffic():
     return d.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(coo, R, F0, target_s: float):
-    """Time the FP64 oracle (as it stands, one thread) on a bounded sample:
-    one CP-ALS iteration plus one GD gradient on the first S nonzeros."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sample, dims, R, F0, target_s: float, threads: int):
+    """Time the FP64 oracle's MTTKRP (its loop as it stands, over `threads`
+    row-partitioned workers whose results are bitwise those of one) for the
+    three modes on the first S of the sampled nonzeros, with the full-size
+    factors; S grows until the run takes about target_s.  Returns the
+    line's cpu_baseline dict (unit nnz*R/s, the metric's)."""
     import numpy as np
     import oracle
     oracle.build()
-    S = min(coo.nnz, 1_000_000)
-    best = None
-    while True:
-        i, j, k = coo.i[:S], coo.j[:S], coo.k[:S]
-        v = coo.val[:S].astype(np.float64)
-        t0 = time.perf_counter()
-        A, B, C, lam, info = oracle.als_iter(i, j, k, v, coo.dims, F0)
-        oracle.gd_grad(i, j, k, v, coo.dims, (A, B, C))
-        dt = time.perf_counter() - t0
-        best = (S, dt)
-        if dt >= target_s * 0.5 or S >= coo.nnz:
-            break
-        S = min(coo.nnz, int(S * min(8.0, target_s / max(dt, 1e-3))))
-    S, dt = best
-    return {"value": 6.0 * S * R / dt, "unit": "nnz·R/s", "cores": 1, "kind": "oracle",
-            "seconds": dt,
-            "sample": f"oracle CP-ALS iteration + GD gradient (6 MTTKRPs, FP64, 1 thread) on the "
-                      f"first {S:,} of {coo.nnz:,} nonzeros, same dims, R={R}"}
+    i_all, j_all, k_all, v_all = sample
+    oracle.config(threads, assume_distinct=True)
+    try:
+        S = min(len(v_all), 1_000_000)
+        while True:
+            i, j, k = i_all[:S], j_all[:S], k_all[:S]
+            v = v_all[:S].astype(np.float64)
+            t0 = time.perf_counter()
+            for m in range(3):
+                oracle.mttkrp(i, j, k, v, dims, F0, m)
+            dt = time.perf_counter() - t0
+            if dt >= target_s * 0.5 or S >= len(v_all):
+                break
+            S = min(len(v_all), int(S * min(8.0, target_s / max(dt, 1e-3))))
+    finally:
+        oracle.config(1, False)
+    return {"value": 3.0 * S * R / dt, "unit": "nnz·R/s", "cores": threads, "kind": "oracle",
+            "seconds": round(dt, 3), "cpu_model": cpu_model(),
+            "sample": f"oracle MTTKRP, all three modes (FP64, {threads} "
+                      f"thread{'s' if threads > 1 else ''}, output rows split by nonzero count), "
+                      f"on {S:,} seeded random nonzeros of the tensor with its full-size "
+                      f"factors, R={R}"}
 
 
 def run_batched(args):
@@ -407,187 +431,103 @@ def run_joint(args):
     ctx.close()
 
 
-def run_paper(args):
-    """Paper-shape tensor on one GPU: 6.5M x 2.5M x 1.5M with 1.2B distinct
-    coordinates, Zipf(1.2) per mode over seeded permutations, |N(0,1)| FP32
-    values (generated and deduplicated on the device); for R = 10 and 32 and
-    FP32 / BF16 factor storage: one CP-ALS iteration plus one GD gradient
-    (6 MTTKRPs) after one warm-up step.  value = FP32, R = 32 MTTKRP
-    throughput of the step (6 nnz R per step time)."""
+
+def _dev_sample(i, j, k, v, n, seed=11):
+    """n seeded random nonzeros of a device COO, copied to host (uint32 /
+    float32 numpy), for the CPU baseline."""
+    import numpy as np
+    import torch
+    g = torch.Generator(device=i.device)
+    g.manual_seed(seed)
+    n = min(n, i.numel())
+    pick = torch.randperm(i.numel(), generator=g, device=i.device)[:n].sort().values
+    out = [a[pick].cpu().numpy() for a in (i, j, k)]
+    out = [np.ascontiguousarray(a).view(np.uint32) for a in out]
+    return out[0], out[1], out[2], v[pick].cpu().numpy()
+
+
+def _stream_bw(dev, gib=4):
+    """Achievable device bandwidth: a plain device-to-device copy of `gib`
+    GiB (read + write), best of 5."""
+    import torch
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = 1e30
+    for _ in range(6):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * 4 * n / (best * 1e-3) / 1e9
+
+
+def run_tensor(args):
+    """The default workload (paper1200m) and zipf50m / small: timed steps of
+    CP-ALS iterations + one GD gradient for each (R, factor dtype)."""
     import numpy as np
     import torch
     from paper_1406_4519_amd import dfacto, gen
 
     dev = torch.device("cuda:0")
-    dims = (6_500_000, 2_500_000, 1_500_000)
     t0 = time.perf_counter()
-    i, j, k, v = gen.zipf_distinct_torch(
-        dims, args.paper_nnz, 1.2, seed=3, device=dev, batch=1 << 28,
-        progress=lambda m: log(f"  [{time.perf_counter() - t0:.0f}s] {m}"))
-    arrs = [i, j, k]
-    del i, j, k
-    torch.cuda.synchronize()
-    torch.cuda.empty_cache()
-    log(f"generated {args.paper_nnz:,} distinct coordinates in {time.perf_counter() - t0:.1f}s")
-    ctx = dfacto.Context(0)
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    T = dfacto.build_flattenings(ctx, dims, *arrs, v)
-    torch.cuda.synchronize()
-    build_ms = (time.perf_counter() - tb) * 1e3
-    del arrs, v
-    torch.cuda.empty_cache()
-    info = T.info()
-    nnz = info["nnz"]
-    log(f"built in {build_ms:.0f} ms: {nnz:,} distinct nonzeros, nfib={info['nfib']} "
-        f"bytes={info['bytes'] / 1e9:.1f} GB")
-    res = {}
-    for R in (32, 10):
-        F0 = gen.init_factors(dims, R, seed=1003)
-        for dt in ("f32", "bf16"):
-            tdt = torch.float32 if dt == "f32" else torch.bfloat16
-            F = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(dev).to(tdt)
-                 for f in F0]
-            G = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in dims]
-            lam = torch.zeros(R, dtype=torch.float64, device=dev)
-            fit = torch.zeros(1, dtype=torch.float64, device=dev)
-            fv = torch.zeros(1, dtype=torch.float64, device=dev)
-            dfacto.als_iter(ctx, T, F, lam, fit)
-            dfacto.gd_grad(ctx, T, F, G, fv)
-            torch.cuda.synchronize()
-            dfacto.profile_enable(ctx, True)
-            ts = time.perf_counter()
-            dfacto.als_iter(ctx, T, F, lam, fit)
-            torch.cuda.synchronize()
-            als_ms = (time.perf_counter() - ts) * 1e3
-            tg = time.perf_counter()
-            dfacto.gd_grad(ctx, T, F, G, fv)
-            torch.cuda.synchronize()
-            gd_ms = (time.perf_counter() - tg) * 1e3
-            prof = dfacto.profile_read(ctx)
-            dfacto.profile_enable(ctx, False)
-            avg = prof["ms"] / max(prof["launches"], 1)
-            gbs = prof["bytes"] / max(prof["launches"], 1) / (avg * 1e-3) / 1e9
-            res[f"R{R}_{dt}"] = dict(als_iter_ms=round(als_ms, 2), gd_grad_ms=round(gd_ms, 2),
-                                     step_nnzR_per_s=6.0 * nnz * R / ((als_ms + gd_ms) * 1e-3),
-                                     mttkrp_main_ms=round(avg, 3), mttkrp_GBs=round(gbs, 1),
-                                     hbm_frac=round(gbs / HBM_PEAK_GBS, 4), fit=float(fit.item()))
-            log(f"R={R} {dt}: {res[f'R{R}_{dt}']}")
-            del F, G
-            torch.cuda.empty_cache()
-    r = res["R32_f32"]
-    line = {"metric": METRIC, "value": r["step_nnzR_per_s"], "unit": "nnz·R/s", "n_gpus": 1,
-            "steps": 1, "warmup": 1, "ms_per_step": round(r["als_iter_ms"] + r["gd_grad_ms"], 3),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-            "data": "synthetic",
-            "config": {"workload": "paper shape: 6.5M x 2.5M x 1.5M, 1.2B distinct Zipf(1.2) "
-                                   "coordinates, FP32 values; R = 32 (also R = 10) FP32 and BF16 "
-                                   "factors; one CP-ALS iteration + one GD gradient",
-                       "nnz": nnz, "nfib": list(info["nfib"]), "parallelism": "single GPU"},
-            "roofline": {"bound": "hbm", "achieved": r["mttkrp_GBs"], "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": r["hbm_frac"], "traffic": None},
-            "extra": {"build_ms": round(build_ms, 1), "runs": res,
-                      "paper_context_s": {"als_iter_4_machines": 480, "gd_iter_4_machines": 1143}}}
-    print(json.dumps(line), flush=True)
-    T.close()
-    ctx.close()
-
-
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="zipf50m",
-                    choices=["zipf50m", "small", "batched", "served", "paper1200m", "synthetic",
-                             "joint"])
-    ap.add_argument("--batch", type=int, default=256, help="batched workload: number of tensors")
-    ap.add_argument("--iters", type=int, default=20, help="batched workload: ALS iterations")
-    ap.add_argument("--rate", type=float, default=200.0, help="served workload: arrivals per second")
-    ap.add_argument("--duration", type=float, default=1.0,
-                    help="served workload: seconds of Poisson arrivals")
-    ap.add_argument("--large-frac", type=float, default=0.05,
-                    help="served workload: fraction of 50M-nonzero requests")
-    ap.add_argument("--pool", type=int, default=48, help="served workload: distinct small tensors")
-    ap.add_argument("--paper-nnz", type=int, default=1_200_000_000,
-                    help="paper1200m workload: distinct nonzeros")
-    ap.add_argument("--served-dtypes", default="f32,bf16",
-                    help="served workload: factor storage dtypes, run in this order")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-factor side run")
-    ap.add_argument("--als-per-step", type=int, default=10,
-                    help="CP-ALS iterations in a step (then one GD gradient)")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="time eager launches instead of a HIP graph replay of the step")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="after the timed region, run one plain device copy of this many MiB "
-                         "(a known-size kernel for calibrating hardware byte counters)")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(how it would shard is a design note). Run with --gpus 1.", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    from paper_1406_4519_amd import dfacto, gen
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    dfacto.load()  # fail loudly if the HIP library is missing
-    if args.workload == "batched":
-        return run_batched(args)
-    if args.workload == "served":
-        return run_served(args)
     if args.workload == "paper1200m":
-        return run_paper(args)
-    if args.workload == "synthetic":
-        return run_synthetic(args)
-    if args.workload == "joint":
-        return run_joint(args)
-
-    t0 = time.perf_counter()
-    if args.workload == "zipf50m":
-        coo, R, F0 = gen.zipf_50m()
-        wl = ("zipf50m: 1,000,000 x 500,000 x 200,000, 50M distinct Zipf(1.1) coordinates "
-              "(seeded permutation per mode), |N(0,1)| FP32 values, R=32, U(0,1) FP32 factors; "
-              f"step = {args.als_per_step} CP-ALS iterations + 1 GD gradient "
-              f"({3 * args.als_per_step + 3} MTTKRPs)")
+        dims = (6_500_000, 2_500_000, 1_500_000)
+        i, j, k, v = gen.zipf_distinct_torch(
+            dims, args.paper_nnz, 1.2, seed=3, device=dev, batch=1 << 28,
+            progress=lambda m: log(f"  [{time.perf_counter() - t0:.0f}s] {m}"))
+        ranks, init_seed = (32, 10), 1003
+        aps = args.als_per_step or 1
+        wl = (f"paper1200m: 6,500,000 x 2,500,000 x 1,500,000, {args.paper_nnz:,} distinct "
+              f"Zipf(1.2) coordinates (seeded permutation per mode), |N(0,1)| FP32 values, R=32, "
+              f"U(0,1) FP32 factors; step = {aps} CP-ALS iteration{'s' if aps > 1 else ''} + 1 GD "
+              f"gradient ({3 * aps + 3} MTTKRPs); R=32 BF16 and R=10 FP32/BF16 in extra.runs")
     else:
-        coo, R, F0 = gen.small_uniform()
-        wl = "small: 200 x 150 x 100, 20,000 distinct uniform coordinates, N(0,1), R=8"
-    log(f"generated {coo.nnz:,} nonzeros in {time.perf_counter() - t0:.1f}s")
-
-    dev = torch.device("cuda:0")
+        coo, R0, _ = gen.zipf_50m() if args.workload == "zipf50m" else gen.small_uniform()
+        dims = coo.dims
+        i, j, k = (torch.from_numpy(a.view(np.int32)).to(dev) for a in (coo.i, coo.j, coo.k))
+        v = torch.from_numpy(coo.val).to(dev)
+        ranks, init_seed = (R0,), (1002 if args.workload == "zipf50m" else 1001)
+        aps = args.als_per_step or (10 if args.workload == "zipf50m" else 5)
+        wl = (f"{args.workload}: {' x '.join(f'{d:,}' for d in dims)}, {coo.nnz:,} distinct "
+              f"coordinates, R={R0}; step = {aps} CP-ALS iterations + 1 GD gradient "
+              f"({3 * aps + 3} MTTKRPs)")
+        del coo
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t0:.1f}s")
+    sample = None if args.no_cpu_baseline else _dev_sample(i, j, k, v, args.cpu_sample)
+    torch.cuda.empty_cache()
     ctx = dfacto.Context(0)
-    i = torch.from_numpy(coo.i.view(np.int32)).to(dev)
-    j = torch.from_numpy(coo.j.view(np.int32)).to(dev)
-    k = torch.from_numpy(coo.k.view(np.int32)).to(dev)
-    v = torch.from_numpy(coo.val).to(dev)
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    T = dfacto.build_flattenings(ctx, coo.dims, i, j, k, v)
+    T = dfacto.build_flattenings(ctx, dims, i, j, k, v)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - tb) * 1e3
     del i, j, k, v
+    torch.cuda.empty_cache()
     info = T.info()
-    log(f"built flattenings in {build_ms:.1f} ms: nfib={info['nfib']} nroot={info['nroot']} "
-        f"nentry={info['nentry']} bytes={info['bytes']/1e9:.2f} GB")
+    nnz = info["nnz"]
+    log(f"built in {build_ms:.0f} ms: {nnz:,} nonzeros nfib={info['nfib']} nroot={info['nroot']} "
+        f"bytes={info['bytes'] / 1e9:.2f} GB")
+    per_step = 3.0 * aps + 3.0
 
-    def run(dtype_name: str):
-        tdt = torch.float32 if dtype_name == "f32" else torch.bfloat16
+    def make(R, dt, F0):
+        tdt = torch.float32 if dt == "f32" else torch.bfloat16
         F = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(dev).to(tdt)
              for f in F0]
-        G = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in coo.dims]
-        lam = torch.zeros(R, dtype=torch.float64, device=dev)
-        fit = torch.zeros(1, dtype=torch.float64, device=dev)
-        fval = torch.zeros(1, dtype=torch.float64, device=dev)
+        G = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in dims]
+        z = lambda n: torch.zeros(n, dtype=torch.float64, device=dev)
+        return F, G, z(R), z(1), z(1)
+
+    def variant(R, dt, F0, headline):
+        F, G, lam, fit, fval = make(R, dt, F0)
 
         def step():
-            for _ in range(args.als_per_step):
+            for _ in range(aps):
                 dfacto.als_iter(ctx, T, F, lam, fit)
             dfacto.gd_grad(ctx, T, F, G, fval)
 
@@ -603,8 +543,7 @@ def main():
         el = time.perf_counter() - ts
         prof = dfacto.profile_read(ctx)
         dfacto.profile_enable(ctx, False)
-        el_eager = el
-        graph_ok = None
+        el_eager, graph_ok = el, None
         if not args.no_graph:
             # the same step captured once as a HIP graph and replayed; its
             # first replay must equal an eager step from the same state
@@ -614,6 +553,7 @@ def main():
             eager = [x.clone() for x in (*F, lam, fit, *G, fval)]
             for x, y in zip((*F, lam, fit), state):
                 x.copy_(y)
+            del state
             torch.cuda.synchronize()
             g = torch.cuda.CUDAGraph()
             side = torch.cuda.Stream()
@@ -627,10 +567,10 @@ def main():
                 ctx.set_stream(main)
             g.replay()
             torch.cuda.synchronize()
-            got = [x.clone() for x in (*F, lam, fit, *G, fval)]
-            graph_ok = all(torch.equal(a.view(torch.int16) if a.dtype == torch.bfloat16 else a,
-                                       b.view(torch.int16) if b.dtype == torch.bfloat16 else b)
-                           for a, b in zip(got, eager))
+            as_bits = lambda a: a.view(torch.int16) if a.dtype == torch.bfloat16 else a
+            graph_ok = all(torch.equal(as_bits(a), as_bits(b))
+                           for a, b in zip((*F, lam, fit, *G, fval), eager))
+            del eager
             if graph_ok:
                 for _ in range(2):
                     g.replay()
@@ -643,9 +583,8 @@ def main():
             else:
                 log("graph replay differs from the eager step: timing the eager steps")
             del g
-        # per-call timings (separately, after the timed region)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = max(3, min(args.steps, 10))
+        reps = 3
         e0.record()
         for _ in range(reps):
             dfacto.als_iter(ctx, T, F, lam, fit)
@@ -658,71 +597,103 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         gd_ms = e0.elapsed_time(e1) / reps
-        mt_ms = []
+        # per mode: the main kernel alone (library events) and the whole call
+        modes = []
         for m in range(3):
-            out = G[m]
+            dfacto.profile_enable(ctx, True)
             e0.record()
             for _ in range(reps):
-                dfacto.mttkrp(ctx, T, m, F, out)
+                dfacto.mttkrp(ctx, T, m, F, G[m])
             e1.record()
+            pm = dfacto.profile_read(ctx)
+            dfacto.profile_enable(ctx, False)
+            kms = pm["ms"] / pm["launches"]
+            kb = pm["bytes"] / pm["launches"]
+            modes.append(dict(call_ms=round(e0.elapsed_time(e1) / reps, 4),
+                              kernel_ms=round(kms, 4), alg_bytes=round(kb),
+                              frac=round(kb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              nnzR_per_s=round(nnz * R / (kms * 1e-3))))
+        avg = prof["ms"] / max(prof["launches"], 1)
+        bpl = prof["bytes"] / max(prof["launches"], 1)
+        out = dict(ms_per_step=round(el * 1e3 / args.steps, 4),
+                   ms_per_step_eager=round(el_eager * 1e3 / args.steps, 4),
+                   graph_replay_equals_eager=graph_ok,
+                   value=per_step * nnz * R * args.steps / el,
+                   als_iter_ms=round(als_ms, 3), gd_grad_ms=round(gd_ms, 3),
+                   main_kernel_ms=round(avg, 4), launches=prof["launches"],
+                   alg_bytes_per_launch=round(bpl),
+                   achieved_GBs=round(bpl / (avg * 1e-3) / 1e9, 1) if avg > 0 else 0.0,
+                   modes=modes, fit=float(fit.item()), f=float(fval.item()))
+        out["frac"] = round(out["achieved_GBs"] / HBM_PEAK_GBS, 4)
+        if headline:
+            out["_state"] = (F, G)
+        else:
+            del F, G
+            torch.cuda.empty_cache()
+        log(f"R={R} {dt}: {json.dumps({k2: v2 for k2, v2 in out.items() if k2 != '_state'})}")
+        return out
+
+    runs = {}
+    R = ranks[0]
+    F0 = gen.init_factors(dims, R, seed=init_seed)
+    head = variant(R, "f32", F0, True)
+    F, G = head.pop("_state")
+    # the main kernel's request ceiling (same requests without arithmetic)
+    # and cold repetitions (a 2 GiB write-read first evicts the 256 MB
+    # Infinity Cache), per mode, headline configuration
+    ceiling, cold = [], []
+    evict = torch.empty((2 << 30) // 4, dtype=torch.float32, device=dev)
+    sink = None
+    for m in range(3):
+        row = {}
+        for pat, name in ((0, "own_rows"), (1, "uniform_rows"), (2, "l2_rows"), (3, "no_gathers")):
+            sink = dfacto.gather_probe(ctx, T, m, F, pat, sink)
             torch.cuda.synchronize()
-            mt_ms.append(e0.elapsed_time(e1) / reps)
-        fit_v, f_v = float(fit.item()), float(fval.item())
-        # full GD iterations (gradient + Armijo backtracking + update) from the
-        # initial factors: the first from alpha0 = 1, the next ones from twice
-        # the previous step
+            dfacto.profile_enable(ctx, True)
+            for _ in range(3):
+                dfacto.gather_probe(ctx, T, m, F, pat, sink)
+            pp = dfacto.profile_read(ctx)
+            dfacto.profile_enable(ctx, False)
+            row[name + "_ms"] = round(pp["ms"] / pp["launches"], 4)
+        row["mttkrp_frac_of_own_ceiling"] = round(row["own_rows_ms"] /
+                                                  head["modes"][m]["kernel_ms"], 4)
+        ceiling.append(row)
+        ks = []
+        for _ in range(5):
+            evict.fill_(float(len(ks)))
+            dfacto.profile_enable(ctx, True)
+            dfacto.mttkrp(ctx, T, m, F, G[m])
+            pp = dfacto.profile_read(ctx)
+            dfacto.profile_enable(ctx, False)
+            ks.append(pp["ms"])
+        kb = head["modes"][m]["alg_bytes"]
+        cms = float(np.median(ks))
+        cold.append(dict(kernel_ms=round(cms, 4),
+                         frac=round(kb / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
+    del evict, sink
+    gd_iters = []
+    if args.gd_iters > 0:
         for m, f0 in enumerate(F0):
-            F[m].copy_(torch.from_numpy(np.ascontiguousarray(f0, dtype=np.float32)).to(dev).to(tdt))
-        gd_iters, a0 = [], 1.0
-        for _ in range(3):
+            F[m].copy_(torch.from_numpy(np.ascontiguousarray(f0, dtype=np.float32)).to(dev))
+        a0 = 1.0
+        for _ in range(args.gd_iters):
             torch.cuda.synchronize()
             tg = time.perf_counter()
             inf = dfacto.gd_step(ctx, T, F, G, alpha0=a0, shrink=0.5, c=1e-4, max_trials=60)
             gd_iters.append(dict(ms=round((time.perf_counter() - tg) * 1e3, 3),
                                  trials=inf["trials"], alpha=inf["alpha"], f=inf["f"]))
             a0 = 2.0 * inf["alpha"] if inf["accepted"] else a0
-        return dict(elapsed=el, elapsed_eager=el_eager, graph_ok=graph_ok, prof=prof,
-                    als_ms=als_ms, gd_ms=gd_ms, mttkrp_ms=mt_ms, fit=fit_v, f=f_v,
-                    gd_iters=gd_iters)
-
-    r32 = run("f32")
-    nnz = info["nnz"]
-    ms_per_step = r32["elapsed"] * 1e3 / args.steps
-    per_step = 3.0 * args.als_per_step + 3.0  # MTTKRPs in a step
-    value = per_step * nnz * R * args.steps / r32["elapsed"]
-    prof = r32["prof"]
-    avg_ms = prof["ms"] / max(prof["launches"], 1)
-    bytes_per_launch = prof["bytes"] / max(prof["launches"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = load_traffic()
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_mttkrp (main MTTKRP kernel, all 3 modes)",
-                "launches": prof["launches"], "avg_launch_ms": round(avg_ms, 4),
-                "alg_bytes_per_launch": round(bytes_per_launch)}
-    extra = {"timed_as": "HIP graph replay of the step" if r32["graph_ok"] else "eager launches",
-             "graph_replay_equals_eager": r32["graph_ok"],
-             "ms_per_step_eager": round(r32["elapsed_eager"] * 1e3 / args.steps, 4),
-             "build_ms": round(build_ms, 1), "als_iter_ms": round(r32["als_ms"], 3),
-             "gd_grad_ms": round(r32["gd_ms"], 3),
-             "mttkrp_ms": [round(x, 4) for x in r32["mttkrp_ms"]],
-             "mttkrp_nnzR_per_s": [round(nnz * R / (x * 1e-3)) for x in r32["mttkrp_ms"]],
-             "fit_after_timed_steps": r32["fit"], "gd_iterations": r32["gd_iters"],
-             "nfib": list(info["nfib"]),
-             "nroot": list(info["nroot"]), "nnz": nnz}
+    del F, G
+    torch.cuda.empty_cache()
+    runs[f"R{R}_f32"] = head
     if not args.no_bf16:
-        rb = run("bf16")
-        pb = rb["prof"]
-        ab = pb["ms"] / max(pb["launches"], 1)
-        extra["bf16"] = {"ms_per_step": round(rb["elapsed"] * 1e3 / args.steps, 4),
-                         "ms_per_step_eager": round(rb["elapsed_eager"] * 1e3 / args.steps, 4),
-                         "graph_replay_equals_eager": rb["graph_ok"],
-                         "value": per_step * nnz * R * args.steps / rb["elapsed"],
-                         "als_iter_ms": round(rb["als_ms"], 3), "gd_grad_ms": round(rb["gd_ms"], 3),
-                         "mttkrp_ms": [round(x, 4) for x in rb["mttkrp_ms"]],
-                         "gd_iterations": rb["gd_iters"],
-                         "roofline_achieved_GBs": round(pb["bytes"] / max(pb["launches"], 1)
-                                                        / (ab * 1e-3) / 1e9, 1) if ab > 0 else 0}
+        runs[f"R{R}_bf16"] = variant(R, "bf16", F0, False)
+    for R2 in ranks[1:]:
+        F02 = gen.init_factors(dims, R2, seed=init_seed)
+        runs[f"R{R2}_f32"] = variant(R2, "f32", F02, False)
+        if not args.no_bf16:
+            runs[f"R{R2}_bf16"] = variant(R2, "bf16", F02, False)
+    stream_gbs = _stream_bw(dev)
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -730,22 +701,111 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        extra["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n}
         del src, dst
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample ...")
-        cpu = cpu_baseline(coo, R, F0, args.cpu_seconds)
-    line = {"metric": METRIC, "value": value, "unit": "nnz·R/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-            "data": "synthetic", "config": {"workload": wl, "nnz": nnz, "R": R,
-                                            "dims": list(coo.dims), "als_per_step": args.als_per_step,
-                                            "parallelism": "single GPU"},
-            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
-    print(json.dumps(line), flush=True)
     T.close()
     ctx.close()
+    cpu = None
+    if sample is not None:
+        threads = oracle_threads()
+        log(f"timing the CPU oracle on a bounded sample ({threads} threads) ...")
+        cpu = cpu_baseline(sample, dims, R, F0, args.cpu_seconds, threads)
+        if threads > 1:
+            one = cpu_baseline(sample, dims, R, F0, args.cpu_seconds / 2, 1)
+            cpu["one_thread"] = {k2: one[k2] for k2 in ("value", "seconds", "sample")}
+    traffic = load_traffic(args.workload)
+    roofline = {"bound": "hbm", "achieved": head["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": head["frac"], "traffic": traffic,
+                "kernel": "k_mttkrp (main MTTKRP kernel, all 3 modes)",
+                "launches": head["launches"], "avg_launch_ms": head["main_kernel_ms"],
+                "alg_bytes_per_launch": head["alg_bytes_per_launch"],
+                "frac_cold": round(sum(c["frac"] for c in cold) / 3, 4),
+                "achievable_stream_GBs": round(stream_gbs, 1),
+                "frac_of_achievable": round(head["achieved_GBs"] / stream_gbs, 4)}
+    line = {"metric": METRIC, "value": head["value"], "unit": "nnz·R/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": wl, "nnz": nnz, "R": R, "dims": list(dims),
+                       "als_per_step": aps, "parallelism": "single GPU"},
+            "roofline": roofline, "cpu_baseline": cpu,
+            "extra": {"timed_as": "HIP graph replay of the step" if head["graph_replay_equals_eager"]
+                      else "eager launches",
+                      "build_ms": round(build_ms, 1), "nfib": list(info["nfib"]),
+                      "nroot": list(info["nroot"]), "nentry": list(info["nentry"]),
+                      "runs": runs, "gather_ceiling": ceiling, "cold_mttkrp": cold,
+                      "gd_iterations": gd_iters,
+                      "paper_context_s": {"als_iter_4_machines": 480, "gd_iter_4_machines": 1143}}}
+    print(json.dumps(line), flush=True)
+
+
+def oracle_threads() -> int:
+    """Host cores this process may use, capped at the 16 a one-GPU share of
+    the host offers."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="paper1200m",
+                    choices=["paper1200m", "zipf50m", "small", "batched", "served", "synthetic",
+                             "joint"])
+    ap.add_argument("--batch", type=int, default=256, help="batched workload: number of tensors")
+    ap.add_argument("--iters", type=int, default=20, help="batched workload: ALS iterations")
+    ap.add_argument("--rate", type=float, default=200.0, help="served workload: arrivals per second")
+    ap.add_argument("--duration", type=float, default=1.0,
+                    help="served workload: seconds of Poisson arrivals")
+    ap.add_argument("--large-frac", type=float, default=0.05,
+                    help="served workload: fraction of 50M-nonzero requests")
+    ap.add_argument("--pool", type=int, default=48, help="served workload: distinct small tensors")
+    ap.add_argument("--paper-nnz", type=int, default=1_200_000_000,
+                    help="paper1200m workload: distinct nonzeros")
+    ap.add_argument("--served-dtypes", default="f32,bf16",
+                    help="served workload: factor storage dtypes, run in this order")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=100_000_000,
+                    help="nonzeros copied to the host for the CPU baseline (at most)")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-factor runs")
+    ap.add_argument("--als-per-step", type=int, default=0,
+                    help="CP-ALS iterations in a step, then one GD gradient "
+                         "(default: 1 for paper1200m, 10 for zipf50m)")
+    ap.add_argument("--gd-iters", type=int, default=3,
+                    help="full GD iterations (line search) timed after the steps")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches instead of a HIP graph replay of the step")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the timed region, run one plain device copy of this many MiB "
+                         "(a known-size kernel for calibrating hardware byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(how it would shard is a design note). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1406_4519_amd import dfacto
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dfacto.load()  # fail loudly if the HIP library is missing
+    if args.workload == "batched":
+        return run_batched(args)
+    if args.workload == "served":
+        return run_served(args)
+    if args.workload == "synthetic":
+        return run_synthetic(args)
+    if args.workload == "joint":
+        return run_joint(args)
+    return run_tensor(args)
 
 
 if __name__ == "__main__":
