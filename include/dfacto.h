@@ -219,6 +219,23 @@ void dfacto_tensor_destroy(dfacto_tensor *t);
 dfacto_status dfacto_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
                             dfacto_dtype dtype, const void *const d_F[3], float *d_out);
 
+/* dfacto_mttkrp for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same computation and kernels, bitwise the same result, with the
+ * call's buffers -- the carries of output rows split over work chunks and,
+ * for a relabeled tensor, the factor tables permuted into rank order -- in
+ * a fixed device array of 64 MiB that the library holds on every GPU it
+ * runs on until the process ends.  It calls no allocator and takes no
+ * workspace of the context.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race, and
+ * must be ordered by the caller.  Arguments as dfacto_mttkrp.  Errors as
+ * there, and DFACTO_E_UNSUPPORTED when the call needs more than the array
+ * holds (nchunk x R x 4 bytes of carries, plus for a relabeled tensor the
+ * two gathered factors' rows), DFACTO_E_INVALID for a tensor built on
+ * another device. */
+dfacto_status dfacto_mttkrp_noalloc(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
+                                    dfacto_dtype dtype, const void *const d_F[3], float *d_out);
+
 /* One CP-ALS iteration (Algorithm 2 / Algorithm 4), in place on
  * d_F = {A, B, C}, modes updated in the order 0, 1, 2, each with the
  * factors already updated:

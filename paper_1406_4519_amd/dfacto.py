@@ -34,6 +34,7 @@ EXPORTS = (
     "dfacto_group_destroy", "dfacto_server_create", "dfacto_server_submit", "dfacto_server_poll",
     "dfacto_server_wait", "dfacto_server_get_stats", "dfacto_server_destroy",
     "dfacto_profile_enable", "dfacto_profile_read", "dfacto_gather_probe",
+    "dfacto_mttkrp_noalloc",
 )
 GROUP_GRAPH, GROUP_TUNE, GROUP_CTX_STREAM = 1, 2, 4
 
@@ -122,6 +123,7 @@ def load():
     lib.dfacto_tensor_destroy.argtypes = [P]
     lib.dfacto_tensor_destroy.restype = None
     lib.dfacto_mttkrp.argtypes = [P, P, I, I, I, PP, P]
+    lib.dfacto_mttkrp_noalloc.argtypes = [P, P, I, I, I, PP, P]
     lib.dfacto_als_iter.argtypes = [P, P, I, I, D, PP, P, P]
     lib.dfacto_gd_grad.argtypes = [P, P, I, I, D, PP, PP, P]
     lib.dfacto_gd_step.argtypes = [P, P, I, I, D, PP, PP, ctypes.POINTER(_LineSearch),
@@ -402,6 +404,17 @@ def mttkrp(ctx: Context, t: Tensor, mode: int, factors, out: torch.Tensor | None
         raise ValueError("out must be a contiguous float32 tensor of shape (dims[mode], R)")
     ctx.check(load().dfacto_mttkrp(ctx.handle, t.handle, int(mode), R, code, _ptrs(factors),
                                    _ptr(out)))
+    return out
+
+
+def mttkrp_noalloc(ctx: Context, t: Tensor, mode: int, factors, out: torch.Tensor):
+    """dfacto_mttkrp with the library's fixed scratch array (no allocation;
+    calls on one GPU must not overlap)."""
+    dims, R, code = _check_factors(t, factors, skip=mode)
+    if out.dtype != torch.float32 or not out.is_contiguous() or tuple(out.shape) != (dims[mode], R):
+        raise ValueError("out must be a contiguous float32 tensor of shape (dims[mode], R)")
+    ctx.check(load().dfacto_mttkrp_noalloc(ctx.handle, t.handle, int(mode), R, code,
+                                           _ptrs(factors), _ptr(out)))
     return out
 
 
