@@ -127,14 +127,46 @@ def test_paper_shape_mttkrp_r10_sampled_rows(paper):
 
 
 # FP32: relative Frobenius 1e-5 on factors, weights and gradients, fit 1e-6,
-# objective 1e-6 relative; BF16 storage: 2^-8 and fit 1e-4 (as at small size)
+# objective 1e-6 relative; BF16 storage: 2^-8 and fit 1e-4 (as at small size).
+# A factor update F_n = M_n H_n^-1 passes the relative errors of its inputs
+# -- e_acc from the FP32 sums of M_n (measured 4e-8 on sampled rows; 1e-7
+# taken), and the error of each factor already updated in this iteration,
+# which enters M_n and H_n -- through the condition number of H_n:
+#   e_n <= kappa(H_n) * (e_acc + 4 * (e_0 + ... + e_{n-1})),
+# to first order.  U(0,1) starting factors have strongly correlated columns:
+# kappa(H_0), kappa(H_1) are tens, but kappa(H_2) is above 1e4, where an FP32
+# pipeline and the FP64 one may differ by any amount up to the size of the
+# factor itself (measured: 1e-4).  So with that start a factor is compared
+# element-wise only when kappa(H_n) <= 1e3 (against the propagated bound),
+# and the ill-conditioned update is checked through the fit; the N(0,1)
+# start (kappa below 3) checks every factor and lambda against the flat
+# bound.  kappa is computed in FP64 from the oracle's own factors, as the
+# update uses them.
 SOLVER_TOL = {"f32": (1e-5, 1e-6), "bf16": (2.0 ** -8, 1e-4)}
+E_ACC = 1e-7
+KAPPA_MAX = 1e3
 
 
-@pytest.mark.parametrize("Rr,dtype", [(32, "f32"), (10, "f32"), (10, "bf16")])
-def test_paper_shape_als_iteration(paper, Rr, dtype):
+def _kappas(F0, F1):
+    """kappa(H_n) of the three updates of one iteration: H_0 from the
+    starting B, C; H_1 from the starting C and the new A; H_2 from the new
+    A and B."""
+    G = lambda F: F.T @ F
+    pairs = ((F0[1], F0[2]), (F0[2], F1[0]), (F1[0], F1[1]))
+    return [float(np.linalg.cond(G(p) * G(q))) for p, q in pairs]
+
+
+@pytest.mark.parametrize("Rr,dtype,init", [(32, "f32", "uniform"), (32, "f32", "normal"),
+                                           (10, "f32", "uniform"), (10, "bf16", "uniform")])
+def test_paper_shape_als_iteration(paper, Rr, dtype, init):
+    """uniform: the workload's U(0,1) start (ill-conditioned Grams, the
+    propagated bound applies); normal: N(0,1) factors, whose columns are
+    nearly orthogonal, so kappa is small and the flat bound must hold."""
     ctx, t, _, _, host = paper
-    F0 = gen.init_factors(DIMS, Rr, seed=1003 if Rr == 32 else 1010)
+    if init == "uniform":
+        F0 = gen.init_factors(DIMS, Rr, seed=1003 if Rr == 32 else 1010)
+    else:
+        F0 = gen.planted_factors(DIMS, Rr, seed=1020)
     Fd, Fw = factors_to_dev(F0, dtype)
     lam = torch.zeros(Rr, dtype=torch.float64, device=DEV)
     fit = torch.zeros(1, dtype=torch.float64, device=DEV)
@@ -147,11 +179,22 @@ def test_paper_shape_als_iteration(paper, Rr, dtype):
                                              store="f64" if dtype == "f32" else "bf16")
     ftol, fit_tol = SOLVER_TOL[dtype]
     errs = [rel_fro(g, ref) for g, ref in zip(got, (A, B, C))]
-    say(f"  ALS R={Rr} {dtype}: factor errors {errs}, lambda "
+    kap = _kappas(Fw, (A, B, C))
+    bound, prev = [], 0.0
+    for k_n in kap:  # the propagated first-order bound, mode by mode
+        e = k_n * (E_ACC + 4.0 * prev)
+        bound.append(max(ftol, e))
+        prev += e
+    say(f"  ALS R={Rr} {dtype}: factor errors {errs}, bounds {bound}, kappa {kap}, lambda "
         f"{rel_fro(lam.cpu().numpy(), lam_ref):.2e}, fit {fit.item():.9f} vs {info['fit']:.9f}, "
         f"pinv {info['pinv_mask']}")
-    assert max(errs) <= ftol
-    assert rel_fro(lam.cpu().numpy(), lam_ref) <= ftol
+    checked = [n for n in range(3) if kap[n] <= KAPPA_MAX]
+    for n in checked:
+        assert errs[n] <= bound[n], (n, errs[n], bound[n])
+    if 2 in checked:  # lambda is the last mode's column norms
+        assert rel_fro(lam.cpu().numpy(), lam_ref) <= bound[2]
+    if init == "normal":
+        assert checked == [0, 1, 2]
     assert abs(fit.item() - info["fit"]) <= fit_tol
 
 
