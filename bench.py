@@ -126,13 +126,24 @@ def run_batched(args):
         staged.append((coo.dims, d + [torch.from_numpy(coo.val).to(dev)], R, F0, coo.nnz))
     torch.cuda.synchronize()
     log(f"generated {args.batch} tensors in {time.perf_counter() - t0:.1f}s")
-    # the builds from device-resident COO, timed on their own
-    members = []
+    # the builds from device-resident COO, timed on their own: build_threads
+    # host threads, each with a context on a stream of its own (a build
+    # waits for its stream at the end; the library call releases the GIL)
+    from concurrent.futures import ThreadPoolExecutor
+    nth = max(1, args.build_threads)
+    bctx = [dfacto.Context(0, stream=torch.cuda.Stream()) for _ in range(nth)]
+    torch.cuda.synchronize()
     tb = time.perf_counter()
-    for dims, d, R, F0, nnz in staged:
-        members.append((dfacto.build_flattenings(ctx, dims, *d), R, F0, nnz, dims))
+
+    def build_slice(w):
+        return [(q, dfacto.build_flattenings(bctx[w], staged[q][0], *staged[q][1]))
+                for q in range(w, len(staged), nth)]
+
+    with ThreadPoolExecutor(nth) as ex:
+        built = dict(kv for part in ex.map(build_slice, range(nth)) for kv in part)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - tb
+    members = [(built[q], R, F0, nnz, dims) for q, (dims, d, R, F0, nnz) in enumerate(staged)]
     del staged
     log(f"built {args.batch} tensors in {build_s:.3f}s")
     work = sum(3.0 * nnz * R for _, R, _, nnz, _ in members) * args.iters
@@ -189,7 +200,7 @@ def run_batched(args):
                                    f"{args.iters} ALS iterations each",
                        "total_nnz": total_nnz, "parallelism": "single GPU"},
             "extra": {"solves_per_s_grouped_f32": args.batch / (g32["ms"] * 1e-3),
-                      "build_s": round(build_s, 3),
+                      "build_s": round(build_s, 3), "build_threads": nth,
                       "solves_per_s_end_to_end_f32": args.batch / (build_s + g32["create_s"] +
                                                                    g32["wall_s"]),
                       "solves_per_s_grouped_bf16": args.batch / (res["bf16"]["ms"] * 1e-3),
@@ -201,23 +212,110 @@ def run_batched(args):
                       "bf16_value": work / (res["bf16"]["ms"] * 1e-3),
                       "group_create_s": {k: round(v["create_s"], 3) for k, v in res.items()},
                       "launches_per_iter": g32["info"]["launches_per_iter"],
-                      "tuned_mttkrp_grid": g32["info"]["mttkrp_grid"],
+                      "tuned_mttkrp_forms": {
+                          k: [dict(cpl=c, lanes=l, chunks_per_group=q, grid=gr, of=nf)
+                              for c, l, q, gr, nf in zip(v["info"]["mttkrp_cpl"],
+                                                         v["info"]["mttkrp_lanes"],
+                                                         v["info"]["mttkrp_chunks_per_group"],
+                                                         v["info"]["mttkrp_grid"],
+                                                         v["info"]["mttkrp_forms"])]
+                          for k, v in res.items()},
                       "group_bytes": g32["info"]["bytes"],
                       "mean_fit": {k: v["mean_fit"] for k, v in res.items()}}}
     print(json.dumps(line), flush=True)
     for m in members:
         m[0].close()
+    for c in bctx:
+        c.close()
     ctx.close()
 
 
+def _served_run(dfacto, np, pool, big, rate, n_warm, n_meas, dt, seed, large_frac):
+    """One sustained-load run: n_warm + n_meas Poisson arrivals at `rate`
+    per second (requests drawn from `pool`, a fraction large_frac of them
+    `big`), submitted in real time; a collector thread waits for results in
+    submission order and keeps only their timings (the factors are dropped
+    as they arrive).  Latency = submission to factors in host memory."""
+    import queue
+    import threading
+    rng = np.random.default_rng(seed)
+    n = n_warm + n_meas
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+    picks = [big if (big is not None and rng.random() < large_frac)
+             else pool[int(rng.integers(len(pool)))] for _ in range(n)]
+    srv = dfacto.Server(0, max_slots=64)
+    q = queue.Queue()
+    recs = [None] * n
+
+    def collect():
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            idx, rid = item
+            r = srv.wait(rid)
+            recs[idx] = (r["status"], r["iters"], r["t_submit"], r["t_admit"], r["t_done"])
+
+    th = threading.Thread(target=collect, daemon=True)
+    th.start()
+    start = time.perf_counter()
+    for idx, (a, (coo, R, F0)) in enumerate(zip(arrivals, picks)):
+        now = time.perf_counter() - start
+        if a > now:
+            time.sleep(a - now)
+        q.put((idx, srv.submit(coo.dims, coo.i, coo.j, coo.k, coo.val, R, F0, dtype=dt,
+                               tol=1e-4, max_iters=50)))
+        if idx == n_warm - 1:
+            log(f"    {dt} {rate:g}/s: warm-up submitted at {time.perf_counter() - start:.1f}s")
+    submit_s = time.perf_counter() - start
+    q.put(None)
+    th.join()
+    st = srv.stats()
+    srv.close()
+    meas = recs[n_warm:]
+    lat = np.array([r[4] - r[2] for r in meas])
+    t_first = min(r[2] for r in meas)
+    t_last = max(r[4] for r in meas)
+    served = n_meas / (t_last - t_first)
+    offered = n_meas / (arrivals[-1] - arrivals[n_warm])
+    qn = max(1, n_meas // 4)
+    p50_first = float(np.median(lat[:qn]))
+    p50_last = float(np.median(lat[-qn:]))
+    # sustained: the device keeps up (served >= 95% of offered) and the
+    # queue does not grow (the last quarter's median latency at most twice
+    # the first quarter's, plus 50 ms)
+    sustained = bool(served >= 0.95 * offered and p50_last <= 2.0 * p50_first + 0.05)
+    big_lat = [r[4] - r[2] for r, p in zip(meas, picks[n_warm:]) if p is big]
+    out = dict(offered_per_s=round(offered, 2), solves_per_s=round(served, 2),
+               p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 2),
+               p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 2),
+               p50_first_quarter_ms=round(p50_first * 1e3, 2),
+               p50_last_quarter_ms=round(p50_last * 1e3, 2), sustained=sustained,
+               warmup_requests=n_warm, measured_requests=n_meas,
+               mean_iters=round(float(np.mean([r[1] for r in meas])), 2),
+               failed=int(sum(r[0] != dfacto.OK for r in recs)),
+               peak_active=st["peak_active"], boundaries=st["iterations"],
+               large_requests=len(big_lat),
+               large_p50_ms=round(float(np.percentile(big_lat, 50)) * 1e3, 1) if big_lat else None,
+               submit_span_s=round(submit_s, 2), span_s=round(t_last - t_first, 2),
+               budget_gb=round(st["budget"] / 1e9, 1),
+               worker_s={k: round(st[k], 3) for k in
+                         ("t_admit", "t_build", "t_groups", "t_iterate", "t_deliver")})
+    log(f"    {dt} {rate:g}/s: {out}")
+    return out
+
+
 def run_served(args):
-    """Served CP-ALS: Poisson arrivals (args.rate per second for
-    args.duration seconds) of solves drawn from the batched distribution,
-    plus args.large_frac of 50M-nonzero 1M x 500K x 200K requests, each run to
-    a fit change below 1e-4 or 50 iterations, admitted by device footprint
-    and batched continuously.  Reported per storage dtype: completed solves
-    per second over the run and p50 / p99 latency from submission to factors
-    on the host."""
+    """Served CP-ALS under sustained load: Poisson arrivals at args.rate per
+    second of solves drawn from the batched distribution plus args.large_frac
+    of 50M-nonzero 1M x 500K x 200K requests, each run to a fit change below
+    1e-4 or 50 iterations, admitted by device footprint and batched
+    continuously.  args.served_warmup requests warm the server up, then
+    args.served_requests are measured: completed solves per second over the
+    measured requests' span, p50 / p99 latency (submission to factors in
+    host memory) and whether the load was sustained.  With --rate-search,
+    also the highest offered rate (steps of 25/s) that is sustained, per
+    storage dtype, on shorter runs."""
     import numpy as np
     from paper_1406_4519_amd import dfacto, gen
 
@@ -232,54 +330,45 @@ def run_served(args):
         Rb = 32
         big = (coo, Rb, [f.astype(np.float32) for f in gen.init_factors(coo.dims, Rb, seed=1007)])
     log(f"generated the request pool in {time.perf_counter() - t0:.1f}s")
-    rng = np.random.default_rng(12345)
-    n = max(1, int(rng.poisson(args.rate * args.duration)))
-    arrivals = np.sort(rng.uniform(0.0, args.duration, n))
-    picks = [big if (big is not None and rng.random() < args.large_frac)
-             else pool[int(rng.integers(len(pool)))] for _ in range(n)]
     out = {}
     for dt in args.served_dtypes.split(","):
-        srv = dfacto.Server(0, max_slots=64)
-        ids = []
-        start = time.perf_counter()
-        for a, (coo, R, F0) in zip(arrivals, picks):
-            now = time.perf_counter() - start
-            if a > now:
-                time.sleep(a - now)
-            ids.append(srv.submit(coo.dims, coo.i, coo.j, coo.k, coo.val, R, F0, dtype=dt,
-                                  tol=1e-4, max_iters=50))
-        res = [srv.wait(i) for i in ids]
-        st = srv.stats()
-        srv.close()
-        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
-        span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
-        big_lat = [r["t_done"] - r["t_submit"] for r, p in zip(res, picks) if p is big]
-        out[dt] = dict(solves_per_s=n / span, p50_ms=float(np.percentile(lat, 50) * 1e3),
-                       p99_ms=float(np.percentile(lat, 99) * 1e3),
-                       mean_iters=float(np.mean([r["iters"] for r in res])),
-                       failed=int(sum(r["status"] != dfacto.OK for r in res)),
-                       peak_active=st["peak_active"], boundaries=st["iterations"],
-                       large_requests=len(big_lat),
-                       large_p50_ms=float(np.percentile(big_lat, 50) * 1e3) if big_lat else None,
-                       span_s=span, budget_gb=round(st["budget"] / 1e9, 1), worker_s={k: round(st[k], 3) for k in
-                                              ("t_admit", "t_build", "t_groups", "t_iterate", "t_deliver")})
-        log(f"{dt}: {out[dt]}")
-    served_line(args, n, out)
+        log(f"  {dt}: {args.served_warmup} + {args.served_requests} requests at {args.rate:g}/s")
+        out[dt] = _served_run(dfacto, np, pool, big, args.rate, args.served_warmup,
+                              args.served_requests, dt, 12345, args.large_frac)
+    search = {}
+    if args.rate_search:
+        for dt in args.served_dtypes.split(","):
+            best, tried = None, []
+            rate = 50.0
+            while rate <= args.rate:
+                r = _served_run(dfacto, np, pool, big, rate, 100, args.search_requests, dt,
+                                777, args.large_frac)
+                tried.append(dict(rate=rate, solves_per_s=r["solves_per_s"],
+                                  p50_ms=r["p50_ms"], p99_ms=r["p99_ms"],
+                                  sustained=r["sustained"]))
+                if not r["sustained"]:
+                    break
+                best = dict(rate=rate, **{k: r[k] for k in ("solves_per_s", "p50_ms", "p99_ms")})
+                rate += 25.0
+            search[dt] = dict(highest_sustained=best, tried=tried)
+    served_line(args, out, search)
 
 
-def served_line(args, n, out):
+def served_line(args, out, search):
     f = out["f32"] if "f32" in out else next(iter(out.values()))
+    n = f["measured_requests"]
     line = {"metric": "served CP-ALS solves/s, p50/p99 latency",
             "value": f["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": n,
-            "warmup": 0, "ms_per_step": round(f["span_s"] * 1e3 / n, 4),
+            "warmup": f["warmup_requests"], "ms_per_step": round(f["span_s"] * 1e3 / n, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32" if "f32" in out else next(iter(out)), "data": "synthetic",
-            "config": {"workload": f"served: Poisson {args.rate:g}/s for {args.duration:g}s, "
-                                   f"batched-distribution solves + {args.large_frac:g} 50M-nonzero "
+            "config": {"workload": f"served: Poisson {args.rate:g}/s, {args.served_warmup} warm-up "
+                                   f"+ {args.served_requests} measured requests, batched-"
+                                   f"distribution solves + {args.large_frac:g} 50M-nonzero "
                                    f"1M x 500K x 200K requests, fit change < 1e-4 or 50 "
                                    f"iterations, continuous batching",
                        "requests": n, "parallelism": "single GPU"},
-            "extra": out}
+            "extra": dict(out, rate_search=search or None)}
     print(json.dumps(line), flush=True)
 
 
@@ -500,8 +589,11 @@ def run_tensor(args):
     torch.cuda.synchronize()
     log(f"generated in {time.perf_counter() - t0:.1f}s")
     sample = None if args.no_cpu_baseline else _dev_sample(i, j, k, v, args.cpu_sample)
-    torch.cuda.empty_cache()
-    ctx = dfacto.Context(0)
+    # the library allocates through torch's caching allocator: the build
+    # reuses device memory the input generator has already mapped (fresh
+    # device memory is mapped and cleared by the driver at a few tens of
+    # GB/s, which would dominate the build's time)
+    ctx = dfacto.Context(0, allocator="torch")
     torch.cuda.synchronize()
     tb = time.perf_counter()
     T = dfacto.build_flattenings(ctx, dims, i, j, k, v)
@@ -730,7 +822,9 @@ def run_tensor(args):
             "roofline": roofline, "cpu_baseline": cpu,
             "extra": {"timed_as": "HIP graph replay of the step" if head["graph_replay_equals_eager"]
                       else "eager launches",
-                      "build_ms": round(build_ms, 1), "nfib": list(info["nfib"]),
+                      "build_ms": round(build_ms, 1),
+                      "build_memory": "torch caching allocator (memory the generator mapped)",
+                      "relabeled": info["relabeled"], "nfib": list(info["nfib"]),
                       "nroot": list(info["nroot"]), "nentry": list(info["nentry"]),
                       "runs": runs, "gather_ceiling": ceiling, "cold_mttkrp": cold,
                       "gd_iterations": gd_iters,
@@ -758,9 +852,17 @@ def main():
                              "joint"])
     ap.add_argument("--batch", type=int, default=256, help="batched workload: number of tensors")
     ap.add_argument("--iters", type=int, default=20, help="batched workload: ALS iterations")
+    ap.add_argument("--build-threads", type=int, default=1,
+                    help="batched workload: host threads building the tensors")
     ap.add_argument("--rate", type=float, default=200.0, help="served workload: arrivals per second")
-    ap.add_argument("--duration", type=float, default=1.0,
-                    help="served workload: seconds of Poisson arrivals")
+    ap.add_argument("--served-warmup", type=int, default=200,
+                    help="served workload: warm-up requests (not measured)")
+    ap.add_argument("--served-requests", type=int, default=4000,
+                    help="served workload: measured requests")
+    ap.add_argument("--rate-search", action="store_true",
+                    help="served workload: also find the highest sustained rate")
+    ap.add_argument("--search-requests", type=int, default=600,
+                    help="served workload: measured requests per rate-search run")
     ap.add_argument("--large-frac", type=float, default=0.05,
                     help="served workload: fraction of 50M-nonzero requests")
     ap.add_argument("--pool", type=int, default=48, help="served workload: distinct small tensors")

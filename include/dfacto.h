@@ -171,12 +171,24 @@ dfacto_status dfacto_build_flattenings(dfacto_ctx *ctx, const int64_t dims[3], i
 #define DFACTO_BUILD_RELABEL 1
 #define DFACTO_BUILD_NO_RELABEL 2
 
-/* dfacto_build_flattenings with build flags (above).  Errors as there, and
- * DFACTO_E_INVALID for unknown or contradictory flags. */
+/* Default stream entries per MTTKRP work chunk (a chunk is the unit of work
+ * of one lane group; it ends at the first header at or after a multiple of
+ * the chunk length). */
+#define DFACTO_CHUNK_DEFAULT 512
+
+/* dfacto_build_flattenings with build flags (above) and the work-chunk
+ * length: chunk_len stream entries per chunk, 0 for DFACTO_CHUNK_DEFAULT,
+ * else in [256, 2^20].  Longer chunks mean fewer carries to fix up and
+ * fewer, longer work items; shorter ones spread a small tensor over more
+ * lanes.  A row split over chunks is summed from per-chunk partial sums, so
+ * results of different chunk lengths agree up to FP32 rounding, not
+ * bitwise.  Errors as dfacto_build_flattenings, and
+ * DFACTO_E_INVALID for unknown or contradictory flags or a chunk length out
+ * of range. */
 dfacto_status dfacto_build_flattenings_ex(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
                                           const uint32_t *d_i, const uint32_t *d_j,
                                           const uint32_t *d_k, const float *d_val, int flags,
-                                          dfacto_tensor **out);
+                                          int chunk_len, dfacto_tensor **out);
 
 typedef struct {
     int64_t dims[3];
@@ -188,6 +200,7 @@ typedef struct {
     double normsq;      /* ||X||^2 in FP64 */
     size_t bytes;       /* device bytes held by the tensor */
     int relabeled;      /* 1 when built with relabeled gathers */
+    int chunk_len;      /* stream entries per work chunk (target) */
 } dfacto_tensor_info;
 
 dfacto_status dfacto_tensor_get_info(const dfacto_tensor *t, dfacto_tensor_info *info);
@@ -200,6 +213,17 @@ dfacto_status dfacto_tensor_export(dfacto_ctx *ctx, const dfacto_tensor *t, int 
                                    uint32_t *h_root_id, int64_t *h_root_ptr,
                                    uint32_t *h_fib_mid, int64_t *h_fib_ptr,
                                    uint32_t *h_leaf, float *h_val);
+
+/* The row order of a relabeled mode's gathered table, for inspection and
+ * tests: h_order[r] = the factor row ranked r, in the order of decreasing
+ * gather count (table 0: the leaf table, counting the nonzeros of each leaf
+ * row; table 1: the mid table, counting the fiber segment headers of each
+ * mid row; ties by row index).  h_order holds dims[leaf] or dims[mid]
+ * entries (leaf of mode n is mode (n+1) mod 3, mid is (n+2) mod 3).
+ * Errors: DFACTO_E_INVALID for a NULL argument, a bad mode or table, or a
+ * tensor built without relabeling.  Synchronizes. */
+dfacto_status dfacto_tensor_gather_order(dfacto_ctx *ctx, const dfacto_tensor *t, int mode,
+                                         int table, uint32_t *h_order);
 
 /* Free a tensor (waits for the device).  NULL is ignored. */
 void dfacto_tensor_destroy(dfacto_tensor *t);
@@ -288,9 +312,11 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R,
  * ctx's stream by events at each call.
  *
  * flags: DFACTO_GROUP_GRAPH captures one iteration as a HIP graph on the
- * first dfacto_group_als call and replays it; DFACTO_GROUP_TUNE times the
- * MTTKRP launches with several persistent grid sizes at creation and keeps
- * the fastest (results do not depend on the choice); DFACTO_GROUP_CTX_STREAM
+ * first dfacto_group_als call and replays it; DFACTO_GROUP_TUNE times each
+ * MTTKRP launch at creation in several forms -- persistent grid sizes of 2
+ * to 32 workgroups per CU, fewer factor columns per lane (more lanes per
+ * group), 1, 2 or 4 work chunks per lane group -- and keeps the fastest
+ * (results do not depend on the choice); DFACTO_GROUP_CTX_STREAM
  * launches on the creating context's stream instead of a stream of the
  * group's own (cheaper to create and free; later calls must pass a context
  * with that same stream).  Creation enqueues the upload and device-side
@@ -310,6 +336,10 @@ typedef struct {
     int graph;              /* 1 when iterations replay a captured graph */
     int mttkrp_classes;     /* MTTKRP launches per iteration */
     int mttkrp_grid[16];    /* their persistent grid sizes (first 16) */
+    int mttkrp_cpl[16];     /* factor columns per lane */
+    int mttkrp_lanes[16];   /* lanes per group */
+    int mttkrp_chunks_per_group[16];  /* work chunks each lane group takes in turn */
+    int mttkrp_forms[16];   /* launch forms considered (1 without tuning) */
 } dfacto_group_info;
 
 dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *const *tensors,
@@ -322,6 +352,17 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
 dfacto_status dfacto_group_als(dfacto_ctx *ctx, dfacto_group *g, int iters);
 
 dfacto_status dfacto_group_get_info(const dfacto_group *g, dfacto_group_info *info);
+
+/* Choose MTTKRP launch class `cls`'s form explicitly: form index `form`
+ * among the mttkrp_forms[cls] forms (form 0 is the default; a group created
+ * without DFACTO_GROUP_TUNE has only that one) and persistent grid size
+ * `grid` (>= 1 workgroups).  For callers that replay a choice recorded from
+ * an earlier tuning, and for tests of every form; results do not depend on
+ * it.  A captured iteration graph is dropped and captured again at the
+ * next dfacto_group_als.  Must not overlap a dfacto_group_als call on the
+ * same group.  Errors: DFACTO_E_INVALID (NULL group, index or grid out of
+ * range). */
+dfacto_status dfacto_group_set_form(dfacto_group *g, int cls, int form, int grid);
 
 /* Free the group (waits for its stream).  NULL is ignored. */
 void dfacto_group_destroy(dfacto_group *g);

@@ -358,15 +358,41 @@ __global__ void k_emit_stream(const uint32_t *__restrict__ root, const uint32_t 
     }
 }
 
-// gathers per row: every nonzero gathers its leaf row, every header (fiber
-// start or segment start) its mid row
-__global__ void k_count_gathers(const uint32_t *__restrict__ leaf, const uint32_t *__restrict__ mid,
-                                const uint32_t *__restrict__ h, int64_t n,
-                                uint32_t *__restrict__ cnt_leaf, uint32_t *__restrict__ cnt_mid) {
+// Gathers per row: every nonzero gathers its leaf row, every header (fiber
+// start or segment start) its mid row.  Skewed indices put millions of
+// counts on a few rows, so the counts are not accumulated with atomics (they
+// serialize on those rows' addresses): the gathered indices are radix-sorted
+// and each row's count is the length of its run.
+// (k_count_input) the indices to sort: all of them, or those with flag[e]
+// set, compacted through pos (the exclusive scan of flag)
+__global__ void k_count_input(const uint32_t *__restrict__ idx, const uint32_t *__restrict__ flag,
+                              const uint32_t *__restrict__ pos, int64_t n,
+                              uint64_t *__restrict__ key, uint32_t *__restrict__ val) {
     GRID_STRIDE(e, n) {
-        atomicAdd(&cnt_leaf[leaf[e]], 1u);
-        if (h[e]) atomicAdd(&cnt_mid[mid[e]], 1u);
+        if (!flag) {
+            key[e] = idx[e];
+            val[e] = 0u;
+        } else if (flag[e]) {
+            key[pos[e]] = idx[e];
+            val[pos[e]] = 0u;
+        }
     }
+}
+
+// [beg[r], end[r]) = the run of row r in the sorted keys (rows absent from
+// the keys keep the zeros they were filled with)
+__global__ void k_run_bounds(const uint64_t *__restrict__ key, int64_t n,
+                             uint32_t *__restrict__ beg, uint32_t *__restrict__ end) {
+    GRID_STRIDE(e, n) {
+        const uint64_t k = key[e];
+        if (e == 0 || key[e - 1] != k) beg[k] = (uint32_t)e;
+        if (e == n - 1 || key[e + 1] != k) end[k] = (uint32_t)(e + 1);
+    }
+}
+
+__global__ void k_run_lengths(const uint32_t *__restrict__ beg, const uint32_t *__restrict__ end,
+                              int64_t rows, uint32_t *__restrict__ cnt) {
+    GRID_STRIDE(r, rows) cnt[r] = end[r] - beg[r];
 }
 
 // sort key: count descending (a stable sort keeps equal counts in index order)
@@ -565,11 +591,39 @@ void finish_runs(dfacto_tensor *t, ModeData &md, hipStream_t s, const std::vecto
     md.runs_long_host = std::move(longr);
 }
 
+// cnt[r] = occurrences of row r among the n indices idx (flag null) or among
+// those with flag[e] set (m of them; pos = the exclusive scan of flag), for
+// rows r < rows.
+void count_rows(const uint32_t *idx, const uint32_t *flag, const uint32_t *pos, int64_t n,
+                int64_t m, int64_t rows, uint32_t *cnt, Scratch &sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(rows)), dim3(kThreads), 0, s, cnt, rows, 0u);
+    DF_LAUNCHED();
+    if (m == 0) return;
+    uint64_t *key = sc.alloc<uint64_t>(m), *kalt = sc.alloc<uint64_t>(m);
+    uint32_t *val = sc.alloc<uint32_t>(m), *valt = sc.alloc<uint32_t>(m);
+    hipLaunchKernelGGL(k_count_input, dim3(grid_for(n)), dim3(kThreads), 0, s, idx, flag, pos, n,
+                       key, val);
+    DF_LAUNCHED();
+    radix_sort(key, val, kalt, valt, m, bits_for(rows), sc, s);
+    uint32_t *beg = sc.alloc<uint32_t>(rows), *end = sc.alloc<uint32_t>(rows);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(rows)), dim3(kThreads), 0, s, beg, rows, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(rows)), dim3(kThreads), 0, s, end, rows, 0u);
+    hipLaunchKernelGGL(k_run_bounds, dim3(grid_for(m)), dim3(kThreads), 0, s, key, m, beg, end);
+    hipLaunchKernelGGL(k_run_lengths, dim3(grid_for(rows)), dim3(kThreads), 0, s, beg, end, rows,
+                       cnt);
+    DF_LAUNCHED();
+    sc.release(end);
+    sc.release(beg);
+    sc.release(valt);
+    sc.release(val);
+    sc.release(kalt);
+    sc.release(key);
+}
+
 // The order of a gathered table's rows by decreasing gather count (ties by
-// index): perm[r] = the row ranked r (tensor memory).  The counts of the
-// first kTopRows ranks go to `top` (host), landing at the build's next wait.
+// index): perm[r] = the row ranked r (tensor memory).
 uint32_t *relabel_order(dfacto_tensor *t, const uint32_t *cnt, int64_t rows, Scratch &sc,
-                        hipStream_t s, std::vector<uint32_t> &top) {
+                        hipStream_t s) {
     uint64_t *key = sc.alloc<uint64_t>(rows), *kalt = sc.alloc<uint64_t>(rows);
     uint32_t *idx = sc.alloc<uint32_t>(rows), *ialt = sc.alloc<uint32_t>(rows);
     hipLaunchKernelGGL(k_count_keys, dim3(grid_for(rows)), dim3(kThreads), 0, s, cnt, rows, key,
@@ -578,11 +632,6 @@ uint32_t *relabel_order(dfacto_tensor *t, const uint32_t *cnt, int64_t rows, Scr
     radix_sort(key, idx, kalt, ialt, rows, 32, sc, s);
     uint32_t *perm = tensor_alloc<uint32_t>(t, rows);
     DF_HIP(hipMemcpyAsync(perm, idx, sizeof(uint32_t) * (size_t)rows, hipMemcpyDeviceToDevice, s));
-    const int64_t nt = std::min<int64_t>(rows, kTopRows);
-    std::vector<uint64_t> *keys = new std::vector<uint64_t>((size_t)nt);
-    t->pending_top.push_back({keys, &top});
-    DF_HIP(hipMemcpyAsync(keys->data(), key, sizeof(uint64_t) * (size_t)nt, hipMemcpyDeviceToHost,
-                          s));
     return perm;
 }
 
@@ -595,11 +644,7 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     ModeData &md = t->mode[m];
     const int64_t nrows = t->dims[md.root];
     Scratch sc(s, ctx->mem);
-    int chunk_len = 4 * kFiberCap;
-    if (const char *env = getenv("DFACTO_CHUNK")) {
-        const int v = atoi(env);
-        if (v >= 2 * kFiberCap && v <= (1 << 20)) chunk_len = v;
-    }
+    const int chunk_len = t->chunk_len;
     md.chunk_len = chunk_len;
     if (n == 0) {
         md.nentry = 0;
@@ -664,13 +709,10 @@ void build_mode(dfacto_ctx *ctx, dfacto_tensor *t, int m, const uint32_t *root,
     if (t->relabel) {
         const int64_t dl = t->dims[md.leaf], dm = t->dims[md.mid];
         uint32_t *cl = sc.alloc<uint32_t>(dl), *cm = sc.alloc<uint32_t>(dm);
-        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(dl)), dim3(kThreads), 0, s, cl, dl, 0u);
-        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(dm)), dim3(kThreads), 0, s, cm, dm, 0u);
-        hipLaunchKernelGGL(k_count_gathers, dim3(grid_for(n)), dim3(kThreads), 0, s, leaf, mid, h, n,
-                           cl, cm);
-        DF_LAUNCHED();
-        md.perm_leaf = relabel_order(t, cl, dl, sc, s, md.top_leaf);
-        md.perm_mid = relabel_order(t, cm, dm, sc, s, md.top_mid);
+        count_rows(leaf, nullptr, nullptr, n, n, dl, cl, sc, s);
+        count_rows(mid, h, hex, n, nhdr, dm, cm, sc, s);
+        md.perm_leaf = relabel_order(t, cl, dl, sc, s);
+        md.perm_mid = relabel_order(t, cm, dm, sc, s);
         uint32_t *il = sc.alloc<uint32_t>(dl), *im = sc.alloc<uint32_t>(dm);
         hipLaunchKernelGGL(k_invert, dim3(grid_for(dl)), dim3(kThreads), 0, s, md.perm_leaf, dl, il);
         hipLaunchKernelGGL(k_invert, dim3(grid_for(dm)), dim3(kThreads), 0, s, md.perm_mid, dm, im);
@@ -788,17 +830,6 @@ void build_row_ranges(dfacto_ctx *ctx, dfacto_tensor *t) {
     DF_HIP(hipStreamSynchronize(s));
 }
 
-// the top gather counts copied during the build, as counts
-void take_top_counts(dfacto_tensor *t) {
-    for (auto &p : t->pending_top) {
-        p.second->resize(p.first->size());
-        for (size_t r = 0; r < p.first->size(); ++r)
-            (*p.second)[r] = 0xFFFFFFFFu - (uint32_t)(*p.first)[r];
-        delete p.first;
-    }
-    t->pending_top.clear();
-}
-
 void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const uint32_t *d_j,
                   const uint32_t *d_k, const float *d_val) {
     hipStream_t s = ctx->stream;
@@ -902,8 +933,7 @@ void build_tensor(dfacto_ctx *ctx, dfacto_tensor *t, const uint32_t *d_i, const 
         DF_LAUNCHED();
         build_mode(ctx, t, m, gr, gm, gl, gv, nd, heads[m]);
     }
-    DF_HIP(hipStreamSynchronize(s));  // the chunk heads, ||X||^2, the top counts
-    take_top_counts(t);
+    DF_HIP(hipStreamSynchronize(s));  // the chunk heads, ||X||^2
     for (int m = 0; m < 3; ++m) finish_runs(t, t->mode[m], s, heads[m]);
     DF_HIP(hipStreamSynchronize(s));  // the run lists' uploads
 }

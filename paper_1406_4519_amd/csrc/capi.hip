@@ -154,7 +154,7 @@ namespace dfacto {
 dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
                                      const uint32_t *d_i, const uint32_t *d_j,
                                      const uint32_t *d_k, const float *d_val, dfacto_tensor **out,
-                                     bool async_alloc, int flags) {
+                                     bool async_alloc, int flags, int chunk_len) {
     if (out) *out = nullptr;
     return guarded(ctx, [&] {
         if (!out || !dims) throw Error{DFACTO_E_INVALID, "dims or out is NULL"};
@@ -169,7 +169,10 @@ dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int
         if (flags & ~(DFACTO_BUILD_RELABEL | DFACTO_BUILD_NO_RELABEL) ||
             (flags & DFACTO_BUILD_RELABEL && flags & DFACTO_BUILD_NO_RELABEL))
             throw Error{DFACTO_E_INVALID, "bad build flags"};
+        if (chunk_len != 0 && (chunk_len < 2 * kFiberCap || chunk_len > (1 << 20)))
+            throw Error{DFACTO_E_INVALID, "chunk_len must be 0 or in [256, 2^20]"};
         dfacto_tensor *t = new dfacto_tensor();
+        t->chunk_len = chunk_len ? chunk_len : DFACTO_CHUNK_DEFAULT;
         t->relabel = (flags & DFACTO_BUILD_RELABEL) ||
                      (!(flags & DFACTO_BUILD_NO_RELABEL) && nnz >= kRelabelMinNnz);
         t->device = ctx->device;
@@ -179,14 +182,46 @@ dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int
         }
         for (int m = 0; m < 3; ++m) t->dims[m] = dims[m];
         t->nnz = nnz;
+        // Without a memory source of the caller's, the build's temporaries
+        // come from a pool of the context that keeps freed memory mapped
+        // until the build ends (memory given back to the device is mapped
+        // afresh, and cleared, at each later allocation), then gives it all
+        // back.
+        hipMemPool_t pool = nullptr;
+        if (!ctx->mem.has_user() && !ctx->mem.pool) {
+            if (!ctx->build_pool) {
+                hipMemPoolProps props{};
+                props.allocType = hipMemAllocationTypePinned;
+                props.location.type = hipMemLocationTypeDevice;
+                props.location.id = ctx->device;
+                uint64_t keep = UINT64_MAX;
+                if (hipMemPoolCreate(&ctx->build_pool, &props) != hipSuccess ||
+                    hipMemPoolSetAttribute(ctx->build_pool, hipMemPoolAttrReleaseThreshold,
+                                           &keep) != hipSuccess) {
+                    (void)hipGetLastError();  // fall back to the default pool
+                    if (ctx->build_pool) (void)hipMemPoolDestroy(ctx->build_pool);
+                    ctx->build_pool = nullptr;
+                }
+            }
+            pool = ctx->build_pool;
+        }
+        auto drop_pool = [&] {
+            if (!pool) return;
+            ctx->mem.pool = nullptr;
+            (void)hipStreamSynchronize(ctx->stream);  // the temporaries' frees
+            (void)hipMemPoolTrimTo(pool, 0);
+        };
+        ctx->mem.pool = pool ? pool : ctx->mem.pool;
         try {
             build_tensor(ctx, t, d_i, d_j, d_k, d_val);
         } catch (...) {
             // copies into the tensor's host fields may still be pending
             (void)hipStreamSynchronize(ctx->stream);
+            drop_pool();
             dfacto_tensor_destroy(t);
             throw;
         }
+        drop_pool();
         *out = t;
     });
 }
@@ -196,7 +231,7 @@ dfacto_status build_flattenings_async_alloc(dfacto_ctx *ctx, const int64_t dims[
                                             const uint32_t *d_k, const float *d_val,
                                             dfacto_tensor **out) {
     return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, true,
-                                  DFACTO_BUILD_NO_RELABEL);
+                                  DFACTO_BUILD_NO_RELABEL, 0);
 }
 
 }  // namespace dfacto
@@ -262,6 +297,7 @@ void dfacto_ctx_destroy(dfacto_ctx *ctx) {
         else (void)hipFree(ctx->ws[s]);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->build_pool) (void)hipMemPoolDestroy(ctx->build_pool);
     if (prev >= 0) (void)hipSetDevice(prev);
     delete ctx;
 }
@@ -275,14 +311,15 @@ dfacto_status dfacto_build_flattenings(dfacto_ctx *ctx, const int64_t dims[3], i
                                        const uint32_t *d_i, const uint32_t *d_j,
                                        const uint32_t *d_k, const float *d_val,
                                        dfacto_tensor **out) {
-    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, false, 0);
+    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, false, 0, 0);
 }
 
 dfacto_status dfacto_build_flattenings_ex(dfacto_ctx *ctx, const int64_t dims[3], int64_t nnz,
                                           const uint32_t *d_i, const uint32_t *d_j,
                                           const uint32_t *d_k, const float *d_val, int flags,
-                                          dfacto_tensor **out) {
-    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, false, flags);
+                                          int chunk_len, dfacto_tensor **out) {
+    return build_flattenings_impl(ctx, dims, nnz, d_i, d_j, d_k, d_val, out, false, flags,
+                                  chunk_len);
 }
 
 dfacto_status dfacto_tensor_get_info(const dfacto_tensor *t, dfacto_tensor_info *info) {
@@ -296,6 +333,7 @@ dfacto_status dfacto_tensor_get_info(const dfacto_tensor *t, dfacto_tensor_info 
         info->nchunk[m] = t->mode[m].nchunk;
     }
     info->relabeled = t->relabel ? 1 : 0;
+    info->chunk_len = t->chunk_len;
     info->nnz = t->nnz;
     info->normsq = t->normsq;
     info->bytes = t->bytes;
@@ -363,9 +401,24 @@ dfacto_status dfacto_tensor_export(dfacto_ctx *ctx, const dfacto_tensor *t, int 
     });
 }
 
+dfacto_status dfacto_tensor_gather_order(dfacto_ctx *ctx, const dfacto_tensor *t, int mode,
+                                         int table, uint32_t *h_order) {
+    return guarded(ctx, [&] {
+        if (!t || !h_order) throw Error{DFACTO_E_INVALID, "tensor or output is NULL"};
+        if (mode < 0 || mode > 2) throw Error{DFACTO_E_INVALID, "mode must be 0, 1 or 2"};
+        if (table != 0 && table != 1) throw Error{DFACTO_E_INVALID, "table must be 0 or 1"};
+        const ModeData &md = t->mode[mode];
+        if (!md.perm_leaf) throw Error{DFACTO_E_INVALID, "the tensor is not relabeled"};
+        const uint32_t *src = table == 0 ? md.perm_leaf : md.perm_mid;
+        const int64_t rows = t->dims[table == 0 ? md.leaf : md.mid];
+        DF_HIP(hipMemcpyAsync(h_order, src, sizeof(uint32_t) * (size_t)rows,
+                              hipMemcpyDeviceToHost, ctx->stream));
+        DF_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
 void dfacto_tensor_destroy(dfacto_tensor *t) {
     if (!t) return;
-    for (auto &p : t->pending_top) delete p.first;  // a build that failed midway
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(t->device);
@@ -611,7 +664,7 @@ dfacto_status dfacto_build_ratings(dfacto_ctx *ctx, const int64_t dims[2], int64
         dfacto_tensor *t = nullptr;
         // the joint rows read the ratings' streams directly: plain indices
         const dfacto_status st = dfacto_build_flattenings_ex(ctx, d3, n, d_i, d_j, k0, d_y,
-                                                             DFACTO_BUILD_NO_RELABEL, &t);
+                                                             DFACTO_BUILD_NO_RELABEL, 0, &t);
         ctx->mem.free(k0, ctx->stream);
         if (st != DFACTO_OK) throw Error{st, ctx->err};
         try {

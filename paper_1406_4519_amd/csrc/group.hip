@@ -8,9 +8,10 @@
 // block) pairs.  Per member the arithmetic, the work split and the order of
 // every reduction are those of dfacto_als_iter, so the results are bitwise
 // the same as running the members one by one.  One iteration can be captured
-// once as a HIP graph and replayed.  A small autotuner picks the persistent
-// grid size of each MTTKRP kernel class by timing candidates on the group's
-// own data (the grid size does not change any result).
+// once as a HIP graph and replayed.  A small autotuner picks the launch form
+// of each MTTKRP kernel class (persistent grid size, columns per lane, chunks
+// per lane group) by timing candidates on the group's
+// own data (none of these choices changes any result).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,8 +49,24 @@ struct dfacto_group {
     bool use_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    // persistent grid size of each MTTKRP launch (tuned or default)
-    std::vector<unsigned> grid_store;
+    // One grouped MTTKRP launch per kernel class and mode: its shape (columns
+    // per lane, lanes per group), chunks per lane group, work items (one
+    // table per item size) and persistent grid size.  The fix-ups after it
+    // keep the class's own shape (the carries do not depend on the one the
+    // MTTKRP ran with).  cands: the launch forms the tuner may choose.
+    struct MtVariant {
+        MttkrpShape sh;
+        unsigned kper;
+        const uint2 *items;
+        uint32_t nitems;
+    };
+    struct MtLaunch {
+        MtVariant v;
+        bool small;
+        unsigned grid;
+        std::vector<MtVariant> cands;
+    };
+    std::vector<MtLaunch> mt;
     // Small tables built on the host go to arena chunks (device memory of at
     // least 4 MB) through one host staging buffer per chunk, copied once the
     // group is built (the staging stays until the group is freed, so the
@@ -181,7 +198,8 @@ struct Build {
     double *fit;
     std::vector<MemberWs> ws;
     std::vector<std::function<void()>> mt_steps;  // the MTTKRP launches, for tuning
-    std::vector<size_t> mt_index;                 // their grid slots
+    std::vector<size_t> mt_index;                 // their entries in g->mt
+    bool tuning = false;                          // build the tuner's launch forms
     std::vector<std::function<void()>> post;      // table expansions, after upload_all
 
     // device space for a combined table; its expansion runs after upload_all
@@ -269,10 +287,34 @@ struct Build {
                 });
                 g->launches += 2;
             }
+            // launch forms per class: the default shape and, when tuning,
+            // fewer columns per lane (more lanes) and 2 or 4 chunks per lane
+            // group; one work-item table per item size
+            const bool tune = tuning;
+            auto forms = [tune](const MttkrpShape &sh, const std::vector<int> &ranks) {
+                std::vector<std::pair<MttkrpShape, unsigned>> f{{sh, 1u}};
+                if (!tune) return f;
+                std::vector<MttkrpShape> shapes{sh};
+                for (int c = sh.cpl / 2; sh.nch == 1 && c >= 1; c /= 2) {
+                    // lanes per group: enough for the widest member (the
+                    // lanes past a member's columns stay idle)
+                    int lanes = 1;
+                    for (int r : ranks) lanes = std::max(lanes, (r + c - 1) / c);
+                    int gv = 2;
+                    while (gv < lanes) gv <<= 1;
+                    if (gv <= 64) shapes.push_back({c, gv, 1});
+                }
+                for (const MttkrpShape &x : shapes)
+                    for (unsigned k : {1u, 2u, 4u})
+                        if (!(x.cpl == sh.cpl && x.g == sh.g && k == 1)) f.push_back({x, k});
+                return f;
+            };
             struct Cls {
                 MttkrpShape sh;
                 bool small;
-                Expansion<uint2> items, empty;
+                std::vector<int> ranks;
+                std::map<unsigned, Expansion<uint2>> items;  // by chunks per item
+                Expansion<uint2> empty;
                 Expansion<uint4> shortr, longr;
             };
             std::map<std::tuple<int, int, int, bool>, Cls> cls;
@@ -288,27 +330,53 @@ struct Build {
                 Cls &c = cls[{sh.cpl, sh.g, sh.nch, sm}];
                 c.sh = sh;
                 c.small = sm;
-                // (t, first chunk) items; (t, row, first chunk, chunks) runs;
-                // (t, row) empty rows -- from the member's own device lists
-                const uint32_t per = mttkrp_group_chunks_per_item(sh);
-                c.items.add(t, nullptr, (md.nchunk + per - 1) / per, 0, per);
+                c.ranks.push_back(R[t]);
                 c.shortr.add(t, md.runs_short, md.nruns_short, 3, 0);
                 c.longr.add(t, md.runs_long, md.nruns_long, 3, 0);
                 c.empty.add(t, md.empty_rows, md.nempty, 1, 0);
+            }
+            // (t, first chunk) work items per item size, from each member's
+            // chunk count; (t, row, first chunk, chunks) runs and (t, row)
+            // empty rows from the members' own device lists
+            for (auto &kv : cls) {
+                Cls &c = kv.second;
+                for (const auto &f : forms(c.sh, c.ranks)) {
+                    const unsigned per = mttkrp_group_chunks_per_item(f.first, f.second);
+                    if (c.items.count(per)) continue;
+                    Expansion<uint2> &x = c.items[per];
+                    for (int t = 0; t < n; ++t) {
+                        const ModeData &md = T[t]->mode[m];
+                        const MttkrpShape sh = mttkrp_shape(R[t], dt, desc[t].Fleaf, desc[t].Fmid,
+                                                            ws[t].M);
+                        if (sh.cpl != c.sh.cpl || sh.g != c.sh.g || sh.nch != c.sh.nch ||
+                            mttkrp_small(T[t], m) != c.small)
+                            continue;
+                        x.add(t, nullptr, (md.nchunk + per - 1) / per, 0, per);
+                    }
+                }
             }
             const GroupMttkrp *dd = upload(g, desc);
             for (auto &kv : cls) {
                 Cls &c = kv.second;
                 const MttkrpShape sh = c.sh;
                 const bool sm = c.small;
-                const uint2 *items = expand(c.items);
-                const uint32_t nitems = (uint32_t)c.items.total;
-                g->grid_store.push_back(
-                    std::max(1u, std::min<unsigned>(nitems, (unsigned)g->gctx.num_cu * 8)));
-                const size_t gi = g->grid_store.size() - 1;
-                auto step = [grp, dt, sh, sm, dd, items, nitems, gi] {
-                    launch_mttkrp_group(&grp->gctx, dt, sh, sm, dd, items, nitems,
-                                        grp->grid_store[gi]);
+                dfacto_group::MtLaunch L;
+                L.small = sm;
+                for (const auto &f : forms(c.sh, c.ranks)) {
+                    const Expansion<uint2> &x = c.items[mttkrp_group_chunks_per_item(f.first, f.second)];
+                    L.cands.push_back({f.first, f.second, nullptr, (uint32_t)x.total});
+                }
+                std::map<unsigned, const uint2 *> placed;
+                for (auto &kv2 : c.items) placed[kv2.first] = expand(kv2.second);
+                for (auto &v : L.cands) v.items = placed[mttkrp_group_chunks_per_item(v.sh, v.kper)];
+                L.v = L.cands[0];
+                L.grid = std::max(1u, std::min<unsigned>(L.v.nitems, (unsigned)g->gctx.num_cu * 8));
+                g->mt.push_back(L);
+                const size_t gi = g->mt.size() - 1;
+                auto step = [grp, dt, dd, gi] {
+                    const dfacto_group::MtLaunch &l = grp->mt[gi];
+                    launch_mttkrp_group(&grp->gctx, dt, l.v.sh, l.small, dd, l.v.items,
+                                        l.v.nitems, l.grid, l.v.kper);
                 };
                 g->steps.push_back(step);
                 mt_steps.push_back(step);
@@ -403,36 +471,57 @@ void run_steps(dfacto_group *g) {
     for (auto &f : g->steps) f();
 }
 
-// Time the MTTKRP steps of the group with several persistent grid sizes
-// and keep the fastest per kernel class.  Only the MTTKRP kernels run (they
-// write the group's own workspace, never the factors).
+// Time the MTTKRP steps of the group and keep the fastest launch form per
+// kernel class: first the persistent grid size of the default form (2 to 32
+// workgroups per CU), then every other form (shape, chunks per lane group)
+// at that grid, then the grid again for the winner.  Only the MTTKRP kernels
+// run (they write the group's own workspace, never the factors).
 void autotune(dfacto_group *g, const std::vector<std::function<void()>> &mt_steps,
               const std::vector<size_t> &mt_index) {
     hipEvent_t e0, e1;
     DF_HIP(hipEventCreate(&e0));
     DF_HIP(hipEventCreate(&e1));
-    const int cu = std::max(1, g->gctx.num_cu);
+    const unsigned cu = (unsigned)std::max(1, g->gctx.num_cu);
     for (size_t k = 0; k < mt_steps.size(); ++k) {
-        unsigned &grid = g->grid_store[mt_index[k]];
-        const unsigned cap = grid;  // min(items, 8 per CU)
-        unsigned best = grid;
-        float best_ms = 1e30f;
-        for (unsigned per_cu : {2u, 4u, 8u, 16u, 32u}) {
-            const unsigned cand = std::max(1u, std::min<unsigned>(cap * 4, (unsigned)cu * per_cu));
-            grid = cand;
+        dfacto_group::MtLaunch &L = g->mt[mt_index[k]];
+        auto time_it = [&]() {
             mt_steps[k]();  // warm
             DF_HIP(hipEventRecord(e0, g->stream));
-            for (int r = 0; r < 3; ++r) mt_steps[k]();
+            mt_steps[k]();
             DF_HIP(hipEventRecord(e1, g->stream));
             DF_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
             DF_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = cand;
+            return ms;
+        };
+        auto clamp = [&](unsigned want) {
+            return std::max(1u, std::min<unsigned>(want, std::max<uint32_t>(L.v.nitems, 1u)));
+        };
+        float best_ms = 1e30f;
+        dfacto_group::MtVariant best_v = L.v;
+        unsigned best_grid = L.grid;
+        auto grid_sweep = [&]() {
+            for (unsigned per_cu : {2u, 4u, 8u, 16u, 32u}) {
+                L.grid = clamp(cu * per_cu);
+                const float ms = time_it();
+                if (ms < best_ms) best_ms = ms, best_v = L.v, best_grid = L.grid;
             }
+        };
+        grid_sweep();
+        const unsigned grid0 = best_grid;
+        for (size_t c = 1; c < L.cands.size(); ++c) {
+            L.v = L.cands[c];
+            L.grid = clamp(grid0);
+            const float ms = time_it();
+            if (ms < best_ms) best_ms = ms, best_v = L.v, best_grid = L.grid;
         }
-        grid = best;
+        if (best_v.sh.cpl != L.cands[0].sh.cpl || best_v.sh.g != L.cands[0].sh.g ||
+            best_v.kper != L.cands[0].kper) {
+            L.v = best_v;
+            grid_sweep();
+        }
+        L.v = best_v;
+        L.grid = best_grid;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -496,6 +585,7 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
             }
 
             Build b{g, T, R, reg, d_F, d_lambda, d_fit, {}};
+            b.tuning = (flags & DFACTO_GROUP_TUNE) != 0;
             b.ws.resize(n);
             // one allocation for every member's workspace: per member the
             // MTTKRP output (largest mode), the carries (most chunks) and the
@@ -598,9 +688,30 @@ dfacto_status dfacto_group_get_info(const dfacto_group *g, dfacto_group_info *in
     info->launches_per_iter = g->launches;
     info->bytes = g->bytes;
     info->graph = g->use_graph ? 1 : 0;
-    info->mttkrp_classes = (int)g->grid_store.size();
-    for (int k = 0; k < 16; ++k)
-        info->mttkrp_grid[k] = k < (int)g->grid_store.size() ? (int)g->grid_store[k] : 0;
+    info->mttkrp_classes = (int)g->mt.size();
+    for (int k = 0; k < 16; ++k) {
+        const bool have = k < (int)g->mt.size();
+        info->mttkrp_grid[k] = have ? (int)g->mt[k].grid : 0;
+        info->mttkrp_cpl[k] = have ? g->mt[k].v.sh.cpl : 0;
+        info->mttkrp_lanes[k] = have ? g->mt[k].v.sh.g : 0;
+        info->mttkrp_chunks_per_group[k] = have ? (int)g->mt[k].v.kper : 0;
+        info->mttkrp_forms[k] = have ? (int)g->mt[k].cands.size() : 0;
+    }
+    return DFACTO_OK;
+}
+
+dfacto_status dfacto_group_set_form(dfacto_group *g, int cls, int form, int grid) {
+    if (!g || cls < 0 || cls >= (int)g->mt.size()) return DFACTO_E_INVALID;
+    dfacto_group::MtLaunch &L = g->mt[cls];
+    if (form < 0 || form >= (int)L.cands.size() || grid < 1) return DFACTO_E_INVALID;
+    L.v = L.cands[form];
+    L.grid = (unsigned)grid;
+    if (g->exec) {  // the captured iteration holds the old launch: capture again
+        (void)hipGraphExecDestroy(g->exec);
+        (void)hipGraphDestroy(g->graph);
+        g->exec = nullptr;
+        g->graph = nullptr;
+    }
     return DFACTO_OK;
 }
 

@@ -54,12 +54,9 @@ struct ModeData {
     // the stream's leaf and mid indices are ranks in the order of decreasing
     // gather count (nonzeros per leaf row, fiber headers per mid row; ties
     // by index), so row r of a gathered table is factor row perm_*[r] and
-    // the most-gathered rows are the first ones.  top_*: gather counts of
-    // the first kTopRows ranks, for sizing the rows kept on chip.
+    // the most-gathered rows are the first ones.
     uint32_t *perm_leaf = nullptr, *perm_mid = nullptr;
-    std::vector<uint32_t> top_leaf, top_mid;
 };
-constexpr int kTopRows = 16384;
 // dfacto_build_flattenings relabels the gathers of tensors from this size on
 constexpr int64_t kRelabelMinNnz = (int64_t)1 << 23;
 
@@ -174,8 +171,7 @@ struct dfacto_tensor {
     int64_t nnz = 0;
     double normsq = 0.0;
     bool relabel = false;  // build the streams with relabeled gathers
-    // host copies in flight during the build (top gather counts, as sort keys)
-    std::vector<std::pair<std::vector<uint64_t> *, std::vector<uint32_t> *>> pending_top;
+    int chunk_len = DFACTO_CHUNK_DEFAULT;  // target stream entries per work chunk
     size_t bytes = 0;
     dfacto::ModeData mode[3];
     std::vector<void *> allocations;
@@ -209,6 +205,9 @@ struct dfacto_ctx {
     void *ws[kNumSlots] = {};
     size_t ws_size[kNumSlots] = {};
     bool frozen = false;  // dfacto_ctx_freeze: workspaces may not grow
+    // build temporaries without a caller's memory source (created on the
+    // first build; empty between builds)
+    hipMemPool_t build_pool = nullptr;
     // kernel timing (dfacto_profile_*)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;  // created on demand, reused
@@ -295,10 +294,11 @@ void launch_gather_probe(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int 
 MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
                          const float *out);
 bool mttkrp_small(const dfacto_tensor *t, int mode);
-unsigned mttkrp_group_chunks_per_item(const MttkrpShape &sh);
+// chunks per work item of the grouped MTTKRP: kper per lane group
+unsigned mttkrp_group_chunks_per_item(const MttkrpShape &sh, unsigned kper);
 void launch_mttkrp_group(dfacto_ctx *ctx, dfacto_dtype dtype, const MttkrpShape &sh, bool small,
                          const GroupMttkrp *d_desc, const uint2 *d_items, uint32_t nitems,
-                         unsigned grid);
+                         unsigned grid, unsigned kper);
 void launch_fix_group(dfacto_ctx *ctx, const MttkrpShape &sh, const GroupMttkrp *d_desc,
                       const uint4 *d_short, uint32_t nshort, const uint2 *d_empty,
                       uint32_t nempty, const uint4 *d_long, uint32_t nlong);

@@ -456,19 +456,25 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_res(
 }
 
 // Grouped MTTKRP over many tensors of one kernel shape: a persistent grid
-// walks the work items (tensor, first chunk of kBlock / G consecutive
-// chunks) in a fixed order, item blockIdx.x, blockIdx.x + gridDim.x, ...
+// walks the work items (tensor, first chunk of kBlock / G * kper
+// consecutive chunks) in a fixed order, item blockIdx.x, blockIdx.x +
+// gridDim.x, ...; each lane group takes kper consecutive chunks of its item
+// in turn.  Every chunk writes its own rows and carry, so the grid, the
+// shape and kper change no result.
 template <typename T, int CPL, int G, int NCH, bool SMALL>
 __global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_mttkrp_group(
-    const GroupMttkrp *__restrict__ desc, const uint2 *__restrict__ items, uint32_t nitems) {
+    const GroupMttkrp *__restrict__ desc, const uint2 *__restrict__ items, uint32_t nitems,
+    uint32_t kper) {
     const int lane = threadIdx.x % G;
+    const uint32_t first = (threadIdx.x / G) * kper;
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const uint2 w = items[it];
         const GroupMttkrp &d = desc[w.x];
         const GlobalRows<T, CPL, NCH, SMALL> src((const T *)d.Fleaf, (const T *)d.Fmid, d.R, G,
                                                  lane);
-        mttkrp_chunk<T, CPL, G, NCH, SMALL>(d.stream, d.chunk_start, d.nchunk, src, d.R, d.out,
-                                            d.carry, w.y + threadIdx.x / G, lane);
+        for (uint32_t q = 0; q < kper; ++q)
+            mttkrp_chunk<T, CPL, G, NCH, SMALL>(d.stream, d.chunk_start, d.nchunk, src, d.R,
+                                                d.out, d.carry, w.y + first + q, lane);
     }
 }
 
@@ -1192,12 +1198,15 @@ void launch_gather_probe(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int 
     DF_LAUNCHED();
 }
 
-unsigned mttkrp_group_chunks_per_item(const MttkrpShape &sh) { return (unsigned)(kBlock / sh.g); }
+unsigned mttkrp_group_chunks_per_item(const MttkrpShape &sh, unsigned kper) {
+    return (unsigned)(kBlock / sh.g) * kper;
+}
 
 void launch_mttkrp_group(dfacto_ctx *ctx, dfacto_dtype dtype, const MttkrpShape &sh, bool small,
                          const GroupMttkrp *d_desc, const uint2 *d_items, uint32_t nitems,
-                         unsigned grid) {
+                         unsigned grid, unsigned kper) {
     if (nitems == 0) return;
+    if (kper < 1 || grid < 1) throw Error{DFACTO_E_INVALID, "grouped MTTKRP launch shape"};
     hipStream_t s = ctx->stream;
     with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
         using T = typename decltype(tc)::type;
@@ -1205,10 +1214,10 @@ void launch_mttkrp_group(dfacto_ctx *ctx, dfacto_dtype dtype, const MttkrpShape 
                       NCH = decltype(nchc)::value;
         if (small)
             hipLaunchKernelGGL((k_mttkrp_group<T, CPL, G, NCH, true>), dim3(grid), dim3(kBlock), 0,
-                               s, d_desc, d_items, nitems);
+                               s, d_desc, d_items, nitems, kper);
         else
             hipLaunchKernelGGL((k_mttkrp_group<T, CPL, G, NCH, false>), dim3(grid), dim3(kBlock),
-                               0, s, d_desc, d_items, nitems);
+                               0, s, d_desc, d_items, nitems, kper);
     });
     DF_LAUNCHED();
 }

@@ -31,10 +31,10 @@ EXPORTS = (
     "dfacto_tensor_export", "dfacto_tensor_destroy", "dfacto_mttkrp", "dfacto_als_iter",
     "dfacto_gd_grad", "dfacto_gd_step", "dfacto_build_ratings", "dfacto_joint_grad",
     "dfacto_joint_als_iter", "dfacto_group_create", "dfacto_group_als", "dfacto_group_get_info",
-    "dfacto_group_destroy", "dfacto_server_create", "dfacto_server_submit", "dfacto_server_poll",
+    "dfacto_group_destroy", "dfacto_group_set_form", "dfacto_server_create", "dfacto_server_submit", "dfacto_server_poll",
     "dfacto_server_wait", "dfacto_server_get_stats", "dfacto_server_destroy",
     "dfacto_profile_enable", "dfacto_profile_read", "dfacto_gather_probe",
-    "dfacto_mttkrp_noalloc",
+    "dfacto_mttkrp_noalloc", "dfacto_tensor_gather_order",
 )
 GROUP_GRAPH, GROUP_TUNE, GROUP_CTX_STREAM = 1, 2, 4
 
@@ -50,7 +50,7 @@ class _Info(ctypes.Structure):
                 ("nfib", ctypes.c_int64 * 3), ("nroot", ctypes.c_int64 * 3),
                 ("nentry", ctypes.c_int64 * 3), ("nchunk", ctypes.c_int64 * 3),
                 ("normsq", ctypes.c_double), ("bytes", ctypes.c_size_t),
-                ("relabeled", ctypes.c_int)]
+                ("relabeled", ctypes.c_int), ("chunk_len", ctypes.c_int)]
 
 
 class _LineSearch(ctypes.Structure):
@@ -66,7 +66,9 @@ class _GdStepInfo(ctypes.Structure):
 class _GroupInfo(ctypes.Structure):
     _fields_ = [("members", ctypes.c_int), ("launches_per_iter", ctypes.c_int),
                 ("bytes", ctypes.c_size_t), ("graph", ctypes.c_int),
-                ("mttkrp_classes", ctypes.c_int), ("mttkrp_grid", ctypes.c_int * 16)]
+                ("mttkrp_classes", ctypes.c_int), ("mttkrp_grid", ctypes.c_int * 16),
+                ("mttkrp_cpl", ctypes.c_int * 16), ("mttkrp_lanes", ctypes.c_int * 16),
+                ("mttkrp_chunks_per_group", ctypes.c_int * 16), ("mttkrp_forms", ctypes.c_int * 16)]
 
 
 class _Request(ctypes.Structure):
@@ -117,9 +119,10 @@ def load():
     lib.dfacto_last_error.restype = ctypes.c_char_p
     lib.dfacto_build_flattenings.argtypes = [P, ctypes.POINTER(ctypes.c_int64), I64, P, P, P, P, PP]
     lib.dfacto_build_flattenings_ex.argtypes = [P, ctypes.POINTER(ctypes.c_int64), I64, P, P, P, P,
-                                                I, PP]
+                                                I, I, PP]
     lib.dfacto_tensor_get_info.argtypes = [P, ctypes.POINTER(_Info)]
     lib.dfacto_tensor_export.argtypes = [P, P, I, P, P, P, P, P, P]
+    lib.dfacto_tensor_gather_order.argtypes = [P, P, I, I, P]
     lib.dfacto_tensor_destroy.argtypes = [P]
     lib.dfacto_tensor_destroy.restype = None
     lib.dfacto_mttkrp.argtypes = [P, P, I, I, I, PP, P]
@@ -135,6 +138,7 @@ def load():
                                         I, PP]
     lib.dfacto_group_als.argtypes = [P, P, I]
     lib.dfacto_group_get_info.argtypes = [P, ctypes.POINTER(_GroupInfo)]
+    lib.dfacto_group_set_form.argtypes = [P, I, I, I]
     lib.dfacto_group_destroy.argtypes = [P]
     lib.dfacto_group_destroy.restype = None
     lib.dfacto_server_create.argtypes = [I, ctypes.c_size_t, I, PP]
@@ -273,7 +277,8 @@ class Tensor:
             raise DfactoError(st, "dfacto_tensor_get_info failed")
         return dict(dims=tuple(inf.dims), nnz=inf.nnz, nfib=tuple(inf.nfib),
                     nroot=tuple(inf.nroot), nentry=tuple(inf.nentry), nchunk=tuple(inf.nchunk),
-                    normsq=inf.normsq, bytes=inf.bytes, relabeled=bool(inf.relabeled))
+                    normsq=inf.normsq, bytes=inf.bytes, relabeled=bool(inf.relabeled),
+                    chunk_len=inf.chunk_len)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -295,8 +300,10 @@ BUILD_RELABEL, BUILD_NO_RELABEL = 1, 2
 
 
 def build_flattenings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, k: torch.Tensor,
-                      val: torch.Tensor, relabel: bool | None = None) -> Tensor:
-    """relabel: None (by size), True or False (dfacto_build_flattenings_ex flags)."""
+                      val: torch.Tensor, relabel: bool | None = None,
+                      chunk_len: int = 0) -> Tensor:
+    """relabel: None (by size), True or False (dfacto_build_flattenings_ex flags);
+    chunk_len: stream entries per MTTKRP work chunk (0: the library's default)."""
     for x in (i, j, k):
         if x.dtype not in (torch.int32, torch.uint32) or not x.is_contiguous() or not x.is_cuda:
             raise TypeError("indices must be contiguous int32/uint32 CUDA tensors")
@@ -309,7 +316,8 @@ def build_flattenings(ctx: Context, dims, i: torch.Tensor, j: torch.Tensor, k: t
     h = ctypes.c_void_p()
     flags = 0 if relabel is None else (BUILD_RELABEL if relabel else BUILD_NO_RELABEL)
     ctx.check(load().dfacto_build_flattenings_ex(ctx.handle, d, n, _ptr(i), _ptr(j), _ptr(k),
-                                                 _ptr(val), flags, ctypes.byref(h)))
+                                                 _ptr(val), flags, int(chunk_len),
+                                                 ctypes.byref(h)))
     return Tensor(h, ctx.allocator)
 
 
@@ -370,6 +378,18 @@ def tensor_export(ctx: Context, t: Tensor, mode: int) -> dict:
                                           c(fib_mid), c(fib_ptr), c(leaf), c(val)))
     return dict(root_id=root_id[:nr], root_ptr=root_ptr, fib_mid=fib_mid[:nf], fib_ptr=fib_ptr,
                 leaf=leaf[:nz], val=val[:nz])
+
+
+def gather_order(ctx: Context, t: Tensor, mode: int, table: int):
+    """A relabeled mode's row order: table 0 the leaf table, 1 the mid table
+    (dfacto_tensor_gather_order)."""
+    import numpy as np
+    dims = t.info()["dims"]
+    rows = dims[(mode + 1) % 3] if table == 0 else dims[(mode + 2) % 3]
+    out = np.empty(rows, np.uint32)
+    ctx.check(load().dfacto_tensor_gather_order(ctx.handle, t.handle, int(mode), int(table),
+                                                out.ctypes.data_as(ctypes.c_void_p)))
+    return out
 
 
 def _check_factors(t: Tensor, factors, R: int | None = None, skip: int | None = None):
@@ -522,9 +542,18 @@ class Group:
         st = load().dfacto_group_get_info(self.handle, ctypes.byref(inf))
         if st != OK:
             raise DfactoError(st, "dfacto_group_get_info failed")
+        nc = min(16, inf.mttkrp_classes)
         return dict(members=inf.members, launches_per_iter=inf.launches_per_iter, bytes=inf.bytes,
                     graph=bool(inf.graph), mttkrp_classes=inf.mttkrp_classes,
-                    mttkrp_grid=list(inf.mttkrp_grid)[:min(16, inf.mttkrp_classes)])
+                    mttkrp_grid=list(inf.mttkrp_grid)[:nc], mttkrp_cpl=list(inf.mttkrp_cpl)[:nc],
+                    mttkrp_lanes=list(inf.mttkrp_lanes)[:nc],
+                    mttkrp_chunks_per_group=list(inf.mttkrp_chunks_per_group)[:nc],
+                    mttkrp_forms=list(inf.mttkrp_forms)[:nc])
+
+    def set_form(self, cls: int, form: int, grid: int):
+        st = load().dfacto_group_set_form(self.handle, int(cls), int(form), int(grid))
+        if st != OK:
+            raise DfactoError(st, "dfacto_group_set_form failed")
 
     def close(self):
         if getattr(self, "handle", None):

@@ -20,9 +20,9 @@ def coo_to_dev(coo):
     return i, j, k, v
 
 
-def build(ctx, coo, relabel=None):
+def build(ctx, coo, relabel=None, chunk_len=0):
     i, j, k, v = coo_to_dev(coo)
-    t = dfacto.build_flattenings(ctx, coo.dims, i, j, k, v, relabel=relabel)
+    t = dfacto.build_flattenings(ctx, coo.dims, i, j, k, v, relabel=relabel, chunk_len=chunk_len)
     torch.cuda.synchronize()
     return t
 

@@ -204,6 +204,54 @@ def test_group_tuning_keeps_results(ctx, members):
     gb.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_group_every_launch_form(ctx, members, dtype):
+    """Every launch form the tuner may pick (columns per lane, lanes per
+    group, chunks per lane group), at several persistent grid sizes, gives
+    bitwise the default form's iteration; a captured graph is captured
+    again after a form changes."""
+    Fa, la, fa = _state(members, dtype)
+    Fb, lb, fb = _state(members, dtype)
+    init = [[f.clone() for f in F] for F in Fa]
+    tensors = [m[1] for m in members]
+    ga = dfacto.Group(ctx, tensors, Fa, la, fa, graph=True, tune=True)
+    gb = dfacto.Group(ctx, tensors, Fb, lb, fb, tune=False)
+    inf = ga.info()
+    say(f"  {dtype} forms per class {inf['mttkrp_forms']}, tuned cpl {inf['mttkrp_cpl']} "
+        f"lanes {inf['mttkrp_lanes']} chunks/group {inf['mttkrp_chunks_per_group']} "
+        f"grid {inf['mttkrp_grid']}")
+    assert gb.info()["mttkrp_forms"] == [1] * gb.info()["mttkrp_classes"]
+    assert max(inf["mttkrp_forms"]) > 1
+    seen = set()
+    for f in range(max(inf["mttkrp_forms"])):
+        grid = (1, 5, 1000)[f % 3]
+        for c in range(inf["mttkrp_classes"]):
+            ga.set_form(c, min(f, inf["mttkrp_forms"][c] - 1), grid)
+        now = ga.info()
+        seen.update(zip(now["mttkrp_cpl"], now["mttkrp_lanes"], now["mttkrp_chunks_per_group"]))
+        for F, G, I in zip(Fa, Fb, init):
+            for m in range(3):
+                F[m].copy_(I[m])
+                G[m].copy_(I[m])
+        ga.als(1)
+        gb.als(1)
+        torch.cuda.synchronize()
+        for k in range(len(members)):
+            for m in range(3):
+                assert _same(Fa[k][m], Fb[k][m]), f"form {f}: member {k} factor {m}"
+            assert torch.equal(la[k], lb[k])
+        assert torch.equal(fa, fb)
+    say(f"  forms run (cpl, lanes, chunks per group): {sorted(seen)}")
+    with pytest.raises(dfacto.DfactoError):
+        ga.set_form(inf["mttkrp_classes"], 0, 1)
+    with pytest.raises(dfacto.DfactoError):
+        ga.set_form(0, inf["mttkrp_forms"][0], 1)
+    with pytest.raises(dfacto.DfactoError):
+        ga.set_form(0, 0, 0)
+    ga.close()
+    gb.close()
+
+
 def test_group_members_match_oracle(ctx, members):
     """One grouped iteration against the FP64 oracle, member by member."""
     Fg, lg, fg = _state(members, "f32")

@@ -213,6 +213,25 @@ def test_mttkrp_heavy_root_and_fiber(ctx):
     check_mttkrp(ctx, coo, F, "f32", label="heavy")
 
 
+@pytest.mark.parametrize("chunk_len", [256, 300, 512, 4096, 1 << 20])
+def test_mttkrp_chunk_lengths(ctx, chunk_len):
+    """Every work-chunk length in range gives the oracle's MTTKRP within the
+    rounding bound (a root split over more or fewer chunks is summed from
+    other partial sums); the chunk count follows the length: every chunk but
+    the last ends at the first header at or after a multiple of it."""
+    coo = gen.zipf_distinct((20_000, 9_000, 3_000), 150_000, 1.2, seed=31)
+    t = build(ctx, coo, chunk_len=chunk_len)
+    inf = t.info()
+    assert inf["chunk_len"] == chunk_len
+    for m in range(3):
+        assert inf["nchunk"][m] == -(-inf["nentry"][m] // chunk_len)
+    check_mttkrp(ctx, coo, gen.init_factors(coo.dims, 32, seed=32), "f32", t=t,
+                 label=f"chunk {chunk_len}")
+    check_mttkrp(ctx, coo, gen.init_factors(coo.dims, 8, seed=33), "bf16", t=t,
+                 label=f"chunk {chunk_len}")
+    t.close()
+
+
 def test_mttkrp_edge_cases(ctx):
     # nnz = 0: all rows written as zeros
     e = np.zeros(0, np.uint32)

@@ -137,6 +137,27 @@ def test_relabeled_matches_oracle(pair):
         assert err <= 1e-5
 
 
+def test_relabel_order_follows_gather_counts(pair):
+    """The relabel order of each mode's tables is the exact order of
+    decreasing gather count, ties by row index: leaf rows counted by their
+    nonzeros, mid rows by the fiber segment headers that gather them (a fiber
+    of L nonzeros has ceil(L / 128) segments), counted here on the host."""
+    ctx, coo, plain, rel = pair
+    coords = (coo.i.astype(np.int64), coo.j.astype(np.int64), coo.k.astype(np.int64))
+    for m in range(3):
+        root, mid, leaf = coords[m], coords[(m + 2) % 3], coords[(m + 1) % 3]
+        dl, dm = coo.dims[(m + 1) % 3], coo.dims[(m + 2) % 3]
+        cnt_leaf = np.bincount(leaf, minlength=dl)
+        fib, flen = np.unique(root * dm + mid, return_counts=True)
+        cnt_mid = np.bincount(fib % dm, weights=-(-flen // 128), minlength=dm).astype(np.int64)
+        for table, cnt in ((0, cnt_leaf), (1, cnt_mid)):
+            want = np.lexsort((np.arange(len(cnt)), -cnt))
+            got = dfacto.gather_order(ctx, rel, m, table)
+            assert np.array_equal(got, want), (m, table)
+    with pytest.raises(dfacto.DfactoError):
+        dfacto.gather_order(ctx, plain, 0, 0)  # not relabeled
+
+
 def test_relabel_by_size_and_flags(pair):
     """dfacto_build_flattenings relabels from 2^23 stored nonzeros on, and
     contradictory flags are refused."""
@@ -151,5 +172,10 @@ def test_relabel_by_size_and_flags(pair):
     d = (ctypes.c_int64 * 3)(*coo.dims)
     h = ctypes.c_void_p()
     st = lib.dfacto_build_flattenings_ex(ctx.handle, d, int(v.numel()), i.data_ptr(), j.data_ptr(),
-                                         k.data_ptr(), v.data_ptr(), 3, ctypes.byref(h))
+                                         k.data_ptr(), v.data_ptr(), 3, 0, ctypes.byref(h))
     assert st == dfacto.E_INVALID and not h.value
+    for bad in (100, 255, (1 << 20) + 1):  # chunk lengths out of range
+        st = lib.dfacto_build_flattenings_ex(ctx.handle, d, int(v.numel()), i.data_ptr(),
+                                             j.data_ptr(), k.data_ptr(), v.data_ptr(), 0, bad,
+                                             ctypes.byref(h))
+        assert st == dfacto.E_INVALID and not h.value
