@@ -1041,8 +1041,11 @@ MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const voi
     int cpl = 1;
     // Eight columns per lane only for BF16 (one 16-byte load per lane): a
     // gather instruction then fetches 16 rows of 64 bytes instead of 8.  For
-    // FP32 eight columns are two loads per lane, no fewer instructions.
-    if (dtype == DFACTO_BF16 && R % 8 == 0 && aligned8 && DFACTO_MAX_CPL >= 8) cpl = 8;
+    // FP32 eight columns are two loads per lane, no fewer instructions.  Not
+    // below R = 32: groups of one or two lanes share each batch of stream
+    // entries over too few lanes (measured slower than four columns).
+    if (dtype == DFACTO_BF16 && R % 8 == 0 && R >= 32 && aligned8 && DFACTO_MAX_CPL >= 8)
+        cpl = 8;
     else if (R % 4 == 0 && aligned4 && DFACTO_MAX_CPL >= 4) cpl = 4;
     else if (R % 2 == 0 && aligned2 && DFACTO_MAX_CPL >= 2) cpl = 2;
     const int lanes = (R + cpl - 1) / cpl;

@@ -84,6 +84,71 @@ struct Member {
     hipStream_t mem_stream = nullptr;  // stream the member's memory is ordered on
 };
 
+// Host-device copies through two pinned host buffers in turn.  Copies from
+// the caller's pageable memory otherwise go through the runtime's own small
+// staging copies (tens per request); here the host copies a chunk of up to
+// kBytes into a pinned buffer while the device copies the previous one.
+// One ring per thread that copies (each builder, the delivery thread).
+struct Staging {
+    static constexpr size_t kBytes = (size_t)32 << 20;
+    void *buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int next = 0;
+    bool init() {
+        for (int k = 0; k < 2; ++k)
+            if (hipHostMalloc(&buf[k], kBytes, hipHostMallocDefault) != hipSuccess ||
+                hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                return false;
+            }
+        return true;
+    }
+    void release() {
+        for (int k = 0; k < 2; ++k) {
+            if (ev[k]) (void)hipEventSynchronize(ev[k]), (void)hipEventDestroy(ev[k]);
+            if (buf[k]) (void)hipHostFree(buf[k]);
+            ev[k] = nullptr;
+            buf[k] = nullptr;
+        }
+    }
+    // host -> device on stream st; returns once the last chunk is queued
+    // (the buffers stay in use until their events complete)
+    void upload(void *dst, const void *src, size_t bytes, hipStream_t st) {
+        for (size_t off = 0; off < bytes; off += kBytes) {
+            const size_t n = std::min(kBytes, bytes - off);
+            const int k = next;
+            next ^= 1;
+            DF_HIP(hipEventSynchronize(ev[k]));  // the buffer's previous copy is done
+            std::memcpy(buf[k], (const char *)src + off, n);
+            DF_HIP(hipMemcpyAsync((char *)dst + off, buf[k], n, hipMemcpyHostToDevice, st));
+            DF_HIP(hipEventRecord(ev[k], st));
+        }
+    }
+    // device -> host on stream st, waiting for the copies (the host copy of
+    // one chunk overlaps the device copy of the next)
+    void download(void *dst, const void *src, size_t bytes, hipStream_t st) {
+        size_t pend_off = 0, pend_n = 0;
+        int pend_k = -1;
+        auto drain = [&] {
+            if (pend_k < 0) return;
+            DF_HIP(hipEventSynchronize(ev[pend_k]));
+            std::memcpy((char *)dst + pend_off, buf[pend_k], pend_n);
+            pend_k = -1;
+        };
+        for (size_t off = 0; off < bytes; off += kBytes) {
+            const size_t n = std::min(kBytes, bytes - off);
+            const int k = next;
+            next ^= 1;
+            DF_HIP(hipEventSynchronize(ev[k]));
+            DF_HIP(hipMemcpyAsync(buf[k], (const char *)src + off, n, hipMemcpyDeviceToHost, st));
+            DF_HIP(hipEventRecord(ev[k], st));
+            drain();
+            pend_off = off, pend_n = n, pend_k = k;
+        }
+        drain();
+    }
+};
+
 }  // namespace
 
 struct dfacto_server {
@@ -100,6 +165,7 @@ struct dfacto_server {
     static constexpr int kBuilders = 2;
     dfacto_ctx *bctx[kBuilders] = {};  // the builders' contexts (own streams)
     hipStream_t bstream[kBuilders] = {};
+    Staging bstage[kBuilders], dstage;  // pinned staging: builders, delivery
     Clock::time_point t0;
 
     std::mutex mu;
@@ -199,11 +265,12 @@ void admit(dfacto_server *s, int b, Member &m, double *t_build) {
         hip_check(stream_alloc((void **)&dj, 4 * n, st, s->pool), "request upload");
         hip_check(stream_alloc((void **)&dk, 4 * n, st, s->pool), "request upload");
         hip_check(stream_alloc((void **)&dv, 4 * n, st, s->pool), "request upload");
+        Staging &sg = s->bstage[b];
         if (r.nnz > 0) {
-            DF_HIP(hipMemcpyAsync(di, r.i, 4 * r.nnz, hipMemcpyHostToDevice, st));
-            DF_HIP(hipMemcpyAsync(dj, r.j, 4 * r.nnz, hipMemcpyHostToDevice, st));
-            DF_HIP(hipMemcpyAsync(dk, r.k, 4 * r.nnz, hipMemcpyHostToDevice, st));
-            DF_HIP(hipMemcpyAsync(dv, r.val, 4 * r.nnz, hipMemcpyHostToDevice, st));
+            sg.upload(di, r.i, 4 * r.nnz, st);
+            sg.upload(dj, r.j, 4 * r.nnz, st);
+            sg.upload(dk, r.k, 4 * r.nnz, st);
+            sg.upload(dv, r.val, 4 * r.nnz, st);
         }
         const auto tb = Clock::now();
         const dfacto_status bs =
@@ -221,13 +288,13 @@ void admit(dfacto_server *s, int b, Member &m, double *t_build) {
             if (r.dtype == DFACTO_BF16) {  // FP32 upload, rounded to BF16 on the device
                 float *tmp = nullptr;
                 hip_check(stream_alloc((void **)&tmp, 4 * cnt, st, s->pool), "factor staging");
-                DF_HIP(hipMemcpyAsync(tmp, r.init[k], 4 * cnt, hipMemcpyHostToDevice, st));
+                sg.upload(tmp, r.init[k], 4 * cnt, st);
                 hipLaunchKernelGGL(k_f32_to_bf16, dim3(convert_grid((int64_t)cnt)), dim3(256), 0,
                                    st, tmp, (uint16_t *)m.F[k], (int64_t)cnt);
                 DF_LAUNCHED();
                 DF_HIP(hipFreeAsync(tmp, st));
             } else {
-                DF_HIP(hipMemcpyAsync(m.F[k], r.init[k], 4 * cnt, hipMemcpyHostToDevice, st));
+                sg.upload(m.F[k], r.init[k], 4 * cnt, st);
             }
         }
         hip_check(stream_alloc((void **)&m.lambda, 8 * (size_t)r.R, st, s->pool),
@@ -247,6 +314,7 @@ void admit(dfacto_server *s, int b, Member &m, double *t_build) {
 void deliver(dfacto_server *s, Member &m) {
     const dfacto_request &r = m.req;
     hipStream_t st = s->dstream;
+    Staging &sg = s->dstage;
     std::vector<float *> tmps;
     try {
         for (int k = 0; k < 3; ++k) {
@@ -259,14 +327,12 @@ void deliver(dfacto_server *s, Member &m) {
                 hipLaunchKernelGGL(k_bf16_to_f32, dim3(convert_grid((int64_t)cnt)), dim3(256), 0,
                                    st, (const uint16_t *)m.F[k], tmp, (int64_t)cnt);
                 DF_LAUNCHED();
-                DF_HIP(hipMemcpyAsync(r.out_F[k], tmp, 4 * cnt, hipMemcpyDeviceToHost, st));
+                sg.download(r.out_F[k], tmp, 4 * cnt, st);
             } else {
-                DF_HIP(hipMemcpyAsync(r.out_F[k], m.F[k], 4 * cnt, hipMemcpyDeviceToHost, st));
+                sg.download(r.out_F[k], m.F[k], 4 * cnt, st);
             }
         }
-        if (r.out_lambda)
-            DF_HIP(hipMemcpyAsync(r.out_lambda, m.lambda, 8 * (size_t)r.R, hipMemcpyDeviceToHost,
-                                  st));
+        if (r.out_lambda) sg.download(r.out_lambda, m.lambda, 8 * (size_t)r.R, st);
         for (float *p : tmps) (void)hipFreeAsync(p, st);
         DF_HIP(hipStreamSynchronize(st));
     } catch (...) {
@@ -555,12 +621,16 @@ dfacto_status dfacto_server_create(int device, size_t hbm_budget, int max_slots,
               dfacto_ctx_create(device, s->stream, nullptr, &s->ctx) == DFACTO_OK;
     for (int b = 0; ok && b < dfacto_server::kBuilders; ++b)
         ok = dfacto_ctx_create(device, s->bstream[b], nullptr, &s->bctx[b]) == DFACTO_OK;
+    for (int b = 0; ok && b < dfacto_server::kBuilders; ++b) ok = s->bstage[b].init();
+    ok = ok && s->dstage.init();
     if (ok) {
         s->ctx->mem.pool = s->pool;
         for (int b = 0; b < dfacto_server::kBuilders; ++b) s->bctx[b]->mem.pool = s->pool;
     }
     if (!ok) {
         (void)hipGetLastError();
+        for (int b = 0; b < dfacto_server::kBuilders; ++b) s->bstage[b].release();
+        s->dstage.release();
         if (s->ctx) dfacto_ctx_destroy(s->ctx);
         for (int b = 0; b < dfacto_server::kBuilders; ++b) {
             if (s->bctx[b]) dfacto_ctx_destroy(s->bctx[b]);
@@ -665,6 +735,8 @@ void dfacto_server_destroy(dfacto_server *s) {
         (void)hipStreamSynchronize(s->bstream[b]);  // stream-ordered frees
         (void)hipStreamDestroy(s->bstream[b]);
     }
+    for (int b = 0; b < dfacto_server::kBuilders; ++b) s->bstage[b].release();
+    s->dstage.release();
     if (s->dstream) (void)hipStreamDestroy(s->dstream);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     // every allocation from the pool has been freed and its stream finished
