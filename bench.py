@@ -871,7 +871,7 @@ def main():
     ap.add_argument("--served-dtypes", default="f32,bf16",
                     help="served workload: factor storage dtypes, run in this order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=100_000_000,
+    ap.add_argument("--cpu-sample", type=int, default=400_000_000,
                     help="nonzeros copied to the host for the CPU baseline (at most)")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-factor runs")
     ap.add_argument("--als-per-step", type=int, default=0,

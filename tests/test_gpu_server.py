@@ -102,6 +102,40 @@ def test_served_result_equals_repeated_als_iter(requests, which):
     ctx.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_served_large_request_staged_in_chunks(dtype):
+    """A request whose COO arrays (36 MB each) and factors (38 MB) exceed one
+    32 MB pinned staging buffer, so uploads and downloads run in several
+    chunks through both buffers: the served result equals dfacto_als_iter
+    repeated on the request from the same start, bitwise."""
+    coo = gen.uniform_distinct((300_000, 250_000, 600), 9_000_000, seed=41)
+    R = 32
+    init = [f.astype(np.float32) for f in gen.init_factors(coo.dims, R, seed=42)]
+    srv = dfacto.Server(0, max_slots=2)
+    res = srv.wait(srv.submit(coo.dims, coo.i, coo.j, coo.k, coo.val, R, init, dtype=dtype,
+                              tol=0.0, max_iters=3))
+    srv.close()
+    assert res["status"] == dfacto.OK and res["iters"] == 3
+    ctx = dfacto.Context(0)
+    from gpu_util import build
+    t = build(ctx, coo)
+    F = [torch.from_numpy(f.copy()).to(DEV) for f in init]
+    if dtype == "bf16":
+        F = [f.to(torch.bfloat16) for f in F]
+    lam = torch.zeros(R, dtype=torch.float64, device=DEV)
+    fit = torch.zeros(1, dtype=torch.float64, device=DEV)
+    for _ in range(3):
+        dfacto.als_iter(ctx, t, F, lam, fit)
+    torch.cuda.synchronize()
+    say(f"  {dtype} large served request: fit {res['fit']:.9f}")
+    assert fit.item() == res["fit"]
+    for m in range(3):
+        assert np.array_equal(F[m].float().cpu().numpy(), res["factors"][m])
+    assert np.array_equal(lam.cpu().numpy(), res["lam"])
+    t.close()
+    ctx.close()
+
+
 def test_admission_limits(requests):
     # one slot: never more than one active
     srv = dfacto.Server(0, max_slots=1)
