@@ -596,7 +596,8 @@ def run_tensor(args):
     ctx = dfacto.Context(0, allocator="torch")
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    T = dfacto.build_flattenings(ctx, dims, i, j, k, v)
+    relabel = {"auto": None, "on": True, "off": False}[args.relabel]
+    T = dfacto.build_flattenings(ctx, dims, i, j, k, v, relabel=relabel)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - tb) * 1e3
     del i, j, k, v
@@ -874,6 +875,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=400_000_000,
                     help="nonzeros copied to the host for the CPU baseline (at most)")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-factor runs")
+    ap.add_argument("--relabel", choices=("auto", "on", "off"), default="auto",
+                    help="relabeled gathers: by size (the library's default), always or never")
     ap.add_argument("--als-per-step", type=int, default=0,
                     help="CP-ALS iterations in a step, then one GD gradient "
                          "(default: 1 for paper1200m, 10 for zipf50m)")
