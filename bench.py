@@ -853,7 +853,7 @@ def main():
                              "joint"])
     ap.add_argument("--batch", type=int, default=256, help="batched workload: number of tensors")
     ap.add_argument("--iters", type=int, default=20, help="batched workload: ALS iterations")
-    ap.add_argument("--build-threads", type=int, default=1,
+    ap.add_argument("--build-threads", type=int, default=2,
                     help="batched workload: host threads building the tensors")
     ap.add_argument("--rate", type=float, default=200.0, help="served workload: arrivals per second")
     ap.add_argument("--served-warmup", type=int, default=200,

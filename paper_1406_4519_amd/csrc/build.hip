@@ -463,6 +463,7 @@ struct Scratch {
     T *alloc(int64_t n) {
         void *p = nullptr;
         const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+        if (mem.arena && (p = mem.arena->take(bytes))) return (T *)p;  // freed with the arena
         if (mem.alloc(&p, bytes, s) != hipSuccess) {
             (void)hipGetLastError();
             throw Error{DFACTO_E_NOMEM, "device allocation of " + std::to_string(bytes) +
@@ -480,20 +481,40 @@ struct Scratch {
     }
 };
 
+// Tensor memory.  Arrays up to kSlabTake bytes (chunk starts, run lists,
+// empty rows, the streams of small tensors) share slabs of kSlabBytes, so a
+// small tensor makes a few allocations instead of about fifteen.
+constexpr size_t kSlabTake = (size_t)256 << 10, kSlabBytes = (size_t)1 << 20;
+
+void *tensor_alloc_bytes(dfacto_tensor *t, size_t bytes) {
+    bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    auto raw = [&](size_t b) {
+        void *p = nullptr;
+        const hipError_t e =
+            t->alloc_stream ? t->mem.alloc(&p, b, t->alloc_stream) : hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{DFACTO_E_NOMEM, "device allocation of " + std::to_string(b) +
+                                            " bytes failed for the flattenings"};
+        }
+        t->allocations.push_back(p);
+        t->bytes += b;
+        return (char *)p;
+    };
+    if (bytes > kSlabTake) return raw(bytes);
+    if (bytes > t->slab_left) {
+        t->slab = raw(kSlabBytes);
+        t->slab_left = kSlabBytes;
+    }
+    void *p = t->slab;
+    t->slab += bytes;
+    t->slab_left -= bytes;
+    return p;
+}
+
 template <typename T>
 T *tensor_alloc(dfacto_tensor *t, int64_t n) {
-    void *p = nullptr;
-    const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
-    const hipError_t e =
-        t->alloc_stream ? t->mem.alloc(&p, bytes, t->alloc_stream) : hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw Error{DFACTO_E_NOMEM, "device allocation of " + std::to_string(bytes) +
-                                        " bytes failed for the flattenings"};
-    }
-    t->allocations.push_back(p);
-    t->bytes += bytes;
-    return (T *)p;
+    return (T *)tensor_alloc_bytes(t, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
 }
 
 // out[q] = *a[q] + *b[q] for several scan totals (last offset plus last

@@ -213,7 +213,17 @@ dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int
         };
         ctx->mem.pool = pool ? pool : ctx->mem.pool;
         try {
-            build_tensor(ctx, t, d_i, d_j, d_k, d_val);
+            // the build's small temporaries come from an arena whose chunks
+            // go back (stream-ordered) before the pool is emptied
+            Arena arena(ctx->stream, ctx->mem);
+            ctx->mem.arena = &arena;
+            try {
+                build_tensor(ctx, t, d_i, d_j, d_k, d_val);
+            } catch (...) {
+                ctx->mem.arena = nullptr;
+                throw;
+            }
+            ctx->mem.arena = nullptr;
         } catch (...) {
             // copies into the tensor's host fields may still be pending
             (void)hipStreamSynchronize(ctx->stream);

@@ -484,8 +484,8 @@ void autotune(dfacto_group *g, const std::vector<std::function<void()>> &mt_step
     const unsigned cu = (unsigned)std::max(1, g->gctx.num_cu);
     for (size_t k = 0; k < mt_steps.size(); ++k) {
         dfacto_group::MtLaunch &L = g->mt[mt_index[k]];
+        mt_steps[k]();  // warm the class's data once
         auto time_it = [&]() {
-            mt_steps[k]();  // warm
             DF_HIP(hipEventRecord(e0, g->stream));
             mt_steps[k]();
             DF_HIP(hipEventRecord(e1, g->stream));

@@ -140,9 +140,13 @@ inline hipError_t stream_alloc(void **p, size_t bytes, hipStream_t s, hipMemPool
 // callbacks when user.alloc is set, else stream-ordered allocation from
 // `pool` (null: the device's default pool).  Every free names the stream the
 // memory was last used on, so its reuse is ordered after that stream's work.
+struct Arena;
+
 struct DevMem {
     dfacto_allocator user{nullptr, nullptr, nullptr};
     hipMemPool_t pool = nullptr;
+    // a build's bump allocator for its temporaries (set while a build runs)
+    Arena *arena = nullptr;
     bool has_user() const { return user.alloc != nullptr; }
     hipError_t alloc(void **p, size_t bytes, hipStream_t s) const {
         if (has_user()) {
@@ -155,6 +159,54 @@ struct DevMem {
         if (!p) return;
         if (has_user()) user.free(p, (void *)s, user.user);
         else (void)hipFreeAsync(p, s);
+    }
+};
+
+// Temporaries of one build: allocations up to kMaxTake bytes are carved
+// from a few large chunks (each from the build's memory source) and all
+// given back when the build ends, instead of one allocation and one free
+// per temporary (a small build makes about eighty; each costs 10-30 us of
+// host time in the runtime, several times the build's kernel time).
+// Freed in stream order on the build's stream.
+struct Arena {
+    static constexpr size_t kMaxTake = (size_t)16 << 20;
+    static constexpr size_t kFirstChunk = (size_t)16 << 20;
+    hipStream_t s;
+    DevMem mem;  // the chunks' source (no arena)
+    std::vector<std::pair<char *, size_t>> chunks;
+    char *cur = nullptr;
+    size_t left = 0, next = kFirstChunk;
+    Arena(hipStream_t st, const DevMem &m) : s(st), mem(m) { mem.arena = nullptr; }
+    Arena(const Arena &) = delete;
+    Arena &operator=(const Arena &) = delete;
+    ~Arena() {
+        for (auto &c : chunks) mem.free(c.first, s);
+    }
+    // nullptr: too large for the arena, or no device memory for a chunk
+    void *take(size_t bytes) {
+        bytes = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+        if (bytes > kMaxTake) return nullptr;
+        if (bytes > left) {
+            const size_t c = std::max(bytes, next);
+            void *p = nullptr;
+            if (mem.alloc(&p, c, s) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            chunks.push_back({(char *)p, c});
+            cur = (char *)p;
+            left = c;
+            next = std::min<size_t>(2 * c, (size_t)1 << 30);
+        }
+        void *r = cur;
+        cur += bytes;
+        left -= bytes;
+        return r;
+    }
+    bool owns(const void *p) const {
+        for (const auto &c : chunks)
+            if ((const char *)p >= c.first && (const char *)p < c.first + c.second) return true;
+        return false;
     }
 };
 
@@ -175,6 +227,8 @@ struct dfacto_tensor {
     size_t bytes = 0;
     dfacto::ModeData mode[3];
     std::vector<void *> allocations;
+    char *slab = nullptr;  // the current slab of small arrays (build.hip)
+    size_t slab_left = 0;
     // ratings matrix of the joint model (dims[2] == 1, built by
     // dfacto_build_ratings): per output row of modes 0 and 1, the range
     // [x, y) of its entries in that mode's stream ((0, 0) for an empty row)

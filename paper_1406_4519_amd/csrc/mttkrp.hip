@@ -466,6 +466,17 @@ __global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_mttkrp_group(
     const GroupMttkrp *__restrict__ desc, const uint2 *__restrict__ items, uint32_t nitems,
     uint32_t kper) {
     const int lane = threadIdx.x % G;
+    if (kper == 1) {  // the common form, without the inner loop
+        for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+            const uint2 w = items[it];
+            const GroupMttkrp &d = desc[w.x];
+            const GlobalRows<T, CPL, NCH, SMALL> src((const T *)d.Fleaf, (const T *)d.Fmid, d.R,
+                                                     G, lane);
+            mttkrp_chunk<T, CPL, G, NCH, SMALL>(d.stream, d.chunk_start, d.nchunk, src, d.R,
+                                                d.out, d.carry, w.y + threadIdx.x / G, lane);
+        }
+        return;
+    }
     const uint32_t first = (threadIdx.x / G) * kper;
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const uint2 w = items[it];

@@ -214,9 +214,18 @@ size_t footprint_estimate(const dfacto_request &r) {
     return b;
 }
 
-// Peak transient device memory of building the flattenings (COO staging,
-// sort keys and permutations, gathered copies).
-size_t build_transient(const dfacto_request &r) { return 80 * (size_t)r.nnz + (1 << 20); }
+// Peak transient device memory of building the flattenings: COO staging,
+// sort keys and permutations, gathered copies (about 80 bytes per nonzero
+// with buffers reused within the build), plus the build's arena of small
+// temporaries, which are kept until the build ends (at most about 160 bytes
+// per nonzero and 24 per row, doubled for chunk rounding, and at most a
+// few chunks of up to 1 GB).
+size_t build_transient(const dfacto_request &r) {
+    const size_t rows = (size_t)(r.dims[0] + r.dims[1] + r.dims[2]);
+    const size_t arena = std::min<size_t>(320 * (size_t)r.nnz + 48 * rows + (32 << 20),
+                                          (size_t)1 << 30);
+    return 80 * (size_t)r.nnz + arena + (1 << 20);
+}
 
 // Release a member's memory, ordered on the stream it was allocated on.  The
 // caller has already waited for every kernel that reads it.
