@@ -326,6 +326,13 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R,
 #define DFACTO_GROUP_GRAPH 1
 #define DFACTO_GROUP_TUNE 2
 #define DFACTO_GROUP_CTX_STREAM 4
+/* The caller does not write the members' factors between dfacto_group_als
+ * calls (only the group's iterations change them).  With BF16 storage an
+ * iteration opens with the Grams of the stored B and C, which the previous
+ * iteration has just formed for the same factors; they are reused after
+ * the first iteration of every call anyway, and with this flag also across
+ * calls.  Results are the same bitwise. */
+#define DFACTO_GROUP_OWN_FACTORS 8
 
 typedef struct dfacto_group dfacto_group;
 

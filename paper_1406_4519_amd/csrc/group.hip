@@ -47,8 +47,18 @@ struct dfacto_group {
     std::vector<std::function<void()>> steps;  // enqueue one iteration
     int launches = 0;                          // kernel launches per iteration
     bool use_graph = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // Captured iterations: [0] every step, [1] from open_end on (see below)
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    // BF16 storage: an iteration opens with the Grams of the stored B and C,
+    // which are exactly the Grams the previous iteration formed last for
+    // those factors (same kernels, same data).  Iterations after the first
+    // of a call -- and, with DFACTO_GROUP_OWN_FACTORS, after the group's
+    // previous iteration -- start at open_end instead.
+    size_t open_end = 0;
+    bool reuse_grams = false;   // BF16 storage
+    bool own_factors = false;   // DFACTO_GROUP_OWN_FACTORS
+    bool grams_valid = false;   // an iteration has run since creation
     // One grouped MTTKRP launch per kernel class and mode: its shape (columns
     // per lane, lanes per group), chunks per lane group, work items (one
     // table per item size) and persistent grid size.  The fix-ups after it
@@ -467,8 +477,17 @@ struct Build {
     }
 };
 
-void run_steps(dfacto_group *g) {
-    for (auto &f : g->steps) f();
+void run_steps(dfacto_group *g, size_t from) {
+    for (size_t k = from; k < g->steps.size(); ++k) g->steps[k]();
+}
+
+void drop_graphs(dfacto_group *g) {
+    for (int q = 0; q < 2; ++q) {
+        if (g->exec[q]) (void)hipGraphExecDestroy(g->exec[q]);
+        if (g->graph[q]) (void)hipGraphDestroy(g->graph[q]);
+        g->exec[q] = nullptr;
+        g->graph[q] = nullptr;
+    }
 }
 
 // Time the MTTKRP steps of the group and keep the fastest launch form per
@@ -630,6 +649,9 @@ dfacto_status dfacto_group_create(dfacto_ctx *ctx, int n, const dfacto_tensor *c
                 b.add_gram(
                     dtype, [&](int t) -> const void * { return d_F[3 * t + m]; },
                     [&](int t) { return T[t]->dims[m]; }, [&](int t) { return b.ws[t].G[m]; });
+            g->open_end = g->steps.size();
+            g->reuse_grams = dtype == DFACTO_BF16;
+            g->own_factors = (flags & DFACTO_GROUP_OWN_FACTORS) != 0;
             for (int m = 0; m < 3; ++m) b.add_mode(m);
             // the host tables in one copy per arena chunk, then the combined
             // tables expanded on the device (stream order keeps them ahead of
@@ -658,23 +680,29 @@ dfacto_status dfacto_group_als(dfacto_ctx *ctx, dfacto_group *g, int iters) {
             DF_HIP(hipEventRecord(g->ev_in, ctx->stream));
             DF_HIP(hipStreamWaitEvent(g->stream, g->ev_in, 0));
         }
-        if (g->use_graph && !g->exec && iters > 0) {
-            DF_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
-            try {
-                run_steps(g);
-            } catch (...) {
-                hipGraph_t tmp = nullptr;
-                (void)hipStreamEndCapture(g->stream, &tmp);
-                if (tmp) (void)hipGraphDestroy(tmp);
-                throw;
-            }
-            DF_HIP(hipStreamEndCapture(g->stream, &g->graph));
-            DF_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
-        }
         for (int i = 0; i < iters; ++i) {
-            if (g->use_graph) DF_HIP(hipGraphLaunch(g->exec, g->stream));
-            else run_steps(g);
+            const int q = g->reuse_grams && (i > 0 || (g->own_factors && g->grams_valid)) ? 1 : 0;
+            const size_t from = q ? g->open_end : 0;
+            if (!g->use_graph) {
+                run_steps(g, from);
+                continue;
+            }
+            if (!g->exec[q]) {
+                DF_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
+                try {
+                    run_steps(g, from);
+                } catch (...) {
+                    hipGraph_t tmp = nullptr;
+                    (void)hipStreamEndCapture(g->stream, &tmp);
+                    if (tmp) (void)hipGraphDestroy(tmp);
+                    throw;
+                }
+                DF_HIP(hipStreamEndCapture(g->stream, &g->graph[q]));
+                DF_HIP(hipGraphInstantiate(&g->exec[q], g->graph[q], nullptr, nullptr, 0));
+            }
+            DF_HIP(hipGraphLaunch(g->exec[q], g->stream));
         }
+        if (iters > 0) g->grams_valid = true;
         if (g->own_stream) {
             DF_HIP(hipEventRecord(g->ev_out, g->stream));
             DF_HIP(hipStreamWaitEvent(ctx->stream, g->ev_out, 0));
@@ -706,12 +734,7 @@ dfacto_status dfacto_group_set_form(dfacto_group *g, int cls, int form, int grid
     if (form < 0 || form >= (int)L.cands.size() || grid < 1) return DFACTO_E_INVALID;
     L.v = L.cands[form];
     L.grid = (unsigned)grid;
-    if (g->exec) {  // the captured iteration holds the old launch: capture again
-        (void)hipGraphExecDestroy(g->exec);
-        (void)hipGraphDestroy(g->graph);
-        g->exec = nullptr;
-        g->graph = nullptr;
-    }
+    drop_graphs(g);  // the captured iterations hold the old launch: capture again
     return DFACTO_OK;
 }
 
@@ -720,8 +743,7 @@ void dfacto_group_destroy(dfacto_group *g) {
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(g->device);
-    if (g->exec) (void)hipGraphExecDestroy(g->exec);
-    if (g->graph) (void)hipGraphDestroy(g->graph);
+    drop_graphs(g);
     for (void *p : g->allocs) g->mem.free(p, g->stream);
     if (g->stream || !g->own_stream) (void)hipStreamSynchronize(g->stream);  // host tables
     if (g->ev_in) (void)hipEventDestroy(g->ev_in);

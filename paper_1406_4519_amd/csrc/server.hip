@@ -390,7 +390,8 @@ void build_groups(dfacto_server *s) {
             dfacto_group *g = nullptr;
             const dfacto_status st =
                 dfacto_group_create(s->ctx, (int)T.size(), T.data(), R.data(), dt, reg, F.data(),
-                                    lam.data(), s->d_fits + a, DFACTO_GROUP_CTX_STREAM, &g);
+                                    lam.data(), s->d_fits + a,
+                                    DFACTO_GROUP_CTX_STREAM | DFACTO_GROUP_OWN_FACTORS, &g);
             if (st != DFACTO_OK) throw Error{st, dfacto_last_error(s->ctx)};
             s->groups.push_back(g);
             a = b;

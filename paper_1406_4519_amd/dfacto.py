@@ -36,7 +36,7 @@ EXPORTS = (
     "dfacto_profile_enable", "dfacto_profile_read", "dfacto_gather_probe",
     "dfacto_mttkrp_noalloc", "dfacto_tensor_gather_order",
 )
-GROUP_GRAPH, GROUP_TUNE, GROUP_CTX_STREAM = 1, 2, 4
+GROUP_GRAPH, GROUP_TUNE, GROUP_CTX_STREAM, GROUP_OWN_FACTORS = 1, 2, 4, 8
 
 
 class DfactoError(RuntimeError):
@@ -505,7 +505,7 @@ class Group:
 
     def __init__(self, ctx: Context, tensors, factors, lams, fits: torch.Tensor,
                  reg: float = 0.0, graph: bool = False, tune: bool = False,
-                 ctx_stream: bool = False):
+                 ctx_stream: bool = False, own_factors: bool = False):
         n = len(tensors)
         if not (len(factors) == len(lams) == n) or n < 1:
             raise ValueError("tensors, factors and lams must have one entry per member")
@@ -527,7 +527,8 @@ class Group:
         fp = (ctypes.c_void_p * (3 * n))(*ptrs)
         lp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in lams])
         flags = ((GROUP_GRAPH if graph else 0) | (GROUP_TUNE if tune else 0)
-                 | (GROUP_CTX_STREAM if ctx_stream else 0))
+                 | (GROUP_CTX_STREAM if ctx_stream else 0)
+                 | (GROUP_OWN_FACTORS if own_factors else 0))
         h = ctypes.c_void_p()
         ctx.check(load().dfacto_group_create(ctx.handle, n, th, rk, code, float(reg), fp, lp,
                                              _ptr(fits), flags, ctypes.byref(h)))

@@ -184,6 +184,39 @@ def test_group_on_context_stream(ctx, members, graph):
     sctx.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_group_bf16_reused_grams_bitwise(ctx, members, graph):
+    """BF16 storage: iterations after the first of a call, and with
+    own_factors every iteration after the group's first, reuse the stored
+    factors' Grams of the previous iteration instead of forming them again.
+    Four calls of 1, 2, 1 and 3 iterations equal seven dfacto_als_iter calls
+    per member, bitwise, with and without graph replay."""
+    Fg, lg, fg = _state(members, "bf16")
+    Fo, lo, fo = _state(members, "bf16")
+    Fs, ls, fs = _state(members, "bf16")
+    tensors = [m[1] for m in members]
+    g = dfacto.Group(ctx, tensors, Fg, lg, fg, graph=graph)
+    go = dfacto.Group(ctx, tensors, Fo, lo, fo, graph=graph, own_factors=True)
+    for it in (1, 2, 1, 3):
+        g.als(it)
+        go.als(it)
+        torch.cuda.synchronize()
+    for k, (coo, t, R, _) in enumerate(members):
+        fit = torch.zeros(1, dtype=torch.float64, device=DEV)
+        for _ in range(7):
+            dfacto.als_iter(ctx, t, Fs[k], ls[k], fit)
+        fs[k] = fit[0]
+    torch.cuda.synchronize()
+    for k in range(len(members)):
+        for m in range(3):
+            assert _same(Fg[k][m], Fs[k][m]), f"member {k} factor {m}"
+            assert _same(Fo[k][m], Fs[k][m]), f"own_factors: member {k} factor {m}"
+        assert torch.equal(lg[k], ls[k]) and torch.equal(lo[k], ls[k])
+    assert torch.equal(fg, fs) and torch.equal(fo, fs)
+    g.close()
+    go.close()
+
+
 def test_group_tuning_keeps_results(ctx, members):
     """Tuned persistent grid sizes do not change any result."""
     Fa, la, fa = _state(members, "f32")
