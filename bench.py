@@ -314,8 +314,8 @@ def run_served(args):
     args.served_requests are measured: completed solves per second over the
     measured requests' span, p50 / p99 latency (submission to factors in
     host memory) and whether the load was sustained.  With --rate-search,
-    also the highest offered rate (steps of 25/s) that is sustained, per
-    storage dtype, on shorter runs."""
+    also the highest offered rate that is sustained (steps of 25/s, then
+    two halvings of the interval), per storage dtype, on shorter runs."""
     import numpy as np
     from paper_1406_4519_amd import dfacto, gen
 
@@ -339,17 +339,35 @@ def run_served(args):
     if args.rate_search:
         for dt in args.served_dtypes.split(","):
             best, tried = None, []
-            rate = 50.0
-            while rate <= args.rate:
+
+            def probe(rate):
                 r = _served_run(dfacto, np, pool, big, rate, 100, args.search_requests, dt,
                                 777, args.large_frac)
                 tried.append(dict(rate=rate, solves_per_s=r["solves_per_s"],
                                   p50_ms=r["p50_ms"], p99_ms=r["p99_ms"],
                                   sustained=r["sustained"]))
+                return r
+
+            # steps of 25/s up to the first rate not sustained, then halving
+            # the interval twice (6.25/s resolution)
+            lo, hi, rate = None, None, 50.0
+            while rate <= args.rate:
+                r = probe(rate)
                 if not r["sustained"]:
+                    hi = rate
                     break
+                lo = rate
                 best = dict(rate=rate, **{k: r[k] for k in ("solves_per_s", "p50_ms", "p99_ms")})
                 rate += 25.0
+            for _ in range(2 if lo is not None and hi is not None else 0):
+                mid = (lo + hi) / 2
+                r = probe(mid)
+                if r["sustained"]:
+                    lo = mid
+                    best = dict(rate=mid,
+                                **{k: r[k] for k in ("solves_per_s", "p50_ms", "p99_ms")})
+                else:
+                    hi = mid
             search[dt] = dict(highest_sustained=best, tried=tried)
     served_line(args, out, search)
 

@@ -167,7 +167,10 @@ dfacto_status dfacto_build_flattenings(dfacto_ctx *ctx, const int64_t dims[3], i
  * share cache lines (rows shorter than a line: BF16 factors, small R).
  * The nonzeros' order, and so every result, is the same either way.
  * DFACTO_BUILD_RELABEL: relabel; DFACTO_BUILD_NO_RELABEL: plain indices;
- * neither (dfacto_build_flattenings): relabel from 2^23 stored nonzeros on. */
+ * neither (dfacto_build_flattenings): relabel from 2^23 nonzeros on when
+ * there are at least 64 nonzeros per factor row (nnz >= 64 (I + J + K)):
+ * each MTTKRP of a relabeled tensor first copies its two gathered factors
+ * into rank order, which pays only when rows are gathered often. */
 #define DFACTO_BUILD_RELABEL 1
 #define DFACTO_BUILD_NO_RELABEL 2
 
@@ -314,8 +317,9 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R,
  * flags: DFACTO_GROUP_GRAPH captures one iteration as a HIP graph on the
  * first dfacto_group_als call and replays it; DFACTO_GROUP_TUNE times each
  * MTTKRP launch at creation in several forms -- persistent grid sizes of 2
- * to 32 workgroups per CU, fewer factor columns per lane (more lanes per
- * group), 1, 2 or 4 work chunks per lane group -- and keeps the fastest
+ * to 32 workgroups per CU, other factor columns per lane (fewer, or eight
+ * for BF16 ranks that are multiples of 8) with the lanes per group to
+ * match, 1, 2 or 4 work chunks per lane group -- and keeps the fastest
  * (results do not depend on the choice); DFACTO_GROUP_CTX_STREAM
  * launches on the creating context's stream instead of a stream of the
  * group's own (cheaper to create and free; later calls must pass a context

@@ -174,7 +174,8 @@ dfacto_status build_flattenings_impl(dfacto_ctx *ctx, const int64_t dims[3], int
         dfacto_tensor *t = new dfacto_tensor();
         t->chunk_len = chunk_len ? chunk_len : DFACTO_CHUNK_DEFAULT;
         t->relabel = (flags & DFACTO_BUILD_RELABEL) ||
-                     (!(flags & DFACTO_BUILD_NO_RELABEL) && nnz >= kRelabelMinNnz);
+                     (!(flags & DFACTO_BUILD_NO_RELABEL) && nnz >= kRelabelMinNnz &&
+                      nnz >= kRelabelPerRow * (dims[0] + dims[1] + dims[2]));
         t->device = ctx->device;
         if (async_alloc || ctx->mem.has_user()) {
             t->alloc_stream = ctx->stream;
@@ -506,6 +507,9 @@ dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, df
                 if (n == 0) {
                     launch_gram(ctx, d_F[1], dtype, t->dims[1], R, sw.G[1]);
                     launch_gram(ctx, d_F[2], dtype, t->dims[2], R, sw.G[2]);
+                } else if (dtype == DFACTO_BF16) {
+                    // the Gram of the previous mode's stored (rounded) factor
+                    launch_gram(ctx, d_F[n - 1], dtype, t->dims[n - 1], R, sw.G[n - 1]);
                 }
                 launch_solve(ctx, R, sw.G[(n + 1) % 3], sw.G[(n + 2) % 3], reg, sw.Hinv,
                              sw.solve_scratch, sw.flag + n);
@@ -519,13 +523,14 @@ dfacto_status dfacto_als_iter(dfacto_ctx *ctx, const dfacto_tensor *t, int R, df
             launch_rowmap(ctx, M, t->dims[n], R, sw.W, d_F[n], dtype);
             // A BF16-stored factor differs from the FP64 one by its rounding;
             // the next modes' normal equations must use the Gram of what the
-            // next MTTKRPs read, so form it from the stored factor; and the
-            // fit is that of the stored factors (lambda from the FP64 ones).
-            if (dtype == DFACTO_BF16) {
-                launch_gram(ctx, d_F[n], dtype, t->dims[n], R, sw.G[n]);
-                if (n == 2)
-                    launch_fit_stored(ctx, d_F[2], dtype, M, t->dims[2], R, d_lambda, sw.G[0],
-                                      sw.G[1], sw.G[2], t->normsq, sw.part0, d_fit);
+            // next MTTKRPs read, so it is formed from the stored factor (for
+            // modes 0 and 1 on the side stream beside the next MTTKRP, ahead
+            // of the next solve); and the fit is that of the stored factors
+            // (lambda from the FP64 ones).
+            if (dtype == DFACTO_BF16 && n == 2) {
+                launch_gram(ctx, d_F[2], dtype, t->dims[2], R, sw.G[2]);
+                launch_fit_stored(ctx, d_F[2], dtype, M, t->dims[2], R, d_lambda, sw.G[0],
+                                  sw.G[1], sw.G[2], t->normsq, sw.part0, d_fit);
             }
         }
     });

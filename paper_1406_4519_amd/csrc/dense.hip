@@ -1720,7 +1720,12 @@ GramPlan gram_plan(int64_t rows, int R, const void *F, dfacto_dtype dtype) {
     GramPlan g;
     g.nt = (R + 15) / 16;
     const int bs = g.nt <= 2 ? 1024 : 256;  // 16 waves per block when the registers allow
-    const int64_t want = (rows + 16 * 2 * (bs / 64) - 1) / (16 * 2 * (bs / 64));
+    // Short factors (batched members): eight 16-row steps per wave, so that a
+    // block's fixed costs (combining its waves' sums in LDS, writing its
+    // partial R x R block) stay small beside its work.  Longer ones: two, so
+    // that a single Gram spreads over enough blocks to fill the device.
+    const int64_t per_blk = 16 * (rows < 65536 ? 8 : 2) * (bs / 64);
+    const int64_t want = (rows + per_blk - 1) / per_blk;
     g.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256));
     const size_t es = dtype == DFACTO_F32 ? 4 : 2;
     g.vec = R == 32 && (uintptr_t)F % (2 * es) == 0;

@@ -298,14 +298,21 @@ struct Build {
                 g->launches += 2;
             }
             // launch forms per class: the default shape and, when tuning,
-            // fewer columns per lane (more lanes) and 2 or 4 chunks per lane
-            // group; one work-item table per item size
+            // other columns per lane (fewer, or eight for BF16), lanes per
+            // group to match, and 2 or 4 chunks per lane group; one
+            // work-item table per item size
             const bool tune = tuning;
-            auto forms = [tune](const MttkrpShape &sh, const std::vector<int> &ranks) {
+            auto forms = [tune, dt](const MttkrpShape &sh, const std::vector<int> &ranks) {
                 std::vector<std::pair<MttkrpShape, unsigned>> f{{sh, 1u}};
                 if (!tune) return f;
                 std::vector<MttkrpShape> shapes{sh};
-                for (int c = sh.cpl / 2; sh.nch == 1 && c >= 1; c /= 2) {
+                // BF16 rows of a multiple of 8 columns: also 8 columns per
+                // lane (one 16-byte load; the factors are 16-byte aligned)
+                bool wide = dt == DFACTO_BF16 && sh.nch == 1 && sh.cpl < 8;
+                for (int r : ranks) wide = wide && r % 8 == 0;
+                const int top = wide ? 8 : sh.cpl / 2;
+                for (int c = top; sh.nch == 1 && c >= 1; c /= 2) {
+                    if (c == sh.cpl) continue;
                     // lanes per group: enough for the widest member (the
                     // lanes past a member's columns stay idle)
                     int lanes = 1;
@@ -335,7 +342,8 @@ struct Build {
                     relabeled_tables(T[t], m, R[t], dt, ws[t].perm, &Fl, &Fm);
                 desc[t] = {md.stream, md.chunk_start, (uint32_t)md.nchunk, R[t], Fl, Fm,
                            ws[t].M, ws[t].carry};
-                const MttkrpShape sh = mttkrp_shape(R[t], dt, Fl, Fm, ws[t].M);
+                const MttkrpShape sh =
+                    mttkrp_shape(R[t], dt, Fl, Fm, ws[t].M, ws[t].perm && md.perm_leaf);
                 const bool sm = mttkrp_small(T[t], m);
                 Cls &c = cls[{sh.cpl, sh.g, sh.nch, sm}];
                 c.sh = sh;
@@ -356,8 +364,9 @@ struct Build {
                     Expansion<uint2> &x = c.items[per];
                     for (int t = 0; t < n; ++t) {
                         const ModeData &md = T[t]->mode[m];
-                        const MttkrpShape sh = mttkrp_shape(R[t], dt, desc[t].Fleaf, desc[t].Fmid,
-                                                            ws[t].M);
+                        const MttkrpShape sh =
+                            mttkrp_shape(R[t], dt, desc[t].Fleaf, desc[t].Fmid, ws[t].M,
+                                         ws[t].perm && md.perm_leaf);
                         if (sh.cpl != c.sh.cpl || sh.g != c.sh.g || sh.nch != c.sh.nch ||
                             mttkrp_small(T[t], m) != c.small)
                             continue;

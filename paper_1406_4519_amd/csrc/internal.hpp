@@ -57,8 +57,12 @@ struct ModeData {
     // the most-gathered rows are the first ones.
     uint32_t *perm_leaf = nullptr, *perm_mid = nullptr;
 };
-// dfacto_build_flattenings relabels the gathers of tensors from this size on
+// dfacto_build_flattenings relabels the gathers of tensors from this size on,
+// when they hold at least kRelabelPerRow nonzeros per factor row (the copies
+// into rank order cost a pass over the gathered factors per MTTKRP, which
+// the shared lines repay only when each row is gathered often)
 constexpr int64_t kRelabelMinNnz = (int64_t)1 << 23;
+constexpr int64_t kRelabelPerRow = 64;
 
 constexpr int kShortRun = 16;
 
@@ -345,8 +349,9 @@ void launch_mttkrp_resid(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int 
 void launch_gather_probe(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
                          dfacto_dtype dtype, const void *Fleaf, const void *Fmid, int pattern,
                          float *sink);
+// relabeled: the mode gathers through rank-ordered copies
 MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
-                         const float *out);
+                         const float *out, bool relabeled);
 bool mttkrp_small(const dfacto_tensor *t, int mode);
 // chunks per work item of the grouped MTTKRP: kper per lane group
 unsigned mttkrp_group_chunks_per_item(const MttkrpShape &sh, unsigned kper);

@@ -1042,7 +1042,7 @@ size_t perm_bytes(const dfacto_tensor *t, int R, dfacto_dtype dtype) {
 }
 
 MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
-                         const float *out) {
+                         const float *out, bool relabeled) {
     const size_t es = dtype == DFACTO_BF16 ? 2 : 4;
     auto al = [&](size_t a) {
         return ((uintptr_t)Fleaf % a == 0) && ((uintptr_t)Fmid % a == 0) &&
@@ -1052,10 +1052,14 @@ MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const voi
     int cpl = 1;
     // Eight columns per lane only for BF16 (one 16-byte load per lane): a
     // gather instruction then fetches 16 rows of 64 bytes instead of 8.  For
-    // FP32 eight columns are two loads per lane, no fewer instructions.  Not
-    // below R = 32: groups of one or two lanes share each batch of stream
-    // entries over too few lanes (measured slower than four columns).
-    if (dtype == DFACTO_BF16 && R % 8 == 0 && R >= 32 && aligned8 && DFACTO_MAX_CPL >= 8)
+    // FP32 eight columns are two loads per lane, no fewer instructions.  Only
+    // for relabeled gathers (where the most-gathered rows share lines and the
+    // wider loads pay: 13.1 -> 12.7 ms per paper-shape launch; with plain
+    // gathers they cost 7%: 0.66 -> 0.70 ms at 50M nonzeros), and not below
+    // R = 32, where groups of one or two lanes would share each batch of
+    // stream entries over too few lanes.
+    if (dtype == DFACTO_BF16 && relabeled && R % 8 == 0 && R >= 32 && aligned8 &&
+        DFACTO_MAX_CPL >= 8)
         cpl = 8;
     else if (R % 4 == 0 && aligned4 && DFACTO_MAX_CPL >= 4) cpl = 4;
     else if (R % 2 == 0 && aligned2 && DFACTO_MAX_CPL >= 2) cpl = 2;
@@ -1088,7 +1092,7 @@ void launch_mttkrp(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R, dfa
                            sf * (double)(t->dims[md.leaf] + t->dims[md.mid]) * R;
         ctx->prof_flops += 2.0 * R * (double)(t->nnz + md.nfib);
     }
-    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out);
+    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out, md.perm_leaf != nullptr);
     const bool sm = mttkrp_small(t, mode);
     const Tables tb = gather_tables(ctx, t, mode, R, dtype, Fleaf, Fmid);
     with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
@@ -1112,7 +1116,7 @@ void launch_mttkrp_in(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
                       dfacto_dtype dtype, const void *Fleaf, const void *Fmid, float *out,
                       float *carry, void *perm) {
     const ModeData &md = t->mode[mode];
-    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out);
+    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out, md.perm_leaf != nullptr);
     const bool sm = mttkrp_small(t, mode);
     const Tables tb = gather_tables(ctx, t, mode, R, dtype, Fleaf, Fmid, perm);
     with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
@@ -1134,7 +1138,7 @@ void launch_mttkrp_split(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int 
                            sf * (double)(t->dims[md.leaf] + t->dims[md.mid]) * R;
         ctx->prof_flops += 2.0 * R * (double)(t->nnz + md.nfib);
     }
-    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out);
+    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out, md.perm_leaf != nullptr);
     const bool sm = mttkrp_small(t, mode);
     const Tables tb = gather_tables(ctx, t, mode, R, dtype, Fleaf, Fmid);
     with_shape(dtype, sh, [&](auto tc, auto cplc, auto gc, auto nchc) {
@@ -1149,8 +1153,8 @@ void launch_mttkrp_resid(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int 
                          const void *Froot, float *out) {
     const ModeData &md = t->mode[mode];
     // the root rows share the alignment rule of the gathered rows
-    MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out);
-    const MttkrpShape sr = mttkrp_shape(R, dtype, Froot, Froot, out);
+    MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, out, false);
+    const MttkrpShape sr = mttkrp_shape(R, dtype, Froot, Froot, out, false);
     if (sr.cpl < sh.cpl) sh = sr;
     const bool sm = mttkrp_small(t, mode);
     const Tables tb = gather_tables(ctx, t, mode, R, dtype, Fleaf, Fmid);
@@ -1165,7 +1169,7 @@ void launch_gather_probe(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int 
                          dfacto_dtype dtype, const void *Fleaf, const void *Fmid, int pattern,
                          float *sink) {
     const ModeData &md = t->mode[mode];
-    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, sink);
+    const MttkrpShape sh = mttkrp_shape(R, dtype, Fleaf, Fmid, sink, md.perm_leaf != nullptr);
     if (sh.nch != 1) throw Error{DFACTO_E_UNSUPPORTED, "the gather probe takes R <= 64 * CPL"};
     if ((pattern == 5 || pattern >= 8) && R > kProbeLdsRowElems)
         throw Error{DFACTO_E_UNSUPPORTED, "the LDS patterns take R <= 64"};

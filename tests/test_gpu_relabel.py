@@ -159,14 +159,21 @@ def test_relabel_order_follows_gather_counts(pair):
 
 
 def test_relabel_by_size_and_flags(pair):
-    """dfacto_build_flattenings relabels from 2^23 stored nonzeros on, and
-    contradictory flags are refused."""
+    """dfacto_build_flattenings relabels from 2^23 nonzeros on when there are
+    at least 64 nonzeros per factor row, and contradictory flags or chunk
+    lengths out of range are refused."""
     ctx, coo, plain, rel = pair
     from gpu_util import coo_to_dev
     i, j, k, v = coo_to_dev(coo)
     t = dfacto.build_flattenings(ctx, coo.dims, i, j, k, v)
     assert not t.info()["relabeled"]  # 400K nonzeros
     t.close()
+    for dims, want in (((1000, 1000, 1000), True), ((200_000, 100_000, 50_000), False)):
+        gi, gj, gk, gv = gen.zipf_distinct_torch(dims, 9_000_000, 1.1, seed=63, device=DEV)
+        t = dfacto.build_flattenings(ctx, dims, gi, gj, gk, gv)
+        assert t.info()["relabeled"] == want, dims  # 9M nonzeros: 3000 / 26 per row
+        t.close()
+        del gi, gj, gk, gv
     import ctypes
     lib = dfacto.load()
     d = (ctypes.c_int64 * 3)(*coo.dims)
