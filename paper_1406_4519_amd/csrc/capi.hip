@@ -106,9 +106,11 @@ void ws_prepare(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfacto_dtype dt,
         cmax = std::max<int64_t>(cmax, t->mode[m].nchunk);
         if (t2) cmax = std::max<int64_t>(cmax, t2->mode[m].nchunk);
     }
-    ws_get(ctx, dfacto_ctx::kCarry, sizeof(float) * (size_t)carry_sets * cmax * R);
+    const int kc = std::max(kernel_cols(t, R, dt), t2 ? kernel_cols(t2, R, dt) : R);
+    ws_get(ctx, dfacto_ctx::kCarry, sizeof(float) * (size_t)carry_sets * cmax * kc);
     const size_t pb = perm_bytes(t, R, dt);
     if (pb) ws_get(ctx, dfacto_ctx::kPerm, pb);
+    if (pad_out_stride(t, R, dt)) ws_get(ctx, dfacto_ctx::kPadOut, pad_out_bytes(t, R, dt, carry_sets));
     if (grams) {
         ws_get(ctx, dfacto_ctx::kPartial, sizeof(double) * 256 * (size_t)R * R);
         ws_get(ctx, dfacto_ctx::kPartialSide, sizeof(double) * 256 * (size_t)R * R);
@@ -560,7 +562,7 @@ dfacto_status dfacto_gd_grad(dfacto_ctx *ctx, const dfacto_tensor *t, int R, dfa
         const hipStream_t main = ctx->stream;
         int64_t cmax = 1;
         for (int m = 0; m < 3; ++m) cmax = std::max<int64_t>(cmax, t->mode[m].nchunk);
-        const size_t cstride = (size_t)cmax * R;
+        const size_t cstride = (size_t)cmax * kernel_cols(t, R, dtype);
         float *carry =
             (float *)ws_get(ctx, dfacto_ctx::kCarry, sizeof(float) * 3 * cstride);
         DF_HIP(hipEventRecord(ctx->ev_fork, main));

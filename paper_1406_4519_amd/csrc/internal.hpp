@@ -259,7 +259,9 @@ struct dfacto_ctx {
     std::string err;
     // growable device workspace, one slot per purpose (Gram partial sums: one
     // slot per stream, so that Grams on the two streams may overlap)
-    enum Slot { kM = 0, kCarry, kPartial, kPartialSide, kSmall, kTrial, kJoint, kPerm, kNumSlots };
+    enum Slot {
+        kM = 0, kCarry, kPartial, kPartialSide, kSmall, kTrial, kJoint, kPerm, kPadOut, kNumSlots
+    };
     void *ws[kNumSlots] = {};
     size_t ws_size[kNumSlots] = {};
     bool frozen = false;  // dfacto_ctx_freeze: workspaces may not grow
@@ -349,6 +351,13 @@ void launch_mttkrp_resid(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int 
 void launch_gather_probe(dfacto_ctx *ctx, const dfacto_tensor *t, int mode, int R,
                          dfacto_dtype dtype, const void *Fleaf, const void *Fmid, int pattern,
                          float *sink);
+// Padded rows of relabeled gathered tables (mttkrp.hip): the row stride of
+// the copies, the floats per padded output set (0 without padding), the
+// bytes of `sets` such sets, and the main kernel's column count for t.
+int table_stride(int R, dfacto_dtype dtype);
+size_t pad_out_stride(const dfacto_tensor *t, int R, dfacto_dtype dtype);
+size_t pad_out_bytes(const dfacto_tensor *t, int R, dfacto_dtype dtype, int sets);
+int kernel_cols(const dfacto_tensor *t, int R, dfacto_dtype dtype);
 // relabeled: the mode gathers through rank-ordered copies
 MttkrpShape mttkrp_shape(int R, dfacto_dtype dtype, const void *Fleaf, const void *Fmid,
                          const float *out, bool relabeled);
