@@ -609,7 +609,7 @@ def run_tensor(args):
     sample = None if args.no_cpu_baseline else _dev_sample(i, j, k, v, args.cpu_sample)
     # the library allocates through torch's caching allocator: the build
     # reuses device memory the input generator has already mapped (fresh
-    # device memory is mapped and cleared by the driver at a few tens of
+    # device memory is mapped and cleared by the kernel driver at a few tens of
     # GB/s, which would dominate the build's time)
     ctx = dfacto.Context(0, allocator="torch")
     torch.cuda.synchronize()
