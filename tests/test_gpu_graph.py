@@ -19,15 +19,20 @@ def _bits(x):
     return x.view(torch.int16) if x.dtype == torch.bfloat16 else x
 
 
-@pytest.mark.parametrize("R,dtype", [(32, "f32"), (16, "bf16")])
-def test_captured_step_replays_bitwise(R, dtype):
+# relabel: gathers from rank-ordered copies of the factors, which at R = 10
+# are padded to 16 columns (the copies, the padded output and its narrowing
+# are launched inside the capture too)
+@pytest.mark.parametrize("R,dtype,relabel", [(32, "f32", False), (16, "bf16", False),
+                                             (10, "f32", True), (10, "bf16", True)])
+def test_captured_step_replays_bitwise(R, dtype, relabel):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     coo = gen.zipf_distinct((20_000, 15_000, 10_000), 300_000, 1.1, seed=81)
     F0 = gen.init_factors(coo.dims, R, seed=82)
     tdt = torch.float32 if dtype == "f32" else torch.bfloat16
     ctx = dfacto.Context(0)
-    T = build(ctx, coo)
+    T = build(ctx, coo, relabel=relabel)
+    assert T.info()["relabeled"] == relabel
     F = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(DEV).to(tdt) for f in F0]
     G = [torch.empty((d, R), dtype=torch.float32, device=DEV) for d in coo.dims]
     lam = torch.zeros(R, dtype=torch.float64, device=DEV)
@@ -122,3 +127,34 @@ def test_frozen_context_refuses_to_grow_workspaces():
         t.close()
     ctx.close()
     ctx2.close()
+
+
+def test_frozen_context_runs_padded_relabeled_calls():
+    """A relabeled tensor at R = 10 (rank-ordered copies padded to 16
+    columns, a padded output per MTTKRP): once CP-ALS and the GD gradient have
+    run, every workspace they use is reserved, so the same calls on a frozen
+    context run, with bitwise the same results."""
+    from gpu_util import build, factors_to_dev
+    ctx = dfacto.Context(0)
+    coo = gen.zipf_distinct((6000, 4000, 3000), 150_000, 1.1, seed=35)
+    t = build(ctx, coo, relabel=True)
+    assert t.info()["relabeled"]
+    R = 10
+    F0 = gen.init_factors(coo.dims, R, seed=36)
+    lam = torch.zeros(R, dtype=torch.float64, device="cuda:0")
+    fit = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    fv = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    G = [torch.empty((d, R), dtype=torch.float32, device="cuda:0") for d in coo.dims]
+    outs = []
+    for frozen in (False, True):
+        F, _ = factors_to_dev(F0, "f32")
+        ctx.freeze(frozen)
+        dfacto.als_iter(ctx, t, F, lam, fit)
+        dfacto.gd_grad(ctx, t, F, G, fv, 0.05)
+        torch.cuda.synchronize()
+        outs.append([x.clone() for x in (*F, lam, fit, *G, fv)])
+    ctx.freeze(False)
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+    t.close()
+    ctx.close()
