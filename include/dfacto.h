@@ -170,7 +170,12 @@ dfacto_status dfacto_build_flattenings(dfacto_ctx *ctx, const int64_t dims[3], i
  * neither (dfacto_build_flattenings): relabel from 2^23 nonzeros on when
  * there are at least 64 nonzeros per factor row (nnz >= 64 (I + J + K)):
  * each MTTKRP of a relabeled tensor first copies its two gathered factors
- * into rank order, which pays only when rows are gathered often. */
+ * into rank order, which pays only when rows are gathered often.  Rows
+ * shorter than 128 bytes are copied at a stride of the next power of two
+ * columns (zero filled), so that none straddles two cache lines; the
+ * MTTKRP then writes a padded output in a context workspace and narrows it
+ * into the caller's R columns (workspace per call: the two copies plus
+ * dims x stride x 4 bytes of output, three outputs for the GD gradient). */
 #define DFACTO_BUILD_RELABEL 1
 #define DFACTO_BUILD_NO_RELABEL 2
 
