@@ -88,11 +88,14 @@ struct Member {
 // the caller's pageable memory otherwise go through the runtime's own small
 // staging copies (tens per request); here the host copies a chunk of up to
 // kBytes into a pinned buffer while the device copies the previous one.
-// One ring per thread that copies (each builder, the delivery thread).
+// BF16 factors are converted chunk by chunk in a device buffer of the ring,
+// so a request makes no allocation for the conversion.  One ring per thread
+// that copies (each builder, the delivery thread).
 struct Staging {
     static constexpr size_t kBytes = (size_t)32 << 20;
     void *buf[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
+    float *dev = nullptr;  // kBytes on the device: one FP32 chunk being converted
     int next = 0;
     bool init() {
         for (int k = 0; k < 2; ++k)
@@ -101,6 +104,11 @@ struct Staging {
                 (void)hipGetLastError();
                 return false;
             }
+        if (hipMalloc((void **)&dev, kBytes) != hipSuccess) {
+            (void)hipGetLastError();
+            dev = nullptr;
+            return false;
+        }
         return true;
     }
     void release() {
@@ -110,6 +118,8 @@ struct Staging {
             ev[k] = nullptr;
             buf[k] = nullptr;
         }
+        if (dev) (void)hipFree(dev);
+        dev = nullptr;
     }
     // host -> device on stream st; returns once the last chunk is queued
     // (the buffers stay in use until their events complete)
@@ -141,6 +151,51 @@ struct Staging {
             next ^= 1;
             DF_HIP(hipEventSynchronize(ev[k]));
             DF_HIP(hipMemcpyAsync(buf[k], (const char *)src + off, n, hipMemcpyDeviceToHost, st));
+            DF_HIP(hipEventRecord(ev[k], st));
+            drain();
+            pend_off = off, pend_n = n, pend_k = k;
+        }
+        drain();
+    }
+    // host FP32 -> device BF16 (rounded on the device), on stream st: each
+    // chunk is copied into the device buffer and rounded from there (stream
+    // order keeps the next chunk's copy behind the rounding)
+    void upload_bf16(uint16_t *dst, const float *src, size_t count, hipStream_t st) {
+        constexpr size_t per = kBytes / 4;
+        for (size_t off = 0; off < count; off += per) {
+            const size_t n = std::min(per, count - off);
+            const int k = next;
+            next ^= 1;
+            DF_HIP(hipEventSynchronize(ev[k]));
+            std::memcpy(buf[k], src + off, 4 * n);
+            DF_HIP(hipMemcpyAsync(dev, buf[k], 4 * n, hipMemcpyHostToDevice, st));
+            DF_HIP(hipEventRecord(ev[k], st));
+            hipLaunchKernelGGL(k_f32_to_bf16, dim3(convert_grid((int64_t)n)), dim3(256), 0, st,
+                               (const float *)dev, dst + off, (int64_t)n);
+            DF_LAUNCHED();
+        }
+    }
+    // device BF16 -> host FP32 (widened on the device), on stream st, waiting
+    // for the copies
+    void download_bf16(float *dst, const uint16_t *src, size_t count, hipStream_t st) {
+        constexpr size_t per = kBytes / 4;
+        size_t pend_off = 0, pend_n = 0;
+        int pend_k = -1;
+        auto drain = [&] {
+            if (pend_k < 0) return;
+            DF_HIP(hipEventSynchronize(ev[pend_k]));
+            std::memcpy(dst + pend_off, buf[pend_k], 4 * pend_n);
+            pend_k = -1;
+        };
+        for (size_t off = 0; off < count; off += per) {
+            const size_t n = std::min(per, count - off);
+            const int k = next;
+            next ^= 1;
+            DF_HIP(hipEventSynchronize(ev[k]));
+            hipLaunchKernelGGL(k_bf16_to_f32, dim3(convert_grid((int64_t)n)), dim3(256), 0, st,
+                               src + off, dev, (int64_t)n);
+            DF_LAUNCHED();
+            DF_HIP(hipMemcpyAsync(buf[k], dev, 4 * n, hipMemcpyDeviceToHost, st));
             DF_HIP(hipEventRecord(ev[k], st));
             drain();
             pend_off = off, pend_n = n, pend_k = k;
@@ -295,13 +350,7 @@ void admit(dfacto_server *s, int b, Member &m, double *t_build) {
             hip_check(stream_alloc(&m.F[k], std::max<size_t>(es * cnt, 16), st, s->pool),
                       "factor allocation");
             if (r.dtype == DFACTO_BF16) {  // FP32 upload, rounded to BF16 on the device
-                float *tmp = nullptr;
-                hip_check(stream_alloc((void **)&tmp, 4 * cnt, st, s->pool), "factor staging");
-                sg.upload(tmp, r.init[k], 4 * cnt, st);
-                hipLaunchKernelGGL(k_f32_to_bf16, dim3(convert_grid((int64_t)cnt)), dim3(256), 0,
-                                   st, tmp, (uint16_t *)m.F[k], (int64_t)cnt);
-                DF_LAUNCHED();
-                DF_HIP(hipFreeAsync(tmp, st));
+                sg.upload_bf16((uint16_t *)m.F[k], r.init[k], cnt, st);
             } else {
                 sg.upload(m.F[k], r.init[k], 4 * cnt, st);
             }
@@ -324,28 +373,18 @@ void deliver(dfacto_server *s, Member &m) {
     const dfacto_request &r = m.req;
     hipStream_t st = s->dstream;
     Staging &sg = s->dstage;
-    std::vector<float *> tmps;
     try {
         for (int k = 0; k < 3; ++k) {
             const size_t cnt = (size_t)r.dims[k] * r.R;
             if (!r.out_F[k]) continue;
-            if (r.dtype == DFACTO_BF16) {
-                float *tmp = nullptr;
-                hip_check(stream_alloc((void **)&tmp, 4 * cnt, st, s->pool), "result staging");
-                tmps.push_back(tmp);
-                hipLaunchKernelGGL(k_bf16_to_f32, dim3(convert_grid((int64_t)cnt)), dim3(256), 0,
-                                   st, (const uint16_t *)m.F[k], tmp, (int64_t)cnt);
-                DF_LAUNCHED();
-                sg.download(r.out_F[k], tmp, 4 * cnt, st);
-            } else {
+            if (r.dtype == DFACTO_BF16)
+                sg.download_bf16(r.out_F[k], (const uint16_t *)m.F[k], cnt, st);
+            else
                 sg.download(r.out_F[k], m.F[k], 4 * cnt, st);
-            }
         }
         if (r.out_lambda) sg.download(r.out_lambda, m.lambda, 8 * (size_t)r.R, st);
-        for (float *p : tmps) (void)hipFreeAsync(p, st);
         DF_HIP(hipStreamSynchronize(st));
     } catch (...) {
-        for (float *p : tmps) (void)hipFreeAsync(p, st);
         (void)hipStreamSynchronize(st);
         throw;
     }
