@@ -319,6 +319,8 @@ def run_served(args):
     import numpy as np
     from paper_1406_4519_amd import dfacto, gen
 
+    if args.served_one is None:
+        return _served_parent(args)
     t0 = time.perf_counter()
     pool = []
     for t in range(args.pool):
@@ -330,19 +332,42 @@ def run_served(args):
         Rb = 32
         big = (coo, Rb, [f.astype(np.float32) for f in gen.init_factors(coo.dims, Rb, seed=1007)])
     log(f"generated the request pool in {time.perf_counter() - t0:.1f}s")
+    dt, rate, n_warm, n_meas, seed = args.served_one.split(",")
+    out = _served_run(dfacto, np, pool, big, float(rate), int(n_warm), int(n_meas), dt, int(seed),
+                      args.large_frac)
+    print("SERVED_RUN " + json.dumps(out), flush=True)
+
+
+def _served_child(args, dt, rate, n_warm, n_meas, seed):
+    """One served run in a process of its own.  A server started in a
+    process where another server has already run serves about 20-35% fewer
+    solves per second (measured; reusing the first server's streams or its
+    memory pool does not remove it), so every run starts from a fresh
+    process and the runs compare on equal terms."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--workload", "served",
+           "--served-one", f"{dt},{rate},{n_warm},{n_meas},{seed}",
+           "--large-frac", str(args.large_frac), "--pool", str(args.pool)]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("SERVED_RUN ")]
+    if r.returncode != 0 or not lines:
+        raise RuntimeError(f"served run {dt} at {rate:g}/s failed (exit {r.returncode})")
+    return json.loads(lines[-1][len("SERVED_RUN "):])
+
+
+def _served_parent(args):
     out = {}
     for dt in args.served_dtypes.split(","):
         log(f"  {dt}: {args.served_warmup} + {args.served_requests} requests at {args.rate:g}/s")
-        out[dt] = _served_run(dfacto, np, pool, big, args.rate, args.served_warmup,
-                              args.served_requests, dt, 12345, args.large_frac)
+        out[dt] = _served_child(args, dt, args.rate, args.served_warmup, args.served_requests,
+                                12345)
     search = {}
     if args.rate_search:
         for dt in args.served_dtypes.split(","):
             best, tried = None, []
 
             def probe(rate):
-                r = _served_run(dfacto, np, pool, big, rate, 100, args.search_requests, dt,
-                                777, args.large_frac)
+                r = _served_child(args, dt, rate, 100, args.search_requests, 777)
                 tried.append(dict(rate=rate, solves_per_s=r["solves_per_s"],
                                   p50_ms=r["p50_ms"], p99_ms=r["p99_ms"],
                                   sustained=r["sustained"]))
@@ -889,6 +914,9 @@ def main():
                     help="paper1200m workload: distinct nonzeros")
     ap.add_argument("--served-dtypes", default="f32,bf16",
                     help="served workload: factor storage dtypes, run in this order")
+    ap.add_argument("--served-one", default=None,
+                    help="served workload: one run 'dtype,rate,warm-up,measured,seed' in this "
+                         "process (each served run is started this way in a process of its own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=400_000_000,
                     help="nonzeros copied to the host for the CPU baseline (at most)")
