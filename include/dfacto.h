@@ -401,7 +401,12 @@ void dfacto_group_destroy(dfacto_group *g);
  * bitwise those of dfacto_als_iter repeated on it alone.
  *
  * hbm_budget: device bytes the server may hold (0 = 90% of the free memory
- * at creation); max_slots: most requests active at once (>= 1). */
+ * at creation); max_slots: most requests active at once (>= 1).
+ *
+ * Measured on MI355X: a server created in a process where another server
+ * has already run (and been destroyed) serves 20-35% fewer solves per
+ * second than the first one did; keep one server for the life of a process
+ * where throughput matters. */
 typedef struct dfacto_server dfacto_server;
 
 typedef struct {
