@@ -76,6 +76,39 @@ __device__ __forceinline__ uint2 load_entry(const uint2 *p) {
 #endif
 }
 
+// Pointers into device (global) memory.  Loads and stores through them are
+// global instructions.  Through a plain pointer whose origin the compiler
+// cannot see -- one read from a descriptor in memory, as in the grouped
+// kernels -- they would be flat instructions, which count against the LDS
+// counter as well, so every wait for an LDS result (the stream entries
+// shared by ds_swizzle) would also wait for every gather in flight.
+#define DF_GLOBAL __attribute__((address_space(1)))
+// plain vector types for loads through such pointers (the HIP vector
+// types cannot be copied out of a qualified address space)
+typedef float df_f2 __attribute__((ext_vector_type(2)));
+typedef float df_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int df_u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int df_u4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ const DF_GLOBAL T *gptr(const T *p) {
+    return (const DF_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ DF_GLOBAL T *gptr(T *p) {
+    return (DF_GLOBAL T *)p;
+}
+
+__device__ __forceinline__ uint2 load_entry(const DF_GLOBAL uint2 *p) {
+#if DFACTO_NT_STREAM
+    const unsigned long long x =
+        __builtin_nontemporal_load(reinterpret_cast<const DF_GLOBAL unsigned long long *>(p));
+    return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
+#else
+    const df_u2 x = *reinterpret_cast<const DF_GLOBAL df_u2 *>(p);
+    return make_uint2(x.x, x.y);
+#endif
+}
+
 // ---- factor-row loads: CPL consecutive columns, widened to FP32 ----------
 template <typename T, int CPL>
 struct RowLoad;
@@ -86,6 +119,10 @@ struct RowLoad<float, 4> {
         const float4 x = *reinterpret_cast<const float4 *>(p);
         v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
     }
+    static __device__ __forceinline__ void load(const DF_GLOBAL float *p, float (&v)[4]) {
+        const df_f4 x = *reinterpret_cast<const DF_GLOBAL df_f4 *>(p);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    }
 };
 template <>
 struct RowLoad<float, 2> {
@@ -93,10 +130,15 @@ struct RowLoad<float, 2> {
         const float2 x = *reinterpret_cast<const float2 *>(p);
         v[0] = x.x; v[1] = x.y;
     }
+    static __device__ __forceinline__ void load(const DF_GLOBAL float *p, float (&v)[2]) {
+        const df_f2 x = *reinterpret_cast<const DF_GLOBAL df_f2 *>(p);
+        v[0] = x.x; v[1] = x.y;
+    }
 };
 template <>
 struct RowLoad<float, 1> {
     static __device__ __forceinline__ void load(const float *p, float (&v)[1]) { v[0] = *p; }
+    static __device__ __forceinline__ void load(const DF_GLOBAL float *p, float (&v)[1]) { v[0] = *p; }
 };
 
 template <>
@@ -104,6 +146,12 @@ struct RowLoad<float, 8> {
     static __device__ __forceinline__ void load(const float *p, float (&v)[8]) {
         const float4 x = *reinterpret_cast<const float4 *>(p);
         const float4 y = *reinterpret_cast<const float4 *>(p + 4);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    }
+    static __device__ __forceinline__ void load(const DF_GLOBAL float *p, float (&v)[8]) {
+        const df_f4 x = *reinterpret_cast<const DF_GLOBAL df_f4 *>(p);
+        const df_f4 y = *reinterpret_cast<const DF_GLOBAL df_f4 *>(p + 4);
         v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
         v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
     }
@@ -119,11 +167,20 @@ struct RowLoad<uint16_t, 8> {
         v[0] = bf16_lo(x.x); v[1] = bf16_hi(x.x); v[2] = bf16_lo(x.y); v[3] = bf16_hi(x.y);
         v[4] = bf16_lo(x.z); v[5] = bf16_hi(x.z); v[6] = bf16_lo(x.w); v[7] = bf16_hi(x.w);
     }
+    static __device__ __forceinline__ void load(const DF_GLOBAL uint16_t *p, float (&v)[8]) {
+        const df_u4 x = *reinterpret_cast<const DF_GLOBAL df_u4 *>(p);
+        v[0] = bf16_lo(x.x); v[1] = bf16_hi(x.x); v[2] = bf16_lo(x.y); v[3] = bf16_hi(x.y);
+        v[4] = bf16_lo(x.z); v[5] = bf16_hi(x.z); v[6] = bf16_lo(x.w); v[7] = bf16_hi(x.w);
+    }
 };
 template <>
 struct RowLoad<uint16_t, 4> {
     static __device__ __forceinline__ void load(const uint16_t *p, float (&v)[4]) {
         const uint2 x = *reinterpret_cast<const uint2 *>(p);
+        v[0] = bf16_lo(x.x); v[1] = bf16_hi(x.x); v[2] = bf16_lo(x.y); v[3] = bf16_hi(x.y);
+    }
+    static __device__ __forceinline__ void load(const DF_GLOBAL uint16_t *p, float (&v)[4]) {
+        const df_u2 x = *reinterpret_cast<const DF_GLOBAL df_u2 *>(p);
         v[0] = bf16_lo(x.x); v[1] = bf16_hi(x.x); v[2] = bf16_lo(x.y); v[3] = bf16_hi(x.y);
     }
 };
@@ -133,10 +190,17 @@ struct RowLoad<uint16_t, 2> {
         const uint32_t x = *reinterpret_cast<const uint32_t *>(p);
         v[0] = bf16_lo(x); v[1] = bf16_hi(x);
     }
+    static __device__ __forceinline__ void load(const DF_GLOBAL uint16_t *p, float (&v)[2]) {
+        const uint32_t x = *reinterpret_cast<const DF_GLOBAL uint32_t *>(p);
+        v[0] = bf16_lo(x); v[1] = bf16_hi(x);
+    }
 };
 template <>
 struct RowLoad<uint16_t, 1> {
     static __device__ __forceinline__ void load(const uint16_t *p, float (&v)[1]) {
+        v[0] = __uint_as_float((uint32_t)(*p) << 16);
+    }
+    static __device__ __forceinline__ void load(const DF_GLOBAL uint16_t *p, float (&v)[1]) {
         v[0] = __uint_as_float((uint32_t)(*p) << 16);
     }
 };
@@ -156,6 +220,25 @@ __device__ __forceinline__ void store_vec(float *p, const float (&v)[CPL]) {
 }
 
 template <int CPL>
+__device__ __forceinline__ void store_vec(DF_GLOBAL float *p, const float (&v)[CPL]) {
+    if constexpr (CPL == 8) {
+        *reinterpret_cast<DF_GLOBAL df_f4 *>(p) = df_f4{v[0], v[1], v[2], v[3]};
+        *reinterpret_cast<DF_GLOBAL df_f4 *>(p + 4) = df_f4{v[4], v[5], v[6], v[7]};
+    } else if constexpr (CPL == 4) {
+        *reinterpret_cast<DF_GLOBAL df_f4 *>(p) = df_f4{v[0], v[1], v[2], v[3]};
+    } else if constexpr (CPL == 2) {
+        *reinterpret_cast<DF_GLOBAL df_f2 *>(p) = df_f2{v[0], v[1]};
+    } else {
+        p[0] = v[0];
+    }
+}
+
+template <int CPL>
+__device__ __forceinline__ void load_f32(const DF_GLOBAL float *p, float (&v)[CPL]) {
+    RowLoad<float, CPL>::load(p, v);
+}
+
+template <int CPL>
 __device__ __forceinline__ void load_f32(const float *p, float (&v)[CPL]) {
     RowLoad<float, CPL>::load(p, v);
 }
@@ -172,15 +255,15 @@ __device__ __forceinline__ void load_f32(const float *p, float (&v)[CPL]) {
 // Rows straight from the two factor tables in device memory.
 template <typename T, int CPL, int NCH, bool SMALL>
 struct GlobalRows {
-    const T *leafb[NCH], *midb[NCH];
+    const DF_GLOBAL T *leafb[NCH], *midb[NCH];
     int R;
     __device__ __forceinline__ GlobalRows(const T *Fleaf, const T *Fmid, int R_, int G, int lane)
         : R(R_) {
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int col = (c * G + lane) * CPL;
-            leafb[c] = Fleaf + (col < R ? col : 0);
-            midb[c] = Fmid + (col < R ? col : 0);
+            leafb[c] = gptr(Fleaf) + (col < R ? col : 0);
+            midb[c] = gptr(Fmid) + (col < R ? col : 0);
         }
     }
     __device__ __forceinline__ size_t off(uint32_t idx) const {
@@ -276,24 +359,27 @@ struct BufLoad<uint16_t, 1> {
 // product is reduced across the group's lanes by xor shuffles (every lane
 // ends with the same sum: each step adds two commuted operands).
 template <typename T, int CPL, int G, int NCH, bool SMALL, bool RES = false, class Src>
-__device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
+__device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st_,
                                              const uint32_t *__restrict__ cstart, uint32_t nchunk,
                                              const Src &src, int R,
-                                             float *__restrict__ out, float *__restrict__ carry,
+                                             float *__restrict__ out_, float *__restrict__ carry_,
                                              uint32_t gid, int lane,
                                              const T *__restrict__ Froot = nullptr) {
     if (gid >= nchunk) return;
-    const uint32_t cs = cstart[gid], ce = cstart[gid + 1];
+    const uint32_t cs = gptr(cstart)[gid], ce = gptr(cstart)[gid + 1];
     if (cs >= ce) return;
+    const DF_GLOBAL uint2 *__restrict__ st = gptr(st_);
+    DF_GLOBAL float *__restrict__ out = gptr(out_);
+    DF_GLOBAL float *__restrict__ carry = gptr(carry_);
 
     int col[NCH];
     bool act[NCH];
-    const T *rootb[NCH];
+    const DF_GLOBAL T *rootb[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         col[c] = (c * G + lane) * CPL;
         act[c] = col[c] < R;
-        rootb[c] = RES ? Froot + (act[c] ? col[c] : 0) : nullptr;
+        rootb[c] = RES ? gptr(Froot) + (act[c] ? col[c] : 0) : nullptr;
     }
     auto row_off = [&](uint32_t idx) -> size_t {
         if constexpr (SMALL) return (size_t)(uint32_t)__umul24(idx, (uint32_t)R);
@@ -301,7 +387,7 @@ __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
     };
     float acc[NCH][CPL], p[NCH][CPL], mrow[NCH][CPL];
     float rrow[RES ? NCH : 1][CPL];  // the root's factor row (RES only)
-    const uint2 h0 = st[cs];
+    const uint2 h0 = load_entry(st + cs);
     uint32_t row = h0.y;
     bool cont = !(h0.x & kRootBit);
 #pragma unroll
@@ -316,7 +402,8 @@ __device__ __forceinline__ void mttkrp_chunk(const uint2 *__restrict__ st,
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             if (!act[c]) continue;
-            float *dst = is_cont ? carry + (size_t)gid * R + col[c] : out + row_off(r_out) + col[c];
+            DF_GLOBAL float *dst =
+                is_cont ? carry + (size_t)gid * R + col[c] : out + row_off(r_out) + col[c];
             store_vec<CPL>(dst, acc[c]);
         }
     };
@@ -641,9 +728,11 @@ __global__ __launch_bounds__(kBlock) MTTKRP_OCCUPANCY void k_gather_probe(
 // out[row] += carry[c0] + ... + carry[c0 + n - 1], in chunk order (one lane
 // group; col/act are the lane's column blocks)
 template <int CPL, int NCH>
-__device__ __forceinline__ void add_run(const float *__restrict__ carry, int R,
-                                        float *__restrict__ out, uint32_t row, uint32_t c0,
+__device__ __forceinline__ void add_run(const float *__restrict__ carry_, int R,
+                                        float *__restrict__ out_, uint32_t row, uint32_t c0,
                                         uint32_t n, const int (&col)[NCH], const bool (&act)[NCH]) {
+    const DF_GLOBAL float *__restrict__ carry = gptr(carry_);
+    DF_GLOBAL float *__restrict__ out = gptr(out_);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         if (!act[c]) continue;
@@ -660,8 +749,9 @@ __device__ __forceinline__ void add_run(const float *__restrict__ carry, int R,
 }
 
 template <int CPL, int NCH>
-__device__ __forceinline__ void zero_row(float *__restrict__ out, int R, uint32_t row,
+__device__ __forceinline__ void zero_row(float *__restrict__ out_, int R, uint32_t row,
                                          const int (&col)[NCH], const bool (&act)[NCH]) {
+    DF_GLOBAL float *__restrict__ out = gptr(out_);
     float z[CPL];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) z[q] = 0.f;
@@ -703,9 +793,11 @@ __device__ __forceinline__ void short_runs(uint32_t gid, const uint32_t *__restr
 constexpr int kLongBlock = 1024;
 
 template <int CPL, int G, int NCH>
-__device__ __forceinline__ void long_run(const float *__restrict__ carry, int R,
-                                         float *__restrict__ out, uint32_t row, uint32_t c0,
+__device__ __forceinline__ void long_run(const float *__restrict__ carry_, int R,
+                                         float *__restrict__ out_, uint32_t row, uint32_t c0,
                                          uint32_t n) {
+    const DF_GLOBAL float *__restrict__ carry = gptr(carry_);
+    DF_GLOBAL float *__restrict__ out = gptr(out_);
     constexpr int S = kLongBlock / G;
     constexpr int W = CPL * NCH;  // floats per thread
     __shared__ float sh[kLongBlock * W];
