@@ -167,17 +167,29 @@ constexpr int kMfmaMaxTiles = 4;
 // value is its FP32 pattern with the low half zero), zero past the last row
 // or column.  VEC: R == 16 NT and the rows are aligned for one NT-element
 // vector load.
+// the FP32 bits of element i (BF16: its bits in the upper half)
+__device__ __forceinline__ uint32_t gram_bits(const DF_GLOBAL float *F, int64_t i) {
+    return __float_as_uint(F[i]);
+}
+__device__ __forceinline__ uint32_t gram_bits(const DF_GLOBAL uint16_t *F, int64_t i) {
+    return (uint32_t)F[i] << 16;
+}
+
+// F through a global-space pointer (the grouped kernels read it from a
+// descriptor: plain loads would be flat ones, whose waits also cover the
+// loads issued for the next steps)
 template <typename T, int NT, bool VEC>
-__device__ __forceinline__ void gram_load(const T *__restrict__ F, int64_t row, int64_t rows, int R,
-                                          int c0, uint32_t (&v)[NT]) {
+__device__ __forceinline__ void gram_load(const T *__restrict__ F_, int64_t row, int64_t rows,
+                                          int R, int c0, uint32_t (&v)[NT]) {
+    const DF_GLOBAL T *F = gptr(F_);
     if (VEC && NT == 2) {
         if (row < rows) {
             if constexpr (sizeof(T) == 4) {
-                const uint2 a = *reinterpret_cast<const uint2 *>(F + row * R + c0);
+                const df_u2 a = *reinterpret_cast<const DF_GLOBAL df_u2 *>(F + row * R + c0);
                 v[0] = a.x;
                 v[1] = a.y;
             } else {
-                const uint32_t a = *reinterpret_cast<const uint32_t *>(F + row * R + c0);
+                const uint32_t a = *reinterpret_cast<const DF_GLOBAL uint32_t *>(F + row * R + c0);
                 v[0] = a << 16;
                 v[1] = a & 0xFFFF0000u;
             }
@@ -188,7 +200,7 @@ __device__ __forceinline__ void gram_load(const T *__restrict__ F, int64_t row, 
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-        v[t] = (row < rows && c0 + t < R) ? __float_as_uint((float)ld<T>(F, row * R + c0 + t)) : 0u;
+        v[t] = (row < rows && c0 + t < R) ? gram_bits(F, row * R + c0 + t) : 0u;
 }
 
 // Block b of nb: the launch's own block, or a grouped launch's virtual one.
@@ -265,7 +277,7 @@ __device__ __forceinline__ void gram_mfma_body(const T *__restrict__ F, int64_t 
         }
         __syncthreads();
     }
-    double *pb = part + (size_t)b * R * R;
+    DF_GLOBAL double *pb = gptr(part) + (size_t)b * R * R;
     for (int e = threadIdx.x; e < NP * 256; e += BS) {
         int q = e / 256, rt = 0;
         while (q >= NT - rt) { q -= NT - rt; ++rt; }  // pair index -> (rt, ct)
@@ -295,8 +307,10 @@ __global__ __launch_bounds__(BS) void k_gram_mfma_group(const GramJob *__restric
 // G[e] = sum_b part[b][e]: a block takes 16 entries; slice q (16 per entry)
 // sums the partials b = q, q + 16, ...; the slices are combined in order.
 // The first 16 partials of a slice are loaded together, then added in order.
-__device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part, int nblk, int R,
-                                                 double *__restrict__ G, uint32_t b) {
+__device__ __forceinline__ void gram_reduce_body(const double *__restrict__ part_, int nblk, int R,
+                                                 double *__restrict__ G_, uint32_t b) {
+    const DF_GLOBAL double *part = gptr(part_);
+    DF_GLOBAL double *G = gptr(G_);
     __shared__ double sh[16][17];
     const int e = b * 16 + threadIdx.x % 16;
     const int sl = threadIdx.x / 16;

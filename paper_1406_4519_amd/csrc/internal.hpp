@@ -286,6 +286,28 @@ struct Error {
 
 dfacto_status fail(dfacto_ctx *ctx, dfacto_status code, const std::string &msg);
 
+// Pointers into device (global) memory.  Loads and stores through them are
+// global instructions.  Through a plain pointer whose origin the compiler
+// cannot see -- one read from a descriptor in memory, as in the grouped
+// kernels -- they would be flat instructions, which count against the LDS
+// counter as well, so every wait for an LDS result (the stream entries
+// shared by ds_swizzle) would also wait for every gather in flight.
+#define DF_GLOBAL __attribute__((address_space(1)))
+// plain vector types for loads through such pointers (the HIP vector
+// types cannot be copied out of a qualified address space)
+typedef float df_f2 __attribute__((ext_vector_type(2)));
+typedef float df_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int df_u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int df_u4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ const DF_GLOBAL T *gptr(const T *p) {
+    return (const DF_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ DF_GLOBAL T *gptr(T *p) {
+    return (DF_GLOBAL T *)p;
+}
+
 void hip_check(hipError_t e, const char *what);  // throws Error on failure
 #define DF_HIP(call) ::dfacto::hip_check((call), #call)
 // after kernel launches: a launch error names the launching function
